@@ -1,0 +1,224 @@
+"""Pressure Poisson operator and geometric multigrid (oracle; test-only).
+
+Paper, Sec. 2: the pressure system (with the BDIM-modified matrix) is solved
+by geometric multigrid whose cost grows linearly with the cell count; the
+projection kernel u[I,i] -= coeff[I,i]*(p[I]-p[I-del(i)]) fixes the face
+gradient and its coefficient.  The operator is therefore
+
+  (A p)(I) = sum_i  L_i(I+delta_i) (p(I+delta_i) - p(I))
+                  - L_i(I)         (p(I) - p(I-delta_i)),
+
+the L-weighted divergence of the face gradient.  A is symmetric negative
+semi-definite with A 1 = 0.  A cell whose 2d face coefficients are all zero is
+INACTIVE (fully solid).
+
+"Exact" solution = minimum-norm solution of A p = b_proj, where b_proj is b
+with inactive cells zeroed and the active-set mean removed.
+
+READINGS for the constants the paper leaves open (it names only GMG and,
+for smoothing, kernel-friendly non-ordered relaxation):
+  * smoother: damped Jacobi x <- x + w (b - A x)/diag(A), w = 2d/(2d+1),
+    inactive cells held at zero; nu1 = nu2 = 2 sweeps (symmetric V-cycle);
+  * restriction: coarse RHS = sum of the 2^d child residuals;
+  * prolongation: piecewise-constant injection x(I) += x_c(parent(I));
+  * coarse coefficient: half the sum of the 2^(d-1) fine faces a coarse face
+    covers (the unit-spacing rediscretisation of the integrated operator);
+  * coarsest level: minimum-norm least squares (a library routine);
+  * V-cycles until ||b - A x||_2 / ||b||_2 <= tol, tested before each cycle.
+"""
+
+import numpy as np
+
+from .grid import PERIODIC, shift
+
+NU1 = 2
+NU2 = 2
+
+
+def omega(d):
+    return 2.0 * d / (2.0 * d + 1.0)
+
+
+def periodic_flags(bc_lo):
+    return [b == PERIODIC for b in bc_lo]
+
+
+def apply_A(L, p, per):
+    d = p.ndim
+    out = np.zeros_like(p)
+    for i in range(d):
+        g = L[i] * (p - shift(p, i, -1, per[i]))        # face gradient * L at lower faces
+        out += shift(g, i, 1, per[i]) - g                # upper face minus lower face
+    return out
+
+
+def diag_A(L, per):
+    d = L[0].ndim
+    D = np.zeros_like(L[0])
+    for i in range(d):
+        D += L[i] + shift(L[i], i, 1, per[i])
+    return -D
+
+
+def active_mask(L, per):
+    return diag_A(L, per) != 0.0
+
+
+def project_rhs(b, active):
+    b = np.where(active, b, 0.0)
+    if active.any():
+        b = b - np.where(active, b[active].mean(), 0.0)
+    return b
+
+
+def remove_mean(x, active):
+    if not active.any():
+        return x
+    return np.where(active, x - x[active].mean(), 0.0)
+
+
+def jacobi(L, x, b, per, diag=None):
+    d = x.ndim
+    if diag is None:
+        diag = diag_A(L, per)
+    r = b - apply_A(L, x, per)
+    safe = np.where(diag != 0.0, diag, 1.0)
+    return np.where(diag != 0.0, x + omega(d) * r / safe, 0.0)
+
+
+def restrict(r):
+    d = r.ndim
+    shp = []
+    for m in r.shape:
+        shp += [m // 2, 2]
+    return r.reshape(shp).sum(axis=tuple(range(1, 2 * d, 2)))
+
+
+def prolong(xc):
+    x = xc
+    for ax in range(xc.ndim):
+        x = np.repeat(x, 2, axis=ax)
+    return x
+
+
+def coarsen_L(L):
+    """Coarse face coefficient = 1/2 * sum of the fine faces it covers."""
+    d = L[0].ndim
+    out = []
+    for i in range(d):
+        idx = [slice(None)] * d
+        idx[i] = slice(0, None, 2)                       # fine faces on coarse face planes
+        a = L[i][tuple(idx)]
+        for j in range(d):
+            if j == i:
+                continue
+            shp = list(a.shape)
+            shp[j:j + 1] = [shp[j] // 2, 2]
+            a = a.reshape(shp).sum(axis=j + 1)
+        out.append(0.5 * a)
+    return out
+
+
+def dense_matrix(L, per):
+    """Assemble A densely, face by face (graph-Laplacian assembly).
+
+    Independent of apply_A: every interior face between cells a and b with
+    coefficient c contributes +c to A[a,b], A[b,a] and -c to A[a,a], A[b,b].
+    """
+    shape = L[0].shape
+    d = len(shape)
+    N = int(np.prod(shape))
+    A = np.zeros((N, N))
+    flat = np.arange(N).reshape(shape)
+    for i in range(d):
+        for I in np.ndindex(*shape):
+            c = L[i][I]
+            if c == 0.0:
+                continue
+            J = list(I)
+            J[i] -= 1
+            if J[i] < 0:
+                if not per[i]:
+                    continue
+                J[i] += shape[i]
+            a, b = flat[I], flat[tuple(J)]
+            A[a, b] += c
+            A[b, a] += c
+            A[a, a] -= c
+            A[b, b] -= c
+    return A
+
+
+class Hierarchy:
+    """Coefficients of every level plus the coarsest pseudo-inverse (cached)."""
+
+    def __init__(self, L, nlev, per):
+        self.per = list(per)
+        self.L = [list(L)]
+        for _ in range(nlev - 1):
+            self.L.append(coarsen_L(self.L[-1]))
+        self.diag = [diag_A(Ll, self.per) for Ll in self.L]
+        self.active = [dg != 0.0 for dg in self.diag]
+        self._pinv = None
+
+    @property
+    def nlev(self):
+        return len(self.L)
+
+    def coarse_solve(self, b):
+        """Minimum-norm least-squares solution on the coarsest level."""
+        if self._pinv is None:
+            self._pinv = np.linalg.pinv(dense_matrix(self.L[-1], self.per))
+        return (self._pinv @ b.reshape(-1)).reshape(b.shape)
+
+
+def vcycle(h, lev, x, b):
+    L, per, diag = h.L[lev], h.per, h.diag[lev]
+    if lev == h.nlev - 1:
+        return h.coarse_solve(b)
+    for _ in range(NU1):
+        x = jacobi(L, x, b, per, diag)
+    r = b - apply_A(L, x, per)
+    xc = vcycle(h, lev + 1, np.zeros(tuple(m // 2 for m in x.shape)), restrict(r))
+    x = x + prolong(xc)
+    for _ in range(NU2):
+        x = jacobi(L, x, b, per, diag)
+    return x
+
+
+def solve(h, b, x0=None, tol=1e-8, max_vcycles=100, force_vcycles=None):
+    """GMG solve of A x = b on hierarchy h.
+
+    Returns (x, vcycles, rel_resid_history, converged).  With force_vcycles the
+    stopping test is replaced by exactly that many V-cycles (replay mode).
+    """
+    L, per = h.L[0], h.per
+    active = h.active[0]
+    b = project_rhs(np.asarray(b, dtype=np.float64), active)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    bnorm = np.linalg.norm(b)
+    if bnorm == 0.0 and force_vcycles is None:
+        return np.zeros_like(b), 0, [0.0], True
+    hist = []
+    k = 0
+    while True:
+        rel = np.linalg.norm(b - apply_A(L, x, per)) / (bnorm if bnorm > 0 else 1.0)
+        hist.append(rel)
+        if force_vcycles is not None:
+            if k == force_vcycles:
+                return x, k, hist, True
+        else:
+            if rel <= tol:
+                return x, k, hist, True
+            if k == max_vcycles:
+                return x, k, hist, False
+        x = vcycle(h, 0, x, b)
+        k += 1
+
+
+def min_norm_solution(L, per, b):
+    """Exact minimum-norm solution of A x = b_proj by dense least squares."""
+    active = active_mask(L, per)
+    bp = project_rhs(b, active)
+    x, *_ = np.linalg.lstsq(dense_matrix(L, per), bp.reshape(-1), rcond=None)
+    return x.reshape(b.shape)

@@ -1,0 +1,169 @@
+"""Pins of the Poisson / GMG oracle: closed forms, algebra and brute force."""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import geometry as G
+from oracle import poisson as P
+from oracle.grid import PERIODIC, WALL, auto_levels
+
+
+def _rand_L(rng, n, per, solid=()):
+    L = [rng.uniform(0.0, 1.0, n) for _ in n]
+    for i in range(len(n)):
+        if not per[i]:
+            idx = [slice(None)] * len(n)
+            idx[i] = 0
+            L[i][tuple(idx)] = 0.0
+    for cell in solid:                          # make a fully solid cell
+        for i in range(len(n)):
+            L[i][cell] = 0.0
+            up = list(cell)
+            up[i] += 1
+            if up[i] == n[i]:
+                if not per[i]:
+                    continue
+                up[i] = 0
+            L[i][tuple(up)] = 0.0
+    return L
+
+
+@pytest.mark.parametrize("n,per", [((6, 5), (True, False)), ((4, 3, 5), (False, True, True))])
+def test_matrix_free_operator_equals_face_assembly(n, per):
+    rng = np.random.default_rng(1)
+    L = _rand_L(rng, n, per)
+    A = P.dense_matrix(L, per)
+    N = int(np.prod(n))
+    for k in range(N):
+        e = np.zeros(N)
+        e[k] = 1.0
+        np.testing.assert_allclose(P.apply_A(L, e.reshape(n), per).reshape(-1), A[:, k],
+                                   atol=1e-15)
+
+
+def test_operator_symmetric_semidefinite_and_kills_constants():
+    rng = np.random.default_rng(2)
+    n, per = (7, 6, 5), (True, False, False)
+    L = _rand_L(rng, n, per, solid=[(3, 2, 2)])
+    x, y = rng.standard_normal(n), rng.standard_normal(n)
+    assert np.vdot(x, P.apply_A(L, y, per)) == pytest.approx(np.vdot(P.apply_A(L, x, per), y),
+                                                             rel=1e-13)
+    assert np.abs(P.apply_A(L, np.ones(n), per)).max() < 1e-15
+    assert np.vdot(x, P.apply_A(L, x, per)) < 0.0
+    assert not P.active_mask(L, per)[3, 2, 2]
+
+
+@pytest.mark.parametrize("n,k", [((16, 12), (3, 2)), ((8, 6, 10), (1, 4, 3))])
+def test_neumann_cosine_modes_are_exact_eigenvectors(n, k):
+    """L = 1 in a Neumann box: prod cos(pi k (i+1/2)/n) has eigenvalue
+    -4 sum sin^2(pi k / 2n) (closed form of the discrete Laplacian)."""
+    d = len(n)
+    L = G.measure(n, [WALL] * d)[2]
+    X = G.cell_centres(n)
+    p = np.ones(n)
+    for j in range(d):
+        p = p * np.cos(math.pi * k[j] * X[j] / n[j])
+    lam = -4.0 * sum(math.sin(math.pi * k[j] / (2 * n[j])) ** 2 for j in range(d))
+    np.testing.assert_allclose(P.apply_A(L, p, [False] * d), lam * p, atol=1e-13)
+
+
+def test_periodic_fourier_modes_are_exact_eigenvectors():
+    n = (12, 10, 8)
+    L = G.measure(n, [PERIODIC] * 3)[2]
+    X = G.cell_centres(n)
+    k = (2, 3, 1)
+    p = np.cos(sum(2 * math.pi * k[j] * X[j] / n[j] for j in range(3)))
+    lam = -4.0 * sum(math.sin(math.pi * k[j] / n[j]) ** 2 for j in range(3))
+    np.testing.assert_allclose(P.apply_A(L, p, [True] * 3), lam * p, atol=1e-13)
+
+
+def test_continuous_manufactured_solution_is_second_order():
+    errs = []
+    for N in (16, 32, 64):
+        n = (N, N)
+        L = G.measure(n, [PERIODIC] * 2)[2]
+        h = 1.0 / N                                   # unit box, grid spacing h
+        X = G.cell_centres(n)
+        p = np.cos(2 * math.pi * X[0] * h) * np.cos(2 * math.pi * X[1] * h)
+        lap = -(2 * (2 * math.pi) ** 2) * p * h * h   # continuous Laplacian in grid units
+        errs.append(np.abs(P.apply_A(L, p, [True, True]) - lap).max() / (h * h))
+    assert errs[0] / errs[1] == pytest.approx(4.0, rel=0.05)
+    assert errs[1] / errs[2] == pytest.approx(4.0, rel=0.05)
+
+
+def test_transfers_are_adjoint_and_coarse_operator_is_half_galerkin():
+    rng = np.random.default_rng(3)
+    for n, per in [((8, 12), [True, False]), ((8, 4, 6), [False, True, False])]:
+        r = rng.standard_normal(n)
+        xc = rng.standard_normal(tuple(m // 2 for m in n))
+        assert np.vdot(P.restrict(r), xc) == pytest.approx(np.vdot(r, P.prolong(xc)), rel=1e-13)
+        assert P.restrict(r).sum() == pytest.approx(r.sum(), rel=1e-12, abs=1e-12)
+        L = _rand_L(rng, n, per)
+        Lc = P.coarsen_L(L)
+        galerkin = P.restrict(P.apply_A(L, P.prolong(xc), per))
+        np.testing.assert_allclose(P.apply_A(Lc, xc, per), 0.5 * galerkin, atol=1e-13)
+    # uniform coefficients: 2D stays 1, 3D doubles per level
+    assert np.all(P.coarsen_L(G.measure((8, 8), [PERIODIC] * 2)[2])[0] == 1.0)
+    assert np.all(P.coarsen_L(G.measure((8, 8, 8), [PERIODIC] * 3)[2])[1] == 2.0)
+
+
+@pytest.mark.parametrize("n,per,solid", [
+    ((8, 8), (False, False), [(2, 5)]),
+    ((8, 8), (True, True), []),
+    ((4, 4, 4), (False, True, False), [(1, 2, 1)]),
+])
+def test_gmg_matches_dense_min_norm_solve(n, per, solid):
+    rng = np.random.default_rng(4)
+    L = _rand_L(rng, n, per, solid)
+    b = rng.standard_normal(n)
+    h = P.Hierarchy(L, auto_levels(n, 2), list(per))
+    x, k, hist, ok = P.solve(h, b, tol=1e-13, max_vcycles=400)
+    assert ok
+    act = h.active[0]
+    exact = P.min_norm_solution(L, list(per), b)
+    xs = P.remove_mean(x, act)
+    np.testing.assert_allclose(xs[act], exact[act], atol=1e-11 * np.abs(exact).max())
+
+
+def test_manufactured_discrete_solution_with_sphere_coefficients():
+    n = (32, 32, 32)
+    bc = [WALL] * 3
+    L = G.measure(n, bc, dict(centre=(15.3, 16.6, 16.1), radius=7.0))[2]
+    per = [False] * 3
+    h = P.Hierarchy(L, auto_levels(n), per)
+    act = h.active[0]
+    ps = P.remove_mean(np.random.default_rng(5).standard_normal(n), act)
+    b = P.apply_A(L, ps, per)
+    x, k, hist, ok = P.solve(h, b, tol=1e-10, max_vcycles=200)
+    assert ok and hist[-1] <= 1e-10
+    err = np.linalg.norm(P.remove_mean(x, act) - ps) / np.linalg.norm(ps)
+    assert err < 1e-6
+
+
+@pytest.mark.parametrize("n,per", [((32, 32, 32), True), ((32, 32, 32), False),
+                                   ((64, 64, 64), True), ((128, 128), True)])
+def test_vcycle_contraction(n, per):
+    """Residual contraction per V-cycle from a random RHS (measured: 3D
+    ~0.32-0.39 mean over 8 cycles, 2D ~0.12)."""
+    d = len(n)
+    bc = [PERIODIC if per else WALL] * d
+    L = G.measure(n, bc)[2]
+    h = P.Hierarchy(L, auto_levels(n), [per] * d)
+    b = np.random.default_rng(6).standard_normal(n)
+    x, k, hist, _ = P.solve(h, b, tol=0.0, max_vcycles=8)
+    rho = [hist[i + 1] / hist[i] for i in range(8)]
+    assert np.mean(rho) <= 0.45
+    assert max(rho) <= 0.6
+
+
+def test_zero_rhs_returns_zero_and_replay_count_is_exact():
+    n = (8, 8)
+    L = G.measure(n, [PERIODIC] * 2)[2]
+    h = P.Hierarchy(L, 2, [True, True])
+    x, k, hist, ok = P.solve(h, np.zeros(n), x0=np.ones(n))
+    assert k == 0 and np.all(x == 0.0)
+    b = np.random.default_rng(7).standard_normal(n)
+    x, k, hist, ok = P.solve(h, b, force_vcycles=3)
+    assert k == 3 and len(hist) == 4
