@@ -1,0 +1,189 @@
+/*
+ * wl.h - C ABI of the MI355X (gfx950) incompressible Navier-Stokes hot path.
+ *
+ * Method: Weymouth & Font, "WaterLily.jl: A differentiable fluid simulator in
+ * Julia with fast heterogeneous execution" (arXiv 2304.08159), Sec. 2: a
+ * uniform Cartesian grid, third-order finite-volume convection-diffusion with
+ * explicit adaptive time stepping and implicit LES, Boundary Data Immersion
+ * (BDIM) of a signed-distance body that also modifies the pressure-Poisson
+ * matrix, and a geometric-multigrid (GMG) pressure solve followed by the
+ * pressure-gradient update u[I,i] -= coeff[I,i]*(p[I]-p[I-del(i)]).
+ * Sec. 3 (Tables 1-2) times the step simstep! and its routines convdiff!,
+ * BDIM!, BC!, project! and CFL!.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  Grid      : n[0] x n[1] x n[2] cells, spacing 1.  2D problems use
+ *              ndim = 2 and n[2] = 1.  Cell I has centre I + 1/2.
+ *  Layout    : every field is an interior-only, contiguous array of
+ *              n[0]*n[1]*n[2] elements, x fastest (index x + n0*(y + n1*z)).
+ *              Velocity component i sits on the LOWER i-face of each cell.
+ *              In a non-periodic direction i the stored face with index 0 is
+ *              the domain-boundary face; the upper x boundary face of an
+ *              OUTFLOW boundary is a separate plane of n[1]*n[2] values
+ *              (field WL_FIELD_UOUT, y fastest).
+ *  Precision : WL_FP32 fields are float, WL_FP64 fields are double,
+ *              WL_MIXED: float fields, FP32 V-cycles, FP64 outer
+ *              defect-correction residual; Poisson x, b and coefficients are
+ *              double in MIXED mode.
+ *  Memory    : all array arguments are DEVICE pointers owned by the caller.
+ *              The library never allocates device memory: each handle lives
+ *              in a caller-supplied device workspace whose exact size the
+ *              *_footprint call returns (host-only computation).  The library
+ *              keeps the workspace and the stream given at creation, and no
+ *              other pointer beyond a call.
+ *  Streams   : work is enqueued on the creation stream (a hipStream_t passed
+ *              as void*, NULL = default stream).  Calls that return scalar
+ *              results (residuals, V-cycle counts, dt) synchronise it.
+ *  Errors    : every call returns a wl_status; negative values are errors and
+ *              wl_last_error() gives a message (thread-local, valid until the
+ *              next call on the same thread).  WL_ERR_NOT_CONVERGED leaves
+ *              the last iterate in place with its residual reported; after
+ *              any other error the outputs are unspecified and the handle
+ *              remains usable unless the status is WL_ERR_HIP.
+ *  Threads   : a handle must not be used from two threads at once.
+ */
+#ifndef WL_H
+#define WL_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    WL_OK = 0,
+    WL_ERR_INVALID_ARG = -1,
+    WL_ERR_OUT_OF_MEMORY = -2,   /* workspace smaller than the footprint       */
+    WL_ERR_NOT_CONVERGED = -3,   /* max V-cycles reached before the tolerance */
+    WL_ERR_NONFINITE = -4,       /* NaN/Inf met in a residual norm            */
+    WL_ERR_HIP = -5,             /* a HIP runtime call failed                 */
+    WL_ERR_STATE = -6            /* call not valid in the handle's state      */
+} wl_status;
+
+typedef enum { WL_FP32 = 0, WL_FP64 = 1, WL_MIXED = 2 } wl_precision;
+
+/* Domain-face boundary codes.  PERIODIC must be set on both faces of a
+ * direction.  INFLOW only on the lower x face, OUTFLOW only on the upper x
+ * face.  For the pressure every non-periodic face is homogeneous Neumann. */
+typedef enum {
+    WL_BC_PERIODIC = 0,
+    WL_BC_INFLOW = 1,   /* velocity = U on the boundary face and its ghosts  */
+    WL_BC_OUTFLOW = 2,  /* convective outflow plane with exit-flux balance   */
+    WL_BC_WALL = 3      /* free-slip wall (zero normal velocity)             */
+} wl_bc;
+
+/* Body given by its signed-distance function (Sec. 2): kind 0 = none,
+ * kind 1 = sphere (circle when ndim = 2) of the given centre and radius in
+ * cell units.  eps is the BDIM kernel half-width (<= 0 selects 1 cell). */
+typedef struct {
+    int kind;
+    double centre[3];
+    double radius;
+    double eps;
+} wl_body;
+
+typedef struct {
+    int ndim;             /* 2 or 3                                          */
+    int n[3];             /* cells per direction (n[2] = 1 when ndim = 2)     */
+    int bc_lo[3];         /* wl_bc per lower domain face                      */
+    int bc_hi[3];         /* wl_bc per upper domain face                      */
+    double U[3];          /* inflow / reference velocity, cells per time unit */
+    double nu;            /* kinematic viscosity in grid units                */
+    wl_body body;
+    int prec;             /* wl_precision                                     */
+    int mg_levels;        /* 0 = automatic coarsening                         */
+    double tol;           /* relative residual of each pressure solve         */
+    int max_vcycles;      /* per pressure solve (<= 0 selects 100)            */
+    int inner_vcycles;    /* MIXED: FP32 V-cycles per outer iteration (0: 3)  */
+    double cfl;           /* CFL number of the adaptive time step (0: 0.5)    */
+} wl_sim_desc;
+
+typedef struct {
+    double dt;            /* time step taken                                  */
+    double t;             /* simulation time after the step                   */
+    int vcycles[2];       /* V-cycles of the predictor and corrector solves   */
+    double rel_resid[2];  /* final relative residuals of the two solves       */
+} wl_step_stats;
+
+/* Fields addressable by wl_set_field / wl_get_field. */
+enum {
+    WL_FIELD_U0 = 0, WL_FIELD_U1 = 1, WL_FIELD_U2 = 2,  /* velocity, r/w     */
+    WL_FIELD_P = 3,                                     /* pressure, r/w     */
+    WL_FIELD_UOUT = 4,     /* outflow plane (n1*n2), r/w                     */
+    WL_FIELD_L0 = 5, WL_FIELD_L1 = 6, WL_FIELD_L2 = 7,  /* Poisson coeff, r  */
+    WL_FIELD_MU0_0 = 8, WL_FIELD_MU0_1 = 9, WL_FIELD_MU0_2 = 10, /* mu0, r   */
+    WL_FIELD_MU1N = 11,    /* (mu1 n)_ij, 9 consecutive fields i*3+j, r      */
+    WL_FIELD_SIGMA = 20    /* projection RHS of the last stage, r            */
+};
+
+typedef struct wl_sim wl_sim;
+typedef struct wl_poisson wl_poisson;
+
+/* ---- Navier-Stokes simulation (the simstep! analogue, Sec. 2-3) -------- */
+
+/* Exact workspace size in bytes for a simulation described by desc.
+ * Host-only; validates desc (WL_ERR_INVALID_ARG on a bad description). */
+wl_status wl_sim_footprint(const wl_sim_desc* desc, size_t* bytes);
+
+/* Create a simulation in the caller's device workspace (>= footprint bytes,
+ * 256-byte aligned).  Measures the body (BDIM moments and Poisson
+ * coefficients on every multigrid level), sets u = U on every face (boundary
+ * faces to their boundary values), p = 0, t = 0, and synchronises. */
+wl_status wl_sim_create(const wl_sim_desc* desc, void* workspace, size_t ws_bytes,
+                        void* hip_stream, wl_sim** out);
+wl_status wl_sim_destroy(wl_sim* sim);
+
+/* Copy one field from / to a caller device array in the layout above.
+ * Writing U or UOUT invalidates the cached CFL maximum.  mu1n fields use
+ * field WL_FIELD_MU1N + 3*i + j. */
+wl_status wl_set_field(wl_sim* sim, int field, const void* src);
+wl_status wl_get_field(const wl_sim* sim, int field, void* dst);
+wl_status wl_set_time(wl_sim* sim, double t);
+
+/* Advance one Heun step (predictor and corrector, each: convection-diffusion,
+ * BDIM blend, boundary rules, divergence, GMG pressure solve, projection).
+ * dt <= 0 selects the CFL-adaptive step from the current velocity.  stats
+ * may be NULL.  Returns WL_ERR_NOT_CONVERGED when a solve hits max_vcycles
+ * (the step is still completed with the last iterate). */
+wl_status wl_step(wl_sim* sim, double dt, wl_step_stats* stats);
+
+/* ---- Standalone pressure-Poisson GMG solve (project!, Sec. 2) ---------- */
+
+/* Exact workspace size of a Poisson solver.  periodic[i] != 0 makes
+ * direction i periodic, otherwise its faces are Neumann.  levels = 0 selects
+ * automatic coarsening. */
+wl_status wl_poisson_footprint(int ndim, const int n[3], const int periodic[3], int prec,
+                               int levels, size_t* bytes);
+wl_status wl_poisson_create(int ndim, const int n[3], const int periodic[3], int prec,
+                            int levels, void* workspace, size_t ws_bytes, void* hip_stream,
+                            wl_poisson** out);
+
+/* Solve A x = b with A the coefficient-weighted 2d-point operator
+ *   (A x)(I) = sum_i L_i(I+delta_i)(x(I+delta_i)-x(I)) - L_i(I)(x(I)-x(I-delta_i)).
+ * coeffs: ndim consecutive face arrays L_0, L_1[, L_2] (lower faces, layout
+ * above); the lower face of a non-periodic direction is treated as zero.
+ * Pass NULL to reuse the coefficients of the previous call.  x: initial guess
+ * in, solution out.  b is read only: the solver uses b with inactive cells
+ * (all face coefficients zero) dropped and the active mean removed.  V-cycles
+ * run until ||b - A x|| <= tol ||b|| (tested before each cycle) or
+ * max_vcycles.  vcycles_out / rel_resid_out may be NULL. */
+wl_status wl_poisson_solve(wl_poisson* ps, const void* coeffs, void* x, const void* b,
+                           double tol, int max_vcycles, int* vcycles_out,
+                           double* rel_resid_out);
+wl_status wl_poisson_destroy(wl_poisson* ps);
+
+/* ---- Misc --------------------------------------------------------------- */
+
+/* Message of the last error on this thread ("" when none). */
+const char* wl_last_error(void);
+
+/* Library version string. */
+const char* wl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WL_H */

@@ -1,0 +1,187 @@
+"""MI355X (gfx950) hot path of a WaterLily-style incompressible NS solver.
+
+Python face of libwl (include/wl.h): torch supplies device memory (the
+workspace and field tensors) and the HIP stream; every step of the method
+runs in the HIP kernels of libwl.so.  Field tensors use the library layout,
+shape (n2, n1, n0) contiguous (x fastest), dtype float32 for WL_FP32 /
+WL_MIXED simulations and float64 for WL_FP64.
+
+Paper: Weymouth & Font, arXiv 2304.08159 (Sec. 2: method; Sec. 3: simstep!
+and its routines).
+"""
+
+import ctypes
+
+from . import _lib
+from ._lib import (FIELD_L0, FIELD_MU0_0, FIELD_MU1N, FIELD_P, FIELD_SIGMA, FIELD_U0,  # noqa: F401
+                   FIELD_UOUT, INFLOW, OUTFLOW, PERIODIC, WALL, WL_FP32, WL_FP64, WL_MIXED,
+                   WlError, check, load)
+
+__all__ = ["Sim", "Poisson", "load", "WlError", "WL_FP32", "WL_FP64", "WL_MIXED",
+           "PERIODIC", "INFLOW", "OUTFLOW", "WALL"]
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("libwl needs a ROCm GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _stream(torch):
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _workspace(torch, nbytes, device):
+    # 256-byte aligned byte buffer owned by torch
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws, ctypes.c_void_p(ws.data_ptr() + off), nbytes
+
+
+class Sim:
+    """One Navier-Stokes configuration resident on the GPU (wl_sim)."""
+
+    def __init__(self, n, bc_lo, bc_hi, U, nu, body=None, prec=WL_FP32, levels=0, tol=1e-5,
+                 max_vcycles=100, inner_vcycles=3, cfl=0.5, eps=1.0, device="cuda"):
+        torch = _torch()
+        lib = load()
+        n = tuple(int(m) for m in n)
+        ndim = len(n)
+        d = _lib.SimDesc()
+        d.ndim = ndim
+        nn = list(n) + [1] * (3 - ndim)
+        bl = list(bc_lo) + [WALL] * (3 - ndim)
+        bh = list(bc_hi) + [WALL] * (3 - ndim)
+        Uv = list(U) + [0.0] * (3 - ndim)
+        for i in range(3):
+            d.n[i], d.bc_lo[i], d.bc_hi[i], d.U[i] = nn[i], bl[i], bh[i], float(Uv[i])
+        d.nu = float(nu)
+        if body is not None:
+            d.body.kind = 1
+            c = list(body["centre"]) + [0.0] * (3 - ndim)
+            for i in range(3):
+                d.body.centre[i] = float(c[i])
+            d.body.radius = float(body["radius"])
+            d.body.eps = float(body.get("eps", eps))
+        d.prec, d.mg_levels, d.tol = int(prec), int(levels), float(tol)
+        d.max_vcycles, d.inner_vcycles, d.cfl = int(max_vcycles), int(inner_vcycles), float(cfl)
+        nbytes = ctypes.c_size_t()
+        check(lib.wl_sim_footprint(ctypes.byref(d), ctypes.byref(nbytes)))
+        self.footprint = nbytes.value
+        self._ws, wptr, wlen = _workspace(torch, nbytes.value, device)
+        h = ctypes.c_void_p()
+        check(lib.wl_sim_create(ctypes.byref(d), wptr, wlen, _stream(torch), ctypes.byref(h)))
+        self._h = h
+        self._lib = lib
+        self.desc = d
+        self.n = n
+        self.ndim = ndim
+        self.shape = (nn[2], nn[1], nn[0])
+        self.dtype = torch.float64 if prec == WL_FP64 else torch.float32
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.wl_sim_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _field_shape(self, field):
+        if field == FIELD_UOUT:
+            return (self.shape[0], self.shape[1])
+        return self.shape
+
+    def get(self, field):
+        torch = _torch()
+        t = torch.empty(self._field_shape(field), dtype=self.dtype, device=self.device)
+        check(self._lib.wl_get_field(self._h, int(field), _ptr(t)))
+        return t
+
+    def set(self, field, value):
+        torch = _torch()
+        t = value.to(device=self.device, dtype=self.dtype).contiguous()
+        if tuple(t.shape) != self._field_shape(field):
+            raise ValueError(f"field shape {tuple(t.shape)} != {self._field_shape(field)}")
+        check(self._lib.wl_set_field(self._h, int(field), _ptr(t)))
+        torch.cuda.current_stream().synchronize()
+
+    def velocity(self):
+        return [self.get(FIELD_U0 + i) for i in range(self.ndim)]
+
+    def pressure(self):
+        return self.get(FIELD_P)
+
+    def set_time(self, t):
+        check(self._lib.wl_set_time(self._h, float(t)))
+
+    def step(self, dt=0.0, allow_not_converged=False):
+        st = _lib.StepStats()
+        check(self._lib.wl_step(self._h, float(dt), ctypes.byref(st)),
+              allow=(-3,) if allow_not_converged else ())
+        return dict(dt=st.dt, t=st.t, vcycles=(st.vcycles[0], st.vcycles[1]),
+                    rel_resid=(st.rel_resid[0], st.rel_resid[1]))
+
+
+class Poisson:
+    """Standalone GMG pressure solver (wl_poisson)."""
+
+    def __init__(self, n, periodic, prec=WL_FP32, levels=0, device="cuda"):
+        torch = _torch()
+        lib = load()
+        n = tuple(int(m) for m in n)
+        ndim = len(n)
+        nn = (ctypes.c_int * 3)(*(list(n) + [1] * (3 - ndim)))
+        per = (ctypes.c_int * 3)(*([int(bool(p)) for p in periodic] + [0] * (3 - ndim)))
+        nbytes = ctypes.c_size_t()
+        check(lib.wl_poisson_footprint(ndim, nn, per, int(prec), int(levels), ctypes.byref(nbytes)))
+        self.footprint = nbytes.value
+        self._ws, wptr, wlen = _workspace(torch, nbytes.value, device)
+        h = ctypes.c_void_p()
+        check(lib.wl_poisson_create(ndim, nn, per, int(prec), int(levels), wptr, wlen,
+                                    _stream(torch), ctypes.byref(h)))
+        self._h = h
+        self._lib = lib
+        self.ndim = ndim
+        self.shape = (nn[2], nn[1], nn[0])
+        self.prec = prec
+        self.dtype = torch.float32 if prec == WL_FP32 else torch.float64
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.wl_poisson_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, coeffs, x, b, tol=1e-8, max_vcycles=100, allow_not_converged=False):
+        """coeffs: tensor (ndim, n2, n1, n0) or None (reuse); x: initial guess,
+        overwritten with the solution; b: right-hand side.  Returns
+        (vcycles, relative residual)."""
+        for t in (x, b) + ((coeffs,) if coeffs is not None else ()):
+            if t.dtype != self.dtype or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError(f"tensors must be contiguous {self.dtype} on the GPU")
+        if tuple(x.shape) != self.shape or tuple(b.shape) != self.shape:
+            raise ValueError("x / b shape mismatch")
+        if coeffs is not None and tuple(coeffs.shape) != (self.ndim,) + self.shape:
+            raise ValueError("coeffs shape mismatch")
+        vc = ctypes.c_int()
+        rel = ctypes.c_double()
+        cptr = _ptr(coeffs) if coeffs is not None else ctypes.c_void_p()
+        check(self._lib.wl_poisson_solve(self._h, cptr, _ptr(x), _ptr(b), float(tol),
+                                         int(max_vcycles), ctypes.byref(vc), ctypes.byref(rel)),
+              allow=(-3,) if allow_not_converged else ())
+        return vc.value, rel.value

@@ -1,0 +1,100 @@
+"""ctypes binding of libwl.so (argument marshalling only).
+
+Every computation happens in the HIP library; this module converts Python
+arguments into the C ABI declared in include/wl.h and hands torch device
+pointers and the current HIP stream to it.  There is no fallback: when the
+library is missing or no GPU is present, the calls raise.
+"""
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwl.so")
+
+WL_OK = 0
+STATUS = {
+    0: "WL_OK", -1: "WL_ERR_INVALID_ARG", -2: "WL_ERR_OUT_OF_MEMORY",
+    -3: "WL_ERR_NOT_CONVERGED", -4: "WL_ERR_NONFINITE", -5: "WL_ERR_HIP", -6: "WL_ERR_STATE",
+}
+WL_FP32, WL_FP64, WL_MIXED = 0, 1, 2
+PERIODIC, INFLOW, OUTFLOW, WALL = 0, 1, 2, 3
+
+FIELD_U0, FIELD_U1, FIELD_U2, FIELD_P, FIELD_UOUT = 0, 1, 2, 3, 4
+FIELD_L0, FIELD_MU0_0, FIELD_MU1N, FIELD_SIGMA = 5, 8, 11, 20
+
+# Every symbol include/wl.h declares.
+EXPORTS = (
+    "wl_sim_footprint", "wl_sim_create", "wl_sim_destroy", "wl_set_field", "wl_get_field",
+    "wl_set_time", "wl_step", "wl_poisson_footprint", "wl_poisson_create",
+    "wl_poisson_solve", "wl_poisson_destroy", "wl_last_error", "wl_version",
+)
+
+
+class WlError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Body(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("centre", ctypes.c_double * 3),
+                ("radius", ctypes.c_double), ("eps", ctypes.c_double)]
+
+
+class SimDesc(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int * 3),
+                ("bc_lo", ctypes.c_int * 3), ("bc_hi", ctypes.c_int * 3),
+                ("U", ctypes.c_double * 3), ("nu", ctypes.c_double), ("body", Body),
+                ("prec", ctypes.c_int), ("mg_levels", ctypes.c_int), ("tol", ctypes.c_double),
+                ("max_vcycles", ctypes.c_int), ("inner_vcycles", ctypes.c_int),
+                ("cfl", ctypes.c_double)]
+
+
+class StepStats(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("t", ctypes.c_double),
+                ("vcycles", ctypes.c_int * 2), ("rel_resid", ctypes.c_double * 2)]
+
+
+_lib = None
+
+
+def load():
+    """Load libwl.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2304_08159_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, f64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    ip3 = ctypes.POINTER(ctypes.c_int)
+    sig = {
+        "wl_sim_footprint": [ctypes.POINTER(SimDesc), ctypes.POINTER(sz)],
+        "wl_sim_create": [ctypes.POINTER(SimDesc), vp, sz, vp, ctypes.POINTER(vp)],
+        "wl_sim_destroy": [vp],
+        "wl_set_field": [vp, i32, vp],
+        "wl_get_field": [vp, i32, vp],
+        "wl_set_time": [vp, f64],
+        "wl_step": [vp, f64, ctypes.POINTER(StepStats)],
+        "wl_poisson_footprint": [i32, ip3, ip3, i32, i32, ctypes.POINTER(sz)],
+        "wl_poisson_create": [i32, ip3, ip3, i32, i32, vp, sz, vp, ctypes.POINTER(vp)],
+        "wl_poisson_solve": [vp, vp, vp, vp, f64, i32, ctypes.POINTER(i32), ctypes.POINTER(f64)],
+        "wl_poisson_destroy": [vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.wl_last_error.restype = ctypes.c_char_p
+    lib.wl_last_error.argtypes = []
+    lib.wl_version.restype = ctypes.c_char_p
+    lib.wl_version.argtypes = []
+    _lib = lib
+    return lib
+
+
+def check(status, allow=()):
+    if status != WL_OK and status not in allow:
+        raise WlError(status, load().wl_last_error().decode())
+    return status

@@ -1,0 +1,683 @@
+// C ABI of libwl: argument checking, workspace carving and the orchestration
+// of one Navier-Stokes step (paper Sec. 2-3: simstep! = convdiff!, BDIM!,
+// BC!, project!, CFL!) and of the standalone GMG pressure solve.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "wl_internal.h"
+#include "wl_ns.h"
+
+namespace wl {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+void clear_error() { g_err.clear(); }
+
+static wl_status invalid(const std::string& msg) {
+    set_error(msg);
+    return WL_ERR_INVALID_ARG;
+}
+
+// ------------------------------------------------------------ simulation
+
+struct SimConfig {
+    wl_sim_desc d;
+    Grid g;
+    int nlev;
+    bool allper, unif, outflow, body;
+    size_t N, P;  // cells, outflow-plane points
+};
+
+static wl_status check_desc(const wl_sim_desc* desc, SimConfig* cfg) {
+    if (!desc) return invalid("desc is NULL");
+    wl_sim_desc d = *desc;
+    if (d.ndim != 2 && d.ndim != 3) return invalid("ndim must be 2 or 3");
+    if (d.ndim == 2) {
+        if (d.n[2] != 1) return invalid("2D problems need n[2] == 1");
+        d.bc_lo[2] = d.bc_hi[2] = WL_BC_WALL;
+    }
+    for (int i = 0; i < d.ndim; ++i) {
+        if (d.n[i] < 4) return invalid("every direction needs at least 4 cells");
+        const int lo = d.bc_lo[i], hi = d.bc_hi[i];
+        if (lo < 0 || lo > 3 || hi < 0 || hi > 3) return invalid("unknown boundary code");
+        if ((lo == WL_BC_PERIODIC) != (hi == WL_BC_PERIODIC))
+            return invalid("periodic boundaries must be set on both faces of a direction");
+        if (lo == WL_BC_OUTFLOW) return invalid("OUTFLOW is only valid on the upper x face");
+        if (hi == WL_BC_INFLOW) return invalid("INFLOW is only valid on the lower x face");
+        if (i > 0 && (lo == WL_BC_INFLOW || hi == WL_BC_OUTFLOW))
+            return invalid("INFLOW/OUTFLOW are only valid on the x faces");
+    }
+    if (d.prec < 0 || d.prec > 2) return invalid("prec must be WL_FP32, WL_FP64 or WL_MIXED");
+    if (!(d.nu >= 0.0)) return invalid("nu must be >= 0");
+    if (d.cfl <= 0.0) d.cfl = 0.5;
+    if (d.max_vcycles <= 0) d.max_vcycles = 100;
+    if (d.inner_vcycles <= 0) d.inner_vcycles = 3;
+    if (!(d.tol >= 0.0)) return invalid("tol must be >= 0");
+    if (d.body.kind != 0 && d.body.kind != 1) return invalid("body.kind must be 0 or 1");
+    if (d.body.kind == 1 && !(d.body.radius > 0.0)) return invalid("body radius must be > 0");
+    if (!(d.body.eps > 0.0)) d.body.eps = 1.0;
+    if (d.mg_levels < 0 || d.mg_levels > kMaxLevels) return invalid("mg_levels out of range");
+    SimConfig c;
+    c.d = d;
+    c.g = Grid{d.n[0], d.n[1], d.n[2], d.bc_lo[0] == WL_BC_PERIODIC, d.bc_lo[1] == WL_BC_PERIODIC,
+               d.ndim == 3 && d.bc_lo[2] == WL_BC_PERIODIC, d.ndim};
+    c.nlev = auto_levels(d.ndim, d.n, d.mg_levels);
+    if (d.mg_levels > 0 && c.nlev != d.mg_levels)
+        return invalid("the requested number of multigrid levels needs more even halvings");
+    {
+        int m[3] = {d.n[0], d.n[1], d.n[2]};
+        for (int l = 1; l < c.nlev; ++l)
+            for (int i = 0; i < d.ndim; ++i) m[i] /= 2;
+        if (size_t(m[0]) * m[1] * m[2] > size_t(kCoarseMax))
+            return invalid("coarsest multigrid level exceeds 1024 cells (request more levels)");
+    }
+    c.allper = c.g.per0 && c.g.per1 && (d.ndim == 2 || c.g.per2);
+    c.body = d.body.kind == 1;
+    c.unif = c.allper && !c.body;
+    c.outflow = d.bc_hi[0] == WL_BC_OUTFLOW;
+    c.N = cells(c.g);
+    c.P = size_t(d.n[1]) * d.n[2];
+    *cfg = c;
+    return WL_OK;
+}
+
+template <typename T>
+struct SimImpl {
+    SimConfig cfg;
+    T* vel[3][3];         // three buffer sets of the velocity components
+    T* plane[3] = {nullptr, nullptr, nullptr};  // outflow planes
+    int S = 0;            // buffer set holding the state
+    int PS = 0;           // plane holding the state's outflow plane
+    T* p = nullptr;
+    T* sigma = nullptr;
+    T* mu0[3];
+    T* mu1n[9];
+    Hierarchy<T> h;
+    Reduce red;
+    double* scal = nullptr;  // [0] dt, [1] dt_next, [2] cfl max
+    int dt_cur = 0;          // which scalar holds the current dt
+    // mixed precision (T == float only)
+    Hierarchy<float>* h32 = nullptr;
+    Mixed64 mix;
+    double* p64 = nullptr;
+    double* sigma64 = nullptr;
+    double t = 0.0;
+    bool cfl_valid = false;
+};
+
+template <typename T>
+static void carve_sim(Carver& c, SimImpl<T>& s, const SimConfig& cfg) {
+    s.cfg = cfg;
+    const size_t N = cfg.N;
+    for (int b = 0; b < 3; ++b)
+        for (int i = 0; i < 3; ++i) s.vel[b][i] = c.take<T>(N);
+    if (cfg.outflow)
+        for (int b = 0; b < 3; ++b) s.plane[b] = c.take<T>(cfg.P);
+    s.p = c.take<T>(N);
+    s.sigma = c.take<T>(N);
+    for (int i = 0; i < 3; ++i) s.mu0[i] = c.take<T>(N);
+    for (int i = 0; i < 9; ++i) s.mu1n[i] = c.take<T>(N);
+    const int per[3] = {cfg.g.per0, cfg.g.per1, cfg.g.per2};
+    carve_hierarchy<T>(c, s.h, cfg.d.ndim, cfg.d.n, per, cfg.nlev, cfg.d.prec == WL_MIXED);
+    s.red.slots = reduce_slots_for(cfg.g);
+    s.red.partial = c.take<double>(2 * s.red.slots);
+    s.red.result = c.take<double>(8);
+    s.scal = c.take<double>(4);
+    if (cfg.d.prec == WL_MIXED) {
+        for (int i = 0; i < 3; ++i) s.mix.L[i] = c.take<double>(N);
+        s.mix.inner = cfg.d.inner_vcycles;
+        s.p64 = c.take<double>(N);
+        s.sigma64 = c.take<double>(N);
+    }
+}
+
+template <typename T>
+static VelField<T> field_of(const SimImpl<T>& s, int set, const T* plane) {
+    VelField<T> V;
+    for (int i = 0; i < 3; ++i) V.u[i] = s.vel[set][i];
+    V.uout = plane;
+    V.g = s.cfg.g;
+    for (int i = 0; i < 3; ++i) {
+        V.bclo[i] = s.cfg.d.bc_lo[i];
+        V.bchi[i] = s.cfg.d.bc_hi[i];
+        V.U[i] = T(s.cfg.d.U[i]);
+    }
+    return V;
+}
+
+}  // namespace wl
+
+struct wl_sim {
+    int prec;
+    hipStream_t stream;
+    void* impl;  // wl::SimImpl<float> or wl::SimImpl<double>
+};
+
+struct wl_poisson {
+    int prec;
+    hipStream_t stream;
+    void* impl;
+};
+
+namespace wl {
+
+template <typename T>
+static wl_status sim_init(SimImpl<T>& s, hipStream_t st) {
+    const SimConfig& c = s.cfg;
+    const size_t N = c.N;
+    // geometry: BDIM moments and fine Poisson coefficients
+    BodyDev body{c.d.body.kind,
+                 {c.d.body.centre[0], c.d.body.centre[1], c.d.body.centre[2]},
+                 c.d.body.radius,
+                 c.d.body.eps};
+    MeasureOut<T> M;
+    for (int i = 0; i < 3; ++i) {
+        M.mu0[i] = s.mu0[i];
+        M.L[i] = s.h.lev[0].L[i];
+        M.L64[i] = s.mix.L[i];
+    }
+    for (int i = 0; i < 9; ++i) M.mu1n[i] = s.mu1n[i];
+    WL_TRY(ns_measure<T>(c.g, body, c.d.bc_lo, M, st));
+    s.h.lev[0].uniform = c.unif ? 1 : 0;
+    s.h.lev[0].Lc = T(1);
+    WL_TRY(mg_coarsen_all<T>(s.h, st));
+    if (c.d.prec == WL_MIXED) {
+        s.h.coarse_tol = 1e-6;
+    } else {
+        s.h.coarse_tol = sizeof(T) == 8 ? 1e-10 : 1e-6;
+    }
+    WL_TRY(mg_count_active<T>(s.h, s.red, st));
+    // initial state: u = U on every face, boundary faces at their values, p = 0
+    {
+        T* u0[3] = {s.vel[0][0], s.vel[0][1], s.vel[0][2]};
+        WL_TRY(ns_init_velocity<T>(c.g, c.d.bc_lo, c.d.U, u0, st));
+    }
+    if (c.outflow)
+        for (int b = 0; b < 3; ++b) WL_TRY(fill<T>(s.plane[b], c.P, T(c.d.U[0]), st));
+    WL_TRY(fill<T>(s.p, N, T(0), st));
+    if (s.p64) WL_TRY(fill<double>(s.p64, N, 0.0, st));
+    s.S = 0;
+    s.PS = 0;
+    s.t = 0.0;
+    s.cfl_valid = false;
+    WL_CHECK_HIP(hipStreamSynchronize(st));
+    return WL_OK;
+}
+
+template <typename T>
+static wl_status pressure_solve(SimImpl<T>& s, hipStream_t st, SolveResult* r) {
+    const SimConfig& c = s.cfg;
+    if (c.d.prec == WL_MIXED) {
+        if constexpr (sizeof(T) == 4) {
+            WL_TRY((convert<float, double>(s.sigma, s.sigma64, c.N, st)));
+            wl_status rc = mg_solve_mixed(s.h, s.mix, s.red, s.p64, s.sigma64, c.d.tol,
+                                          c.d.max_vcycles, st, r);
+            if (rc != WL_OK && rc != WL_ERR_NOT_CONVERGED) return rc;
+            WL_TRY((convert<double, float>(s.p64, s.p, c.N, st)));
+            return rc;
+        }
+        return invalid("mixed precision needs FP32 fields");
+    }
+    return mg_solve<T>(s.h, s.red, s.p, s.sigma, c.d.tol, c.d.max_vcycles, st, r);
+}
+
+template <typename T>
+static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hipStream_t st) {
+    const SimConfig& c = s.cfg;
+    const bool ap = c.allper;
+    double* dt_dev = s.scal + s.dt_cur;
+    if (dt_in > 0.0) {
+        WL_TRY(ns_set_scalar(dt_dev, dt_in, st));
+    } else if (!s.cfl_valid) {
+        WL_TRY(ns_cfl<T>(field_of(s, s.S, s.plane[s.PS]), ap, s.red.partial, st));
+        WL_TRY(ns_dt_from_max(s.red.partial, s.red.slots, c.d.cfl, 2.0 * c.d.ndim * c.d.nu, dt_dev,
+                              s.scal + 2, st));
+    }
+    const int S = s.S;
+    const int A = (S + 1) % 3, B = (S + 2) % 3;
+    const int PS = s.PS, P1 = (PS + 1) % 3, P2 = (PS + 2) % 3;
+    const T* un[3] = {s.vel[S][0], s.vel[S][1], s.vel[S][2]};
+    wl_status worst = WL_OK;
+    SolveResult r1, r2;
+    // ---- predictor (c = 1)
+    {
+        T* f[3] = {s.vel[A][0], s.vel[A][1], s.vel[A][2]};
+        WL_TRY(ns_momentum<T>(field_of(s, S, s.plane[PS]), un, f, T(c.d.nu), false, ap, dt_dev, st));
+        if (c.outflow)
+            WL_TRY(ns_outflow<T>(c.g, s.vel[S][0], s.plane[PS], s.plane[PS], s.vel[A][0],
+                                 T(c.d.U[0]), false, dt_dev, s.plane[P1], st));
+        int us = A;
+        if (c.body) {
+            T* o[3] = {s.vel[B][0], s.vel[B][1], s.vel[B][2]};
+            BdimFields<T> bf;
+            for (int i = 0; i < 3; ++i) bf.mu0[i] = s.mu0[i];
+            for (int i = 0; i < 9; ++i) bf.mu1n[i] = s.mu1n[i];
+            WL_TRY(ns_bdim<T>(field_of(s, A, s.plane[P1]), bf, o, st));
+            us = B;
+        }
+        const VelField<T> V = field_of(s, us, s.plane[P1]);
+        WL_TRY(ns_divergence<T>(V, 1.0, dt_dev, s.sigma, ap, st));
+        wl_status rc = pressure_solve(s, st, &r1);
+        if (rc == WL_ERR_NOT_CONVERGED) worst = rc;
+        else if (rc != WL_OK) return rc;
+        ProjCoeffs<T> pc{{s.h.lev[0].L[0], s.h.lev[0].L[1], s.h.lev[0].L[2]}, T(1)};
+        T* o[3] = {s.vel[us][0], s.vel[us][1], s.vel[us][2]};
+        WL_TRY(ns_project<T>(V, s.p, pc, c.unif, 1.0, dt_dev, o, false, nullptr, ap, st));
+        // stage result now in set `us`; the remaining set is free
+        const int u1 = us;
+        const int fr = (u1 == A) ? B : A;
+        // ---- corrector (c = 1/2)
+        T* f2[3] = {s.vel[fr][0], s.vel[fr][1], s.vel[fr][2]};
+        WL_TRY(ns_momentum<T>(field_of(s, u1, s.plane[P1]), un, f2, T(c.d.nu), true, ap, dt_dev,
+                              st));
+        if (c.outflow)
+            WL_TRY(ns_outflow<T>(c.g, s.vel[u1][0], s.plane[P1], s.plane[PS], s.vel[fr][0],
+                                 T(c.d.U[0]), true, dt_dev, s.plane[P2], st));
+        int us2 = fr;
+        if (c.body) {
+            T* o2[3] = {s.vel[S][0], s.vel[S][1], s.vel[S][2]};
+            BdimFields<T> bf;
+            for (int i = 0; i < 3; ++i) bf.mu0[i] = s.mu0[i];
+            for (int i = 0; i < 9; ++i) bf.mu1n[i] = s.mu1n[i];
+            WL_TRY(ns_bdim<T>(field_of(s, fr, s.plane[P2]), bf, o2, st));
+            us2 = S;
+        }
+        const VelField<T> V2 = field_of(s, us2, s.plane[P2]);
+        WL_TRY(ns_divergence<T>(V2, 0.5, dt_dev, s.sigma, ap, st));
+        rc = pressure_solve(s, st, &r2);
+        if (rc == WL_ERR_NOT_CONVERGED) worst = rc;
+        else if (rc != WL_OK) return rc;
+        int dest = (us2 == S) ? u1 : S;
+        T* o3[3] = {s.vel[dest][0], s.vel[dest][1], s.vel[dest][2]};
+        WL_TRY(ns_project<T>(V2, s.p, pc, c.unif, 0.5, dt_dev, o3, true, s.red.partial, ap, st));
+        double* dt_next = s.scal + (1 - s.dt_cur);
+        WL_TRY(ns_dt_from_max(s.red.partial, s.red.slots, c.d.cfl, 2.0 * c.d.ndim * c.d.nu,
+                              dt_next, s.scal + 2, st));
+        s.S = dest;
+        s.PS = P2;
+    }
+    double dt = 0.0;
+    WL_CHECK_HIP(hipMemcpyAsync(&dt, dt_dev, sizeof(double), hipMemcpyDeviceToHost, st));
+    WL_CHECK_HIP(hipStreamSynchronize(st));
+    s.dt_cur = 1 - s.dt_cur;
+    s.cfl_valid = true;
+    s.t += dt;
+    if (stats) {
+        stats->dt = dt;
+        stats->t = s.t;
+        stats->vcycles[0] = r1.vcycles;
+        stats->vcycles[1] = r2.vcycles;
+        stats->rel_resid[0] = r1.rel;
+        stats->rel_resid[1] = r2.rel;
+    }
+    return worst;
+}
+
+template <typename T>
+static wl_status sim_field_ptr(SimImpl<T>& s, int field, T** ptr, size_t* count, bool writable) {
+    const SimConfig& c = s.cfg;
+    *count = c.N;
+    if (field >= WL_FIELD_U0 && field <= WL_FIELD_U2) {
+        if (field - WL_FIELD_U0 >= c.d.ndim) return invalid("velocity component beyond ndim");
+        *ptr = s.vel[s.S][field - WL_FIELD_U0];
+        return WL_OK;
+    }
+    if (field == WL_FIELD_P) {
+        *ptr = s.p;
+        return WL_OK;
+    }
+    if (field == WL_FIELD_UOUT) {
+        if (!c.outflow) return invalid("no outflow plane in this simulation");
+        *ptr = s.plane[s.PS];
+        *count = c.P;
+        return WL_OK;
+    }
+    if (writable) return invalid("field is read-only");
+    if (field >= WL_FIELD_L0 && field <= WL_FIELD_L2) {
+        *ptr = s.h.lev[0].L[field - WL_FIELD_L0];
+        return WL_OK;
+    }
+    if (field >= WL_FIELD_MU0_0 && field <= WL_FIELD_MU0_2) {
+        *ptr = s.mu0[field - WL_FIELD_MU0_0];
+        return WL_OK;
+    }
+    if (field >= WL_FIELD_MU1N && field < WL_FIELD_MU1N + 9) {
+        *ptr = s.mu1n[field - WL_FIELD_MU1N];
+        return WL_OK;
+    }
+    if (field == WL_FIELD_SIGMA) {
+        *ptr = s.sigma;
+        return WL_OK;
+    }
+    return invalid("unknown field id");
+}
+
+static size_t sim_bytes(const SimConfig& cfg) {
+    Carver c;
+    if (cfg.d.prec == WL_FP64) {
+        SimImpl<double> s;
+        carve_sim<double>(c, s, cfg);
+    } else {
+        SimImpl<float> s;
+        carve_sim<float>(c, s, cfg);
+    }
+    return c.off;
+}
+
+// ------------------------------------------------------------ Poisson
+template <typename T>
+struct PoissonImpl {
+    Grid g;
+    int nlev;
+    Hierarchy<T> h;
+    Reduce red;
+    bool have = false;
+};
+
+struct PoissonMixedImpl {
+    Grid g;
+    int nlev;
+    Hierarchy<float> h;
+    Mixed64 mix;
+    Reduce red;
+    bool have = false;
+};
+
+static wl_status check_poisson(int ndim, const int n[3], const int periodic[3], int prec, int levels,
+                               Grid* g, int* nlev) {
+    if (ndim != 2 && ndim != 3) return invalid("ndim must be 2 or 3");
+    if (!n || !periodic) return invalid("n / periodic is NULL");
+    if (ndim == 2 && n[2] != 1) return invalid("2D problems need n[2] == 1");
+    for (int i = 0; i < ndim; ++i)
+        if (n[i] < 2) return invalid("every direction needs at least 2 cells");
+    if (prec < 0 || prec > 2) return invalid("prec must be WL_FP32, WL_FP64 or WL_MIXED");
+    if (levels < 0 || levels > kMaxLevels) return invalid("levels out of range");
+    *g = Grid{n[0], n[1], n[2], periodic[0] != 0, periodic[1] != 0, ndim == 3 && periodic[2] != 0,
+              ndim};
+    *nlev = auto_levels(ndim, n, levels);
+    if (levels > 0 && *nlev != levels)
+        return invalid("the requested number of multigrid levels needs more even halvings");
+    int m[3] = {n[0], n[1], n[2]};
+    for (int l = 1; l < *nlev; ++l)
+        for (int i = 0; i < ndim; ++i) m[i] /= 2;
+    if (size_t(m[0]) * m[1] * m[2] > size_t(kCoarseMax))
+        return invalid("coarsest multigrid level exceeds 1024 cells (request more levels)");
+    return WL_OK;
+}
+
+template <typename H>
+static void carve_poisson_common(Carver& c, H& P, const Grid& g, int nlev, bool fine_x) {
+    const int n[3] = {g.n0, g.n1, g.n2};
+    const int per[3] = {g.per0, g.per1, g.per2};
+    carve_hierarchy(c, P.h, g.ndim, n, per, nlev, fine_x);
+    P.red.slots = reduce_slots_for(g);
+    P.red.partial = c.take<double>(2 * P.red.slots);
+    P.red.result = c.take<double>(8);
+}
+
+template <typename T>
+static wl_status copy_field(wl_sim* sim, int field, const void* src, void* dst) {
+    SimImpl<T>& s = *static_cast<SimImpl<T>*>(sim->impl);
+    T* ptr = nullptr;
+    size_t count = 0;
+    WL_TRY(sim_field_ptr<T>(s, field, &ptr, &count, src != nullptr));
+    if (src) {
+        WL_CHECK_HIP(hipMemcpyAsync(ptr, src, count * sizeof(T), hipMemcpyDeviceToDevice, sim->stream));
+        if (field != WL_FIELD_P) s.cfl_valid = false;
+        if (field == WL_FIELD_P && s.p64)
+            WL_TRY((convert<float, double>(reinterpret_cast<float*>(s.p), s.p64, count, sim->stream)));
+    } else {
+        WL_CHECK_HIP(hipMemcpyAsync(dst, ptr, count * sizeof(T), hipMemcpyDeviceToDevice, sim->stream));
+    }
+    WL_CHECK_HIP(hipStreamSynchronize(sim->stream));
+    return WL_OK;
+}
+
+template <typename T>
+static wl_status poisson_solve_plain(wl_poisson* ps, const void* coeffs, void* x, const void* b,
+                                     double tol, int maxv, int* vc, double* rel) {
+    PoissonImpl<T>& P = *static_cast<PoissonImpl<T>*>(ps->impl);
+    hipStream_t st = ps->stream;
+    if (coeffs) {
+        WL_TRY((mg_load_coeffs<T, T>(P.g, static_cast<const T*>(coeffs), P.h.lev[0].L, nullptr, st)));
+        P.h.lev[0].uniform = 0;
+        WL_TRY(mg_coarsen_all<T>(P.h, st));
+        WL_TRY(mg_count_active<T>(P.h, P.red, st));
+        P.have = true;
+    }
+    if (!P.have) return invalid("no coefficients given yet");
+    SolveResult r;
+    wl_status rc = mg_solve<T>(P.h, P.red, static_cast<T*>(x), static_cast<const T*>(b), tol, maxv,
+                               st, &r);
+    if (vc) *vc = r.vcycles;
+    if (rel) *rel = r.rel;
+    return rc;
+}
+
+static wl_status poisson_solve_mixed(wl_poisson* ps, const void* coeffs, void* x, const void* b,
+                                     double tol, int maxv, int* vc, double* rel) {
+    PoissonMixedImpl& P = *static_cast<PoissonMixedImpl*>(ps->impl);
+    hipStream_t st = ps->stream;
+    if (coeffs) {
+        WL_TRY((mg_load_coeffs<double, float>(P.g, static_cast<const double*>(coeffs), P.h.lev[0].L,
+                                              P.mix.L, st)));
+        P.h.lev[0].uniform = 0;
+        WL_TRY(mg_coarsen_all<float>(P.h, st));
+        WL_TRY(mg_count_active64(P.g, P.mix.L, P.red, &P.h.n_active, st));
+        P.have = true;
+    }
+    if (!P.have) return invalid("no coefficients given yet");
+    SolveResult r;
+    wl_status rc = mg_solve_mixed(P.h, P.mix, P.red, static_cast<double*>(x),
+                                  static_cast<const double*>(b), tol, maxv, st, &r);
+    if (vc) *vc = r.vcycles;
+    if (rel) *rel = r.rel;
+    return rc;
+}
+
+}  // namespace wl
+
+using namespace wl;
+
+extern "C" {
+
+const char* wl_last_error(void) { return g_err.c_str(); }
+const char* wl_version(void) { return "wl 0.1 (gfx950)"; }
+
+wl_status wl_sim_footprint(const wl_sim_desc* desc, size_t* bytes) {
+    clear_error();
+    if (!bytes) return invalid("bytes is NULL");
+    SimConfig cfg;
+    WL_TRY(check_desc(desc, &cfg));
+    *bytes = sim_bytes(cfg);
+    return WL_OK;
+}
+
+wl_status wl_sim_create(const wl_sim_desc* desc, void* workspace, size_t ws_bytes, void* hip_stream,
+                        wl_sim** out) {
+    clear_error();
+    if (!out) return invalid("out is NULL");
+    *out = nullptr;
+    SimConfig cfg;
+    WL_TRY(check_desc(desc, &cfg));
+    const size_t need = sim_bytes(cfg);
+    if (!workspace) return invalid("workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) return invalid("workspace must be 256-byte aligned");
+    if (ws_bytes < need) {
+        set_error("workspace smaller than wl_sim_footprint");
+        return WL_ERR_OUT_OF_MEMORY;
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    wl_sim* sim = new (std::nothrow) wl_sim;
+    if (!sim) return invalid("host allocation failed");
+    sim->prec = cfg.d.prec;
+    sim->stream = st;
+    Carver c;
+    c.base = static_cast<char*>(workspace);
+    wl_status rc;
+    if (cfg.d.prec == WL_FP64) {
+        auto* s = new (std::nothrow) SimImpl<double>;
+        carve_sim<double>(c, *s, cfg);
+        sim->impl = s;
+        rc = sim_init<double>(*s, st);
+    } else {
+        auto* s = new (std::nothrow) SimImpl<float>;
+        carve_sim<float>(c, *s, cfg);
+        sim->impl = s;
+        rc = sim_init<float>(*s, st);
+    }
+    if (rc != WL_OK) {
+        wl_sim_destroy(sim);
+        return rc;
+    }
+    *out = sim;
+    return WL_OK;
+}
+
+wl_status wl_sim_destroy(wl_sim* sim) {
+    clear_error();
+    if (!sim) return WL_OK;
+    if (sim->prec == WL_FP64)
+        delete static_cast<SimImpl<double>*>(sim->impl);
+    else
+        delete static_cast<SimImpl<float>*>(sim->impl);
+    delete sim;
+    return WL_OK;
+}
+
+wl_status wl_set_field(wl_sim* sim, int field, const void* src) {
+    clear_error();
+    if (!sim || !src) return invalid("sim / src is NULL");
+    return sim->prec == WL_FP64 ? copy_field<double>(sim, field, src, nullptr)
+                                : copy_field<float>(sim, field, src, nullptr);
+}
+
+wl_status wl_get_field(const wl_sim* sim, int field, void* dst) {
+    clear_error();
+    if (!sim || !dst) return invalid("sim / dst is NULL");
+    wl_sim* s = const_cast<wl_sim*>(sim);
+    return sim->prec == WL_FP64 ? copy_field<double>(s, field, nullptr, dst)
+                                : copy_field<float>(s, field, nullptr, dst);
+}
+
+wl_status wl_set_time(wl_sim* sim, double t) {
+    clear_error();
+    if (!sim) return invalid("sim is NULL");
+    if (sim->prec == WL_FP64)
+        static_cast<SimImpl<double>*>(sim->impl)->t = t;
+    else
+        static_cast<SimImpl<float>*>(sim->impl)->t = t;
+    return WL_OK;
+}
+
+wl_status wl_step(wl_sim* sim, double dt, wl_step_stats* stats) {
+    clear_error();
+    if (!sim) return invalid("sim is NULL");
+    if (sim->prec == WL_FP64)
+        return sim_step<double>(*static_cast<SimImpl<double>*>(sim->impl), dt, stats, sim->stream);
+    return sim_step<float>(*static_cast<SimImpl<float>*>(sim->impl), dt, stats, sim->stream);
+}
+
+wl_status wl_poisson_footprint(int ndim, const int n[3], const int periodic[3], int prec, int levels,
+                               size_t* bytes) {
+    clear_error();
+    if (!bytes) return invalid("bytes is NULL");
+    Grid g;
+    int nlev;
+    WL_TRY(check_poisson(ndim, n, periodic, prec, levels, &g, &nlev));
+    Carver c;
+    if (prec == WL_FP32) {
+        PoissonImpl<float> P;
+        carve_poisson_common(c, P, g, nlev, false);
+    } else if (prec == WL_FP64) {
+        PoissonImpl<double> P;
+        carve_poisson_common(c, P, g, nlev, false);
+    } else {
+        PoissonMixedImpl P;
+        carve_poisson_common(c, P, g, nlev, true);
+        for (int i = 0; i < 3; ++i) P.mix.L[i] = c.take<double>(cells(g));
+    }
+    *bytes = c.off;
+    return WL_OK;
+}
+
+wl_status wl_poisson_create(int ndim, const int n[3], const int periodic[3], int prec, int levels,
+                            void* workspace, size_t ws_bytes, void* hip_stream, wl_poisson** out) {
+    clear_error();
+    if (!out) return invalid("out is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    WL_TRY(wl_poisson_footprint(ndim, n, periodic, prec, levels, &need));
+    if (!workspace) return invalid("workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) return invalid("workspace must be 256-byte aligned");
+    if (ws_bytes < need) {
+        set_error("workspace smaller than wl_poisson_footprint");
+        return WL_ERR_OUT_OF_MEMORY;
+    }
+    Grid g;
+    int nlev;
+    WL_TRY(check_poisson(ndim, n, periodic, prec, levels, &g, &nlev));
+    wl_poisson* ps = new (std::nothrow) wl_poisson;
+    if (!ps) return invalid("host allocation failed");
+    ps->prec = prec;
+    ps->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    Carver c;
+    c.base = static_cast<char*>(workspace);
+    if (prec == WL_FP32) {
+        auto* P = new PoissonImpl<float>;
+        P->g = g;
+        P->nlev = nlev;
+        carve_poisson_common(c, *P, g, nlev, false);
+        P->h.coarse_tol = 1e-6;
+        ps->impl = P;
+    } else if (prec == WL_FP64) {
+        auto* P = new PoissonImpl<double>;
+        P->g = g;
+        P->nlev = nlev;
+        carve_poisson_common(c, *P, g, nlev, false);
+        P->h.coarse_tol = 1e-10;
+        ps->impl = P;
+    } else {
+        auto* P = new PoissonMixedImpl;
+        P->g = g;
+        P->nlev = nlev;
+        carve_poisson_common(c, *P, g, nlev, true);
+        for (int i = 0; i < 3; ++i) P->mix.L[i] = c.take<double>(cells(g));
+        P->h.coarse_tol = 1e-6;
+        ps->impl = P;
+    }
+    *out = ps;
+    return WL_OK;
+}
+
+wl_status wl_poisson_solve(wl_poisson* ps, const void* coeffs, void* x, const void* b, double tol,
+                           int max_vcycles, int* vcycles_out, double* rel_resid_out) {
+    clear_error();
+    if (!ps || !x || !b) return invalid("ps / x / b is NULL");
+    if (!(tol >= 0.0)) return invalid("tol must be >= 0");
+    if (max_vcycles <= 0) max_vcycles = 100;
+    if (ps->prec == WL_FP32)
+        return poisson_solve_plain<float>(ps, coeffs, x, b, tol, max_vcycles, vcycles_out,
+                                          rel_resid_out);
+    if (ps->prec == WL_FP64)
+        return poisson_solve_plain<double>(ps, coeffs, x, b, tol, max_vcycles, vcycles_out,
+                                           rel_resid_out);
+    return poisson_solve_mixed(ps, coeffs, x, b, tol, max_vcycles, vcycles_out, rel_resid_out);
+}
+
+wl_status wl_poisson_destroy(wl_poisson* ps) {
+    clear_error();
+    if (!ps) return WL_OK;
+    if (ps->prec == WL_FP32)
+        delete static_cast<PoissonImpl<float>*>(ps->impl);
+    else if (ps->prec == WL_FP64)
+        delete static_cast<PoissonImpl<double>*>(ps->impl);
+    else
+        delete static_cast<PoissonMixedImpl*>(ps->impl);
+    delete ps;
+    return WL_OK;
+}
+
+}  // extern "C"

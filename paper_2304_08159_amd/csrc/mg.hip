@@ -1,0 +1,754 @@
+// Matrix-free geometric multigrid for the BDIM-modified pressure Poisson
+// system (paper Sec. 2: GMG with a solution time linear in the cell count;
+// the operator is fixed by the gradient loop u[I,i] -= coeff*(p[I]-p[I-del(i)])).
+//
+// One thread per cell; every kernel is an HBM sweep with neighbour reads
+// served by L1/L2.  Damped Jacobi (w = 2d/(2d+1), two pre- and two
+// post-sweeps), residual fused with sum-restriction, piecewise-constant
+// prolongation fused with the first post-sweep, a one-workgroup FP64 CG on
+// the coarsest level, and FP64 fixed-order reductions for the norms and the
+// active-set mean.
+#include <cmath>
+#include <cstdio>
+
+#include "wl_device.h"
+
+namespace wl {
+
+// ------------------------------------------------------------ host shapes
+static unsigned pow2ceil(unsigned v) {
+    unsigned p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+Launch launch_for(int n0, int n1, int n2) {
+    Launch l;
+    unsigned bx = pow2ceil(unsigned(n0));
+    if (bx > 64) bx = 64;
+    const unsigned by = kBlock / bx;
+    l.block = dim3(bx, by, 1);
+    l.grid = dim3((n0 + bx - 1) / bx, (n1 + by - 1) / by, n2);
+    return l;
+}
+
+size_t reduce_slots_for(const Grid& g) { return launch_for(g.n0, g.n1, g.n2).nblocks(); }
+
+int auto_levels(int ndim, const int n[3], int requested) {
+    int m[3] = {n[0], n[1], n[2]};
+    int count = 1;
+    for (;;) {
+        if (requested > 0 && count >= requested) break;
+        bool even = true, big = true;
+        for (int d = 0; d < ndim; ++d) {
+            if (m[d] % 2) even = false;
+            if (m[d] / 2 < 4) big = false;
+        }
+        if (!even) break;
+        if (requested <= 0 && !big) break;
+        for (int d = 0; d < ndim; ++d) m[d] /= 2;
+        ++count;
+        if (count >= kMaxLevels) break;
+    }
+    return count;
+}
+
+template <typename T>
+void carve_hierarchy(Carver& c, Hierarchy<T>& h, int ndim, const int n[3], const int per[3],
+                     int nlev, bool alloc_fine_x) {
+    h.nlev = nlev;
+    h.omega = 2.0 * ndim / (2.0 * ndim + 1.0);
+    int m[3] = {n[0], n[1], n[2]};
+    for (int l = 0; l < nlev; ++l) {
+        Level<T>& L = h.lev[l];
+        L.g = Grid{m[0], m[1], m[2], per[0], per[1], per[2], ndim};
+        const size_t N = cells(L.g);
+        for (int d = 0; d < 3; ++d) L.L[d] = c.take<T>(N);
+        L.x[0] = (l > 0 || alloc_fine_x) ? c.take<T>(N) : nullptr;
+        L.x[1] = c.take<T>(N);
+        L.b = c.take<T>(N);
+        for (int d = 0; d < ndim; ++d) m[d] /= 2;
+    }
+}
+
+template void carve_hierarchy<float>(Carver&, Hierarchy<float>&, int, const int*, const int*, int,
+                                     bool);
+template void carve_hierarchy<double>(Carver&, Hierarchy<double>&, int, const int*, const int*,
+                                      int, bool);
+
+// ---------------------------------------------------------------- kernels
+
+// One damped-Jacobi sweep  x_out = x - w (b - A x) / D  (zero on inactive
+// cells, D = 0).  FIRST: b is the raw right-hand side; the sweep writes the
+// projected copy bproj = (b - mean) on active cells, 0 elsewhere, and uses it.
+// NORM: per-block partial sums of r^2 (and of bproj^2 when FIRST) in FP64.
+template <typename T, int XM, bool UNIF, bool NORM, bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_smooth(Grid g, XAccess<T, XM> X, Coeffs<T> C,
+                                                   const T* __restrict__ b, T omega,
+                                                   T* __restrict__ xout,
+                                                   double* __restrict__ partial,
+                                                   T* __restrict__ bproj,
+                                                   const double* __restrict__ bmean) {
+    __shared__ double lds[8];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    double r2 = 0.0, b2 = 0.0;
+    if (i < g.n0 && j < g.n1) {
+        const size_t id = cid(g, i, j, k);
+        T xI, Ax, D;
+        apply_row<T, XM, UNIF>(g, X, C, i, j, k, xI, Ax, D);
+        T bv = b[id];
+        if (FIRST) {
+            bv = (D > T(0)) ? T(double(bv) - *bmean) : T(0);
+            bproj[id] = bv;
+        }
+        const T r = bv - Ax;
+        xout[id] = (D > T(0)) ? xI - omega * r / D : T(0);
+        if (NORM) {
+            r2 = double(r) * double(r);
+            if (FIRST) b2 = double(bv) * double(bv);
+        }
+    }
+    if (NORM) {
+        const double s = block_sum(r2, lds);
+        __syncthreads();
+        const double sb = FIRST ? block_sum(b2, lds + 4) : 0.0;
+        if (threadIdx.x == 0 && threadIdx.y == 0) {
+            partial[2 * block_linear()] = s;
+            partial[2 * block_linear() + 1] = sb;
+        }
+    }
+}
+
+// Coarse right-hand side = sum of the 2^d child residuals r = b - A x.
+template <typename T, bool UNIF>
+__global__ __launch_bounds__(kBlock) void k_resid_restrict(Grid g, Grid gc, XAccess<T, XM_PLAIN> X,
+                                                           Coeffs<T> C, const T* __restrict__ b,
+                                                           T* __restrict__ bc) {
+    const int ic = blockIdx.x * blockDim.x + threadIdx.x;
+    const int jc = blockIdx.y * blockDim.y + threadIdx.y;
+    const int kc = blockIdx.z;
+    if (ic >= gc.n0 || jc >= gc.n1) return;
+    const int fz = (g.n2 > gc.n2) ? 2 : 1;
+    T sum = T(0);
+    for (int dz = 0; dz < fz; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                const int i = 2 * ic + dx, j = 2 * jc + dy, k = fz * kc + dz;
+                T xI, Ax, D;
+                apply_row<T, XM_PLAIN, UNIF>(g, X, C, i, j, k, xI, Ax, D);
+                sum += b[cid(g, i, j, k)] - Ax;
+            }
+    bc[cid(gc, ic, jc, kc)] = sum;
+}
+
+// Per-block partial sums of v over active cells (v == nullptr counts them).
+template <typename T, bool UNIF>
+__global__ __launch_bounds__(kBlock) void k_sum_active(Grid g, Coeffs<T> C, const T* __restrict__ v,
+                                                       double* __restrict__ partial) {
+    __shared__ double lds[8];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    double s = 0.0;
+    if (i < g.n0 && j < g.n1) {
+        XAccess<T, XM_ZERO> X{nullptr, nullptr, 0, 0};
+        T xI, Ax, D;
+        apply_row<T, XM_ZERO, UNIF>(g, X, C, i, j, k, xI, Ax, D);
+        if (D > T(0)) s = v ? double(v[cid(g, i, j, k)]) : 1.0;
+    }
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) partial[block_linear()] = s;
+}
+
+// out[c] = sum over slots of partial[slot*ncomp + c] in slot order; then
+// out[ncomp + c] = out[c] * scale (e.g. a mean).  One block of 1024 threads.
+__global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ partial, size_t nslots,
+                                                 int ncomp, double scale, double* __restrict__ out) {
+    __shared__ double lds[1024];
+    for (int c = 0; c < ncomp; ++c) {
+        double s = 0.0;
+        for (size_t q = threadIdx.x; q < nslots; q += blockDim.x) s += partial[q * ncomp + c];
+        lds[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) lds[threadIdx.x] += lds[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            out[c] = lds[0];
+            out[ncomp + c] = lds[0] * scale;
+        }
+        __syncthreads();
+    }
+}
+
+// Mean of the active cells: out[0] = sum, out[1] = sum / count(active)
+// where count comes from a device scalar.
+__global__ void k_mean_fix(double* out, const double* count) {
+    if (threadIdx.x == 0) out[1] = (*count > 0.0) ? out[0] / *count : 0.0;
+}
+
+// Coarsest level: CG on -A (SPD on the active set) with the right-hand side
+// restricted to the active cells and made mean-free there; FP64 internally,
+// minimum-norm (mean-free) result.  One workgroup, everything in LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_cg(Grid g, Coeffs<T> C, int uniform,
+                                                   const T* __restrict__ b, T* __restrict__ xout,
+                                                   double tol, int maxit) {
+    __shared__ double sL[3][kCoarseMax];
+    __shared__ double sx[kCoarseMax], sr[kCoarseMax], sp[kCoarseMax], sq[kCoarseMax];
+    __shared__ double red[8];
+    const int N = int(cells(g));
+    const int t = threadIdx.x, nt = blockDim.x;
+    auto dot_all = [&](double v) -> double {  // fixed-order block sum broadcast to all
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if ((t & 63) == 0) red[t >> 6] = v;
+        __syncthreads();
+        double s = 0.0;
+        for (int w = 0; w < (nt + 63) / 64; ++w) s += red[w];
+        __syncthreads();
+        return s;
+    };
+    for (int c = t; c < N; c += nt) {
+        sL[0][c] = uniform ? double(C.Lc) : double(C.L0[c]);
+        sL[1][c] = uniform ? double(C.Lc) : double(C.L1[c]);
+        sL[2][c] = (g.ndim == 3) ? (uniform ? double(C.Lc) : double(C.L2[c])) : 0.0;
+    }
+    __syncthreads();
+    auto coords = [&](int c, int& i, int& j, int& k) {
+        i = c % g.n0;
+        j = (c / g.n0) % g.n1;
+        k = c / (g.n0 * g.n1);
+    };
+    auto lup = [&](int d, int i, int j, int k) -> double {  // coefficient of the upper d-face
+        int n = d == 0 ? g.n0 : (d == 1 ? g.n1 : g.n2);
+        int per = d == 0 ? g.per0 : (d == 1 ? g.per1 : g.per2);
+        int c = d == 0 ? i : (d == 1 ? j : k);
+        if (c < n - 1 || per) {
+            int cu = (c < n - 1) ? c + 1 : 0;
+            int ii = d == 0 ? cu : i, jj = d == 1 ? cu : j, kk = d == 2 ? cu : k;
+            return sL[d][ii + g.n0 * (jj + g.n1 * kk)];
+        }
+        return 0.0;
+    };
+    auto diag = [&](int c) -> double {  // sum of the 2d face coefficients of cell c
+        int i, j, k;
+        coords(c, i, j, k);
+        double D = 0.0;
+        for (int d = 0; d < g.ndim; ++d) D += sL[d][c] + lup(d, i, j, k);
+        return D;
+    };
+    // sq holds D during set-up and A p during the iteration
+    double sumb = 0.0, cnt = 0.0;
+    for (int c = t; c < N; c += nt) {
+        const double D = diag(c);
+        sq[c] = D;
+        if (D > 0.0) {
+            sumb += double(b[c]);
+            cnt += 1.0;
+        }
+    }
+    sumb = dot_all(sumb);
+    cnt = dot_all(cnt);
+    const double mean = cnt > 0.0 ? sumb / cnt : 0.0;
+    // solve M x = B with M = -A, B = -(b - mean) on active cells
+    double rr = 0.0;
+    for (int c = t; c < N; c += nt) {
+        const double B = sq[c] > 0.0 ? -(double(b[c]) - mean) : 0.0;
+        sx[c] = 0.0;
+        sr[c] = B;
+        sp[c] = B;
+        rr += B * B;
+    }
+    rr = dot_all(rr);
+    const double rr0 = rr;
+    if (rr0 > 0.0) {
+        for (int it = 0; it < maxit; ++it) {
+            double pq = 0.0;
+            for (int c = t; c < N; c += nt) {
+                int i, j, k;
+                coords(c, i, j, k);
+                double Mp = 0.0;
+                const double D = diag(c);
+                if (D > 0.0) {
+                    const double pc = sp[c];
+                    Mp = D * pc;
+                    // neighbours
+                    {
+                        int il = nb_lo(i, g.n0, g.per0), iu = nb_up(i, g.n0, g.per0);
+                        Mp -= sL[0][c] * sp[il + g.n0 * (j + g.n1 * k)];
+                        Mp -= lup(0, i, j, k) * sp[iu + g.n0 * (j + g.n1 * k)];
+                    }
+                    {
+                        int jl = nb_lo(j, g.n1, g.per1), ju = nb_up(j, g.n1, g.per1);
+                        Mp -= sL[1][c] * sp[i + g.n0 * (jl + g.n1 * k)];
+                        Mp -= lup(1, i, j, k) * sp[i + g.n0 * (ju + g.n1 * k)];
+                    }
+                    if (g.ndim == 3) {
+                        int kl = nb_lo(k, g.n2, g.per2), ku = nb_up(k, g.n2, g.per2);
+                        Mp -= sL[2][c] * sp[i + g.n0 * (j + g.n1 * kl)];
+                        Mp -= lup(2, i, j, k) * sp[i + g.n0 * (j + g.n1 * ku)];
+                    }
+                }
+                sq[c] = Mp;
+                pq += sp[c] * Mp;
+            }
+            pq = dot_all(pq);
+            if (!(pq > 0.0)) break;
+            const double alpha = rr / pq;
+            double rn = 0.0;
+            for (int c = t; c < N; c += nt) {
+                sx[c] += alpha * sp[c];
+                sr[c] -= alpha * sq[c];
+                rn += sr[c] * sr[c];
+            }
+            rn = dot_all(rn);
+            if (rn <= tol * tol * rr0) break;
+            const double beta = rn / rr;
+            rr = rn;
+            for (int c = t; c < N; c += nt) sp[c] = sr[c] + beta * sp[c];
+            __syncthreads();
+        }
+    }
+    // mean-free result on the active cells
+    double sx_sum = 0.0;
+    for (int c = t; c < N; c += nt)
+        if (diag(c) > 0.0) sx_sum += sx[c];
+    sx_sum = dot_all(sx_sum);
+    const double xm = cnt > 0.0 ? sx_sum / cnt : 0.0;
+    for (int c = t; c < N; c += nt) xout[c] = diag(c) > 0.0 ? T(sx[c] - xm) : T(0);
+}
+
+// Coarse coefficient = 1/2 * sum of the fine faces the coarse face covers.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_coarsen(Grid gf, Grid gc, const T* __restrict__ f0,
+                                                    const T* __restrict__ f1,
+                                                    const T* __restrict__ f2, T* __restrict__ c0,
+                                                    T* __restrict__ c1, T* __restrict__ c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= gc.n0 || j >= gc.n1) return;
+    const int fz = (gf.n2 > gc.n2) ? 2 : 1;
+    const int I = 2 * i, J = 2 * j, K = fz * k;
+    T s0 = T(0), s1 = T(0), s2 = T(0);
+    for (int dz = 0; dz < fz; ++dz)
+        for (int dy = 0; dy < 2; ++dy) s0 += f0[cid(gf, I, J + dy, K + dz)];
+    for (int dz = 0; dz < fz; ++dz)
+        for (int dx = 0; dx < 2; ++dx) s1 += f1[cid(gf, I + dx, J, K + dz)];
+    if (gf.ndim == 3)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) s2 += f2[cid(gf, I + dx, J + dy, K)];
+    const size_t id = cid(gc, i, j, k);
+    c0[id] = T(0.5) * s0;
+    c1[id] = T(0.5) * s1;
+    c2[id] = T(0.5) * s2;
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ p, size_t n, T v) {
+    const size_t q = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q < n) p[q] = v;
+}
+
+// x64 += e32 (mixed-precision correction).
+__global__ __launch_bounds__(kBlock) void k_axpy64(size_t n, const float* __restrict__ e,
+                                                   double* __restrict__ x) {
+    const size_t q = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q < n) x[q] += double(e[q]);
+}
+
+// FP64 defect r = (b - mean)|active - A64 x, rounded to FP32 for the inner
+// solve; partial sums of r^2 and of the projected b^2.
+__global__ __launch_bounds__(kBlock) void k_resid64(Grid g, XAccess<double, XM_PLAIN> X,
+                                                    Coeffs<double> C, const double* __restrict__ b,
+                                                    const double* __restrict__ bmean,
+                                                    float* __restrict__ r32,
+                                                    double* __restrict__ partial) {
+    __shared__ double lds[8];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    double r2 = 0.0, b2 = 0.0;
+    if (i < g.n0 && j < g.n1) {
+        const size_t id = cid(g, i, j, k);
+        double xI, Ax, D;
+        apply_row<double, XM_PLAIN, false>(g, X, C, i, j, k, xI, Ax, D);
+        const double bv = (D > 0.0) ? b[id] - *bmean : 0.0;
+        const double r = bv - Ax;
+        r32[id] = float(r);
+        r2 = r * r;
+        b2 = bv * bv;
+    }
+    const double s = block_sum(r2, lds);
+    __syncthreads();
+    const double sb = block_sum(b2, lds + 4);
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        partial[2 * block_linear()] = s;
+        partial[2 * block_linear() + 1] = sb;
+    }
+}
+
+// Load caller coefficients (ndim consecutive face arrays) into a level,
+// forcing zero on non-periodic lower boundary faces and on the z faces in 2D;
+// optionally keep an FP64 copy.
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(kBlock) void k_load_coeffs(Grid g, const Tin* __restrict__ src,
+                                                        Tout* __restrict__ L0, Tout* __restrict__ L1,
+                                                        Tout* __restrict__ L2, double* M0,
+                                                        double* M1, double* M2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= g.n0 || j >= g.n1) return;
+    const size_t id = cid(g, i, j, k);
+    const size_t N = cells(g);
+    const int coord[3] = {i, j, k};
+    const int per[3] = {g.per0, g.per1, g.per2};
+    Tout* dst[3] = {L0, L1, L2};
+    double* d64[3] = {M0, M1, M2};
+    for (int d = 0; d < 3; ++d) {
+        double v = (d < g.ndim) ? double(src[d * N + id]) : 0.0;
+        if (!per[d] && coord[d] == 0) v = 0.0;
+        dst[d][id] = Tout(v);
+        if (d64[d]) d64[d][id] = v;
+    }
+}
+
+template <typename Tin, typename Tout>
+wl_status mg_load_coeffs(const Grid& g, const Tin* src, Tout* const L[3], double* const L64[3],
+                         hipStream_t s) {
+    const Launch ln = launch_for(g.n0, g.n1, g.n2);
+    k_load_coeffs<Tin, Tout><<<ln.grid, ln.block, 0, s>>>(g, src, L[0], L[1], L[2],
+                                                          L64 ? L64[0] : nullptr,
+                                                          L64 ? L64[1] : nullptr,
+                                                          L64 ? L64[2] : nullptr);
+    WL_CHECK_LAUNCH();
+    return WL_OK;
+}
+template wl_status mg_load_coeffs<float, float>(const Grid&, const float*, float* const*,
+                                                double* const*, hipStream_t);
+template wl_status mg_load_coeffs<double, double>(const Grid&, const double*, double* const*,
+                                                  double* const*, hipStream_t);
+template wl_status mg_load_coeffs<double, float>(const Grid&, const double*, float* const*,
+                                                 double* const*, hipStream_t);
+
+template <typename T>
+wl_status fill(T* p, size_t n, T v, hipStream_t s) {
+    if (n == 0) return WL_OK;
+    k_fill<T><<<unsigned((n + 255) / 256), 256, 0, s>>>(p, n, v);
+    WL_CHECK_LAUNCH();
+    return WL_OK;
+}
+template wl_status fill<float>(float*, size_t, float, hipStream_t);
+template wl_status fill<double>(double*, size_t, double, hipStream_t);
+
+template <typename Tin, typename Tout>
+__global__ void k_convert(const Tin* __restrict__ a, Tout* __restrict__ b, size_t n) {
+    const size_t q = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q < n) b[q] = Tout(a[q]);
+}
+
+template <typename Tin, typename Tout>
+wl_status convert(const Tin* a, Tout* b, size_t n, hipStream_t s) {
+    if (n == 0) return WL_OK;
+    k_convert<Tin, Tout><<<unsigned((n + 255) / 256), 256, 0, s>>>(a, b, n);
+    WL_CHECK_LAUNCH();
+    return WL_OK;
+}
+template wl_status convert<float, double>(const float*, double*, size_t, hipStream_t);
+template wl_status convert<double, float>(const double*, float*, size_t, hipStream_t);
+
+// Count of active cells from FP64 coefficients (mixed-precision solver).
+wl_status mg_count_active64(const Grid& g, double* const L64[3], Reduce& red, size_t* count,
+                            hipStream_t s) {
+    const Launch ln = launch_for(g.n0, g.n1, g.n2);
+    Coeffs<double> C{L64[0], L64[1], L64[2], 1.0};
+    k_sum_active<double, false><<<ln.grid, ln.block, 0, s>>>(g, C, nullptr, red.partial);
+    WL_CHECK_LAUNCH();
+    k_reduce<<<1, 1024, 0, s>>>(red.partial, ln.nblocks(), 1, 1.0, red.result + 6);
+    WL_CHECK_LAUNCH();
+    double cnt = 0.0;
+    WL_CHECK_HIP(hipMemcpyAsync(&cnt, red.result + 6, sizeof(double), hipMemcpyDeviceToHost, s));
+    WL_CHECK_HIP(hipStreamSynchronize(s));
+    *count = size_t(cnt);
+    return WL_OK;
+}
+
+// ----------------------------------------------------------- host driving
+
+template <typename T>
+static Coeffs<T> coeffs_of(const Level<T>& L) {
+    return Coeffs<T>{L.L[0], L.L[1], L.L[2], L.Lc};
+}
+
+template <typename T, int XM, bool NORM, bool FIRST>
+static wl_status smooth(const Level<T>& L, const T* xin, const T* xc, const Grid* gc,
+                        const T* b, T omega, T* xout, double* partial, T* bproj,
+                        const double* bmean, hipStream_t s) {
+    const Launch ln = launch_for(L.g.n0, L.g.n1, L.g.n2);
+    XAccess<T, XM> X{xin, xc, gc ? gc->n0 : 0, gc ? gc->n1 : 0};
+    if (L.uniform)
+        k_smooth<T, XM, true, NORM, FIRST><<<ln.grid, ln.block, 0, s>>>(
+            L.g, X, coeffs_of(L), b, omega, xout, partial, bproj, bmean);
+    else
+        k_smooth<T, XM, false, NORM, FIRST><<<ln.grid, ln.block, 0, s>>>(
+            L.g, X, coeffs_of(L), b, omega, xout, partial, bproj, bmean);
+    WL_CHECK_LAUNCH();
+    return WL_OK;
+}
+
+template <typename T>
+static wl_status resid_restrict(const Level<T>& L, const T* x, Level<T>& C, hipStream_t s) {
+    const Launch ln = launch_for(C.g.n0, C.g.n1, C.g.n2);
+    XAccess<T, XM_PLAIN> X{x, nullptr, 0, 0};
+    if (L.uniform)
+        k_resid_restrict<T, true><<<ln.grid, ln.block, 0, s>>>(L.g, C.g, X, coeffs_of(L), L.b, C.b);
+    else
+        k_resid_restrict<T, false><<<ln.grid, ln.block, 0, s>>>(L.g, C.g, X, coeffs_of(L), L.b, C.b);
+    WL_CHECK_LAUNCH();
+    return WL_OK;
+}
+
+template <typename T>
+static wl_status coarse_solve(const Hierarchy<T>& h, const Level<T>& L, T* xout, hipStream_t s) {
+    const int N = int(cells(L.g));
+    const int maxit = N + 64;
+    k_coarse_cg<T><<<1, 256, 0, s>>>(L.g, coeffs_of(L), L.uniform, L.b, xout, h.coarse_tol, maxit);
+    WL_CHECK_LAUNCH();
+    return WL_OK;
+}
+
+template <typename T>
+static wl_status reduce(Reduce& red, size_t nslots, int ncomp, double scale, double* out,
+                        hipStream_t s) {
+    k_reduce<<<1, 1024, 0, s>>>(red.partial, nslots, ncomp, scale, out);
+    WL_CHECK_LAUNCH();
+    return WL_OK;
+}
+
+template <typename T>
+wl_status mg_coarsen_all(Hierarchy<T>& h, hipStream_t s) {
+    for (int l = 1; l < h.nlev; ++l) {
+        Level<T>& F = h.lev[l - 1];
+        Level<T>& C = h.lev[l];
+        const Launch ln = launch_for(C.g.n0, C.g.n1, C.g.n2);
+        k_coarsen<T><<<ln.grid, ln.block, 0, s>>>(F.g, C.g, F.L[0], F.L[1], F.L[2], C.L[0],
+                                                  C.L[1], C.L[2]);
+        WL_CHECK_LAUNCH();
+        C.uniform = F.uniform;
+        C.Lc = F.Lc * (F.g.ndim == 3 ? T(2) : T(1));
+    }
+    return WL_OK;
+}
+
+template <typename T>
+wl_status mg_count_active(Hierarchy<T>& h, Reduce& red, hipStream_t s) {
+    const Level<T>& F = h.lev[0];
+    const Launch ln = launch_for(F.g.n0, F.g.n1, F.g.n2);
+    if (F.uniform)
+        k_sum_active<T, true><<<ln.grid, ln.block, 0, s>>>(F.g, coeffs_of(F), nullptr, red.partial);
+    else
+        k_sum_active<T, false><<<ln.grid, ln.block, 0, s>>>(F.g, coeffs_of(F), nullptr, red.partial);
+    WL_CHECK_LAUNCH();
+    // result[6] = active count (kept on the device for the mean kernels)
+    k_reduce<<<1, 1024, 0, s>>>(red.partial, ln.nblocks(), 1, 1.0, red.result + 6);
+    WL_CHECK_LAUNCH();
+    double cnt = 0.0;
+    WL_CHECK_HIP(hipMemcpyAsync(&cnt, red.result + 6, sizeof(double), hipMemcpyDeviceToHost, s));
+    WL_CHECK_HIP(hipStreamSynchronize(s));
+    h.n_active = size_t(cnt);
+    return WL_OK;
+}
+
+template wl_status mg_coarsen_all<float>(Hierarchy<float>&, hipStream_t);
+template wl_status mg_coarsen_all<double>(Hierarchy<double>&, hipStream_t);
+template wl_status mg_count_active<float>(Hierarchy<float>&, Reduce&, hipStream_t);
+template wl_status mg_count_active<double>(Hierarchy<double>&, Reduce&, hipStream_t);
+
+// Remainder of one V-cycle once its first fine pre-sweep has written
+// lev[0].x[1]; leaves the fine iterate in lev[0].x[0].
+template <typename T>
+static wl_status vcycle_rest(Hierarchy<T>& h, hipStream_t s) {
+    Level<T>& F = h.lev[0];
+    const T w = T(h.omega);
+    if (h.nlev == 1) return coarse_solve(h, F, F.x[0], s);
+    WL_TRY((smooth<T, XM_PLAIN, false, false>(F, F.x[1], nullptr, nullptr, F.b, w, F.x[0],
+                                              nullptr, nullptr, nullptr, s)));
+    WL_TRY(resid_restrict(F, F.x[0], h.lev[1], s));
+    for (int l = 1; l < h.nlev - 1; ++l) {
+        Level<T>& L = h.lev[l];
+        WL_TRY((smooth<T, XM_ZERO, false, false>(L, nullptr, nullptr, nullptr, L.b, w, L.x[0],
+                                                 nullptr, nullptr, nullptr, s)));
+        WL_TRY((smooth<T, XM_PLAIN, false, false>(L, L.x[0], nullptr, nullptr, L.b, w, L.x[1],
+                                                  nullptr, nullptr, nullptr, s)));
+        WL_TRY(resid_restrict(L, L.x[1], h.lev[l + 1], s));
+    }
+    Level<T>& Cst = h.lev[h.nlev - 1];
+    WL_TRY(coarse_solve(h, Cst, Cst.x[1], s));
+    for (int l = h.nlev - 2; l >= 1; --l) {
+        Level<T>& L = h.lev[l];
+        const Level<T>& C = h.lev[l + 1];
+        WL_TRY((smooth<T, XM_PROLONG, false, false>(L, L.x[1], C.x[1], &C.g, L.b, w, L.x[0],
+                                                    nullptr, nullptr, nullptr, s)));
+        WL_TRY((smooth<T, XM_PLAIN, false, false>(L, L.x[0], nullptr, nullptr, L.b, w, L.x[1],
+                                                  nullptr, nullptr, nullptr, s)));
+    }
+    const Level<T>& C1 = h.lev[1];
+    WL_TRY((smooth<T, XM_PROLONG, false, false>(F, F.x[0], C1.x[1], &C1.g, F.b, w, F.x[1], nullptr,
+                                                nullptr, nullptr, s)));
+    WL_TRY((smooth<T, XM_PLAIN, false, false>(F, F.x[1], nullptr, nullptr, F.b, w, F.x[0], nullptr,
+                                              nullptr, nullptr, s)));
+    return WL_OK;
+}
+
+static wl_status read_norms(Reduce& red, double* host2, hipStream_t s) {
+    WL_CHECK_HIP(hipMemcpyAsync(host2, red.result, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    WL_CHECK_HIP(hipStreamSynchronize(s));
+    return WL_OK;
+}
+
+template <typename T>
+static wl_status active_mean(Hierarchy<T>& h, Reduce& red, const T* b, hipStream_t s) {
+    const Level<T>& F = h.lev[0];
+    const Launch ln = launch_for(F.g.n0, F.g.n1, F.g.n2);
+    if (F.uniform)
+        k_sum_active<T, true><<<ln.grid, ln.block, 0, s>>>(F.g, coeffs_of(F), b, red.partial);
+    else
+        k_sum_active<T, false><<<ln.grid, ln.block, 0, s>>>(F.g, coeffs_of(F), b, red.partial);
+    WL_CHECK_LAUNCH();
+    // result[4] = sum, result[5] = mean
+    k_reduce<<<1, 1024, 0, s>>>(red.partial, ln.nblocks(), 1, 1.0, red.result + 4);
+    WL_CHECK_LAUNCH();
+    k_mean_fix<<<1, 64, 0, s>>>(red.result + 4, red.result + 6);
+    WL_CHECK_LAUNCH();
+    return WL_OK;
+}
+
+template <typename T>
+wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, int max_vcycles,
+                   hipStream_t s, SolveResult* res) {
+    Level<T>& F = h.lev[0];
+    F.x[0] = x;
+    const T w = T(h.omega);
+    const Launch ln = launch_for(F.g.n0, F.g.n1, F.g.n2);
+    WL_TRY(active_mean(h, red, b, s));
+    // first fine sweep: projects b, measures ||r0|| and ||b||
+    WL_TRY((smooth<T, XM_PLAIN, true, true>(F, x, nullptr, nullptr, b, w, F.x[1], red.partial, F.b,
+                                            red.result + 5, s)));
+    WL_TRY(reduce<T>(red, ln.nblocks(), 2, 1.0, red.result, s));
+    double nr[2];
+    WL_TRY(read_norms(red, nr, s));
+    if (!std::isfinite(nr[0]) || !std::isfinite(nr[1])) {
+        set_error("non-finite residual norm in the pressure solve");
+        return WL_ERR_NONFINITE;
+    }
+    const double b2 = nr[1];
+    res->bnorm = std::sqrt(b2);
+    if (b2 == 0.0) {
+        const size_t N = cells(F.g);
+        k_fill<T><<<unsigned((N + 255) / 256), 256, 0, s>>>(x, N, T(0));
+        WL_CHECK_LAUNCH();
+        res->vcycles = 0;
+        res->rel = 0.0;
+        return WL_OK;
+    }
+    double rel = std::sqrt(nr[0] / b2);
+    int k = 0;
+    while (rel > tol && k < max_vcycles) {
+        WL_TRY(vcycle_rest(h, s));
+        ++k;
+        WL_TRY((smooth<T, XM_PLAIN, true, false>(F, x, nullptr, nullptr, F.b, w, F.x[1],
+                                                 red.partial, nullptr, nullptr, s)));
+        WL_TRY(reduce<T>(red, ln.nblocks(), 2, 1.0, red.result, s));
+        WL_TRY(read_norms(red, nr, s));
+        if (!std::isfinite(nr[0])) {
+            set_error("non-finite residual norm in the pressure solve");
+            return WL_ERR_NONFINITE;
+        }
+        rel = std::sqrt(nr[0] / b2);
+    }
+    res->vcycles = k;
+    res->rel = rel;
+    if (rel > tol) {
+        set_error("pressure solve reached max_vcycles before the tolerance");
+        return WL_ERR_NOT_CONVERGED;
+    }
+    return WL_OK;
+}
+
+template wl_status mg_solve<float>(Hierarchy<float>&, Reduce&, float*, const float*, double, int,
+                                   hipStream_t, SolveResult*);
+template wl_status mg_solve<double>(Hierarchy<double>&, Reduce&, double*, const double*, double,
+                                    int, hipStream_t, SolveResult*);
+
+wl_status mg_solve_mixed(Hierarchy<float>& h32, const Mixed64& m, Reduce& red, double* x,
+                         const double* b, double tol, int max_vcycles, hipStream_t s,
+                         SolveResult* res) {
+    Level<float>& F = h32.lev[0];
+    const Grid g = F.g;
+    const Launch ln = launch_for(g.n0, g.n1, g.n2);
+    const size_t N = cells(g);
+    const float w = float(h32.omega);
+    Coeffs<double> C64{m.L[0], m.L[1], m.L[2], 1.0};
+    // active mean of b in FP64 (result[5])
+    k_sum_active<double, false><<<ln.grid, ln.block, 0, s>>>(g, C64, b, red.partial);
+    WL_CHECK_LAUNCH();
+    k_reduce<<<1, 1024, 0, s>>>(red.partial, ln.nblocks(), 1, 1.0, red.result + 4);
+    WL_CHECK_LAUNCH();
+    k_mean_fix<<<1, 64, 0, s>>>(red.result + 4, red.result + 6);
+    WL_CHECK_LAUNCH();
+    int inner_total = 0;
+    double b2 = -1.0, rel = 0.0;
+    for (;;) {
+        XAccess<double, XM_PLAIN> X{x, nullptr, 0, 0};
+        k_resid64<<<ln.grid, ln.block, 0, s>>>(g, X, C64, b, red.result + 5, F.b, red.partial);
+        WL_CHECK_LAUNCH();
+        WL_TRY(reduce<double>(red, ln.nblocks(), 2, 1.0, red.result, s));
+        double nr[2];
+        WL_TRY(read_norms(red, nr, s));
+        if (!std::isfinite(nr[0]) || !std::isfinite(nr[1])) {
+            set_error("non-finite residual norm in the mixed-precision solve");
+            return WL_ERR_NONFINITE;
+        }
+        if (b2 < 0.0) {
+            b2 = nr[1];
+            res->bnorm = std::sqrt(b2);
+            if (b2 == 0.0) {
+                k_fill<double><<<unsigned((N + 255) / 256), 256, 0, s>>>(x, N, 0.0);
+                WL_CHECK_LAUNCH();
+                res->vcycles = 0;
+                res->rel = 0.0;
+                return WL_OK;
+            }
+        }
+        rel = std::sqrt(nr[0] / b2);
+        if (rel <= tol || inner_total >= max_vcycles) break;
+        // inner FP32 V-cycles on A e = r from e = 0
+        for (int v = 0; v < m.inner && inner_total < max_vcycles; ++v, ++inner_total) {
+            if (v == 0)
+                WL_TRY((smooth<float, XM_ZERO, false, false>(F, nullptr, nullptr, nullptr, F.b, w,
+                                                             F.x[1], nullptr, nullptr, nullptr,
+                                                             s)));
+            else
+                WL_TRY((smooth<float, XM_PLAIN, false, false>(F, F.x[0], nullptr, nullptr, F.b, w,
+                                                              F.x[1], nullptr, nullptr, nullptr,
+                                                              s)));
+            WL_TRY(vcycle_rest(h32, s));
+        }
+        k_axpy64<<<unsigned((N + kBlock - 1) / kBlock), kBlock, 0, s>>>(N, F.x[0], x);
+        WL_CHECK_LAUNCH();
+    }
+    res->vcycles = inner_total;
+    res->rel = rel;
+    if (rel > tol) {
+        set_error("mixed-precision solve reached max_vcycles before the tolerance");
+        return WL_ERR_NOT_CONVERGED;
+    }
+    return WL_OK;
+}
+
+}  // namespace wl

@@ -1,0 +1,565 @@
+// Navier-Stokes step kernels: geometry measure (BDIM moments and Poisson
+// coefficients), CFL time step, third-order limited convection-diffusion with
+// the Heun stage update, BDIM blend, outflow plane with exit-flux balance,
+// divergence and the pressure-gradient projection.
+//
+// Paper Sec. 2 fixes the method (third-order finite volume, explicit adaptive
+// time stepping, implicit LES, BDIM on velocity and pressure matrix, the
+// gradient loop u[I,i] -= coeff[I,i]*(p[I]-p[I-del(i)]) fused over i);
+// Sec. 3 / Table 2 name the routines convdiff!, BDIM!, BC!, project!, CFL!.
+// Constants the paper leaves open follow the readings stated in the headers:
+// kappa = 1/3 interpolant bounded by the Koren limiter (median form), cosine
+// BDIM kernel of half-width eps, Heun stages with projection factor c = 1 and
+// c = 1/2, CFL from the per-cell outflow velocity plus 2 d nu.
+#include <cmath>
+
+#include "wl_device.h"
+#include "wl_ns.h"
+
+namespace wl {
+
+// --------------------------------------------------------- velocity ghosts
+
+// Value of velocity component c at (i, j, k), where at most one coordinate
+// lies outside the grid (by up to two cells).  Ghost rules: periodic wrap;
+// INFLOW ghosts = U; free-slip WALL: normal component odd about the wall
+// face (boundary face 0), tangential components even; OUTFLOW (upper x): the
+// boundary face is the plane uout, ghosts beyond it zero-gradient.
+template <typename T, bool ALLPER>
+__device__ __forceinline__ T vget(const VelField<T>& V, int c, int i, int j, int k) {
+    const Grid& g = V.g;
+    if (ALLPER) {
+        i = i < 0 ? i + g.n0 : (i >= g.n0 ? i - g.n0 : i);
+        j = j < 0 ? j + g.n1 : (j >= g.n1 ? j - g.n1 : j);
+        if (g.ndim == 3) k = k < 0 ? k + g.n2 : (k >= g.n2 ? k - g.n2 : k);
+        return V.u[c][cid(g, i, j, k)];
+    }
+    int q[3] = {i, j, k};
+    const int n[3] = {g.n0, g.n1, g.n2};
+    const int per[3] = {g.per0, g.per1, g.per2};
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        if (per[d]) q[d] = q[d] < 0 ? q[d] + n[d] : (q[d] >= n[d] ? q[d] - n[d] : q[d]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int m = n[d], kk = q[d];
+        if (kk >= 0 && kk < m) continue;
+        // (the other coordinates are in range for every evaluation the kernels
+        // make; clamping keeps any other request inside the array)
+        auto at = [&](int idx) -> T {
+            int r[3] = {q[0], q[1], q[2]};
+            r[d] = idx;
+#pragma unroll
+            for (int e = 0; e < 3; ++e) r[e] = r[e] < 0 ? 0 : (r[e] >= n[e] ? n[e] - 1 : r[e]);
+            return V.u[c][cid(g, r[0], r[1], r[2])];
+        };
+        if (kk < 0) {
+            if (V.bclo[d] == WL_BC_INFLOW) return V.U[c];
+            if (c == d) {
+                const int mir = -kk;
+                return -at(mir < m ? mir : 0);
+            }
+            const int mir = -1 - kk;
+            return at(mir < m - 1 ? mir : m - 1);
+        }
+        if (c == d) {
+            if (V.bchi[d] == WL_BC_OUTFLOW) {
+                const int a = q[1] < 0 ? 0 : (q[1] >= g.n1 ? g.n1 - 1 : q[1]);
+                const int b = q[2] < 0 ? 0 : (q[2] >= g.n2 ? g.n2 - 1 : q[2]);
+                return V.uout[a + size_t(g.n1) * b];
+            }
+            if (kk == m) return T(0);
+            return -at(m - 1 > 0 ? m - 1 : 0);
+        }
+        if (V.bchi[d] == WL_BC_OUTFLOW) return at(m - 1);
+        if (kk == m) return at(m - 1);
+        return at(m - 2 > 0 ? m - 2 : 0);
+    }
+    return V.u[c][cid(g, q[0], q[1], q[2])];
+}
+
+__device__ __forceinline__ float med3(float a, float b, float c) {
+    return __builtin_amdgcn_fmed3f(a, b, c);
+}
+__device__ __forceinline__ double med3(double a, double b, double c) {
+    return fmax(fmin(a, b), fmin(fmax(a, b), c));
+}
+
+// Flux of u_c through the lower d-face of the c-momentum control volume at J:
+// ubar * phi - nu (u_c(J) - u_c(J - delta_d)), phi the limited third-order
+// upwind-biased face value.
+template <typename T, bool ALLPER>
+__device__ __forceinline__ T face_flux(const VelField<T>& V, int c, int d, int i, int j, int k,
+                                       T nu) {
+    const int di = d == 0, dj = d == 1, dk = d == 2;
+    const int ci = c == 0, cj = c == 1, ck = c == 2;
+    const T um2 = vget<T, ALLPER>(V, c, i - 2 * di, j - 2 * dj, k - 2 * dk);
+    const T um1 = vget<T, ALLPER>(V, c, i - di, j - dj, k - dk);
+    const T u0 = vget<T, ALLPER>(V, c, i, j, k);
+    const T up1 = vget<T, ALLPER>(V, c, i + di, j + dj, k + dk);
+    const T ubar = T(0.5) * (vget<T, ALLPER>(V, d, i, j, k) +
+                             vget<T, ALLPER>(V, d, i - ci, j - cj, k - ck));
+    const bool pos = ubar >= T(0);
+    const T cu = pos ? um1 : u0;
+    const T bd = pos ? u0 : um1;
+    const T au = pos ? um2 : up1;
+    const T phik = (T(5) * cu + T(2) * bd - au) / T(6);
+    const T phi = med3(phik, cu, med3(T(2) * cu - au, cu, bd));
+    return ubar * phi - nu * (u0 - um1);
+}
+
+// Stage update of every interior face of cell (i,j,k):
+//   PRED: f = u_e + dt R(u_e)          CORR: f = (u_n + u_e + dt R(u_e)) / 2
+// with R_c = -sum_d [F_cd(I + delta_d) - F_cd(I)].  Domain-boundary faces take
+// their boundary value (U_c at an inflow, 0 at a wall).
+template <typename T, bool ALLPER, bool CORR>
+__global__ __launch_bounds__(kBlock) void k_momentum(VelField<T> E, const T* __restrict__ un0,
+                                                     const T* __restrict__ un1,
+                                                     const T* __restrict__ un2,
+                                                     T* __restrict__ f0, T* __restrict__ f1,
+                                                     T* __restrict__ f2, T nu,
+                                                     const double* __restrict__ dt_dev) {
+    const Grid& g = E.g;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= g.n0 || j >= g.n1) return;
+    const size_t id = cid(g, i, j, k);
+    const T dt = T(*dt_dev);
+    const int coord[3] = {i, j, k};
+    const int per[3] = {g.per0, g.per1, g.per2};
+    const T* un[3] = {un0, un1, un2};
+    T* fo[3] = {f0, f1, f2};
+    for (int c = 0; c < g.ndim; ++c) {
+        if (!per[c] && coord[c] == 0) {
+            fo[c][id] = (E.bclo[c] == WL_BC_INFLOW) ? E.U[c] : T(0);
+            continue;
+        }
+        T R = T(0);
+        for (int d = 0; d < g.ndim; ++d) {
+            const T Flo = face_flux<T, ALLPER>(E, c, d, i, j, k, nu);
+            const T Fhi = face_flux<T, ALLPER>(E, c, d, i + (d == 0), j + (d == 1), k + (d == 2), nu);
+            R -= Fhi - Flo;
+        }
+        const T ue = E.u[c][id];
+        fo[c][id] = CORR ? T(0.5) * (un[c][id] + ue + dt * R) : ue + dt * R;
+    }
+}
+
+// Outflow plane (upper x face): convective update d(uout)/dt = -U_x (uout -
+// u_x(n0-1)) in the same stage form, then a uniform shift making its total
+// flux equal to the inflow plane's (FP64 sums, one workgroup, fixed order).
+template <typename T, bool CORR>
+__global__ __launch_bounds__(1024) void k_outflow(Grid g, const T* __restrict__ ue_x,
+                                                  const T* __restrict__ out_e,
+                                                  const T* __restrict__ out_n,
+                                                  const T* __restrict__ f_x, T Ux,
+                                                  const double* __restrict__ dt_dev,
+                                                  T* __restrict__ fout) {
+    __shared__ double lds[32];
+    const int P = g.n1 * g.n2;
+    const T dt = T(*dt_dev);
+    double sin_ = 0.0, sout = 0.0;
+    for (int q = threadIdx.x; q < P; q += blockDim.x) {
+        const int j = q % g.n1, k = q / g.n1;
+        const T last = ue_x[cid(g, g.n0 - 1, j, k)];
+        const T R = -Ux * (out_e[q] - last);
+        const T f = CORR ? T(0.5) * (out_n[q] + out_e[q] + dt * R) : out_e[q] + dt * R;
+        fout[q] = f;
+        sout += double(f);
+        sin_ += double(f_x[cid(g, 0, j, k)]);
+    }
+    auto bsum = [&](double v) -> double {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+        __syncthreads();
+        double s = 0.0;
+        for (int w = 0; w < int(blockDim.x + 63) / 64; ++w) s += lds[w];
+        __syncthreads();
+        return s;
+    };
+    const double tin = bsum(sin_);
+    const double tout = bsum(sout);
+    const T shift = T((tin - tout) / double(P));
+    for (int q = threadIdx.x; q < P; q += blockDim.x) fout[q] += shift;
+}
+
+// First-order BDIM blend (body at rest) on interior faces:
+//   u*_c = mu0_c f_c + sum_d (mu1 n)_cd (f_c(I+delta_d) - f_c(I-delta_d)) / 2.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bdim(VelField<T> F, BdimFields<T> B,
+                                                 T* __restrict__ o0, T* __restrict__ o1,
+                                                 T* __restrict__ o2) {
+    const Grid& g = F.g;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= g.n0 || j >= g.n1) return;
+    const size_t id = cid(g, i, j, k);
+    const int coord[3] = {i, j, k};
+    const int per[3] = {g.per0, g.per1, g.per2};
+    T* out[3] = {o0, o1, o2};
+    for (int c = 0; c < g.ndim; ++c) {
+        const T f = F.u[c][id];
+        if (!per[c] && coord[c] == 0) {
+            out[c][id] = f;
+            continue;
+        }
+        T v = B.mu0[c][id] * f;
+        for (int d = 0; d < g.ndim; ++d) {
+            const T m = B.mu1n[3 * c + d][id];
+            if (m != T(0)) {
+                const T fp = vget<T, false>(F, c, i + (d == 0), j + (d == 1), k + (d == 2));
+                const T fm = vget<T, false>(F, c, i - (d == 0), j - (d == 1), k - (d == 2));
+                v += m * (T(0.5) * (fp - fm));
+            }
+        }
+        out[c][id] = v;
+    }
+}
+
+// sigma = div(u*) / (c dt).
+template <typename T, bool ALLPER>
+__global__ __launch_bounds__(kBlock) void k_divergence(VelField<T> V, double c,
+                                                       const double* __restrict__ dt_dev,
+                                                       T* __restrict__ sigma) {
+    const Grid& g = V.g;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= g.n0 || j >= g.n1) return;
+    const size_t id = cid(g, i, j, k);
+    T div = T(0);
+    for (int d = 0; d < g.ndim; ++d)
+        div += vget<T, ALLPER>(V, d, i + (d == 0), j + (d == 1), k + (d == 2)) - V.u[d][id];
+    sigma[id] = div * T(1.0 / (c * *dt_dev));
+}
+
+// Projected face value u*_d(J) - c dt L_d(J) (p(J) - p(J - delta_d)) for an
+// in-grid face J (coordinates already wrapped).
+template <typename T, bool UNIF>
+__device__ __forceinline__ T projected(const VelField<T>& V, const T* __restrict__ p,
+                                       const ProjCoeffs<T>& C, int d, int i, int j, int k, T coef) {
+    const Grid& g = V.g;
+    const size_t id = cid(g, i, j, k);
+    const int per = d == 0 ? g.per0 : (d == 1 ? g.per1 : g.per2);
+    const int n = d == 0 ? g.n0 : (d == 1 ? g.n1 : g.n2);
+    const int c = d == 0 ? i : (d == 1 ? j : k);
+    const T L = UNIF ? C.Lc : C.L[d][id];
+    if (!UNIF && !per && c == 0) return V.u[d][id];  // boundary face: L = 0
+    const int cl = c > 0 ? c - 1 : n - 1;
+    const int il = d == 0 ? cl : i, jl = d == 1 ? cl : j, kl = d == 2 ? cl : k;
+    return V.u[d][id] - coef * L * (p[id] - p[cid(g, il, jl, kl)]);
+}
+
+// u = u* - c dt L grad(p) for every direction in one pass (the gradient loop
+// of Sec. 2 with coeff = c dt L, fused over directions); optionally the
+// per-block CFL maximum of sum_d max(u_d(I+delta_d),0) - min(u_d(I),0) of the
+// projected field (upper neighbours recomputed, so the output can alias
+// nothing that is read).
+template <typename T, bool ALLPER, bool UNIF, bool CFL>
+__global__ __launch_bounds__(kBlock) void k_project(VelField<T> V, const T* __restrict__ p,
+                                                    ProjCoeffs<T> C, double c,
+                                                    const double* __restrict__ dt_dev,
+                                                    T* o0, T* o1, T* o2,
+                                                    double* __restrict__ partial) {
+    __shared__ double lds[8];
+    const Grid& g = V.g;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    const T coef = T(c * *dt_dev);
+    T* out[3] = {o0, o1, o2};
+    double cfl = 0.0;
+    if (i < g.n0 && j < g.n1) {
+        const size_t id = cid(g, i, j, k);
+        T s = T(0);
+        for (int d = 0; d < g.ndim; ++d) {
+            const T ud = projected<T, UNIF>(V, p, C, d, i, j, k, coef);
+            out[d][id] = ud;
+            if (CFL) {
+                const int n = d == 0 ? g.n0 : (d == 1 ? g.n1 : g.n2);
+                const int cc = d == 0 ? i : (d == 1 ? j : k);
+                const int per = d == 0 ? g.per0 : (d == 1 ? g.per1 : g.per2);
+                T up;
+                if (cc + 1 < n || per) {
+                    const int cu = cc + 1 < n ? cc + 1 : 0;
+                    up = projected<T, UNIF>(V, p, C, d, d == 0 ? cu : i, d == 1 ? cu : j,
+                                            d == 2 ? cu : k, coef);
+                } else {
+                    up = vget<T, ALLPER>(V, d, i + (d == 0), j + (d == 1), k + (d == 2));
+                }
+                s += fmax(up, T(0)) - fmin(ud, T(0));
+            }
+        }
+        cfl = double(s);
+    }
+    if (CFL) {
+        const double m = block_max(cfl, lds);
+        if (threadIdx.x == 0 && threadIdx.y == 0) partial[block_linear()] = m;
+    }
+}
+
+// Per-block CFL maximum of the current field.
+template <typename T, bool ALLPER>
+__global__ __launch_bounds__(kBlock) void k_cfl(VelField<T> V, double* __restrict__ partial) {
+    __shared__ double lds[8];
+    const Grid& g = V.g;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    double v = 0.0;
+    if (i < g.n0 && j < g.n1) {
+        const size_t id = cid(g, i, j, k);
+        T s = T(0);
+        for (int d = 0; d < g.ndim; ++d) {
+            const T up = vget<T, ALLPER>(V, d, i + (d == 0), j + (d == 1), k + (d == 2));
+            s += fmax(up, T(0)) - fmin(V.u[d][id], T(0));
+        }
+        v = double(s);
+    }
+    const double m = block_max(v, lds);
+    if (threadIdx.x == 0 && threadIdx.y == 0) partial[block_linear()] = m;
+}
+
+// dt = cfl / (max over slots + visc); visc = 2 d nu.  One block.
+__global__ __launch_bounds__(1024) void k_dt_from_max(const double* __restrict__ partial,
+                                                      size_t nslots, double cfl, double visc,
+                                                      double* __restrict__ dt_out,
+                                                      double* __restrict__ max_out) {
+    __shared__ double lds[1024];
+    double m = 0.0;
+    for (size_t q = threadIdx.x; q < nslots; q += blockDim.x) m = fmax(m, partial[q]);
+    lds[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) lds[threadIdx.x] = fmax(lds[threadIdx.x], lds[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double den = lds[0] + visc;
+        *max_out = lds[0];
+        *dt_out = den > 0.0 ? cfl / den : 0.0;
+    }
+}
+
+__global__ void k_set_scalar(double* p, double v) {
+    if (threadIdx.x == 0) *p = v;
+}
+
+// BDIM moments and Poisson coefficients of every face from the sphere SDF
+// d = |x - centre| - R (face centre x = I + 1/2 - delta_c / 2; 2D ignores z):
+// mu0 = (1 + r + sin(pi r)/pi)/2, mu1 = eps [(1-r^2)/4 - r sin(pi r)/(2 pi)
+// - (1 + cos(pi r))/(2 pi^2)] for |r| = |d/eps| < 1 (1/0 and 0 outside),
+// (mu1 n)_cd = mu1 n_d, L_c = mu0 except 0 on non-periodic lower boundary faces.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_measure(Grid g, BodyDev body, int bclo0, int bclo1,
+                                                    int bclo2, MeasureOut<T> M) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= g.n0 || j >= g.n1) return;
+    const size_t id = cid(g, i, j, k);
+    const int coord[3] = {i, j, k};
+    const int bclo[3] = {bclo0, bclo1, bclo2};
+    for (int c = 0; c < 3; ++c) {
+        double m0 = 1.0, m1 = 0.0, nrm[3] = {0.0, 0.0, 0.0};
+        if (body.kind == 1 && c < g.ndim) {
+            double x[3] = {i + 0.5, j + 0.5, k + 0.5};
+            x[c] -= 0.5;
+            double rel[3], r2 = 0.0;
+            for (int d = 0; d < g.ndim; ++d) {
+                rel[d] = x[d] - body.centre[d];
+                r2 += rel[d] * rel[d];
+            }
+            const double dist = sqrt(r2);
+            const double sd = dist - body.radius;
+            if (dist > 0.0)
+                for (int d = 0; d < g.ndim; ++d) nrm[d] = rel[d] / dist;
+            const double r = sd / body.eps;
+            if (r >= 1.0) {
+                m0 = 1.0;
+            } else if (r <= -1.0) {
+                m0 = 0.0;
+            } else {
+                const double pi = 3.14159265358979323846;
+                const double sn = sin(pi * r), cs = cos(pi * r);
+                m0 = 0.5 * (1.0 + r + sn / pi);
+                m1 = body.eps * ((1.0 - r * r) / 4.0 - r * sn / (2.0 * pi) -
+                                 (1.0 + cs) / (2.0 * pi * pi));
+            }
+        }
+        M.mu0[c][id] = T(m0);
+        for (int d = 0; d < 3; ++d) M.mu1n[3 * c + d][id] = T(m1 * nrm[d]);
+        double L = (c < g.ndim) ? m0 : 0.0;
+        if (bclo[c] != WL_BC_PERIODIC && coord[c] == 0) L = 0.0;
+        M.L[c][id] = T(L);
+        if (M.L64[c]) M.L64[c][id] = L;
+    }
+}
+
+// Initial velocity: U_c on every face, boundary faces at their boundary value.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_init_velocity(Grid g, int b0, int b1, int b2, T U0, T U1,
+                                                          T U2, T* __restrict__ u0,
+                                                          T* __restrict__ u1, T* __restrict__ u2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= g.n0 || j >= g.n1) return;
+    const size_t id = cid(g, i, j, k);
+    const int coord[3] = {i, j, k};
+    const int per[3] = {g.per0, g.per1, g.per2};
+    const int bclo[3] = {b0, b1, b2};
+    const T U[3] = {U0, U1, U2};
+    T* u[3] = {u0, u1, u2};
+    for (int c = 0; c < 3; ++c) {
+        T v = c < g.ndim ? U[c] : T(0);
+        if (!per[c] && coord[c] == 0) v = (bclo[c] == WL_BC_INFLOW) ? U[c] : T(0);
+        u[c][id] = v;
+    }
+}
+
+// ------------------------------------------------------------- launchers
+
+template <typename T>
+wl_status ns_init_velocity(const Grid& g, const int bclo[3], const double U[3], T* const u[3],
+                           hipStream_t s) {
+    const Launch ln = launch_for(g.n0, g.n1, g.n2);
+    k_init_velocity<T><<<ln.grid, ln.block, 0, s>>>(g, bclo[0], bclo[1], bclo[2], T(U[0]), T(U[1]),
+                                                    T(U[2]), u[0], u[1], u[2]);
+    WL_CHECK_LAUNCH();
+    return WL_OK;
+}
+
+template <typename T>
+wl_status ns_measure(const Grid& g, const BodyDev& body, const int bclo[3], const MeasureOut<T>& M,
+                     hipStream_t s) {
+    const Launch ln = launch_for(g.n0, g.n1, g.n2);
+    k_measure<T><<<ln.grid, ln.block, 0, s>>>(g, body, bclo[0], bclo[1], bclo[2], M);
+    WL_CHECK_LAUNCH();
+    return WL_OK;
+}
+
+template <typename T>
+wl_status ns_momentum(const VelField<T>& E, const T* const un[3], T* const f[3], T nu, bool corr,
+                      bool allper, const double* dt_dev, hipStream_t s) {
+    const Grid& g = E.g;
+    const Launch ln = launch_for(g.n0, g.n1, g.n2);
+#define WL_MOM(AP, CR)                                                                      \
+    k_momentum<T, AP, CR><<<ln.grid, ln.block, 0, s>>>(E, un[0], un[1], un[2], f[0], f[1], f[2], \
+                                                        nu, dt_dev)
+    if (allper) {
+        if (corr) WL_MOM(true, true); else WL_MOM(true, false);
+    } else {
+        if (corr) WL_MOM(false, true); else WL_MOM(false, false);
+    }
+#undef WL_MOM
+    WL_CHECK_LAUNCH();
+    return WL_OK;
+}
+
+template <typename T>
+wl_status ns_outflow(const Grid& g, const T* ue_x, const T* out_e, const T* out_n, const T* f_x,
+                     T Ux, bool corr, const double* dt_dev, T* fout, hipStream_t s) {
+    if (corr)
+        k_outflow<T, true><<<1, 1024, 0, s>>>(g, ue_x, out_e, out_n, f_x, Ux, dt_dev, fout);
+    else
+        k_outflow<T, false><<<1, 1024, 0, s>>>(g, ue_x, out_e, out_n, f_x, Ux, dt_dev, fout);
+    WL_CHECK_LAUNCH();
+    return WL_OK;
+}
+
+template <typename T>
+wl_status ns_bdim(const VelField<T>& F, const BdimFields<T>& B, T* const out[3], hipStream_t s) {
+    const Launch ln = launch_for(F.g.n0, F.g.n1, F.g.n2);
+    k_bdim<T><<<ln.grid, ln.block, 0, s>>>(F, B, out[0], out[1], out[2]);
+    WL_CHECK_LAUNCH();
+    return WL_OK;
+}
+
+template <typename T>
+wl_status ns_divergence(const VelField<T>& V, double c, const double* dt_dev, T* sigma, bool allper,
+                        hipStream_t s) {
+    const Launch ln = launch_for(V.g.n0, V.g.n1, V.g.n2);
+    if (allper)
+        k_divergence<T, true><<<ln.grid, ln.block, 0, s>>>(V, c, dt_dev, sigma);
+    else
+        k_divergence<T, false><<<ln.grid, ln.block, 0, s>>>(V, c, dt_dev, sigma);
+    WL_CHECK_LAUNCH();
+    return WL_OK;
+}
+
+template <typename T>
+wl_status ns_project(const VelField<T>& V, const T* p, const ProjCoeffs<T>& C, bool unif, double c,
+                     const double* dt_dev, T* const out[3], bool cfl, double* partial, bool allper,
+                     hipStream_t s) {
+    const Launch ln = launch_for(V.g.n0, V.g.n1, V.g.n2);
+#define WL_PRJ(AP, UN, CF)                                                                      \
+    k_project<T, AP, UN, CF><<<ln.grid, ln.block, 0, s>>>(V, p, C, c, dt_dev, out[0], out[1], \
+                                                           out[2], partial)
+    if (allper) {
+        if (unif) {
+            if (cfl) WL_PRJ(true, true, true); else WL_PRJ(true, true, false);
+        } else {
+            if (cfl) WL_PRJ(true, false, true); else WL_PRJ(true, false, false);
+        }
+    } else {
+        if (unif) {
+            if (cfl) WL_PRJ(false, true, true); else WL_PRJ(false, true, false);
+        } else {
+            if (cfl) WL_PRJ(false, false, true); else WL_PRJ(false, false, false);
+        }
+    }
+#undef WL_PRJ
+    WL_CHECK_LAUNCH();
+    return WL_OK;
+}
+
+template <typename T>
+wl_status ns_cfl(const VelField<T>& V, bool allper, double* partial, hipStream_t s) {
+    const Launch ln = launch_for(V.g.n0, V.g.n1, V.g.n2);
+    if (allper)
+        k_cfl<T, true><<<ln.grid, ln.block, 0, s>>>(V, partial);
+    else
+        k_cfl<T, false><<<ln.grid, ln.block, 0, s>>>(V, partial);
+    WL_CHECK_LAUNCH();
+    return WL_OK;
+}
+
+wl_status ns_dt_from_max(const double* partial, size_t nslots, double cfl, double visc,
+                         double* dt_dev, double* max_dev, hipStream_t s) {
+    k_dt_from_max<<<1, 1024, 0, s>>>(partial, nslots, cfl, visc, dt_dev, max_dev);
+    WL_CHECK_LAUNCH();
+    return WL_OK;
+}
+
+wl_status ns_set_scalar(double* p, double v, hipStream_t s) {
+    k_set_scalar<<<1, 64, 0, s>>>(p, v);
+    WL_CHECK_LAUNCH();
+    return WL_OK;
+}
+
+#define WL_INST(T)                                                                               \
+    template wl_status ns_measure<T>(const Grid&, const BodyDev&, const int*,                     \
+                                     const MeasureOut<T>&, hipStream_t);                          \
+    template wl_status ns_momentum<T>(const VelField<T>&, const T* const*, T* const*, T, bool,   \
+                                      bool, const double*, hipStream_t);                          \
+    template wl_status ns_outflow<T>(const Grid&, const T*, const T*, const T*, const T*, T, bool, \
+                                     const double*, T*, hipStream_t);                             \
+    template wl_status ns_bdim<T>(const VelField<T>&, const BdimFields<T>&, T* const*,            \
+                                  hipStream_t);                                                   \
+    template wl_status ns_divergence<T>(const VelField<T>&, double, const double*, T*, bool,      \
+                                        hipStream_t);                                             \
+    template wl_status ns_project<T>(const VelField<T>&, const T*, const ProjCoeffs<T>&, bool,    \
+                                     double, const double*, T* const*, bool, double*, bool,        \
+                                     hipStream_t);                                                \
+    template wl_status ns_cfl<T>(const VelField<T>&, bool, double*, hipStream_t);          \
+    template wl_status ns_init_velocity<T>(const Grid&, const int*, const double*, T* const*,   \
+                                           hipStream_t);
+WL_INST(float)
+WL_INST(double)
+#undef WL_INST
+
+}  // namespace wl

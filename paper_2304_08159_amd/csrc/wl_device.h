@@ -1,0 +1,144 @@
+// Device-side helpers shared by the HIP translation units: cell indexing,
+// the coefficient-weighted 2d-point stencil and deterministic block sums.
+#pragma once
+
+#include "wl_internal.h"
+
+namespace wl {
+
+__device__ __forceinline__ size_t cid(const Grid& g, int i, int j, int k) {
+    return size_t(i) + size_t(g.n0) * (size_t(j) + size_t(g.n1) * size_t(k));
+}
+
+// Lower / upper neighbour coordinate along one direction (clamped when the
+// direction is not periodic; the face coefficient is zero there).
+__device__ __forceinline__ int nb_lo(int c, int n, int per) {
+    return c > 0 ? c - 1 : (per ? n - 1 : c);
+}
+__device__ __forceinline__ int nb_up(int c, int n, int per) {
+    return c < n - 1 ? c + 1 : (per ? 0 : c);
+}
+
+// How a smoother reads the iterate: the stored x, zero (first sweep on a
+// coarse level), or x plus the piecewise-constant prolongation of the
+// coarse correction xc.
+enum { XM_PLAIN = 0, XM_ZERO = 1, XM_PROLONG = 2 };
+
+template <typename T, int XM>
+struct XAccess {
+    const T* __restrict__ x;
+    const T* __restrict__ xc;
+    int nc0, nc1;
+    __device__ __forceinline__ T operator()(const Grid& g, int i, int j, int k) const {
+        if (XM == XM_ZERO) return T(0);
+        T v = x[cid(g, i, j, k)];
+        if (XM == XM_PROLONG)
+            v += xc[size_t(i >> 1) + size_t(nc0) * (size_t(j >> 1) + size_t(nc1) * size_t(k >> 1))];
+        return v;
+    }
+};
+
+template <typename T>
+struct Coeffs {
+    const T* __restrict__ L0;
+    const T* __restrict__ L1;
+    const T* __restrict__ L2;
+    T Lc;  // the constant coefficient when the level is uniform
+};
+
+// (A x)(I) and the diagonal magnitude D(I) = sum of the 2d face coefficients,
+// for A x = sum_d L_d(I+delta_d)(x(I+delta_d)-x(I)) - L_d(I)(x(I)-x(I-delta_d)).
+template <typename T, int XM, bool UNIF>
+__device__ __forceinline__ void apply_row(const Grid& g, const XAccess<T, XM>& X, const Coeffs<T>& C,
+                                          int i, int j, int k, T& xI, T& Ax, T& D) {
+    xI = X(g, i, j, k);
+    Ax = T(0);
+    D = T(0);
+    const size_t id = cid(g, i, j, k);
+    // direction 0
+    {
+        T Llo, Lup;
+        if (UNIF) {
+            Llo = C.Lc;
+            Lup = C.Lc;
+        } else {
+            Llo = C.L0[id];
+            Lup = (i < g.n0 - 1) ? C.L0[id + 1] : (g.per0 ? C.L0[id - (g.n0 - 1)] : T(0));
+        }
+        const T xl = X(g, nb_lo(i, g.n0, g.per0), j, k);
+        const T xu = X(g, nb_up(i, g.n0, g.per0), j, k);
+        Ax += Lup * (xu - xI) - Llo * (xI - xl);
+        D += Llo + Lup;
+    }
+    // direction 1
+    {
+        T Llo, Lup;
+        if (UNIF) {
+            Llo = C.Lc;
+            Lup = C.Lc;
+        } else {
+            Llo = C.L1[id];
+            Lup = (j < g.n1 - 1) ? C.L1[id + g.n0]
+                                 : (g.per1 ? C.L1[id - size_t(g.n1 - 1) * g.n0] : T(0));
+        }
+        const T xl = X(g, i, nb_lo(j, g.n1, g.per1), k);
+        const T xu = X(g, i, nb_up(j, g.n1, g.per1), k);
+        Ax += Lup * (xu - xI) - Llo * (xI - xl);
+        D += Llo + Lup;
+    }
+    // direction 2 (absent in 2D, where the z faces carry zero coefficients)
+    if (g.ndim == 3) {
+        const size_t plane = size_t(g.n0) * g.n1;
+        T Llo, Lup;
+        if (UNIF) {
+            Llo = C.Lc;
+            Lup = C.Lc;
+        } else {
+            Llo = C.L2[id];
+            Lup = (k < g.n2 - 1) ? C.L2[id + plane]
+                                 : (g.per2 ? C.L2[id - size_t(g.n2 - 1) * plane] : T(0));
+        }
+        const T xl = X(g, i, j, nb_lo(k, g.n2, g.per2));
+        const T xu = X(g, i, j, nb_up(k, g.n2, g.per2));
+        Ax += Lup * (xu - xI) - Llo * (xI - xl);
+        D += Llo + Lup;
+    }
+}
+
+// Deterministic sum of one double per thread over a 256-thread block: wave
+// butterflies, then the 4 wave totals in index order.  Returns the total in
+// thread 0 (other threads get an unspecified value).
+__device__ __forceinline__ double block_sum(double v, double* lds /* >= 4 */) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int t = threadIdx.x + blockDim.x * threadIdx.y;
+    if ((t & 63) == 0) lds[t >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (t == 0) {
+        const int nw = (blockDim.x * blockDim.y + 63) >> 6;
+        for (int w = 0; w < nw; ++w) s += lds[w];
+    }
+    return s;
+}
+
+__device__ __forceinline__ double block_max(double v, double* lds) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    const int t = threadIdx.x + blockDim.x * threadIdx.y;
+    if ((t & 63) == 0) lds[t >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (t == 0) {
+        const int nw = (blockDim.x * blockDim.y + 63) >> 6;
+        s = lds[0];
+        for (int w = 1; w < nw; ++w) s = fmax(s, lds[w]);
+    }
+    return s;
+}
+
+__device__ __forceinline__ unsigned block_linear() {
+    return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+}
+
+}  // namespace wl

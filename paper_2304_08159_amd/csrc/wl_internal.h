@@ -1,0 +1,147 @@
+// Internal declarations shared by the HIP translation units of libwl.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/wl.h"
+
+namespace wl {
+
+constexpr int kMaxLevels = 16;
+constexpr int kBlock = 256;           // threads per block of the stencil kernels
+constexpr int kCoarseMax = 1024;      // cells a one-workgroup coarsest solve accepts
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+void clear_error();
+
+#define WL_CHECK_HIP(expr)                                                            \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess) {                                                       \
+            ::wl::set_error(std::string("HIP error in " #expr ": ") +                 \
+                            hipGetErrorString(e_));                                   \
+            return WL_ERR_HIP;                                                        \
+        }                                                                             \
+    } while (0)
+
+#define WL_CHECK_LAUNCH() WL_CHECK_HIP(hipGetLastError())
+
+#define WL_TRY(expr)                                                                  \
+    do {                                                                              \
+        wl_status s_ = (expr);                                                        \
+        if (s_ != WL_OK) return s_;                                                   \
+    } while (0)
+
+// ------------------------------------------------------------- workspace
+// Bump allocator over the caller's device workspace.  With base == nullptr it
+// only counts, which is how the footprint calls compute exact sizes.
+struct Carver {
+    char* base = nullptr;
+    size_t off = 0;
+    template <typename T>
+    T* take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+// ------------------------------------------------------------ grid shapes
+// Kernel-side description of one grid level.
+struct Grid {
+    int n0, n1, n2;       // cells per direction
+    int per0, per1, per2; // periodic flags
+    int ndim;             // 2 or 3 (2: n2 == 1 and the z faces carry zero)
+};
+
+__host__ __device__ inline size_t cells(const Grid& g) { return size_t(g.n0) * g.n1 * g.n2; }
+
+// Launch shape for one-thread-per-cell kernels: x-fastest blocks of 256 threads.
+struct Launch {
+    dim3 grid, block;
+    unsigned nblocks() const { return grid.x * grid.y * grid.z; }
+};
+Launch launch_for(int n0, int n1, int n2);
+
+// Number of multigrid levels: halve every active direction while all of them
+// are even and the coarse grid keeps >= 4 cells each; an explicit request only
+// needs evenness.
+int auto_levels(int ndim, const int n[3], int requested);
+
+// ------------------------------------------------------ multigrid levels
+template <typename T>
+struct Level {
+    Grid g;
+    T* L[3] = {nullptr, nullptr, nullptr};  // lower-face coefficients
+    T* x[2] = {nullptr, nullptr};           // Jacobi ping-pong (level 0: x[0] is the caller's x)
+    T* b = nullptr;                         // right-hand side (level 0: projected copy)
+    int uniform = 0;                        // all active faces equal Lc, fully periodic
+    T Lc = T(1);
+};
+
+template <typename T>
+struct Hierarchy {
+    int nlev = 0;
+    Level<T> lev[kMaxLevels];
+    double omega = 0.0;
+    double coarse_tol = 1e-10;
+    size_t n_active = 0;         // active fine cells (host copy)
+};
+
+// Reduction scratch: per-block FP64 partial slots plus a few result scalars.
+struct Reduce {
+    double* partial = nullptr;   // capacity slots * 2
+    size_t slots = 0;
+    double* result = nullptr;    // 8 doubles
+};
+
+template <typename T>
+void carve_hierarchy(Carver& c, Hierarchy<T>& h, int ndim, const int n[3], const int per[3],
+                     int nlev, bool alloc_fine_x);
+
+// GMG building blocks (mg.hip).
+template <typename T>
+wl_status mg_coarsen_all(Hierarchy<T>& h, hipStream_t s);
+template <typename T>
+wl_status mg_count_active(Hierarchy<T>& h, Reduce& red, hipStream_t s);
+
+struct SolveResult {
+    int vcycles = 0;
+    double rel = 0.0;
+    double bnorm = 0.0;
+};
+
+// Plain GMG solve on h (level 0 x = caller x).  b is the raw right-hand side.
+template <typename T>
+wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, int max_vcycles,
+                   hipStream_t s, SolveResult* res);
+
+// Mixed precision: FP64 outer residual with FP64 fine coefficients L64,
+// FP32 inner V-cycles on h32.
+struct Mixed64 {
+    double* L[3] = {nullptr, nullptr, nullptr};
+    int inner = 3;
+};
+wl_status mg_solve_mixed(Hierarchy<float>& h32, const Mixed64& m, Reduce& red, double* x,
+                         const double* b, double tol, int max_vcycles, hipStream_t s,
+                         SolveResult* res);
+
+size_t reduce_slots_for(const Grid& g);
+
+template <typename Tin, typename Tout>
+wl_status mg_load_coeffs(const Grid& g, const Tin* src, Tout* const L[3], double* const L64[3],
+                         hipStream_t s);
+wl_status mg_count_active64(const Grid& g, double* const L64[3], Reduce& red, size_t* count,
+                            hipStream_t s);
+template <typename T>
+wl_status fill(T* p, size_t n, T v, hipStream_t s);
+template <typename Tin, typename Tout>
+wl_status convert(const Tin* a, Tout* b, size_t n, hipStream_t s);
+
+}  // namespace wl

@@ -1,0 +1,74 @@
+// Host/device structures and launchers of the Navier-Stokes step kernels.
+#pragma once
+
+#include "wl_internal.h"
+
+namespace wl {
+
+// A velocity field with its boundary description (device pointers).  u[c]
+// are interior face arrays; uout is the outflow plane (upper x boundary face)
+// or null when there is none.
+template <typename T>
+struct VelField {
+    const T* u[3];
+    const T* uout;
+    Grid g;
+    int bclo[3], bchi[3];
+    T U[3];
+};
+
+template <typename T>
+struct BdimFields {
+    const T* mu0[3];
+    const T* mu1n[9];
+};
+
+template <typename T>
+struct ProjCoeffs {
+    const T* L[3];
+    T Lc;
+};
+
+template <typename T>
+struct MeasureOut {
+    T* mu0[3];
+    T* mu1n[9];
+    T* L[3];
+    double* L64[3];  // optional FP64 copy of L (mixed-precision solves)
+};
+
+struct BodyDev {
+    int kind;
+    double centre[3];
+    double radius;
+    double eps;
+};
+
+template <typename T>
+wl_status ns_measure(const Grid& g, const BodyDev& body, const int bclo[3], const MeasureOut<T>& M,
+                     hipStream_t s);
+template <typename T>
+wl_status ns_momentum(const VelField<T>& E, const T* const un[3], T* const f[3], T nu, bool corr,
+                      bool allper, const double* dt_dev, hipStream_t s);
+template <typename T>
+wl_status ns_outflow(const Grid& g, const T* ue_x, const T* out_e, const T* out_n, const T* f_x,
+                     T Ux, bool corr, const double* dt_dev, T* fout, hipStream_t s);
+template <typename T>
+wl_status ns_bdim(const VelField<T>& F, const BdimFields<T>& B, T* const out[3], hipStream_t s);
+template <typename T>
+wl_status ns_divergence(const VelField<T>& V, double c, const double* dt_dev, T* sigma, bool allper,
+                        hipStream_t s);
+template <typename T>
+wl_status ns_project(const VelField<T>& V, const T* p, const ProjCoeffs<T>& C, bool unif, double c,
+                     const double* dt_dev, T* const out[3], bool cfl, double* partial, bool allper,
+                     hipStream_t s);
+template <typename T>
+wl_status ns_cfl(const VelField<T>& V, bool allper, double* partial, hipStream_t s);
+wl_status ns_dt_from_max(const double* partial, size_t nslots, double cfl, double visc,
+                         double* dt_dev, double* max_dev, hipStream_t s);
+wl_status ns_set_scalar(double* p, double v, hipStream_t s);
+template <typename T>
+wl_status ns_init_velocity(const Grid& g, const int bclo[3], const double U[3], T* const u[3],
+                           hipStream_t s);
+
+}  // namespace wl

@@ -1,0 +1,133 @@
+"""GPU parity of the Navier-Stokes step against the FP64 oracle (replay mode).
+
+Replay: the oracle starts from the GPU state u^n, p^n (widened to FP64),
+takes the GPU's dt and V-cycle counts, and advances one step; the GPU's
+u^{n+1}, p^{n+1} must match to 1e-5 relative L2 (pressure compared mean-free
+over active cells).
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import geometry as G
+from oracle import momentum as M
+from oracle import step as S
+from tests.gpu_util import mean_free, plane_to_oracle, rel_l2, to_device, to_oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _make(cfg, prec, tol):
+    import paper_2304_08159_amd as wl
+    sim = wl.Sim(cfg["n"], cfg["bc_lo"], cfg["bc_hi"], cfg["U"], cfg["nu"], body=cfg.get("body"),
+                 prec=prec, levels=cfg.get("levels", 0), tol=tol, cfl=cfg.get("cfl", 0.5))
+    osim = S.Sim(cfg["n"], cfg["bc_lo"], cfg["bc_hi"], cfg["U"], cfg["nu"], body=cfg.get("body"),
+                 levels=cfg.get("levels", 0), tol=tol, cfl=cfg.get("cfl", 0.5))
+    return sim, osim
+
+
+def _replay(sim, osim, nsteps, tol_u, tol_p, label):
+    d = sim.ndim
+    worst_u = worst_p = 0.0
+    for step in range(nsteps):
+        un = [to_oracle(t, d) for t in sim.velocity()]
+        pn = to_oracle(sim.pressure(), d)
+        outflow = osim.bc_hi[0] == 2
+        uo = plane_to_oracle(sim.get(4), d) if outflow else None
+        st = sim.step()
+        osim.u, osim.p, osim.uout = un, pn, uo
+        ost = osim.step(dt=st["dt"], force_vcycles=st["vcycles"])
+        act = osim.h.active[0]
+        ug = [to_oracle(t, d) for t in sim.velocity()]
+        eu = math.sqrt(sum(np.sum((a - b) ** 2) for a, b in zip(ug, osim.u)) /
+                       sum(np.sum(b ** 2) for b in osim.u))
+        ep = rel_l2(mean_free(to_oracle(sim.pressure(), d), act), mean_free(osim.p, act), act)
+        worst_u, worst_p = max(worst_u, eu), max(worst_p, ep)
+        print(f"{label} step {step}: dt={st['dt']:.6f} vc={st['vcycles']} "
+              f"res={st['rel_resid'][0]:.2e},{st['rel_resid'][1]:.2e} err_u={eu:.2e} err_p={ep:.2e}")
+    assert worst_u <= tol_u and worst_p <= tol_p
+    return worst_u, worst_p
+
+
+def test_geometry_measure_matches_oracle():
+    import paper_2304_08159_amd as wl
+    for n, bc_lo, bc_hi, body, prec in [
+        ((48, 32), [1, 3], [2, 3], dict(centre=(16.3, 15.8), radius=6.0), wl.WL_FP64),
+        ((40, 24, 24), [1, 3, 0], [2, 3, 0], dict(centre=(12.0, 12.2, 11.7), radius=5.0),
+         wl.WL_FP32),
+    ]:
+        d = len(n)
+        sim = wl.Sim(n, bc_lo, bc_hi, (1.0,) + (0.0,) * (d - 1), 0.01, body=body, prec=prec)
+        mu0, mu1n, L = G.measure(n, bc_lo, body)
+        tol = 1e-14 if prec == wl.WL_FP64 else 2e-7
+        for i in range(d):
+            np.testing.assert_allclose(to_oracle(sim.get(wl.FIELD_L0 + i), d), L[i], atol=tol)
+            np.testing.assert_allclose(to_oracle(sim.get(wl.FIELD_MU0_0 + i), d), mu0[i], atol=tol)
+            for j in range(d):
+                np.testing.assert_allclose(to_oracle(sim.get(wl.FIELD_MU1N + 3 * i + j), d),
+                                           mu1n[i][j], atol=tol)
+
+
+def test_cfl_time_step_closed_form():
+    import paper_2304_08159_amd as wl
+    n = (32, 16, 16)
+    sim = wl.Sim(n, [0, 0, 0], [0, 0, 0], (1.5, 0.0, 0.0), 0.02, prec=wl.WL_FP64, tol=1e-8)
+    st = sim.step()
+    assert st["dt"] == pytest.approx(0.5 / (1.5 + 6 * 0.02), rel=1e-15)
+    assert st["vcycles"] == (0, 0)   # uniform flow: zero divergence, nothing to solve
+
+
+def test_tgv3d_fp32_replay_parity():
+    import paper_2304_08159_amd as wl
+    N = 32
+    u, v, w, nu = W.tgv3d(N)
+    cfg = dict(n=(N, N, N), bc_lo=[0] * 3, bc_hi=[0] * 3, U=(0.0, 0.0, 0.0), nu=nu)
+    sim, osim = _make(cfg, wl.WL_FP32, 1e-5)
+    for i, a in enumerate((u, v, w)):
+        sim.set(wl.FIELD_U0 + i, to_device(a, 3, torch, torch.float32))
+    _replay(sim, osim, 4, 1e-5, 1e-5, "tgv32")
+
+
+def test_tgv2d_fp64_free_running_matches_oracle():
+    import paper_2304_08159_amd as wl
+    N = 48
+    u, v, p, nug = W.tgv2d(N, 0.01)
+    cfg = dict(n=(N, N), bc_lo=[0, 0], bc_hi=[0, 0], U=(0.0, 0.0), nu=nug)
+    sim, osim = _make(cfg, wl.WL_FP64, 1e-10)
+    sim.set(wl.FIELD_U0, to_device(u, 2, torch, torch.float64))
+    sim.set(wl.FIELD_U0 + 1, to_device(v, 2, torch, torch.float64))
+    osim.u = [u.copy(), v.copy()]
+    for _ in range(5):
+        st = sim.step()
+        ost = osim.step()
+        assert st["dt"] == pytest.approx(ost["dt"], rel=1e-12)
+    ug = [to_oracle(t, 2) for t in sim.velocity()]
+    err = math.sqrt(sum(np.sum((a - b) ** 2) for a, b in zip(ug, osim.u)) /
+                    sum(np.sum(b ** 2) for b in osim.u))
+    print(f"tgv2d fp64 free-running 5 steps: err_u={err:.3e}")
+    assert err <= 1e-9
+
+
+def test_cylinder_fp64_replay_parity():
+    import paper_2304_08159_amd as wl
+    cfg = W.cylinder_config()
+    sim, osim = _make(cfg, wl.WL_FP64, cfg["tol"])
+    _replay(sim, osim, 6, 1e-9, 1e-7, "cylinder")
+    # mirror symmetry and the inflow / wall boundary values on the GPU
+    u, v = [to_oracle(t, 2) for t in sim.velocity()]
+    assert np.abs(u - u[:, ::-1]).max() < 1e-10
+    assert np.all(u[0] == 1.0) and np.all(v[:, 0] == 0.0)
+    uo = plane_to_oracle(sim.get(4), 2)
+    assert uo.sum() == pytest.approx(64.0, rel=1e-12)
+
+
+def test_sphere_fp32_replay_parity():
+    import paper_2304_08159_amd as wl
+    cfg = dict(n=(64, 32, 32), bc_lo=[1, 3, 3], bc_hi=[2, 3, 3], U=(1.0, 0.0, 0.0),
+               nu=0.08, body=dict(centre=(16.0, 16.0, 16.0), radius=4.0), tol=1e-5)
+    sim, osim = _make(cfg, wl.WL_FP32, cfg["tol"])
+    _replay(sim, osim, 3, 1e-5, 1e-5, "sphere")

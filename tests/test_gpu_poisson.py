@@ -1,0 +1,103 @@
+"""GPU parity of the GMG pressure solve against the FP64 oracle."""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import geometry as G
+from oracle import poisson as P
+from oracle.grid import PERIODIC, WALL, auto_levels
+from tests.gpu_util import mean_free, rel_l2, to_device, to_oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _case(n, per, body, seed):
+    d = len(n)
+    bc = [PERIODIC if p else WALL for p in per]
+    L = G.measure(n, bc, body)[2]
+    b = W.random_rhs(n, seed)
+    return L, b
+
+
+def _coeff_tensor(L, ndim, dtype):
+    return torch.stack([to_device(L[i], ndim, torch, dtype) for i in range(ndim)]).contiguous()
+
+
+CASES = [
+    ((32, 32, 32), (False, False, False), dict(centre=(15.6, 16.2, 16.7), radius=6.5), 0),
+    ((24, 20, 12), (True, False, True), dict(centre=(11.0, 10.0, 6.0), radius=4.0), 0),
+    ((64, 48), (False, True), dict(centre=(30.0, 24.5), radius=9.0), 0),
+    ((96, 40, 32), (True, True, True), None, 0),
+    ((128, 64), (False, False), dict(centre=(32.0, 32.0), radius=8.0), 4),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n,per,body,levels", CASES)
+def test_gmg_solve_matches_oracle_replay(n, per, body, levels, prec):
+    import paper_2304_08159_amd as wl
+    ndim = len(n)
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    L, b = _case(n, per, body, seed=11)
+    ps = wl.Poisson(n, per, prec=wl.WL_FP64 if prec == "fp64" else wl.WL_FP32, levels=levels)
+    x = torch.zeros(ps.shape, dtype=dtype, device="cuda")
+    tol = 1e-9 if prec == "fp64" else 1e-5
+    k, rel = ps.solve(_coeff_tensor(L, ndim, dtype), x, to_device(b, ndim, torch, dtype), tol=tol)
+    h = P.Hierarchy(L, auto_levels(n, levels), list(per))
+    xo, ko, hist, _ = P.solve(h, b, tol=tol, force_vcycles=k)
+    act = h.active[0]
+    xg = to_oracle(x, ndim)
+    err = rel_l2(mean_free(xg, act), mean_free(xo, act), act)
+    print(f"{n} {per} {prec}: vcycles={k} rel={rel:.3e} oracle_rel={hist[-1]:.3e} err={err:.3e}")
+    assert rel <= tol and k >= 1
+    assert abs(np.log10(max(rel, 1e-300)) - np.log10(max(hist[-1], 1e-300))) < 0.5
+    assert err <= (1e-9 if prec == "fp64" else 1e-5)
+    # inactive cells are returned as zero
+    assert np.all(xg[~act] == 0.0)
+
+
+def test_mixed_precision_reaches_fp64_tolerance():
+    import paper_2304_08159_amd as wl
+    n, per = (32, 32, 32), (False, False, False)
+    L, b = _case(n, per, dict(centre=(16.0, 16.0, 16.0), radius=8.0), 0)
+    ps = wl.Poisson(n, per, prec=wl.WL_MIXED)
+    x = torch.zeros(ps.shape, dtype=torch.float64, device="cuda")
+    k, rel = ps.solve(_coeff_tensor(L, 3, torch.float64), x,
+                      to_device(b, 3, torch, torch.float64), tol=1e-8)
+    xg = to_oracle(x, 3)
+    h = P.Hierarchy(L, auto_levels(n), list(per))
+    act = h.active[0]
+    bp = P.project_rhs(b, act)
+    res = np.linalg.norm(bp - P.apply_A(L, xg, list(per))) / np.linalg.norm(bp)
+    xo, *_ = P.solve(h, b, tol=1e-12)
+    err = rel_l2(mean_free(xg, act), mean_free(xo, act), act)
+    print(f"mixed: vcycles={k} rel={rel:.3e} oracle-recomputed={res:.3e} err vs oracle={err:.3e}")
+    assert rel <= 1e-8 and res <= 1.05e-8
+    assert err <= 1e-6
+
+
+def test_zero_rhs_and_not_converged_and_bad_args():
+    import paper_2304_08159_amd as wl
+    n, per = (16, 16, 16), (True, True, True)
+    L, b = _case(n, per, None, 0)
+    ps = wl.Poisson(n, per, prec=wl.WL_FP32)
+    C = _coeff_tensor(L, 3, torch.float32)
+    x = torch.ones(ps.shape, dtype=torch.float32, device="cuda")
+    k, rel = ps.solve(C, x, torch.zeros_like(x), tol=1e-6)
+    assert k == 0 and rel == 0.0 and float(x.abs().max()) == 0.0
+    with pytest.raises(wl.WlError) as e:
+        ps.solve(None, x, to_device(b, 3, torch, torch.float32), tol=1e-30, max_vcycles=2)
+    assert e.value.status == -3
+    k, rel = ps.solve(None, x.zero_(), to_device(b, 3, torch, torch.float32), tol=1e-30,
+                      max_vcycles=2, allow_not_converged=True)
+    assert k == 2 and 0.0 < rel < 1.0
+    with pytest.raises(wl.WlError) as e:
+        wl.Poisson((16, 16, 3), per, prec=wl.WL_FP32, levels=2)
+    assert e.value.status == -1
+    nan_b = to_device(b, 3, torch, torch.float32)
+    nan_b[0, 0, 0] = float("nan")
+    with pytest.raises(wl.WlError) as e:
+        ps.solve(None, x.zero_(), nan_b, tol=1e-6)
+    assert e.value.status == -4
