@@ -1,0 +1,196 @@
+"""Benchmark: 3D Taylor-Green vortex time steps on one MI355X.
+
+Workload (the metric configuration): triply periodic TGV, N^3 = 256^3 cells,
+FP32 fields and FP32 GMG pressure solves to relative residual 1e-5, Re = 1600,
+no body, CFL-adaptive Heun steps.  A step is one full pass of the hot path:
+CFL time step, two stages of convection-diffusion + divergence + GMG solve +
+projection.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line: cell-steps/s, the roofline of the dominant kernel
+(algorithmic bytes / HIP-event-timed launch duration vs 8 TB/s), the
+whole-step algorithmic-byte fraction, and the FP64 oracle timed on the host
+as a CPU baseline.
+"""
+
+import argparse
+import ctypes
+import json
+import math
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per fine cell of each timed kernel class (FP32, 3D,
+# uniform coefficients: the TGV has no body and is periodic, so the Poisson
+# coefficients are never read).  Reads + writes of the fields each kernel
+# must touch once.
+BYTES_PER_CELL = {
+    "smooth_fine": 12.0,     # read x, b; write x'
+    "smooth_norm": 12.0,     # same sweep + per-block partial sums
+    "prolong_fine": 12.5,    # read x, b, x_coarse (1/8); write x'
+    "restrict_fine": 8.5,    # read x, b; write b_coarse (1/8)
+    "momentum": 30.0,        # predictor 24 (read u, write f), corrector 36 (+ read u^n)
+    "divergence": 16.0,      # read u* (3 comps); write sigma
+    "project": 28.0,         # read u* (3), p; write u (3)
+}
+
+
+def step_bytes_per_cell(vcycles_total, nlev_coarse_factor=1.0 / 7.0):
+    """Algorithmic bytes of one step per fine cell (FP32, uniform L, 3D).
+
+    momentum 24 + 36, divergence 2 x 16, projection 2 x 28, per solve the
+    active-mean pass (4) and the projecting first sweep (16), and per V-cycle
+    the fine sweeps/transfers (12 + 8.5 + 12.5 + 12) plus the norm sweep (12)
+    and the coarse levels (53 B per coarse cell, 1/7 of the fine count).
+    """
+    per_vcycle = 12 + 8.5 + 12.5 + 12 + 12 + 53.0 * nlev_coarse_factor
+    return 60.0 + 32.0 + 56.0 + 2 * 20.0 + per_vcycle * vcycles_total
+
+
+def cpu_baseline(N, vcycles):
+    """Time the FP64 oracle for one Heun step of the TGV at N^3 on one core."""
+    code = (
+        "import sys, time; sys.path.insert(0, %r)\n"
+        "import workloads as W\n"
+        "from oracle import step as S\n"
+        "N = %d\n"
+        "u, v, w, nu = W.tgv3d(N)\n"
+        "sim = S.Sim((N, N, N), [0]*3, [0]*3, (0, 0, 0), nu, tol=1e-5)\n"
+        "sim.u = [u, v, w]\n"
+        "dt = sim.dt_cfl()\n"
+        "t = time.perf_counter()\n"
+        "sim.step(dt=dt, force_vcycles=%r)\n"
+        "print(time.perf_counter() - t)\n"
+    ) % (ROOT, N, tuple(vcycles))
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                       timeout=600)
+    if r.returncode != 0:
+        raise RuntimeError(r.stderr)
+    secs = float(r.stdout.strip().splitlines()[-1])
+    return dict(value=N ** 3 / secs, unit="cell-steps/s", cores=1, kind="oracle",
+                sample=f"one Heun step of the 3D TGV at {N}^3 (FP64 NumPy oracle, "
+                       f"V-cycles per solve {tuple(vcycles)} = the GPU's mean), {secs:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--N", type=int, default=256)
+    ap.add_argument("--cpu-N", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(multi-GPU sharding is a design note, not implemented)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2304_08159_amd as wl
+    from paper_2304_08159_amd import _lib
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    N = args.N
+    u, v, w, nu = W.tgv3d(N)
+    sim = wl.Sim((N, N, N), [0] * 3, [0] * 3, (0.0, 0.0, 0.0), nu, prec=wl.WL_FP32, tol=1e-5,
+                 max_vcycles=100)
+    for i, a in enumerate((u, v, w)):
+        t = torch.from_numpy(np.ascontiguousarray(a.transpose(2, 1, 0))).float().cuda()
+        sim.set(wl.FIELD_U0 + i, t)
+    del u, v, w
+    for _ in range(args.warmup):
+        sim.step()
+    lib = _lib.load()
+
+    def ctypes_mask(on):
+        return (1 << len(_lib.PROF)) - 1 if on else 0
+
+    def timed(nsteps, profile):
+        lib.wl_profile_enable(ctypes_mask(profile))
+        lib.wl_profile_reset()
+        vc = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            st = sim.step()
+            vc.append(st["vcycles"])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        lib.wl_profile_enable(0)
+        return el, vc
+
+    # timed region: value (no event brackets)
+    elapsed, vcs = timed(args.steps, False)
+    # same number of steps again with HIP-event brackets on every timed kernel class
+    elapsed_p, vcs_p = timed(args.steps, True)
+    kern = {}
+    for name, kid in _lib.PROF.items():
+        ms, n, cellsn = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_longlong()
+        lib.wl_profile_read(kid, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(cellsn))
+        if n.value:
+            avg_us = 1e3 * ms.value / n.value
+            bytes_launch = BYTES_PER_CELL[name] * cellsn.value
+            kern[name] = dict(launches=n.value, total_ms=ms.value, avg_us=avg_us,
+                              gbs=bytes_launch / (avg_us * 1e-6) / 1e9)
+    dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    ms_step = 1e3 * elapsed / args.steps
+    cells = N ** 3
+    value = cells * args.steps / elapsed
+    vc_mean = [float(np.mean([a[i] for a in vcs])) for i in range(2)]
+    step_b = step_bytes_per_cell(sum(vc_mean)) * cells
+    step_gbs = step_b / (ms_step * 1e-3) / 1e9
+    out = {
+        "metric": "cell-steps/s (3D TGV 256^3 FP32)",
+        "value": value,
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"3D Taylor-Green vortex, triply periodic {N}^3, FP32, Re=1600, "
+                               f"no body, CFL 0.5 Heun steps, FP32 GMG to 1e-5",
+                   "N": N, "Re": 1600, "tol": 1e-5,
+                   "vcycles_per_solve_mean": vc_mean},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dom,
+            "achieved": kern[dom]["gbs"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": kern[dom]["gbs"] / HBM_PEAK_GBS,
+            "traffic": None,
+            "bytes_per_cell": BYTES_PER_CELL[dom],
+            "avg_launch_us": kern[dom]["avg_us"],
+        },
+        "step_roofline": {"alg_bytes_per_step": step_b, "achieved_GBs": step_gbs,
+                          "frac": step_gbs / HBM_PEAK_GBS},
+        "kernels": kern,
+        "profiled_ms_per_step": 1e3 * elapsed_p / args.steps,
+    }
+    if not args.no_cpu_baseline:
+        vcr = [max(1, int(round(x))) for x in vc_mean]
+        try:
+            out["cpu_baseline"] = cpu_baseline(args.cpu_N, vcr)
+        except Exception as e:  # report, do not hide
+            out["cpu_baseline"] = {"error": str(e)[:200]}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

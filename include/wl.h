@@ -94,7 +94,8 @@ typedef struct {
     wl_body body;
     int prec;             /* wl_precision                                     */
     int mg_levels;        /* 0 = automatic coarsening                         */
-    double tol;           /* relative residual of each pressure solve         */
+    double tol;           /* pressure solves stop once the RMS divergence they
+                             leave in the projected velocity is <= tol        */
     int max_vcycles;      /* per pressure solve (<= 0 selects 100)            */
     int inner_vcycles;    /* MIXED: FP32 V-cycles per outer iteration (0: 3)  */
     double cfl;           /* CFL number of the adaptive time step (0: 0.5)    */
@@ -104,7 +105,8 @@ typedef struct {
     double dt;            /* time step taken                                  */
     double t;             /* simulation time after the step                   */
     int vcycles[2];       /* V-cycles of the predictor and corrector solves   */
-    double rel_resid[2];  /* final relative residuals of the two solves       */
+    double resid[2];      /* RMS divergence each solve leaves in the projected
+                             velocity, c dt ||sigma - A p||_2 / sqrt(n_active) */
 } wl_step_stats;
 
 /* Fields addressable by wl_set_field / wl_get_field. */
@@ -173,6 +175,32 @@ wl_status wl_poisson_solve(wl_poisson* ps, const void* coeffs, void* x, const vo
                            double tol, int max_vcycles, int* vcycles_out,
                            double* rel_resid_out);
 wl_status wl_poisson_destroy(wl_poisson* ps);
+
+/* ---- Kernel timing (measurement support) -------------------------------- */
+
+/* Kernels whose launches can be bracketed by HIP events, to turn algorithmic
+ * bytes into achieved bandwidth without an external profiler.  Fine level
+ * means the caller's grid (level 0 of the multigrid hierarchy). */
+enum {
+    WL_PROF_SMOOTH_FINE = 0,     /* plain damped-Jacobi sweep, fine level     */
+    WL_PROF_SMOOTH_NORM = 1,     /* sweep fused with the residual norm        */
+    WL_PROF_PROLONG_FINE = 2,    /* prolongation fused with a sweep, fine     */
+    WL_PROF_RESTRICT_FINE = 3,   /* residual + restriction, fine level        */
+    WL_PROF_MOMENTUM = 4,        /* convection-diffusion stage update         */
+    WL_PROF_DIVERGENCE = 5,      /* projection right-hand side                */
+    WL_PROF_PROJECT = 6,         /* pressure-gradient update (+ CFL)          */
+    WL_PROF_COUNT = 7
+};
+
+/* Enable event timing for the kernels in mask (bit k = kernel k); 0 turns it
+ * off.  Events are recorded on the stream each kernel is launched on. */
+wl_status wl_profile_enable(unsigned mask);
+/* Clear accumulated timings. */
+wl_status wl_profile_reset(void);
+/* Synchronise the recorded events and return the total time in ms, the
+ * number of timed launches and the grid cells each launch covered (last). */
+wl_status wl_profile_read(int kernel, double* total_ms, long long* launches,
+                          long long* cells_per_launch);
 
 /* ---- Misc --------------------------------------------------------------- */
 

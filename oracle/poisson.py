@@ -186,10 +186,12 @@ def vcycle(h, lev, x, b):
     return x
 
 
-def solve(h, b, x0=None, tol=1e-8, max_vcycles=100, force_vcycles=None):
+def solve(h, b, x0=None, tol=1e-8, max_vcycles=100, force_vcycles=None, atol=0.0):
     """GMG solve of A x = b on hierarchy h.
 
-    Returns (x, vcycles, rel_resid_history, converged).  With force_vcycles the
+    Stops before a V-cycle once ||b - A x||_2 <= tol ||b||_2 or
+    ||b - A x||_2 <= atol (both norms over the projected b).  Returns
+    (x, vcycles, rel_resid_history, converged).  With force_vcycles the
     stopping test is replaced by exactly that many V-cycles (replay mode).
     """
     L, per = h.L[0], h.per
@@ -202,13 +204,14 @@ def solve(h, b, x0=None, tol=1e-8, max_vcycles=100, force_vcycles=None):
     hist = []
     k = 0
     while True:
-        rel = np.linalg.norm(b - apply_A(L, x, per)) / (bnorm if bnorm > 0 else 1.0)
+        res = np.linalg.norm(b - apply_A(L, x, per))
+        rel = res / (bnorm if bnorm > 0 else 1.0)
         hist.append(rel)
         if force_vcycles is not None:
             if k == force_vcycles:
                 return x, k, hist, True
         else:
-            if rel <= tol:
+            if rel <= tol or res <= atol:
                 return x, k, hist, True
             if k == max_vcycles:
                 return x, k, hist, False

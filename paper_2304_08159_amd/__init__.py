@@ -129,7 +129,7 @@ class Sim:
         check(self._lib.wl_step(self._h, float(dt), ctypes.byref(st)),
               allow=(-3,) if allow_not_converged else ())
         return dict(dt=st.dt, t=st.t, vcycles=(st.vcycles[0], st.vcycles[1]),
-                    rel_resid=(st.rel_resid[0], st.rel_resid[1]))
+                    resid=(st.resid[0], st.resid[1]))
 
 
 class Poisson:

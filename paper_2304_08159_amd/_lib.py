@@ -27,8 +27,11 @@ FIELD_L0, FIELD_MU0_0, FIELD_MU1N, FIELD_SIGMA = 5, 8, 11, 20
 EXPORTS = (
     "wl_sim_footprint", "wl_sim_create", "wl_sim_destroy", "wl_set_field", "wl_get_field",
     "wl_set_time", "wl_step", "wl_poisson_footprint", "wl_poisson_create",
-    "wl_poisson_solve", "wl_poisson_destroy", "wl_last_error", "wl_version",
+    "wl_poisson_solve", "wl_poisson_destroy", "wl_profile_enable", "wl_profile_reset",
+    "wl_profile_read", "wl_last_error", "wl_version",
 )
+PROF = dict(smooth_fine=0, smooth_norm=1, prolong_fine=2, restrict_fine=3, momentum=4,
+            divergence=5, project=6)
 
 
 class WlError(RuntimeError):
@@ -53,7 +56,7 @@ class SimDesc(ctypes.Structure):
 
 class StepStats(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("t", ctypes.c_double),
-                ("vcycles", ctypes.c_int * 2), ("rel_resid", ctypes.c_double * 2)]
+                ("vcycles", ctypes.c_int * 2), ("resid", ctypes.c_double * 2)]
 
 
 _lib = None
@@ -81,6 +84,10 @@ def load():
         "wl_poisson_create": [i32, ip3, ip3, i32, i32, vp, sz, vp, ctypes.POINTER(vp)],
         "wl_poisson_solve": [vp, vp, vp, vp, f64, i32, ctypes.POINTER(i32), ctypes.POINTER(f64)],
         "wl_poisson_destroy": [vp],
+        "wl_profile_enable": [ctypes.c_uint],
+        "wl_profile_reset": [],
+        "wl_profile_read": [i32, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_longlong),
+                            ctypes.POINTER(ctypes.c_longlong)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

@@ -104,6 +104,7 @@ struct SimImpl {
     double* p64 = nullptr;
     double* sigma64 = nullptr;
     double t = 0.0;
+    double dt_next_host = 0.0;
     bool cfl_valid = false;
 };
 
@@ -206,13 +207,19 @@ static wl_status sim_init(SimImpl<T>& s, hipStream_t st) {
     return WL_OK;
 }
 
+// Pressure solve of one stage.  It stops once the divergence it leaves in the
+// projected velocity, c dt (sigma - A p), has RMS over the active cells <= tol,
+// i.e. ||r||^2 <= (tol sqrt(n_active) / (c dt))^2.
 template <typename T>
-static wl_status pressure_solve(SimImpl<T>& s, hipStream_t st, SolveResult* r) {
+static wl_status pressure_solve(SimImpl<T>& s, double cfac, double dt, hipStream_t st,
+                                SolveResult* r) {
     const SimConfig& c = s.cfg;
+    const double a = c.d.tol * std::sqrt(double(s.h.n_active)) / (cfac * dt);
+    const double abs_r2 = a * a;
     if (c.d.prec == WL_MIXED) {
         if constexpr (sizeof(T) == 4) {
             WL_TRY((convert<float, double>(s.sigma, s.sigma64, c.N, st)));
-            wl_status rc = mg_solve_mixed(s.h, s.mix, s.red, s.p64, s.sigma64, c.d.tol,
+            wl_status rc = mg_solve_mixed(s.h, s.mix, s.red, s.p64, s.sigma64, 0.0, abs_r2,
                                           c.d.max_vcycles, st, r);
             if (rc != WL_OK && rc != WL_ERR_NOT_CONVERGED) return rc;
             WL_TRY((convert<double, float>(s.p64, s.p, c.N, st)));
@@ -220,7 +227,7 @@ static wl_status pressure_solve(SimImpl<T>& s, hipStream_t st, SolveResult* r) {
         }
         return invalid("mixed precision needs FP32 fields");
     }
-    return mg_solve<T>(s.h, s.red, s.p, s.sigma, c.d.tol, c.d.max_vcycles, st, r);
+    return mg_solve<T>(s.h, s.red, s.p, s.sigma, 0.0, abs_r2, c.d.max_vcycles, st, r);
 }
 
 template <typename T>
@@ -228,12 +235,22 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
     const SimConfig& c = s.cfg;
     const bool ap = c.allper;
     double* dt_dev = s.scal + s.dt_cur;
+    double dt = 0.0;
     if (dt_in > 0.0) {
         WL_TRY(ns_set_scalar(dt_dev, dt_in, st));
-    } else if (!s.cfl_valid) {
+        dt = dt_in;
+    } else if (s.cfl_valid) {
+        dt = s.dt_next_host;  // computed on the device by the last projection
+    } else {
         WL_TRY(ns_cfl<T>(field_of(s, s.S, s.plane[s.PS]), ap, s.red.partial, st));
         WL_TRY(ns_dt_from_max(s.red.partial, s.red.slots, c.d.cfl, 2.0 * c.d.ndim * c.d.nu, dt_dev,
                               s.scal + 2, st));
+        WL_CHECK_HIP(hipMemcpyAsync(&dt, dt_dev, sizeof(double), hipMemcpyDeviceToHost, st));
+        WL_CHECK_HIP(hipStreamSynchronize(st));
+    }
+    if (!(dt > 0.0) || !std::isfinite(dt)) {
+        set_error("time step is not positive (zero velocity and zero viscosity?)");
+        return WL_ERR_INVALID_ARG;
     }
     const int S = s.S;
     const int A = (S + 1) % 3, B = (S + 2) % 3;
@@ -259,7 +276,7 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
         }
         const VelField<T> V = field_of(s, us, s.plane[P1]);
         WL_TRY(ns_divergence<T>(V, 1.0, dt_dev, s.sigma, ap, st));
-        wl_status rc = pressure_solve(s, st, &r1);
+        wl_status rc = pressure_solve(s, 1.0, dt, st, &r1);
         if (rc == WL_ERR_NOT_CONVERGED) worst = rc;
         else if (rc != WL_OK) return rc;
         ProjCoeffs<T> pc{{s.h.lev[0].L[0], s.h.lev[0].L[1], s.h.lev[0].L[2]}, T(1)};
@@ -286,7 +303,7 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
         }
         const VelField<T> V2 = field_of(s, us2, s.plane[P2]);
         WL_TRY(ns_divergence<T>(V2, 0.5, dt_dev, s.sigma, ap, st));
-        rc = pressure_solve(s, st, &r2);
+        rc = pressure_solve(s, 0.5, dt, st, &r2);
         if (rc == WL_ERR_NOT_CONVERGED) worst = rc;
         else if (rc != WL_OK) return rc;
         int dest = (us2 == S) ? u1 : S;
@@ -298,8 +315,8 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
         s.S = dest;
         s.PS = P2;
     }
-    double dt = 0.0;
-    WL_CHECK_HIP(hipMemcpyAsync(&dt, dt_dev, sizeof(double), hipMemcpyDeviceToHost, st));
+    WL_CHECK_HIP(hipMemcpyAsync(&s.dt_next_host, s.scal + (1 - s.dt_cur), sizeof(double),
+                                hipMemcpyDeviceToHost, st));
     WL_CHECK_HIP(hipStreamSynchronize(st));
     s.dt_cur = 1 - s.dt_cur;
     s.cfl_valid = true;
@@ -309,8 +326,9 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
         stats->t = s.t;
         stats->vcycles[0] = r1.vcycles;
         stats->vcycles[1] = r2.vcycles;
-        stats->rel_resid[0] = r1.rel;
-        stats->rel_resid[1] = r2.rel;
+        const double na = double(s.h.n_active > 0 ? s.h.n_active : 1);
+        stats->resid[0] = 1.0 * dt * std::sqrt(r1.r2 / na);
+        stats->resid[1] = 0.5 * dt * std::sqrt(r2.r2 / na);
     }
     return worst;
 }
@@ -449,8 +467,8 @@ static wl_status poisson_solve_plain(wl_poisson* ps, const void* coeffs, void* x
     }
     if (!P.have) return invalid("no coefficients given yet");
     SolveResult r;
-    wl_status rc = mg_solve<T>(P.h, P.red, static_cast<T*>(x), static_cast<const T*>(b), tol, maxv,
-                               st, &r);
+    wl_status rc = mg_solve<T>(P.h, P.red, static_cast<T*>(x), static_cast<const T*>(b), tol, 0.0,
+                               maxv, st, &r);
     if (vc) *vc = r.vcycles;
     if (rel) *rel = r.rel;
     return rc;
@@ -471,7 +489,7 @@ static wl_status poisson_solve_mixed(wl_poisson* ps, const void* coeffs, void* x
     if (!P.have) return invalid("no coefficients given yet");
     SolveResult r;
     wl_status rc = mg_solve_mixed(P.h, P.mix, P.red, static_cast<double*>(x),
-                                  static_cast<const double*>(b), tol, maxv, st, &r);
+                                  static_cast<const double*>(b), tol, 0.0, maxv, st, &r);
     if (vc) *vc = r.vcycles;
     if (rel) *rel = r.rel;
     return rc;

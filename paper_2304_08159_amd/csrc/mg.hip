@@ -488,8 +488,9 @@ static Coeffs<T> coeffs_of(const Level<T>& L) {
 template <typename T, int XM, bool NORM, bool FIRST>
 static wl_status smooth(const Level<T>& L, const T* xin, const T* xc, const Grid* gc,
                         const T* b, T omega, T* xout, double* partial, T* bproj,
-                        const double* bmean, hipStream_t s) {
+                        const double* bmean, hipStream_t s, int prof = -1) {
     const Launch ln = launch_for(L.g.n0, L.g.n1, L.g.n2);
+    ProfScope ps(prof, s, cells(L.g));
     XAccess<T, XM> X{xin, xc, gc ? gc->n0 : 0, gc ? gc->n1 : 0};
     if (L.uniform)
         k_smooth<T, XM, true, NORM, FIRST><<<ln.grid, ln.block, 0, s>>>(
@@ -502,8 +503,10 @@ static wl_status smooth(const Level<T>& L, const T* xin, const T* xc, const Grid
 }
 
 template <typename T>
-static wl_status resid_restrict(const Level<T>& L, const T* x, Level<T>& C, hipStream_t s) {
+static wl_status resid_restrict(const Level<T>& L, const T* x, Level<T>& C, hipStream_t s,
+                                int prof = -1) {
     const Launch ln = launch_for(C.g.n0, C.g.n1, C.g.n2);
+    ProfScope ps(prof, s, cells(L.g));
     XAccess<T, XM_PLAIN> X{x, nullptr, 0, 0};
     if (L.uniform)
         k_resid_restrict<T, true><<<ln.grid, ln.block, 0, s>>>(L.g, C.g, X, coeffs_of(L), L.b, C.b);
@@ -577,8 +580,8 @@ static wl_status vcycle_rest(Hierarchy<T>& h, hipStream_t s) {
     const T w = T(h.omega);
     if (h.nlev == 1) return coarse_solve(h, F, F.x[0], s);
     WL_TRY((smooth<T, XM_PLAIN, false, false>(F, F.x[1], nullptr, nullptr, F.b, w, F.x[0],
-                                              nullptr, nullptr, nullptr, s)));
-    WL_TRY(resid_restrict(F, F.x[0], h.lev[1], s));
+                                              nullptr, nullptr, nullptr, s, WL_PROF_SMOOTH_FINE)));
+    WL_TRY(resid_restrict(F, F.x[0], h.lev[1], s, WL_PROF_RESTRICT_FINE));
     for (int l = 1; l < h.nlev - 1; ++l) {
         Level<T>& L = h.lev[l];
         WL_TRY((smooth<T, XM_ZERO, false, false>(L, nullptr, nullptr, nullptr, L.b, w, L.x[0],
@@ -599,9 +602,9 @@ static wl_status vcycle_rest(Hierarchy<T>& h, hipStream_t s) {
     }
     const Level<T>& C1 = h.lev[1];
     WL_TRY((smooth<T, XM_PROLONG, false, false>(F, F.x[0], C1.x[1], &C1.g, F.b, w, F.x[1], nullptr,
-                                                nullptr, nullptr, s)));
+                                                nullptr, nullptr, s, WL_PROF_PROLONG_FINE)));
     WL_TRY((smooth<T, XM_PLAIN, false, false>(F, F.x[1], nullptr, nullptr, F.b, w, F.x[0], nullptr,
-                                              nullptr, nullptr, s)));
+                                              nullptr, nullptr, s, WL_PROF_SMOOTH_FINE)));
     return WL_OK;
 }
 
@@ -629,8 +632,8 @@ static wl_status active_mean(Hierarchy<T>& h, Reduce& red, const T* b, hipStream
 }
 
 template <typename T>
-wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, int max_vcycles,
-                   hipStream_t s, SolveResult* res) {
+wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, double abs_r2,
+                   int max_vcycles, hipStream_t s, SolveResult* res) {
     Level<T>& F = h.lev[0];
     F.x[0] = x;
     const T w = T(h.omega);
@@ -656,38 +659,41 @@ wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, i
         res->rel = 0.0;
         return WL_OK;
     }
-    double rel = std::sqrt(nr[0] / b2);
+    double r2 = nr[0];
+    auto done = [&](double q) { return q <= tol * tol * b2 || q <= abs_r2; };
     int k = 0;
-    while (rel > tol && k < max_vcycles) {
+    while (!done(r2) && k < max_vcycles) {
         WL_TRY(vcycle_rest(h, s));
         ++k;
         WL_TRY((smooth<T, XM_PLAIN, true, false>(F, x, nullptr, nullptr, F.b, w, F.x[1],
-                                                 red.partial, nullptr, nullptr, s)));
+                                                 red.partial, nullptr, nullptr, s,
+                                                 WL_PROF_SMOOTH_NORM)));
         WL_TRY(reduce<T>(red, ln.nblocks(), 2, 1.0, red.result, s));
         WL_TRY(read_norms(red, nr, s));
         if (!std::isfinite(nr[0])) {
             set_error("non-finite residual norm in the pressure solve");
             return WL_ERR_NONFINITE;
         }
-        rel = std::sqrt(nr[0] / b2);
+        r2 = nr[0];
     }
     res->vcycles = k;
-    res->rel = rel;
-    if (rel > tol) {
+    res->rel = std::sqrt(r2 / b2);
+    res->r2 = r2;
+    if (!done(r2)) {
         set_error("pressure solve reached max_vcycles before the tolerance");
         return WL_ERR_NOT_CONVERGED;
     }
     return WL_OK;
 }
 
-template wl_status mg_solve<float>(Hierarchy<float>&, Reduce&, float*, const float*, double, int,
-                                   hipStream_t, SolveResult*);
+template wl_status mg_solve<float>(Hierarchy<float>&, Reduce&, float*, const float*, double,
+                                   double, int, hipStream_t, SolveResult*);
 template wl_status mg_solve<double>(Hierarchy<double>&, Reduce&, double*, const double*, double,
-                                    int, hipStream_t, SolveResult*);
+                                    double, int, hipStream_t, SolveResult*);
 
 wl_status mg_solve_mixed(Hierarchy<float>& h32, const Mixed64& m, Reduce& red, double* x,
-                         const double* b, double tol, int max_vcycles, hipStream_t s,
-                         SolveResult* res) {
+                         const double* b, double tol, double abs_r2, int max_vcycles,
+                         hipStream_t s, SolveResult* res) {
     Level<float>& F = h32.lev[0];
     const Grid g = F.g;
     const Launch ln = launch_for(g.n0, g.n1, g.n2);
@@ -702,7 +708,8 @@ wl_status mg_solve_mixed(Hierarchy<float>& h32, const Mixed64& m, Reduce& red, d
     k_mean_fix<<<1, 64, 0, s>>>(red.result + 4, red.result + 6);
     WL_CHECK_LAUNCH();
     int inner_total = 0;
-    double b2 = -1.0, rel = 0.0;
+    double b2 = -1.0, r2 = 0.0;
+    auto done = [&](double q) { return q <= tol * tol * b2 || q <= abs_r2; };
     for (;;) {
         XAccess<double, XM_PLAIN> X{x, nullptr, 0, 0};
         k_resid64<<<ln.grid, ln.block, 0, s>>>(g, X, C64, b, red.result + 5, F.b, red.partial);
@@ -725,8 +732,8 @@ wl_status mg_solve_mixed(Hierarchy<float>& h32, const Mixed64& m, Reduce& red, d
                 return WL_OK;
             }
         }
-        rel = std::sqrt(nr[0] / b2);
-        if (rel <= tol || inner_total >= max_vcycles) break;
+        r2 = nr[0];
+        if (done(r2) || inner_total >= max_vcycles) break;
         // inner FP32 V-cycles on A e = r from e = 0
         for (int v = 0; v < m.inner && inner_total < max_vcycles; ++v, ++inner_total) {
             if (v == 0)
@@ -743,8 +750,9 @@ wl_status mg_solve_mixed(Hierarchy<float>& h32, const Mixed64& m, Reduce& red, d
         WL_CHECK_LAUNCH();
     }
     res->vcycles = inner_total;
-    res->rel = rel;
-    if (rel > tol) {
+    res->rel = std::sqrt(r2 / b2);
+    res->r2 = r2;
+    if (!done(r2)) {
         set_error("mixed-precision solve reached max_vcycles before the tolerance");
         return WL_ERR_NOT_CONVERGED;
     }

@@ -447,6 +447,7 @@ wl_status ns_momentum(const VelField<T>& E, const T* const un[3], T* const f[3],
                       bool allper, const double* dt_dev, hipStream_t s) {
     const Grid& g = E.g;
     const Launch ln = launch_for(g.n0, g.n1, g.n2);
+    ProfScope ps(WL_PROF_MOMENTUM, s, cells(g));
 #define WL_MOM(AP, CR)                                                                      \
     k_momentum<T, AP, CR><<<ln.grid, ln.block, 0, s>>>(E, un[0], un[1], un[2], f[0], f[1], f[2], \
                                                         nu, dt_dev)
@@ -483,6 +484,7 @@ template <typename T>
 wl_status ns_divergence(const VelField<T>& V, double c, const double* dt_dev, T* sigma, bool allper,
                         hipStream_t s) {
     const Launch ln = launch_for(V.g.n0, V.g.n1, V.g.n2);
+    ProfScope ps(WL_PROF_DIVERGENCE, s, cells(V.g));
     if (allper)
         k_divergence<T, true><<<ln.grid, ln.block, 0, s>>>(V, c, dt_dev, sigma);
     else
@@ -496,6 +498,7 @@ wl_status ns_project(const VelField<T>& V, const T* p, const ProjCoeffs<T>& C, b
                      const double* dt_dev, T* const out[3], bool cfl, double* partial, bool allper,
                      hipStream_t s) {
     const Launch ln = launch_for(V.g.n0, V.g.n1, V.g.n2);
+    ProfScope ps(WL_PROF_PROJECT, s, cells(V.g));
 #define WL_PRJ(AP, UN, CF)                                                                      \
     k_project<T, AP, UN, CF><<<ln.grid, ln.block, 0, s>>>(V, p, C, c, dt_dev, out[0], out[1], \
                                                            out[2], partial)

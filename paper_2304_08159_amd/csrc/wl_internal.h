@@ -37,6 +37,16 @@ void clear_error();
         if (s_ != WL_OK) return s_;                                                   \
     } while (0)
 
+// ---------------------------------------------------------- kernel timing
+// Optional HIP-event brackets around selected launches (wl_profile_*).
+struct ProfScope {
+    int id;
+    hipStream_t s;
+    bool on;
+    ProfScope(int kernel, hipStream_t stream, size_t cells);
+    ~ProfScope();
+};
+
 // ------------------------------------------------------------- workspace
 // Bump allocator over the caller's device workspace.  With base == nullptr it
 // only counts, which is how the footprint calls compute exact sizes.
@@ -113,14 +123,16 @@ wl_status mg_count_active(Hierarchy<T>& h, Reduce& red, hipStream_t s);
 
 struct SolveResult {
     int vcycles = 0;
-    double rel = 0.0;
+    double rel = 0.0;     // ||r|| / ||b|| at exit
+    double r2 = 0.0;      // ||r||^2 at exit
     double bnorm = 0.0;
 };
 
 // Plain GMG solve on h (level 0 x = caller x).  b is the raw right-hand side.
+// Converged before a V-cycle when ||r||^2 <= tol^2 ||b||^2 or ||r||^2 <= abs_r2.
 template <typename T>
-wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, int max_vcycles,
-                   hipStream_t s, SolveResult* res);
+wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, double abs_r2,
+                   int max_vcycles, hipStream_t s, SolveResult* res);
 
 // Mixed precision: FP64 outer residual with FP64 fine coefficients L64,
 // FP32 inner V-cycles on h32.
@@ -129,8 +141,8 @@ struct Mixed64 {
     int inner = 3;
 };
 wl_status mg_solve_mixed(Hierarchy<float>& h32, const Mixed64& m, Reduce& red, double* x,
-                         const double* b, double tol, int max_vcycles, hipStream_t s,
-                         SolveResult* res);
+                         const double* b, double tol, double abs_r2, int max_vcycles,
+                         hipStream_t s, SolveResult* res);
 
 size_t reduce_slots_for(const Grid& g);
 

@@ -48,7 +48,7 @@ def _replay(sim, osim, nsteps, tol_u, tol_p, label):
         ep = rel_l2(mean_free(to_oracle(sim.pressure(), d), act), mean_free(osim.p, act), act)
         worst_u, worst_p = max(worst_u, eu), max(worst_p, ep)
         print(f"{label} step {step}: dt={st['dt']:.6f} vc={st['vcycles']} "
-              f"res={st['rel_resid'][0]:.2e},{st['rel_resid'][1]:.2e} err_u={eu:.2e} err_p={ep:.2e}")
+              f"div={st['resid'][0]:.2e},{st['resid'][1]:.2e} err_u={eu:.2e} err_p={ep:.2e}")
     assert worst_u <= tol_u and worst_p <= tol_p
     return worst_u, worst_p
 
