@@ -183,6 +183,22 @@ def main():
         "kernels": kern,
         "profiled_ms_per_step": 1e3 * elapsed_p / args.steps,
     }
+    # plain device copy of 512 MiB (read + write) as the practical HBM ceiling
+    src = torch.empty(128 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() * 4 * 20 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    out["copy_GBs"] = copy_gbs
+    out["roofline"]["frac_of_copy"] = kern[dom]["gbs"] / copy_gbs
+    out["step_roofline"]["frac_of_copy"] = step_gbs / copy_gbs
+    del src, dst
     if not args.no_cpu_baseline:
         vcr = [max(1, int(round(x))) for x in vc_mean]
         try:

@@ -227,7 +227,7 @@ static wl_status pressure_solve(SimImpl<T>& s, double cfac, double dt, hipStream
         }
         return invalid("mixed precision needs FP32 fields");
     }
-    return mg_solve<T>(s.h, s.red, s.p, s.sigma, 0.0, abs_r2, c.d.max_vcycles, st, r);
+    return mg_solve<T>(s.h, s.red, s.p, s.sigma, 0.0, abs_r2, c.d.max_vcycles, st, r, true);
 }
 
 template <typename T>
@@ -258,6 +258,7 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
     const T* un[3] = {s.vel[S][0], s.vel[S][1], s.vel[S][2]};
     wl_status worst = WL_OK;
     SolveResult r1, r2;
+    const ProjCoeffs<T> pc{{s.h.lev[0].L[0], s.h.lev[0].L[1], s.h.lev[0].L[2]}, T(1)};
     // ---- predictor (c = 1)
     {
         T* f[3] = {s.vel[A][0], s.vel[A][1], s.vel[A][2]};
@@ -275,11 +276,10 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
             us = B;
         }
         const VelField<T> V = field_of(s, us, s.plane[P1]);
-        WL_TRY(ns_divergence<T>(V, 1.0, dt_dev, s.sigma, ap, st));
+        WL_TRY(ns_divergence<T>(V, pc, c.unif, 1.0, dt_dev, s.sigma, s.red.partial, ap, st));
         wl_status rc = pressure_solve(s, 1.0, dt, st, &r1);
         if (rc == WL_ERR_NOT_CONVERGED) worst = rc;
         else if (rc != WL_OK) return rc;
-        ProjCoeffs<T> pc{{s.h.lev[0].L[0], s.h.lev[0].L[1], s.h.lev[0].L[2]}, T(1)};
         T* o[3] = {s.vel[us][0], s.vel[us][1], s.vel[us][2]};
         WL_TRY(ns_project<T>(V, s.p, pc, c.unif, 1.0, dt_dev, o, false, nullptr, ap, st));
         // stage result now in set `us`; the remaining set is free
@@ -302,7 +302,7 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
             us2 = S;
         }
         const VelField<T> V2 = field_of(s, us2, s.plane[P2]);
-        WL_TRY(ns_divergence<T>(V2, 0.5, dt_dev, s.sigma, ap, st));
+        WL_TRY(ns_divergence<T>(V2, pc, c.unif, 0.5, dt_dev, s.sigma, s.red.partial, ap, st));
         rc = pressure_solve(s, 0.5, dt, st, &r2);
         if (rc == WL_ERR_NOT_CONVERGED) worst = rc;
         else if (rc != WL_OK) return rc;

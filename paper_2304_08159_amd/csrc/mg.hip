@@ -10,6 +10,7 @@
 // active-set mean.
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 
 #include "wl_device.h"
 
@@ -22,13 +23,40 @@ static unsigned pow2ceil(unsigned v) {
     return p;
 }
 
+// Target block count of a tiled launch (8 per CU on 256 CUs); WL_TILE_BLOCKS
+// overrides it for tuning.
+static unsigned target_blocks() {
+    static const unsigned v = [] {
+        const char* e = std::getenv("WL_TILE_BLOCKS");
+        const long t = e ? std::atol(e) : 0;
+        return t > 0 ? unsigned(t) : 2048u;
+    }();
+    return v;
+}
+
 Launch launch_for(int n0, int n1, int n2) {
     Launch l;
     unsigned bx = pow2ceil(unsigned(n0));
     if (bx > 64) bx = 64;
+    int lbx = 0;
+    while ((1u << lbx) < bx) ++lbx;
     const unsigned by = kBlock / bx;
-    l.block = dim3(bx, by, 1);
-    l.grid = dim3((n0 + bx - 1) / bx, (n1 + by - 1) / by, n2);
+    const int tx = int((unsigned(n0) + bx - 1) / bx);
+    const int ty = int((unsigned(n1) + by - 1) / by);
+    const size_t cols = size_t(tx) * ty;
+    size_t zc = (cols * size_t(n2) + target_blocks() - 1) / target_blocks();
+    if (zc < 1) zc = 1;
+    if (zc > 64) zc = 64;
+    if (zc > size_t(n2)) zc = size_t(n2);
+    const unsigned chunks = unsigned((size_t(n2) + zc - 1) / zc);
+    l.td.lbx = lbx;
+    l.td.tx = tx;
+    l.td.ty = ty;
+    l.td.zc = int(zc);
+    l.td.nb = unsigned(cols) * chunks;
+    l.td.remap = (l.td.nb % 8u == 0u) ? 1 : 0;
+    l.block = dim3(kBlock, 1, 1);
+    l.grid = dim3(l.td.nb, 1, 1);
     return l;
 }
 
@@ -83,18 +111,18 @@ template void carve_hierarchy<double>(Carver&, Hierarchy<double>&, int, const in
 // projected copy bproj = (b - mean) on active cells, 0 elsewhere, and uses it.
 // NORM: per-block partial sums of r^2 (and of bproj^2 when FIRST) in FP64.
 template <typename T, int XM, bool UNIF, bool NORM, bool FIRST>
-__global__ __launch_bounds__(kBlock) void k_smooth(Grid g, XAccess<T, XM> X, Coeffs<T> C,
+__global__ __launch_bounds__(kBlock) void k_smooth(TileDev TL, Grid g, XAccess<T, XM> X, Coeffs<T> C,
                                                    const T* __restrict__ b, T omega,
                                                    T* __restrict__ xout,
                                                    double* __restrict__ partial,
                                                    T* __restrict__ bproj,
                                                    const double* __restrict__ bmean) {
     __shared__ double lds[8];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
+    const Span sp = tile_span(TL, g.n0, g.n1, g.n2);
+    const int i = sp.i, j = sp.j;
     double r2 = 0.0, b2 = 0.0;
     if (i < g.n0 && j < g.n1) {
+        for (int k = sp.z0; k < sp.z1; ++k) {
         const size_t id = cid(g, i, j, k);
         T xI, Ax, D;
         apply_row<T, XM, UNIF>(g, X, C, i, j, k, xI, Ax, D);
@@ -106,15 +134,15 @@ __global__ __launch_bounds__(kBlock) void k_smooth(Grid g, XAccess<T, XM> X, Coe
         const T r = bv - Ax;
         xout[id] = (D > T(0)) ? xI - omega * r / D : T(0);
         if (NORM) {
-            r2 = double(r) * double(r);
-            if (FIRST) b2 = double(bv) * double(bv);
+            r2 += double(r) * double(r);
+            if (FIRST) b2 += double(bv) * double(bv);
+        }
         }
     }
     if (NORM) {
-        const double s = block_sum(r2, lds);
-        __syncthreads();
-        const double sb = FIRST ? block_sum(b2, lds + 4) : 0.0;
-        if (threadIdx.x == 0 && threadIdx.y == 0) {
+        double s, sb;
+        block_sum2(r2, b2, lds, s, sb);
+        if (threadIdx.x == 0) {
             partial[2 * block_linear()] = s;
             partial[2 * block_linear() + 1] = sb;
         }
@@ -123,13 +151,13 @@ __global__ __launch_bounds__(kBlock) void k_smooth(Grid g, XAccess<T, XM> X, Coe
 
 // Coarse right-hand side = sum of the 2^d child residuals r = b - A x.
 template <typename T, bool UNIF>
-__global__ __launch_bounds__(kBlock) void k_resid_restrict(Grid g, Grid gc, XAccess<T, XM_PLAIN> X,
+__global__ __launch_bounds__(kBlock) void k_resid_restrict(TileDev TL, Grid g, Grid gc, XAccess<T, XM_PLAIN> X,
                                                            Coeffs<T> C, const T* __restrict__ b,
                                                            T* __restrict__ bc) {
-    const int ic = blockIdx.x * blockDim.x + threadIdx.x;
-    const int jc = blockIdx.y * blockDim.y + threadIdx.y;
-    const int kc = blockIdx.z;
+    const Span sp = tile_span(TL, gc.n0, gc.n1, gc.n2);
+    const int ic = sp.i, jc = sp.j;
     if (ic >= gc.n0 || jc >= gc.n1) return;
+    for (int kc = sp.z0; kc < sp.z1; ++kc) {
     const int fz = (g.n2 > gc.n2) ? 2 : 1;
     T sum = T(0);
     for (int dz = 0; dz < fz; ++dz)
@@ -141,22 +169,24 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(Grid g, Grid gc, XAcc
                 sum += b[cid(g, i, j, k)] - Ax;
             }
     bc[cid(gc, ic, jc, kc)] = sum;
+    }
 }
 
 // Per-block partial sums of v over active cells (v == nullptr counts them).
 template <typename T, bool UNIF>
-__global__ __launch_bounds__(kBlock) void k_sum_active(Grid g, Coeffs<T> C, const T* __restrict__ v,
+__global__ __launch_bounds__(kBlock) void k_sum_active(TileDev TL, Grid g, Coeffs<T> C, const T* __restrict__ v,
                                                        double* __restrict__ partial) {
     __shared__ double lds[8];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
+    const Span sp = tile_span(TL, g.n0, g.n1, g.n2);
+    const int i = sp.i, j = sp.j;
     double s = 0.0;
     if (i < g.n0 && j < g.n1) {
+        for (int k = sp.z0; k < sp.z1; ++k) {
         XAccess<T, XM_ZERO> X{nullptr, nullptr, 0, 0};
         T xI, Ax, D;
         apply_row<T, XM_ZERO, UNIF>(g, X, C, i, j, k, xI, Ax, D);
-        if (D > T(0)) s = v ? double(v[cid(g, i, j, k)]) : 1.0;
+        if (D > T(0)) s += v ? double(v[cid(g, i, j, k)]) : 1.0;
+        }
     }
     s = block_sum(s, lds);
     if (threadIdx.x == 0 && threadIdx.y == 0) partial[block_linear()] = s;
@@ -324,14 +354,14 @@ __global__ __launch_bounds__(256) void k_coarse_cg(Grid g, Coeffs<T> C, int unif
 
 // Coarse coefficient = 1/2 * sum of the fine faces the coarse face covers.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_coarsen(Grid gf, Grid gc, const T* __restrict__ f0,
+__global__ __launch_bounds__(kBlock) void k_coarsen(TileDev TL, Grid gf, Grid gc, const T* __restrict__ f0,
                                                     const T* __restrict__ f1,
                                                     const T* __restrict__ f2, T* __restrict__ c0,
                                                     T* __restrict__ c1, T* __restrict__ c2) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
+    const Span sp = tile_span(TL, gc.n0, gc.n1, gc.n2);
+    const int i = sp.i, j = sp.j;
     if (i >= gc.n0 || j >= gc.n1) return;
+    for (int k = sp.z0; k < sp.z1; ++k) {
     const int fz = (gf.n2 > gc.n2) ? 2 : 1;
     const int I = 2 * i, J = 2 * j, K = fz * k;
     T s0 = T(0), s1 = T(0), s2 = T(0);
@@ -346,6 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_coarsen(Grid gf, Grid gc, const T* _
     c0[id] = T(0.5) * s0;
     c1[id] = T(0.5) * s1;
     c2[id] = T(0.5) * s2;
+    }
 }
 
 template <typename T>
@@ -363,30 +394,30 @@ __global__ __launch_bounds__(kBlock) void k_axpy64(size_t n, const float* __rest
 
 // FP64 defect r = (b - mean)|active - A64 x, rounded to FP32 for the inner
 // solve; partial sums of r^2 and of the projected b^2.
-__global__ __launch_bounds__(kBlock) void k_resid64(Grid g, XAccess<double, XM_PLAIN> X,
+__global__ __launch_bounds__(kBlock) void k_resid64(TileDev TL, Grid g, XAccess<double, XM_PLAIN> X,
                                                     Coeffs<double> C, const double* __restrict__ b,
                                                     const double* __restrict__ bmean,
                                                     float* __restrict__ r32,
                                                     double* __restrict__ partial) {
     __shared__ double lds[8];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
+    const Span sp = tile_span(TL, g.n0, g.n1, g.n2);
+    const int i = sp.i, j = sp.j;
     double r2 = 0.0, b2 = 0.0;
     if (i < g.n0 && j < g.n1) {
+        for (int k = sp.z0; k < sp.z1; ++k) {
         const size_t id = cid(g, i, j, k);
         double xI, Ax, D;
         apply_row<double, XM_PLAIN, false>(g, X, C, i, j, k, xI, Ax, D);
         const double bv = (D > 0.0) ? b[id] - *bmean : 0.0;
         const double r = bv - Ax;
         r32[id] = float(r);
-        r2 = r * r;
-        b2 = bv * bv;
+        r2 += r * r;
+        b2 += bv * bv;
+        }
     }
-    const double s = block_sum(r2, lds);
-    __syncthreads();
-    const double sb = block_sum(b2, lds + 4);
-    if (threadIdx.x == 0 && threadIdx.y == 0) {
+    double s, sb;
+    block_sum2(r2, b2, lds, s, sb);
+    if (threadIdx.x == 0) {
         partial[2 * block_linear()] = s;
         partial[2 * block_linear() + 1] = sb;
     }
@@ -396,14 +427,14 @@ __global__ __launch_bounds__(kBlock) void k_resid64(Grid g, XAccess<double, XM_P
 // forcing zero on non-periodic lower boundary faces and on the z faces in 2D;
 // optionally keep an FP64 copy.
 template <typename Tin, typename Tout>
-__global__ __launch_bounds__(kBlock) void k_load_coeffs(Grid g, const Tin* __restrict__ src,
+__global__ __launch_bounds__(kBlock) void k_load_coeffs(TileDev TL, Grid g, const Tin* __restrict__ src,
                                                         Tout* __restrict__ L0, Tout* __restrict__ L1,
                                                         Tout* __restrict__ L2, double* M0,
                                                         double* M1, double* M2) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
+    const Span sp = tile_span(TL, g.n0, g.n1, g.n2);
+    const int i = sp.i, j = sp.j;
     if (i >= g.n0 || j >= g.n1) return;
+    for (int k = sp.z0; k < sp.z1; ++k) {
     const size_t id = cid(g, i, j, k);
     const size_t N = cells(g);
     const int coord[3] = {i, j, k};
@@ -416,13 +447,14 @@ __global__ __launch_bounds__(kBlock) void k_load_coeffs(Grid g, const Tin* __res
         dst[d][id] = Tout(v);
         if (d64[d]) d64[d][id] = v;
     }
+    }
 }
 
 template <typename Tin, typename Tout>
 wl_status mg_load_coeffs(const Grid& g, const Tin* src, Tout* const L[3], double* const L64[3],
                          hipStream_t s) {
     const Launch ln = launch_for(g.n0, g.n1, g.n2);
-    k_load_coeffs<Tin, Tout><<<ln.grid, ln.block, 0, s>>>(g, src, L[0], L[1], L[2],
+    k_load_coeffs<Tin, Tout><<<ln.grid, ln.block, 0, s>>>(ln.td, g, src, L[0], L[1], L[2],
                                                           L64 ? L64[0] : nullptr,
                                                           L64 ? L64[1] : nullptr,
                                                           L64 ? L64[2] : nullptr);
@@ -467,7 +499,7 @@ wl_status mg_count_active64(const Grid& g, double* const L64[3], Reduce& red, si
                             hipStream_t s) {
     const Launch ln = launch_for(g.n0, g.n1, g.n2);
     Coeffs<double> C{L64[0], L64[1], L64[2], 1.0};
-    k_sum_active<double, false><<<ln.grid, ln.block, 0, s>>>(g, C, nullptr, red.partial);
+    k_sum_active<double, false><<<ln.grid, ln.block, 0, s>>>(ln.td, g, C, nullptr, red.partial);
     WL_CHECK_LAUNCH();
     k_reduce<<<1, 1024, 0, s>>>(red.partial, ln.nblocks(), 1, 1.0, red.result + 6);
     WL_CHECK_LAUNCH();
@@ -493,10 +525,10 @@ static wl_status smooth(const Level<T>& L, const T* xin, const T* xc, const Grid
     ProfScope ps(prof, s, cells(L.g));
     XAccess<T, XM> X{xin, xc, gc ? gc->n0 : 0, gc ? gc->n1 : 0};
     if (L.uniform)
-        k_smooth<T, XM, true, NORM, FIRST><<<ln.grid, ln.block, 0, s>>>(
+        k_smooth<T, XM, true, NORM, FIRST><<<ln.grid, ln.block, 0, s>>>(ln.td, 
             L.g, X, coeffs_of(L), b, omega, xout, partial, bproj, bmean);
     else
-        k_smooth<T, XM, false, NORM, FIRST><<<ln.grid, ln.block, 0, s>>>(
+        k_smooth<T, XM, false, NORM, FIRST><<<ln.grid, ln.block, 0, s>>>(ln.td, 
             L.g, X, coeffs_of(L), b, omega, xout, partial, bproj, bmean);
     WL_CHECK_LAUNCH();
     return WL_OK;
@@ -509,9 +541,9 @@ static wl_status resid_restrict(const Level<T>& L, const T* x, Level<T>& C, hipS
     ProfScope ps(prof, s, cells(L.g));
     XAccess<T, XM_PLAIN> X{x, nullptr, 0, 0};
     if (L.uniform)
-        k_resid_restrict<T, true><<<ln.grid, ln.block, 0, s>>>(L.g, C.g, X, coeffs_of(L), L.b, C.b);
+        k_resid_restrict<T, true><<<ln.grid, ln.block, 0, s>>>(ln.td, L.g, C.g, X, coeffs_of(L), L.b, C.b);
     else
-        k_resid_restrict<T, false><<<ln.grid, ln.block, 0, s>>>(L.g, C.g, X, coeffs_of(L), L.b, C.b);
+        k_resid_restrict<T, false><<<ln.grid, ln.block, 0, s>>>(ln.td, L.g, C.g, X, coeffs_of(L), L.b, C.b);
     WL_CHECK_LAUNCH();
     return WL_OK;
 }
@@ -539,7 +571,7 @@ wl_status mg_coarsen_all(Hierarchy<T>& h, hipStream_t s) {
         Level<T>& F = h.lev[l - 1];
         Level<T>& C = h.lev[l];
         const Launch ln = launch_for(C.g.n0, C.g.n1, C.g.n2);
-        k_coarsen<T><<<ln.grid, ln.block, 0, s>>>(F.g, C.g, F.L[0], F.L[1], F.L[2], C.L[0],
+        k_coarsen<T><<<ln.grid, ln.block, 0, s>>>(ln.td, F.g, C.g, F.L[0], F.L[1], F.L[2], C.L[0],
                                                   C.L[1], C.L[2]);
         WL_CHECK_LAUNCH();
         C.uniform = F.uniform;
@@ -553,9 +585,9 @@ wl_status mg_count_active(Hierarchy<T>& h, Reduce& red, hipStream_t s) {
     const Level<T>& F = h.lev[0];
     const Launch ln = launch_for(F.g.n0, F.g.n1, F.g.n2);
     if (F.uniform)
-        k_sum_active<T, true><<<ln.grid, ln.block, 0, s>>>(F.g, coeffs_of(F), nullptr, red.partial);
+        k_sum_active<T, true><<<ln.grid, ln.block, 0, s>>>(ln.td, F.g, coeffs_of(F), nullptr, red.partial);
     else
-        k_sum_active<T, false><<<ln.grid, ln.block, 0, s>>>(F.g, coeffs_of(F), nullptr, red.partial);
+        k_sum_active<T, false><<<ln.grid, ln.block, 0, s>>>(ln.td, F.g, coeffs_of(F), nullptr, red.partial);
     WL_CHECK_LAUNCH();
     // result[6] = active count (kept on the device for the mean kernels)
     k_reduce<<<1, 1024, 0, s>>>(red.partial, ln.nblocks(), 1, 1.0, red.result + 6);
@@ -615,13 +647,16 @@ static wl_status read_norms(Reduce& red, double* host2, hipStream_t s) {
 }
 
 template <typename T>
-static wl_status active_mean(Hierarchy<T>& h, Reduce& red, const T* b, hipStream_t s) {
+static wl_status active_mean(Hierarchy<T>& h, Reduce& red, const T* b, bool have_partials,
+                             hipStream_t s) {
     const Level<T>& F = h.lev[0];
     const Launch ln = launch_for(F.g.n0, F.g.n1, F.g.n2);
-    if (F.uniform)
-        k_sum_active<T, true><<<ln.grid, ln.block, 0, s>>>(F.g, coeffs_of(F), b, red.partial);
+    if (have_partials) {
+        // the producer of b left its per-block active sums in red.partial
+    } else if (F.uniform)
+        k_sum_active<T, true><<<ln.grid, ln.block, 0, s>>>(ln.td, F.g, coeffs_of(F), b, red.partial);
     else
-        k_sum_active<T, false><<<ln.grid, ln.block, 0, s>>>(F.g, coeffs_of(F), b, red.partial);
+        k_sum_active<T, false><<<ln.grid, ln.block, 0, s>>>(ln.td, F.g, coeffs_of(F), b, red.partial);
     WL_CHECK_LAUNCH();
     // result[4] = sum, result[5] = mean
     k_reduce<<<1, 1024, 0, s>>>(red.partial, ln.nblocks(), 1, 1.0, red.result + 4);
@@ -633,12 +668,12 @@ static wl_status active_mean(Hierarchy<T>& h, Reduce& red, const T* b, hipStream
 
 template <typename T>
 wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, double abs_r2,
-                   int max_vcycles, hipStream_t s, SolveResult* res) {
+                   int max_vcycles, hipStream_t s, SolveResult* res, bool b_partials) {
     Level<T>& F = h.lev[0];
     F.x[0] = x;
     const T w = T(h.omega);
     const Launch ln = launch_for(F.g.n0, F.g.n1, F.g.n2);
-    WL_TRY(active_mean(h, red, b, s));
+    WL_TRY(active_mean(h, red, b, b_partials, s));
     // first fine sweep: projects b, measures ||r0|| and ||b||
     WL_TRY((smooth<T, XM_PLAIN, true, true>(F, x, nullptr, nullptr, b, w, F.x[1], red.partial, F.b,
                                             red.result + 5, s)));
@@ -687,9 +722,9 @@ wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, d
 }
 
 template wl_status mg_solve<float>(Hierarchy<float>&, Reduce&, float*, const float*, double,
-                                   double, int, hipStream_t, SolveResult*);
+                                   double, int, hipStream_t, SolveResult*, bool);
 template wl_status mg_solve<double>(Hierarchy<double>&, Reduce&, double*, const double*, double,
-                                    double, int, hipStream_t, SolveResult*);
+                                    double, int, hipStream_t, SolveResult*, bool);
 
 wl_status mg_solve_mixed(Hierarchy<float>& h32, const Mixed64& m, Reduce& red, double* x,
                          const double* b, double tol, double abs_r2, int max_vcycles,
@@ -701,7 +736,7 @@ wl_status mg_solve_mixed(Hierarchy<float>& h32, const Mixed64& m, Reduce& red, d
     const float w = float(h32.omega);
     Coeffs<double> C64{m.L[0], m.L[1], m.L[2], 1.0};
     // active mean of b in FP64 (result[5])
-    k_sum_active<double, false><<<ln.grid, ln.block, 0, s>>>(g, C64, b, red.partial);
+    k_sum_active<double, false><<<ln.grid, ln.block, 0, s>>>(ln.td, g, C64, b, red.partial);
     WL_CHECK_LAUNCH();
     k_reduce<<<1, 1024, 0, s>>>(red.partial, ln.nblocks(), 1, 1.0, red.result + 4);
     WL_CHECK_LAUNCH();
@@ -712,7 +747,7 @@ wl_status mg_solve_mixed(Hierarchy<float>& h32, const Mixed64& m, Reduce& red, d
     auto done = [&](double q) { return q <= tol * tol * b2 || q <= abs_r2; };
     for (;;) {
         XAccess<double, XM_PLAIN> X{x, nullptr, 0, 0};
-        k_resid64<<<ln.grid, ln.block, 0, s>>>(g, X, C64, b, red.result + 5, F.b, red.partial);
+        k_resid64<<<ln.grid, ln.block, 0, s>>>(ln.td, g, X, C64, b, red.result + 5, F.b, red.partial);
         WL_CHECK_LAUNCH();
         WL_TRY(reduce<double>(red, ln.nblocks(), 2, 1.0, red.result, s));
         double nr[2];

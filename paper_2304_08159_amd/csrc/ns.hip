@@ -12,6 +12,7 @@
 // BDIM kernel of half-width eps, Heun stages with projection factor c = 1 and
 // c = 1/2, CFL from the per-cell outflow velocity plus 2 d nu.
 #include <cmath>
+#include <cstdlib>
 
 #include "wl_device.h"
 #include "wl_ns.h"
@@ -113,17 +114,17 @@ __device__ __forceinline__ T face_flux(const VelField<T>& V, int c, int d, int i
 // with R_c = -sum_d [F_cd(I + delta_d) - F_cd(I)].  Domain-boundary faces take
 // their boundary value (U_c at an inflow, 0 at a wall).
 template <typename T, bool ALLPER, bool CORR>
-__global__ __launch_bounds__(kBlock) void k_momentum(VelField<T> E, const T* __restrict__ un0,
+__global__ __launch_bounds__(kBlock) void k_momentum(TileDev TL, VelField<T> E, const T* __restrict__ un0,
                                                      const T* __restrict__ un1,
                                                      const T* __restrict__ un2,
                                                      T* __restrict__ f0, T* __restrict__ f1,
                                                      T* __restrict__ f2, T nu,
                                                      const double* __restrict__ dt_dev) {
     const Grid& g = E.g;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
+    const Span sp = tile_span(TL, g.n0, g.n1, g.n2);
+    const int i = sp.i, j = sp.j;
     if (i >= g.n0 || j >= g.n1) return;
+    for (int k = sp.z0; k < sp.z1; ++k) {
     const size_t id = cid(g, i, j, k);
     const T dt = T(*dt_dev);
     const int coord[3] = {i, j, k};
@@ -143,6 +144,202 @@ __global__ __launch_bounds__(kBlock) void k_momentum(VelField<T> E, const T* __r
         }
         const T ue = E.u[c][id];
         fo[c][id] = CORR ? T(0.5) * (un[c][id] + ue + dt * R) : ue + dt * R;
+    }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// LDS-tiled convection-diffusion for FP32 3D grids.  A block owns a 64 x 4
+// column of cells and marches through a chunk of z planes.  Planes z-2..z+2
+// of all three components (with a two-cell x/y halo) sit in an LDS ring; the
+// next plane is fetched into registers while the current one is computed.
+// Every face flux is evaluated once: x- and y-face fluxes of the plane go
+// through LDS, the z-face flux of the upper face is kept in a register and
+// reused as the lower face of the next plane.  Block ids are remapped so that
+// each XCD (blocks are dealt round-robin to the 8 XCDs) walks a contiguous
+// range of tiles and shares halo rows through its own L2.
+namespace {
+constexpr int MT_X = 64, MT_Y = 4;
+constexpr int MT_LX = MT_X + 4, MT_LY = MT_Y + 4, MT_PL = MT_LX * MT_LY;
+constexpr int MT_NP = 5;
+constexpr int MT_LOADS = (MT_PL + kBlock - 1) / kBlock;
+}  // namespace
+
+__device__ __forceinline__ int wrapi(int a, int n) {
+    int r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+template <bool ALLPER>
+__device__ __forceinline__ float tile_fetch(const VelField<float>& V, int c, int gx, int gy, int gz) {
+    if (ALLPER) {
+        const Grid& g = V.g;
+        return V.u[c][cid(g, wrapi(gx, g.n0), wrapi(gy, g.n1), wrapi(gz, g.n2))];
+    }
+    return vget<float, false>(V, c, gx, gy, gz);
+}
+
+__device__ __forceinline__ float flux1(float um2, float um1, float u0, float up1, float ubar,
+                                       float nu) {
+    const bool pos = ubar >= 0.f;
+    const float cu = pos ? um1 : u0;
+    const float bd = pos ? u0 : um1;
+    const float au = pos ? um2 : up1;
+    const float phik = (5.f * cu + 2.f * bd - au) * (1.f / 6.f);
+    const float phi = med3(phik, cu, med3(2.f * cu - au, cu, bd));
+    return ubar * phi - nu * (u0 - um1);
+}
+
+template <bool ALLPER, bool CORR>
+__global__ __launch_bounds__(kBlock) void k_momentum_tiled(VelField<float> E,
+                                                           const float* __restrict__ un0,
+                                                           const float* __restrict__ un1,
+                                                           const float* __restrict__ un2,
+                                                           float* __restrict__ f0,
+                                                           float* __restrict__ f1,
+                                                           float* __restrict__ f2, float nu,
+                                                           const double* __restrict__ dt_dev,
+                                                           TileMap tm) {
+    __shared__ float sU[3][MT_NP][MT_PL];
+    __shared__ float sFx[3][MT_Y][MT_X + 1];
+    __shared__ float sFy[3][MT_Y + 1][MT_X];
+    const Grid& g = E.g;
+    unsigned b = blockIdx.x;
+    if (tm.remap) b = (b & 7u) * (tm.nblocks >> 3) + (b >> 3);
+    const int tix = int(b % unsigned(tm.tiles_x));
+    b /= unsigned(tm.tiles_x);
+    const int tiy = int(b % unsigned(tm.tiles_y));
+    const int ch = int(b / unsigned(tm.tiles_y));
+    const int x0 = tix * MT_X, y0 = tiy * MT_Y, z0 = ch * tm.zc;
+    const int z1 = min(z0 + tm.zc, g.n2);
+    const int t = threadIdx.x, tx = t & 63, ty = t >> 6;
+    const int lx = tx + 2, ly = ty + 2;
+    const float dt = float(*dt_dev);
+    const int gx = x0 + tx, gy = y0 + ty;
+    const bool inside = gx < g.n0 && gy < g.n1;
+    const float* un[3] = {un0, un1, un2};
+    float* fo[3] = {f0, f1, f2};
+    auto slot = [](int z) { return wrapi(z, MT_NP); };
+    auto U = [&](int c, int sl, int x, int y) -> float { return sU[c][sl][y * MT_LX + x]; };
+    // halo positions of this thread's loads; with periodic wrap their x/y
+    // offsets are fixed for the whole column, so they are computed once
+    unsigned offxy[MT_LOADS];
+    int pxs[MT_LOADS], pys[MT_LOADS];
+#pragma unroll
+    for (int k = 0; k < MT_LOADS; ++k) {
+        const int p = t + k * kBlock;
+        pxs[k] = x0 - 2 + p % MT_LX;
+        pys[k] = y0 - 2 + p / MT_LX;
+        offxy[k] = ALLPER ? unsigned(wrapi(pxs[k], g.n0)) + unsigned(g.n0) * unsigned(wrapi(pys[k], g.n1))
+                          : 0u;
+    }
+    const unsigned plane = unsigned(g.n0) * unsigned(g.n1);
+    auto fetch = [&](int zz, float (&r)[3][MT_LOADS]) {
+        if (ALLPER) {
+            const int gz = zz < 0 ? zz + g.n2 : (zz >= g.n2 ? zz - g.n2 : zz);
+            const unsigned base = unsigned(gz) * plane;
+#pragma unroll
+            for (int k = 0; k < MT_LOADS; ++k)
+                if (t + k * kBlock < MT_PL)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) r[c][k] = E.u[c][base + offxy[k]];
+        } else {
+#pragma unroll
+            for (int k = 0; k < MT_LOADS; ++k)
+                if (t + k * kBlock < MT_PL)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) r[c][k] = tile_fetch<false>(E, c, pxs[k], pys[k], zz);
+        }
+    };
+    auto store = [&](int zz, const float (&r)[3][MT_LOADS]) {
+        const int sl = slot(zz);
+#pragma unroll
+        for (int k = 0; k < MT_LOADS; ++k) {
+            const int p = t + k * kBlock;
+            if (p < MT_PL)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) sU[c][sl][p] = r[c][k];
+        }
+    };
+    {
+        float r[3][MT_LOADS];
+        for (int zz = z0 - 2; zz <= z0 + 2; ++zz) {
+            fetch(zz, r);
+            store(zz, r);
+        }
+    }
+    __syncthreads();
+    float Fzlo[3];
+    {
+        const int s0 = slot(z0), sm1 = slot(z0 - 1), sm2 = slot(z0 - 2), sp1 = slot(z0 + 1);
+        const float w0 = U(2, s0, lx, ly);
+        const float wb[3] = {U(2, s0, lx - 1, ly), U(2, s0, lx, ly - 1), U(2, sm1, lx, ly)};
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            Fzlo[c] = flux1(U(c, sm2, lx, ly), U(c, sm1, lx, ly), U(c, s0, lx, ly),
+                            U(c, sp1, lx, ly), 0.5f * (w0 + wb[c]), nu);
+    }
+    for (int z = z0; z < z1; ++z) {
+        const int s0 = slot(z), sm1 = slot(z - 1), sp1 = slot(z + 1), sp2 = slot(z + 2);
+        float pre[3][MT_LOADS];
+        const bool more = z + 1 < z1;
+        if (more) fetch(z + 3, pre);
+        // x faces of the plane: 65 per row
+        for (int f = t; f < (MT_X + 1) * MT_Y; f += kBlock) {
+            const int row = f / (MT_X + 1), col = f - row * (MT_X + 1);
+            const int X = col + 2, Y = row + 2;
+            const float a0 = U(0, s0, X, Y);
+            const float ab[3] = {U(0, s0, X - 1, Y), U(0, s0, X, Y - 1), U(0, sm1, X, Y)};
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                sFx[c][row][col] = flux1(U(c, s0, X - 2, Y), U(c, s0, X - 1, Y), U(c, s0, X, Y),
+                                         U(c, s0, X + 1, Y), 0.5f * (a0 + ab[c]), nu);
+        }
+        // y faces of the plane: 5 rows of 64
+        for (int f = t; f < MT_X * (MT_Y + 1); f += kBlock) {
+            const int row = f / MT_X, col = f - row * MT_X;
+            const int X = col + 2, Y = row + 2;
+            const float a0 = U(1, s0, X, Y);
+            const float ab[3] = {U(1, s0, X - 1, Y), U(1, s0, X, Y - 1), U(1, sm1, X, Y)};
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                sFy[c][row][col] = flux1(U(c, s0, X, Y - 2), U(c, s0, X, Y - 1), U(c, s0, X, Y),
+                                         U(c, s0, X, Y + 1), 0.5f * (a0 + ab[c]), nu);
+        }
+        // upper z face of the thread's cell
+        float Fzhi[3];
+        {
+            const float w0 = U(2, sp1, lx, ly);
+            const float wb[3] = {U(2, sp1, lx - 1, ly), U(2, sp1, lx, ly - 1), U(2, s0, lx, ly)};
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                Fzhi[c] = flux1(U(c, sm1, lx, ly), U(c, s0, lx, ly), U(c, sp1, lx, ly),
+                                U(c, sp2, lx, ly), 0.5f * (w0 + wb[c]), nu);
+        }
+        __syncthreads();
+        if (inside) {
+            const unsigned id = unsigned(gx) + unsigned(g.n0) * unsigned(gy) + plane * unsigned(z);
+            const int coord[3] = {gx, gy, z};
+            const int per[3] = {g.per0, g.per1, g.per2};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                float v;
+                if (!ALLPER && !per[c] && coord[c] == 0) {
+                    v = (E.bclo[c] == WL_BC_INFLOW) ? E.U[c] : 0.f;
+                } else {
+                    float R = -(sFx[c][ty][tx + 1] - sFx[c][ty][tx]);
+                    R -= sFy[c][ty + 1][tx] - sFy[c][ty][tx];
+                    R -= Fzhi[c] - Fzlo[c];
+                    const float ue = U(c, s0, lx, ly);
+                    v = CORR ? 0.5f * (un[c][id] + ue + dt * R) : ue + dt * R;
+                }
+                fo[c][id] = v;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Fzlo[c] = Fzhi[c];
+        if (more) store(z + 3, pre);
+        __syncthreads();
     }
 }
 
@@ -188,14 +385,14 @@ __global__ __launch_bounds__(1024) void k_outflow(Grid g, const T* __restrict__ 
 // First-order BDIM blend (body at rest) on interior faces:
 //   u*_c = mu0_c f_c + sum_d (mu1 n)_cd (f_c(I+delta_d) - f_c(I-delta_d)) / 2.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_bdim(VelField<T> F, BdimFields<T> B,
+__global__ __launch_bounds__(kBlock) void k_bdim(TileDev TL, VelField<T> F, BdimFields<T> B,
                                                  T* __restrict__ o0, T* __restrict__ o1,
                                                  T* __restrict__ o2) {
     const Grid& g = F.g;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
+    const Span sp = tile_span(TL, g.n0, g.n1, g.n2);
+    const int i = sp.i, j = sp.j;
     if (i >= g.n0 || j >= g.n1) return;
+    for (int k = sp.z0; k < sp.z1; ++k) {
     const size_t id = cid(g, i, j, k);
     const int coord[3] = {i, j, k};
     const int per[3] = {g.per0, g.per1, g.per2};
@@ -217,107 +414,131 @@ __global__ __launch_bounds__(kBlock) void k_bdim(VelField<T> F, BdimFields<T> B,
         }
         out[c][id] = v;
     }
+    }
 }
 
-// sigma = div(u*) / (c dt).
-template <typename T, bool ALLPER>
-__global__ __launch_bounds__(kBlock) void k_divergence(VelField<T> V, double c,
-                                                       const double* __restrict__ dt_dev,
-                                                       T* __restrict__ sigma) {
+// sigma = div(u*) / (c dt), plus per-block partial sums of sigma over the
+// active cells (D != 0; every cell when the coefficients are uniform) for the
+// mean removal of the pressure solve.
+template <typename T, bool ALLPER, bool UNIF>
+__global__ __launch_bounds__(kBlock) void k_divergence(TileDev TL, VelField<T> V, ProjCoeffs<T> C,
+                                                       double c, const double* __restrict__ dt_dev,
+                                                       T* __restrict__ sigma,
+                                                       double* __restrict__ partial) {
+    __shared__ double lds[8];
     const Grid& g = V.g;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= g.n0 || j >= g.n1) return;
-    const size_t id = cid(g, i, j, k);
-    T div = T(0);
-    for (int d = 0; d < g.ndim; ++d)
-        div += vget<T, ALLPER>(V, d, i + (d == 0), j + (d == 1), k + (d == 2)) - V.u[d][id];
-    sigma[id] = div * T(1.0 / (c * *dt_dev));
-}
-
-// Projected face value u*_d(J) - c dt L_d(J) (p(J) - p(J - delta_d)) for an
-// in-grid face J (coordinates already wrapped).
-template <typename T, bool UNIF>
-__device__ __forceinline__ T projected(const VelField<T>& V, const T* __restrict__ p,
-                                       const ProjCoeffs<T>& C, int d, int i, int j, int k, T coef) {
-    const Grid& g = V.g;
-    const size_t id = cid(g, i, j, k);
-    const int per = d == 0 ? g.per0 : (d == 1 ? g.per1 : g.per2);
-    const int n = d == 0 ? g.n0 : (d == 1 ? g.n1 : g.n2);
-    const int c = d == 0 ? i : (d == 1 ? j : k);
-    const T L = UNIF ? C.Lc : C.L[d][id];
-    if (!UNIF && !per && c == 0) return V.u[d][id];  // boundary face: L = 0
-    const int cl = c > 0 ? c - 1 : n - 1;
-    const int il = d == 0 ? cl : i, jl = d == 1 ? cl : j, kl = d == 2 ? cl : k;
-    return V.u[d][id] - coef * L * (p[id] - p[cid(g, il, jl, kl)]);
+    const Span sp = tile_span(TL, g.n0, g.n1, g.n2);
+    const int i = sp.i, j = sp.j;
+    const T scale = T(1.0 / (c * *dt_dev));
+    double sum = 0.0;
+    if (i < g.n0 && j < g.n1) {
+        for (int k = sp.z0; k < sp.z1; ++k) {
+            const size_t id = cid(g, i, j, k);
+            T div = T(0);
+            for (int d = 0; d < g.ndim; ++d)
+                div += vget<T, ALLPER>(V, d, i + (d == 0), j + (d == 1), k + (d == 2)) - V.u[d][id];
+            const T sg = div * scale;
+            sigma[id] = sg;
+            bool active = true;
+            if (!UNIF) {
+                T D = T(0);
+                const int n[3] = {g.n0, g.n1, g.n2};
+                const int per[3] = {g.per0, g.per1, g.per2};
+                const int q[3] = {i, j, k};
+                for (int d = 0; d < g.ndim; ++d) {
+                    D += C.L[d][id];
+                    if (q[d] + 1 < n[d] || per[d]) {
+                        int r[3] = {i, j, k};
+                        r[d] = q[d] + 1 < n[d] ? q[d] + 1 : 0;
+                        D += C.L[d][cid(g, r[0], r[1], r[2])];
+                    }
+                }
+                active = D > T(0);
+            }
+            if (active) sum += double(sg);
+        }
+    }
+    const double bs = block_sum(sum, lds);
+    if (threadIdx.x == 0) partial[block_linear()] = bs;
 }
 
 // u = u* - c dt L grad(p) for every direction in one pass (the gradient loop
-// of Sec. 2 with coeff = c dt L, fused over directions); optionally the
-// per-block CFL maximum of sum_d max(u_d(I+delta_d),0) - min(u_d(I),0) of the
-// projected field (upper neighbours recomputed, so the output can alias
-// nothing that is read).
+// of Sec. 2 with coeff = c dt L, fused over directions).  With CFL, also the
+// per-block maximum of sum_d max(u_d(I+delta_d),0) - min(u_d(I),0) of the
+// projected field; the upper neighbour faces are recomputed from u* and p, so
+// the output must not alias u*.
 template <typename T, bool ALLPER, bool UNIF, bool CFL>
-__global__ __launch_bounds__(kBlock) void k_project(VelField<T> V, const T* __restrict__ p,
+__global__ __launch_bounds__(kBlock) void k_project(TileDev TL, VelField<T> V, const T* __restrict__ p,
                                                     ProjCoeffs<T> C, double c,
                                                     const double* __restrict__ dt_dev,
                                                     T* o0, T* o1, T* o2,
                                                     double* __restrict__ partial) {
     __shared__ double lds[8];
     const Grid& g = V.g;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
+    const Span sp = tile_span(TL, g.n0, g.n1, g.n2);
+    const int i = sp.i, j = sp.j;
     const T coef = T(c * *dt_dev);
     T* out[3] = {o0, o1, o2};
+    const int n[3] = {g.n0, g.n1, g.n2};
+    const int per[3] = {ALLPER ? 1 : g.per0, ALLPER ? 1 : g.per1, ALLPER ? 1 : g.per2};
+    const unsigned stride[3] = {1u, unsigned(g.n0), unsigned(g.n0) * unsigned(g.n1)};
     double cfl = 0.0;
     if (i < g.n0 && j < g.n1) {
-        const size_t id = cid(g, i, j, k);
-        T s = T(0);
-        for (int d = 0; d < g.ndim; ++d) {
-            const T ud = projected<T, UNIF>(V, p, C, d, i, j, k, coef);
-            out[d][id] = ud;
-            if (CFL) {
-                const int n = d == 0 ? g.n0 : (d == 1 ? g.n1 : g.n2);
-                const int cc = d == 0 ? i : (d == 1 ? j : k);
-                const int per = d == 0 ? g.per0 : (d == 1 ? g.per1 : g.per2);
-                T up;
-                if (cc + 1 < n || per) {
-                    const int cu = cc + 1 < n ? cc + 1 : 0;
-                    up = projected<T, UNIF>(V, p, C, d, d == 0 ? cu : i, d == 1 ? cu : j,
-                                            d == 2 ? cu : k, coef);
+        for (int k = sp.z0; k < sp.z1; ++k) {
+            const int q[3] = {i, j, k};
+            const unsigned id = unsigned(i) + stride[1] * unsigned(j) + stride[2] * unsigned(k);
+            const T pI = p[id];
+            T s = T(0);
+            for (int d = 0; d < g.ndim; ++d) {
+                T ud;
+                if (!ALLPER && !per[d] && q[d] == 0) {
+                    ud = V.u[d][id];  // boundary face: L = 0
                 } else {
-                    up = vget<T, ALLPER>(V, d, i + (d == 0), j + (d == 1), k + (d == 2));
+                    const unsigned idl = q[d] > 0 ? id - stride[d] : id + stride[d] * unsigned(n[d] - 1);
+                    const T L = UNIF ? C.Lc : C.L[d][id];
+                    ud = V.u[d][id] - coef * L * (pI - p[idl]);
                 }
-                s += fmax(up, T(0)) - fmin(ud, T(0));
+                out[d][id] = ud;
+                if (CFL) {
+                    T up;
+                    if (q[d] + 1 < n[d] || per[d]) {
+                        const unsigned idu = q[d] + 1 < n[d] ? id + stride[d]
+                                                             : id - stride[d] * unsigned(n[d] - 1);
+                        const T Lu = UNIF ? C.Lc : C.L[d][idu];
+                        up = V.u[d][idu] - coef * Lu * (p[idu] - pI);
+                    } else {
+                        up = vget<T, ALLPER>(V, d, i + (d == 0), j + (d == 1), k + (d == 2));
+                    }
+                    s += fmax(up, T(0)) - fmin(ud, T(0));
+                }
             }
+            cfl = fmax(cfl, double(s));
         }
-        cfl = double(s);
     }
     if (CFL) {
         const double m = block_max(cfl, lds);
-        if (threadIdx.x == 0 && threadIdx.y == 0) partial[block_linear()] = m;
+        if (threadIdx.x == 0) partial[block_linear()] = m;
     }
 }
 
 // Per-block CFL maximum of the current field.
 template <typename T, bool ALLPER>
-__global__ __launch_bounds__(kBlock) void k_cfl(VelField<T> V, double* __restrict__ partial) {
+__global__ __launch_bounds__(kBlock) void k_cfl(TileDev TL, VelField<T> V, double* __restrict__ partial) {
     __shared__ double lds[8];
     const Grid& g = V.g;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
+    const Span sp = tile_span(TL, g.n0, g.n1, g.n2);
+    const int i = sp.i, j = sp.j;
     double v = 0.0;
     if (i < g.n0 && j < g.n1) {
+        for (int k = sp.z0; k < sp.z1; ++k) {
         const size_t id = cid(g, i, j, k);
         T s = T(0);
         for (int d = 0; d < g.ndim; ++d) {
             const T up = vget<T, ALLPER>(V, d, i + (d == 0), j + (d == 1), k + (d == 2));
             s += fmax(up, T(0)) - fmin(V.u[d][id], T(0));
         }
-        v = double(s);
+        v = fmax(v, double(s));
+        }
     }
     const double m = block_max(v, lds);
     if (threadIdx.x == 0 && threadIdx.y == 0) partial[block_linear()] = m;
@@ -354,12 +575,12 @@ __global__ void k_set_scalar(double* p, double v) {
 // - (1 + cos(pi r))/(2 pi^2)] for |r| = |d/eps| < 1 (1/0 and 0 outside),
 // (mu1 n)_cd = mu1 n_d, L_c = mu0 except 0 on non-periodic lower boundary faces.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_measure(Grid g, BodyDev body, int bclo0, int bclo1,
+__global__ __launch_bounds__(kBlock) void k_measure(TileDev TL, Grid g, BodyDev body, int bclo0, int bclo1,
                                                     int bclo2, MeasureOut<T> M) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
+    const Span sp = tile_span(TL, g.n0, g.n1, g.n2);
+    const int i = sp.i, j = sp.j;
     if (i >= g.n0 || j >= g.n1) return;
+    for (int k = sp.z0; k < sp.z1; ++k) {
     const size_t id = cid(g, i, j, k);
     const int coord[3] = {i, j, k};
     const int bclo[3] = {bclo0, bclo1, bclo2};
@@ -397,17 +618,18 @@ __global__ __launch_bounds__(kBlock) void k_measure(Grid g, BodyDev body, int bc
         M.L[c][id] = T(L);
         if (M.L64[c]) M.L64[c][id] = L;
     }
+    }
 }
 
 // Initial velocity: U_c on every face, boundary faces at their boundary value.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_init_velocity(Grid g, int b0, int b1, int b2, T U0, T U1,
+__global__ __launch_bounds__(kBlock) void k_init_velocity(TileDev TL, Grid g, int b0, int b1, int b2, T U0, T U1,
                                                           T U2, T* __restrict__ u0,
                                                           T* __restrict__ u1, T* __restrict__ u2) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
+    const Span sp = tile_span(TL, g.n0, g.n1, g.n2);
+    const int i = sp.i, j = sp.j;
     if (i >= g.n0 || j >= g.n1) return;
+    for (int k = sp.z0; k < sp.z1; ++k) {
     const size_t id = cid(g, i, j, k);
     const int coord[3] = {i, j, k};
     const int per[3] = {g.per0, g.per1, g.per2};
@@ -419,6 +641,7 @@ __global__ __launch_bounds__(kBlock) void k_init_velocity(Grid g, int b0, int b1
         if (!per[c] && coord[c] == 0) v = (bclo[c] == WL_BC_INFLOW) ? U[c] : T(0);
         u[c][id] = v;
     }
+    }
 }
 
 // ------------------------------------------------------------- launchers
@@ -427,7 +650,7 @@ template <typename T>
 wl_status ns_init_velocity(const Grid& g, const int bclo[3], const double U[3], T* const u[3],
                            hipStream_t s) {
     const Launch ln = launch_for(g.n0, g.n1, g.n2);
-    k_init_velocity<T><<<ln.grid, ln.block, 0, s>>>(g, bclo[0], bclo[1], bclo[2], T(U[0]), T(U[1]),
+    k_init_velocity<T><<<ln.grid, ln.block, 0, s>>>(ln.td, g, bclo[0], bclo[1], bclo[2], T(U[0]), T(U[1]),
                                                     T(U[2]), u[0], u[1], u[2]);
     WL_CHECK_LAUNCH();
     return WL_OK;
@@ -437,9 +660,30 @@ template <typename T>
 wl_status ns_measure(const Grid& g, const BodyDev& body, const int bclo[3], const MeasureOut<T>& M,
                      hipStream_t s) {
     const Launch ln = launch_for(g.n0, g.n1, g.n2);
-    k_measure<T><<<ln.grid, ln.block, 0, s>>>(g, body, bclo[0], bclo[1], bclo[2], M);
+    k_measure<T><<<ln.grid, ln.block, 0, s>>>(ln.td, g, body, bclo[0], bclo[1], bclo[2], M);
     WL_CHECK_LAUNCH();
     return WL_OK;
+}
+
+// z planes per block of the tiled momentum kernel (WL_MOM_ZC overrides).
+int momentum_zchunk() {
+    static const int zc = [] {
+        const char* e = std::getenv("WL_MOM_ZC");
+        const int v = e ? std::atoi(e) : 0;
+        return v > 0 ? v : 64;
+    }();
+    return zc;
+}
+
+TileMap tile_map(const Grid& g, int tile_x, int tile_y, int zc) {
+    TileMap tm;
+    tm.tiles_x = (g.n0 + tile_x - 1) / tile_x;
+    tm.tiles_y = (g.n1 + tile_y - 1) / tile_y;
+    tm.zc = zc < g.n2 ? zc : g.n2;
+    tm.nchunks = (g.n2 + tm.zc - 1) / tm.zc;
+    tm.nblocks = unsigned(tm.tiles_x) * unsigned(tm.tiles_y) * unsigned(tm.nchunks);
+    tm.remap = (tm.nblocks % 8u == 0u) ? 1 : 0;
+    return tm;
 }
 
 template <typename T>
@@ -448,8 +692,24 @@ wl_status ns_momentum(const VelField<T>& E, const T* const un[3], T* const f[3],
     const Grid& g = E.g;
     const Launch ln = launch_for(g.n0, g.n1, g.n2);
     ProfScope ps(WL_PROF_MOMENTUM, s, cells(g));
+    if constexpr (sizeof(T) == 4) {
+        if (g.ndim == 3) {
+            const TileMap tm = tile_map(g, MT_X, MT_Y, momentum_zchunk());
+#define WL_MT(AP, CR)                                                                          \
+    k_momentum_tiled<AP, CR><<<tm.nblocks, kBlock, 0, s>>>(E, un[0], un[1], un[2], f[0], f[1], \
+                                                           f[2], nu, dt_dev, tm)
+            if (allper) {
+                if (corr) WL_MT(true, true); else WL_MT(true, false);
+            } else {
+                if (corr) WL_MT(false, true); else WL_MT(false, false);
+            }
+#undef WL_MT
+            WL_CHECK_LAUNCH();
+            return WL_OK;
+        }
+    }
 #define WL_MOM(AP, CR)                                                                      \
-    k_momentum<T, AP, CR><<<ln.grid, ln.block, 0, s>>>(E, un[0], un[1], un[2], f[0], f[1], f[2], \
+    k_momentum<T, AP, CR><<<ln.grid, ln.block, 0, s>>>(ln.td, E, un[0], un[1], un[2], f[0], f[1], f[2], \
                                                         nu, dt_dev)
     if (allper) {
         if (corr) WL_MOM(true, true); else WL_MOM(true, false);
@@ -475,20 +735,25 @@ wl_status ns_outflow(const Grid& g, const T* ue_x, const T* out_e, const T* out_
 template <typename T>
 wl_status ns_bdim(const VelField<T>& F, const BdimFields<T>& B, T* const out[3], hipStream_t s) {
     const Launch ln = launch_for(F.g.n0, F.g.n1, F.g.n2);
-    k_bdim<T><<<ln.grid, ln.block, 0, s>>>(F, B, out[0], out[1], out[2]);
+    k_bdim<T><<<ln.grid, ln.block, 0, s>>>(ln.td, F, B, out[0], out[1], out[2]);
     WL_CHECK_LAUNCH();
     return WL_OK;
 }
 
 template <typename T>
-wl_status ns_divergence(const VelField<T>& V, double c, const double* dt_dev, T* sigma, bool allper,
+wl_status ns_divergence(const VelField<T>& V, const ProjCoeffs<T>& C, bool unif, double c,
+                        const double* dt_dev, T* sigma, double* partial, bool allper,
                         hipStream_t s) {
     const Launch ln = launch_for(V.g.n0, V.g.n1, V.g.n2);
     ProfScope ps(WL_PROF_DIVERGENCE, s, cells(V.g));
-    if (allper)
-        k_divergence<T, true><<<ln.grid, ln.block, 0, s>>>(V, c, dt_dev, sigma);
-    else
-        k_divergence<T, false><<<ln.grid, ln.block, 0, s>>>(V, c, dt_dev, sigma);
+#define WL_DIV(AP, UN) \
+    k_divergence<T, AP, UN><<<ln.grid, ln.block, 0, s>>>(ln.td, V, C, c, dt_dev, sigma, partial)
+    if (allper) {
+        if (unif) WL_DIV(true, true); else WL_DIV(true, false);
+    } else {
+        if (unif) WL_DIV(false, true); else WL_DIV(false, false);
+    }
+#undef WL_DIV
     WL_CHECK_LAUNCH();
     return WL_OK;
 }
@@ -500,7 +765,7 @@ wl_status ns_project(const VelField<T>& V, const T* p, const ProjCoeffs<T>& C, b
     const Launch ln = launch_for(V.g.n0, V.g.n1, V.g.n2);
     ProfScope ps(WL_PROF_PROJECT, s, cells(V.g));
 #define WL_PRJ(AP, UN, CF)                                                                      \
-    k_project<T, AP, UN, CF><<<ln.grid, ln.block, 0, s>>>(V, p, C, c, dt_dev, out[0], out[1], \
+    k_project<T, AP, UN, CF><<<ln.grid, ln.block, 0, s>>>(ln.td, V, p, C, c, dt_dev, out[0], out[1], \
                                                            out[2], partial)
     if (allper) {
         if (unif) {
@@ -524,9 +789,9 @@ template <typename T>
 wl_status ns_cfl(const VelField<T>& V, bool allper, double* partial, hipStream_t s) {
     const Launch ln = launch_for(V.g.n0, V.g.n1, V.g.n2);
     if (allper)
-        k_cfl<T, true><<<ln.grid, ln.block, 0, s>>>(V, partial);
+        k_cfl<T, true><<<ln.grid, ln.block, 0, s>>>(ln.td, V, partial);
     else
-        k_cfl<T, false><<<ln.grid, ln.block, 0, s>>>(V, partial);
+        k_cfl<T, false><<<ln.grid, ln.block, 0, s>>>(ln.td, V, partial);
     WL_CHECK_LAUNCH();
     return WL_OK;
 }
@@ -553,8 +818,8 @@ wl_status ns_set_scalar(double* p, double v, hipStream_t s) {
                                      const double*, T*, hipStream_t);                             \
     template wl_status ns_bdim<T>(const VelField<T>&, const BdimFields<T>&, T* const*,            \
                                   hipStream_t);                                                   \
-    template wl_status ns_divergence<T>(const VelField<T>&, double, const double*, T*, bool,      \
-                                        hipStream_t);                                             \
+    template wl_status ns_divergence<T>(const VelField<T>&, const ProjCoeffs<T>&, bool, double,  \
+                                        const double*, T*, double*, bool, hipStream_t);           \
     template wl_status ns_project<T>(const VelField<T>&, const T*, const ProjCoeffs<T>&, bool,    \
                                      double, const double*, T* const*, bool, double*, bool,        \
                                      hipStream_t);                                                \

@@ -6,6 +6,27 @@
 
 namespace wl {
 
+struct Span {
+    int i, j;    // cell column of this thread
+    int z0, z1;  // z planes [z0, z1) it walks
+};
+
+__device__ __forceinline__ Span tile_span(const TileDev& T, int n0, int n1, int n2) {
+    unsigned b = blockIdx.x;
+    if (T.remap) b = (b & 7u) * (T.nb >> 3) + (b >> 3);
+    const unsigned tix = b % unsigned(T.tx);
+    b /= unsigned(T.tx);
+    const unsigned tiy = b % unsigned(T.ty);
+    const unsigned ch = b / unsigned(T.ty);
+    const int bx = 1 << T.lbx;
+    Span s;
+    s.i = int(tix) * bx + int(threadIdx.x & unsigned(bx - 1));
+    s.j = int(tiy) * (kBlock >> T.lbx) + int(threadIdx.x >> T.lbx);
+    s.z0 = int(ch) * T.zc;
+    s.z1 = min(s.z0 + T.zc, n2);
+    return s;
+}
+
 __device__ __forceinline__ size_t cid(const Grid& g, int i, int j, int k) {
     return size_t(i) + size_t(g.n0) * (size_t(j) + size_t(g.n1) * size_t(k));
 }
@@ -122,6 +143,29 @@ __device__ __forceinline__ double block_sum(double v, double* lds /* >= 4 */) {
     return s;
 }
 
+// Two deterministic block sums in one pass (lds >= 8 doubles); totals in
+// thread 0.
+__device__ __forceinline__ void block_sum2(double a, double b, double* lds, double& sa,
+                                           double& sb) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+    }
+    const int t = threadIdx.x;
+    if ((t & 63) == 0) {
+        lds[t >> 6] = a;
+        lds[4 + (t >> 6)] = b;
+    }
+    __syncthreads();
+    sa = sb = 0.0;
+    if (t == 0)
+        for (int w = 0; w < (kBlock >> 6); ++w) {
+            sa += lds[w];
+            sb += lds[4 + w];
+        }
+}
+
 __device__ __forceinline__ double block_max(double v, double* lds) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
@@ -137,8 +181,6 @@ __device__ __forceinline__ double block_max(double v, double* lds) {
     return s;
 }
 
-__device__ __forceinline__ unsigned block_linear() {
-    return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-}
+__device__ __forceinline__ unsigned block_linear() { return blockIdx.x; }
 
 }  // namespace wl

@@ -72,10 +72,23 @@ struct Grid {
 
 __host__ __device__ inline size_t cells(const Grid& g) { return size_t(g.n0) * g.n1 * g.n2; }
 
-// Launch shape for one-thread-per-cell kernels: x-fastest blocks of 256 threads.
+// Tile decomposition used by every stencil kernel: a 1D grid of 256-thread
+// blocks; block b owns a bx x (256/bx) column of cells and marches through
+// zc consecutive z planes.  With remap set, block ids are permuted so that
+// each of the 8 XCDs (blocks are dealt to them round-robin) walks a
+// contiguous range of tiles and neighbouring tiles share its L2.
+struct TileDev {
+    int lbx;        // log2 of the tile width bx (<= 64)
+    int tx, ty;     // tiles along x and y
+    int zc;         // z planes per block
+    unsigned nb;    // blocks
+    int remap;
+};
+
 struct Launch {
     dim3 grid, block;
-    unsigned nblocks() const { return grid.x * grid.y * grid.z; }
+    TileDev td;
+    unsigned nblocks() const { return td.nb; }
 };
 Launch launch_for(int n0, int n1, int n2);
 
@@ -130,9 +143,11 @@ struct SolveResult {
 
 // Plain GMG solve on h (level 0 x = caller x).  b is the raw right-hand side.
 // Converged before a V-cycle when ||r||^2 <= tol^2 ||b||^2 or ||r||^2 <= abs_r2.
+// b_partials: red.partial already holds the per-block sums of b over the
+// active cells for the fine-level tiling (written by the producer of b).
 template <typename T>
 wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, double abs_r2,
-                   int max_vcycles, hipStream_t s, SolveResult* res);
+                   int max_vcycles, hipStream_t s, SolveResult* res, bool b_partials = false);
 
 // Mixed precision: FP64 outer residual with FP64 fine coefficients L64,
 // FP32 inner V-cycles on h32.

@@ -37,6 +37,16 @@ struct MeasureOut {
     double* L64[3];  // optional FP64 copy of L (mixed-precision solves)
 };
 
+// Tile decomposition of a z-marching kernel: tiles_x * tiles_y columns of
+// tile_x * tile_y cells, each split into chunks of zc planes.
+struct TileMap {
+    int tiles_x, tiles_y, nchunks, zc;
+    unsigned nblocks;
+    int remap;  // 1: XCD-contiguous block order (nblocks divisible by 8)
+};
+TileMap tile_map(const Grid& g, int tile_x, int tile_y, int zc);
+int momentum_zchunk();
+
 struct BodyDev {
     int kind;
     double centre[3];
@@ -56,7 +66,8 @@ wl_status ns_outflow(const Grid& g, const T* ue_x, const T* out_e, const T* out_
 template <typename T>
 wl_status ns_bdim(const VelField<T>& F, const BdimFields<T>& B, T* const out[3], hipStream_t s);
 template <typename T>
-wl_status ns_divergence(const VelField<T>& V, double c, const double* dt_dev, T* sigma, bool allper,
+wl_status ns_divergence(const VelField<T>& V, const ProjCoeffs<T>& C, bool unif, double c,
+                        const double* dt_dev, T* sigma, double* partial, bool allper,
                         hipStream_t s);
 template <typename T>
 wl_status ns_project(const VelField<T>& V, const T* p, const ProjCoeffs<T>& C, bool unif, double c,
