@@ -79,6 +79,42 @@ def cpu_baseline(N, vcycles):
                        f"V-cycles per solve {tuple(vcycles)} = the GPU's mean), {secs:.1f} s")
 
 
+def poisson_compare(torch, wl, W, n, radius=32.0, tol=1e-8, reps=3):
+    """Mixed-precision vs plain FP64 GMG on the sphere-in-a-box Poisson problem
+    (BDIM coefficients of a sphere of radius 32 cells, N(0,1) RHS, tol 1e-8)."""
+    import numpy as np
+    from paper_2304_08159_amd import _lib
+    cfg = W.poisson_sphere_config(n, radius)
+    # BDIM coefficients come from the library's own geometry kernel (a 3D
+    # simulation handle with the same body and Neumann walls)
+    sim = wl.Sim(n, cfg["bc_lo"], cfg["bc_hi"], (0.0, 0.0, 0.0), 0.0, body=cfg["body"],
+                 prec=wl.WL_FP64, levels=0, tol=tol)
+    L = torch.stack([sim.get(wl.FIELD_L0 + i) for i in range(3)]).contiguous()
+    sim.close()
+    del sim
+    b = torch.from_numpy(np.ascontiguousarray(W.random_rhs(n, 2304).transpose(2, 1, 0))).cuda()
+    out = {}
+    for name, prec in (("fp64", wl.WL_FP64), ("mixed", wl.WL_MIXED)):
+        ps = wl.Poisson(n, (False, False, False), prec=prec)
+        x = torch.zeros_like(b)
+        ps.solve(L, x, b, tol=tol, max_vcycles=400)      # warm-up (also loads coefficients)
+        times = []
+        for _ in range(reps):
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            k, rel = ps.solve(None, x, b, tol=tol, max_vcycles=400)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        out[name] = {"ms": 1e3 * min(times), "vcycles": k, "rel_resid": rel,
+                     "footprint_MB": ps.footprint / 1e6}
+        ps.close()
+    out["speedup_mixed_over_fp64"] = out["fp64"]["ms"] / out["mixed"]["ms"]
+    out["workload"] = (f"Poisson {n[0]}x{n[1]}x{n[2]} Neumann box, sphere r={radius} BDIM "
+                       f"coefficients, N(0,1) RHS seed 2304, to relative residual {tol}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +123,8 @@ def main():
     ap.add_argument("--N", type=int, default=256)
     ap.add_argument("--cpu-N", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-poisson", action="store_true",
+                    help="skip the mixed-vs-FP64 Poisson comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -199,6 +237,11 @@ def main():
     out["roofline"]["frac_of_copy"] = kern[dom]["gbs"] / copy_gbs
     out["step_roofline"]["frac_of_copy"] = step_gbs / copy_gbs
     del src, dst
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    if not args.no_poisson:
+        out["poisson_mixed_vs_fp64"] = poisson_compare(torch, wl, W, (N, N, N))
     if not args.no_cpu_baseline:
         vcr = [max(1, int(round(x))) for x in vc_mean]
         try:

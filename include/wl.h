@@ -176,6 +176,15 @@ wl_status wl_poisson_solve(wl_poisson* ps, const void* coeffs, void* x, const vo
                            double* rel_resid_out);
 wl_status wl_poisson_destroy(wl_poisson* ps);
 
+/* BDIM-modified Poisson coefficients of a body (Sec. 2): L_i = mu0 of the
+ * signed distance at every lower i-face centre (cosine kernel of half-width
+ * body->eps, <= 0 selects 1 cell), zero on non-periodic lower boundary faces;
+ * body->kind == 0 gives L = 1.  L_out receives ndim consecutive face arrays
+ * (layout above) of float (prec WL_FP32) or double (WL_FP64, WL_MIXED).
+ * Enqueued on hip_stream and synchronised before returning. */
+wl_status wl_body_coeffs(const wl_body* body, int ndim, const int n[3], const int periodic[3],
+                         int prec, void* L_out, void* hip_stream);
+
 /* ---- Kernel timing (measurement support) -------------------------------- */
 
 /* Kernels whose launches can be bracketed by HIP events, to turn algorithmic

@@ -17,7 +17,7 @@ from ._lib import (FIELD_L0, FIELD_MU0_0, FIELD_MU1N, FIELD_P, FIELD_SIGMA, FIEL
                    FIELD_UOUT, INFLOW, OUTFLOW, PERIODIC, WALL, WL_FP32, WL_FP64, WL_MIXED,
                    WlError, check, load)
 
-__all__ = ["Sim", "Poisson", "load", "WlError", "WL_FP32", "WL_FP64", "WL_MIXED",
+__all__ = ["Sim", "Poisson", "body_coeffs", "load", "WlError", "WL_FP32", "WL_FP64", "WL_MIXED",
            "PERIODIC", "INFLOW", "OUTFLOW", "WALL"]
 
 
@@ -130,6 +130,28 @@ class Sim:
               allow=(-3,) if allow_not_converged else ())
         return dict(dt=st.dt, t=st.t, vcycles=(st.vcycles[0], st.vcycles[1]),
                     resid=(st.resid[0], st.resid[1]))
+
+
+def body_coeffs(n, periodic, body=None, prec=WL_FP32, device="cuda"):
+    """BDIM Poisson coefficients of a sphere/circle body: tensor (ndim, n2, n1, n0)."""
+    torch = _torch()
+    lib = load()
+    n = tuple(int(m) for m in n)
+    ndim = len(n)
+    nn = (ctypes.c_int * 3)(*(list(n) + [1] * (3 - ndim)))
+    per = (ctypes.c_int * 3)(*([int(bool(p)) for p in periodic] + [0] * (3 - ndim)))
+    b = _lib.Body()
+    if body is not None:
+        b.kind = 1
+        c = list(body["centre"]) + [0.0] * (3 - ndim)
+        for i in range(3):
+            b.centre[i] = float(c[i])
+        b.radius = float(body["radius"])
+        b.eps = float(body.get("eps", 1.0))
+    dtype = torch.float32 if prec == WL_FP32 else torch.float64
+    L = torch.empty((ndim, nn[2], nn[1], nn[0]), dtype=dtype, device=device)
+    check(lib.wl_body_coeffs(ctypes.byref(b), ndim, nn, per, int(prec), _ptr(L), _stream(torch)))
+    return L
 
 
 class Poisson:

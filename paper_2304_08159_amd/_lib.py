@@ -27,7 +27,8 @@ FIELD_L0, FIELD_MU0_0, FIELD_MU1N, FIELD_SIGMA = 5, 8, 11, 20
 EXPORTS = (
     "wl_sim_footprint", "wl_sim_create", "wl_sim_destroy", "wl_set_field", "wl_get_field",
     "wl_set_time", "wl_step", "wl_poisson_footprint", "wl_poisson_create",
-    "wl_poisson_solve", "wl_poisson_destroy", "wl_profile_enable", "wl_profile_reset",
+    "wl_poisson_solve", "wl_poisson_destroy", "wl_body_coeffs", "wl_profile_enable",
+    "wl_profile_reset",
     "wl_profile_read", "wl_last_error", "wl_version",
 )
 PROF = dict(smooth_fine=0, smooth_norm=1, prolong_fine=2, restrict_fine=3, momentum=4,
@@ -84,6 +85,7 @@ def load():
         "wl_poisson_create": [i32, ip3, ip3, i32, i32, vp, sz, vp, ctypes.POINTER(vp)],
         "wl_poisson_solve": [vp, vp, vp, vp, f64, i32, ctypes.POINTER(i32), ctypes.POINTER(f64)],
         "wl_poisson_destroy": [vp],
+        "wl_body_coeffs": [ctypes.POINTER(Body), i32, ip3, ip3, i32, vp, vp],
         "wl_profile_enable": [ctypes.c_uint],
         "wl_profile_reset": [],
         "wl_profile_read": [i32, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_longlong),

@@ -685,6 +685,48 @@ wl_status wl_poisson_solve(wl_poisson* ps, const void* coeffs, void* x, const vo
     return poisson_solve_mixed(ps, coeffs, x, b, tol, max_vcycles, vcycles_out, rel_resid_out);
 }
 
+wl_status wl_body_coeffs(const wl_body* body, int ndim, const int n[3], const int periodic[3],
+                         int prec, void* L_out, void* hip_stream) {
+    clear_error();
+    if (!body || !n || !periodic || !L_out) return invalid("NULL argument");
+    if (ndim != 2 && ndim != 3) return invalid("ndim must be 2 or 3");
+    if (ndim == 2 && n[2] != 1) return invalid("2D problems need n[2] == 1");
+    for (int i = 0; i < ndim; ++i)
+        if (n[i] < 1) return invalid("grid dimensions must be positive");
+    if (prec < 0 || prec > 2) return invalid("prec must be WL_FP32, WL_FP64 or WL_MIXED");
+    if (body->kind != 0 && body->kind != 1) return invalid("body.kind must be 0 or 1");
+    if (body->kind == 1 && !(body->radius > 0.0)) return invalid("body radius must be > 0");
+    const Grid g{n[0], n[1], n[2], periodic[0] != 0, periodic[1] != 0,
+                 ndim == 3 && periodic[2] != 0, ndim};
+    const int bclo[3] = {g.per0 ? WL_BC_PERIODIC : WL_BC_WALL, g.per1 ? WL_BC_PERIODIC : WL_BC_WALL,
+                         g.per2 ? WL_BC_PERIODIC : WL_BC_WALL};
+    BodyDev bd{body->kind,
+               {body->centre[0], body->centre[1], body->centre[2]},
+               body->radius,
+               body->eps > 0.0 ? body->eps : 1.0};
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    const size_t N = cells(g);
+    if (prec == WL_FP32) {
+        float* L = static_cast<float*>(L_out);
+        MeasureOut<float> M{{nullptr, nullptr, nullptr},
+                            {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                             nullptr},
+                            {L, L + N, ndim == 3 ? L + 2 * N : nullptr},
+                            {nullptr, nullptr, nullptr}};
+        WL_TRY(ns_measure<float>(g, bd, bclo, M, st));
+    } else {
+        double* L = static_cast<double*>(L_out);
+        MeasureOut<double> M{{nullptr, nullptr, nullptr},
+                             {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                              nullptr, nullptr},
+                             {L, L + N, ndim == 3 ? L + 2 * N : nullptr},
+                             {nullptr, nullptr, nullptr}};
+        WL_TRY(ns_measure<double>(g, bd, bclo, M, st));
+    }
+    WL_CHECK_HIP(hipStreamSynchronize(st));
+    return WL_OK;
+}
+
 wl_status wl_poisson_destroy(wl_poisson* ps) {
     clear_error();
     if (!ps) return WL_OK;

@@ -611,11 +611,12 @@ __global__ __launch_bounds__(kBlock) void k_measure(TileDev TL, Grid g, BodyDev 
                                  (1.0 + cs) / (2.0 * pi * pi));
             }
         }
-        M.mu0[c][id] = T(m0);
-        for (int d = 0; d < 3; ++d) M.mu1n[3 * c + d][id] = T(m1 * nrm[d]);
+        if (M.mu0[c]) M.mu0[c][id] = T(m0);
+        if (M.mu1n[3 * c])
+            for (int d = 0; d < 3; ++d) M.mu1n[3 * c + d][id] = T(m1 * nrm[d]);
         double L = (c < g.ndim) ? m0 : 0.0;
         if (bclo[c] != WL_BC_PERIODIC && coord[c] == 0) L = 0.0;
-        M.L[c][id] = T(L);
+        if (M.L[c]) M.L[c][id] = T(L);
         if (M.L64[c]) M.L64[c][id] = L;
     }
     }

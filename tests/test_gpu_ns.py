@@ -131,3 +131,42 @@ def test_sphere_fp32_replay_parity():
                nu=0.08, body=dict(centre=(16.0, 16.0, 16.0), radius=4.0), tol=1e-5)
     sim, osim = _make(cfg, wl.WL_FP32, cfg["tol"])
     _replay(sim, osim, 3, 1e-5, 1e-5, "sphere")
+
+
+def test_sphere_mixed_precision_step_matches_tight_oracle():
+    """WL_MIXED: FP32 fields, FP32 V-cycles with FP64 defect correction.  With
+    both solves tight, one step from the same state agrees with the oracle."""
+    import paper_2304_08159_amd as wl
+    cfg = dict(n=(48, 24, 24), bc_lo=[1, 3, 3], bc_hi=[2, 3, 3], U=(1.0, 0.0, 0.0),
+               nu=0.06, body=dict(centre=(12.0, 12.0, 12.2), radius=4.0))
+    sim = wl.Sim(cfg["n"], cfg["bc_lo"], cfg["bc_hi"], cfg["U"], cfg["nu"], body=cfg["body"],
+                 prec=wl.WL_MIXED, tol=1e-9, max_vcycles=300)
+    osim = S.Sim(cfg["n"], cfg["bc_lo"], cfg["bc_hi"], cfg["U"], cfg["nu"], body=cfg["body"],
+                 tol=1e-13, max_vcycles=300)
+    for step in range(3):
+        un = [to_oracle(t, 3) for t in sim.velocity()]
+        pn = to_oracle(sim.pressure(), 3)
+        uo = plane_to_oracle(sim.get(4), 3)
+        st = sim.step()
+        osim.u, osim.p, osim.uout = un, pn, uo
+        osim.step(dt=st["dt"])
+        ug = [to_oracle(t, 3) for t in sim.velocity()]
+        eu = math.sqrt(sum(np.sum((a - b) ** 2) for a, b in zip(ug, osim.u)) /
+                       sum(np.sum(b ** 2) for b in osim.u))
+        act = osim.h.active[0]
+        ep = rel_l2(mean_free(to_oracle(sim.pressure(), 3), act), mean_free(osim.p, act), act)
+        print(f"mixed step {step}: vc={st['vcycles']} div={st['resid']} err_u={eu:.2e} err_p={ep:.2e}")
+        assert eu <= 1e-5 and ep <= 1e-5
+
+
+def test_body_coeffs_matches_oracle():
+    import paper_2304_08159_amd as wl
+    for n, per, prec in [((40, 30), (False, True), wl.WL_FP32),
+                         ((20, 16, 12), (True, False, False), wl.WL_FP64)]:
+        body = dict(centre=tuple(m / 2.0 + 0.3 for m in n), radius=4.5)
+        L = wl.body_coeffs(n, per, body, prec=prec)
+        d = len(n)
+        Lo = G.measure(n, [0 if p else 3 for p in per], body)[2]
+        tol = 2e-7 if prec == wl.WL_FP32 else 1e-15
+        for i in range(d):
+            np.testing.assert_allclose(to_oracle(L[i], d), Lo[i], atol=tol)

@@ -1,0 +1,62 @@
+"""GPU serving: results are bitwise the same alone and in the mix, and served
+Poisson solutions meet the FP64 tolerance on the oracle's operator."""
+
+import numpy as np
+import pytest
+
+from oracle import geometry as G
+from oracle import poisson as P
+from oracle.grid import WALL
+from tests.gpu_util import to_oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _mix():
+    from paper_2304_08159_amd.serving import Request
+    sizes = [(64, 64), (128, 128), (32, 32, 32), (48, 48, 48), (64, 64, 64), (96, 64)]
+    reqs = []
+    for k in range(12):
+        n = sizes[k % len(sizes)]
+        kind = "poisson" if k % 2 == 0 else "ns"
+        reqs.append(Request(id=k, kind=kind, n=n, arrival=0.0,
+                            radius=min(n) / 6.0 if kind == "poisson" else n[1] / 10.0,
+                            steps=5, seed=100 + k))
+    return reqs
+
+
+def test_results_identical_alone_and_in_the_mix():
+    from paper_2304_08159_amd.serving import GpuExecutor, Server, summarize
+    ex = GpuExecutor()
+    alone = {}
+    for r in _mix():
+        out = Server(ex, 64 << 30, slots=1).run([r])[0]
+        assert out.status == "done", out.error
+        alone[r.id] = out.result[0]
+    mixed = Server(ex, 64 << 30, slots=8).run(_mix())
+    s = summarize(mixed)
+    print(s)
+    assert s["done"] == 12
+    for r in mixed:
+        assert r.result[0] == alone[r.id], f"request {r.id} differs in the mix"
+
+
+def test_served_poisson_meets_tolerance_on_oracle_operator():
+    from paper_2304_08159_amd.serving import GpuExecutor, Request, Server
+    ex = GpuExecutor(keep_fields=True)
+    for n in [(64, 48), (24, 32, 16)]:
+        r = Request(id=0, kind="poisson", n=n, radius=min(n) / 5.0, seed=7, tol=1e-8)
+        out = Server(ex, 8 << 30, slots=1).run([r])[0]
+        assert out.status == "done", out.error
+        x, b, L = out.result[2]
+        d = len(n)
+        xg, bg = to_oracle(x, d), to_oracle(b, d)
+        Lo = G.measure(n, [WALL] * d, dict(centre=tuple(m / 2 for m in n), radius=r.radius))[2]
+        for i in range(d):
+            np.testing.assert_allclose(to_oracle(L[i], d), Lo[i], atol=1e-14)
+        act = P.active_mask(Lo, [False] * d)
+        bp = P.project_rhs(bg, act)
+        res = np.linalg.norm(bp - P.apply_A(Lo, xg, [False] * d)) / np.linalg.norm(bp)
+        print(n, "served residual (oracle operator)", res, out.result[1])
+        assert res <= 1.05e-8
