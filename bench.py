@@ -115,6 +115,27 @@ def poisson_compare(torch, wl, W, n, radius=32.0, tol=1e-8, reps=3):
     return out
 
 
+def serving_bench(count=512, seed=2304, budget=16e9, slots=8):
+    """Served mix: sizes uniform over 2D {64^2,128^2,256^2} and 3D {64^3,96^3,128^3},
+    half Poisson solves (FP32 V-cycles + FP64 refinement to 1e-8), half 20-step NS
+    runs with a body; HBM budget 16 GB; saturated throughput first (all requests at
+    t = 0), then Poisson arrivals at 0.5 and 0.8 of it."""
+    from paper_2304_08159_amd.serving import GpuExecutor, Server, make_requests, summarize
+    ex = GpuExecutor()
+    Server(ex, budget, slots=slots).run(make_requests(count=16, seed=seed + 1))   # warm-up
+    sat = summarize(Server(ex, budget, slots=slots).run(make_requests(count=count, seed=seed)))
+    mu = sat["throughput_rps"]
+    res = {"saturated": sat}
+    for frac in (0.5, 0.8):
+        srv = Server(ex, budget, slots=slots)
+        r = summarize(srv.run(make_requests(count=count, seed=seed, rate=frac * mu)))
+        r["arrival_rate_rps"] = frac * mu
+        r["peak_bytes"] = srv.peak_bytes
+        res[f"rate_{frac}"] = r
+    res["config"] = dict(requests=count, budget_bytes=budget, slots=slots, seed=seed)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +146,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-poisson", action="store_true",
                     help="skip the mixed-vs-FP64 Poisson comparison")
+    ap.add_argument("--no-serving", action="store_true", help="skip the served request mix")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -242,6 +264,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_poisson:
         out["poisson_mixed_vs_fp64"] = poisson_compare(torch, wl, W, (N, N, N))
+    if not args.no_serving:
+        out["serving"] = serving_bench()
     if not args.no_cpu_baseline:
         vcr = [max(1, int(round(x))) for x in vc_mean]
         try:
