@@ -99,6 +99,7 @@ typedef struct {
     int max_vcycles;      /* per pressure solve (<= 0 selects 100)            */
     int inner_vcycles;    /* MIXED: FP32 V-cycles per outer iteration (0: 3)  */
     double cfl;           /* CFL number of the adaptive time step (0: 0.5)    */
+    int tape_steps;       /* steps the adjoint tape can hold (0: no adjoint)  */
 } wl_sim_desc;
 
 typedef struct {
@@ -150,6 +151,34 @@ wl_status wl_set_time(wl_sim* sim, double t);
  * may be NULL.  Returns WL_ERR_NOT_CONVERGED when a solve hits max_vcycles
  * (the step is still completed with the last iterate). */
 wl_status wl_step(wl_sim* sim, double dt, wl_step_stats* stats);
+
+/* ---- Adjoint of the step (the solver is differentiable, Sec. 2) --------- */
+
+/* Pressure drag of the body from the current pressure (the corrector
+ * pressure of the last step): F_x = -sum over active cells of
+ * (p - mean p) n_x K(d) at cell centres, K the BDIM kernel, n = grad d. */
+wl_status wl_drag(wl_sim* sim, double* Fx);
+
+/* Start (on != 0) or stop recording an adjoint tape: while recording, each
+ * wl_step stores its intermediate fields (state, stage fields, pressures,
+ * dt) in the next free slot of the tape (at most desc.tape_steps slots,
+ * carved from the workspace; steps taken once it is full are not recorded).
+ * Starting clears the tape and the geometry adjoint accumulators.
+ * WL_ERR_STATE when the simulation was created with tape_steps = 0. */
+wl_status wl_tape_record(wl_sim* sim, int on);
+
+/* Reverse one recorded step (the most recent one still on the tape), with dt
+ * and the limiter / upwind branches frozen at their forward values and every
+ * pressure solve treated as exact (its adjoint is the same GMG solve).
+ * ubar_in: adjoint of the state after the step (ndim face arrays followed by
+ * the outflow plane when there is one; sim dtype); ubar_out: adjoint of the
+ * state before it (same layout; may alias ubar_in).  drag_weight: dJ/dF_x of
+ * the step's drag.  g_params[4] (host, may be NULL) accumulates
+ * dJ/d(radius, centre x, y, z) through the geometry (BDIM moments, Poisson
+ * coefficients, drag weights).  Synchronous on the simulation's stream.
+ * WL_ERR_STATE when the tape is empty. */
+wl_status wl_step_adjoint(wl_sim* sim, const void* ubar_in, double drag_weight, void* ubar_out,
+                          double* g_params);
 
 /* ---- Standalone pressure-Poisson GMG solve (project!, Sec. 2) ---------- */
 

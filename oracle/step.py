@@ -50,6 +50,24 @@ def grad_update(u, p, L, per, coef):
     return [u[i] - coef * L[i] * (p - shift(p, i, -1, per[i])) for i in range(len(u))]
 
 
+def drag(sim):
+    """Pressure drag of the body from the current pressure.
+
+    READING (the paper defines no force): the kernel-smoothed surface integral
+    of the pressure, F_x = -sum over active cells of (p - mean p) n_x K(d) at
+    cell centres, with K the BDIM kernel and n the SDF gradient; the active
+    mean makes it independent of the pressure's free constant.
+    """
+    if sim.body is None:
+        return 0.0
+    X = geometry.cell_centres(sim.n)
+    dist, normal = geometry.sphere_sdf(X, sim.body["centre"], sim.body["radius"])
+    w = normal[0] * geometry.kernel(dist)
+    act = sim.h.active[0]
+    p = sim.p[act]
+    return float(-np.sum((p - p.mean()) * w[act]))
+
+
 class Sim:
     """FP64 reference of one NS configuration (uniform grid, optional sphere)."""
 

@@ -47,7 +47,7 @@ class Sim:
     """One Navier-Stokes configuration resident on the GPU (wl_sim)."""
 
     def __init__(self, n, bc_lo, bc_hi, U, nu, body=None, prec=WL_FP32, levels=0, tol=1e-5,
-                 max_vcycles=100, inner_vcycles=3, cfl=0.5, eps=1.0, device="cuda"):
+                 max_vcycles=100, inner_vcycles=3, cfl=0.5, eps=1.0, tape_steps=0, device="cuda"):
         torch = _torch()
         lib = load()
         n = tuple(int(m) for m in n)
@@ -70,6 +70,7 @@ class Sim:
             d.body.eps = float(body.get("eps", eps))
         d.prec, d.mg_levels, d.tol = int(prec), int(levels), float(tol)
         d.max_vcycles, d.inner_vcycles, d.cfl = int(max_vcycles), int(inner_vcycles), float(cfl)
+        d.tape_steps = int(tape_steps)
         nbytes = ctypes.c_size_t()
         check(lib.wl_sim_footprint(ctypes.byref(d), ctypes.byref(nbytes)))
         self.footprint = nbytes.value
@@ -123,6 +124,51 @@ class Sim:
 
     def set_time(self, t):
         check(self._lib.wl_set_time(self._h, float(t)))
+
+    @property
+    def has_outflow(self):
+        return self.desc.bc_hi[0] == OUTFLOW
+
+    def state_size(self):
+        cells = self.shape[0] * self.shape[1] * self.shape[2]
+        return self.ndim * cells + (self.shape[0] * self.shape[1] if self.has_outflow else 0)
+
+    def get_state(self):
+        """Velocity components and outflow plane as one flat tensor."""
+        torch = _torch()
+        parts = [t.reshape(-1) for t in self.velocity()]
+        if self.has_outflow:
+            parts.append(self.get(FIELD_UOUT).reshape(-1))
+        return torch.cat(parts)
+
+    def set_state(self, vec, p=None):
+        cells = self.shape[0] * self.shape[1] * self.shape[2]
+        for i in range(self.ndim):
+            self.set(FIELD_U0 + i, vec[i * cells:(i + 1) * cells].reshape(self.shape))
+        if self.has_outflow:
+            self.set(FIELD_UOUT, vec[self.ndim * cells:].reshape(self.shape[0], self.shape[1]))
+        if p is not None:
+            self.set(FIELD_P, p)
+
+    def drag(self):
+        F = ctypes.c_double()
+        check(self._lib.wl_drag(self._h, ctypes.byref(F)))
+        return F.value
+
+    def tape(self, on=True):
+        check(self._lib.wl_tape_record(self._h, int(bool(on))))
+
+    def step_adjoint(self, ubar, drag_weight=0.0):
+        """Reverse the last recorded step: returns (adjoint of the state before
+        it, dJ/d(radius, cx, cy, cz) contributed by this step)."""
+        torch = _torch()
+        ubar = ubar.to(device=self.device, dtype=self.dtype).contiguous()
+        if ubar.numel() != self.state_size():
+            raise ValueError("adjoint state has the wrong size")
+        out = torch.empty_like(ubar)
+        g = (ctypes.c_double * 4)(0.0, 0.0, 0.0, 0.0)
+        check(self._lib.wl_step_adjoint(self._h, _ptr(ubar), float(drag_weight), _ptr(out), g))
+        return out, [g[0], g[1], g[2], g[3]]
 
     def step(self, dt=0.0, allow_not_converged=False):
         st = _lib.StepStats()

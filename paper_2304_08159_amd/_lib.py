@@ -26,7 +26,8 @@ FIELD_L0, FIELD_MU0_0, FIELD_MU1N, FIELD_SIGMA = 5, 8, 11, 20
 # Every symbol include/wl.h declares.
 EXPORTS = (
     "wl_sim_footprint", "wl_sim_create", "wl_sim_destroy", "wl_set_field", "wl_get_field",
-    "wl_set_time", "wl_step", "wl_poisson_footprint", "wl_poisson_create",
+    "wl_set_time", "wl_step", "wl_drag", "wl_tape_record", "wl_step_adjoint",
+    "wl_poisson_footprint", "wl_poisson_create",
     "wl_poisson_solve", "wl_poisson_destroy", "wl_body_coeffs", "wl_profile_enable",
     "wl_profile_reset",
     "wl_profile_read", "wl_last_error", "wl_version",
@@ -52,7 +53,7 @@ class SimDesc(ctypes.Structure):
                 ("U", ctypes.c_double * 3), ("nu", ctypes.c_double), ("body", Body),
                 ("prec", ctypes.c_int), ("mg_levels", ctypes.c_int), ("tol", ctypes.c_double),
                 ("max_vcycles", ctypes.c_int), ("inner_vcycles", ctypes.c_int),
-                ("cfl", ctypes.c_double)]
+                ("cfl", ctypes.c_double), ("tape_steps", ctypes.c_int)]
 
 
 class StepStats(ctypes.Structure):
@@ -81,6 +82,9 @@ def load():
         "wl_get_field": [vp, i32, vp],
         "wl_set_time": [vp, f64],
         "wl_step": [vp, f64, ctypes.POINTER(StepStats)],
+        "wl_drag": [vp, ctypes.POINTER(f64)],
+        "wl_tape_record": [vp, i32],
+        "wl_step_adjoint": [vp, vp, f64, vp, ctypes.POINTER(f64)],
         "wl_poisson_footprint": [i32, ip3, ip3, i32, i32, ctypes.POINTER(sz)],
         "wl_poisson_create": [i32, ip3, ip3, i32, i32, vp, sz, vp, ctypes.POINTER(vp)],
         "wl_poisson_solve": [vp, vp, vp, vp, f64, i32, ctypes.POINTER(i32), ctypes.POINTER(f64)],

@@ -6,6 +6,7 @@
 #include <new>
 #include <string>
 
+#include "wl_adj.h"
 #include "wl_internal.h"
 #include "wl_ns.h"
 
@@ -59,6 +60,7 @@ static wl_status check_desc(const wl_sim_desc* desc, SimConfig* cfg) {
     if (d.body.kind == 1 && !(d.body.radius > 0.0)) return invalid("body radius must be > 0");
     if (!(d.body.eps > 0.0)) d.body.eps = 1.0;
     if (d.mg_levels < 0 || d.mg_levels > kMaxLevels) return invalid("mg_levels out of range");
+    if (d.tape_steps < 0 || d.tape_steps > 100000) return invalid("tape_steps out of range");
     SimConfig c;
     c.d = d;
     c.g = Grid{d.n[0], d.n[1], d.n[2], d.bc_lo[0] == WL_BC_PERIODIC, d.bc_lo[1] == WL_BC_PERIODIC,
@@ -83,6 +85,53 @@ static wl_status check_desc(const wl_sim_desc* desc, SimConfig* cfg) {
     return WL_OK;
 }
 
+// One recorded step: everything the reverse pass needs.
+template <typename T>
+struct TapeSlot {
+    T* un[3];
+    T* outn;   // state at the step start (evaluation field of the predictor)
+    T* u1[3];
+    T* out1;   // predictor result (evaluation field of the corrector)
+    T* f1[3];
+    T* fo1;    // predictor stage field before BDIM
+    T* f2[3];
+    T* fo2;    // corrector stage field before BDIM
+    T* p1;
+    T* p2;     // stage pressures
+    double dt;
+};
+
+// Adjoint workspace (carved with the simulation when tape_steps > 0).
+template <typename T>
+struct AdjointWS {
+    int cap = 0, count = 0;
+    bool recording = false;
+    TapeSlot<T>* tape = nullptr;  // host array of cap slots
+    PadGrid pg;
+    T* pad[3];
+    T* ub[3];
+    T* uob;     // adjoint of the state after the step (working copy)
+    T* u1b[3];
+    T* u1ob;    // adjoint of the predictor result
+    T* unb[3];
+    T* unob;    // adjoint of the state before the step
+    T* gb[3];   // adjoint of the post-BDIM stage field
+    T* fb[3];
+    T* fob;     // adjoint of the stage field and its outflow plane
+    T* Rb[3];   // adjoint of the convection-diffusion tendency
+    T* rhs;
+    T* sbar;
+    T* pbar;    // cells
+    T* Lb[3];
+    T* mu0b[3];
+    T* mu1nb[9];
+    double* rhs64 = nullptr;
+    double* x64 = nullptr;
+    double* part4;  // 4 * slots
+    double* res;    // 16
+    T* dummy;       // P (plane-sized scratch)
+};
+
 template <typename T>
 struct SimImpl {
     SimConfig cfg;
@@ -106,6 +155,13 @@ struct SimImpl {
     double t = 0.0;
     double dt_next_host = 0.0;
     bool cfl_valid = false;
+    AdjointWS<T>* adj = nullptr;  // host bookkeeping of the adjoint workspace
+    ~SimImpl() {
+        if (adj) {
+            delete[] adj->tape;
+            delete adj;
+        }
+    }
 };
 
 template <typename T>
@@ -123,14 +179,66 @@ static void carve_sim(Carver& c, SimImpl<T>& s, const SimConfig& cfg) {
     const int per[3] = {cfg.g.per0, cfg.g.per1, cfg.g.per2};
     carve_hierarchy<T>(c, s.h, cfg.d.ndim, cfg.d.n, per, cfg.nlev, cfg.d.prec == WL_MIXED);
     s.red.slots = reduce_slots_for(cfg.g);
-    s.red.partial = c.take<double>(2 * s.red.slots);
-    s.red.result = c.take<double>(8);
+    s.red.partial = c.take<double>(4 * s.red.slots);
+    s.red.result = c.take<double>(16);
     s.scal = c.take<double>(4);
     if (cfg.d.prec == WL_MIXED) {
         for (int i = 0; i < 3; ++i) s.mix.L[i] = c.take<double>(N);
         s.mix.inner = cfg.d.inner_vcycles;
         s.p64 = c.take<double>(N);
         s.sigma64 = c.take<double>(N);
+    }
+    if (cfg.d.tape_steps > 0) {
+        if (!s.adj) s.adj = new AdjointWS<T>;
+        AdjointWS<T>& A = *s.adj;
+        A.cap = cfg.d.tape_steps;
+        delete[] A.tape;
+        A.tape = new TapeSlot<T>[A.cap];
+        const size_t P = cfg.outflow ? cfg.P : 1;
+        for (int q = 0; q < A.cap; ++q) {
+            TapeSlot<T>& t = A.tape[q];
+            for (int i = 0; i < 3; ++i) {
+                t.un[i] = c.take<T>(N);
+                t.u1[i] = c.take<T>(N);
+                t.f1[i] = c.take<T>(N);
+                t.f2[i] = c.take<T>(N);
+            }
+            t.outn = c.take<T>(P);
+            t.out1 = c.take<T>(P);
+            t.fo1 = c.take<T>(P);
+            t.fo2 = c.take<T>(P);
+            t.p1 = c.take<T>(N);
+            t.p2 = c.take<T>(N);
+            t.dt = 0.0;
+        }
+        A.pg = pad_grid(cfg.g);
+        const size_t NP = pad_cells(A.pg);
+        for (int i = 0; i < 3; ++i) {
+            A.pad[i] = c.take<T>(NP);
+            A.ub[i] = c.take<T>(N);
+            A.u1b[i] = c.take<T>(N);
+            A.unb[i] = c.take<T>(N);
+            A.gb[i] = c.take<T>(N);
+            A.fb[i] = c.take<T>(N);
+            A.Rb[i] = c.take<T>(N);
+            A.Lb[i] = c.take<T>(N);
+            A.mu0b[i] = c.take<T>(N);
+        }
+        for (int i = 0; i < 9; ++i) A.mu1nb[i] = c.take<T>(N);
+        A.uob = c.take<T>(P);
+        A.u1ob = c.take<T>(P);
+        A.unob = c.take<T>(P);
+        A.fob = c.take<T>(P);
+        A.dummy = c.take<T>(P);
+        A.rhs = c.take<T>(N);
+        A.sbar = c.take<T>(N);
+        A.pbar = c.take<T>(N);
+        if (cfg.d.prec == WL_MIXED) {
+            A.rhs64 = c.take<double>(N);
+            A.x64 = c.take<double>(N);
+        }
+        A.part4 = c.take<double>(4 * s.red.slots);
+        A.res = c.take<double>(16);
     }
 }
 
@@ -255,6 +363,24 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
     const int S = s.S;
     const int A = (S + 1) % 3, B = (S + 2) % 3;
     const int PS = s.PS, P1 = (PS + 1) % 3, P2 = (PS + 2) % 3;
+    TapeSlot<T>* tp = nullptr;
+    if (s.adj && s.adj->recording && s.adj->count < s.adj->cap) {
+        tp = &s.adj->tape[s.adj->count];
+        tp->dt = dt;
+    }
+    auto rec = [&](T* dst, const T* src, size_t n) -> wl_status {
+        if (!dst || !src || n == 0) return WL_OK;
+        WL_CHECK_HIP(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToDevice, st));
+        return WL_OK;
+    };
+    auto rec3 = [&](T* const* dst, T* const* src) -> wl_status {
+        for (int i = 0; i < 3; ++i) WL_TRY(rec(dst[i], src[i], c.N));
+        return WL_OK;
+    };
+    if (tp) {
+        WL_TRY(rec3(tp->un, s.vel[S]));
+        if (c.outflow) WL_TRY(rec(tp->outn, s.plane[PS], c.P));
+    }
     const T* un[3] = {s.vel[S][0], s.vel[S][1], s.vel[S][2]};
     wl_status worst = WL_OK;
     SolveResult r1, r2;
@@ -266,6 +392,10 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
         if (c.outflow)
             WL_TRY(ns_outflow<T>(c.g, s.vel[S][0], s.plane[PS], s.plane[PS], s.vel[A][0],
                                  T(c.d.U[0]), false, dt_dev, s.plane[P1], st));
+        if (tp) {
+            WL_TRY(rec3(tp->f1, s.vel[A]));
+            if (c.outflow) WL_TRY(rec(tp->fo1, s.plane[P1], c.P));
+        }
         int us = A;
         if (c.body) {
             T* o[3] = {s.vel[B][0], s.vel[B][1], s.vel[B][2]};
@@ -280,11 +410,16 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
         wl_status rc = pressure_solve(s, 1.0, dt, st, &r1);
         if (rc == WL_ERR_NOT_CONVERGED) worst = rc;
         else if (rc != WL_OK) return rc;
+        if (tp) WL_TRY(rec(tp->p1, s.p, c.N));
         T* o[3] = {s.vel[us][0], s.vel[us][1], s.vel[us][2]};
         WL_TRY(ns_project<T>(V, s.p, pc, c.unif, 1.0, dt_dev, o, false, nullptr, ap, st));
         // stage result now in set `us`; the remaining set is free
         const int u1 = us;
         const int fr = (u1 == A) ? B : A;
+        if (tp) {
+            WL_TRY(rec3(tp->u1, s.vel[u1]));
+            if (c.outflow) WL_TRY(rec(tp->out1, s.plane[P1], c.P));
+        }
         // ---- corrector (c = 1/2)
         T* f2[3] = {s.vel[fr][0], s.vel[fr][1], s.vel[fr][2]};
         WL_TRY(ns_momentum<T>(field_of(s, u1, s.plane[P1]), un, f2, T(c.d.nu), true, ap, dt_dev,
@@ -292,6 +427,10 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
         if (c.outflow)
             WL_TRY(ns_outflow<T>(c.g, s.vel[u1][0], s.plane[P1], s.plane[PS], s.vel[fr][0],
                                  T(c.d.U[0]), true, dt_dev, s.plane[P2], st));
+        if (tp) {
+            WL_TRY(rec3(tp->f2, s.vel[fr]));
+            if (c.outflow) WL_TRY(rec(tp->fo2, s.plane[P2], c.P));
+        }
         int us2 = fr;
         if (c.body) {
             T* o2[3] = {s.vel[S][0], s.vel[S][1], s.vel[S][2]};
@@ -306,6 +445,7 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
         rc = pressure_solve(s, 0.5, dt, st, &r2);
         if (rc == WL_ERR_NOT_CONVERGED) worst = rc;
         else if (rc != WL_OK) return rc;
+        if (tp) WL_TRY(rec(tp->p2, s.p, c.N));
         int dest = (us2 == S) ? u1 : S;
         T* o3[3] = {s.vel[dest][0], s.vel[dest][1], s.vel[dest][2]};
         WL_TRY(ns_project<T>(V2, s.p, pc, c.unif, 0.5, dt_dev, o3, true, s.red.partial, ap, st));
@@ -321,6 +461,7 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
     s.dt_cur = 1 - s.dt_cur;
     s.cfl_valid = true;
     s.t += dt;
+    if (tp) s.adj->count += 1;
     if (stats) {
         stats->dt = dt;
         stats->t = s.t;
@@ -331,6 +472,198 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
         stats->resid[1] = 0.5 * dt * std::sqrt(r2.r2 / na);
     }
     return worst;
+}
+
+// Adjoint Poisson solve  A sbar = rhs  (treated as exact: same hierarchy,
+// tight relative tolerance).
+template <typename T>
+static wl_status adj_solve(SimImpl<T>& s, hipStream_t st) {
+    AdjointWS<T>& A = *s.adj;
+    const SimConfig& c = s.cfg;
+    SolveResult r;
+    wl_status rc;
+    if (c.d.prec == WL_MIXED) {
+        if constexpr (sizeof(T) == 4) {
+            WL_TRY((convert<float, double>(A.rhs, A.rhs64, c.N, st)));
+            WL_TRY(fill<double>(A.x64, c.N, 0.0, st));
+            rc = mg_solve_mixed(s.h, s.mix, s.red, A.x64, A.rhs64, 1e-10, 0.0, 400, st, &r);
+            if (rc != WL_OK && rc != WL_ERR_NOT_CONVERGED) return rc;
+            WL_TRY((convert<double, float>(A.x64, A.sbar, c.N, st)));
+            return WL_OK;
+        }
+        return invalid("mixed precision needs FP32 fields");
+    }
+    WL_TRY(fill<T>(A.sbar, c.N, T(0), st));
+    rc = mg_solve<T>(s.h, s.red, A.sbar, A.rhs, sizeof(T) == 8 ? 1e-11 : 1e-6, 0.0,
+                     sizeof(T) == 8 ? 400 : 60, st, &r, false);
+    if (rc != WL_OK && rc != WL_ERR_NOT_CONVERGED) return rc;
+    return WL_OK;
+}
+
+// Adjoint of one projected stage: u = g - coef L G p, p = A^+ div(g)/coef
+// (coef = c dt), outflow plane = the exit-flux-balanced stage plane.  In: the
+// adjoint of the stage result (faces ubar, plane uoutb) and of its pressure
+// (pbar, may be null).  Out: A.fb / A.fob = adjoint of the stage field before
+// BDIM; geometry adjoints accumulate into A.Lb, A.mu0b, A.mu1nb.
+template <typename T>
+static wl_status adj_stage_projection(SimImpl<T>& s, T* const ubar[3], const T* uoutb, const T* pbar,
+                                      const T* p, T* const f[3], const T* fo, double coef,
+                                      hipStream_t st) {
+    AdjointWS<T>& A = *s.adj;
+    const SimConfig& c = s.cfg;
+    const Grid& g = c.g;
+    T* L[3] = {s.h.lev[0].L[0], s.h.lev[0].L[1], s.h.lev[0].L[2]};
+    WL_TRY(adj_proj_rhs<T>(g, pbar, ubar, L, T(1), c.unif, coef, A.rhs, st));
+    WL_TRY(adj_solve(s, st));
+    WL_TRY(adj_proj_update<T>(g, ubar, A.sbar, p, L, T(1), c.unif, coef, A.gb, A.Lb, st));
+    // The stage plane is balanced (exit flux) before BDIM and the divergence
+    // read it, so both of their plane adjoints go through the balance's
+    // transpose: collect BDIM's share first, then add the divergence's and
+    // remove the mean.
+    if (c.outflow) WL_TRY(fill<T>(A.fob, c.P, T(0), st));
+    if (c.body) {
+        const PadField<T> pf{{A.pad[0], A.pad[1], A.pad[2]}, A.pg};
+        T* m0[3] = {s.mu0[0], s.mu0[1], s.mu0[2]};
+        WL_TRY(adj_bdim<T>(g, A.gb, m0, s.mu1n, pf, st));
+        WL_TRY(adj_faces_axpy<T>(g, A.gb, 0.0, A.fb, false, st));   // fb = 0
+        WL_TRY(adj_fold<T>(field_of(s, 0, static_cast<const T*>(nullptr)), pf, A.fb,
+                           c.outflow ? A.fob : nullptr, st));
+        VelField<T> F = field_of(s, 0, fo);
+        for (int i = 0; i < 3; ++i) F.u[i] = f[i];
+        WL_TRY(adj_bdim_param<T>(F, A.gb, A.mu0b, A.mu1nb, st));
+    } else {
+        WL_TRY(adj_faces_axpy<T>(g, A.gb, 1.0, A.fb, false, st));
+    }
+    if (c.outflow) WL_TRY(adj_plane_proj<T>(g, uoutb, A.sbar, coef, A.fob, st));
+    return WL_OK;
+}
+
+// Adjoint of R'(e)^T applied to Rbar, added into ebar (faces) and eoutb.
+template <typename T>
+static wl_status adj_tendency(SimImpl<T>& s, T* const e[3], const T* eout, T* const ebar[3],
+                              T* eoutb, hipStream_t st) {
+    AdjointWS<T>& A = *s.adj;
+    const SimConfig& c = s.cfg;
+    VelField<T> E = field_of(s, 0, eout);
+    for (int i = 0; i < 3; ++i) E.u[i] = e[i];
+    const PadField<T> pf{{A.pad[0], A.pad[1], A.pad[2]}, A.pg};
+    WL_TRY(adj_flux<T>(E, A.Rb, T(c.d.nu), pf, c.allper, st));
+    WL_TRY(adj_fold<T>(E, pf, ebar, c.outflow ? eoutb : nullptr, st));
+    return WL_OK;
+}
+
+template <typename T>
+static wl_status read_doubles(const double* dev, double* host, int n, hipStream_t st) {
+    WL_CHECK_HIP(hipMemcpyAsync(host, dev, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    WL_CHECK_HIP(hipStreamSynchronize(st));
+    return WL_OK;
+}
+
+// F_x = -sum_active (p - mean p) n_x K(d) of the current pressure.
+template <typename T>
+static wl_status sim_drag(SimImpl<T>& s, double* F, hipStream_t st) {
+    const SimConfig& c = s.cfg;
+    if (!c.body) {
+        *F = 0.0;
+        return WL_OK;
+    }
+    const BodyDev body{c.d.body.kind,
+                       {c.d.body.centre[0], c.d.body.centre[1], c.d.body.centre[2]},
+                       c.d.body.radius,
+                       c.d.body.eps};
+    T* L[3] = {s.h.lev[0].L[0], s.h.lev[0].L[1], s.h.lev[0].L[2]};
+    WL_TRY(drag_sums<T>(c.g, body, s.p, L, s.red.partial, st));
+    WL_TRY(reduce_cols(s.red.partial, s.red.slots, 4, s.red.result + 8, st));
+    double sums[4];
+    WL_TRY(read_doubles<T>(s.red.result + 8, sums, 4, st));
+    const double cnt = sums[3] > 0.0 ? sums[3] : 1.0;
+    *F = -(sums[2] - sums[1] * sums[0] / cnt);
+    return WL_OK;
+}
+
+template <typename T>
+static wl_status sim_step_adjoint(SimImpl<T>& s, const void* ubar_in, double drag_weight,
+                                  void* ubar_out, double* gp, hipStream_t st) {
+    if (!s.adj || s.adj->count <= 0) {
+        set_error("the adjoint tape is empty (record steps with wl_tape_record first)");
+        return WL_ERR_STATE;
+    }
+    AdjointWS<T>& A = *s.adj;
+    const SimConfig& c = s.cfg;
+    const Grid& g = c.g;
+    const size_t N = c.N;
+    TapeSlot<T>& tp = A.tape[--A.count];
+    const double dt = tp.dt;
+    const BodyDev body{c.d.body.kind,
+                       {c.d.body.centre[0], c.d.body.centre[1], c.d.body.centre[2]},
+                       c.d.body.radius,
+                       c.d.body.eps};
+    T* L[3] = {s.h.lev[0].L[0], s.h.lev[0].L[1], s.h.lev[0].L[2]};
+    const T* in = static_cast<const T*>(ubar_in);
+    for (int i = 0; i < c.d.ndim; ++i)
+        WL_CHECK_HIP(hipMemcpyAsync(A.ub[i], in + i * N, N * sizeof(T), hipMemcpyDeviceToDevice, st));
+    if (c.outflow)
+        WL_CHECK_HIP(hipMemcpyAsync(A.uob, in + c.d.ndim * N, c.P * sizeof(T),
+                                    hipMemcpyDeviceToDevice, st));
+    WL_TRY(adj_faces_axpy<T>(g, A.ub, 1.0, A.ub, false, st));  // constants on boundary faces
+    double gsum[4] = {0.0, 0.0, 0.0, 0.0};
+    // ---- drag of the step (corrector pressure p2): pbar and its direct theta term
+    const T* pbar = nullptr;
+    if (c.body && drag_weight != 0.0) {
+        WL_TRY(drag_sums<T>(g, body, tp.p2, L, A.part4, st));
+        WL_TRY(reduce_cols(A.part4, s.red.slots, 4, A.res, st));
+        double sums[4];
+        WL_TRY(read_doubles<T>(A.res, sums, 4, st));
+        const double cnt = sums[3] > 0.0 ? sums[3] : 1.0;
+        WL_TRY(ns_set_scalar(A.res + 8, sums[0] / cnt, st));
+        WL_TRY(ns_set_scalar(A.res + 9, sums[1] / cnt, st));
+        WL_TRY(drag_adj<T>(g, body, tp.p2, L, drag_weight, A.res + 8, A.pbar, A.part4, st));
+        WL_TRY(reduce_cols(A.part4, s.red.slots, 4, A.res, st));
+        double dg[4];
+        WL_TRY(read_doubles<T>(A.res, dg, 4, st));
+        for (int q = 0; q < 4; ++q) gsum[q] += dg[q];
+        pbar = A.pbar;
+    }
+    // ---- corrector projection (c = 1/2) and BDIM: fb, fob
+    WL_TRY(adj_stage_projection<T>(s, A.ub, A.uob, pbar, tp.p2, tp.f2, tp.fo2, 0.5 * dt, st));
+    // ---- corrector stage f2 = (u^n + u1)/2 + dt/2 R(u1)
+    WL_TRY(adj_faces_axpy<T>(g, A.fb, 0.5, A.unb, false, st));
+    WL_TRY(adj_faces_axpy<T>(g, A.fb, 0.5, A.u1b, false, st));
+    WL_TRY(adj_faces_axpy<T>(g, A.fb, 0.5 * dt, A.Rb, false, st));
+    if (c.outflow) {
+        WL_TRY(fill<T>(A.unob, c.P, T(0), st));
+        WL_TRY(fill<T>(A.u1ob, c.P, T(0), st));
+        WL_TRY(adj_plane_stage<T>(g, A.fob, 0.5, 0.5 * dt, T(c.d.U[0]), A.unob, A.u1ob, A.u1b[0], st));
+        WL_TRY(adj_plane_stage<T>(g, A.fob, 0.5, 0.0, T(c.d.U[0]), A.u1ob, A.dummy, A.u1b[0], st));
+    }
+    WL_TRY(adj_tendency<T>(s, tp.u1, tp.out1, A.u1b, A.u1ob, st));
+    // ---- predictor projection (c = 1) and BDIM
+    WL_TRY(adj_stage_projection<T>(s, A.u1b, A.u1ob, nullptr, tp.p1, tp.f1, tp.fo1, dt, st));
+    // ---- predictor stage f1 = u^n + dt R(u^n)
+    WL_TRY(adj_faces_axpy<T>(g, A.fb, 1.0, A.unb, true, st));
+    WL_TRY(adj_faces_axpy<T>(g, A.fb, dt, A.Rb, false, st));
+    if (c.outflow)
+        WL_TRY(adj_plane_stage<T>(g, A.fob, 1.0, dt, T(c.d.U[0]), A.unob, A.unob, A.unb[0], st));
+    WL_TRY(adj_tendency<T>(s, tp.un, tp.outn, A.unb, A.unob, st));
+    // ---- geometry adjoints -> parameters
+    if (c.body) {
+        WL_TRY(adj_params<T>(g, body, A.Lb, A.mu0b, A.mu1nb, A.part4, st));
+        WL_TRY(reduce_cols(A.part4, s.red.slots, 4, A.res, st));
+        double dg[4];
+        WL_TRY(read_doubles<T>(A.res, dg, 4, st));
+        for (int q = 0; q < 4; ++q) gsum[q] += dg[q];
+    }
+    // ---- output
+    T* out = static_cast<T*>(ubar_out);
+    for (int i = 0; i < c.d.ndim; ++i)
+        WL_CHECK_HIP(hipMemcpyAsync(out + i * N, A.unb[i], N * sizeof(T), hipMemcpyDeviceToDevice, st));
+    if (c.outflow)
+        WL_CHECK_HIP(hipMemcpyAsync(out + c.d.ndim * N, A.unob, c.P * sizeof(T),
+                                    hipMemcpyDeviceToDevice, st));
+    WL_CHECK_HIP(hipStreamSynchronize(st));
+    if (gp)
+        for (int q = 0; q < 4; ++q) gp[q] += gsum[q];
+    return WL_OK;
 }
 
 template <typename T>
@@ -495,6 +828,34 @@ static wl_status poisson_solve_mixed(wl_poisson* ps, const void* coeffs, void* x
     return rc;
 }
 
+// Clear the geometry-adjoint accumulators (the workspace starts uninitialised).
+template <typename T>
+static wl_status adj_clear(SimImpl<T>& s, hipStream_t st) {
+    AdjointWS<T>& A = *s.adj;
+    const size_t N = s.cfg.N;
+    for (int i = 0; i < 3; ++i) {
+        WL_TRY(fill<T>(A.Lb[i], N, T(0), st));
+        WL_TRY(fill<T>(A.mu0b[i], N, T(0), st));
+    }
+    for (int i = 0; i < 9; ++i) WL_TRY(fill<T>(A.mu1nb[i], N, T(0), st));
+    WL_CHECK_HIP(hipStreamSynchronize(st));
+    return WL_OK;
+}
+
+template <typename T>
+static wl_status tape_record(SimImpl<T>& s, int on, hipStream_t st) {
+    if (!s.adj) {
+        set_error("this simulation was created with tape_steps = 0");
+        return WL_ERR_STATE;
+    }
+    s.adj->recording = on != 0;
+    if (on) {
+        s.adj->count = 0;
+        WL_TRY(adj_clear(s, st));
+    }
+    return WL_OK;
+}
+
 }  // namespace wl
 
 using namespace wl;
@@ -596,6 +957,33 @@ wl_status wl_step(wl_sim* sim, double dt, wl_step_stats* stats) {
     if (sim->prec == WL_FP64)
         return sim_step<double>(*static_cast<SimImpl<double>*>(sim->impl), dt, stats, sim->stream);
     return sim_step<float>(*static_cast<SimImpl<float>*>(sim->impl), dt, stats, sim->stream);
+}
+
+wl_status wl_drag(wl_sim* sim, double* Fx) {
+    clear_error();
+    if (!sim || !Fx) return invalid("sim / Fx is NULL");
+    if (sim->prec == WL_FP64)
+        return sim_drag<double>(*static_cast<SimImpl<double>*>(sim->impl), Fx, sim->stream);
+    return sim_drag<float>(*static_cast<SimImpl<float>*>(sim->impl), Fx, sim->stream);
+}
+
+wl_status wl_tape_record(wl_sim* sim, int on) {
+    clear_error();
+    if (!sim) return invalid("sim is NULL");
+    if (sim->prec == WL_FP64)
+        return tape_record<double>(*static_cast<SimImpl<double>*>(sim->impl), on, sim->stream);
+    return tape_record<float>(*static_cast<SimImpl<float>*>(sim->impl), on, sim->stream);
+}
+
+wl_status wl_step_adjoint(wl_sim* sim, const void* ubar_in, double drag_weight, void* ubar_out,
+                          double* g_params) {
+    clear_error();
+    if (!sim || !ubar_in || !ubar_out) return invalid("sim / ubar_in / ubar_out is NULL");
+    if (sim->prec == WL_FP64)
+        return sim_step_adjoint<double>(*static_cast<SimImpl<double>*>(sim->impl), ubar_in,
+                                        drag_weight, ubar_out, g_params, sim->stream);
+    return sim_step_adjoint<float>(*static_cast<SimImpl<float>*>(sim->impl), ubar_in, drag_weight,
+                                   ubar_out, g_params, sim->stream);
 }
 
 wl_status wl_poisson_footprint(int ndim, const int n[3], const int periodic[3], int prec, int levels,

@@ -120,3 +120,30 @@ def test_cylinder_flow_keeps_mirror_symmetry_and_zero_velocity_inside():
     assert np.all(u[0] == 1.0) and np.all(v[:, 0] == 0.0)
     assert sim.uout.sum() == pytest.approx(64.0, rel=1e-13)
     assert 0.05 < st["dt"] < 0.5
+
+
+@pytest.mark.parametrize("n,centre,radius,exact", [
+    ((40, 40, 40), (20.3, 19.8, 20.1), 7.0, 4.0 / 3.0 * math.pi * 7.0 ** 3),
+    ((64, 64), (31.7, 32.2), 10.0, math.pi * 10.0 ** 2),
+])
+def test_drag_of_a_linear_pressure_is_minus_gradient_times_volume(n, centre, radius, exact):
+    """For p = a x the surface integral -oint p n_x dS equals -a V (divergence
+    theorem), whatever the pressure's free constant; the kernel-smoothed sum
+    reproduces it to second order in the band width over the radius.  A
+    pressure even in x about the centre, or independent of x, has zero drag."""
+    from oracle.grid import WALL
+    d = len(n)
+    sim = S.Sim(n, [WALL] * d, [WALL] * d, (0.0,) * d, 0.01,
+                body=dict(centre=centre, radius=radius))
+    X = np.meshgrid(*[np.arange(m) + 0.5 for m in n], indexing="ij")
+    a = 0.37
+    sim.p = a * X[0] + 5.0
+    F = S.drag(sim)
+    # quadrature error O((eps / R)^2): 0.9 % at R = 7 (3D), 0.24 % at R = 10 (2D)
+    assert abs(F - (-a * exact)) <= 0.02 * a * exact
+    from oracle import geometry as G
+    dist, normal = G.sphere_sdf(X, centre, radius)
+    for p in ((X[0] - centre[0]) ** 2, X[1] - 3.0):
+        sim.p = p
+        bound = np.sum(np.abs(p) * np.abs(normal[0]) * G.kernel(dist))
+        assert abs(S.drag(sim)) <= 0.01 * bound
