@@ -214,6 +214,17 @@ wl_status wl_poisson_destroy(wl_poisson* ps);
 wl_status wl_body_coeffs(const wl_body* body, int ndim, const int n[3], const int periodic[3],
                          int prec, void* L_out, void* hip_stream);
 
+/* ---- Execution ----------------------------------------------------------- */
+
+/* Repeated solve bodies (one V-cycle with its residual norm; one
+ * mixed-precision outer iteration) are captured once per solver and solution
+ * array, on a private stream of default priority, and replayed as HIP graphs
+ * on the caller's stream from their second use on (default, enable != 0).
+ * enable = 0 launches every kernel individually.  Results are bitwise the
+ * same either way.  Process-wide; bodies are launched individually while any
+ * multigrid kernel class is timed (wl_profile_enable). */
+wl_status wl_set_graphs(int enable);
+
 /* ---- Kernel timing (measurement support) -------------------------------- */
 
 /* Kernels whose launches can be bracketed by HIP events, to turn algorithmic

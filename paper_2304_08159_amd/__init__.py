@@ -17,7 +17,7 @@ from ._lib import (FIELD_L0, FIELD_MU0_0, FIELD_MU1N, FIELD_P, FIELD_SIGMA, FIEL
                    FIELD_UOUT, INFLOW, OUTFLOW, PERIODIC, WALL, WL_FP32, WL_FP64, WL_MIXED,
                    WlError, check, load)
 
-__all__ = ["Sim", "Poisson", "body_coeffs", "load", "WlError", "WL_FP32", "WL_FP64", "WL_MIXED",
+__all__ = ["Sim", "Poisson", "body_coeffs", "set_graphs", "load", "WlError", "WL_FP32", "WL_FP64", "WL_MIXED",
            "PERIODIC", "INFLOW", "OUTFLOW", "WALL"]
 
 
@@ -176,6 +176,12 @@ class Sim:
               allow=(-3,) if allow_not_converged else ())
         return dict(dt=st.dt, t=st.t, vcycles=(st.vcycles[0], st.vcycles[1]),
                     resid=(st.resid[0], st.resid[1]))
+
+
+def set_graphs(enable=True):
+    """Replay repeated solve bodies as captured HIP graphs (default) or launch
+    every kernel individually; results are bitwise the same."""
+    check(load().wl_set_graphs(1 if enable else 0))
 
 
 def body_coeffs(n, periodic, body=None, prec=WL_FP32, device="cuda"):

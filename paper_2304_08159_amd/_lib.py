@@ -28,7 +28,8 @@ EXPORTS = (
     "wl_sim_footprint", "wl_sim_create", "wl_sim_destroy", "wl_set_field", "wl_get_field",
     "wl_set_time", "wl_step", "wl_drag", "wl_tape_record", "wl_step_adjoint",
     "wl_poisson_footprint", "wl_poisson_create",
-    "wl_poisson_solve", "wl_poisson_destroy", "wl_body_coeffs", "wl_profile_enable",
+    "wl_poisson_solve", "wl_poisson_destroy", "wl_body_coeffs", "wl_set_graphs",
+    "wl_profile_enable",
     "wl_profile_reset",
     "wl_profile_read", "wl_last_error", "wl_version",
 )
@@ -90,6 +91,7 @@ def load():
         "wl_poisson_solve": [vp, vp, vp, vp, f64, i32, ctypes.POINTER(i32), ctypes.POINTER(f64)],
         "wl_poisson_destroy": [vp],
         "wl_body_coeffs": [ctypes.POINTER(Body), i32, ip3, ip3, i32, vp, vp],
+        "wl_set_graphs": [i32],
         "wl_profile_enable": [ctypes.c_uint],
         "wl_profile_reset": [],
         "wl_profile_read": [i32, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_longlong),

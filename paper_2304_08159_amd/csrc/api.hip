@@ -143,6 +143,7 @@ struct SimImpl {
     T* sigma = nullptr;
     T* mu0[3];
     T* mu1n[9];
+    unsigned char* tile_cls = nullptr;  // BDIM tile classes (one per block of the cell tiling)
     Hierarchy<T> h;
     Reduce red;
     double* scal = nullptr;  // [0] dt, [1] dt_next, [2] cfl max
@@ -176,6 +177,7 @@ static void carve_sim(Carver& c, SimImpl<T>& s, const SimConfig& cfg) {
     s.sigma = c.take<T>(N);
     for (int i = 0; i < 3; ++i) s.mu0[i] = c.take<T>(N);
     for (int i = 0; i < 9; ++i) s.mu1n[i] = c.take<T>(N);
+    s.tile_cls = c.take<unsigned char>(reduce_slots_for(cfg.g));
     const int per[3] = {cfg.g.per0, cfg.g.per1, cfg.g.per2};
     carve_hierarchy<T>(c, s.h, cfg.d.ndim, cfg.d.n, per, cfg.nlev, cfg.d.prec == WL_MIXED);
     s.red.slots = reduce_slots_for(cfg.g);
@@ -273,6 +275,15 @@ struct wl_poisson {
 namespace wl {
 
 template <typename T>
+static BdimFields<T> bdim_fields(const SimImpl<T>& s) {
+    BdimFields<T> b;
+    for (int i = 0; i < 3; ++i) b.mu0[i] = s.mu0[i];
+    for (int i = 0; i < 9; ++i) b.mu1n[i] = s.mu1n[i];
+    b.cls = s.tile_cls;
+    return b;
+}
+
+template <typename T>
 static wl_status sim_init(SimImpl<T>& s, hipStream_t st) {
     const SimConfig& c = s.cfg;
     const size_t N = c.N;
@@ -289,6 +300,7 @@ static wl_status sim_init(SimImpl<T>& s, hipStream_t st) {
     }
     for (int i = 0; i < 9; ++i) M.mu1n[i] = s.mu1n[i];
     WL_TRY(ns_measure<T>(c.g, body, c.d.bc_lo, M, st));
+    if (c.body) WL_TRY(ns_tile_class<T>(c.g, bdim_fields(s), s.tile_cls, st));
     s.h.lev[0].uniform = c.unif ? 1 : 0;
     s.h.lev[0].Lc = T(1);
     WL_TRY(mg_coarsen_all<T>(s.h, st));
@@ -353,8 +365,7 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
         WL_TRY(ns_cfl<T>(field_of(s, s.S, s.plane[s.PS]), ap, s.red.partial, st));
         WL_TRY(ns_dt_from_max(s.red.partial, s.red.slots, c.d.cfl, 2.0 * c.d.ndim * c.d.nu, dt_dev,
                               s.scal + 2, st));
-        WL_CHECK_HIP(hipMemcpyAsync(&dt, dt_dev, sizeof(double), hipMemcpyDeviceToHost, st));
-        WL_CHECK_HIP(hipStreamSynchronize(st));
+        WL_TRY(host_read(s.red, dt_dev, 1, &dt, st));
     }
     if (!(dt > 0.0) || !std::isfinite(dt)) {
         set_error("time step is not positive (zero velocity and zero viscosity?)");
@@ -399,10 +410,7 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
         int us = A;
         if (c.body) {
             T* o[3] = {s.vel[B][0], s.vel[B][1], s.vel[B][2]};
-            BdimFields<T> bf;
-            for (int i = 0; i < 3; ++i) bf.mu0[i] = s.mu0[i];
-            for (int i = 0; i < 9; ++i) bf.mu1n[i] = s.mu1n[i];
-            WL_TRY(ns_bdim<T>(field_of(s, A, s.plane[P1]), bf, o, st));
+            WL_TRY(ns_bdim<T>(field_of(s, A, s.plane[P1]), bdim_fields(s), o, st));
             us = B;
         }
         const VelField<T> V = field_of(s, us, s.plane[P1]);
@@ -434,10 +442,7 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
         int us2 = fr;
         if (c.body) {
             T* o2[3] = {s.vel[S][0], s.vel[S][1], s.vel[S][2]};
-            BdimFields<T> bf;
-            for (int i = 0; i < 3; ++i) bf.mu0[i] = s.mu0[i];
-            for (int i = 0; i < 9; ++i) bf.mu1n[i] = s.mu1n[i];
-            WL_TRY(ns_bdim<T>(field_of(s, fr, s.plane[P2]), bf, o2, st));
+            WL_TRY(ns_bdim<T>(field_of(s, fr, s.plane[P2]), bdim_fields(s), o2, st));
             us2 = S;
         }
         const VelField<T> V2 = field_of(s, us2, s.plane[P2]);
@@ -455,9 +460,7 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
         s.S = dest;
         s.PS = P2;
     }
-    WL_CHECK_HIP(hipMemcpyAsync(&s.dt_next_host, s.scal + (1 - s.dt_cur), sizeof(double),
-                                hipMemcpyDeviceToHost, st));
-    WL_CHECK_HIP(hipStreamSynchronize(st));
+    WL_TRY(host_read(s.red, s.scal + (1 - s.dt_cur), 1, &s.dt_next_host, st));
     s.dt_cur = 1 - s.dt_cur;
     s.cfl_valid = true;
     s.t += dt;

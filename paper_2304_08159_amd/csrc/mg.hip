@@ -1,3 +1,5 @@
+#include <chrono>
+#include <algorithm>
 // Matrix-free geometric multigrid for the BDIM-modified pressure Poisson
 // system (paper Sec. 2: GMG with a solution time linear in the cell count;
 // the operator is fixed by the gradient loop u[I,i] -= coeff*(p[I]-p[I-del(i)])).
@@ -149,26 +151,35 @@ __global__ __launch_bounds__(kBlock) void k_smooth(TileDev TL, Grid g, XAccess<T
     }
 }
 
-// Coarse right-hand side = sum of the 2^d child residuals r = b - A x.
+// Coarse right-hand side = sum of the 2^d child residuals r = b - A x.  The
+// launch covers the fine grid (even z chunks): a thread adds the residuals of
+// its z pair, the x pair is combined across neighbouring lanes and the y
+// pair through LDS, and the thread at the even (i, j) corner writes the
+// coarse cell.
 template <typename T, bool UNIF>
 __global__ __launch_bounds__(kBlock) void k_resid_restrict(TileDev TL, Grid g, Grid gc, XAccess<T, XM_PLAIN> X,
                                                            Coeffs<T> C, const T* __restrict__ b,
                                                            T* __restrict__ bc) {
-    const Span sp = tile_span(TL, gc.n0, gc.n1, gc.n2);
-    const int ic = sp.i, jc = sp.j;
-    if (ic >= gc.n0 || jc >= gc.n1) return;
-    for (int kc = sp.z0; kc < sp.z1; ++kc) {
+    __shared__ T sy[kBlock];
+    const Span sp = tile_span(TL, g.n0, g.n1, g.n2);
+    const int i = sp.i, j = sp.j;
+    const bool valid = i < g.n0 && j < g.n1;
     const int fz = (g.n2 > gc.n2) ? 2 : 1;
-    T sum = T(0);
-    for (int dz = 0; dz < fz; ++dz)
-        for (int dy = 0; dy < 2; ++dy)
-            for (int dx = 0; dx < 2; ++dx) {
-                const int i = 2 * ic + dx, j = 2 * jc + dy, k = fz * kc + dz;
+    const int t = threadIdx.x, bx = 1 << TL.lbx;
+    for (int k = sp.z0; k < sp.z1; k += fz) {
+        T r = T(0);
+        if (valid)
+            for (int dz = 0; dz < fz; ++dz) {
                 T xI, Ax, D;
-                apply_row<T, XM_PLAIN, UNIF>(g, X, C, i, j, k, xI, Ax, D);
-                sum += b[cid(g, i, j, k)] - Ax;
+                apply_row<T, XM_PLAIN, UNIF>(g, X, C, i, j, k + dz, xI, Ax, D);
+                r += b[cid(g, i, j, k + dz)] - Ax;
             }
-    bc[cid(gc, ic, jc, kc)] = sum;
+        r += __shfl_xor(r, 1, 64);
+        sy[t] = r;
+        __syncthreads();
+        if (valid && (i & 1) == 0 && (j & 1) == 0)
+            bc[cid(gc, i >> 1, j >> 1, k / fz)] = r + sy[t + bx];
+        __syncthreads();
     }
 }
 
@@ -190,6 +201,58 @@ __global__ __launch_bounds__(kBlock) void k_sum_active(TileDev TL, Grid g, Coeff
     }
     s = block_sum(s, lds);
     if (threadIdx.x == 0 && threadIdx.y == 0) partial[block_linear()] = s;
+}
+
+// Copies n doubles to pinned host memory, then (after a system-scope fence)
+// the sequence number the host is waiting for.  One thread.
+__global__ void k_publish(const double* __restrict__ src, int n, double* dst, unsigned* seqw,
+                          unsigned q) {
+    for (int k = 0; k < n; ++k) dst[k] = src[k];
+    __threadfence_system();
+    __hip_atomic_store(seqw, q, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+HostMailbox::~HostMailbox() {
+    if (vals) (void)hipHostFree(vals);
+}
+
+wl_status host_read(Reduce& red, const double* src, int n, double* out, hipStream_t s) {
+    HostMailbox& mb = red.mb;
+    if (n < 0 || n > 8) {
+        set_error("host_read: at most 8 values");
+        return WL_ERR_INVALID_ARG;
+    }
+    if (!mb.vals) {
+        void* p = nullptr;
+        WL_CHECK_HIP(hipHostMalloc(&p, 128, hipHostMallocCoherent | hipHostMallocMapped));
+        mb.vals = static_cast<double*>(p);
+        mb.seqw = reinterpret_cast<unsigned*>(mb.vals + 8);
+        *mb.seqw = 0u;
+        void* d = nullptr;
+        WL_CHECK_HIP(hipHostGetDevicePointer(&d, p, 0));
+        mb.vals_dev = static_cast<double*>(d);
+        mb.seqw_dev = reinterpret_cast<unsigned*>(mb.vals_dev + 8);
+    }
+    const unsigned q = ++mb.seq;
+    k_publish<<<1, 1, 0, s>>>(src, n, mb.vals_dev, mb.seqw_dev, q);
+    WL_CHECK_LAUNCH();
+    // Poll for up to 20 ms (a step's solves publish every few hundred
+    // microseconds), then let HIP wait and report any kernel failure.
+    const auto t0 = std::chrono::steady_clock::now();
+    unsigned spins = 0;
+    while (__atomic_load_n(mb.seqw, __ATOMIC_ACQUIRE) != q) {
+        if ((++spins & 1023u) == 0u &&
+            std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(20)) {
+            WL_CHECK_HIP(hipStreamSynchronize(s));
+            if (__atomic_load_n(mb.seqw, __ATOMIC_ACQUIRE) != q) {
+                set_error("device result did not arrive in the host mailbox");
+                return WL_ERR_HIP;
+            }
+            break;
+        }
+    }
+    for (int k = 0; k < n; ++k) out[k] = mb.vals[k];
+    return WL_OK;
 }
 
 // out[c] = sum over slots of partial[slot*ncomp + c] in slot order; then
@@ -534,10 +597,25 @@ static wl_status smooth(const Level<T>& L, const T* xin, const T* xc, const Grid
     return WL_OK;
 }
 
+// launch_for over a fine level with its z chunk rounded up to even, so that
+// every chunk holds whole z pairs of a restriction.
+static Launch launch_pairs(const Grid& g) {
+    Launch l = launch_for(g.n0, g.n1, g.n2);
+    if (g.n2 > 1 && (l.td.zc & 1)) {
+        l.td.zc += 1;
+        const unsigned cols = unsigned(l.td.tx) * unsigned(l.td.ty);
+        const unsigned chunks = unsigned((g.n2 + l.td.zc - 1) / l.td.zc);
+        l.td.nb = cols * chunks;
+        l.td.remap = (l.td.nb % 8u == 0u) ? 1 : 0;
+        l.grid = dim3(l.td.nb, 1, 1);
+    }
+    return l;
+}
+
 template <typename T>
 static wl_status resid_restrict(const Level<T>& L, const T* x, Level<T>& C, hipStream_t s,
                                 int prof = -1) {
-    const Launch ln = launch_for(C.g.n0, C.g.n1, C.g.n2);
+    const Launch ln = launch_pairs(L.g);
     ProfScope ps(prof, s, cells(L.g));
     XAccess<T, XM_PLAIN> X{x, nullptr, 0, 0};
     if (L.uniform)
@@ -641,9 +719,7 @@ static wl_status vcycle_rest(Hierarchy<T>& h, hipStream_t s) {
 }
 
 static wl_status read_norms(Reduce& red, double* host2, hipStream_t s) {
-    WL_CHECK_HIP(hipMemcpyAsync(host2, red.result, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-    WL_CHECK_HIP(hipStreamSynchronize(s));
-    return WL_OK;
+    return host_read(red, red.result, 2, host2, s);
 }
 
 template <typename T>
@@ -697,13 +773,17 @@ wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, d
     double r2 = nr[0];
     auto done = [&](double q) { return q <= tol * tol * b2 || q <= abs_r2; };
     int k = 0;
-    while (!done(r2) && k < max_vcycles) {
-        WL_TRY(vcycle_rest(h, s));
-        ++k;
+    // one V-cycle and the residual norms it leaves (replayed as a graph)
+    auto body = [&](hipStream_t q) -> wl_status {
+        WL_TRY(vcycle_rest(h, q));
         WL_TRY((smooth<T, XM_PLAIN, true, false>(F, x, nullptr, nullptr, F.b, w, F.x[1],
-                                                 red.partial, nullptr, nullptr, s,
+                                                 red.partial, nullptr, nullptr, q,
                                                  WL_PROF_SMOOTH_NORM)));
-        WL_TRY(reduce<T>(red, ln.nblocks(), 2, 1.0, red.result, s));
+        return reduce<T>(red, ln.nblocks(), 2, 1.0, red.result, q);
+    };
+    while (!done(r2) && k < max_vcycles) {
+        WL_TRY(run_cached(h.graphs, x, s, body));
+        ++k;
         WL_TRY(read_norms(red, nr, s));
         if (!std::isfinite(nr[0])) {
             set_error("non-finite residual norm in the pressure solve");
@@ -745,11 +825,33 @@ wl_status mg_solve_mixed(Hierarchy<float>& h32, const Mixed64& m, Reduce& red, d
     int inner_total = 0;
     double b2 = -1.0, r2 = 0.0;
     auto done = [&](double q) { return q <= tol * tol * b2 || q <= abs_r2; };
-    for (;;) {
+    // FP64 residual (projected into the FP32 fine RHS) and its norms
+    auto resid = [&](hipStream_t q) -> wl_status {
         XAccess<double, XM_PLAIN> X{x, nullptr, 0, 0};
-        k_resid64<<<ln.grid, ln.block, 0, s>>>(ln.td, g, X, C64, b, red.result + 5, F.b, red.partial);
+        k_resid64<<<ln.grid, ln.block, 0, q>>>(ln.td, g, X, C64, b, red.result + 5, F.b, red.partial);
         WL_CHECK_LAUNCH();
-        WL_TRY(reduce<double>(red, ln.nblocks(), 2, 1.0, red.result, s));
+        return reduce<double>(red, ln.nblocks(), 2, 1.0, red.result, q);
+    };
+    // `count` inner FP32 V-cycles on A e = r from e = 0, x += e in FP64, and
+    // the next residual
+    auto outer = [&](hipStream_t q, int count) -> wl_status {
+        for (int v = 0; v < count; ++v) {
+            if (v == 0)
+                WL_TRY((smooth<float, XM_ZERO, false, false>(F, nullptr, nullptr, nullptr, F.b, w,
+                                                             F.x[1], nullptr, nullptr, nullptr,
+                                                             q)));
+            else
+                WL_TRY((smooth<float, XM_PLAIN, false, false>(F, F.x[0], nullptr, nullptr, F.b, w,
+                                                              F.x[1], nullptr, nullptr, nullptr,
+                                                              q)));
+            WL_TRY(vcycle_rest(h32, q));
+        }
+        k_axpy64<<<unsigned((N + kBlock - 1) / kBlock), kBlock, 0, q>>>(N, F.x[0], x);
+        WL_CHECK_LAUNCH();
+        return resid(q);
+    };
+    WL_TRY(resid(s));
+    for (;;) {
         double nr[2];
         WL_TRY(read_norms(red, nr, s));
         if (!std::isfinite(nr[0]) || !std::isfinite(nr[1])) {
@@ -769,20 +871,12 @@ wl_status mg_solve_mixed(Hierarchy<float>& h32, const Mixed64& m, Reduce& red, d
         }
         r2 = nr[0];
         if (done(r2) || inner_total >= max_vcycles) break;
-        // inner FP32 V-cycles on A e = r from e = 0
-        for (int v = 0; v < m.inner && inner_total < max_vcycles; ++v, ++inner_total) {
-            if (v == 0)
-                WL_TRY((smooth<float, XM_ZERO, false, false>(F, nullptr, nullptr, nullptr, F.b, w,
-                                                             F.x[1], nullptr, nullptr, nullptr,
-                                                             s)));
-            else
-                WL_TRY((smooth<float, XM_PLAIN, false, false>(F, F.x[0], nullptr, nullptr, F.b, w,
-                                                              F.x[1], nullptr, nullptr, nullptr,
-                                                              s)));
-            WL_TRY(vcycle_rest(h32, s));
-        }
-        k_axpy64<<<unsigned((N + kBlock - 1) / kBlock), kBlock, 0, s>>>(N, F.x[0], x);
-        WL_CHECK_LAUNCH();
+        const int count = std::min(m.inner, max_vcycles - inner_total);
+        if (count == m.inner)
+            WL_TRY(run_cached(h32.graphs, x, s, [&](hipStream_t q) { return outer(q, count); }));
+        else
+            WL_TRY(outer(s, count));
+        inner_total += count;
     }
     res->vcycles = inner_total;
     res->rel = std::sqrt(r2 / b2);

@@ -84,24 +84,55 @@ __global__ __launch_bounds__(kBlock) void k_momentum(TileDev TL, VelField<T> E, 
 
 // ---------------------------------------------------------------------------
 // LDS-tiled convection-diffusion for FP32 3D grids.  A block owns a 64 x 4
-// column of cells and marches through a chunk of z planes.  Planes z-2..z+2
-// of all three components (with a two-cell x/y halo) sit in an LDS ring; the
-// next plane is fetched into registers while the current one is computed.
-// Every face flux is evaluated once: x- and y-face fluxes of the plane go
-// through LDS, the z-face flux of the upper face is kept in a register and
-// reused as the lower face of the next plane.  Block ids are remapped so that
-// each XCD (blocks are dealt round-robin to the 8 XCDs) walks a contiguous
-// range of tiles and shares halo rows through its own L2.
+// column of cells and marches through a chunk of z planes.  Planes z-1, z,
+// z+1 of all three components (with a two-cell x/y halo) sit in a 3-plane LDS
+// ring; the thread's own column of planes z-2 .. z+2 is kept in registers for
+// the z stencil.  Planes are fetched two ahead into alternating register sets
+// (the loop is unrolled by two so no copy waits on a load).  Every face flux
+// is evaluated once: a thread computes the lower x, y and z faces of its cell;
+// the tile's extra x column goes to wave 1 and its extra y row to wave 2, and
+// the upper x / y fluxes a cell needs are read from LDS, the upper z flux is
+// kept for the next plane.  Fluxes are evaluated doubled (sum of the two
+// advecting velocities instead of their mean, 2 nu) and the step uses dt/2:
+// scaling by two is exact, so this changes no bit of the result.  Block ids
+// are remapped so that each XCD (blocks are dealt round-robin to the 8 XCDs)
+// walks a contiguous range of tiles and shares halo rows through its L2.
 namespace {
 constexpr int MT_X = 64, MT_Y = 4;
 constexpr int MT_LX = MT_X + 4, MT_LY = MT_Y + 4, MT_PL = MT_LX * MT_LY;
-constexpr int MT_NP = 5;
-constexpr int MT_LOADS = (MT_PL + kBlock - 1) / kBlock;
+constexpr int MT_NP = 3;
+constexpr int MT_HALO = MT_PL - MT_X * MT_Y;
+constexpr int MT_LOADS = 1 + (MT_HALO + kBlock - 1) / kBlock;
+static_assert(kBlock == MT_X * MT_Y, "one thread per tile column");
 }  // namespace
 
 __device__ __forceinline__ int wrapi(int a, int n) {
     int r = a % n;
     return r < 0 ? r + n : r;
+}
+
+// LDS position (Y * MT_LX + X) of load slot k of thread t, -1 if unused.
+// Slot 0 is the thread's own cell; the halo (rows 0, 1 and MT_LY-2, MT_LY-1
+// in full, then columns 0, 1, MT_LX-2, MT_LX-1 of the tile rows) is dealt
+// out over the following slots in that order, so consecutive threads read
+// consecutive x.
+__device__ __forceinline__ int mt_pos(int t, int k) {
+    if (k == 0) return ((t >> 6) + 2) * MT_LX + (t & 63) + 2;
+    const int h = t + (k - 1) * kBlock;
+    if (h >= MT_HALO) return -1;
+    if (h < 4 * MT_LX) {
+        const int r = h / MT_LX, x = h - r * MT_LX;
+        return (r < 2 ? r : r + MT_Y) * MT_LX + x;
+    }
+    const int q = h - 4 * MT_LX, r = q >> 2, c = q & 3;
+    return (r + 2) * MT_LX + (c < 2 ? c : MT_X + c);
+}
+
+// Ghost-rule read, kept out of line: the tiled kernel takes it only for halo
+// positions outside the grid, and inlining it at every load site would tie
+// up registers for the whole z march.
+__device__ __noinline__ float ghost_fetch(const VelField<float>* V, int c, int gx, int gy, int gz) {
+    return vget<float, false>(*V, c, gx, gy, gz);
 }
 
 template <bool ALLPER>
@@ -113,15 +144,18 @@ __device__ __forceinline__ float tile_fetch(const VelField<float>& V, int c, int
     return vget<float, false>(V, c, gx, gy, gz);
 }
 
-__device__ __forceinline__ float flux1(float um2, float um1, float u0, float up1, float ubar,
-                                       float nu) {
-    const bool pos = ubar >= 0.f;
+// Twice the flux through a face of a momentum control volume: s is the sum of
+// the two advecting velocities on the face, nu2 = 2 nu; the face value is the
+// kappa = 1/3 upwind-biased interpolant bounded by the median-form limiter.
+__device__ __forceinline__ float flux2(float um2, float um1, float u0, float up1, float s,
+                                       float nu2) {
+    const bool pos = s >= 0.f;
     const float cu = pos ? um1 : u0;
     const float bd = pos ? u0 : um1;
     const float au = pos ? um2 : up1;
-    const float phik = (5.f * cu + 2.f * bd - au) * (1.f / 6.f);
-    const float phi = med3(phik, cu, med3(2.f * cu - au, cu, bd));
-    return ubar * phi - nu * (u0 - um1);
+    const float phik = fmaf(5.f, cu, fmaf(2.f, bd, -au)) * (1.f / 6.f);
+    const float phi = med3(phik, cu, med3(fmaf(2.f, cu, -au), cu, bd));
+    return fmaf(s, phi, -(nu2 * (u0 - um1)));
 }
 
 template <bool ALLPER, bool CORR>
@@ -147,25 +181,34 @@ __global__ __launch_bounds__(kBlock) void k_momentum_tiled(VelField<float> E,
     const int x0 = tix * MT_X, y0 = tiy * MT_Y, z0 = ch * tm.zc;
     const int z1 = min(z0 + tm.zc, g.n2);
     const int t = threadIdx.x, tx = t & 63, ty = t >> 6;
-    const int lx = tx + 2, ly = ty + 2;
-    const float dt = float(*dt_dev);
+    const int lx = tx + 2, ly = ty + 2, own = ly * MT_LX + lx;
+    const float hdt = 0.5f * float(*dt_dev);
+    const float nu2 = 2.f * nu;
     const int gx = x0 + tx, gy = y0 + ty;
     const bool inside = gx < g.n0 && gy < g.n1;
     const float* un[3] = {un0, un1, un2};
     float* fo[3] = {f0, f1, f2};
-    auto slot = [](int z) { return wrapi(z, MT_NP); };
-    auto U = [&](int c, int sl, int x, int y) -> float { return sU[c][sl][y * MT_LX + x]; };
-    // halo positions of this thread's loads; with periodic wrap their x/y
-    // offsets are fixed for the whole column, so they are computed once
+    // extra flux items: the tile's upper x column (wave 1) and upper y row (wave 2)
+    const bool xtra_x = t >= 64 && t < 64 + MT_Y;
+    const bool xtra_y = t >= 128 && t < 192;
+    const int xx_pos = (t - 64 + 2) * MT_LX + MT_X + 2;  // (X = 66, Y = row + 2)
+    const int xy_pos = (MT_Y + 2) * MT_LX + (t - 128) + 2;
+    // load slots; with periodic wrap the x/y part of each global offset is
+    // fixed for the whole column and computed once
+    int lpos[MT_LOADS];
     unsigned offxy[MT_LOADS];
     int pxs[MT_LOADS], pys[MT_LOADS];
+    bool inxy[MT_LOADS];  // x/y position inside the grid (no ghost rule needed)
 #pragma unroll
     for (int k = 0; k < MT_LOADS; ++k) {
-        const int p = t + k * kBlock;
-        pxs[k] = x0 - 2 + p % MT_LX;
-        pys[k] = y0 - 2 + p / MT_LX;
+        lpos[k] = mt_pos(t, k);
+        const int p = lpos[k] < 0 ? 0 : lpos[k];
+        const int Y = p / MT_LX;
+        pxs[k] = x0 - 2 + (p - Y * MT_LX);
+        pys[k] = y0 - 2 + Y;
+        inxy[k] = pxs[k] >= 0 && pxs[k] < g.n0 && pys[k] >= 0 && pys[k] < g.n1;
         offxy[k] = ALLPER ? unsigned(wrapi(pxs[k], g.n0)) + unsigned(g.n0) * unsigned(wrapi(pys[k], g.n1))
-                          : 0u;
+                          : (inxy[k] ? unsigned(pxs[k]) + unsigned(g.n0) * unsigned(pys[k]) : 0u);
     }
     const unsigned plane = unsigned(g.n0) * unsigned(g.n1);
     auto fetch = [&](int zz, float (&r)[3][MT_LOADS]) {
@@ -174,85 +217,128 @@ __global__ __launch_bounds__(kBlock) void k_momentum_tiled(VelField<float> E,
             const unsigned base = unsigned(gz) * plane;
 #pragma unroll
             for (int k = 0; k < MT_LOADS; ++k)
-                if (t + k * kBlock < MT_PL)
+                if (lpos[k] >= 0)
 #pragma unroll
                     for (int c = 0; c < 3; ++c) r[c][k] = E.u[c][base + offxy[k]];
         } else {
+            const bool zin = zz >= 0 && zz < g.n2;
+            const unsigned base = zin ? unsigned(zz) * plane : 0u;
 #pragma unroll
-            for (int k = 0; k < MT_LOADS; ++k)
-                if (t + k * kBlock < MT_PL)
+            for (int k = 0; k < MT_LOADS; ++k) {
+                if (lpos[k] < 0) continue;
+                if (zin && inxy[k]) {
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) r[c][k] = tile_fetch<false>(E, c, pxs[k], pys[k], zz);
+                    for (int c = 0; c < 3; ++c) r[c][k] = E.u[c][base + offxy[k]];
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) r[c][k] = ghost_fetch(&E, c, pxs[k], pys[k], zz);
+                }
+            }
         }
     };
+    auto slot = [](int z) { return (z + MT_NP) % MT_NP; };  // z >= -1
     auto store = [&](int zz, const float (&r)[3][MT_LOADS]) {
         const int sl = slot(zz);
 #pragma unroll
-        for (int k = 0; k < MT_LOADS; ++k) {
-            const int p = t + k * kBlock;
-            if (p < MT_PL)
+        for (int k = 0; k < MT_LOADS; ++k)
+            if (lpos[k] >= 0)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) sU[c][sl][p] = r[c][k];
-        }
+                for (int c = 0; c < 3; ++c) sU[c][sl][lpos[k]] = r[c][k];
     };
-    {
-        float r[3][MT_LOADS];
-        for (int zz = z0 - 2; zz <= z0 + 2; ++zz) {
-            fetch(zz, r);
-            store(zz, r);
-        }
-    }
+    auto U = [&](int c, int sl, int p) -> float { return sU[c][sl][p]; };
+
+    float PA[3][MT_LOADS], PB[3][MT_LOADS];
+    float wm2[3];
+    fetch(z0 - 1, PA);
+    fetch(z0, PB);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) wm2[c] = tile_fetch<ALLPER>(E, c, gx, gy, z0 - 2);
+    store(z0 - 1, PA);
+    store(z0, PB);
+    fetch(z0 + 1, PA);
+    fetch(z0 + 2, PB);
+    store(z0 + 1, PA);
     __syncthreads();
+    // own-column window: planes z-1, z, z+1 (plane z+2 is slot 0 of the
+    // register set that holds it)
+    float wm1[3], w0[3], wp1[3];
     float Fzlo[3];
     {
-        const int s0 = slot(z0), sm1 = slot(z0 - 1), sm2 = slot(z0 - 2), sp1 = slot(z0 + 1);
-        const float w0 = U(2, s0, lx, ly);
-        const float wb[3] = {U(2, s0, lx - 1, ly), U(2, s0, lx, ly - 1), U(2, sm1, lx, ly)};
+        const int sm1 = slot(z0 - 1), s0 = slot(z0), sp1 = slot(z0 + 1);
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-            Fzlo[c] = flux1(U(c, sm2, lx, ly), U(c, sm1, lx, ly), U(c, s0, lx, ly),
-                            U(c, sp1, lx, ly), 0.5f * (w0 + wb[c]), nu);
+        for (int c = 0; c < 3; ++c) {
+            wm1[c] = U(c, sm1, own);
+            w0[c] = U(c, s0, own);
+            wp1[c] = U(c, sp1, own);
+        }
+        const float wb[3] = {U(2, s0, own - 1), U(2, s0, own - MT_LX), wm1[2]};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Fzlo[c] = flux2(wm2[c], wm1[c], w0[c], wp1[c], w0[2] + wb[c], nu2);
     }
-    for (int z = z0; z < z1; ++z) {
-        const int s0 = slot(z), sm1 = slot(z - 1), sp1 = slot(z + 1), sp2 = slot(z + 2);
-        float pre[3][MT_LOADS];
+
+    // One plane.  cur holds plane z + 2 (fetched one plane earlier), nxt
+    // receives plane z + 3.
+    auto do_plane = [&](int z, float (&cur)[3][MT_LOADS], float (&nxt)[3][MT_LOADS]) {
+        const int s0 = slot(z), sm1 = slot(z - 1), sp1 = slot(z + 1);
         const bool more = z + 1 < z1;
-        if (more) fetch(z + 3, pre);
-        // x faces of the plane: 65 per row
-        for (int f = t; f < (MT_X + 1) * MT_Y; f += kBlock) {
-            const int row = f / (MT_X + 1), col = f - row * (MT_X + 1);
-            const int X = col + 2, Y = row + 2;
-            const float a0 = U(0, s0, X, Y);
-            const float ab[3] = {U(0, s0, X - 1, Y), U(0, s0, X, Y - 1), U(0, sm1, X, Y)};
+        if (more) fetch(z + 3, nxt);
+        const unsigned id = unsigned(gx) + unsigned(g.n0) * unsigned(gy) + plane * unsigned(z);
+        float ubase[3] = {0.f, 0.f, 0.f};
+        if (CORR && inside) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ubase[c] = un[c][id];
+        }
+        // lower x face of the own cell (and the tile's upper x column)
+        float Fxlo[3], Fylo[3];
+        {
+            const float a0 = U(0, s0, own);
+            const float ab[3] = {U(0, s0, own - 1), U(0, s0, own - MT_LX), U(0, sm1, own)};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                Fxlo[c] = flux2(U(c, s0, own - 2), U(c, s0, own - 1), w0[c], U(c, s0, own + 1),
+                                a0 + ab[c], nu2);
+                sFx[c][ty][tx] = Fxlo[c];
+            }
+        }
+        if (xtra_x) {
+            const int p = xx_pos;
+            const float a0 = U(0, s0, p);
+            const float ab[3] = {U(0, s0, p - 1), U(0, s0, p - MT_LX), U(0, sm1, p)};
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                sFx[c][row][col] = flux1(U(c, s0, X - 2, Y), U(c, s0, X - 1, Y), U(c, s0, X, Y),
-                                         U(c, s0, X + 1, Y), 0.5f * (a0 + ab[c]), nu);
+                sFx[c][t - 64][MT_X] = flux2(U(c, s0, p - 2), U(c, s0, p - 1), U(c, s0, p),
+                                             U(c, s0, p + 1), a0 + ab[c], nu2);
         }
-        // y faces of the plane: 5 rows of 64
-        for (int f = t; f < MT_X * (MT_Y + 1); f += kBlock) {
-            const int row = f / MT_X, col = f - row * MT_X;
-            const int X = col + 2, Y = row + 2;
-            const float a0 = U(1, s0, X, Y);
-            const float ab[3] = {U(1, s0, X - 1, Y), U(1, s0, X, Y - 1), U(1, sm1, X, Y)};
+        // lower y face of the own cell (and the tile's upper y row)
+        {
+            const float a0 = U(1, s0, own);
+            const float ab[3] = {U(1, s0, own - 1), U(1, s0, own - MT_LX), U(1, sm1, own)};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                Fylo[c] = flux2(U(c, s0, own - 2 * MT_LX), U(c, s0, own - MT_LX), w0[c],
+                                U(c, s0, own + MT_LX), a0 + ab[c], nu2);
+                sFy[c][ty][tx] = Fylo[c];
+            }
+        }
+        if (xtra_y) {
+            const int p = xy_pos;
+            const float a0 = U(1, s0, p);
+            const float ab[3] = {U(1, s0, p - 1), U(1, s0, p - MT_LX), U(1, sm1, p)};
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                sFy[c][row][col] = flux1(U(c, s0, X, Y - 2), U(c, s0, X, Y - 1), U(c, s0, X, Y),
-                                         U(c, s0, X, Y + 1), 0.5f * (a0 + ab[c]), nu);
+                sFy[c][MT_Y][t - 128] = flux2(U(c, s0, p - 2 * MT_LX), U(c, s0, p - MT_LX),
+                                              U(c, s0, p), U(c, s0, p + MT_LX), a0 + ab[c], nu2);
         }
-        // upper z face of the thread's cell
+        // upper z face of the own cell
         float Fzhi[3];
         {
-            const float w0 = U(2, sp1, lx, ly);
-            const float wb[3] = {U(2, sp1, lx - 1, ly), U(2, sp1, lx, ly - 1), U(2, s0, lx, ly)};
+            const float wb[3] = {U(2, sp1, own - 1), U(2, sp1, own - MT_LX), w0[2]};
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                Fzhi[c] = flux1(U(c, sm1, lx, ly), U(c, s0, lx, ly), U(c, sp1, lx, ly),
-                                U(c, sp2, lx, ly), 0.5f * (w0 + wb[c]), nu);
+                Fzhi[c] = flux2(wm1[c], w0[c], wp1[c], cur[c][0], wp1[2] + wb[c], nu2);
         }
         __syncthreads();
         if (inside) {
-            const unsigned id = unsigned(gx) + unsigned(g.n0) * unsigned(gy) + plane * unsigned(z);
             const int coord[3] = {gx, gy, z};
             const int per[3] = {g.per0, g.per1, g.per2};
 #pragma unroll
@@ -261,19 +347,27 @@ __global__ __launch_bounds__(kBlock) void k_momentum_tiled(VelField<float> E,
                 if (!ALLPER && !per[c] && coord[c] == 0) {
                     v = (E.bclo[c] == WL_BC_INFLOW) ? E.U[c] : 0.f;
                 } else {
-                    float R = -(sFx[c][ty][tx + 1] - sFx[c][ty][tx]);
-                    R -= sFy[c][ty + 1][tx] - sFy[c][ty][tx];
+                    float R = -(sFx[c][ty][tx + 1] - Fxlo[c]);
+                    R -= sFy[c][ty + 1][tx] - Fylo[c];
                     R -= Fzhi[c] - Fzlo[c];
-                    const float ue = U(c, s0, lx, ly);
-                    v = CORR ? 0.5f * (un[c][id] + ue + dt * R) : ue + dt * R;
+                    v = CORR ? 0.5f * (ubase[c] + w0[c] + hdt * R) : w0[c] + hdt * R;
                 }
                 fo[c][id] = v;
             }
         }
 #pragma unroll
-        for (int c = 0; c < 3; ++c) Fzlo[c] = Fzhi[c];
-        if (more) store(z + 3, pre);
+        for (int c = 0; c < 3; ++c) {
+            Fzlo[c] = Fzhi[c];
+            wm1[c] = w0[c];
+            w0[c] = wp1[c];
+            wp1[c] = cur[c][0];
+        }
+        if (more) store(z + 2, cur);
         __syncthreads();
+    };
+    for (int z = z0; z < z1; z += 2) {
+        do_plane(z, PB, PA);
+        if (z + 1 < z1) do_plane(z + 1, PA, PB);
     }
 }
 
@@ -326,6 +420,15 @@ __global__ __launch_bounds__(kBlock) void k_bdim(TileDev TL, VelField<T> F, Bdim
     const Span sp = tile_span(TL, g.n0, g.n1, g.n2);
     const int i = sp.i, j = sp.j;
     if (i >= g.n0 || j >= g.n1) return;
+    if (B.cls && B.cls[block_linear()] == 0) {
+        // away from the body: u* = 1 * f exactly
+        T* out[3] = {o0, o1, o2};
+        for (int k = sp.z0; k < sp.z1; ++k) {
+            const size_t id = cid(g, i, j, k);
+            for (int c = 0; c < g.ndim; ++c) out[c][id] = F.u[c][id];
+        }
+        return;
+    }
     for (int k = sp.z0; k < sp.z1; ++k) {
     const size_t id = cid(g, i, j, k);
     const int coord[3] = {i, j, k};
@@ -351,6 +454,30 @@ __global__ __launch_bounds__(kBlock) void k_bdim(TileDev TL, VelField<T> F, Bdim
     }
 }
 
+// Tile class of each block: 1 if any face of its tile has mu0 != 1 or a
+// nonzero mu1 n component.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_tile_class(TileDev TL, Grid g, BdimFields<T> B,
+                                                       unsigned char* __restrict__ cls) {
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    const Span sp = tile_span(TL, g.n0, g.n1, g.n2);
+    const int i = sp.i, j = sp.j;
+    bool near = false;
+    if (i < g.n0 && j < g.n1)
+        for (int k = sp.z0; k < sp.z1 && !near; ++k) {
+            const size_t id = cid(g, i, j, k);
+            for (int c = 0; c < g.ndim; ++c) {
+                near = near || B.mu0[c][id] != T(1);
+                for (int d = 0; d < g.ndim; ++d) near = near || B.mu1n[3 * c + d][id] != T(0);
+            }
+        }
+    if (near) any = 1;  // benign race: every writer stores 1
+    __syncthreads();
+    if (threadIdx.x == 0) cls[block_linear()] = any ? 1 : 0;
+}
+
 // sigma = div(u*) / (c dt), plus per-block partial sums of sigma over the
 // active cells (D != 0; every cell when the coefficients are uniform) for the
 // mean removal of the pressure solve.
@@ -365,12 +492,32 @@ __global__ __launch_bounds__(kBlock) void k_divergence(TileDev TL, VelField<T> V
     const int i = sp.i, j = sp.j;
     const T scale = T(1.0 / (c * *dt_dev));
     double sum = 0.0;
-    if (i < g.n0 && j < g.n1) {
-        for (int k = sp.z0; k < sp.z1; ++k) {
-            const size_t id = cid(g, i, j, k);
-            T div = T(0);
-            for (int d = 0; d < g.ndim; ++d)
-                div += vget<T, ALLPER>(V, d, i + (d == 0), j + (d == 1), k + (d == 2)) - V.u[d][id];
+    if (i < g.n0 && j < g.n1 && sp.z0 < sp.z1) {
+        const unsigned n0 = unsigned(g.n0), plane = n0 * unsigned(g.n1);
+        const bool d3 = g.ndim == 3;
+        // upper x / y neighbour offsets (fixed along the column); the
+        // non-periodic upper boundary goes through the ghost rules
+        const bool xin = i + 1 < g.n0 || ALLPER || g.per0;
+        const bool yin = j + 1 < g.n1 || ALLPER || g.per1;
+        const int dxp = i + 1 < g.n0 ? 1 : -(g.n0 - 1);
+        const int dyp = j + 1 < g.n1 ? int(n0) : -int(n0) * (g.n1 - 1);
+        const T* __restrict__ ux = V.u[0];
+        const T* __restrict__ uy = V.u[1];
+        const T* __restrict__ uz = V.u[2];
+        unsigned id = unsigned(i) + n0 * unsigned(j) + plane * unsigned(sp.z0);
+        T wlo = d3 ? uz[id] : T(0);  // lower z face, carried up the column
+        for (int k = sp.z0; k < sp.z1; ++k, id += plane) {
+            const T xu = xin ? ux[id + dxp] : vget<T, ALLPER>(V, 0, i + 1, j, k);
+            const T yu = yin ? uy[id + dyp] : vget<T, ALLPER>(V, 1, i, j + 1, k);
+            T div = (xu - ux[id]) + (yu - uy[id]);
+            if (d3) {
+                T wup;
+                if (k + 1 < g.n2) wup = uz[id + plane];
+                else if (ALLPER || g.per2) wup = uz[id - plane * unsigned(g.n2 - 1)];
+                else wup = vget<T, ALLPER>(V, 2, i, j, k + 1);
+                div += wup - wlo;
+                wlo = wup;
+            }
             const T sg = div * scale;
             sigma[id] = sg;
             bool active = true;
@@ -397,10 +544,15 @@ __global__ __launch_bounds__(kBlock) void k_divergence(TileDev TL, VelField<T> V
 }
 
 // u = u* - c dt L grad(p) for every direction in one pass (the gradient loop
-// of Sec. 2 with coeff = c dt L, fused over directions).  With CFL, also the
+// of Sec. 2 with coeff = c dt L, fused over directions).  Each thread walks
+// its column up the z chunk and evaluates every face once: the lower x and y
+// faces of its cell and the upper z face, which (with p there) is carried to
+// the next plane as its lower z face.  Without CFL the output may alias u*
+// (a thread reads u* only on faces it writes later).  With CFL, also the
 // per-block maximum of sum_d max(u_d(I+delta_d),0) - min(u_d(I),0) of the
-// projected field; the upper neighbour faces are recomputed from u* and p, so
-// the output must not alias u*.
+// projected field: the upper x / y faces come from the neighbouring thread
+// through LDS, or are recomputed at the edge of the block's tile (the output
+// must then not alias u*).
 template <typename T, bool ALLPER, bool UNIF, bool CFL>
 __global__ __launch_bounds__(kBlock) void k_project(TileDev TL, VelField<T> V, const T* __restrict__ p,
                                                     ProjCoeffs<T> C, double c,
@@ -408,46 +560,88 @@ __global__ __launch_bounds__(kBlock) void k_project(TileDev TL, VelField<T> V, c
                                                     T* o0, T* o1, T* o2,
                                                     double* __restrict__ partial) {
     __shared__ double lds[8];
+    __shared__ T sX[CFL ? kBlock : 1], sY[CFL ? kBlock : 1];
     const Grid& g = V.g;
     const Span sp = tile_span(TL, g.n0, g.n1, g.n2);
     const int i = sp.i, j = sp.j;
+    const int t = threadIdx.x, bx = 1 << TL.lbx;
+    const bool valid = i < g.n0 && j < g.n1;
     const T coef = T(c * *dt_dev);
-    T* out[3] = {o0, o1, o2};
-    const int n[3] = {g.n0, g.n1, g.n2};
-    const int per[3] = {ALLPER ? 1 : g.per0, ALLPER ? 1 : g.per1, ALLPER ? 1 : g.per2};
-    const unsigned stride[3] = {1u, unsigned(g.n0), unsigned(g.n0) * unsigned(g.n1)};
+    const bool d3 = g.ndim == 3;
+    const bool per0 = ALLPER || g.per0, per1 = ALLPER || g.per1, per2 = ALLPER || g.per2;
+    const unsigned n0 = unsigned(g.n0), plane = n0 * unsigned(g.n1);
+    const int dxm = i > 0 ? -1 : g.n0 - 1;                       // lower x neighbour
+    const int dym = j > 0 ? -int(n0) : int(n0) * (g.n1 - 1);      // lower y neighbour
+    const bool bx0 = !per0 && i == 0, by0 = !per1 && j == 0;      // boundary faces (L = 0)
+    const T* sx = V.u[0];  // no restrict: the output may alias u*
+    const T* sy = V.u[1];
+    const T* sz = V.u[2];
+    auto Lat = [&](int d, unsigned id) -> T { return UNIF ? C.Lc : C.L[d][id]; };
+    // projected face d with lower cell offset dm (its cell holds pI)
+    auto face = [&](int d, const T* u, unsigned id, int dm, T pI) -> T {
+        return u[id] - coef * Lat(d, id) * (pI - p[id + dm]);
+    };
+    // CFL edge recompute: projected upper face of direction d of cell (i,j,k)
+    auto upper = [&](int d, unsigned id, int k, T pI) -> T {
+        const int q[3] = {i, j, k};
+        const int n[3] = {g.n0, g.n1, g.n2};
+        const bool per[3] = {per0, per1, per2};
+        const int st[3] = {1, int(n0), int(plane)};
+        if (q[d] + 1 < n[d] || per[d]) {
+            const int du = q[d] + 1 < n[d] ? st[d] : -st[d] * (n[d] - 1);
+            const unsigned idu = id + du;
+            return V.u[d][idu] - coef * Lat(d, idu) * (p[idu] - pI);
+        }
+        return vget<T, ALLPER>(V, d, i + (d == 0), j + (d == 1), k + (d == 2));
+    };
     double cfl = 0.0;
-    if (i < g.n0 && j < g.n1) {
-        for (int k = sp.z0; k < sp.z1; ++k) {
-            const int q[3] = {i, j, k};
-            const unsigned id = unsigned(i) + stride[1] * unsigned(j) + stride[2] * unsigned(k);
-            const T pI = p[id];
-            T s = T(0);
-            for (int d = 0; d < g.ndim; ++d) {
-                T ud;
-                if (!ALLPER && !per[d] && q[d] == 0) {
-                    ud = V.u[d][id];  // boundary face: L = 0
+    unsigned id = unsigned(i) + n0 * unsigned(j) + plane * unsigned(sp.z0);
+    T pI = T(0), wlo = T(0);
+    if (valid && sp.z0 < sp.z1) {
+        pI = p[id];
+        if (d3) {
+            if (!per2 && sp.z0 == 0) wlo = sz[id];
+            else wlo = face(2, sz, id, sp.z0 > 0 ? -int(plane) : int(plane) * (g.n2 - 1), pI);
+        }
+    }
+    for (int k = sp.z0; k < sp.z1; ++k, id += plane) {
+        T ux = T(0), uy = T(0), wup = T(0), pU = T(0);
+        const bool carry = k + 1 < sp.z1;
+        if (valid) {
+            ux = bx0 ? sx[id] : face(0, sx, id, dxm, pI);
+            uy = by0 ? sy[id] : face(1, sy, id, dym, pI);
+            if (d3 && (carry || CFL)) {
+                if (k + 1 < g.n2) {
+                    pU = p[id + plane];
+                    wup = sz[id + plane] - coef * Lat(2, id + plane) * (pU - pI);
+                } else if (per2) {
+                    const unsigned i0 = id - plane * unsigned(g.n2 - 1);
+                    wup = sz[i0] - coef * Lat(2, i0) * (p[i0] - pI);
                 } else {
-                    const unsigned idl = q[d] > 0 ? id - stride[d] : id + stride[d] * unsigned(n[d] - 1);
-                    const T L = UNIF ? C.Lc : C.L[d][id];
-                    ud = V.u[d][id] - coef * L * (pI - p[idl]);
-                }
-                out[d][id] = ud;
-                if (CFL) {
-                    T up;
-                    if (q[d] + 1 < n[d] || per[d]) {
-                        const unsigned idu = q[d] + 1 < n[d] ? id + stride[d]
-                                                             : id - stride[d] * unsigned(n[d] - 1);
-                        const T Lu = UNIF ? C.Lc : C.L[d][idu];
-                        up = V.u[d][idu] - coef * Lu * (p[idu] - pI);
-                    } else {
-                        up = vget<T, ALLPER>(V, d, i + (d == 0), j + (d == 1), k + (d == 2));
-                    }
-                    s += fmax(up, T(0)) - fmin(ud, T(0));
+                    wup = vget<T, ALLPER>(V, 2, i, j, k + 1);
                 }
             }
-            cfl = fmax(cfl, double(s));
+            o0[id] = ux;
+            o1[id] = uy;
+            if (d3) o2[id] = wlo;
         }
+        if (CFL) {
+            sX[t] = ux;
+            sY[t] = uy;
+            __syncthreads();
+            if (valid) {
+                const T xu = ((t & (bx - 1)) < bx - 1 && i + 1 < g.n0) ? sX[t + 1] : upper(0, id, k, pI);
+                const T yu = (t + bx < kBlock && j + 1 < g.n1) ? sY[t + bx] : upper(1, id, k, pI);
+                T s = fmax(xu, T(0)) - fmin(ux, T(0));
+                s += fmax(yu, T(0)) - fmin(uy, T(0));
+                if (d3) s += fmax(wup, T(0)) - fmin(wlo, T(0));
+                cfl = fmax(cfl, double(s));
+            }
+            __syncthreads();
+        }
+        wlo = wup;
+        pI = pU;
+        if (valid && carry && !d3) pI = p[id + plane];
     }
     if (CFL) {
         const double m = block_max(cfl, lds);
@@ -676,6 +870,14 @@ wl_status ns_bdim(const VelField<T>& F, const BdimFields<T>& B, T* const out[3],
 }
 
 template <typename T>
+wl_status ns_tile_class(const Grid& g, const BdimFields<T>& B, unsigned char* cls, hipStream_t s) {
+    const Launch ln = launch_for(g.n0, g.n1, g.n2);
+    k_tile_class<T><<<ln.grid, ln.block, 0, s>>>(ln.td, g, B, cls);
+    WL_CHECK_LAUNCH();
+    return WL_OK;
+}
+
+template <typename T>
 wl_status ns_divergence(const VelField<T>& V, const ProjCoeffs<T>& C, bool unif, double c,
                         const double* dt_dev, T* sigma, double* partial, bool allper,
                         hipStream_t s) {
@@ -745,6 +947,8 @@ wl_status ns_set_scalar(double* p, double v, hipStream_t s) {
 }
 
 #define WL_INST(T)                                                                               \
+    template wl_status ns_tile_class<T>(const Grid&, const BdimFields<T>&, unsigned char*,        \
+                                        hipStream_t);                                             \
     template wl_status ns_measure<T>(const Grid&, const BodyDev&, const int*,                     \
                                      const MeasureOut<T>&, hipStream_t);                          \
     template wl_status ns_momentum<T>(const VelField<T>&, const T* const*, T* const*, T, bool,   \

@@ -1,6 +1,7 @@
 // HIP-event timing of selected kernel launches (wl_profile_*): each timed
 // launch is bracketed by two events on its own stream; totals are summed when
 // read.  Events come from a process-wide pool that grows on demand.
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -15,7 +16,7 @@ struct Rec {
 
 struct Profiler {
     std::mutex mu;
-    unsigned mask = 0;
+    std::atomic<unsigned> mask{0};
     std::vector<Rec> pending[WL_PROF_COUNT];
     std::vector<Rec> pool;
     double total_ms[WL_PROF_COUNT] = {};
@@ -44,9 +45,29 @@ thread_local Rec t_open[WL_PROF_COUNT];
 
 }  // namespace
 
+// Timing of a kernel that runs inside captured solve bodies (the multigrid
+// sweeps and transfers) turns graph replay off.
+bool prof_active() {
+    constexpr unsigned in_graphs = (1u << WL_PROF_SMOOTH_FINE) | (1u << WL_PROF_SMOOTH_NORM) |
+                                   (1u << WL_PROF_PROLONG_FINE) | (1u << WL_PROF_RESTRICT_FINE);
+    return (prof().mask.load(std::memory_order_relaxed) & in_graphs) != 0u;
+}
+
+namespace {
+std::atomic<int> g_graphs{1};
+}  // namespace
+
+bool graphs_enabled() { return g_graphs.load(std::memory_order_relaxed) != 0; }
+
+GraphCache::~GraphCache() {
+    for (auto& en : e)
+        if (en.exec) (void)hipGraphExecDestroy(en.exec);
+    if (cap) (void)hipStreamDestroy(cap);
+}
+
 ProfScope::ProfScope(int kernel, hipStream_t stream, size_t ncells) : id(kernel), s(stream) {
     Profiler& P = prof();
-    on = kernel >= 0 && kernel < WL_PROF_COUNT && (P.mask >> kernel & 1u);
+    on = kernel >= 0 && kernel < WL_PROF_COUNT && (P.mask.load() >> kernel & 1u);
     if (!on) return;
     std::lock_guard<std::mutex> g(P.mu);
     Rec r = P.get();
@@ -83,11 +104,17 @@ using namespace wl;
 
 extern "C" {
 
+wl_status wl_set_graphs(int enable) {
+    clear_error();
+    g_graphs.store(enable != 0 ? 1 : 0, std::memory_order_relaxed);
+    return WL_OK;
+}
+
 wl_status wl_profile_enable(unsigned mask) {
     clear_error();
     Profiler& P = prof();
     std::lock_guard<std::mutex> g(P.mu);
-    P.mask = mask;
+    P.mask.store(mask);
     return WL_OK;
 }
 

@@ -108,6 +108,74 @@ struct Level {
     T Lc = T(1);
 };
 
+// Executable HIP graphs of a repeated solve body (one V-cycle with its norm,
+// or one mixed-precision outer iteration), keyed by the solution array the
+// body was captured for: kernel arguments are baked into a graph.  Two
+// entries, the least recently used one is replaced.  Owned by its hierarchy.
+struct GraphCache {
+    struct Entry {
+        const void* key = nullptr;
+        int uses = 0;
+        unsigned long long stamp = 0;
+        hipGraphExec_t exec = nullptr;
+    };
+    Entry e[2];
+    hipStream_t cap = nullptr;  // private stream used only for capture
+    unsigned long long clock = 0;
+    GraphCache() = default;
+    GraphCache(const GraphCache&) = delete;
+    GraphCache& operator=(const GraphCache&) = delete;
+    ~GraphCache();
+};
+
+// Process-wide switch for graph replay (wl_set_graphs) and whether a kernel
+// that runs inside captured bodies is being timed (timed launches are never
+// captured).
+bool graphs_enabled();
+bool prof_active();
+
+// Runs body(stream) on s.  From the second call with the same key on, the
+// body is captured once (on the cache's private stream) and replayed with
+// hipGraphLaunch on s; the body must only enqueue kernels on the stream it
+// is given.
+template <typename F>
+wl_status run_cached(GraphCache& G, const void* key, hipStream_t s, F&& body) {
+    if (!graphs_enabled() || prof_active()) return body(s);
+    GraphCache::Entry* hit = nullptr;
+    for (auto& en : G.e)
+        if (en.key == key) hit = &en;
+    if (!hit) {
+        hit = &G.e[0];
+        for (auto& en : G.e)
+            if (en.stamp < hit->stamp) hit = &en;
+        if (hit->exec) (void)hipGraphExecDestroy(hit->exec);
+        *hit = GraphCache::Entry{};
+        hit->key = key;
+    }
+    hit->stamp = ++G.clock;
+    if (!hit->exec) {
+        if (++hit->uses < 2) return body(s);
+        if (!G.cap) WL_CHECK_HIP(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
+        WL_CHECK_HIP(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal));
+        const wl_status rc = body(G.cap);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(G.cap, &graph);
+        if (rc != WL_OK || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            if (rc != WL_OK) return rc;
+            WL_CHECK_HIP(e);
+        }
+        const hipError_t ei = hipGraphInstantiate(&hit->exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            hit->exec = nullptr;
+            WL_CHECK_HIP(ei);
+        }
+    }
+    WL_CHECK_HIP(hipGraphLaunch(hit->exec, s));
+    return WL_OK;
+}
+
 template <typename T>
 struct Hierarchy {
     int nlev = 0;
@@ -115,6 +183,23 @@ struct Hierarchy {
     double omega = 0.0;
     double coarse_tol = 1e-10;
     size_t n_active = 0;         // active fine cells (host copy)
+    GraphCache graphs;
+};
+
+// A few doubles handed from the device to the host without a copy engine or
+// a stream synchronisation: a one-thread kernel writes them into coherent
+// pinned host memory followed by a sequence number, and the host waits for
+// that number (see host_read).  Allocated on first use, one per solver.
+struct HostMailbox {
+    double* vals = nullptr;      // pinned host: 8 values, then the sequence word
+    unsigned* seqw = nullptr;
+    double* vals_dev = nullptr;  // the same memory as seen by kernels
+    unsigned* seqw_dev = nullptr;
+    unsigned seq = 0;
+    HostMailbox() = default;
+    HostMailbox(const HostMailbox&) = delete;
+    HostMailbox& operator=(const HostMailbox&) = delete;
+    ~HostMailbox();
 };
 
 // Reduction scratch: per-block FP64 partial slots plus a few result scalars.
@@ -122,7 +207,13 @@ struct Reduce {
     double* partial = nullptr;   // capacity slots * 2
     size_t slots = 0;
     double* result = nullptr;    // 8 doubles
+    HostMailbox mb;
 };
+
+// out[0..n) = src[0..n) (device, n <= 8) once every earlier operation on s
+// has completed.  Waits by polling the mailbox for a bounded time, then falls
+// back to hipStreamSynchronize (which also reports a failed kernel).
+wl_status host_read(Reduce& red, const double* src, int n, double* out, hipStream_t s);
 
 template <typename T>
 void carve_hierarchy(Carver& c, Hierarchy<T>& h, int ndim, const int n[3], const int per[3],

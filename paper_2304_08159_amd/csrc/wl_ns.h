@@ -21,6 +21,10 @@ template <typename T>
 struct BdimFields {
     const T* mu0[3];
     const T* mu1n[9];
+    // Tile class per block of the cell tiling (launch_for): 0 where every
+    // face of the tile has mu0 = 1 and mu1 n = 0, so BDIM is the identity
+    // there; null treats every tile as touching the body.
+    const unsigned char* cls = nullptr;
 };
 
 template <typename T>
@@ -65,6 +69,9 @@ wl_status ns_outflow(const Grid& g, const T* ue_x, const T* out_e, const T* out_
                      T Ux, bool corr, const double* dt_dev, T* fout, hipStream_t s);
 template <typename T>
 wl_status ns_bdim(const VelField<T>& F, const BdimFields<T>& B, T* const out[3], hipStream_t s);
+// Tile classes (see BdimFields::cls) from the measured mu0 / mu1 n.
+template <typename T>
+wl_status ns_tile_class(const Grid& g, const BdimFields<T>& B, unsigned char* cls, hipStream_t s);
 template <typename T>
 wl_status ns_divergence(const VelField<T>& V, const ProjCoeffs<T>& C, bool unif, double c,
                         const double* dt_dev, T* sigma, double* partial, bool allper,
