@@ -123,22 +123,93 @@ __global__ __launch_bounds__(kBlock) void k_smooth(TileDev TL, Grid g, XAccess<T
     const Span sp = tile_span(TL, g.n0, g.n1, g.n2);
     const int i = sp.i, j = sp.j;
     double r2 = 0.0, b2 = 0.0;
-    if (i < g.n0 && j < g.n1) {
-        for (int k = sp.z0; k < sp.z1; ++k) {
-        const size_t id = cid(g, i, j, k);
-        T xI, Ax, D;
-        apply_row<T, XM, UNIF>(g, X, C, i, j, k, xI, Ax, D);
-        T bv = b[id];
-        if (FIRST) {
-            bv = (D > T(0)) ? T(double(bv) - *bmean) : T(0);
-            bproj[id] = bv;
+    if (i < g.n0 && j < g.n1 && sp.z0 < sp.z1) {
+        // The thread walks its (i, j) column up the z chunk: x / y neighbour
+        // offsets are fixed along it, the lower z neighbour and coefficient
+        // are carried from the previous cell, and every load of a cell is
+        // issued before any of them is used.  Non-periodic boundaries point
+        // at the cell itself with a zero coefficient.
+        const unsigned n0 = unsigned(g.n0), plane = n0 * unsigned(g.n1);
+        const bool d3 = g.ndim == 3;
+        const int ixm = i > 0 ? i - 1 : (g.per0 ? g.n0 - 1 : i);
+        const int ixp = i < g.n0 - 1 ? i + 1 : (g.per0 ? 0 : i);
+        const int jym = j > 0 ? j - 1 : (g.per1 ? g.n1 - 1 : j);
+        const int jyp = j < g.n1 - 1 ? j + 1 : (g.per1 ? 0 : j);
+        const bool hxu = i < g.n0 - 1 || g.per0, hyu = j < g.n1 - 1 || g.per1;
+        const int oxm = ixm - i, oxp = ixp - i;
+        const int oym = (jym - j) * int(n0), oyp = (jyp - j) * int(n0);
+        // prolongation: parent columns of the cell and its x / y neighbours
+        const unsigned ncp = unsigned(X.nc0) * unsigned(X.nc1);
+        const unsigned pc = unsigned(i >> 1) + unsigned(X.nc0) * unsigned(j >> 1);
+        const unsigned pxm = unsigned(ixm >> 1) + unsigned(X.nc0) * unsigned(j >> 1);
+        const unsigned pxp = unsigned(ixp >> 1) + unsigned(X.nc0) * unsigned(j >> 1);
+        const unsigned pym = unsigned(i >> 1) + unsigned(X.nc0) * unsigned(jym >> 1);
+        const unsigned pyp = unsigned(i >> 1) + unsigned(X.nc0) * unsigned(jyp >> 1);
+        auto xv = [&](unsigned idx, unsigned pcol, int k) -> T {
+            if (XM == XM_ZERO) return T(0);
+            T v = X.x[idx];
+            if (XM == XM_PROLONG) v += X.xc[pcol + ncp * unsigned(k >> 1)];
+            return v;
+        };
+        const double mean = FIRST ? *bmean : 0.0;
+        const int k0 = sp.z0;
+        unsigned id = unsigned(i) + n0 * unsigned(j) + plane * unsigned(k0);
+        // z neighbours of the first cell
+        T xzl = T(0), xI = xv(id, pc, k0), Lzl = T(0);
+        if (d3) {
+            const int km = k0 > 0 ? k0 - 1 : (g.per2 ? g.n2 - 1 : k0);
+            xzl = xv(id + unsigned(km - k0) * plane, pc, km);
+            if (!UNIF) Lzl = C.L2[id];
         }
-        const T r = bv - Ax;
-        xout[id] = (D > T(0)) ? xI - omega * r / D : T(0);
-        if (NORM) {
-            r2 += double(r) * double(r);
-            if (FIRST) b2 += double(bv) * double(bv);
-        }
+        for (int k = k0; k < sp.z1; ++k, id += plane) {
+            // upper z neighbour (carried up as the next centre)
+            T xzu = T(0), Lzu = T(0);
+            bool hzu = false;
+            unsigned idu = id;
+            int ku = k;
+            if (d3) {
+                hzu = k < g.n2 - 1 || g.per2;
+                ku = k < g.n2 - 1 ? k + 1 : (g.per2 ? 0 : k);
+                idu = id + unsigned(ku - k) * plane;
+                xzu = xv(idu, pc, ku);
+            }
+            const T xxl = xv(id + oxm, pxm, k), xxu = xv(id + oxp, pxp, k);
+            const T xyl = xv(id + oym, pym, k), xyu = xv(id + oyp, pyp, k);
+            T bv = b[id];
+            T Lxl, Lxu, Lyl, Lyu;
+            if (UNIF) {
+                Lxl = Lxu = Lyl = Lyu = Lzu = C.Lc;
+                Lzl = C.Lc;
+            } else {
+                Lxl = C.L0[id];
+                Lxu = hxu ? C.L0[id + oxp] : T(0);
+                Lyl = C.L1[id];
+                Lyu = hyu ? C.L1[id + oyp] : T(0);
+                if (d3) Lzu = hzu ? C.L2[idu] : T(0);
+            }
+            T Ax = T(0), D = T(0);
+            Ax += Lxu * (xxu - xI) - Lxl * (xI - xxl);
+            D += Lxl + Lxu;
+            Ax += Lyu * (xyu - xI) - Lyl * (xI - xyl);
+            D += Lyl + Lyu;
+            if (d3) {
+                Ax += Lzu * (xzu - xI) - Lzl * (xI - xzl);
+                D += Lzl + Lzu;
+            }
+            const bool act = D > T(0);
+            if (FIRST) {
+                bv = act ? T(double(bv) - mean) : T(0);
+                bproj[id] = bv;
+            }
+            const T r = bv - Ax;
+            xout[id] = act ? xI - omega * r / D : T(0);
+            if (NORM) {
+                r2 += double(r) * double(r);
+                if (FIRST) b2 += double(bv) * double(bv);
+            }
+            xzl = xI;
+            xI = xzu;
+            Lzl = Lzu;
         }
     }
     if (NORM) {
@@ -164,16 +235,80 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(TileDev TL, Grid g, G
     const Span sp = tile_span(TL, g.n0, g.n1, g.n2);
     const int i = sp.i, j = sp.j;
     const bool valid = i < g.n0 && j < g.n1;
+    const bool d3 = g.ndim == 3;
     const int fz = (g.n2 > gc.n2) ? 2 : 1;
     const int t = threadIdx.x, bx = 1 << TL.lbx;
-    for (int k = sp.z0; k < sp.z1; k += fz) {
+    const unsigned n0 = unsigned(g.n0), plane = n0 * unsigned(g.n1);
+    // column geometry as in k_smooth (non-periodic boundaries: self, L = 0)
+    const int ixm = i > 0 ? i - 1 : (g.per0 ? g.n0 - 1 : i);
+    const int ixp = i < g.n0 - 1 ? i + 1 : (g.per0 ? 0 : i);
+    const int jym = j > 0 ? j - 1 : (g.per1 ? g.n1 - 1 : j);
+    const int jyp = j < g.n1 - 1 ? j + 1 : (g.per1 ? 0 : j);
+    const bool hxu = i < g.n0 - 1 || g.per0, hyu = j < g.n1 - 1 || g.per1;
+    const int oxm = ixm - i, oxp = ixp - i;
+    const int oym = (jym - j) * int(n0), oyp = (jyp - j) * int(n0);
+    unsigned id = unsigned(i) + n0 * unsigned(j) + plane * unsigned(sp.z0);
+    // residual of one cell given its z neighbours and z coefficients
+    auto resid = [&](unsigned c, T xI, T xzl, T xzu, T Lzl, T Lzu) -> T {
+        const T xxl = X.x[c + oxm], xxu = X.x[c + oxp], xyl = X.x[c + oym], xyu = X.x[c + oyp];
+        const T bv = b[c];
+        T Lxl, Lxu, Lyl, Lyu;
+        if (UNIF) {
+            Lxl = Lxu = Lyl = Lyu = C.Lc;
+        } else {
+            Lxl = C.L0[c];
+            Lxu = hxu ? C.L0[c + oxp] : T(0);
+            Lyl = C.L1[c];
+            Lyu = hyu ? C.L1[c + oyp] : T(0);
+        }
+        T Ax = T(0);
+        Ax += Lxu * (xxu - xI) - Lxl * (xI - xxl);
+        Ax += Lyu * (xyu - xI) - Lyl * (xI - xyl);
+        if (d3) Ax += Lzu * (xzu - xI) - Lzl * (xI - xzl);
+        return bv - Ax;
+    };
+    auto zup = [&](int k, unsigned c, bool& live) -> unsigned {  // index of the upper z neighbour
+        live = k < g.n2 - 1 || g.per2;
+        return c + unsigned((k < g.n2 - 1 ? k + 1 : (g.per2 ? 0 : k)) - k) * plane;
+    };
+    T xzl = T(0), xI = T(0), Lzl = T(0);
+    if (valid && sp.z0 < sp.z1) {
+        xI = X.x[id];
+        if (d3) {
+            const int k0 = sp.z0, km = k0 > 0 ? k0 - 1 : (g.per2 ? g.n2 - 1 : k0);
+            xzl = X.x[id + unsigned(km - k0) * plane];
+            Lzl = UNIF ? C.Lc : C.L2[id];
+        }
+    }
+    for (int k = sp.z0; k < sp.z1; k += fz, id += unsigned(fz) * plane) {
         T r = T(0);
-        if (valid)
-            for (int dz = 0; dz < fz; ++dz) {
-                T xI, Ax, D;
-                apply_row<T, XM_PLAIN, UNIF>(g, X, C, i, j, k + dz, xI, Ax, D);
-                r += b[cid(g, i, j, k + dz)] - Ax;
+        if (valid) {
+            if (d3) {
+                // cells k and k + 1 (fz = 2): the upper neighbour of k is the
+                // centre of k + 1
+                bool l1, l2;
+                const unsigned u1 = zup(k, id, l1);
+                const T x1 = X.x[u1];
+                const T Lz1 = l1 ? (UNIF ? C.Lc : C.L2[u1]) : T(0);
+                if (fz == 2) {
+                    const unsigned u2 = zup(k + 1, u1, l2);
+                    const T x2 = X.x[u2];
+                    const T Lz2 = l2 ? (UNIF ? C.Lc : C.L2[u2]) : T(0);
+                    r = resid(id, xI, xzl, x1, Lzl, Lz1);
+                    r += resid(u1, x1, xI, x2, Lz1, Lz2);
+                    xzl = x1;
+                    xI = x2;
+                    Lzl = Lz2;
+                } else {
+                    r = resid(id, xI, xzl, x1, Lzl, Lz1);
+                    xzl = xI;
+                    xI = x1;
+                    Lzl = Lz1;
+                }
+            } else {
+                r = resid(id, xI, T(0), T(0), T(0), T(0));
             }
+        }
         r += __shfl_xor(r, 1, 64);
         sy[t] = r;
         __syncthreads();
