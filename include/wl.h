@@ -31,7 +31,10 @@
  *              in a caller-supplied device workspace whose exact size the
  *              *_footprint call returns (host-only computation).  The library
  *              keeps the workspace and the stream given at creation, and no
- *              other pointer beyond a call.
+ *              other pointer beyond a call.  Per handle it owns a 128-byte
+ *              pinned host buffer (scalar results are read through it), a
+ *              capture stream of default priority and at most two executable
+ *              graphs, created on first use and released by *_destroy.
  *  Streams   : work is enqueued on the creation stream (a hipStream_t passed
  *              as void*, NULL = default stream).  Calls that return scalar
  *              results (residuals, V-cycle counts, dt) synchronise it.
