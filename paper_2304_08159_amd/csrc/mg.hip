@@ -109,16 +109,18 @@ template void carve_hierarchy<double>(Carver&, Hierarchy<double>&, int, const in
 // ---------------------------------------------------------------- kernels
 
 // One damped-Jacobi sweep  x_out = x - w (b - A x) / D  (zero on inactive
-// cells, D = 0).  FIRST: b is the raw right-hand side; the sweep writes the
-// projected copy bproj = (b - mean) on active cells, 0 elsewhere, and uses it.
-// NORM: per-block partial sums of r^2 (and of bproj^2 when FIRST) in FP64.
+// cells, D = 0).  With bshift, b is the raw right-hand side and the sweep uses
+// its projection (b - mean) on active cells, 0 elsewhere, mean = *bshift;
+// FIRST with bproj also stores that projection.
+// NORM: per-block partial sums of r^2 (and, FIRST, of the projected b^2) in
+// FP64.
 template <typename T, int XM, bool UNIF, bool NORM, bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_smooth(TileDev TL, Grid g, XAccess<T, XM> X, Coeffs<T> C,
                                                    const T* __restrict__ b, T omega,
                                                    T* __restrict__ xout,
                                                    double* __restrict__ partial,
-                                                   T* __restrict__ bproj,
-                                                   const double* __restrict__ bmean) {
+                                                   const double* __restrict__ bshift,
+                                                   T* __restrict__ bproj) {
     __shared__ double lds[8];
     const Span sp = tile_span(TL, g.n0, g.n1, g.n2);
     const int i = sp.i, j = sp.j;
@@ -151,7 +153,8 @@ __global__ __launch_bounds__(kBlock) void k_smooth(TileDev TL, Grid g, XAccess<T
             if (XM == XM_PROLONG) v += X.xc[pcol + ncp * unsigned(k >> 1)];
             return v;
         };
-        const double mean = FIRST ? *bmean : 0.0;
+        const bool shift = bshift != nullptr;
+        const double mean = shift ? *bshift : 0.0;
         const int k0 = sp.z0;
         unsigned id = unsigned(i) + n0 * unsigned(j) + plane * unsigned(k0);
         // z neighbours of the first cell
@@ -197,10 +200,8 @@ __global__ __launch_bounds__(kBlock) void k_smooth(TileDev TL, Grid g, XAccess<T
                 D += Lzl + Lzu;
             }
             const bool act = D > T(0);
-            if (FIRST) {
-                bv = act ? T(double(bv) - mean) : T(0);
-                bproj[id] = bv;
-            }
+            if (shift) bv = act ? T(double(bv) - mean) : T(0);
+            if (FIRST && bproj) bproj[id] = bv;
             const T r = bv - Ax;
             xout[id] = act ? xI - omega * r / D : T(0);
             if (NORM) {
@@ -230,6 +231,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth(TileDev TL, Grid g, XAccess<T
 template <typename T, bool UNIF>
 __global__ __launch_bounds__(kBlock) void k_resid_restrict(TileDev TL, Grid g, Grid gc, XAccess<T, XM_PLAIN> X,
                                                            Coeffs<T> C, const T* __restrict__ b,
+                                                           const double* __restrict__ bshift,
                                                            T* __restrict__ bc) {
     __shared__ T sy[kBlock];
     const Span sp = tile_span(TL, g.n0, g.n1, g.n2);
@@ -249,9 +251,11 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(TileDev TL, Grid g, G
     const int oym = (jym - j) * int(n0), oyp = (jyp - j) * int(n0);
     unsigned id = unsigned(i) + n0 * unsigned(j) + plane * unsigned(sp.z0);
     // residual of one cell given its z neighbours and z coefficients
+    const bool shift = bshift != nullptr;
+    const double mean = shift ? *bshift : 0.0;
     auto resid = [&](unsigned c, T xI, T xzl, T xzu, T Lzl, T Lzu) -> T {
         const T xxl = X.x[c + oxm], xxu = X.x[c + oxp], xyl = X.x[c + oym], xyu = X.x[c + oyp];
-        const T bv = b[c];
+        T bv = b[c];
         T Lxl, Lxu, Lyl, Lyu;
         if (UNIF) {
             Lxl = Lxu = Lyl = Lyu = C.Lc;
@@ -261,10 +265,16 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(TileDev TL, Grid g, G
             Lyl = C.L1[c];
             Lyu = hyu ? C.L1[c + oyp] : T(0);
         }
-        T Ax = T(0);
+        T Ax = T(0), D = T(0);
         Ax += Lxu * (xxu - xI) - Lxl * (xI - xxl);
+        D += Lxl + Lxu;
         Ax += Lyu * (xyu - xI) - Lyl * (xI - xyl);
-        if (d3) Ax += Lzu * (xzu - xI) - Lzl * (xI - xzl);
+        D += Lyl + Lyu;
+        if (d3) {
+            Ax += Lzu * (xzu - xI) - Lzl * (xI - xzl);
+            D += Lzl + Lzu;
+        }
+        if (shift) bv = D > T(0) ? T(double(bv) - mean) : T(0);
         return bv - Ax;
     };
     auto zup = [&](int k, unsigned c, bool& live) -> unsigned {  // index of the upper z neighbour
@@ -717,17 +727,17 @@ static Coeffs<T> coeffs_of(const Level<T>& L) {
 
 template <typename T, int XM, bool NORM, bool FIRST>
 static wl_status smooth(const Level<T>& L, const T* xin, const T* xc, const Grid* gc,
-                        const T* b, T omega, T* xout, double* partial, T* bproj,
-                        const double* bmean, hipStream_t s, int prof = -1) {
+                        const T* b, T omega, T* xout, double* partial, const double* bshift,
+                        hipStream_t s, int prof = -1, T* bproj = nullptr) {
     const Launch ln = launch_for(L.g.n0, L.g.n1, L.g.n2);
     ProfScope ps(prof, s, cells(L.g));
     XAccess<T, XM> X{xin, xc, gc ? gc->n0 : 0, gc ? gc->n1 : 0};
     if (L.uniform)
         k_smooth<T, XM, true, NORM, FIRST><<<ln.grid, ln.block, 0, s>>>(ln.td, 
-            L.g, X, coeffs_of(L), b, omega, xout, partial, bproj, bmean);
+            L.g, X, coeffs_of(L), b, omega, xout, partial, bshift, bproj);
     else
         k_smooth<T, XM, false, NORM, FIRST><<<ln.grid, ln.block, 0, s>>>(ln.td, 
-            L.g, X, coeffs_of(L), b, omega, xout, partial, bproj, bmean);
+            L.g, X, coeffs_of(L), b, omega, xout, partial, bshift, bproj);
     WL_CHECK_LAUNCH();
     return WL_OK;
 }
@@ -748,15 +758,17 @@ static Launch launch_pairs(const Grid& g) {
 }
 
 template <typename T>
-static wl_status resid_restrict(const Level<T>& L, const T* x, Level<T>& C, hipStream_t s,
-                                int prof = -1) {
+static wl_status resid_restrict(const Level<T>& L, const T* x, const T* b, const double* bshift,
+                                Level<T>& C, hipStream_t s, int prof = -1) {
     const Launch ln = launch_pairs(L.g);
     ProfScope ps(prof, s, cells(L.g));
     XAccess<T, XM_PLAIN> X{x, nullptr, 0, 0};
     if (L.uniform)
-        k_resid_restrict<T, true><<<ln.grid, ln.block, 0, s>>>(ln.td, L.g, C.g, X, coeffs_of(L), L.b, C.b);
+        k_resid_restrict<T, true><<<ln.grid, ln.block, 0, s>>>(ln.td, L.g, C.g, X, coeffs_of(L), b, bshift,
+                                                               C.b);
     else
-        k_resid_restrict<T, false><<<ln.grid, ln.block, 0, s>>>(ln.td, L.g, C.g, X, coeffs_of(L), L.b, C.b);
+        k_resid_restrict<T, false><<<ln.grid, ln.block, 0, s>>>(ln.td, L.g, C.g, X, coeffs_of(L), b,
+                                                                bshift, C.b);
     WL_CHECK_LAUNCH();
     return WL_OK;
 }
@@ -820,20 +832,22 @@ template wl_status mg_count_active<double>(Hierarchy<double>&, Reduce&, hipStrea
 // Remainder of one V-cycle once its first fine pre-sweep has written
 // lev[0].x[1]; leaves the fine iterate in lev[0].x[0].
 template <typename T>
-static wl_status vcycle_rest(Hierarchy<T>& h, hipStream_t s) {
+static wl_status vcycle_rest(Hierarchy<T>& h, const T* fb, const double* fshift, hipStream_t s) {
+    // fb / fshift: fine-level right-hand side and the mean to remove from it
+    // on the fly (null: fb is already projected)
     Level<T>& F = h.lev[0];
     const T w = T(h.omega);
     if (h.nlev == 1) return coarse_solve(h, F, F.x[0], s);
-    WL_TRY((smooth<T, XM_PLAIN, false, false>(F, F.x[1], nullptr, nullptr, F.b, w, F.x[0],
-                                              nullptr, nullptr, nullptr, s, WL_PROF_SMOOTH_FINE)));
-    WL_TRY(resid_restrict(F, F.x[0], h.lev[1], s, WL_PROF_RESTRICT_FINE));
+    WL_TRY((smooth<T, XM_PLAIN, false, false>(F, F.x[1], nullptr, nullptr, fb, w, F.x[0], nullptr,
+                                              fshift, s, WL_PROF_SMOOTH_FINE)));
+    WL_TRY(resid_restrict(F, F.x[0], fb, fshift, h.lev[1], s, WL_PROF_RESTRICT_FINE));
     for (int l = 1; l < h.nlev - 1; ++l) {
         Level<T>& L = h.lev[l];
         WL_TRY((smooth<T, XM_ZERO, false, false>(L, nullptr, nullptr, nullptr, L.b, w, L.x[0],
-                                                 nullptr, nullptr, nullptr, s)));
+                                                 nullptr, nullptr, s)));
         WL_TRY((smooth<T, XM_PLAIN, false, false>(L, L.x[0], nullptr, nullptr, L.b, w, L.x[1],
-                                                  nullptr, nullptr, nullptr, s)));
-        WL_TRY(resid_restrict(L, L.x[1], h.lev[l + 1], s));
+                                                  nullptr, nullptr, s)));
+        WL_TRY(resid_restrict(L, L.x[1], L.b, nullptr, h.lev[l + 1], s));
     }
     Level<T>& Cst = h.lev[h.nlev - 1];
     WL_TRY(coarse_solve(h, Cst, Cst.x[1], s));
@@ -841,15 +855,15 @@ static wl_status vcycle_rest(Hierarchy<T>& h, hipStream_t s) {
         Level<T>& L = h.lev[l];
         const Level<T>& C = h.lev[l + 1];
         WL_TRY((smooth<T, XM_PROLONG, false, false>(L, L.x[1], C.x[1], &C.g, L.b, w, L.x[0],
-                                                    nullptr, nullptr, nullptr, s)));
+                                                    nullptr, nullptr, s)));
         WL_TRY((smooth<T, XM_PLAIN, false, false>(L, L.x[0], nullptr, nullptr, L.b, w, L.x[1],
-                                                  nullptr, nullptr, nullptr, s)));
+                                                  nullptr, nullptr, s)));
     }
     const Level<T>& C1 = h.lev[1];
-    WL_TRY((smooth<T, XM_PROLONG, false, false>(F, F.x[0], C1.x[1], &C1.g, F.b, w, F.x[1], nullptr,
-                                                nullptr, nullptr, s, WL_PROF_PROLONG_FINE)));
-    WL_TRY((smooth<T, XM_PLAIN, false, false>(F, F.x[1], nullptr, nullptr, F.b, w, F.x[0], nullptr,
-                                              nullptr, nullptr, s, WL_PROF_SMOOTH_FINE)));
+    WL_TRY((smooth<T, XM_PROLONG, false, false>(F, F.x[0], C1.x[1], &C1.g, fb, w, F.x[1], nullptr,
+                                                fshift, s, WL_PROF_PROLONG_FINE)));
+    WL_TRY((smooth<T, XM_PLAIN, false, false>(F, F.x[1], nullptr, nullptr, fb, w, F.x[0], nullptr,
+                                              fshift, s, WL_PROF_SMOOTH_FINE)));
     return WL_OK;
 }
 
@@ -885,9 +899,12 @@ wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, d
     const T w = T(h.omega);
     const Launch ln = launch_for(F.g.n0, F.g.n1, F.g.n2);
     WL_TRY(active_mean(h, red, b, b_partials, s));
-    // first fine sweep: projects b, measures ||r0|| and ||b||
-    WL_TRY((smooth<T, XM_PLAIN, true, true>(F, x, nullptr, nullptr, b, w, F.x[1], red.partial, F.b,
-                                            red.result + 5, s)));
+    // first fine sweep: measures ||r0|| and ||b - mean||.  Every fine-level
+    // sweep removes the mean of b on the fly; only a one-level hierarchy
+    // (whose coarse solve reads F.b) stores the projected copy.
+    const double* bshift = red.result + 5;
+    WL_TRY((smooth<T, XM_PLAIN, true, true>(F, x, nullptr, nullptr, b, w, F.x[1], red.partial,
+                                            bshift, s, -1, h.nlev == 1 ? F.b : nullptr)));
     WL_TRY(reduce<T>(red, ln.nblocks(), 2, 1.0, red.result, s));
     double nr[2];
     WL_TRY(read_norms(red, nr, s));
@@ -910,14 +927,13 @@ wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, d
     int k = 0;
     // one V-cycle and the residual norms it leaves (replayed as a graph)
     auto body = [&](hipStream_t q) -> wl_status {
-        WL_TRY(vcycle_rest(h, q));
-        WL_TRY((smooth<T, XM_PLAIN, true, false>(F, x, nullptr, nullptr, F.b, w, F.x[1],
-                                                 red.partial, nullptr, nullptr, q,
-                                                 WL_PROF_SMOOTH_NORM)));
+        WL_TRY(vcycle_rest(h, b, bshift, q));
+        WL_TRY((smooth<T, XM_PLAIN, true, false>(F, x, nullptr, nullptr, b, w, F.x[1],
+                                                 red.partial, bshift, q, WL_PROF_SMOOTH_NORM)));
         return reduce<T>(red, ln.nblocks(), 2, 1.0, red.result, q);
     };
     while (!done(r2) && k < max_vcycles) {
-        WL_TRY(run_cached(h.graphs, x, s, body));
+        WL_TRY(run_cached(h.graphs, x, b, s, body));
         ++k;
         WL_TRY(read_norms(red, nr, s));
         if (!std::isfinite(nr[0])) {
@@ -973,13 +989,11 @@ wl_status mg_solve_mixed(Hierarchy<float>& h32, const Mixed64& m, Reduce& red, d
         for (int v = 0; v < count; ++v) {
             if (v == 0)
                 WL_TRY((smooth<float, XM_ZERO, false, false>(F, nullptr, nullptr, nullptr, F.b, w,
-                                                             F.x[1], nullptr, nullptr, nullptr,
-                                                             q)));
+                                                             F.x[1], nullptr, nullptr, q)));
             else
                 WL_TRY((smooth<float, XM_PLAIN, false, false>(F, F.x[0], nullptr, nullptr, F.b, w,
-                                                              F.x[1], nullptr, nullptr, nullptr,
-                                                              q)));
-            WL_TRY(vcycle_rest(h32, q));
+                                                              F.x[1], nullptr, nullptr, q)));
+            WL_TRY(vcycle_rest(h32, static_cast<const float*>(F.b), nullptr, q));
         }
         k_axpy64<<<unsigned((N + kBlock - 1) / kBlock), kBlock, 0, q>>>(N, F.x[0], x);
         WL_CHECK_LAUNCH();
@@ -1008,7 +1022,7 @@ wl_status mg_solve_mixed(Hierarchy<float>& h32, const Mixed64& m, Reduce& red, d
         if (done(r2) || inner_total >= max_vcycles) break;
         const int count = std::min(m.inner, max_vcycles - inner_total);
         if (count == m.inner)
-            WL_TRY(run_cached(h32.graphs, x, s, [&](hipStream_t q) { return outer(q, count); }));
+            WL_TRY(run_cached(h32.graphs, x, b, s, [&](hipStream_t q) { return outer(q, count); }));
         else
             WL_TRY(outer(s, count));
         inner_total += count;

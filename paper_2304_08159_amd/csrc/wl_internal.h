@@ -109,12 +109,14 @@ struct Level {
 };
 
 // Executable HIP graphs of a repeated solve body (one V-cycle with its norm,
-// or one mixed-precision outer iteration), keyed by the solution array the
-// body was captured for: kernel arguments are baked into a graph.  Two
+// or one mixed-precision outer iteration), keyed by the solution and
+// right-hand-side arrays the body was captured for: kernel arguments are
+// baked into a graph.  Two
 // entries, the least recently used one is replaced.  Owned by its hierarchy.
 struct GraphCache {
     struct Entry {
         const void* key = nullptr;
+        const void* key2 = nullptr;
         int uses = 0;
         unsigned long long stamp = 0;
         hipGraphExec_t exec = nullptr;
@@ -134,16 +136,16 @@ struct GraphCache {
 bool graphs_enabled();
 bool prof_active();
 
-// Runs body(stream) on s.  From the second call with the same key on, the
+// Runs body(stream) on s.  From the second call with the same keys on, the
 // body is captured once (on the cache's private stream) and replayed with
 // hipGraphLaunch on s; the body must only enqueue kernels on the stream it
 // is given.
 template <typename F>
-wl_status run_cached(GraphCache& G, const void* key, hipStream_t s, F&& body) {
+wl_status run_cached(GraphCache& G, const void* key, const void* key2, hipStream_t s, F&& body) {
     if (!graphs_enabled() || prof_active()) return body(s);
     GraphCache::Entry* hit = nullptr;
     for (auto& en : G.e)
-        if (en.key == key) hit = &en;
+        if (en.key == key && en.key2 == key2) hit = &en;
     if (!hit) {
         hit = &G.e[0];
         for (auto& en : G.e)
@@ -151,6 +153,7 @@ wl_status run_cached(GraphCache& G, const void* key, hipStream_t s, F&& body) {
         if (hit->exec) (void)hipGraphExecDestroy(hit->exec);
         *hit = GraphCache::Entry{};
         hit->key = key;
+        hit->key2 = key2;
     }
     hit->stamp = ++G.clock;
     if (!hit->exec) {
