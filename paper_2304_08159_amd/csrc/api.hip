@@ -329,10 +329,11 @@ static wl_status sim_init(SimImpl<T>& s, hipStream_t st) {
 
 // Pressure solve of one stage.  It stops once the divergence it leaves in the
 // projected velocity, c dt (sigma - A p), has RMS over the active cells <= tol,
-// i.e. ||r||^2 <= (tol sqrt(n_active) / (c dt))^2.
+// i.e. ||r||^2 <= (tol sqrt(n_active) / (c dt))^2.  `tail` (may be null) is
+// work that reads the final pressure, done before returning (see SolveTail).
 template <typename T>
 static wl_status pressure_solve(SimImpl<T>& s, double cfac, double dt, hipStream_t st,
-                                SolveResult* r) {
+                                SolveResult* r, const SolveTail* tail = nullptr) {
     const SimConfig& c = s.cfg;
     const double a = c.d.tol * std::sqrt(double(s.h.n_active)) / (cfac * dt);
     const double abs_r2 = a * a;
@@ -343,11 +344,15 @@ static wl_status pressure_solve(SimImpl<T>& s, double cfac, double dt, hipStream
                                           c.d.max_vcycles, st, r);
             if (rc != WL_OK && rc != WL_ERR_NOT_CONVERGED) return rc;
             WL_TRY((convert<double, float>(s.p64, s.p, c.N, st)));
+            if (tail) {
+                WL_TRY((*tail)(st));
+                WL_TRY(host_wait(s.red, st));
+            }
             return rc;
         }
         return invalid("mixed precision needs FP32 fields");
     }
-    return mg_solve<T>(s.h, s.red, s.p, s.sigma, 0.0, abs_r2, c.d.max_vcycles, st, r, true);
+    return mg_solve<T>(s.h, s.red, s.p, s.sigma, 0.0, abs_r2, c.d.max_vcycles, st, r, true, tail);
 }
 
 template <typename T>
@@ -447,20 +452,26 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
         }
         const VelField<T> V2 = field_of(s, us2, s.plane[P2]);
         WL_TRY(ns_divergence<T>(V2, pc, c.unif, 0.5, dt_dev, s.sigma, s.red.partial, ap, st));
-        rc = pressure_solve(s, 0.5, dt, st, &r2);
+        // projection, CFL maximum and next dt read only the final pressure
+        // and write buffers nothing else reads: the solve may run them
+        // speculatively before its first convergence check returns
+        const int dest = (us2 == S) ? u1 : S;
+        T* o3[3] = {s.vel[dest][0], s.vel[dest][1], s.vel[dest][2]};
+        double* dt_next = s.scal + (1 - s.dt_cur);
+        const SolveTail tail = [&](hipStream_t q) -> wl_status {
+            WL_TRY(ns_project<T>(V2, s.p, pc, c.unif, 0.5, dt_dev, o3, true, s.red.partial, ap, q));
+            WL_TRY(ns_dt_from_max(s.red.partial, s.red.slots, c.d.cfl, 2.0 * c.d.ndim * c.d.nu,
+                                  dt_next, s.scal + 2, q));
+            return host_post(s.red, dt_next, 1, 8, q);
+        };
+        rc = pressure_solve(s, 0.5, dt, st, &r2, &tail);
         if (rc == WL_ERR_NOT_CONVERGED) worst = rc;
         else if (rc != WL_OK) return rc;
         if (tp) WL_TRY(rec(tp->p2, s.p, c.N));
-        int dest = (us2 == S) ? u1 : S;
-        T* o3[3] = {s.vel[dest][0], s.vel[dest][1], s.vel[dest][2]};
-        WL_TRY(ns_project<T>(V2, s.p, pc, c.unif, 0.5, dt_dev, o3, true, s.red.partial, ap, st));
-        double* dt_next = s.scal + (1 - s.dt_cur);
-        WL_TRY(ns_dt_from_max(s.red.partial, s.red.slots, c.d.cfl, 2.0 * c.d.ndim * c.d.nu,
-                              dt_next, s.scal + 2, st));
         s.S = dest;
         s.PS = P2;
     }
-    WL_TRY(host_read(s.red, s.scal + (1 - s.dt_cur), 1, &s.dt_next_host, st));
+    s.dt_next_host = host_slot(s.red, 8);
     s.dt_cur = 1 - s.dt_cur;
     s.cfl_valid = true;
     s.t += dt;

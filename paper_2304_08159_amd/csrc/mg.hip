@@ -361,26 +361,33 @@ HostMailbox::~HostMailbox() {
     if (vals) (void)hipHostFree(vals);
 }
 
-wl_status host_read(Reduce& red, const double* src, int n, double* out, hipStream_t s) {
+wl_status host_post(Reduce& red, const double* src, int n, int slot, hipStream_t s) {
     HostMailbox& mb = red.mb;
-    if (n < 0 || n > 8) {
-        set_error("host_read: at most 8 values");
+    if (n < 0 || slot < 0 || slot + n > HostMailbox::kSlots) {
+        set_error("host_post: slot range outside the mailbox");
         return WL_ERR_INVALID_ARG;
     }
     if (!mb.vals) {
         void* p = nullptr;
-        WL_CHECK_HIP(hipHostMalloc(&p, 128, hipHostMallocCoherent | hipHostMallocMapped));
+        WL_CHECK_HIP(hipHostMalloc(&p, 256, hipHostMallocCoherent | hipHostMallocMapped));
         mb.vals = static_cast<double*>(p);
-        mb.seqw = reinterpret_cast<unsigned*>(mb.vals + 8);
+        mb.seqw = reinterpret_cast<unsigned*>(mb.vals + HostMailbox::kSlots);
         *mb.seqw = 0u;
         void* d = nullptr;
         WL_CHECK_HIP(hipHostGetDevicePointer(&d, p, 0));
         mb.vals_dev = static_cast<double*>(d);
-        mb.seqw_dev = reinterpret_cast<unsigned*>(mb.vals_dev + 8);
+        mb.seqw_dev = reinterpret_cast<unsigned*>(mb.vals_dev + HostMailbox::kSlots);
     }
     const unsigned q = ++mb.seq;
-    k_publish<<<1, 1, 0, s>>>(src, n, mb.vals_dev, mb.seqw_dev, q);
+    k_publish<<<1, 1, 0, s>>>(src, n, mb.vals_dev + slot, mb.seqw_dev, q);
     WL_CHECK_LAUNCH();
+    return WL_OK;
+}
+
+wl_status host_wait(Reduce& red, hipStream_t s) {
+    HostMailbox& mb = red.mb;
+    if (!mb.vals) return WL_OK;
+    const unsigned q = mb.seq;
     // Poll for up to 20 ms (a step's solves publish every few hundred
     // microseconds), then let HIP wait and report any kernel failure.
     const auto t0 = std::chrono::steady_clock::now();
@@ -396,7 +403,13 @@ wl_status host_read(Reduce& red, const double* src, int n, double* out, hipStrea
             break;
         }
     }
-    for (int k = 0; k < n; ++k) out[k] = mb.vals[k];
+    return WL_OK;
+}
+
+wl_status host_read(Reduce& red, const double* src, int n, double* out, hipStream_t s) {
+    WL_TRY(host_post(red, src, n, 0, s));
+    WL_TRY(host_wait(red, s));
+    for (int k = 0; k < n; ++k) out[k] = red.mb.vals[k];
     return WL_OK;
 }
 
@@ -893,7 +906,8 @@ static wl_status active_mean(Hierarchy<T>& h, Reduce& red, const T* b, bool have
 
 template <typename T>
 wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, double abs_r2,
-                   int max_vcycles, hipStream_t s, SolveResult* res, bool b_partials) {
+                   int max_vcycles, hipStream_t s, SolveResult* res, bool b_partials,
+                   const SolveTail* tail) {
     Level<T>& F = h.lev[0];
     F.x[0] = x;
     const T w = T(h.omega);
@@ -907,7 +921,17 @@ wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, d
                                             bshift, s, -1, h.nlev == 1 ? F.b : nullptr)));
     WL_TRY(reduce<T>(red, ln.nblocks(), 2, 1.0, red.result, s));
     double nr[2];
-    WL_TRY(read_norms(red, nr, s));
+    if (tail) {
+        // speculate that the initial iterate already converges: the tail
+        // runs on it while the host waits for the norms
+        WL_TRY(host_post(red, red.result, 2, 0, s));
+        WL_TRY((*tail)(s));
+        WL_TRY(host_wait(red, s));
+        nr[0] = host_slot(red, 0);
+        nr[1] = host_slot(red, 1);
+    } else {
+        WL_TRY(read_norms(red, nr, s));
+    }
     if (!std::isfinite(nr[0]) || !std::isfinite(nr[1])) {
         set_error("non-finite residual norm in the pressure solve");
         return WL_ERR_NONFINITE;
@@ -920,6 +944,10 @@ wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, d
         WL_CHECK_LAUNCH();
         res->vcycles = 0;
         res->rel = 0.0;
+        if (tail) {
+            WL_TRY((*tail)(s));
+            WL_TRY(host_wait(red, s));
+        }
         return WL_OK;
     }
     double r2 = nr[0];
@@ -945,6 +973,11 @@ wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, d
     res->vcycles = k;
     res->rel = std::sqrt(r2 / b2);
     res->r2 = r2;
+    if (tail && k > 0) {
+        // the speculative tail saw the initial iterate: run it again
+        WL_TRY((*tail)(s));
+        WL_TRY(host_wait(red, s));
+    }
     if (!done(r2)) {
         set_error("pressure solve reached max_vcycles before the tolerance");
         return WL_ERR_NOT_CONVERGED;
@@ -953,9 +986,9 @@ wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, d
 }
 
 template wl_status mg_solve<float>(Hierarchy<float>&, Reduce&, float*, const float*, double,
-                                   double, int, hipStream_t, SolveResult*, bool);
+                                   double, int, hipStream_t, SolveResult*, bool, const SolveTail*);
 template wl_status mg_solve<double>(Hierarchy<double>&, Reduce&, double*, const double*, double,
-                                    double, int, hipStream_t, SolveResult*, bool);
+                                    double, int, hipStream_t, SolveResult*, bool, const SolveTail*);
 
 wl_status mg_solve_mixed(Hierarchy<float>& h32, const Mixed64& m, Reduce& red, double* x,
                          const double* b, double tol, double abs_r2, int max_vcycles,

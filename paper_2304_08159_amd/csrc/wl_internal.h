@@ -1,6 +1,8 @@
 // Internal declarations shared by the HIP translation units of libwl.
 #pragma once
 
+#include <functional>
+
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -194,7 +196,8 @@ struct Hierarchy {
 // pinned host memory followed by a sequence number, and the host waits for
 // that number (see host_read).  Allocated on first use, one per solver.
 struct HostMailbox {
-    double* vals = nullptr;      // pinned host: 8 values, then the sequence word
+    static constexpr int kSlots = 16;
+    double* vals = nullptr;      // pinned host: kSlots values, then the sequence word
     unsigned* seqw = nullptr;
     double* vals_dev = nullptr;  // the same memory as seen by kernels
     unsigned* seqw_dev = nullptr;
@@ -213,9 +216,15 @@ struct Reduce {
     HostMailbox mb;
 };
 
-// out[0..n) = src[0..n) (device, n <= 8) once every earlier operation on s
-// has completed.  Waits by polling the mailbox for a bounded time, then falls
-// back to hipStreamSynchronize (which also reports a failed kernel).
+// Enqueue on s: copy src[0..n) (device) into mailbox slots [slot, slot + n)
+// once everything before it on s has completed.  Does not wait.
+wl_status host_post(Reduce& red, const double* src, int n, int slot, hipStream_t s);
+// Wait until the most recent post has arrived (so have all earlier ones, in
+// stream order): polls the mailbox for a bounded time, then falls back to
+// hipStreamSynchronize (which also reports a failed kernel).
+wl_status host_wait(Reduce& red, hipStream_t s);
+inline double host_slot(const Reduce& red, int slot) { return red.mb.vals[slot]; }
+// host_post into slot 0, host_wait, and copy the values out.
 wl_status host_read(Reduce& red, const double* src, int n, double* out, hipStream_t s);
 
 template <typename T>
@@ -239,9 +248,17 @@ struct SolveResult {
 // Converged before a V-cycle when ||r||^2 <= tol^2 ||b||^2 or ||r||^2 <= abs_r2.
 // b_partials: red.partial already holds the per-block sums of b over the
 // active cells for the fine-level tiling (written by the producer of b).
+// Work that follows a converged solve and only reads its solution (e.g. the
+// projection).  mg_solve may enqueue it speculatively right after the first
+// norm check is enqueued and enqueue it again if V-cycles follow; it must
+// therefore be idempotent given the final solution.  On return the tail has
+// run on the final solution and every mailbox post it made has arrived.
+using SolveTail = std::function<wl_status(hipStream_t)>;
+
 template <typename T>
 wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, double abs_r2,
-                   int max_vcycles, hipStream_t s, SolveResult* res, bool b_partials = false);
+                   int max_vcycles, hipStream_t s, SolveResult* res, bool b_partials = false,
+                   const SolveTail* tail = nullptr);
 
 // Mixed precision: FP64 outer residual with FP64 fine coefficients L64,
 // FP32 inner V-cycles on h32.
