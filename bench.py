@@ -35,7 +35,8 @@ BYTES_PER_CELL = {
     "smooth_norm": 12.0,     # same sweep + per-block partial sums
     "prolong_fine": 12.5,    # read x, b, x_coarse (1/8); write x'
     "restrict_fine": 8.5,    # read x, b; write b_coarse (1/8)
-    "momentum": 30.0,        # predictor 24 (read u, write f), corrector 36 (+ read u^n)
+    "momentum": 32.0,        # predictor 24 (read u, write f); corrector 40 (read u*, p, u^n,
+                             # write f: it applies the predictor's projection as it loads)
     "divergence": 16.0,      # read u* (3 comps); write sigma
     "project": 28.0,         # read u* (3), p; write u (3)
 }
@@ -44,13 +45,15 @@ BYTES_PER_CELL = {
 def step_bytes_per_cell(vcycles_total, nlev_coarse_factor=1.0 / 7.0):
     """Algorithmic bytes of one step per fine cell (FP32, uniform L, 3D).
 
-    momentum 24 + 36, divergence 2 x 16, projection 2 x 28, per solve the
-    active-mean pass (4) and the projecting first sweep (16), and per V-cycle
-    the fine sweeps/transfers (12 + 8.5 + 12.5 + 12) plus the norm sweep (12)
-    and the coarse levels (53 B per coarse cell, 1/7 of the fine count).
+    momentum 24 + 40 (the corrector applies the predictor's projection as it
+    loads u*), divergence 2 x 16, the corrector's projection 28, per solve the
+    first sweep (12; the active mean comes with the divergence), and per
+    V-cycle the fine sweeps/transfers (12 + 8.5 + 12.5 + 12) plus the norm
+    sweep (12) and the coarse levels (53 B per coarse cell, 1/7 of the fine
+    count).
     """
     per_vcycle = 12 + 8.5 + 12.5 + 12 + 12 + 53.0 * nlev_coarse_factor
-    return 60.0 + 32.0 + 56.0 + 2 * 20.0 + per_vcycle * vcycles_total
+    return 64.0 + 32.0 + 28.0 + 2 * 12.0 + per_vcycle * vcycles_total
 
 
 # HBM traffic of the dominant kernel per launch from rocprofv3 counters

@@ -425,8 +425,13 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
         else if (rc != WL_OK) return rc;
         if (tp) WL_TRY(rec(tp->p1, s.p, c.N));
         T* o[3] = {s.vel[us][0], s.vel[us][1], s.vel[us][2]};
-        WL_TRY(ns_project<T>(V, s.p, pc, c.unif, 1.0, dt_dev, o, false, nullptr, ap, st));
-        // stage result now in set `us`; the remaining set is free
+        // Periodic FP32 3D grids with uniform coefficients skip storing the
+        // predictor's projection: the corrector's convection-diffusion
+        // kernel applies it as it loads u* (bitwise the same result).  The
+        // adjoint tape needs u1 itself, so recording steps store it.
+        const bool fuse = sizeof(T) == 4 && c.d.ndim == 3 && c.unif && !tp;
+        if (!fuse) WL_TRY(ns_project<T>(V, s.p, pc, c.unif, 1.0, dt_dev, o, false, nullptr, ap, st));
+        // stage result now in set `us` (u1, or u* when fused); the remaining set is free
         const int u1 = us;
         const int fr = (u1 == A) ? B : A;
         if (tp) {
@@ -435,8 +440,17 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
         }
         // ---- corrector (c = 1/2)
         T* f2[3] = {s.vel[fr][0], s.vel[fr][1], s.vel[fr][2]};
-        WL_TRY(ns_momentum<T>(field_of(s, u1, s.plane[P1]), un, f2, T(c.d.nu), true, ap, dt_dev,
-                              st));
+        if constexpr (sizeof(T) == 4) {
+            if (fuse)
+                WL_TRY(ns_momentum_proj(field_of(s, u1, s.plane[P1]), un, f2, float(c.d.nu), dt_dev,
+                                        s.p, float(pc.Lc), st));
+            else
+                WL_TRY(ns_momentum<T>(field_of(s, u1, s.plane[P1]), un, f2, T(c.d.nu), true, ap,
+                                      dt_dev, st));
+        } else {
+            WL_TRY(ns_momentum<T>(field_of(s, u1, s.plane[P1]), un, f2, T(c.d.nu), true, ap, dt_dev,
+                                  st));
+        }
         if (c.outflow)
             WL_TRY(ns_outflow<T>(c.g, s.vel[u1][0], s.plane[P1], s.plane[PS], s.vel[fr][0],
                                  T(c.d.U[0]), true, dt_dev, s.plane[P2], st));

@@ -158,7 +158,18 @@ __device__ __forceinline__ float flux2(float um2, float um1, float u0, float up1
     return fmaf(s, phi, -(nu2 * (u0 - um1)));
 }
 
-template <bool ALLPER, bool CORR>
+// A fetched plane: the velocity at the thread's load slots and, with PROJ,
+// the pressure there and at the slots' x-1 and y-1 neighbours.
+struct MtPlane {
+    float u[3][MT_LOADS];
+    float p[MT_LOADS], pxm[MT_LOADS], pym[MT_LOADS];
+};
+
+// PROJ (periodic, uniform coefficients): E holds the predictor's stage field
+// u* and pp its pressure; the kernel evaluates the projected field
+// u1 = u* - dt Lc grad(pp) as it fills its tile (the predictor's projection is
+// then never stored), with the same rounding as k_project.
+template <bool ALLPER, bool CORR, bool PROJ>
 __global__ __launch_bounds__(kBlock) void k_momentum_tiled(VelField<float> E,
                                                            const float* __restrict__ un0,
                                                            const float* __restrict__ un1,
@@ -167,7 +178,9 @@ __global__ __launch_bounds__(kBlock) void k_momentum_tiled(VelField<float> E,
                                                            float* __restrict__ f1,
                                                            float* __restrict__ f2, float nu,
                                                            const double* __restrict__ dt_dev,
-                                                           TileMap tm) {
+                                                           TileMap tm,
+                                                           const float* __restrict__ pp, float Lc) {
+    static_assert(!PROJ || ALLPER, "the fused projection assumes periodic wrap");
     __shared__ float sU[3][MT_NP][MT_PL];
     __shared__ float sFx[3][MT_Y][MT_X + 1];
     __shared__ float sFy[3][MT_Y + 1][MT_X];
@@ -183,6 +196,7 @@ __global__ __launch_bounds__(kBlock) void k_momentum_tiled(VelField<float> E,
     const int t = threadIdx.x, tx = t & 63, ty = t >> 6;
     const int lx = tx + 2, ly = ty + 2, own = ly * MT_LX + lx;
     const float hdt = 0.5f * float(*dt_dev);
+    const float cl = float(*dt_dev) * Lc;  // c dt L of the predictor projection (c = 1)
     const float nu2 = 2.f * nu;
     const int gx = x0 + tx, gy = y0 + ty;
     const bool inside = gx < g.n0 && gy < g.n1;
@@ -196,7 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_momentum_tiled(VelField<float> E,
     // load slots; with periodic wrap the x/y part of each global offset is
     // fixed for the whole column and computed once
     int lpos[MT_LOADS];
-    unsigned offxy[MT_LOADS];
+    unsigned offxy[MT_LOADS], offxm[MT_LOADS], offym[MT_LOADS];
     int pxs[MT_LOADS], pys[MT_LOADS];
     bool inxy[MT_LOADS];  // x/y position inside the grid (no ghost rule needed)
 #pragma unroll
@@ -209,17 +223,28 @@ __global__ __launch_bounds__(kBlock) void k_momentum_tiled(VelField<float> E,
         inxy[k] = pxs[k] >= 0 && pxs[k] < g.n0 && pys[k] >= 0 && pys[k] < g.n1;
         offxy[k] = ALLPER ? unsigned(wrapi(pxs[k], g.n0)) + unsigned(g.n0) * unsigned(wrapi(pys[k], g.n1))
                           : (inxy[k] ? unsigned(pxs[k]) + unsigned(g.n0) * unsigned(pys[k]) : 0u);
+        offxm[k] = PROJ ? unsigned(wrapi(pxs[k] - 1, g.n0)) + unsigned(g.n0) * unsigned(wrapi(pys[k], g.n1))
+                        : 0u;
+        offym[k] = PROJ ? unsigned(wrapi(pxs[k], g.n0)) + unsigned(g.n0) * unsigned(wrapi(pys[k] - 1, g.n1))
+                        : 0u;
     }
     const unsigned plane = unsigned(g.n0) * unsigned(g.n1);
-    auto fetch = [&](int zz, float (&r)[3][MT_LOADS]) {
+    auto fetch = [&](int zz, MtPlane& P) {
+        float (&r)[3][MT_LOADS] = P.u;
         if (ALLPER) {
             const int gz = zz < 0 ? zz + g.n2 : (zz >= g.n2 ? zz - g.n2 : zz);
             const unsigned base = unsigned(gz) * plane;
 #pragma unroll
             for (int k = 0; k < MT_LOADS; ++k)
-                if (lpos[k] >= 0)
+                if (lpos[k] >= 0) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) r[c][k] = E.u[c][base + offxy[k]];
+                    if (PROJ) {
+                        P.p[k] = pp[base + offxy[k]];
+                        P.pxm[k] = pp[base + offxm[k]];
+                        P.pym[k] = pp[base + offym[k]];
+                    }
+                }
         } else {
             const bool zin = zz >= 0 && zz < g.n2;
             const unsigned base = zin ? unsigned(zz) * plane : 0u;
@@ -237,7 +262,19 @@ __global__ __launch_bounds__(kBlock) void k_momentum_tiled(VelField<float> E,
         }
     };
     auto slot = [](int z) { return (z + MT_NP) % MT_NP; };  // z >= -1
-    auto store = [&](int zz, const float (&r)[3][MT_LOADS]) {
+    // u* -> u1 on a fetched plane; pb: the pressure of the plane below at
+    // the same slots
+    auto project = [&](MtPlane& P, const float (&pb)[MT_LOADS]) {
+#pragma unroll
+        for (int k = 0; k < MT_LOADS; ++k)
+            if (lpos[k] >= 0) {
+                P.u[0][k] = proj_face(P.u[0][k], cl, P.p[k], P.pxm[k]);
+                P.u[1][k] = proj_face(P.u[1][k], cl, P.p[k], P.pym[k]);
+                P.u[2][k] = proj_face(P.u[2][k], cl, P.p[k], pb[k]);
+            }
+    };
+    auto store = [&](int zz, const MtPlane& P) {
+        const float (&r)[3][MT_LOADS] = P.u;
         const int sl = slot(zz);
 #pragma unroll
         for (int k = 0; k < MT_LOADS; ++k)
@@ -247,16 +284,36 @@ __global__ __launch_bounds__(kBlock) void k_momentum_tiled(VelField<float> E,
     };
     auto U = [&](int c, int sl, int p) -> float { return sU[c][sl][p]; };
 
-    float PA[3][MT_LOADS], PB[3][MT_LOADS];
+    MtPlane PA, PB;
     float wm2[3];
     fetch(z0 - 1, PA);
     fetch(z0, PB);
 #pragma unroll
     for (int c = 0; c < 3; ++c) wm2[c] = tile_fetch<ALLPER>(E, c, gx, gy, z0 - 2);
+    if (PROJ) {
+        // plane z0 - 2: pressure at the slots (for plane z0 - 1) and the
+        // projected own-column value
+        const Grid& G = g;
+        auto pat = [&](int x, int y, int z) {
+            return pp[cid(G, wrapi(x, G.n0), wrapi(y, G.n1), wrapi(z, G.n2))];
+        };
+        const int gzm2 = wrapi(z0 - 2, g.n2);
+        float pm2[MT_LOADS];
+#pragma unroll
+        for (int k = 0; k < MT_LOADS; ++k)
+            pm2[k] = lpos[k] >= 0 ? pp[unsigned(gzm2) * plane + offxy[k]] : 0.f;
+        const float po = pat(gx, gy, z0 - 2);
+        wm2[0] = proj_face(wm2[0], cl, po, pat(gx - 1, gy, z0 - 2));
+        wm2[1] = proj_face(wm2[1], cl, po, pat(gx, gy - 1, z0 - 2));
+        wm2[2] = proj_face(wm2[2], cl, po, pat(gx, gy, z0 - 3));
+        project(PA, pm2);
+        project(PB, PA.p);
+    }
     store(z0 - 1, PA);
     store(z0, PB);
     fetch(z0 + 1, PA);
-    fetch(z0 + 2, PB);
+    if (PROJ) project(PA, PB.p);
+    fetch(z0 + 2, PB);  // projected when its plane is first used
     store(z0 + 1, PA);
     __syncthreads();
     // own-column window: planes z-1, z, z+1 (plane z+2 is slot 0 of the
@@ -278,10 +335,17 @@ __global__ __launch_bounds__(kBlock) void k_momentum_tiled(VelField<float> E,
 
     // One plane.  cur holds plane z + 2 (fetched one plane earlier), nxt
     // receives plane z + 3.
-    auto do_plane = [&](int z, float (&cur)[3][MT_LOADS], float (&nxt)[3][MT_LOADS]) {
+    auto do_plane = [&](int z, MtPlane& curP, MtPlane& nxt) {
         const int s0 = slot(z), sm1 = slot(z - 1), sp1 = slot(z + 1);
         const bool more = z + 1 < z1;
+        float pbelow[MT_LOADS];  // pressure of plane z + 1 (held by nxt until refetched)
+        if (PROJ) {
+#pragma unroll
+            for (int k = 0; k < MT_LOADS; ++k) pbelow[k] = nxt.p[k];
+        }
         if (more) fetch(z + 3, nxt);
+        if (PROJ) project(curP, pbelow);
+        const float (&cur)[3][MT_LOADS] = curP.u;
         const unsigned id = unsigned(gx) + unsigned(g.n0) * unsigned(gy) + plane * unsigned(z);
         float ubase[3] = {0.f, 0.f, 0.f};
         if (CORR && inside) {
@@ -362,7 +426,7 @@ __global__ __launch_bounds__(kBlock) void k_momentum_tiled(VelField<float> E,
             w0[c] = wp1[c];
             wp1[c] = cur[c][0];
         }
-        if (more) store(z + 2, cur);
+        if (more) store(z + 2, curP);
         __syncthreads();
     };
     for (int z = z0; z < z1; z += 2) {
@@ -579,7 +643,7 @@ __global__ __launch_bounds__(kBlock) void k_project(TileDev TL, VelField<T> V, c
     auto Lat = [&](int d, unsigned id) -> T { return UNIF ? C.Lc : C.L[d][id]; };
     // projected face d with lower cell offset dm (its cell holds pI)
     auto face = [&](int d, const T* u, unsigned id, int dm, T pI) -> T {
-        return u[id] - coef * Lat(d, id) * (pI - p[id + dm]);
+        return proj_face(u[id], coef * Lat(d, id), pI, p[id + dm]);
     };
     // CFL edge recompute: projected upper face of direction d of cell (i,j,k)
     auto upper = [&](int d, unsigned id, int k, T pI) -> T {
@@ -590,7 +654,7 @@ __global__ __launch_bounds__(kBlock) void k_project(TileDev TL, VelField<T> V, c
         if (q[d] + 1 < n[d] || per[d]) {
             const int du = q[d] + 1 < n[d] ? st[d] : -st[d] * (n[d] - 1);
             const unsigned idu = id + du;
-            return V.u[d][idu] - coef * Lat(d, idu) * (p[idu] - pI);
+            return proj_face(V.u[d][idu], coef * Lat(d, idu), p[idu], pI);
         }
         return vget<T, ALLPER>(V, d, i + (d == 0), j + (d == 1), k + (d == 2));
     };
@@ -613,10 +677,10 @@ __global__ __launch_bounds__(kBlock) void k_project(TileDev TL, VelField<T> V, c
             if (d3 && (carry || CFL)) {
                 if (k + 1 < g.n2) {
                     pU = p[id + plane];
-                    wup = sz[id + plane] - coef * Lat(2, id + plane) * (pU - pI);
+                    wup = proj_face(sz[id + plane], coef * Lat(2, id + plane), pU, pI);
                 } else if (per2) {
                     const unsigned i0 = id - plane * unsigned(g.n2 - 1);
-                    wup = sz[i0] - coef * Lat(2, i0) * (p[i0] - pI);
+                    wup = proj_face(sz[i0], coef * Lat(2, i0), p[i0], pI);
                 } else {
                     wup = vget<T, ALLPER>(V, 2, i, j, k + 1);
                 }
@@ -825,8 +889,9 @@ wl_status ns_momentum(const VelField<T>& E, const T* const un[3], T* const f[3],
         if (g.ndim == 3) {
             const TileMap tm = tile_map(g, MT_X, MT_Y, momentum_zchunk());
 #define WL_MT(AP, CR)                                                                          \
-    k_momentum_tiled<AP, CR><<<tm.nblocks, kBlock, 0, s>>>(E, un[0], un[1], un[2], f[0], f[1], \
-                                                           f[2], nu, dt_dev, tm)
+    k_momentum_tiled<AP, CR, false><<<tm.nblocks, kBlock, 0, s>>>(E, un[0], un[1], un[2], f[0],  \
+                                                                  f[1], f[2], nu, dt_dev, tm,  \
+                                                                  nullptr, 0.f)
             if (allper) {
                 if (corr) WL_MT(true, true); else WL_MT(true, false);
             } else {
@@ -846,6 +911,23 @@ wl_status ns_momentum(const VelField<T>& E, const T* const un[3], T* const f[3],
         if (corr) WL_MOM(false, true); else WL_MOM(false, false);
     }
 #undef WL_MOM
+    WL_CHECK_LAUNCH();
+    return WL_OK;
+}
+
+wl_status ns_momentum_proj(const VelField<float>& E, const float* const un[3], float* const f[3],
+                           float nu, const double* dt_dev, const float* p, float Lc,
+                           hipStream_t s) {
+    const Grid& g = E.g;
+    if (g.ndim != 3 || !(g.per0 && g.per1 && g.per2)) {
+        set_error("fused projection needs a periodic 3D grid");
+        return WL_ERR_INVALID_ARG;
+    }
+    ProfScope ps(WL_PROF_MOMENTUM, s, cells(g));
+    const TileMap tm = tile_map(g, MT_X, MT_Y, momentum_zchunk());
+    k_momentum_tiled<true, true, true><<<tm.nblocks, kBlock, 0, s>>>(E, un[0], un[1], un[2], f[0],
+                                                                     f[1], f[2], nu, dt_dev, tm, p,
+                                                                     Lc);
     WL_CHECK_LAUNCH();
     return WL_OK;
 }

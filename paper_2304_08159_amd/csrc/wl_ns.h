@@ -64,6 +64,13 @@ wl_status ns_measure(const Grid& g, const BodyDev& body, const int bclo[3], cons
 template <typename T>
 wl_status ns_momentum(const VelField<T>& E, const T* const un[3], T* const f[3], T nu, bool corr,
                       bool allper, const double* dt_dev, hipStream_t s);
+// Corrector convection-diffusion of a periodic FP32 3D grid with uniform
+// coefficients Lc whose predictor projection was not stored: E holds the
+// predictor stage field u* and p its pressure; the kernel uses
+// u1 = u* - dt Lc grad(p) (same rounding as ns_project).
+wl_status ns_momentum_proj(const VelField<float>& E, const float* const un[3], float* const f[3],
+                           float nu, const double* dt_dev, const float* p, float Lc,
+                           hipStream_t s);
 template <typename T>
 wl_status ns_outflow(const Grid& g, const T* ue_x, const T* out_e, const T* out_n, const T* f_x,
                      T Ux, bool corr, const double* dt_dev, T* fout, hipStream_t s);

@@ -67,6 +67,16 @@ __device__ __forceinline__ T vget(const VelField<T>& V, int c, int i, int j, int
     return V.u[c][cid(g, q[0], q[1], q[2])];
 }
 
+// Pressure-gradient update of one face: u - cl (p_here - p_lower) with
+// cl = c dt L, one rounding (shared by the projection kernel and the
+// momentum kernel that applies the predictor projection on the fly).
+__device__ __forceinline__ float proj_face(float u, float cl, float ph, float pl) {
+    return fmaf(-cl, ph - pl, u);
+}
+__device__ __forceinline__ double proj_face(double u, double cl, double ph, double pl) {
+    return fma(-cl, ph - pl, u);
+}
+
 __device__ __forceinline__ float med3(float a, float b, float c) {
     return __builtin_amdgcn_fmed3f(a, b, c);
 }
