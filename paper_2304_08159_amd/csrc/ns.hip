@@ -83,8 +83,8 @@ __global__ __launch_bounds__(kBlock) void k_momentum(TileDev TL, VelField<T> E, 
 }
 
 // ---------------------------------------------------------------------------
-// LDS-tiled convection-diffusion for FP32 3D grids.  A block owns a 64 x 4
-// column of cells and marches through a chunk of z planes.  Planes z-1, z,
+// LDS-tiled convection-diffusion for FP32 3D grids.  A block of 512 threads
+// owns a 64 x 8 column of cells and marches through a chunk of z planes.  Planes z-1, z,
 // z+1 of all three components (with a two-cell x/y halo) sit in a 3-plane LDS
 // ring; the thread's own column of planes z-2 .. z+2 is kept in registers for
 // the z stencil.  Planes are fetched two ahead into alternating register sets
@@ -98,12 +98,11 @@ __global__ __launch_bounds__(kBlock) void k_momentum(TileDev TL, VelField<T> E, 
 // are remapped so that each XCD (blocks are dealt round-robin to the 8 XCDs)
 // walks a contiguous range of tiles and shares halo rows through its L2.
 namespace {
-constexpr int MT_X = 64, MT_Y = 4;
+constexpr int MT_X = 64, MT_Y = 8, MT_T = MT_X * MT_Y;  // MT_T threads per block
 constexpr int MT_LX = MT_X + 4, MT_LY = MT_Y + 4, MT_PL = MT_LX * MT_LY;
 constexpr int MT_NP = 3;
 constexpr int MT_HALO = MT_PL - MT_X * MT_Y;
-constexpr int MT_LOADS = 1 + (MT_HALO + kBlock - 1) / kBlock;
-static_assert(kBlock == MT_X * MT_Y, "one thread per tile column");
+constexpr int MT_LOADS = 1 + (MT_HALO + MT_T - 1) / MT_T;
 }  // namespace
 
 __device__ __forceinline__ int wrapi(int a, int n) {
@@ -118,7 +117,7 @@ __device__ __forceinline__ int wrapi(int a, int n) {
 // consecutive x.
 __device__ __forceinline__ int mt_pos(int t, int k) {
     if (k == 0) return ((t >> 6) + 2) * MT_LX + (t & 63) + 2;
-    const int h = t + (k - 1) * kBlock;
+    const int h = t + (k - 1) * MT_T;
     if (h >= MT_HALO) return -1;
     if (h < 4 * MT_LX) {
         const int r = h / MT_LX, x = h - r * MT_LX;
@@ -170,7 +169,7 @@ struct MtPlane {
 // u1 = u* - dt Lc grad(pp) as it fills its tile (the predictor's projection is
 // then never stored), with the same rounding as k_project.
 template <bool ALLPER, bool CORR, bool PROJ>
-__global__ __launch_bounds__(kBlock) void k_momentum_tiled(VelField<float> E,
+__global__ __launch_bounds__(MT_T) void k_momentum_tiled(VelField<float> E,
                                                            const float* __restrict__ un0,
                                                            const float* __restrict__ un1,
                                                            const float* __restrict__ un2,
@@ -889,7 +888,7 @@ wl_status ns_momentum(const VelField<T>& E, const T* const un[3], T* const f[3],
         if (g.ndim == 3) {
             const TileMap tm = tile_map(g, MT_X, MT_Y, momentum_zchunk());
 #define WL_MT(AP, CR)                                                                          \
-    k_momentum_tiled<AP, CR, false><<<tm.nblocks, kBlock, 0, s>>>(E, un[0], un[1], un[2], f[0],  \
+    k_momentum_tiled<AP, CR, false><<<tm.nblocks, MT_T, 0, s>>>(E, un[0], un[1], un[2], f[0],    \
                                                                   f[1], f[2], nu, dt_dev, tm,  \
                                                                   nullptr, 0.f)
             if (allper) {
@@ -925,7 +924,7 @@ wl_status ns_momentum_proj(const VelField<float>& E, const float* const un[3], f
     }
     ProfScope ps(WL_PROF_MOMENTUM, s, cells(g));
     const TileMap tm = tile_map(g, MT_X, MT_Y, momentum_zchunk());
-    k_momentum_tiled<true, true, true><<<tm.nblocks, kBlock, 0, s>>>(E, un[0], un[1], un[2], f[0],
+    k_momentum_tiled<true, true, true><<<tm.nblocks, MT_T, 0, s>>>(E, un[0], un[1], un[2], f[0],
                                                                      f[1], f[2], nu, dt_dev, tm, p,
                                                                      Lc);
     WL_CHECK_LAUNCH();
