@@ -150,13 +150,21 @@ def poisson_compare(torch, wl, W, n, radius=32.0, tol=1e-8, reps=3):
 
 def serving_bench(count=512, seed=2304, budget=16e9, slots=8):
     """Served mix: sizes uniform over 2D {64^2,128^2,256^2} and 3D {64^3,96^3,128^3},
-    half Poisson solves (FP32 V-cycles + FP64 refinement to 1e-8), half 20-step NS
-    runs with a body; HBM budget 16 GB; saturated throughput first (all requests at
+    half Poisson solves, half 20-step NS runs with a body; HBM budget 16 GB.
+    Poisson requests of at most 65536 cells are batched into one persistent
+    work-queue kernel (FP64, to 1e-8), larger ones run alone (FP32 V-cycles +
+    FP64 refinement to 1e-8).  Saturated throughput first (all requests at
     t = 0), then Poisson arrivals at 0.5 and 0.8 of it."""
     from paper_2304_08159_amd.serving import GpuExecutor, Server, make_requests, summarize
     ex = GpuExecutor()
     Server(ex, budget, slots=slots).run(make_requests(count=16, seed=seed + 1))   # warm-up
-    sat = summarize(Server(ex, budget, slots=slots).run(make_requests(count=count, seed=seed)))
+
+    def batch_stats(srv):
+        return dict(units=len(srv.batches),
+                    mean_size=(sum(srv.batches) / len(srv.batches)) if srv.batches else 0.0)
+    srv = Server(ex, budget, slots=slots)
+    sat = summarize(srv.run(make_requests(count=count, seed=seed)))
+    sat["batched"] = batch_stats(srv)
     mu = sat["throughput_rps"]
     res = {"saturated": sat}
     for frac in (0.5, 0.8):
@@ -164,8 +172,10 @@ def serving_bench(count=512, seed=2304, budget=16e9, slots=8):
         r = summarize(srv.run(make_requests(count=count, seed=seed, rate=frac * mu)))
         r["arrival_rate_rps"] = frac * mu
         r["peak_bytes"] = srv.peak_bytes
+        r["batched"] = batch_stats(srv)
         res[f"rate_{frac}"] = r
-    res["config"] = dict(requests=count, budget_bytes=budget, slots=slots, seed=seed)
+    res["config"] = dict(requests=count, budget_bytes=budget, slots=slots, seed=seed,
+                         batch_cells=ex.batch_cells)
     return res
 
 

@@ -208,6 +208,49 @@ wl_status wl_poisson_solve(wl_poisson* ps, const void* coeffs, void* x, const vo
                            double* rel_resid_out);
 wl_status wl_poisson_destroy(wl_poisson* ps);
 
+/* ---- Batched small Poisson solves (serving) ------------------------------ */
+
+/* One Poisson problem of a batch: the same operator, method and stopping rule
+ * as wl_poisson_solve (Sec. 2, project!) in FP64.  coeffs: ndim face arrays of
+ * double (layout above; zero faces are walls / solid); x: initial guess in,
+ * solution out (double); b: right-hand side (double, projected onto the
+ * active cells and made mean-free there by the solver, not modified).  All
+ * device pointers owned by the caller.  At most 262144 cells; the coarsest
+ * multigrid level (every direction halved while all are even and >= 8) must
+ * have at most 1024 cells. */
+typedef struct {
+    int ndim;
+    int n[3];
+    int periodic[3];
+    const void* coeffs;
+    void* x;
+    const void* b;
+    double tol;           /* stop once ||b - A x|| <= tol ||b||              */
+    int max_vcycles;
+} wl_batch_request;
+
+typedef struct {
+    int status;           /* WL_OK, WL_ERR_NOT_CONVERGED or WL_ERR_NONFINITE  */
+    int vcycles;
+    double rel_resid;
+} wl_batch_result;
+
+/* Exact device workspace for wl_poisson_batch_solve on these requests (host
+ * only; pointers may be NULL here).  WL_ERR_INVALID_ARG names the first
+ * request that is malformed or too large. */
+wl_status wl_poisson_batch_footprint(const wl_batch_request* reqs, int count, size_t* bytes);
+
+/* Solves count requests with one persistent kernel on hip_stream: its
+ * workgroups (at most one per compute unit) take requests from a device work
+ * queue until it is empty, one request per workgroup at a time.  Every
+ * reduction is a fixed-order workgroup sum, so each request's result is
+ * bitwise independent of the batch it is in.  workspace: >= the footprint,
+ * 256-byte aligned.  results: count entries (host), filled on return
+ * (synchronises the stream).  Returns WL_OK when every request converged,
+ * else the first failing request's status. */
+wl_status wl_poisson_batch_solve(const wl_batch_request* reqs, int count, void* workspace,
+                                 size_t ws_bytes, void* hip_stream, wl_batch_result* results);
+
 /* BDIM-modified Poisson coefficients of a body (Sec. 2): L_i = mu0 of the
  * signed distance at every lower i-face centre (cosine kernel of half-width
  * body->eps, <= 0 selects 1 cell), zero on non-periodic lower boundary faces;

@@ -17,7 +17,7 @@ from ._lib import (FIELD_L0, FIELD_MU0_0, FIELD_MU1N, FIELD_P, FIELD_SIGMA, FIEL
                    FIELD_UOUT, INFLOW, OUTFLOW, PERIODIC, WALL, WL_FP32, WL_FP64, WL_MIXED,
                    WlError, check, load)
 
-__all__ = ["Sim", "Poisson", "body_coeffs", "set_graphs", "load", "WlError", "WL_FP32", "WL_FP64", "WL_MIXED",
+__all__ = ["Sim", "Poisson", "body_coeffs", "set_graphs", "poisson_batch_solve", "load", "WlError", "WL_FP32", "WL_FP64", "WL_MIXED",
            "PERIODIC", "INFLOW", "OUTFLOW", "WALL"]
 
 
@@ -176,6 +176,49 @@ class Sim:
               allow=(-3,) if allow_not_converged else ())
         return dict(dt=st.dt, t=st.t, vcycles=(st.vcycles[0], st.vcycles[1]),
                     resid=(st.resid[0], st.resid[1]))
+
+
+def poisson_batch_solve(requests, allow_not_converged=False):
+    """Solve many small Poisson problems with one persistent kernel (FP64).
+
+    requests: list of dicts with n (2 or 3 ints), periodic, coeffs (float64
+    tensor (ndim, n2, n1, n0)), x (float64, guess in / solution out), b
+    (float64), tol (relative, default 1e-8), max_vcycles (default 200).
+    Returns a list of (status, vcycles, rel_resid)."""
+    torch = _torch()
+    lib = load()
+    count = len(requests)
+    if count == 0:
+        return []
+    arr = (_lib.BatchRequest * count)()
+    dev = None
+    for q, r in enumerate(requests):
+        n = [int(m) for m in r["n"]]
+        ndim = len(n)
+        per = [int(bool(p)) for p in r.get("periodic", (False,) * ndim)]
+        for t in ("coeffs", "x", "b"):
+            ten = r[t]
+            if ten.dtype != torch.float64 or not ten.is_cuda or not ten.is_contiguous():
+                raise ValueError(f"request {q}: {t} must be a contiguous float64 CUDA tensor")
+            dev = ten.device
+        a = arr[q]
+        a.ndim = ndim
+        for i in range(3):
+            a.n[i] = (n + [1] * (3 - ndim))[i]
+            a.periodic[i] = (per + [0] * (3 - ndim))[i]
+        a.coeffs = r["coeffs"].data_ptr()
+        a.x = r["x"].data_ptr()
+        a.b = r["b"].data_ptr()
+        a.tol = float(r.get("tol", 1e-8))
+        a.max_vcycles = int(r.get("max_vcycles", 200))
+    nbytes = ctypes.c_size_t()
+    check(lib.wl_poisson_batch_footprint(arr, count, ctypes.byref(nbytes)))
+    ws, ptr, nb = _workspace(torch, nbytes.value, dev)
+    res = (_lib.BatchResult * count)()
+    allow = (-3,) if allow_not_converged else ()
+    check(lib.wl_poisson_batch_solve(arr, count, ptr, nb, _stream(torch), res), allow=allow)
+    del ws
+    return [(res[q].status, res[q].vcycles, res[q].rel_resid) for q in range(count)]
 
 
 def set_graphs(enable=True):

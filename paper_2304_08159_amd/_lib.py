@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwl.so")
 
 WL_OK = 0
+WL_ERR_INVALID_ARG, WL_ERR_NOT_CONVERGED, WL_ERR_NONFINITE = -1, -3, -4
 STATUS = {
     0: "WL_OK", -1: "WL_ERR_INVALID_ARG", -2: "WL_ERR_OUT_OF_MEMORY",
     -3: "WL_ERR_NOT_CONVERGED", -4: "WL_ERR_NONFINITE", -5: "WL_ERR_HIP", -6: "WL_ERR_STATE",
@@ -28,7 +29,8 @@ EXPORTS = (
     "wl_sim_footprint", "wl_sim_create", "wl_sim_destroy", "wl_set_field", "wl_get_field",
     "wl_set_time", "wl_step", "wl_drag", "wl_tape_record", "wl_step_adjoint",
     "wl_poisson_footprint", "wl_poisson_create",
-    "wl_poisson_solve", "wl_poisson_destroy", "wl_body_coeffs", "wl_set_graphs",
+    "wl_poisson_solve", "wl_poisson_destroy", "wl_poisson_batch_footprint",
+    "wl_poisson_batch_solve", "wl_body_coeffs", "wl_set_graphs",
     "wl_profile_enable",
     "wl_profile_reset",
     "wl_profile_read", "wl_last_error", "wl_version",
@@ -55,6 +57,16 @@ class SimDesc(ctypes.Structure):
                 ("prec", ctypes.c_int), ("mg_levels", ctypes.c_int), ("tol", ctypes.c_double),
                 ("max_vcycles", ctypes.c_int), ("inner_vcycles", ctypes.c_int),
                 ("cfl", ctypes.c_double), ("tape_steps", ctypes.c_int)]
+
+
+class BatchRequest(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int * 3), ("periodic", ctypes.c_int * 3),
+                ("coeffs", ctypes.c_void_p), ("x", ctypes.c_void_p), ("b", ctypes.c_void_p),
+                ("tol", ctypes.c_double), ("max_vcycles", ctypes.c_int)]
+
+
+class BatchResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("vcycles", ctypes.c_int), ("rel_resid", ctypes.c_double)]
 
 
 class StepStats(ctypes.Structure):
@@ -90,6 +102,9 @@ def load():
         "wl_poisson_create": [i32, ip3, ip3, i32, i32, vp, sz, vp, ctypes.POINTER(vp)],
         "wl_poisson_solve": [vp, vp, vp, vp, f64, i32, ctypes.POINTER(i32), ctypes.POINTER(f64)],
         "wl_poisson_destroy": [vp],
+        "wl_poisson_batch_footprint": [ctypes.POINTER(BatchRequest), i32, ctypes.POINTER(sz)],
+        "wl_poisson_batch_solve": [ctypes.POINTER(BatchRequest), i32, vp, sz, vp,
+                                   ctypes.POINTER(BatchResult)],
         "wl_body_coeffs": [ctypes.POINTER(Body), i32, ip3, ip3, i32, vp, vp],
         "wl_set_graphs": [i32],
         "wl_profile_enable": [ctypes.c_uint],

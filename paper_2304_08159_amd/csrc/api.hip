@@ -15,6 +15,7 @@ namespace wl {
 static thread_local std::string g_err;
 void set_error(const std::string& msg) { g_err = msg; }
 void clear_error() { g_err.clear(); }
+const std::string& last_error_text() { return g_err; }
 
 static wl_status invalid(const std::string& msg) {
     set_error(msg);

@@ -1,0 +1,416 @@
+// Batched Poisson solves for many small problems: one persistent kernel whose
+// workgroups take requests from a device work queue (an atomic head index
+// over the request table) until it is empty; a request is solved entirely by
+// the workgroup that took it, with the same method as wl_poisson_solve
+// (Sec. 2's project!: matrix-free GMG, damped Jacobi, sum restriction,
+// piecewise-constant prolongation, coarse coefficients = 1/2 the covered fine
+// faces, minimum-norm coarsest solve) in FP64.  Every reduction is a
+// fixed-order workgroup sum, so a request's result does not depend on which
+// workgroup solved it or on the rest of the batch.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "wl_cg.h"
+#include "wl_device.h"
+#include "wl_internal.h"
+
+namespace wl {
+namespace {
+
+constexpr int kBatchThreads = 1024;
+constexpr size_t kBatchMaxCells = 262144;  // per request (e.g. 512^2, 64^3)
+
+struct BatchLevel {
+    Grid g;
+    double* x[2];  // level 0: x[0] is the caller's solution
+    double* b;     // level 0: the projected right-hand side
+    double* L[3];  // face coefficients (level 0: the caller's, read only)
+};
+
+struct BatchReq {
+    int nlev;
+    double tol, omega;
+    int max_vcycles;
+    const double* b_in;
+    BatchLevel lev[kMaxLevels];
+};
+
+struct BatchRes {
+    int status, vcycles;
+    double rel;
+};
+
+__device__ __forceinline__ void coords_of(const Grid& g, int c, int& i, int& j, int& k) {
+    i = c % g.n0;
+    const int q = c / g.n0;
+    j = q % g.n1;
+    k = q / g.n1;
+}
+
+// Fixed-order sum over the workgroup, returned to every thread.
+__device__ double wg_sum(double v, double* red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < int(blockDim.x + 63) / 64; ++w) s += red[w];
+    __syncthreads();
+    return s;
+}
+
+__device__ __forceinline__ Coeffs<double> coeffs(const BatchLevel& L) {
+    return Coeffs<double>{L.L[0], L.L[1], L.L[2], 1.0};
+}
+
+// xout = x - w (b - A x) / D on active cells, 0 elsewhere; returns
+// sum (b - A x)^2 when norm (0 otherwise).
+template <int XM>
+__device__ double wg_sweep(const BatchLevel& L, const XAccess<double, XM>& X, const double* b,
+                           double w, double* xout, bool norm, double* red) {
+    const Coeffs<double> C = coeffs(L);
+    const int N = int(cells(L.g));
+    double r2 = 0.0;
+    for (int c = threadIdx.x; c < N; c += blockDim.x) {
+        int i, j, k;
+        coords_of(L.g, c, i, j, k);
+        double xI, Ax, D;
+        apply_row<double, XM, false>(L.g, X, C, i, j, k, xI, Ax, D);
+        const double r = b[c] - Ax;
+        xout[c] = D > 0.0 ? xI - w * r / D : 0.0;
+        r2 += r * r;
+    }
+    __syncthreads();
+    return norm ? wg_sum(r2, red) : 0.0;
+}
+
+// Coarse right-hand side = sum of the child residuals b - A x.
+__device__ void wg_restrict(const BatchLevel& F, const double* x, const double* b,
+                            const BatchLevel& Cl) {
+    const Coeffs<double> C = coeffs(F);
+    const XAccess<double, XM_PLAIN> X{x, nullptr, 0, 0};
+    const int Nc = int(cells(Cl.g));
+    const int fz = F.g.n2 > Cl.g.n2 ? 2 : 1;
+    for (int c = threadIdx.x; c < Nc; c += blockDim.x) {
+        int ic, jc, kc;
+        coords_of(Cl.g, c, ic, jc, kc);
+        double sum = 0.0;
+        for (int dz = 0; dz < fz; ++dz)
+            for (int dy = 0; dy < 2; ++dy)
+                for (int dx = 0; dx < 2; ++dx) {
+                    const int i = 2 * ic + dx, j = 2 * jc + dy, k = fz * kc + dz;
+                    double xI, Ax, D;
+                    apply_row<double, XM_PLAIN, false>(F.g, X, C, i, j, k, xI, Ax, D);
+                    sum += b[cid(F.g, i, j, k)] - Ax;
+                }
+        Cl.b[c] = sum;
+    }
+    __syncthreads();
+}
+
+// Coarse coefficient = 1/2 the sum of the fine faces it covers.
+__device__ void wg_coarsen(const BatchLevel& F, const BatchLevel& Cl) {
+    const int Nc = int(cells(Cl.g));
+    const int fz = F.g.n2 > Cl.g.n2 ? 2 : 1;
+    for (int c = threadIdx.x; c < Nc; c += blockDim.x) {
+        int i, j, k;
+        coords_of(Cl.g, c, i, j, k);
+        const int I = 2 * i, J = 2 * j, K = fz * k;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int dz = 0; dz < fz; ++dz)
+            for (int dy = 0; dy < 2; ++dy) s0 += F.L[0][cid(F.g, I, J + dy, K + dz)];
+        for (int dz = 0; dz < fz; ++dz)
+            for (int dx = 0; dx < 2; ++dx) s1 += F.L[1][cid(F.g, I + dx, J, K + dz)];
+        Cl.L[0][c] = 0.5 * s0;
+        Cl.L[1][c] = 0.5 * s1;
+        if (F.g.ndim == 3) {
+            for (int dy = 0; dy < 2; ++dy)
+                for (int dx = 0; dx < 2; ++dx) s2 += F.L[2][cid(F.g, I + dx, J + dy, K)];
+            Cl.L[2][c] = 0.5 * s2;
+        }
+    }
+    __syncthreads();
+}
+
+__device__ void solve_one(const BatchReq& q, BatchRes& res, CoarseLds& S) {
+    const BatchLevel& F = q.lev[0];
+    const int nlev = q.nlev;
+    const double w = q.omega;
+    double* red = S.red;
+    double* x = F.x[0];
+    double* x1 = F.x[1];
+    const int N = int(cells(F.g));
+    for (int l = 1; l < nlev; ++l) wg_coarsen(q.lev[l - 1], q.lev[l]);
+    // right-hand side projected onto the active cells, mean-free there
+    {
+        const XAccess<double, XM_ZERO> Z{nullptr, nullptr, 0, 0};
+        const Coeffs<double> C = coeffs(F);
+        double sb = 0.0, cnt = 0.0;
+        for (int c = threadIdx.x; c < N; c += blockDim.x) {
+            int i, j, k;
+            coords_of(F.g, c, i, j, k);
+            double xI, Ax, D;
+            apply_row<double, XM_ZERO, false>(F.g, Z, C, i, j, k, xI, Ax, D);
+            if (D > 0.0) {
+                sb += q.b_in[c];
+                cnt += 1.0;
+            }
+        }
+        sb = wg_sum(sb, red);
+        cnt = wg_sum(cnt, red);
+        const double mean = cnt > 0.0 ? sb / cnt : 0.0;
+        double b2 = 0.0;
+        for (int c = threadIdx.x; c < N; c += blockDim.x) {
+            int i, j, k;
+            coords_of(F.g, c, i, j, k);
+            double xI, Ax, D;
+            apply_row<double, XM_ZERO, false>(F.g, Z, C, i, j, k, xI, Ax, D);
+            const double bv = D > 0.0 ? q.b_in[c] - mean : 0.0;
+            F.b[c] = bv;
+            b2 += bv * bv;
+        }
+        __syncthreads();
+        b2 = wg_sum(b2, red);
+        if (b2 == 0.0) {
+            for (int c = threadIdx.x; c < N; c += blockDim.x) x[c] = 0.0;
+            __syncthreads();
+            if (threadIdx.x == 0) res = BatchRes{WL_OK, 0, 0.0};
+            return;
+        }
+        S.x[0] = b2;  // (kept for the final relative residual)
+    }
+    const double b2 = S.x[0];
+    __syncthreads();
+    const double tol2 = q.tol * q.tol * b2;
+    // first sweep of the first V-cycle, with the norm of the initial residual
+    double r2 = wg_sweep<XM_PLAIN>(F, XAccess<double, XM_PLAIN>{x, nullptr, 0, 0}, F.b, w, x1, true,
+                                   red);
+    int k = 0;
+    int status = WL_OK;
+    while (!(r2 <= tol2) && k < q.max_vcycles) {
+        if (!isfinite(r2)) {
+            status = WL_ERR_NONFINITE;
+            break;
+        }
+        if (nlev == 1) {
+            coarse_cg_block<double>(F.g, coeffs(F), 0, F.b, x, 1e-10, N + 64, S);
+        } else {
+            wg_sweep<XM_PLAIN>(F, XAccess<double, XM_PLAIN>{x1, nullptr, 0, 0}, F.b, w, x, false,
+                               red);
+            wg_restrict(F, x, F.b, q.lev[1]);
+            for (int l = 1; l < nlev - 1; ++l) {
+                const BatchLevel& L = q.lev[l];
+                wg_sweep<XM_ZERO>(L, XAccess<double, XM_ZERO>{nullptr, nullptr, 0, 0}, L.b, w,
+                                  L.x[0], false, red);
+                wg_sweep<XM_PLAIN>(L, XAccess<double, XM_PLAIN>{L.x[0], nullptr, 0, 0}, L.b, w,
+                                   L.x[1], false, red);
+                wg_restrict(L, L.x[1], L.b, q.lev[l + 1]);
+            }
+            const BatchLevel& Cst = q.lev[nlev - 1];
+            coarse_cg_block<double>(Cst.g, coeffs(Cst), 0, Cst.b, Cst.x[1], 1e-10,
+                                    int(cells(Cst.g)) + 64, S);
+            for (int l = nlev - 2; l >= 1; --l) {
+                const BatchLevel& L = q.lev[l];
+                const BatchLevel& C = q.lev[l + 1];
+                wg_sweep<XM_PROLONG>(L, XAccess<double, XM_PROLONG>{L.x[1], C.x[1], C.g.n0, C.g.n1},
+                                     L.b, w, L.x[0], false, red);
+                wg_sweep<XM_PLAIN>(L, XAccess<double, XM_PLAIN>{L.x[0], nullptr, 0, 0}, L.b, w,
+                                   L.x[1], false, red);
+            }
+            const BatchLevel& C1 = q.lev[1];
+            wg_sweep<XM_PROLONG>(F, XAccess<double, XM_PROLONG>{x, C1.x[1], C1.g.n0, C1.g.n1}, F.b,
+                                 w, x1, false, red);
+            wg_sweep<XM_PLAIN>(F, XAccess<double, XM_PLAIN>{x1, nullptr, 0, 0}, F.b, w, x, false,
+                               red);
+        }
+        ++k;
+        r2 = wg_sweep<XM_PLAIN>(F, XAccess<double, XM_PLAIN>{x, nullptr, 0, 0}, F.b, w, x1, true,
+                                red);
+    }
+    if (status == WL_OK && !isfinite(r2)) status = WL_ERR_NONFINITE;
+    if (status == WL_OK && !(r2 <= tol2)) status = WL_ERR_NOT_CONVERGED;
+    if (threadIdx.x == 0) res = BatchRes{status, k, sqrt(r2 / b2)};
+    __syncthreads();
+}
+
+// Persistent kernel: each workgroup takes the next request from the queue
+// until none is left (every workgroup reaches the exit).
+__global__ __launch_bounds__(kBatchThreads) void k_poisson_batch(const BatchReq* __restrict__ reqs,
+                                                                 int count, unsigned* head,
+                                                                 BatchRes* __restrict__ res) {
+    __shared__ CoarseLds S;
+    __shared__ int take;
+    for (;;) {
+        if (threadIdx.x == 0) take = int(atomicAdd(head, 1u));
+        __syncthreads();
+        const int r = take;
+        __syncthreads();
+        if (r >= count) return;
+        solve_one(reqs[r], res[r], S);
+    }
+}
+
+// Checks one request and fills its descriptor, carving its level arrays.
+wl_status plan_one(const wl_batch_request& in, Carver& c, BatchReq& q) {
+    const int ndim = in.ndim;
+    if (ndim != 2 && ndim != 3) return set_error("batch request: ndim must be 2 or 3"), WL_ERR_INVALID_ARG;
+    if (ndim == 2 && in.n[2] != 1) {
+        set_error("batch request: 2D problems need n[2] == 1");
+        return WL_ERR_INVALID_ARG;
+    }
+    for (int d = 0; d < ndim; ++d)
+        if (in.n[d] < 2) {
+            set_error("batch request: every direction needs at least 2 cells");
+            return WL_ERR_INVALID_ARG;
+        }
+    const size_t N = size_t(in.n[0]) * in.n[1] * in.n[2];
+    if (N > kBatchMaxCells) {
+        set_error("batch request larger than 262144 cells (use wl_poisson_solve)");
+        return WL_ERR_INVALID_ARG;
+    }
+    if (!(in.tol >= 0.0) || in.max_vcycles < 0) {
+        set_error("batch request: tol must be >= 0 and max_vcycles >= 0");
+        return WL_ERR_INVALID_ARG;
+    }
+    const int nlev = auto_levels(ndim, in.n, 0);
+    int m[3] = {in.n[0], in.n[1], in.n[2]};
+    for (int l = 1; l < nlev; ++l)
+        for (int d = 0; d < ndim; ++d) m[d] /= 2;
+    if (size_t(m[0]) * m[1] * m[2] > size_t(kCoarseMax)) {
+        set_error("batch request: coarsest multigrid level exceeds 1024 cells");
+        return WL_ERR_INVALID_ARG;
+    }
+    q = BatchReq{};
+    q.nlev = nlev;
+    q.tol = in.tol;
+    q.omega = 2.0 * ndim / (2.0 * ndim + 1.0);
+    q.max_vcycles = in.max_vcycles;
+    q.b_in = static_cast<const double*>(in.b);
+    int n[3] = {in.n[0], in.n[1], in.n[2]};
+    for (int l = 0; l < nlev; ++l) {
+        BatchLevel& L = q.lev[l];
+        L.g = Grid{n[0], n[1], n[2], in.periodic[0] != 0, in.periodic[1] != 0,
+                   ndim == 3 && in.periodic[2] != 0, ndim};
+        const size_t Nl = size_t(n[0]) * n[1] * n[2];
+        if (l == 0) {
+            L.x[0] = static_cast<double*>(in.x);
+            L.x[1] = c.take<double>(Nl);
+            L.b = c.take<double>(Nl);
+            const double* co = static_cast<const double*>(in.coeffs);
+            for (int d = 0; d < 3; ++d) L.L[d] = d < ndim ? const_cast<double*>(co + d * Nl) : nullptr;
+        } else {
+            L.x[0] = c.take<double>(Nl);
+            L.x[1] = c.take<double>(Nl);
+            L.b = c.take<double>(Nl);
+            for (int d = 0; d < 3; ++d) L.L[d] = d < ndim ? c.take<double>(Nl) : nullptr;
+        }
+        for (int d = 0; d < ndim; ++d) n[d] /= 2;
+    }
+    return WL_OK;
+}
+
+struct BatchLayout {
+    std::vector<BatchReq> reqs;
+    BatchReq* dev_reqs = nullptr;
+    BatchRes* dev_res = nullptr;
+    unsigned* dev_head = nullptr;
+};
+
+wl_status plan(const wl_batch_request* reqs, int count, Carver& c, BatchLayout& lay) {
+    if (count < 0) return set_error("count must be >= 0"), WL_ERR_INVALID_ARG;
+    if (count > 0 && !reqs) return set_error("reqs is NULL"), WL_ERR_INVALID_ARG;
+    lay.reqs.resize(size_t(count));
+    lay.dev_reqs = c.take<BatchReq>(size_t(count > 0 ? count : 1));
+    lay.dev_res = c.take<BatchRes>(size_t(count > 0 ? count : 1));
+    lay.dev_head = c.take<unsigned>(1);
+    for (int r = 0; r < count; ++r) {
+        const wl_status st = plan_one(reqs[r], c, lay.reqs[r]);
+        if (st != WL_OK) {
+            set_error("request " + std::to_string(r) + ": " + last_error_text());
+            return st;
+        }
+    }
+    return WL_OK;
+}
+
+int compute_units() {
+    static const int n = [] {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return 256;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 256;
+        return v > 0 ? v : 256;
+    }();
+    return n;
+}
+
+}  // namespace
+}  // namespace wl
+
+using namespace wl;
+
+extern "C" {
+
+wl_status wl_poisson_batch_footprint(const wl_batch_request* reqs, int count, size_t* bytes) {
+    clear_error();
+    if (!bytes) return set_error("bytes is NULL"), WL_ERR_INVALID_ARG;
+    Carver c;
+    BatchLayout lay;
+    WL_TRY(plan(reqs, count, c, lay));
+    *bytes = c.off;
+    return WL_OK;
+}
+
+wl_status wl_poisson_batch_solve(const wl_batch_request* reqs, int count, void* workspace,
+                                 size_t ws_bytes, void* hip_stream, wl_batch_result* results) {
+    clear_error();
+    if (count == 0) return WL_OK;
+    if (!workspace || !results) return set_error("workspace / results is NULL"), WL_ERR_INVALID_ARG;
+    if (reinterpret_cast<uintptr_t>(workspace) % 256)
+        return set_error("workspace must be 256-byte aligned"), WL_ERR_INVALID_ARG;
+    for (int r = 0; r < count && reqs; ++r)
+        if (!reqs[r].coeffs || !reqs[r].x || !reqs[r].b) {
+            set_error("request " + std::to_string(r) + ": coeffs / x / b is NULL");
+            return WL_ERR_INVALID_ARG;
+        }
+    Carver need;
+    BatchLayout dry;
+    WL_TRY(plan(reqs, count, need, dry));
+    if (ws_bytes < need.off) {
+        set_error("workspace smaller than wl_poisson_batch_footprint");
+        return WL_ERR_OUT_OF_MEMORY;
+    }
+    Carver c;
+    c.base = static_cast<char*>(workspace);
+    BatchLayout lay;
+    WL_TRY(plan(reqs, count, c, lay));
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    // request table and a zero queue head in one upload
+    std::vector<char> up(sizeof(BatchReq) * size_t(count));
+    std::memcpy(up.data(), lay.reqs.data(), up.size());
+    const unsigned zero = 0u;
+    WL_CHECK_HIP(hipMemcpyAsync(lay.dev_reqs, up.data(), up.size(), hipMemcpyHostToDevice, s));
+    WL_CHECK_HIP(hipMemcpyAsync(lay.dev_head, &zero, sizeof(zero), hipMemcpyHostToDevice, s));
+    const int grid = std::min(count, compute_units());
+    k_poisson_batch<<<grid, kBatchThreads, 0, s>>>(lay.dev_reqs, count, lay.dev_head, lay.dev_res);
+    WL_CHECK_HIP(hipGetLastError());
+    std::vector<BatchRes> res(static_cast<size_t>(count));
+    WL_CHECK_HIP(hipMemcpyAsync(res.data(), lay.dev_res, sizeof(BatchRes) * size_t(count),
+                                hipMemcpyDeviceToHost, s));
+    WL_CHECK_HIP(hipStreamSynchronize(s));
+    wl_status worst = WL_OK;
+    for (int r = 0; r < count; ++r) {
+        results[r].status = res[r].status;
+        results[r].vcycles = res[r].vcycles;
+        results[r].rel_resid = res[r].rel;
+        if (res[r].status != WL_OK && worst == WL_OK) worst = wl_status(res[r].status);
+    }
+    if (worst == WL_ERR_NOT_CONVERGED) set_error("some batch requests reached max_vcycles");
+    if (worst == WL_ERR_NONFINITE) set_error("non-finite residual in a batch request");
+    return worst;
+}
+
+}  // extern "C"

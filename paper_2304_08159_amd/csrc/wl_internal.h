@@ -19,6 +19,7 @@ constexpr int kCoarseMax = 1024;      // cells a one-workgroup coarsest solve ac
 
 // ---------------------------------------------------------------- errors
 void set_error(const std::string& msg);
+const std::string& last_error_text();
 void clear_error();
 
 #define WL_CHECK_HIP(expr)                                                            \

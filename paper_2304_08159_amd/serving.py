@@ -9,6 +9,13 @@ being admitted as earlier ones finish.  Every reduction in the library is a
 fixed-order FP64 sum, so a request's result does not depend on what runs
 beside it (checked bitwise by the tests through result fingerprints).
 
+Small Poisson requests are batched: when one of them is admitted, the
+dispatcher gathers further waiting small Poisson requests (FIFO, up to
+`batch_max`, within the free budget) into the same unit, which the executor
+solves with one persistent work-queue kernel (`wl_poisson_batch_solve`: its
+workgroups take requests from a device queue, one request per workgroup at a
+time).  A unit occupies one slot.
+
 The scheduler is host logic only and talks to an `Executor`; `GpuExecutor`
 drives libwl, tests can drive a fake one on the CPU.
 """
@@ -52,6 +59,12 @@ class Executor:
     def run(self, req):            # runs in a worker thread; returns the result
         raise NotImplementedError
 
+    def batchable(self, req):      # may the request share a batched launch?
+        return False
+
+    def run_batch(self, reqs):     # results (or Exception instances), one per request
+        raise NotImplementedError
+
 
 class Server:
     """Admission by memory footprint, FIFO with bounded overtaking, `slots`
@@ -61,14 +74,16 @@ class Server:
     rejected."""
 
     def __init__(self, executor, budget_bytes, slots=8, max_overtakes=16,
-                 clock=time.perf_counter):
+                 clock=time.perf_counter, batch_max=64):
         self.ex = executor
         self.budget = int(budget_bytes)
         self.slots = int(slots)
         self.max_overtakes = int(max_overtakes)
         self.clock = clock
+        self.batch_max = int(batch_max)
         self.peak_bytes = 0
         self.peak_active = 0
+        self.batches = []          # sizes of the batched units that ran
 
     def run(self, requests):
         reqs = sorted(requests, key=lambda r: (r.arrival, r.id))
@@ -88,18 +103,34 @@ class Server:
                         cv.wait()
                     if state["stop"] and not ready:
                         return
-                    r = ready.popleft()
-                try:
-                    r.result = self.ex.run(r)
-                    r.status = "done"
-                except Exception as e:  # the failure is recorded with the request
-                    r.status = "failed"
-                    r.error = f"{type(e).__name__}: {e}"
+                    unit = ready.popleft()
+                if len(unit) == 1 and not self.ex.batchable(unit[0]):
+                    r = unit[0]
+                    try:
+                        r.result = self.ex.run(r)
+                        r.status = "done"
+                    except Exception as e:  # the failure is recorded with the request
+                        r.status = "failed"
+                        r.error = f"{type(e).__name__}: {e}"
+                else:
+                    try:
+                        outs = self.ex.run_batch(unit)
+                    except Exception as e:
+                        outs = [e] * len(unit)
+                    for r, o in zip(unit, outs):
+                        if isinstance(o, Exception):
+                            r.status = "failed"
+                            r.error = f"{type(o).__name__}: {o}"
+                        else:
+                            r.result = o
+                            r.status = "done"
                 with cv:
-                    r.done = self.clock() - t0
-                    state["free"] += r.footprint
+                    now_done = self.clock() - t0
+                    for r in unit:
+                        r.done = now_done
+                        state["free"] += r.footprint
                     state["active"] -= 1
-                    state["finished"] += 1
+                    state["finished"] += len(unit)
                     cv.notify_all()
 
         threads = [threading.Thread(target=worker, daemon=True) for _ in range(self.slots)]
@@ -125,15 +156,29 @@ class Server:
                 for r in list(waiting):
                     if state["active"] >= self.slots:
                         break
+                    if r not in waiting:       # already taken into a batched unit
+                        continue
                     if r.footprint <= state["free"] and not blocked:
                         waiting.remove(r)
                         state["free"] -= r.footprint
                         state["active"] += 1
-                        r.admitted = now
-                        r.status = "running"
-                        ready.append(r)
+                        unit = [r]
+                        if self.ex.batchable(r):
+                            for q in list(waiting):
+                                if len(unit) >= self.batch_max:
+                                    break
+                                if self.ex.batchable(q) and q.footprint <= state["free"]:
+                                    waiting.remove(q)
+                                    state["free"] -= q.footprint
+                                    unit.append(q)
+                            if len(unit) > 1:
+                                self.batches.append(len(unit))
+                        for u in unit:
+                            u.admitted = now
+                            u.status = "running"
+                        ready.append(unit)
                         for q in waiting:
-                            if q.id != r.id and q.arrival <= r.arrival and q.footprint > r.footprint:
+                            if q.arrival <= r.arrival and q.footprint > r.footprint:
                                 overtaken[q.id] += 1
                         cv.notify_all()
                     elif overtaken[r.id] >= self.max_overtakes:
@@ -205,13 +250,14 @@ class GpuExecutor(Executor):
     pressure solves).  Results are (fingerprint, stats) pairs; the fingerprint
     is an exact integer hash of the output bits."""
 
-    def __init__(self, device="cuda", keep_fields=False):
+    def __init__(self, device="cuda", keep_fields=False, batch_cells=65536):
         import torch
 
         import paper_2304_08159_amd as wl
         self.torch, self.wl = torch, wl
         self.device = device
         self.keep = keep_fields
+        self.batch_cells = int(batch_cells)   # Poisson requests up to this size are batched
         self._tls = threading.local()
 
     def _stream(self):
@@ -233,6 +279,9 @@ class GpuExecutor(Executor):
         return dict(n=r.n, bc_lo=bc_lo, bc_hi=bc_hi, U=U, nu=nu,
                     body=dict(centre=centre, radius=r.radius))
 
+    def batchable(self, r):
+        return r.kind == "poisson" and math.prod(r.n) <= self.batch_cells
+
     def footprint(self, r):
         import ctypes
         from . import _lib
@@ -243,6 +292,14 @@ class GpuExecutor(Executor):
             cells *= m
         nn = (ctypes.c_int * 3)(*(list(r.n) + [1] * (3 - ndim)))
         sz = ctypes.c_size_t()
+        if self.batchable(r):
+            q = _lib.BatchRequest()
+            q.ndim = ndim
+            for i in range(3):
+                q.n[i] = nn[i]
+            q.tol, q.max_vcycles = r.tol, 400
+            _lib.check(lib.wl_poisson_batch_footprint(ctypes.byref(q), 1, ctypes.byref(sz)))
+            return sz.value + 8 * cells * (2 + ndim) + 256
         if r.kind == "poisson":
             per = (ctypes.c_int * 3)(0, 0, 0)
             _lib.check(lib.wl_poisson_footprint(ndim, nn, per, _lib.WL_MIXED, 0, ctypes.byref(sz)))
@@ -267,7 +324,42 @@ class GpuExecutor(Executor):
         w = (torch.arange(bits.numel(), device=bits.device, dtype=torch.int64) % 1000003) + 1
         return int((bits.to(torch.int64) * w).sum().item())
 
+    def run_batch(self, rs):
+        """Small Poisson requests (FP64, Neumann box, centred sphere / circle,
+        N(0,1) right-hand side) through one persistent work-queue kernel."""
+        torch, wl = self.torch, self.wl
+        stream = self._stream()
+        with torch.cuda.stream(stream):
+            reqs, keep = [], []
+            for r in rs:
+                ndim = len(r.n)
+                body = dict(centre=tuple(m / 2.0 for m in r.n), radius=r.radius)
+                L = wl.body_coeffs(r.n, (False,) * ndim, body, prec=wl.WL_FP64)
+                shape = tuple(reversed(list(r.n) + [1] * (3 - ndim)))
+                g = torch.Generator(device=self.device)
+                g.manual_seed(int(r.seed))
+                b = torch.randn(shape, generator=g, dtype=torch.float64, device=self.device)
+                x = torch.zeros_like(b)
+                reqs.append(dict(n=r.n, periodic=(False,) * ndim, coeffs=L, x=x, b=b, tol=r.tol,
+                                 max_vcycles=400))
+                keep.append((x, b, L))
+            res = wl.poisson_batch_solve(reqs, allow_not_converged=True)
+            outs = []
+            for (st, k, rel), (x, b, L) in zip(res, keep):
+                if st != 0:
+                    outs.append(RuntimeError(f"batched Poisson solve status {st} after {k} V-cycles"))
+                    continue
+                outs.append((self._fingerprint(x), dict(vcycles=k, rel_resid=rel, batched=True),
+                             (x, b, L) if self.keep else None))
+            stream.synchronize()
+        return outs
+
     def run(self, r):
+        if self.batchable(r):
+            out = self.run_batch([r])[0]
+            if isinstance(out, Exception):
+                raise out
+            return out
         torch, wl = self.torch, self.wl
         stream = self._stream()
         with torch.cuda.stream(stream):

@@ -67,3 +67,36 @@ def test_host_side_validation_without_gpu():
     n = (ctypes.c_int * 3)(256, 256, 256)
     assert lib.wl_poisson_footprint(3, n, per, 2, 0, ctypes.byref(sz)) == 0
     assert sz.value > 3 * 8 * 256 ** 3
+
+
+def test_batch_footprint_validates_requests_without_a_gpu():
+    from paper_2304_08159_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libwl.so not built")
+    lib = _lib.load()
+
+    def req(ndim, n, per=(0, 0, 0)):
+        r = _lib.BatchRequest()
+        r.ndim = ndim
+        for i in range(3):
+            r.n[i] = n[i]
+            r.periodic[i] = per[i]
+        r.tol = 1e-8
+        r.max_vcycles = 50
+        return r
+    sz = ctypes.c_size_t()
+    ok = (_lib.BatchRequest * 2)(req(2, (64, 48, 1)), req(3, (32, 32, 16)))
+    assert lib.wl_poisson_batch_footprint(ok, 2, ctypes.byref(sz)) == _lib.WL_OK
+    # level arrays of both requests plus the request table
+    assert sz.value > 8 * (2 * 64 * 48 + 2 * 32 * 32 * 16)
+    one = ctypes.c_size_t()
+    assert lib.wl_poisson_batch_footprint(ok, 1, ctypes.byref(one)) == _lib.WL_OK
+    assert one.value < sz.value
+    for bad in (req(3, (128, 64, 64)),      # more than 262144 cells
+                req(2, (64, 48, 2)),        # 2D with n[2] != 1
+                req(4, (8, 8, 8)),          # ndim
+                req(2, (66, 66, 1))):       # coarsest level 33 x 33 > 1024 cells
+        arr = (_lib.BatchRequest * 2)(ok[0], bad)
+        st = lib.wl_poisson_batch_footprint(arr, 2, ctypes.byref(sz))
+        assert st == _lib.WL_ERR_INVALID_ARG
+        assert b"request 1" in lib.wl_last_error()

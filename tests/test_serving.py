@@ -86,3 +86,45 @@ def test_large_request_is_not_starved():
     later = [r for r in out.values() if r.id > 0 and r.arrival > big.arrival]
     # once it has been overtaken three times it goes before the rest of the queue
     assert sum(r.admitted < out[0].admitted for r in later) <= 3 + 4
+
+
+class FakeBatchExecutor(FakeExecutor):
+    """Batches 2D requests; records the units it ran."""
+
+    def __init__(self):
+        super().__init__(unit_s=0.003)
+        self.units = []
+
+    def batchable(self, r):
+        return len(r.n) == 2 and r.kind == "poisson"
+
+    def run_batch(self, rs):
+        with self.lock:
+            self.units.append([r.id for r in rs])
+            self.active += 1
+            self.bytes += sum(r.footprint for r in rs)
+            self.peak = max(self.peak, self.active)
+            self.peak_bytes = max(self.peak_bytes, self.bytes)
+        time.sleep(self.unit)
+        with self.lock:
+            self.active -= 1
+            self.bytes -= sum(r.footprint for r in rs)
+        return [("ok", r.id) if r.id % 17 else RuntimeError("planted") for r in rs]
+
+
+def test_small_requests_are_batched_within_budget():
+    ex = FakeBatchExecutor()
+    reqs = [Request(id=k, kind="poisson" if k % 3 else "ns", n=(64, 64) if k % 2 else (32, 32, 32),
+                    arrival=0.0) for k in range(80)]
+    budget = 40 * 64 * 64 * 100 + 2 * 32 ** 3 * 100
+    srv = Server(ex, budget, slots=3, batch_max=8)
+    out = {r.id: r for r in srv.run(reqs)}
+    assert all(r.status in ("done", "failed") for r in out.values())
+    assert all(out[k].status == ("failed" if (k % 17 == 0 and ex.batchable(out[k])) else "done")
+               for k in out)
+    sizes = [len(u) for u in ex.units]
+    assert max(sizes) > 1 and max(sizes) <= 8
+    # every batched unit holds only batchable requests, each exactly once
+    ids = [i for u in ex.units for i in u]
+    assert len(ids) == len(set(ids)) and all(ex.batchable(out[i]) for i in ids)
+    assert ex.peak <= 3 and ex.peak_bytes <= budget
