@@ -148,6 +148,46 @@ def poisson_compare(torch, wl, W, n, radius=32.0, tol=1e-8, reps=3):
     return out
 
 
+def batch_compare(torch, wl, count=256, n=(128, 128), tol=1e-8):
+    """Many small Poisson problems (circle coefficients, N(0,1) right-hand
+    sides, FP64 to tol): one persistent work-queue launch vs the per-problem
+    solver one after another."""
+    d = len(n)
+    body = dict(centre=tuple(m / 2.0 for m in n), radius=min(n) / 4.0)
+    L = wl.body_coeffs(n, (False,) * d, body, prec=wl.WL_FP64)
+    shape = tuple(reversed(list(n) + [1] * (3 - d)))
+    g = torch.Generator(device="cuda")
+    g.manual_seed(2304)
+    bs = [torch.randn(shape, generator=g, dtype=torch.float64, device="cuda") for _ in range(count)]
+
+    def reqs():
+        return [dict(n=n, periodic=(False,) * d, coeffs=L, x=torch.zeros_like(b), b=b, tol=tol,
+                     max_vcycles=400) for b in bs]
+    wl.poisson_batch_solve(reqs()[:8])          # warm-up
+    rq = reqs()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = wl.poisson_batch_solve(rq)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    ps = wl.Poisson(n, (False,) * d, prec=wl.WL_FP64)
+    x = torch.zeros_like(bs[0])
+    ps.solve(L, x, bs[0], tol=tol, max_vcycles=400)   # warm-up, loads the coefficients
+    nseq = min(count, 64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b in bs[:nseq]:
+        x.zero_()
+        ps.solve(None, x, b, tol=tol, max_vcycles=400)
+    torch.cuda.synchronize()
+    t_seq = (time.perf_counter() - t0) * count / nseq
+    ps.close()
+    return dict(workload=f"{count} Poisson problems {n[0]}x{n[1]}, circle r={min(n) / 4:.0f}, "
+                         f"FP64 to {tol}",
+                batched_problems_per_s=count / t_batch, sequential_problems_per_s=count / t_seq,
+                speedup=t_seq / t_batch, vcycles_mean=sum(o[1] for o in out) / count)
+
+
 def serving_bench(count=512, seed=2304, budget=16e9, slots=8):
     """Served mix: sizes uniform over 2D {64^2,128^2,256^2} and 3D {64^3,96^3,128^3},
     half Poisson solves, half 20-step NS runs with a body; HBM budget 16 GB.
@@ -331,6 +371,7 @@ def main():
     if not args.no_poisson:
         out["poisson_mixed_vs_fp64"] = poisson_compare(torch, wl, W, (N, N, N))
     if not args.no_serving:
+        out["poisson_batch"] = batch_compare(torch, wl)
         out["serving"] = serving_bench()
     if not args.no_cpu_baseline:
         vcr = [max(1, int(round(x))) for x in vc_mean]
