@@ -245,10 +245,6 @@ struct SolveResult {
     double bnorm = 0.0;
 };
 
-// Plain GMG solve on h (level 0 x = caller x).  b is the raw right-hand side.
-// Converged before a V-cycle when ||r||^2 <= tol^2 ||b||^2 or ||r||^2 <= abs_r2.
-// b_partials: red.partial already holds the per-block sums of b over the
-// active cells for the fine-level tiling (written by the producer of b).
 // Work that follows a converged solve and only reads its solution (e.g. the
 // projection).  mg_solve may enqueue it speculatively right after the first
 // norm check is enqueued and enqueue it again if V-cycles follow; it must
@@ -256,6 +252,10 @@ struct SolveResult {
 // run on the final solution and every mailbox post it made has arrived.
 using SolveTail = std::function<wl_status(hipStream_t)>;
 
+// Plain GMG solve on h (level 0 x = caller x).  b is the raw right-hand side.
+// Converged before a V-cycle when ||r||^2 <= tol^2 ||b||^2 or ||r||^2 <= abs_r2.
+// b_partials: red.partial already holds the per-block sums of b over the
+// active cells for the fine-level tiling (written by the producer of b).
 template <typename T>
 wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, double abs_r2,
                    int max_vcycles, hipStream_t s, SolveResult* res, bool b_partials = false,
