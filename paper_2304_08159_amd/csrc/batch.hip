@@ -13,9 +13,8 @@
 #include <string>
 #include <vector>
 
-#include "wl_cg.h"
-#include "wl_device.h"
 #include "wl_internal.h"
+#include "wl_wg.h"
 
 namespace wl {
 namespace {
@@ -23,12 +22,7 @@ namespace {
 constexpr int kBatchThreads = 1024;
 constexpr size_t kBatchMaxCells = 262144;  // per request (e.g. 512^2, 64^3)
 
-struct BatchLevel {
-    Grid g;
-    double* x[2];  // level 0: x[0] is the caller's solution
-    double* b;     // level 0: the projected right-hand side
-    double* L[3];  // face coefficients (level 0: the caller's, read only)
-};
+using BatchLevel = WgLevel<double>;  // uniform = 0, Lc = 1 (coefficients from the request)
 
 struct BatchReq {
     int nlev;
@@ -43,98 +37,6 @@ struct BatchRes {
     double rel;
 };
 
-__device__ __forceinline__ void coords_of(const Grid& g, int c, int& i, int& j, int& k) {
-    i = c % g.n0;
-    const int q = c / g.n0;
-    j = q % g.n1;
-    k = q / g.n1;
-}
-
-// Fixed-order sum over the workgroup, returned to every thread.
-__device__ double wg_sum(double v, double* red) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    double s = 0.0;
-    for (int w = 0; w < int(blockDim.x + 63) / 64; ++w) s += red[w];
-    __syncthreads();
-    return s;
-}
-
-__device__ __forceinline__ Coeffs<double> coeffs(const BatchLevel& L) {
-    return Coeffs<double>{L.L[0], L.L[1], L.L[2], 1.0};
-}
-
-// xout = x - w (b - A x) / D on active cells, 0 elsewhere; returns
-// sum (b - A x)^2 when norm (0 otherwise).
-template <int XM>
-__device__ double wg_sweep(const BatchLevel& L, const XAccess<double, XM>& X, const double* b,
-                           double w, double* xout, bool norm, double* red) {
-    const Coeffs<double> C = coeffs(L);
-    const int N = int(cells(L.g));
-    double r2 = 0.0;
-    for (int c = threadIdx.x; c < N; c += blockDim.x) {
-        int i, j, k;
-        coords_of(L.g, c, i, j, k);
-        double xI, Ax, D;
-        apply_row<double, XM, false>(L.g, X, C, i, j, k, xI, Ax, D);
-        const double r = b[c] - Ax;
-        xout[c] = D > 0.0 ? xI - w * r / D : 0.0;
-        r2 += r * r;
-    }
-    __syncthreads();
-    return norm ? wg_sum(r2, red) : 0.0;
-}
-
-// Coarse right-hand side = sum of the child residuals b - A x.
-__device__ void wg_restrict(const BatchLevel& F, const double* x, const double* b,
-                            const BatchLevel& Cl) {
-    const Coeffs<double> C = coeffs(F);
-    const XAccess<double, XM_PLAIN> X{x, nullptr, 0, 0};
-    const int Nc = int(cells(Cl.g));
-    const int fz = F.g.n2 > Cl.g.n2 ? 2 : 1;
-    for (int c = threadIdx.x; c < Nc; c += blockDim.x) {
-        int ic, jc, kc;
-        coords_of(Cl.g, c, ic, jc, kc);
-        double sum = 0.0;
-        for (int dz = 0; dz < fz; ++dz)
-            for (int dy = 0; dy < 2; ++dy)
-                for (int dx = 0; dx < 2; ++dx) {
-                    const int i = 2 * ic + dx, j = 2 * jc + dy, k = fz * kc + dz;
-                    double xI, Ax, D;
-                    apply_row<double, XM_PLAIN, false>(F.g, X, C, i, j, k, xI, Ax, D);
-                    sum += b[cid(F.g, i, j, k)] - Ax;
-                }
-        Cl.b[c] = sum;
-    }
-    __syncthreads();
-}
-
-// Coarse coefficient = 1/2 the sum of the fine faces it covers.
-__device__ void wg_coarsen(const BatchLevel& F, const BatchLevel& Cl) {
-    const int Nc = int(cells(Cl.g));
-    const int fz = F.g.n2 > Cl.g.n2 ? 2 : 1;
-    for (int c = threadIdx.x; c < Nc; c += blockDim.x) {
-        int i, j, k;
-        coords_of(Cl.g, c, i, j, k);
-        const int I = 2 * i, J = 2 * j, K = fz * k;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-        for (int dz = 0; dz < fz; ++dz)
-            for (int dy = 0; dy < 2; ++dy) s0 += F.L[0][cid(F.g, I, J + dy, K + dz)];
-        for (int dz = 0; dz < fz; ++dz)
-            for (int dx = 0; dx < 2; ++dx) s1 += F.L[1][cid(F.g, I + dx, J, K + dz)];
-        Cl.L[0][c] = 0.5 * s0;
-        Cl.L[1][c] = 0.5 * s1;
-        if (F.g.ndim == 3) {
-            for (int dy = 0; dy < 2; ++dy)
-                for (int dx = 0; dx < 2; ++dx) s2 += F.L[2][cid(F.g, I + dx, J + dy, K)];
-            Cl.L[2][c] = 0.5 * s2;
-        }
-    }
-    __syncthreads();
-}
-
 __device__ void solve_one(const BatchReq& q, BatchRes& res, CoarseLds& S) {
     const BatchLevel& F = q.lev[0];
     const int nlev = q.nlev;
@@ -143,51 +45,47 @@ __device__ void solve_one(const BatchReq& q, BatchRes& res, CoarseLds& S) {
     double* x = F.x[0];
     double* x1 = F.x[1];
     const int N = int(cells(F.g));
-    for (int l = 1; l < nlev; ++l) wg_coarsen(q.lev[l - 1], q.lev[l]);
+    for (int l = 1; l < nlev; ++l) wg_coarsen<double>(q.lev[l - 1], q.lev[l]);
     // right-hand side projected onto the active cells, mean-free there
-    {
-        const XAccess<double, XM_ZERO> Z{nullptr, nullptr, 0, 0};
-        const Coeffs<double> C = coeffs(F);
-        double sb = 0.0, cnt = 0.0;
-        for (int c = threadIdx.x; c < N; c += blockDim.x) {
-            int i, j, k;
-            coords_of(F.g, c, i, j, k);
-            double xI, Ax, D;
-            apply_row<double, XM_ZERO, false>(F.g, Z, C, i, j, k, xI, Ax, D);
-            if (D > 0.0) {
-                sb += q.b_in[c];
-                cnt += 1.0;
-            }
+    const XAccess<double, XM_ZERO> Z{nullptr, nullptr, 0, 0};
+    const Coeffs<double> C = wg_coeffs(F);
+    double sb = 0.0, cnt = 0.0;
+    for (int c = threadIdx.x; c < N; c += blockDim.x) {
+        int i, j, k;
+        wg_coords(F.g, c, i, j, k);
+        double xI, Ax, D;
+        apply_row<double, XM_ZERO, false>(F.g, Z, C, i, j, k, xI, Ax, D);
+        if (D > 0.0) {
+            sb += q.b_in[c];
+            cnt += 1.0;
         }
-        sb = wg_sum(sb, red);
-        cnt = wg_sum(cnt, red);
-        const double mean = cnt > 0.0 ? sb / cnt : 0.0;
-        double b2 = 0.0;
-        for (int c = threadIdx.x; c < N; c += blockDim.x) {
-            int i, j, k;
-            coords_of(F.g, c, i, j, k);
-            double xI, Ax, D;
-            apply_row<double, XM_ZERO, false>(F.g, Z, C, i, j, k, xI, Ax, D);
-            const double bv = D > 0.0 ? q.b_in[c] - mean : 0.0;
-            F.b[c] = bv;
-            b2 += bv * bv;
-        }
-        __syncthreads();
-        b2 = wg_sum(b2, red);
-        if (b2 == 0.0) {
-            for (int c = threadIdx.x; c < N; c += blockDim.x) x[c] = 0.0;
-            __syncthreads();
-            if (threadIdx.x == 0) res = BatchRes{WL_OK, 0, 0.0};
-            return;
-        }
-        S.x[0] = b2;  // (kept for the final relative residual)
     }
-    const double b2 = S.x[0];
+    sb = wg_sum(sb, red);
+    cnt = wg_sum(cnt, red);
+    const double mean = cnt > 0.0 ? sb / cnt : 0.0;
+    double b2 = 0.0;
+    for (int c = threadIdx.x; c < N; c += blockDim.x) {
+        int i, j, k;
+        wg_coords(F.g, c, i, j, k);
+        double xI, Ax, D;
+        apply_row<double, XM_ZERO, false>(F.g, Z, C, i, j, k, xI, Ax, D);
+        const double bv = D > 0.0 ? q.b_in[c] - mean : 0.0;
+        F.b[c] = bv;
+        b2 += bv * bv;
+    }
     __syncthreads();
+    b2 = wg_sum(b2, red);
+    if (b2 == 0.0) {
+        for (int c = threadIdx.x; c < N; c += blockDim.x) x[c] = 0.0;
+        __syncthreads();
+        if (threadIdx.x == 0) res = BatchRes{WL_OK, 0, 0.0};
+        __syncthreads();
+        return;
+    }
     const double tol2 = q.tol * q.tol * b2;
     // first sweep of the first V-cycle, with the norm of the initial residual
-    double r2 = wg_sweep<XM_PLAIN>(F, XAccess<double, XM_PLAIN>{x, nullptr, 0, 0}, F.b, w, x1, true,
-                                   red);
+    double r2 = wg_sweep<double, XM_PLAIN>(F, XAccess<double, XM_PLAIN>{x, nullptr, 0, 0}, F.b, w,
+                                           x1, true, red);
     int k = 0;
     int status = WL_OK;
     while (!(r2 <= tol2) && k < q.max_vcycles) {
@@ -196,39 +94,22 @@ __device__ void solve_one(const BatchReq& q, BatchRes& res, CoarseLds& S) {
             break;
         }
         if (nlev == 1) {
-            coarse_cg_block<double>(F.g, coeffs(F), 0, F.b, x, 1e-10, N + 64, S);
+            coarse_cg_block<double>(F.g, C, 0, F.b, x, 1e-10, N + 64, S);
         } else {
-            wg_sweep<XM_PLAIN>(F, XAccess<double, XM_PLAIN>{x1, nullptr, 0, 0}, F.b, w, x, false,
-                               red);
-            wg_restrict(F, x, F.b, q.lev[1]);
-            for (int l = 1; l < nlev - 1; ++l) {
-                const BatchLevel& L = q.lev[l];
-                wg_sweep<XM_ZERO>(L, XAccess<double, XM_ZERO>{nullptr, nullptr, 0, 0}, L.b, w,
-                                  L.x[0], false, red);
-                wg_sweep<XM_PLAIN>(L, XAccess<double, XM_PLAIN>{L.x[0], nullptr, 0, 0}, L.b, w,
-                                   L.x[1], false, red);
-                wg_restrict(L, L.x[1], L.b, q.lev[l + 1]);
-            }
-            const BatchLevel& Cst = q.lev[nlev - 1];
-            coarse_cg_block<double>(Cst.g, coeffs(Cst), 0, Cst.b, Cst.x[1], 1e-10,
-                                    int(cells(Cst.g)) + 64, S);
-            for (int l = nlev - 2; l >= 1; --l) {
-                const BatchLevel& L = q.lev[l];
-                const BatchLevel& C = q.lev[l + 1];
-                wg_sweep<XM_PROLONG>(L, XAccess<double, XM_PROLONG>{L.x[1], C.x[1], C.g.n0, C.g.n1},
-                                     L.b, w, L.x[0], false, red);
-                wg_sweep<XM_PLAIN>(L, XAccess<double, XM_PLAIN>{L.x[0], nullptr, 0, 0}, L.b, w,
-                                   L.x[1], false, red);
-            }
+            wg_sweep<double, XM_PLAIN>(F, XAccess<double, XM_PLAIN>{x1, nullptr, 0, 0}, F.b, w, x,
+                                       false, red);
+            wg_restrict<double>(F, x, F.b, q.lev[1]);
+            wg_vcycle_tail<double>(&q.lev[1], nlev - 1, w, 1e-10, S);
             const BatchLevel& C1 = q.lev[1];
-            wg_sweep<XM_PROLONG>(F, XAccess<double, XM_PROLONG>{x, C1.x[1], C1.g.n0, C1.g.n1}, F.b,
-                                 w, x1, false, red);
-            wg_sweep<XM_PLAIN>(F, XAccess<double, XM_PLAIN>{x1, nullptr, 0, 0}, F.b, w, x, false,
-                               red);
+            wg_sweep<double, XM_PROLONG>(F, XAccess<double, XM_PROLONG>{x, C1.x[1], C1.g.n0,
+                                                                        C1.g.n1},
+                                         F.b, w, x1, false, red);
+            wg_sweep<double, XM_PLAIN>(F, XAccess<double, XM_PLAIN>{x1, nullptr, 0, 0}, F.b, w, x,
+                                       false, red);
         }
         ++k;
-        r2 = wg_sweep<XM_PLAIN>(F, XAccess<double, XM_PLAIN>{x, nullptr, 0, 0}, F.b, w, x1, true,
-                                red);
+        r2 = wg_sweep<double, XM_PLAIN>(F, XAccess<double, XM_PLAIN>{x, nullptr, 0, 0}, F.b, w, x1,
+                                        true, red);
     }
     if (status == WL_OK && !isfinite(r2)) status = WL_ERR_NONFINITE;
     if (status == WL_OK && !(r2 <= tol2)) status = WL_ERR_NOT_CONVERGED;
@@ -294,6 +175,8 @@ wl_status plan_one(const wl_batch_request& in, Carver& c, BatchReq& q) {
         BatchLevel& L = q.lev[l];
         L.g = Grid{n[0], n[1], n[2], in.periodic[0] != 0, in.periodic[1] != 0,
                    ndim == 3 && in.periodic[2] != 0, ndim};
+        L.Lc = 1.0;
+        L.uniform = 0;
         const size_t Nl = size_t(n[0]) * n[1] * n[2];
         if (l == 0) {
             L.x[0] = static_cast<double*>(in.x);
