@@ -39,21 +39,33 @@ BYTES_PER_CELL = {
                              # write f: it applies the predictor's projection as it loads)
     "divergence": 16.0,      # read u* (3 comps); write sigma
     "project": 28.0,         # read u* (3), p; write u (3)
+    "norm_fine": 8.0,        # residual norm only: read x, b
+    "pair_fine": 12.0,       # two sweeps in one pass: read x, b; write x''
+    "pair_prolong_fine": 12.5,  # prolongation + two sweeps: read x, b, x_coarse (1/8); write x''
 }
 
 
-def step_bytes_per_cell(vcycles_total, nlev_coarse_factor=1.0 / 7.0):
+def step_bytes_per_cell(vcycles_total, fused):
     """Algorithmic bytes of one step per fine cell (FP32, uniform L, 3D).
 
     momentum 24 + 40 (the corrector applies the predictor's projection as it
-    loads u*), divergence 2 x 16, the corrector's projection 28, per solve the
-    first sweep (12; the active mean comes with the divergence), and per
-    V-cycle the fine sweeps/transfers (12 + 8.5 + 12.5 + 12) plus the norm
-    sweep (12) and the coarse levels (53 B per coarse cell, 1/7 of the fine
-    count).
+    loads u*), divergence 2 x 16, the corrector's projection 28, then per
+    solve and per V-cycle (coarse levels 1/8, 1/64, ... of the fine count):
+    - separate sweeps: first check-and-sweep 12; per V-cycle the fine
+      sweep, restriction, prolongation sweep and sweep (12 + 8.5 + 12.5 + 12),
+      the norm sweep (12) and 53 B per coarse cell;
+    - fused sweep pairs (fine and first coarse level): first check 8; per
+      V-cycle pair 12, restriction 8.5, prolongation pair 12.5, norm check 8,
+      29 B per level-1 cell (zero-start pair 8, restriction 8.5, prolongation
+      pair 12.5) and 53 B per cell of the coarser levels.
     """
-    per_vcycle = 12 + 8.5 + 12.5 + 12 + 12 + 53.0 * nlev_coarse_factor
-    return 64.0 + 32.0 + 28.0 + 2 * 12.0 + per_vcycle * vcycles_total
+    if fused:
+        first = 8.0
+        per_vcycle = 12 + 8.5 + 12.5 + 8 + 29.0 / 8 + 53.0 * (1.0 / 7 - 1.0 / 8)
+    else:
+        first = 12.0
+        per_vcycle = 12 + 8.5 + 12.5 + 12 + 12 + 53.0 / 7
+    return 64.0 + 32.0 + 28.0 + 2 * first + per_vcycle * vcycles_total
 
 
 # HBM traffic of the dominant kernel per launch from rocprofv3 counters
@@ -310,7 +322,7 @@ def main():
     cells = N ** 3
     value = cells * args.steps / elapsed
     vc_mean = [float(np.mean([a[i] for a in vcs])) for i in range(2)]
-    step_b = step_bytes_per_cell(sum(vc_mean)) * cells
+    step_b = step_bytes_per_cell(sum(vc_mean), "pair_fine" in kern) * cells
     step_gbs = step_b / (ms_step * 1e-3) / 1e9
     out = {
         "metric": "cell-steps/s (3D TGV 256^3 FP32)",

@@ -271,6 +271,17 @@ wl_status wl_body_coeffs(const wl_body* body, int ndim, const int n[3], const in
  * multigrid kernel class is timed (wl_profile_enable). */
 wl_status wl_set_graphs(int enable);
 
+/* Each pre- and post-smoothing pair of damped-Jacobi sweeps (Sec. 2's GMG
+ * smoother) on a uniform, fully periodic 3D level whose x / y extents are
+ * multiples of 64 / 8 runs as one kernel that keeps the intermediate iterate
+ * on chip; the V-cycle then also checks the residual with a measuring pass
+ * that writes nothing.  Iterates, norms and results are bitwise the same as
+ * with separate sweeps.  mode 0: separate sweeps everywhere; 1 (default):
+ * fused on such levels of at least 2^21 cells; 2: fused on every such level.
+ * Process-wide; a solver or simulation takes the mode in force when it is
+ * created.  WL_ERR_INVALID_ARG for another mode. */
+wl_status wl_set_fused_sweeps(int mode);
+
 /* ---- Kernel timing (measurement support) -------------------------------- */
 
 /* Kernels whose launches can be bracketed by HIP events, to turn algorithmic
@@ -284,7 +295,10 @@ enum {
     WL_PROF_MOMENTUM = 4,        /* convection-diffusion stage update         */
     WL_PROF_DIVERGENCE = 5,      /* projection right-hand side                */
     WL_PROF_PROJECT = 6,         /* pressure-gradient update (+ CFL)          */
-    WL_PROF_COUNT = 7
+    WL_PROF_NORM_FINE = 7,       /* residual norm only, fine level            */
+    WL_PROF_PAIR_FINE = 8,       /* two sweeps fused, fine level              */
+    WL_PROF_PAIR_PROLONG_FINE = 9, /* prolongation and two sweeps fused, fine */
+    WL_PROF_COUNT = 10
 };
 
 /* Enable event timing for the kernels in mask (bit k = kernel k); 0 turns it

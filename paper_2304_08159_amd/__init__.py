@@ -17,7 +17,7 @@ from ._lib import (FIELD_L0, FIELD_MU0_0, FIELD_MU1N, FIELD_P, FIELD_SIGMA, FIEL
                    FIELD_UOUT, INFLOW, OUTFLOW, PERIODIC, WALL, WL_FP32, WL_FP64, WL_MIXED,
                    WlError, check, load)
 
-__all__ = ["Sim", "Poisson", "body_coeffs", "set_graphs", "poisson_batch_solve", "load", "WlError", "WL_FP32", "WL_FP64", "WL_MIXED",
+__all__ = ["Sim", "Poisson", "body_coeffs", "set_graphs", "set_fused_sweeps", "poisson_batch_solve", "load", "WlError", "WL_FP32", "WL_FP64", "WL_MIXED",
            "PERIODIC", "INFLOW", "OUTFLOW", "WALL"]
 
 
@@ -225,6 +225,14 @@ def set_graphs(enable=True):
     """Replay repeated solve bodies as captured HIP graphs (default) or launch
     every kernel individually; results are bitwise the same."""
     check(load().wl_set_graphs(1 if enable else 0))
+
+
+def set_fused_sweeps(mode=1):
+    """Fused pre/post-smoothing sweep pairs on uniform periodic 3D levels:
+    0 off, 1 on levels of at least 2^21 cells (default), 2 on every eligible
+    level.  Taken by solvers and simulations created afterwards; results are
+    bitwise the same in every mode."""
+    check(load().wl_set_fused_sweeps(int(mode)))
 
 
 def body_coeffs(n, periodic, body=None, prec=WL_FP32, device="cuda"):

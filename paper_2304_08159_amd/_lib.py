@@ -30,13 +30,13 @@ EXPORTS = (
     "wl_set_time", "wl_step", "wl_drag", "wl_tape_record", "wl_step_adjoint",
     "wl_poisson_footprint", "wl_poisson_create",
     "wl_poisson_solve", "wl_poisson_destroy", "wl_poisson_batch_footprint",
-    "wl_poisson_batch_solve", "wl_body_coeffs", "wl_set_graphs",
+    "wl_poisson_batch_solve", "wl_body_coeffs", "wl_set_graphs", "wl_set_fused_sweeps",
     "wl_profile_enable",
     "wl_profile_reset",
     "wl_profile_read", "wl_last_error", "wl_version",
 )
 PROF = dict(smooth_fine=0, smooth_norm=1, prolong_fine=2, restrict_fine=3, momentum=4,
-            divergence=5, project=6)
+            divergence=5, project=6, norm_fine=7, pair_fine=8, pair_prolong_fine=9)
 
 
 class WlError(RuntimeError):
@@ -107,6 +107,7 @@ def load():
                                    ctypes.POINTER(BatchResult)],
         "wl_body_coeffs": [ctypes.POINTER(Body), i32, ip3, ip3, i32, vp, vp],
         "wl_set_graphs": [i32],
+        "wl_set_fused_sweeps": [i32],
         "wl_profile_enable": [ctypes.c_uint],
         "wl_profile_reset": [],
         "wl_profile_read": [i32, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_longlong),

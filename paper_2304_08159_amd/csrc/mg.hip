@@ -1,5 +1,3 @@
-#include <chrono>
-#include <algorithm>
 // Matrix-free geometric multigrid for the BDIM-modified pressure Poisson
 // system (paper Sec. 2: GMG with a solution time linear in the cell count;
 // the operator is fixed by the gradient loop u[I,i] -= coeff*(p[I]-p[I-del(i)])).
@@ -9,13 +7,19 @@
 // post-sweeps), residual fused with sum-restriction, piecewise-constant
 // prolongation fused with the first post-sweep, a one-workgroup FP64 CG on
 // the coarsest level, and FP64 fixed-order reductions for the norms and the
-// active-set mean.
+// active-set mean.  On uniform periodic 3D levels each pair of sweeps runs as
+// one LDS-tiled kernel that keeps the intermediate iterate on chip.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <type_traits>
 
 #include "wl_cg.h"
 #include "wl_device.h"
+#include "wl_jacobi.h"
 
 namespace wl {
 
@@ -84,10 +88,36 @@ int auto_levels(int ndim, const int n[3], int requested) {
     return count;
 }
 
+// Process-wide choice of the fused two-sweep kernels (wl_set_fused_sweeps),
+// taken by each hierarchy when it is laid out.
+static std::atomic<int> g_pairs{1};
+
+// Levels smaller than this use separate sweeps in mode 1 (WL_PAIR_MIN_CELLS
+// overrides it for tuning).
+static size_t pair_min_cells() {
+    static const size_t v = [] {
+        const char* e = std::getenv("WL_PAIR_MIN_CELLS");
+        const long t = e ? std::atol(e) : -1;
+        return t >= 0 ? size_t(t) : size_t(1) << 21;
+    }();
+    return v;
+}
+
+// Target workgroup count of a fused launch (WL_PAIR_BLOCKS overrides it).
+static unsigned pair_blocks() {
+    static const unsigned v = [] {
+        const char* e = std::getenv("WL_PAIR_BLOCKS");
+        const long t = e ? std::atol(e) : 0;
+        return t > 0 ? unsigned(t) : 2048u;
+    }();
+    return v;
+}
+
 template <typename T>
 void carve_hierarchy(Carver& c, Hierarchy<T>& h, int ndim, const int n[3], const int per[3],
                      int nlev, bool alloc_fine_x) {
     h.nlev = nlev;
+    h.pairs = g_pairs.load(std::memory_order_relaxed);
     h.omega = 2.0 * ndim / (2.0 * ndim + 1.0);
     int m[3] = {n[0], n[1], n[2]};
     for (int l = 0; l < nlev; ++l) {
@@ -110,14 +140,15 @@ template void carve_hierarchy<double>(Carver&, Hierarchy<double>&, int, const in
 // ---------------------------------------------------------------- kernels
 
 // One damped-Jacobi sweep  x_out = x - w (b - A x) / D  (zero on inactive
-// cells, D = 0).  With bshift, b is the raw right-hand side and the sweep uses
+// cells, D = 0); with xout null only the norms are formed.  wgt is w, or on a
+// uniform level the factor w / D of its single D.  With bshift, b is the raw right-hand side and the sweep uses
 // its projection (b - mean) on active cells, 0 elsewhere, mean = *bshift;
 // FIRST with bproj also stores that projection.
 // NORM: per-block partial sums of r^2 (and, FIRST, of the projected b^2) in
 // FP64.
 template <typename T, int XM, bool UNIF, bool NORM, bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_smooth(TileDev TL, Grid g, XAccess<T, XM> X, Coeffs<T> C,
-                                                   const T* __restrict__ b, T omega,
+                                                   const T* __restrict__ b, T wgt,
                                                    T* __restrict__ xout,
                                                    double* __restrict__ partial,
                                                    const double* __restrict__ bshift,
@@ -191,20 +222,14 @@ __global__ __launch_bounds__(kBlock) void k_smooth(TileDev TL, Grid g, XAccess<T
                 Lyu = hyu ? C.L1[id + oyp] : T(0);
                 if (d3) Lzu = hzu ? C.L2[idu] : T(0);
             }
-            T Ax = T(0), D = T(0);
-            Ax += Lxu * (xxu - xI) - Lxl * (xI - xxl);
-            D += Lxl + Lxu;
-            Ax += Lyu * (xyu - xI) - Lyl * (xI - xyl);
-            D += Lyl + Lyu;
-            if (d3) {
-                Ax += Lzu * (xzu - xI) - Lzl * (xI - xzl);
-                D += Lzl + Lzu;
-            }
-            const bool act = D > T(0);
-            if (shift) bv = act ? T(double(bv) - mean) : T(0);
+            T Ax, D;
+            jacobi_terms(xI, xxl, xxu, xyl, xyu, xzl, xzu, Lxl, Lxu, Lyl, Lyu, Lzl, Lzu, d3, Ax, D);
+            bv = jacobi_rhs(bv, D > T(0), shift, mean);
             if (FIRST && bproj) bproj[id] = bv;
             const T r = bv - Ax;
-            xout[id] = act ? xI - omega * r / D : T(0);
+            if (xout)
+                xout[id] = UNIF ? jacobi_new_scaled(xI, r, D > T(0), wgt)
+                                : jacobi_new(xI, r, D, wgt);
             if (NORM) {
                 r2 += double(r) * double(r);
                 if (FIRST) b2 += double(bv) * double(bv);
@@ -220,6 +245,255 @@ __global__ __launch_bounds__(kBlock) void k_smooth(TileDev TL, Grid g, XAccess<T
         if (threadIdx.x == 0) {
             partial[2 * block_linear()] = s;
             partial[2 * block_linear() + 1] = sb;
+        }
+    }
+}
+
+// ------------------------------------------------- fused pair of sweeps
+// Two damped-Jacobi sweeps in one pass over a uniform, fully periodic 3D
+// level.  A workgroup owns a 64 x 8 column tile and walks a chunk of z planes;
+// per plane it computes the first sweep on the tile widened by one cell (its
+// input staged in LDS on the tile widened by two), keeps those values in LDS
+// for the x / y neighbours and in registers for the z neighbours, and writes
+// only the second sweep.  The widened cells are recomputed by the
+// neighbouring workgroups with the same operations, so the result is bitwise
+// that of two separate sweeps while the intermediate iterate never reaches
+// memory (FP32: 12 instead of 24 bytes per cell for the pair).
+constexpr int kPairTX = 64, kPairTY = 8, kPairThreads = kPairTX * kPairTY;
+constexpr int kPairHX = kPairTX + 2, kPairHY = kPairTY + 2;       // first-sweep region
+constexpr int kPairGX = kPairTX + 4, kPairGY = kPairTY + 4;       // input region
+constexpr int kPairRing1 = kPairHX * kPairHY - kPairThreads;      // 148 cells
+constexpr int kPairRing2 = kPairGX * kPairGY - kPairHX * kPairHY; // 156 cells
+constexpr int kPairDepth = 1;  // planes of loads in flight per thread
+
+struct PairTile {
+    int tx, ty;   // tiles along x and y
+    int zc;       // z planes per workgroup
+    unsigned nb;  // workgroups
+    int remap;    // XCD-contiguous tile order (nb % 8 == 0)
+};
+
+// Cell r of the one-cell ring around a w x h rectangle, in coordinates of the
+// ring's (w + 2) x (h + 2) box: bottom row, top row, left and right columns.
+__device__ __forceinline__ void ring_cell(int r, int w, int h, int& x, int& y) {
+    const int W = w + 2;
+    if (r < W) {
+        x = r;
+        y = 0;
+    } else if (r < 2 * W) {
+        x = r - W;
+        y = h + 1;
+    } else if (r < 2 * W + h) {
+        x = 0;
+        y = r - 2 * W + 1;
+    } else {
+        x = W - 1;
+        y = r - 2 * W - h + 1;
+    }
+}
+
+template <typename T, int XM>
+__global__ __launch_bounds__(kPairThreads) void k_smooth_pair(PairTile P, Grid g, XAccess<T, XM> X,
+                                                              T Lc, const T* __restrict__ b,
+                                                              T wD, T* __restrict__ xout,
+                                                              const double* __restrict__ bshift) {
+    __shared__ T s0[2][kPairGY * kPairGX];  // input plane, tile widened by two
+    __shared__ T s1[2][kPairHY * kPairHX];  // first-sweep plane, tile widened by one
+    unsigned blk = blockIdx.x;
+    if (P.remap) blk = (blk & 7u) * (P.nb >> 3) + (blk >> 3);
+    const int tix = int(blk % unsigned(P.tx));
+    blk /= unsigned(P.tx);
+    const int tiy = int(blk % unsigned(P.ty));
+    const int z0 = int(blk / unsigned(P.ty)) * P.zc;
+    const int z1 = min(z0 + P.zc, g.n2);
+    const int i0 = tix * kPairTX, j0 = tiy * kPairTY;
+    const int t = int(threadIdx.x);
+    const unsigned n0 = unsigned(g.n0), plane = n0 * unsigned(g.n1);
+    const unsigned ncp = unsigned(X.nc0) * unsigned(X.nc1);
+    const bool shift = bshift != nullptr;
+    const double mean = shift ? *bshift : 0.0;
+    // A cell this thread handles: periodic grid column, parent column (for
+    // the prolongation) and position in the input-region LDS plane.
+    struct Slot {
+        unsigned col, pcol;
+        int q;
+    };
+    auto slot = [&](int gx, int gy) -> Slot {
+        int i = i0 + gx - 2, j = j0 + gy - 2;
+        i = i < 0 ? i + g.n0 : (i >= g.n0 ? i - g.n0 : i);
+        j = j < 0 ? j + g.n1 : (j >= g.n1 ? j - g.n1 : j);
+        return Slot{unsigned(i) + n0 * unsigned(j),
+                    unsigned(i >> 1) + unsigned(X.nc0) * unsigned(j >> 1), gy * kPairGX + gx};
+    };
+    // A: the thread's own tile cell; B: a cell of the first-sweep ring (the
+    // first kPairRing1 threads); C: a cell of the input ring (the last
+    // kPairRing2 threads), needed only as an x / y neighbour.
+    const int ax = t % kPairTX, ay = t / kPairTX;
+    const Slot A = slot(ax + 2, ay + 2);
+    const int hA = (ay + 1) * kPairHX + ax + 1;
+    const bool hasB = t < kPairRing1;
+    const bool hasC = t >= kPairThreads - kPairRing2;
+    Slot B = A, C = A;
+    int hB = hA;
+    if (hasB) {
+        int hx, hy;
+        ring_cell(t, kPairTX, kPairTY, hx, hy);
+        B = slot(hx + 1, hy + 1);
+        hB = hy * kPairHX + hx;
+    }
+    if (hasC) {
+        int gx, gy;
+        ring_cell(t - (kPairThreads - kPairRing2), kPairHX, kPairHY, gx, gy);
+        C = slot(gx, gy);
+    }
+    // w: a plane index already wrapped into [0, n2)
+    // input = fine part (+ coarse part for the prolongation), loaded apart
+    // and added when first used so that the add does not wait on the loads
+    auto ld = [&](const Slot& S, int w) -> T {
+        return XM == XM_ZERO ? T(0) : X.x[S.col + unsigned(w) * plane];
+    };
+    auto ldc = [&](const Slot& S, int w) -> T {
+        return XM == XM_PROLONG ? X.xc[S.pcol + ncp * unsigned(w >> 1)] : T(0);
+    };
+    auto ldb = [&](const Slot& S, int w) -> T { return b[S.col + unsigned(w) * plane]; };
+    auto wrap = [&](int p) {
+        p %= g.n2;
+        return p < 0 ? p + g.n2 : p;
+    };
+    auto next = [&](int w) { return w + 1 == g.n2 ? 0 : w + 1; };
+    // one D for the whole level; right-hand sides are shifted once, when
+    // they become current, and serve both sweeps
+    const bool act = T(Lc + Lc) + T(Lc + Lc) + T(Lc + Lc) > T(0);
+    auto rhs = [&](T v) { return jacobi_rhs(v, act, shift, mean); };
+    // first sweep at input-region position q of plane S0 (bv shifted)
+    auto sweep1 = [&](const T* S0, int q, T xI, T xzl, T xzu, T bv) -> T {
+        T xxl = T(0), xxu = T(0), xyl = T(0), xyu = T(0);
+        if (XM != XM_ZERO) {
+            xxl = S0[q - 1];
+            xxu = S0[q + 1];
+            xyl = S0[q - kPairGX];
+            xyu = S0[q + kPairGX];
+        }
+        T Ax, D;
+        jacobi_terms(xI, xxl, xxu, xyl, xyu, xzl, xzu, Lc, Lc, Lc, Lc, Lc, Lc, true, Ax, D);
+        return jacobi_new_scaled(xI, bv - Ax, D > T(0), wD);
+    };
+    // second sweep at first-sweep position h of plane S1 (bv shifted)
+    auto sweep2 = [&](const T* S1, int h, T xI, T xzl, T xzu, T bv) -> T {
+        T Ax, D;
+        jacobi_terms(xI, S1[h - 1], S1[h + 1], S1[h - kPairHX], S1[h + kPairHX], xzl, xzu, Lc, Lc,
+                     Lc, Lc, Lc, Lc, true, Ax, D);
+        return jacobi_new_scaled(xI, bv - Ax, D > T(0), wD);
+    };
+    // Step s computes the first sweep on plane s and the second on plane
+    // s - 1, for s = z0 - 1 .. z1, and issues the loads of plane s + 1 + Dp.
+    // Per-plane values live in register rings indexed by plane (mod R); the
+    // loop is unrolled R times so that the indices are compile-time and an
+    // in-flight load is never copied before its use.
+    //   xA, xB: inputs of slots A, B (planes s - 1 .. s + 1 in use)
+    //   rA, rB: right-hand sides (shifted when they become current; A keeps
+    //           plane s - 1 for the second sweep)
+    //   xC:     input of slot C at plane s
+    //   yA:     A's first-sweep values (planes s - 2 .. s)
+    //   pA, pB, pC: coarse parts of the prolongated inputs, added into xA,
+    //           xB when a plane becomes s + 1 and into xC at plane s
+    constexpr int Dp = kPairDepth;
+    constexpr int R = Dp + 3;
+    T xA[R] = {}, xB[R] = {}, rA[R] = {}, rB[R] = {}, xC[R] = {}, yA[R] = {};
+    T pA[R] = {}, pB[R] = {}, pC[R] = {};
+    const int s0p = z0 - 1;  // first step; ring slot of plane p is (p - s0p) mod R
+    int wx;                  // wrapped plane of the next loads, s + 1 + Dp
+    {
+        // every thread issues the same loads (B and C default to A), so that
+        // waits on earlier loads can count them; planes past z1 + 1 that a
+        // short chunk loads here are not used
+        int w = wrap(s0p - 1);
+        xA[R - 1] = ld(A, w);
+        xB[R - 1] = ld(B, w);
+        pA[R - 1] = ldc(A, w);
+        pB[R - 1] = ldc(B, w);
+#pragma unroll
+        for (int k = 0; k <= Dp; ++k) {
+            w = next(w);  // s0p + k
+            xA[k] = ld(A, w);
+            xB[k] = ld(B, w);
+            rA[k] = ldb(A, w);
+            rB[k] = ldb(B, w);
+            xC[k] = ld(C, w);
+            pA[k] = ldc(A, w);
+            pB[k] = ldc(B, w);
+            pC[k] = ldc(C, w);
+        }
+        wx = next(w);  // s0p + 1 + Dp
+        if (XM == XM_PROLONG) {
+            xA[R - 1] += pA[R - 1];
+            xB[R - 1] += pB[R - 1];
+            xA[0] += pA[0];
+            xB[0] += pB[0];
+        }
+    }
+    int s = s0p;
+    // one step; r = (s - s0p) mod R
+    auto step = [&](auto rc) {
+        constexpr int r = decltype(rc)::value;
+        constexpr int im1 = (r + R - 1) % R, i0 = r, ip1 = (r + 1) % R, im2 = (r + R - 2) % R;
+        T* S0 = s0[s & 1];
+        T* S1 = s1[s & 1];
+        const T* S1m = s1[(s & 1) ^ 1];
+        if (XM == XM_PROLONG) xC[i0] += pC[i0];
+        if (XM != XM_ZERO) {
+            S0[A.q] = xA[i0];
+            if (hasB) S0[B.q] = xB[i0];
+            if (hasC) S0[C.q] = xC[i0];
+        }
+        __syncthreads();
+        if (s + Dp <= z1) {
+            constexpr int j = (r + 1 + Dp) % R;
+            xA[j] = ld(A, wx);
+            xB[j] = ld(B, wx);
+            rA[j] = ldb(A, wx);
+            rB[j] = ldb(B, wx);
+            xC[j] = ld(C, wx);
+            pA[j] = ldc(A, wx);
+            pB[j] = ldc(B, wx);
+            pC[j] = ldc(C, wx);
+        }
+        if (XM == XM_PROLONG) {
+            xA[ip1] += pA[ip1];
+            xB[ip1] += pB[ip1];
+        }
+        rA[i0] = rhs(rA[i0]);
+        const T y = sweep1(S0, A.q, xA[i0], xA[im1], xA[ip1], rA[i0]);
+        yA[i0] = y;
+        S1[hA] = y;
+        if (hasB) S1[hB] = sweep1(S0, B.q, xB[i0], xB[im1], xB[ip1], rhs(rB[i0]));
+        if (s > z0)
+            xout[A.col + unsigned(s - 1) * plane] = sweep2(S1m, hA, yA[im1], yA[im2], y, rA[im1]);
+        wx = next(wx);
+        ++s;
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1 % R>;
+    using I2 = std::integral_constant<int, 2 % R>;
+    using I3 = std::integral_constant<int, 3 % R>;
+    using I4 = std::integral_constant<int, 4 % R>;
+    using I5 = std::integral_constant<int, 5 % R>;
+    static_assert(R <= 6, "unrolled steps cover rings of up to 6 planes");
+    while (s <= z1) {
+        step(I0{});
+        if (s > z1) break;
+        step(I1{});
+        if (s > z1) break;
+        step(I2{});
+        if (s > z1) break;
+        step(I3{});
+        if (R > 4) {
+            if (s > z1) break;
+            step(I4{});
+        }
+        if (R > 5) {
+            if (s > z1) break;
+            step(I5{});
         }
     }
 }
@@ -616,6 +890,16 @@ static Coeffs<T> coeffs_of(const Level<T>& L) {
     return Coeffs<T>{L.L[0], L.L[1], L.L[2], L.Lc};
 }
 
+// w / D of a uniform level, D summed in the kernels' order.
+template <typename T>
+static T uniform_wd(const Level<T>& L, T omega) {
+    T D = T(0);
+    D += L.Lc + L.Lc;
+    D += L.Lc + L.Lc;
+    if (L.g.ndim == 3) D += L.Lc + L.Lc;
+    return D > T(0) ? T(omega / D) : T(0);
+}
+
 template <typename T, int XM, bool NORM, bool FIRST>
 static wl_status smooth(const Level<T>& L, const T* xin, const T* xc, const Grid* gc,
                         const T* b, T omega, T* xout, double* partial, const double* bshift,
@@ -625,10 +909,53 @@ static wl_status smooth(const Level<T>& L, const T* xin, const T* xc, const Grid
     XAccess<T, XM> X{xin, xc, gc ? gc->n0 : 0, gc ? gc->n1 : 0};
     if (L.uniform)
         k_smooth<T, XM, true, NORM, FIRST><<<ln.grid, ln.block, 0, s>>>(ln.td, 
-            L.g, X, coeffs_of(L), b, omega, xout, partial, bshift, bproj);
+            L.g, X, coeffs_of(L), b, uniform_wd(L, omega), xout, partial, bshift, bproj);
     else
         k_smooth<T, XM, false, NORM, FIRST><<<ln.grid, ln.block, 0, s>>>(ln.td, 
             L.g, X, coeffs_of(L), b, omega, xout, partial, bshift, bproj);
+    WL_CHECK_LAUNCH();
+    return WL_OK;
+}
+
+// Fused pairs run on uniform, fully periodic 3D levels whose x / y extents
+// are multiples of the 64 x 8 tile (mode 1: only levels of at least
+// pair_min_cells() cells).
+template <typename T>
+static bool pair_ok(const Hierarchy<T>& h, const Level<T>& L) {
+    if (!h.pairs || !L.uniform || L.g.ndim != 3) return false;
+    if (L.g.n0 % kPairTX != 0 || L.g.n1 % kPairTY != 0) return false;
+    return h.pairs == 2 || cells(L.g) >= pair_min_cells();
+}
+
+static PairTile pair_tile(const Grid& g) {
+    PairTile p;
+    p.tx = g.n0 / kPairTX;
+    p.ty = g.n1 / kPairTY;
+    const size_t cols = size_t(p.tx) * size_t(p.ty);
+    size_t zc = (cols * size_t(g.n2) + pair_blocks() - 1) / pair_blocks();
+    // the chunk re-reads two input planes on either side: keep it >= 8
+    zc = std::min(std::max(zc, size_t(8)), size_t(g.n2));
+    const unsigned chunks = unsigned((size_t(g.n2) + zc - 1) / zc);
+    p.zc = int(zc);
+    p.nb = unsigned(cols) * chunks;
+    p.remap = (p.nb % 8u == 0u) ? 1 : 0;
+    return p;
+}
+
+// xout = S(S(xin)) (XM_ZERO: from zero; XM_PROLONG: from xin plus the
+// piecewise-constant prolongation of xc).  xout must not alias the inputs.
+template <typename T, int XM>
+static wl_status pair(const Level<T>& L, const T* xin, const T* xc, const Grid* gc, const T* b,
+                      T omega, T* xout, const double* bshift, hipStream_t s, int prof = -1) {
+    if (xout == xin || xout == xc || xout == b) {
+        set_error("internal: fused sweep pair output aliases an input");
+        return WL_ERR_INVALID_ARG;
+    }
+    const PairTile P = pair_tile(L.g);
+    ProfScope ps(prof, s, cells(L.g));
+    XAccess<T, XM> X{xin, xc, gc ? gc->n0 : 0, gc ? gc->n1 : 0};
+    k_smooth_pair<T, XM><<<P.nb, kPairThreads, 0, s>>>(P, L.g, X, L.Lc, b, uniform_wd(L, omega),
+                                                       xout, bshift);
     WL_CHECK_LAUNCH();
     return WL_OK;
 }
@@ -720,42 +1047,91 @@ template wl_status mg_coarsen_all<double>(Hierarchy<double>&, hipStream_t);
 template wl_status mg_count_active<float>(Hierarchy<float>&, Reduce&, hipStream_t);
 template wl_status mg_count_active<double>(Hierarchy<double>&, Reduce&, hipStream_t);
 
-// Remainder of one V-cycle once its first fine pre-sweep has written
-// lev[0].x[1]; leaves the fine iterate in lev[0].x[0].
+// How a V-cycle finds the fine level's pre-smoothing: the first sweep
+// already done into x[1] (Half), both sweeps still to do from the fine
+// iterate (Full) or from zero (Zero).
+enum class Pre { Half, Full, Zero };
+
+// Pre-smoothing of one level: two sweeps from `home` (or zero), with `other`
+// as the second buffer.  Separate sweeps end in home, a fused pair in other;
+// *out says where.  b / bs: right-hand side and the mean to remove from it
+// (null: none).
 template <typename T>
-static wl_status vcycle_rest(Hierarchy<T>& h, const T* fb, const double* fshift, hipStream_t s) {
+static wl_status pre_smooth(const Hierarchy<T>& h, const Level<T>& L, Pre mode, T* home, T* other,
+                            const T* b, const double* bs, hipStream_t s, const T** out,
+                            bool fine) {
+    const T w = T(h.omega);
+    if (mode != Pre::Half && pair_ok(h, L)) {
+        if (mode == Pre::Zero)
+            WL_TRY((pair<T, XM_ZERO>(L, nullptr, nullptr, nullptr, b, w, other, bs, s,
+                                     fine ? WL_PROF_PAIR_FINE : -1)));
+        else
+            WL_TRY((pair<T, XM_PLAIN>(L, home, nullptr, nullptr, b, w, other, bs, s,
+                                      fine ? WL_PROF_PAIR_FINE : -1)));
+        *out = other;
+        return WL_OK;
+    }
+    if (mode == Pre::Zero)
+        WL_TRY((smooth<T, XM_ZERO, false, false>(L, nullptr, nullptr, nullptr, b, w, other, nullptr,
+                                                 bs, s)));
+    else if (mode == Pre::Full)
+        WL_TRY((smooth<T, XM_PLAIN, false, false>(L, home, nullptr, nullptr, b, w, other, nullptr,
+                                                  bs, s)));
+    WL_TRY((smooth<T, XM_PLAIN, false, false>(L, other, nullptr, nullptr, b, w, home, nullptr, bs, s,
+                                              fine ? WL_PROF_SMOOTH_FINE : -1)));
+    *out = home;
+    return WL_OK;
+}
+
+// Post-smoothing of one level: the coarse correction C.x[1] prolongated onto
+// the pre-smoothed iterate `pre`, fused with the first of two sweeps; the
+// result lands in home.
+template <typename T>
+static wl_status post_smooth(const Hierarchy<T>& h, const Level<T>& L, const T* pre, T* home,
+                             T* other, const Level<T>& C, const T* b, const double* bs,
+                             hipStream_t s, bool fine) {
+    const T w = T(h.omega);
+    if (pre == other) {
+        // only a fused pre-smoothing leaves its result in other
+        if (!pair_ok(h, L)) {
+            set_error("internal: unfused post-smoothing after a fused pre-smoothing");
+            return WL_ERR_INVALID_ARG;
+        }
+        return pair<T, XM_PROLONG>(L, other, C.x[1], &C.g, b, w, home, bs, s,
+                                   fine ? WL_PROF_PAIR_PROLONG_FINE : -1);
+    }
+    WL_TRY((smooth<T, XM_PROLONG, false, false>(L, home, C.x[1], &C.g, b, w, other, nullptr, bs, s,
+                                                fine ? WL_PROF_PROLONG_FINE : -1)));
+    return smooth<T, XM_PLAIN, false, false>(L, other, nullptr, nullptr, b, w, home, nullptr, bs, s,
+                                             fine ? WL_PROF_SMOOTH_FINE : -1);
+}
+
+// Remainder of one V-cycle: fine pre-smoothing as `mode` says, restriction,
+// the coarse levels, and post-smoothing; leaves the fine iterate in
+// lev[0].x[0].  Level l > 0 keeps its result in x[1] (where the next finer
+// prolongation reads it) and uses x[0] as the second buffer.
+template <typename T>
+static wl_status vcycle_rest(Hierarchy<T>& h, Pre mode, const T* fb, const double* fshift,
+                             hipStream_t s) {
     // fb / fshift: fine-level right-hand side and the mean to remove from it
     // on the fly (null: fb is already projected)
     Level<T>& F = h.lev[0];
-    const T w = T(h.omega);
     if (h.nlev == 1) return coarse_solve(h, F, F.x[0], s);
-    WL_TRY((smooth<T, XM_PLAIN, false, false>(F, F.x[1], nullptr, nullptr, fb, w, F.x[0], nullptr,
-                                              fshift, s, WL_PROF_SMOOTH_FINE)));
-    WL_TRY(resid_restrict(F, F.x[0], fb, fshift, h.lev[1], s, WL_PROF_RESTRICT_FINE));
+    const T* pre[kMaxLevels];
+    WL_TRY(pre_smooth(h, F, mode, F.x[0], F.x[1], fb, fshift, s, &pre[0], true));
+    WL_TRY(resid_restrict(F, pre[0], fb, fshift, h.lev[1], s, WL_PROF_RESTRICT_FINE));
     for (int l = 1; l < h.nlev - 1; ++l) {
         Level<T>& L = h.lev[l];
-        WL_TRY((smooth<T, XM_ZERO, false, false>(L, nullptr, nullptr, nullptr, L.b, w, L.x[0],
-                                                 nullptr, nullptr, s)));
-        WL_TRY((smooth<T, XM_PLAIN, false, false>(L, L.x[0], nullptr, nullptr, L.b, w, L.x[1],
-                                                  nullptr, nullptr, s)));
-        WL_TRY(resid_restrict(L, L.x[1], L.b, nullptr, h.lev[l + 1], s));
+        WL_TRY(pre_smooth(h, L, Pre::Zero, L.x[1], L.x[0], L.b, nullptr, s, &pre[l], false));
+        WL_TRY(resid_restrict(L, pre[l], L.b, nullptr, h.lev[l + 1], s));
     }
     Level<T>& Cst = h.lev[h.nlev - 1];
     WL_TRY(coarse_solve(h, Cst, Cst.x[1], s));
     for (int l = h.nlev - 2; l >= 1; --l) {
         Level<T>& L = h.lev[l];
-        const Level<T>& C = h.lev[l + 1];
-        WL_TRY((smooth<T, XM_PROLONG, false, false>(L, L.x[1], C.x[1], &C.g, L.b, w, L.x[0],
-                                                    nullptr, nullptr, s)));
-        WL_TRY((smooth<T, XM_PLAIN, false, false>(L, L.x[0], nullptr, nullptr, L.b, w, L.x[1],
-                                                  nullptr, nullptr, s)));
+        WL_TRY(post_smooth(h, L, pre[l], L.x[1], L.x[0], h.lev[l + 1], L.b, nullptr, s, false));
     }
-    const Level<T>& C1 = h.lev[1];
-    WL_TRY((smooth<T, XM_PROLONG, false, false>(F, F.x[0], C1.x[1], &C1.g, fb, w, F.x[1], nullptr,
-                                                fshift, s, WL_PROF_PROLONG_FINE)));
-    WL_TRY((smooth<T, XM_PLAIN, false, false>(F, F.x[1], nullptr, nullptr, fb, w, F.x[0], nullptr,
-                                              fshift, s, WL_PROF_SMOOTH_FINE)));
-    return WL_OK;
+    return post_smooth(h, F, pre[0], F.x[0], F.x[1], h.lev[1], fb, fshift, s, true);
 }
 
 static wl_status read_norms(Reduce& red, double* host2, hipStream_t s) {
@@ -791,11 +1167,16 @@ wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, d
     const T w = T(h.omega);
     const Launch ln = launch_for(F.g.n0, F.g.n1, F.g.n2);
     WL_TRY(active_mean(h, red, b, b_partials, s));
-    // first fine sweep: measures ||r0|| and ||b - mean||.  Every fine-level
-    // sweep removes the mean of b on the fly; only a one-level hierarchy
-    // (whose coarse solve reads F.b) stores the projected copy.
+    // With fused fine pairs each V-cycle starts with both pre-sweeps from x
+    // and the residual checks only measure; otherwise every check is also
+    // the first pre-sweep of the next V-cycle (into F.x[1]).
+    const bool fused = h.nlev > 1 && pair_ok(h, F);
+    T* const xnext = fused ? nullptr : F.x[1];
+    // first check: ||r0|| and ||b - mean||.  Every fine-level sweep removes
+    // the mean of b on the fly; only a one-level hierarchy (whose coarse
+    // solve reads F.b) stores the projected copy.
     const double* bshift = red.result + 5;
-    WL_TRY((smooth<T, XM_PLAIN, true, true>(F, x, nullptr, nullptr, b, w, F.x[1], red.partial,
+    WL_TRY((smooth<T, XM_PLAIN, true, true>(F, x, nullptr, nullptr, b, w, xnext, red.partial,
                                             bshift, s, -1, h.nlev == 1 ? F.b : nullptr)));
     WL_TRY(reduce<T>(red, ln.nblocks(), 2, 1.0, red.result, s));
     double nr[2];
@@ -833,9 +1214,10 @@ wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, d
     int k = 0;
     // one V-cycle and the residual norms it leaves (replayed as a graph)
     auto body = [&](hipStream_t q) -> wl_status {
-        WL_TRY(vcycle_rest(h, b, bshift, q));
-        WL_TRY((smooth<T, XM_PLAIN, true, false>(F, x, nullptr, nullptr, b, w, F.x[1],
-                                                 red.partial, bshift, q, WL_PROF_SMOOTH_NORM)));
+        WL_TRY(vcycle_rest(h, fused ? Pre::Full : Pre::Half, b, bshift, q));
+        WL_TRY((smooth<T, XM_PLAIN, true, false>(F, x, nullptr, nullptr, b, w, xnext, red.partial,
+                                                 bshift, q,
+                                                 fused ? WL_PROF_NORM_FINE : WL_PROF_SMOOTH_NORM)));
         return reduce<T>(red, ln.nblocks(), 2, 1.0, red.result, q);
     };
     while (!done(r2) && k < max_vcycles) {
@@ -875,7 +1257,6 @@ wl_status mg_solve_mixed(Hierarchy<float>& h32, const Mixed64& m, Reduce& red, d
     const Grid g = F.g;
     const Launch ln = launch_for(g.n0, g.n1, g.n2);
     const size_t N = cells(g);
-    const float w = float(h32.omega);
     Coeffs<double> C64{m.L[0], m.L[1], m.L[2], 1.0};
     // active mean of b in FP64 (result[5])
     k_sum_active<double, false><<<ln.grid, ln.block, 0, s>>>(ln.td, g, C64, b, red.partial);
@@ -897,15 +1278,9 @@ wl_status mg_solve_mixed(Hierarchy<float>& h32, const Mixed64& m, Reduce& red, d
     // `count` inner FP32 V-cycles on A e = r from e = 0, x += e in FP64, and
     // the next residual
     auto outer = [&](hipStream_t q, int count) -> wl_status {
-        for (int v = 0; v < count; ++v) {
-            if (v == 0)
-                WL_TRY((smooth<float, XM_ZERO, false, false>(F, nullptr, nullptr, nullptr, F.b, w,
-                                                             F.x[1], nullptr, nullptr, q)));
-            else
-                WL_TRY((smooth<float, XM_PLAIN, false, false>(F, F.x[0], nullptr, nullptr, F.b, w,
-                                                              F.x[1], nullptr, nullptr, q)));
-            WL_TRY(vcycle_rest(h32, static_cast<const float*>(F.b), nullptr, q));
-        }
+        for (int v = 0; v < count; ++v)
+            WL_TRY(vcycle_rest(h32, v == 0 ? Pre::Zero : Pre::Full, static_cast<const float*>(F.b),
+                               nullptr, q));
         k_axpy64<<<unsigned((N + kBlock - 1) / kBlock), kBlock, 0, q>>>(N, F.x[0], x);
         WL_CHECK_LAUNCH();
         return resid(q);
@@ -949,3 +1324,13 @@ wl_status mg_solve_mixed(Hierarchy<float>& h32, const Mixed64& m, Reduce& red, d
 }
 
 }  // namespace wl
+
+extern "C" wl_status wl_set_fused_sweeps(int mode) {
+    wl::clear_error();
+    if (mode < 0 || mode > 2) {
+        wl::set_error("wl_set_fused_sweeps: mode must be 0, 1 or 2");
+        return WL_ERR_INVALID_ARG;
+    }
+    wl::g_pairs.store(mode, std::memory_order_relaxed);
+    return WL_OK;
+}

@@ -49,7 +49,9 @@ thread_local Rec t_open[WL_PROF_COUNT];
 // sweeps and transfers) turns graph replay off.
 bool prof_active() {
     constexpr unsigned in_graphs = (1u << WL_PROF_SMOOTH_FINE) | (1u << WL_PROF_SMOOTH_NORM) |
-                                   (1u << WL_PROF_PROLONG_FINE) | (1u << WL_PROF_RESTRICT_FINE);
+                                   (1u << WL_PROF_PROLONG_FINE) | (1u << WL_PROF_RESTRICT_FINE) |
+                                   (1u << WL_PROF_NORM_FINE) | (1u << WL_PROF_PAIR_FINE) |
+                                   (1u << WL_PROF_PAIR_PROLONG_FINE);
     return (prof().mask.load(std::memory_order_relaxed) & in_graphs) != 0u;
 }
 

@@ -189,6 +189,7 @@ struct Hierarchy {
     double omega = 0.0;
     double coarse_tol = 1e-10;
     size_t n_active = 0;         // active fine cells (host copy)
+    int pairs = 0;               // fused two-sweep kernels: 0 off, 1 on large levels, 2 on all
     GraphCache graphs;
 };
 

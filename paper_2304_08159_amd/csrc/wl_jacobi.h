@@ -1,0 +1,51 @@
+// The damped-Jacobi update of one cell, shared by the single-sweep and the
+// fused two-sweep multigrid kernels so that both evaluate it with the same
+// operations in the same order (their iterates are then bitwise equal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace wl {
+
+// A x and the diagonal magnitude D of one row,
+//   A x = sum_d Lu_d (x_up - x) - Ll_d (x - x_lo),   D = sum_d (Ll_d + Lu_d),
+// from the cell value, its lower / upper neighbours per direction and the
+// face coefficients; the z terms are left out in 2D.
+template <typename T>
+__device__ __forceinline__ void jacobi_terms(T xI, T xxl, T xxu, T xyl, T xyu, T xzl, T xzu,
+                                             T Lxl, T Lxu, T Lyl, T Lyu, T Lzl, T Lzu, bool d3,
+                                             T& Ax, T& D) {
+    Ax = T(0);
+    D = T(0);
+    Ax += Lxu * (xxu - xI) - Lxl * (xI - xxl);
+    D += Lxl + Lxu;
+    Ax += Lyu * (xyu - xI) - Lyl * (xI - xyl);
+    D += Lyl + Lyu;
+    if (d3) {
+        Ax += Lzu * (xzu - xI) - Lzl * (xI - xzl);
+        D += Lzl + Lzu;
+    }
+}
+
+// Right-hand side seen by the sweep: with a mean to remove, b - mean on
+// active cells (computed in FP64) and 0 on inactive ones.
+template <typename T>
+__device__ __forceinline__ T jacobi_rhs(T bv, bool act, bool shift, double mean) {
+    if (shift) bv = act ? T(double(bv) - mean) : T(0);
+    return bv;
+}
+
+// x - w r / D on active cells (D > 0), 0 elsewhere.
+template <typename T>
+__device__ __forceinline__ T jacobi_new(T xI, T r, T D, T omega) {
+    return D > T(0) ? xI - omega * r / D : T(0);
+}
+
+// The same with the factor w / D given: levels with one coefficient
+// everywhere have one D, and the factor is formed once per level.
+template <typename T>
+__device__ __forceinline__ T jacobi_new_scaled(T xI, T r, bool act, T wD) {
+    return act ? xI - wD * r : T(0);
+}
+
+}  // namespace wl

@@ -100,3 +100,15 @@ def test_batch_footprint_validates_requests_without_a_gpu():
         st = lib.wl_poisson_batch_footprint(arr, 2, ctypes.byref(sz))
         assert st == _lib.WL_ERR_INVALID_ARG
         assert b"request 1" in lib.wl_last_error()
+
+
+def test_fused_sweep_mode_is_validated_without_a_gpu():
+    from paper_2304_08159_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libwl.so not built")
+    lib = _lib.load()
+    assert lib.wl_set_fused_sweeps(3) == -1
+    assert b"mode" in lib.wl_last_error()
+    assert lib.wl_set_fused_sweeps(-1) == -1
+    for mode in (0, 2, 1):
+        assert lib.wl_set_fused_sweeps(mode) == 0
