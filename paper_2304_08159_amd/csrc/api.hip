@@ -183,7 +183,7 @@ static void carve_sim(Carver& c, SimImpl<T>& s, const SimConfig& cfg) {
     carve_hierarchy<T>(c, s.h, cfg.d.ndim, cfg.d.n, per, cfg.nlev, cfg.d.prec == WL_MIXED);
     s.red.slots = reduce_slots_for(cfg.g);
     s.red.partial = c.take<double>(4 * s.red.slots);
-    s.red.result = c.take<double>(16);
+    s.red.result = c.take<double>(kResultDoubles);
     s.scal = c.take<double>(4);
     if (cfg.d.prec == WL_MIXED) {
         for (int i = 0; i < 3; ++i) s.mix.L[i] = c.take<double>(N);
@@ -794,7 +794,7 @@ static void carve_poisson_common(Carver& c, H& P, const Grid& g, int nlev, bool 
     carve_hierarchy(c, P.h, g.ndim, n, per, nlev, fine_x);
     P.red.slots = reduce_slots_for(g);
     P.red.partial = c.take<double>(2 * P.red.slots);
-    P.red.result = c.take<double>(8);
+    P.red.result = c.take<double>(kResultDoubles);
 }
 
 template <typename T>

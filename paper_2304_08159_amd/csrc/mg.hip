@@ -625,37 +625,60 @@ __global__ __launch_bounds__(kBlock) void k_sum_active(TileDev TL, Grid g, Coeff
 
 // Copies n doubles to pinned host memory, then (after a system-scope fence)
 // the sequence number the host is waiting for.  One thread.
-__global__ void k_publish(const double* __restrict__ src, int n, double* dst, unsigned* seqw,
-                          unsigned q) {
-    for (int k = 0; k < n; ++k) dst[k] = src[k];
+template <typename T>
+__global__ void k_fill(T* __restrict__ p, size_t n, T v);
+
+// One thread: the values, then (after a system-scope fence) the next
+// sequence number, counted in device memory.
+__device__ void mailbox_write(const MailboxPost& P, const double* src) {
+    for (int k = 0; k < P.n; ++k) P.vals[P.slot + k] = src[k];
+    const double q = *P.counter + 1.0;
+    *P.counter = q;
     __threadfence_system();
-    __hip_atomic_store(seqw, q, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(P.seqw, unsigned(q), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
+
+__global__ void k_publish(const double* __restrict__ src, MailboxPost P) { mailbox_write(P, src); }
 
 HostMailbox::~HostMailbox() {
     if (vals) (void)hipHostFree(vals);
 }
 
-wl_status host_post(Reduce& red, const double* src, int n, int slot, hipStream_t s) {
+wl_status mailbox_post_args(Reduce& red, int slot, int n, hipStream_t s, MailboxPost* out) {
     HostMailbox& mb = red.mb;
     if (n < 0 || slot < 0 || slot + n > HostMailbox::kSlots) {
-        set_error("host_post: slot range outside the mailbox");
+        set_error("mailbox post: slot range outside the mailbox");
         return WL_ERR_INVALID_ARG;
     }
+    double* counter = red.result + kResultCounter;
     if (!mb.vals) {
         void* p = nullptr;
         WL_CHECK_HIP(hipHostMalloc(&p, 256, hipHostMallocCoherent | hipHostMallocMapped));
         mb.vals = static_cast<double*>(p);
         mb.seqw = reinterpret_cast<unsigned*>(mb.vals + HostMailbox::kSlots);
         *mb.seqw = 0u;
+        mb.seq = 0u;
         void* d = nullptr;
         WL_CHECK_HIP(hipHostGetDevicePointer(&d, p, 0));
         mb.vals_dev = static_cast<double*>(d);
         mb.seqw_dev = reinterpret_cast<unsigned*>(mb.vals_dev + HostMailbox::kSlots);
+        // the device count starts with the host's (a fill kernel: this may be
+        // enqueued while a caller captures)
+        k_fill<double><<<1, 64, 0, s>>>(counter, 1, 0.0);
+        WL_CHECK_LAUNCH();
     }
-    const unsigned q = ++mb.seq;
-    k_publish<<<1, 1, 0, s>>>(src, n, mb.vals_dev + slot, mb.seqw_dev, q);
+    *out = MailboxPost{mb.vals_dev, mb.seqw_dev, counter, slot, n};
+    return WL_OK;
+}
+
+void host_posted(Reduce& red) { ++red.mb.seq; }
+
+wl_status host_post(Reduce& red, const double* src, int n, int slot, hipStream_t s) {
+    MailboxPost P;
+    WL_TRY(mailbox_post_args(red, slot, n, s, &P));
+    k_publish<<<1, 1, 0, s>>>(src, P);
     WL_CHECK_LAUNCH();
+    host_posted(red);
     return WL_OK;
 }
 
@@ -689,9 +712,14 @@ wl_status host_read(Reduce& red, const double* src, int n, double* out, hipStrea
 }
 
 // out[c] = sum over slots of partial[slot*ncomp + c] in slot order; then
-// out[ncomp + c] = out[c] * scale (e.g. a mean).  One block of 1024 threads.
+// out[ncomp + c] = out[c] * scale, or with count (ncomp == 1) the mean
+// out[1] = out[0] / *count (0 when nothing is active); with post.vals the
+// first post.n outputs are posted to the host mailbox.  One block of 1024
+// threads.
 __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ partial, size_t nslots,
-                                                 int ncomp, double scale, double* __restrict__ out) {
+                                                 int ncomp, double scale, double* __restrict__ out,
+                                                 const double* __restrict__ count,
+                                                 MailboxPost post) {
     __shared__ double lds[1024];
     for (int c = 0; c < ncomp; ++c) {
         double s = 0.0;
@@ -704,16 +732,11 @@ __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ part
         }
         if (threadIdx.x == 0) {
             out[c] = lds[0];
-            out[ncomp + c] = lds[0] * scale;
+            out[ncomp + c] = count ? (*count > 0.0 ? lds[0] / *count : 0.0) : lds[0] * scale;
         }
         __syncthreads();
     }
-}
-
-// Mean of the active cells: out[0] = sum, out[1] = sum / count(active)
-// where count comes from a device scalar.
-__global__ void k_mean_fix(double* out, const double* count) {
-    if (threadIdx.x == 0) out[1] = (*count > 0.0) ? out[0] / *count : 0.0;
+    if (threadIdx.x == 0 && post.vals) mailbox_write(post, out);
 }
 
 // Coarsest level (see coarse_cg_block).
@@ -874,7 +897,8 @@ wl_status mg_count_active64(const Grid& g, double* const L64[3], Reduce& red, si
     Coeffs<double> C{L64[0], L64[1], L64[2], 1.0};
     k_sum_active<double, false><<<ln.grid, ln.block, 0, s>>>(ln.td, g, C, nullptr, red.partial);
     WL_CHECK_LAUNCH();
-    k_reduce<<<1, 1024, 0, s>>>(red.partial, ln.nblocks(), 1, 1.0, red.result + 6);
+    k_reduce<<<1, 1024, 0, s>>>(red.partial, ln.nblocks(), 1, 1.0, red.result + 6, nullptr,
+                                MailboxPost{});
     WL_CHECK_LAUNCH();
     double cnt = 0.0;
     WL_CHECK_HIP(hipMemcpyAsync(&cnt, red.result + 6, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1002,8 +1026,8 @@ static wl_status coarse_solve(const Hierarchy<T>& h, const Level<T>& L, T* xout,
 
 template <typename T>
 static wl_status reduce(Reduce& red, size_t nslots, int ncomp, double scale, double* out,
-                        hipStream_t s) {
-    k_reduce<<<1, 1024, 0, s>>>(red.partial, nslots, ncomp, scale, out);
+                        hipStream_t s, const MailboxPost& post = MailboxPost{}) {
+    k_reduce<<<1, 1024, 0, s>>>(red.partial, nslots, ncomp, scale, out, nullptr, post);
     WL_CHECK_LAUNCH();
     return WL_OK;
 }
@@ -1033,7 +1057,8 @@ wl_status mg_count_active(Hierarchy<T>& h, Reduce& red, hipStream_t s) {
         k_sum_active<T, false><<<ln.grid, ln.block, 0, s>>>(ln.td, F.g, coeffs_of(F), nullptr, red.partial);
     WL_CHECK_LAUNCH();
     // result[6] = active count (kept on the device for the mean kernels)
-    k_reduce<<<1, 1024, 0, s>>>(red.partial, ln.nblocks(), 1, 1.0, red.result + 6);
+    k_reduce<<<1, 1024, 0, s>>>(red.partial, ln.nblocks(), 1, 1.0, red.result + 6, nullptr,
+                                MailboxPost{});
     WL_CHECK_LAUNCH();
     double cnt = 0.0;
     WL_CHECK_HIP(hipMemcpyAsync(&cnt, red.result + 6, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1134,10 +1159,6 @@ static wl_status vcycle_rest(Hierarchy<T>& h, Pre mode, const T* fb, const doubl
     return post_smooth(h, F, pre[0], F.x[0], F.x[1], h.lev[1], fb, fshift, s, true);
 }
 
-static wl_status read_norms(Reduce& red, double* host2, hipStream_t s) {
-    return host_read(red, red.result, 2, host2, s);
-}
-
 template <typename T>
 static wl_status active_mean(Hierarchy<T>& h, Reduce& red, const T* b, bool have_partials,
                              hipStream_t s) {
@@ -1150,10 +1171,9 @@ static wl_status active_mean(Hierarchy<T>& h, Reduce& red, const T* b, bool have
     else
         k_sum_active<T, false><<<ln.grid, ln.block, 0, s>>>(ln.td, F.g, coeffs_of(F), b, red.partial);
     WL_CHECK_LAUNCH();
-    // result[4] = sum, result[5] = mean
-    k_reduce<<<1, 1024, 0, s>>>(red.partial, ln.nblocks(), 1, 1.0, red.result + 4);
-    WL_CHECK_LAUNCH();
-    k_mean_fix<<<1, 64, 0, s>>>(red.result + 4, red.result + 6);
+    // result[4] = sum, result[5] = mean over the active count result[6]
+    k_reduce<<<1, 1024, 0, s>>>(red.partial, ln.nblocks(), 1, 1.0, red.result + 4,
+                                red.result + 6, MailboxPost{});
     WL_CHECK_LAUNCH();
     return WL_OK;
 }
@@ -1178,19 +1198,16 @@ wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, d
     const double* bshift = red.result + 5;
     WL_TRY((smooth<T, XM_PLAIN, true, true>(F, x, nullptr, nullptr, b, w, xnext, red.partial,
                                             bshift, s, -1, h.nlev == 1 ? F.b : nullptr)));
-    WL_TRY(reduce<T>(red, ln.nblocks(), 2, 1.0, red.result, s));
-    double nr[2];
-    if (tail) {
-        // speculate that the initial iterate already converges: the tail
-        // runs on it while the host waits for the norms
-        WL_TRY(host_post(red, red.result, 2, 0, s));
-        WL_TRY((*tail)(s));
-        WL_TRY(host_wait(red, s));
-        nr[0] = host_slot(red, 0);
-        nr[1] = host_slot(red, 1);
-    } else {
-        WL_TRY(read_norms(red, nr, s));
-    }
+    // the norm reductions post ||r||^2, ||b||^2 to mailbox slots 0, 1
+    MailboxPost post;
+    WL_TRY(mailbox_post_args(red, 0, 2, s, &post));
+    WL_TRY(reduce<T>(red, ln.nblocks(), 2, 1.0, red.result, s, post));
+    host_posted(red);
+    // speculate that the initial iterate already converges: the tail runs on
+    // it while the host waits for the norms
+    if (tail) WL_TRY((*tail)(s));
+    WL_TRY(host_wait(red, s));
+    double nr[2] = {host_slot(red, 0), host_slot(red, 1)};
     if (!std::isfinite(nr[0]) || !std::isfinite(nr[1])) {
         set_error("non-finite residual norm in the pressure solve");
         return WL_ERR_NONFINITE;
@@ -1218,12 +1235,15 @@ wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, d
         WL_TRY((smooth<T, XM_PLAIN, true, false>(F, x, nullptr, nullptr, b, w, xnext, red.partial,
                                                  bshift, q,
                                                  fused ? WL_PROF_NORM_FINE : WL_PROF_SMOOTH_NORM)));
-        return reduce<T>(red, ln.nblocks(), 2, 1.0, red.result, q);
+        return reduce<T>(red, ln.nblocks(), 2, 1.0, red.result, q, post);
     };
     while (!done(r2) && k < max_vcycles) {
         WL_TRY(run_cached(h.graphs, x, b, s, body));
         ++k;
-        WL_TRY(read_norms(red, nr, s));
+        host_posted(red);
+        WL_TRY(host_wait(red, s));
+        nr[0] = host_slot(red, 0);
+        nr[1] = host_slot(red, 1);
         if (!std::isfinite(nr[0])) {
             set_error("non-finite residual norm in the pressure solve");
             return WL_ERR_NONFINITE;
@@ -1261,19 +1281,21 @@ wl_status mg_solve_mixed(Hierarchy<float>& h32, const Mixed64& m, Reduce& red, d
     // active mean of b in FP64 (result[5])
     k_sum_active<double, false><<<ln.grid, ln.block, 0, s>>>(ln.td, g, C64, b, red.partial);
     WL_CHECK_LAUNCH();
-    k_reduce<<<1, 1024, 0, s>>>(red.partial, ln.nblocks(), 1, 1.0, red.result + 4);
-    WL_CHECK_LAUNCH();
-    k_mean_fix<<<1, 64, 0, s>>>(red.result + 4, red.result + 6);
+    k_reduce<<<1, 1024, 0, s>>>(red.partial, ln.nblocks(), 1, 1.0, red.result + 4,
+                                red.result + 6, MailboxPost{});
     WL_CHECK_LAUNCH();
     int inner_total = 0;
     double b2 = -1.0, r2 = 0.0;
     auto done = [&](double q) { return q <= tol * tol * b2 || q <= abs_r2; };
-    // FP64 residual (projected into the FP32 fine RHS) and its norms
+    // FP64 residual (projected into the FP32 fine RHS) and its norms, posted
+    // to mailbox slots 0, 1 (each execution is matched by one host_posted)
+    MailboxPost post;
+    WL_TRY(mailbox_post_args(red, 0, 2, s, &post));
     auto resid = [&](hipStream_t q) -> wl_status {
         XAccess<double, XM_PLAIN> X{x, nullptr, 0, 0};
         k_resid64<<<ln.grid, ln.block, 0, q>>>(ln.td, g, X, C64, b, red.result + 5, F.b, red.partial);
         WL_CHECK_LAUNCH();
-        return reduce<double>(red, ln.nblocks(), 2, 1.0, red.result, q);
+        return reduce<double>(red, ln.nblocks(), 2, 1.0, red.result, q, post);
     };
     // `count` inner FP32 V-cycles on A e = r from e = 0, x += e in FP64, and
     // the next residual
@@ -1287,8 +1309,10 @@ wl_status mg_solve_mixed(Hierarchy<float>& h32, const Mixed64& m, Reduce& red, d
     };
     WL_TRY(resid(s));
     for (;;) {
-        double nr[2];
-        WL_TRY(read_norms(red, nr, s));
+        // one resid has run since the last wait
+        host_posted(red);
+        WL_TRY(host_wait(red, s));
+        const double nr[2] = {host_slot(red, 0), host_slot(red, 1)};
         if (!std::isfinite(nr[0]) || !std::isfinite(nr[1])) {
             set_error("non-finite residual norm in the mixed-precision solve");
             return WL_ERR_NONFINITE;

@@ -194,9 +194,12 @@ struct Hierarchy {
 };
 
 // A few doubles handed from the device to the host without a copy engine or
-// a stream synchronisation: a one-thread kernel writes them into coherent
-// pinned host memory followed by a sequence number, and the host waits for
-// that number (see host_read).  Allocated on first use, one per solver.
+// a stream synchronisation: a kernel writes them into coherent pinned host
+// memory followed by a sequence number, and the host waits for that number
+// (see host_read).  The number is counted on the device (Reduce::result
+// [kResultCounter]) and, post by post, on the host, so that a post inside a
+// replayed graph still carries a new number.  Allocated on first use, one
+// per solver.
 struct HostMailbox {
     static constexpr int kSlots = 16;
     double* vals = nullptr;      // pinned host: kSlots values, then the sequence word
@@ -211,16 +214,32 @@ struct HostMailbox {
 };
 
 // Reduction scratch: per-block FP64 partial slots plus a few result scalars.
+constexpr int kResultDoubles = 16;
+constexpr int kResultCounter = 15;  // device count of mailbox posts
 struct Reduce {
     double* partial = nullptr;   // capacity slots * 2
     size_t slots = 0;
-    double* result = nullptr;    // 8 doubles
+    double* result = nullptr;    // kResultDoubles doubles
     HostMailbox mb;
+};
+
+// Device addresses a kernel needs to post into the mailbox.
+struct MailboxPost {
+    double* vals = nullptr;      // null: no post
+    unsigned* seqw = nullptr;
+    double* counter = nullptr;
+    int slot = 0, n = 0;
 };
 
 // Enqueue on s: copy src[0..n) (device) into mailbox slots [slot, slot + n)
 // once everything before it on s has completed.  Does not wait.
 wl_status host_post(Reduce& red, const double* src, int n, int slot, hipStream_t s);
+// For a kernel that posts by itself: allocate the mailbox if needed (its
+// device counter is cleared on s) and return the addresses for slots
+// [slot, slot + n).  Every execution of such a kernel must be followed, on
+// the host, by one host_posted before the matching host_wait.
+wl_status mailbox_post_args(Reduce& red, int slot, int n, hipStream_t s, MailboxPost* out);
+void host_posted(Reduce& red);
 // Wait until the most recent post has arrived (so have all earlier ones, in
 // stream order): polls the mailbox for a bounded time, then falls back to
 // hipStreamSynchronize (which also reports a failed kernel).
