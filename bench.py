@@ -264,8 +264,8 @@ def main():
         t = torch.from_numpy(np.ascontiguousarray(a.transpose(2, 1, 0))).float().cuda()
         sim.set(wl.FIELD_U0 + i, t)
     del u, v, w
-    for _ in range(args.warmup):
-        sim.step()
+    if args.warmup:
+        sim.run(args.warmup)
     lib = _lib.load()
 
     def ctypes_mask(on):
@@ -274,12 +274,9 @@ def main():
     def timed(nsteps, profile):
         lib.wl_profile_enable(ctypes_mask(profile))
         lib.wl_profile_reset()
-        vc = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(nsteps):
-            st = sim.step()
-            vc.append(st["vcycles"])
+        vc = [st["vcycles"] for st in sim.run(nsteps)]
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         lib.wl_profile_enable(0)
@@ -309,14 +306,16 @@ def main():
     # launched on; its average launch time gives the roofline
     lib.wl_profile_enable(1 << _lib.PROF[dom])
     lib.wl_profile_reset()
-    vcs = []
+    # the K steps run as one library call (the time loop of the method)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        vcs.append(sim.step()["vcycles"])
+    stats = sim.run(args.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     lib.wl_profile_enable(0)
+    if len(stats) != args.steps:
+        raise RuntimeError(f"the run stopped after {len(stats)} of {args.steps} steps")
+    vcs = [st["vcycles"] for st in stats]
     dom_live = read_prof()[dom]
     ms_step = 1e3 * elapsed / args.steps
     cells = N ** 3

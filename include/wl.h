@@ -155,6 +155,15 @@ wl_status wl_set_time(wl_sim* sim, double t);
  * (the step is still completed with the last iterate). */
 wl_status wl_step(wl_sim* sim, double dt, wl_step_stats* stats);
 
+/* Advance CFL-adaptive steps in one call, as the paper's time loop does
+ * (sim_step! to a target time, Sec. 2): at most nsteps steps, stopping once
+ * the time reaches t_end (t_end <= 0: no time limit).  stats (may be NULL)
+ * holds room for nsteps entries and receives one per step taken; *taken
+ * (may be NULL) the number of steps taken.  Stops at the first step whose
+ * status is not WL_OK and returns that status (a WL_ERR_NOT_CONVERGED step
+ * is completed and counted).  WL_ERR_INVALID_ARG for nsteps < 0. */
+wl_status wl_run(wl_sim* sim, int nsteps, double t_end, wl_step_stats* stats, int* taken);
+
 /* ---- Adjoint of the step (the solver is differentiable, Sec. 2) --------- */
 
 /* Pressure drag of the body from the current pressure (the corrector

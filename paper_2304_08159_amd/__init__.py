@@ -170,12 +170,25 @@ class Sim:
         check(self._lib.wl_step_adjoint(self._h, _ptr(ubar), float(drag_weight), _ptr(out), g))
         return out, [g[0], g[1], g[2], g[3]]
 
+    @staticmethod
+    def _stats(st):
+        return dict(dt=st.dt, t=st.t, vcycles=(st.vcycles[0], st.vcycles[1]),
+                    resid=(st.resid[0], st.resid[1]))
+
     def step(self, dt=0.0, allow_not_converged=False):
         st = _lib.StepStats()
         check(self._lib.wl_step(self._h, float(dt), ctypes.byref(st)),
               allow=(-3,) if allow_not_converged else ())
-        return dict(dt=st.dt, t=st.t, vcycles=(st.vcycles[0], st.vcycles[1]),
-                    resid=(st.resid[0], st.resid[1]))
+        return self._stats(st)
+
+    def run(self, nsteps, t_end=0.0, allow_not_converged=False):
+        """Up to nsteps CFL-adaptive steps in one library call, stopping once
+        the time reaches t_end (> 0); returns the per-step stats."""
+        sts = (_lib.StepStats * max(int(nsteps), 1))()
+        taken = ctypes.c_int(0)
+        check(self._lib.wl_run(self._h, int(nsteps), float(t_end), sts, ctypes.byref(taken)),
+              allow=(-3,) if allow_not_converged else ())
+        return [self._stats(sts[k]) for k in range(taken.value)]
 
 
 def poisson_batch_solve(requests, allow_not_converged=False):

@@ -27,7 +27,7 @@ FIELD_L0, FIELD_MU0_0, FIELD_MU1N, FIELD_SIGMA = 5, 8, 11, 20
 # Every symbol include/wl.h declares.
 EXPORTS = (
     "wl_sim_footprint", "wl_sim_create", "wl_sim_destroy", "wl_set_field", "wl_get_field",
-    "wl_set_time", "wl_step", "wl_drag", "wl_tape_record", "wl_step_adjoint",
+    "wl_set_time", "wl_step", "wl_run", "wl_drag", "wl_tape_record", "wl_step_adjoint",
     "wl_poisson_footprint", "wl_poisson_create",
     "wl_poisson_solve", "wl_poisson_destroy", "wl_poisson_batch_footprint",
     "wl_poisson_batch_solve", "wl_body_coeffs", "wl_set_graphs", "wl_set_fused_sweeps",
@@ -95,6 +95,7 @@ def load():
         "wl_get_field": [vp, i32, vp],
         "wl_set_time": [vp, f64],
         "wl_step": [vp, f64, ctypes.POINTER(StepStats)],
+        "wl_run": [vp, i32, f64, ctypes.POINTER(StepStats), ctypes.POINTER(i32)],
         "wl_drag": [vp, ctypes.POINTER(f64)],
         "wl_tape_record": [vp, i32],
         "wl_step_adjoint": [vp, vp, f64, vp, ctypes.POINTER(f64)],

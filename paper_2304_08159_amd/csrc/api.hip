@@ -988,6 +988,23 @@ wl_status wl_step(wl_sim* sim, double dt, wl_step_stats* stats) {
     return sim_step<float>(*static_cast<SimImpl<float>*>(sim->impl), dt, stats, sim->stream);
 }
 
+wl_status wl_run(wl_sim* sim, int nsteps, double t_end, wl_step_stats* stats, int* taken) {
+    clear_error();
+    if (taken) *taken = 0;
+    if (!sim) return invalid("sim is NULL");
+    if (nsteps < 0) return invalid("nsteps must be >= 0");
+    for (int k = 0; k < nsteps; ++k) {
+        wl_step_stats st{};
+        const wl_status rc = wl_step(sim, 0.0, &st);
+        if (rc != WL_OK && rc != WL_ERR_NOT_CONVERGED) return rc;
+        if (stats) stats[k] = st;
+        if (taken) *taken = k + 1;
+        if (rc != WL_OK) return rc;
+        if (t_end > 0.0 && st.t >= t_end) break;
+    }
+    return WL_OK;
+}
+
 wl_status wl_drag(wl_sim* sim, double* Fx) {
     clear_error();
     if (!sim || !Fx) return invalid("sim / Fx is NULL");

@@ -112,3 +112,14 @@ def test_fused_sweep_mode_is_validated_without_a_gpu():
     assert lib.wl_set_fused_sweeps(-1) == -1
     for mode in (0, 2, 1):
         assert lib.wl_set_fused_sweeps(mode) == 0
+
+
+def test_run_validates_arguments_without_a_gpu():
+    import ctypes as C
+    from paper_2304_08159_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libwl.so not built")
+    lib = _lib.load()
+    taken = C.c_int(7)
+    assert lib.wl_run(None, 3, 0.0, None, C.byref(taken)) == -1
+    assert taken.value == 0 and b"sim" in lib.wl_last_error()

@@ -193,3 +193,30 @@ def test_fused_predictor_projection_is_bitwise_identical():
     (sa, xa, pa), (sb, xb, pb) = runs
     assert sa == sb
     assert torch.equal(xa, xb) and torch.equal(pa, pb)
+
+
+def test_run_equals_repeated_steps_and_stops_at_t_end():
+    """wl_run (many steps in one call) gives bitwise the state of the same
+    number of wl_step calls, and stops once the time reaches t_end."""
+    import paper_2304_08159_amd as wl
+    N = 32
+    u, v, w, nu = W.tgv3d(N, Re=1600.0)
+    outs = []
+    for mode in ("step", "run"):
+        sim = wl.Sim((N, N, N), [0] * 3, [0] * 3, (0.0, 0.0, 0.0), nu, prec=wl.WL_FP32,
+                     tol=1e-6)
+        for i, a in enumerate((u, v, w)):
+            sim.set(wl.FIELD_U0 + i,
+                    torch.from_numpy(np.ascontiguousarray(a.transpose(2, 1, 0))).float().cuda())
+        stats = [sim.step() for _ in range(5)] if mode == "step" else sim.run(5)
+        outs.append((stats, sim.get_state().clone(), sim.pressure().clone()))
+        if mode == "run":
+            t_end = stats[-1]["t"] + 1.5 * stats[-1]["dt"]
+            more = sim.run(50, t_end=t_end)
+            assert 1 <= len(more) <= 3 and more[-1]["t"] >= t_end
+            assert all(m["t"] < t_end for m in more[:-1])
+            assert sim.run(0) == []
+        sim.close()
+    (sa, xa, pa), (sb, xb, pb) = outs
+    assert sa == sb
+    assert torch.equal(xa, xb) and torch.equal(pa, pb)
