@@ -332,6 +332,13 @@ static wl_status sim_init(SimImpl<T>& s, hipStream_t st) {
 // projected velocity, c dt (sigma - A p), has RMS over the active cells <= tol,
 // i.e. ||r||^2 <= (tol sqrt(n_active) / (c dt))^2.  `tail` (may be null) is
 // work that reads the final pressure, done before returning (see SolveTail).
+// The divergence kernel also takes the pressure solve's first residual
+// check (plain periodic FP32/FP64 solves on hierarchies that allow it).
+template <typename T>
+static bool producer_check(const SimImpl<T>& s) {
+    return s.cfg.d.prec != WL_MIXED && s.cfg.unif && s.cfg.d.ndim == 3 && mg_producer_check(s.h);
+}
+
 template <typename T>
 static wl_status pressure_solve(SimImpl<T>& s, double cfac, double dt, hipStream_t st,
                                 SolveResult* r, const SolveTail* tail = nullptr) {
@@ -353,7 +360,8 @@ static wl_status pressure_solve(SimImpl<T>& s, double cfac, double dt, hipStream
         }
         return invalid("mixed precision needs FP32 fields");
     }
-    return mg_solve<T>(s.h, s.red, s.p, s.sigma, 0.0, abs_r2, c.d.max_vcycles, st, r, true, tail);
+    return mg_solve<T>(s.h, s.red, s.p, s.sigma, 0.0, abs_r2, c.d.max_vcycles, st, r,
+                       producer_check(s) ? BPartials::Check : BPartials::Sums, tail);
 }
 
 template <typename T>
@@ -420,7 +428,8 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
             us = B;
         }
         const VelField<T> V = field_of(s, us, s.plane[P1]);
-        WL_TRY(ns_divergence<T>(V, pc, c.unif, 1.0, dt_dev, s.sigma, s.red.partial, ap, st));
+        WL_TRY(ns_divergence<T>(V, pc, c.unif, 1.0, dt_dev, s.sigma, s.red.partial, ap, st,
+                                producer_check(s) ? s.p : nullptr, s.h.lev[0].Lc));
         wl_status rc = pressure_solve(s, 1.0, dt, st, &r1);
         if (rc == WL_ERR_NOT_CONVERGED) worst = rc;
         else if (rc != WL_OK) return rc;
@@ -466,7 +475,8 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
             us2 = S;
         }
         const VelField<T> V2 = field_of(s, us2, s.plane[P2]);
-        WL_TRY(ns_divergence<T>(V2, pc, c.unif, 0.5, dt_dev, s.sigma, s.red.partial, ap, st));
+        WL_TRY(ns_divergence<T>(V2, pc, c.unif, 0.5, dt_dev, s.sigma, s.red.partial, ap, st,
+                                producer_check(s) ? s.p : nullptr, s.h.lev[0].Lc));
         // projection, CFL maximum and next dt read only the final pressure
         // and write buffers nothing else reads: the solve may run them
         // speculatively before its first convergence check returns
@@ -524,7 +534,7 @@ static wl_status adj_solve(SimImpl<T>& s, hipStream_t st) {
     }
     WL_TRY(fill<T>(A.sbar, c.N, T(0), st));
     rc = mg_solve<T>(s.h, s.red, A.sbar, A.rhs, sizeof(T) == 8 ? 1e-11 : 1e-6, 0.0,
-                     sizeof(T) == 8 ? 400 : 60, st, &r, false);
+                     sizeof(T) == 8 ? 400 : 60, st, &r, BPartials::None);
     if (rc != WL_OK && rc != WL_ERR_NOT_CONVERGED) return rc;
     return WL_OK;
 }

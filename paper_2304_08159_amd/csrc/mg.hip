@@ -1159,6 +1159,52 @@ static wl_status vcycle_rest(Hierarchy<T>& h, Pre mode, const T* fb, const doubl
     return post_smooth(h, F, pre[0], F.x[0], F.x[1], h.lev[1], fb, fshift, s, true);
 }
 
+// Sums [b, b^2, c, c^2] of a producer-side first check (see BPartials) ->
+// result[4] = sum b, result[5] = mean m over the active count *count,
+// result[1] = ||b - m||^2 and result[0] = an upper bound of ||c - m||^2:
+// sum c^2 - 2 m sum c + n m^2 plus a bound of the FP64 rounding of those
+// sums (negligible when m is small, as on periodic grids); posts result[0..1].
+__global__ __launch_bounds__(1024) void k_check_reduce(const double* __restrict__ partial,
+                                                       size_t nslots,
+                                                       const double* __restrict__ count,
+                                                       double* __restrict__ out,
+                                                       MailboxPost post) {
+    __shared__ double lds[1024];
+    double S[4];
+    for (int c = 0; c < 4; ++c) {
+        double v = 0.0;
+        for (size_t q = threadIdx.x; q < nslots; q += blockDim.x) v += partial[4 * q + c];
+        lds[threadIdx.x] = v;
+        __syncthreads();
+        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) lds[threadIdx.x] += lds[threadIdx.x + w];
+            __syncthreads();
+        }
+        S[c] = lds[0];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double n = *count;
+        const double m = n > 0.0 ? S[0] / n : 0.0;
+        const double nm2 = n * m * m;
+        const double r2 = S[3] - 2.0 * m * S[2] + nm2;
+        // relative rounding of sums of up to 2^31 terms, taken generously
+        const double err = 1e-6 * (S[3] + 2.0 * fabs(m * S[2]) + nm2);
+        out[0] = fmax(r2, 0.0) + err;
+        out[1] = fmax(S[1] - m * S[0], 0.0);
+        out[4] = S[0];
+        out[5] = m;
+        if (post.vals) mailbox_write(post, out);
+    }
+}
+
+template <typename T>
+bool mg_producer_check(const Hierarchy<T>& h) {
+    return h.nlev > 1 && pair_ok(h, h.lev[0]);
+}
+template bool mg_producer_check<float>(const Hierarchy<float>&);
+template bool mg_producer_check<double>(const Hierarchy<double>&);
+
 template <typename T>
 static wl_status active_mean(Hierarchy<T>& h, Reduce& red, const T* b, bool have_partials,
                              hipStream_t s) {
@@ -1180,28 +1226,39 @@ static wl_status active_mean(Hierarchy<T>& h, Reduce& red, const T* b, bool have
 
 template <typename T>
 wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, double abs_r2,
-                   int max_vcycles, hipStream_t s, SolveResult* res, bool b_partials,
+                   int max_vcycles, hipStream_t s, SolveResult* res, BPartials bp,
                    const SolveTail* tail) {
     Level<T>& F = h.lev[0];
     F.x[0] = x;
     const T w = T(h.omega);
     const Launch ln = launch_for(F.g.n0, F.g.n1, F.g.n2);
-    WL_TRY(active_mean(h, red, b, b_partials, s));
     // With fused fine pairs each V-cycle starts with both pre-sweeps from x
     // and the residual checks only measure; otherwise every check is also
     // the first pre-sweep of the next V-cycle (into F.x[1]).
     const bool fused = h.nlev > 1 && pair_ok(h, F);
     T* const xnext = fused ? nullptr : F.x[1];
-    // first check: ||r0|| and ||b - mean||.  Every fine-level sweep removes
-    // the mean of b on the fly; only a one-level hierarchy (whose coarse
-    // solve reads F.b) stores the projected copy.
-    const double* bshift = red.result + 5;
-    WL_TRY((smooth<T, XM_PLAIN, true, true>(F, x, nullptr, nullptr, b, w, xnext, red.partial,
-                                            bshift, s, -1, h.nlev == 1 ? F.b : nullptr)));
-    // the norm reductions post ||r||^2, ||b||^2 to mailbox slots 0, 1
+    if (bp == BPartials::Check && !mg_producer_check(h)) {
+        set_error("internal: first residual check given for a hierarchy that cannot take it");
+        return WL_ERR_INVALID_ARG;
+    }
+    // the norm reductions post ||r||^2, ||b - mean||^2 to mailbox slots 0, 1
     MailboxPost post;
     WL_TRY(mailbox_post_args(red, 0, 2, s, &post));
-    WL_TRY(reduce<T>(red, ln.nblocks(), 2, 1.0, red.result, s, post));
+    const double* bshift = red.result + 5;
+    if (bp == BPartials::Check) {
+        // the producer of b evaluated the first check
+        k_check_reduce<<<1, 1024, 0, s>>>(red.partial, ln.nblocks(), red.result + 6, red.result,
+                                          post);
+        WL_CHECK_LAUNCH();
+    } else {
+        WL_TRY(active_mean(h, red, b, bp == BPartials::Sums, s));
+        // first check: ||r0|| and ||b - mean||.  Every fine-level sweep
+        // removes the mean of b on the fly; only a one-level hierarchy (whose
+        // coarse solve reads F.b) stores the projected copy.
+        WL_TRY((smooth<T, XM_PLAIN, true, true>(F, x, nullptr, nullptr, b, w, xnext, red.partial,
+                                                bshift, s, -1, h.nlev == 1 ? F.b : nullptr)));
+        WL_TRY(reduce<T>(red, ln.nblocks(), 2, 1.0, red.result, s, post));
+    }
     host_posted(red);
     // speculate that the initial iterate already converges: the tail runs on
     // it while the host waits for the norms
@@ -1266,9 +1323,11 @@ wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, d
 }
 
 template wl_status mg_solve<float>(Hierarchy<float>&, Reduce&, float*, const float*, double,
-                                   double, int, hipStream_t, SolveResult*, bool, const SolveTail*);
+                                   double, int, hipStream_t, SolveResult*, BPartials,
+                                   const SolveTail*);
 template wl_status mg_solve<double>(Hierarchy<double>&, Reduce&, double*, const double*, double,
-                                    double, int, hipStream_t, SolveResult*, bool, const SolveTail*);
+                                    double, int, hipStream_t, SolveResult*, BPartials,
+                                    const SolveTail*);
 
 wl_status mg_solve_mixed(Hierarchy<float>& h32, const Mixed64& m, Reduce& red, double* x,
                          const double* b, double tol, double abs_r2, int max_vcycles,

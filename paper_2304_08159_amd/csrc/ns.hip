@@ -15,6 +15,7 @@
 #include <cstdlib>
 
 #include "wl_device.h"
+#include "wl_jacobi.h"
 #include "wl_ns.h"
 #include "wl_vel.h"
 
@@ -543,18 +544,23 @@ __global__ __launch_bounds__(kBlock) void k_tile_class(TileDev TL, Grid g, BdimF
 
 // sigma = div(u*) / (c dt), plus per-block partial sums of sigma over the
 // active cells (D != 0; every cell when the coefficients are uniform) for the
-// mean removal of the pressure solve.
-template <typename T, bool ALLPER, bool UNIF>
+// mean removal of the pressure solve.  CHK (periodic, uniform coefficient Lp,
+// 3D) also evaluates the pressure solve's first residual check here: with the
+// solve's initial iterate p and c = sigma - A p, the per-block sums
+// [sigma, sigma^2, c, c^2] (partial[4 * block + q]), from which the mean m and
+// ||r||^2 = sum (c - m)^2, ||b - m||^2 follow without another pass.
+template <typename T, bool ALLPER, bool UNIF, bool CHK>
 __global__ __launch_bounds__(kBlock) void k_divergence(TileDev TL, VelField<T> V, ProjCoeffs<T> C,
                                                        double c, const double* __restrict__ dt_dev,
                                                        T* __restrict__ sigma,
-                                                       double* __restrict__ partial) {
-    __shared__ double lds[8];
+                                                       double* __restrict__ partial,
+                                                       const T* __restrict__ p, T Lp) {
+    __shared__ double lds[16];
     const Grid& g = V.g;
     const Span sp = tile_span(TL, g.n0, g.n1, g.n2);
     const int i = sp.i, j = sp.j;
     const T scale = T(1.0 / (c * *dt_dev));
-    double sum = 0.0;
+    double sum = 0.0, sb2 = 0.0, sc = 0.0, sc2 = 0.0;
     if (i < g.n0 && j < g.n1 && sp.z0 < sp.z1) {
         const unsigned n0 = unsigned(g.n0), plane = n0 * unsigned(g.n1);
         const bool d3 = g.ndim == 3;
@@ -569,6 +575,14 @@ __global__ __launch_bounds__(kBlock) void k_divergence(TileDev TL, VelField<T> V
         const T* __restrict__ uz = V.u[2];
         unsigned id = unsigned(i) + n0 * unsigned(j) + plane * unsigned(sp.z0);
         T wlo = d3 ? uz[id] : T(0);  // lower z face, carried up the column
+        // CHK: periodic x / y neighbour offsets of p; p at k - 1 and k carried
+        const int dxm = i > 0 ? -1 : g.n0 - 1;
+        const int dym = j > 0 ? -int(n0) : int(n0) * (g.n1 - 1);
+        T pzl = T(0), pI = T(0);
+        if (CHK) {
+            pI = p[id];
+            pzl = p[sp.z0 > 0 ? id - plane : id + plane * unsigned(g.n2 - 1)];
+        }
         for (int k = sp.z0; k < sp.z1; ++k, id += plane) {
             const T xu = xin ? ux[id + dxp] : vget<T, ALLPER>(V, 0, i + 1, j, k);
             const T yu = yin ? uy[id + dyp] : vget<T, ALLPER>(V, 1, i, j + 1, k);
@@ -583,6 +597,18 @@ __global__ __launch_bounds__(kBlock) void k_divergence(TileDev TL, VelField<T> V
             }
             const T sg = div * scale;
             sigma[id] = sg;
+            if (CHK) {
+                const T pzu = p[k + 1 < g.n2 ? id + plane : id - plane * unsigned(g.n2 - 1)];
+                T Ax, D;
+                jacobi_terms(pI, p[id + dxm], p[id + dxp], p[id + dym], p[id + dyp], pzl, pzu, Lp, Lp,
+                             Lp, Lp, Lp, Lp, true, Ax, D);
+                const double cr = double(sg - Ax);
+                sb2 += double(sg) * double(sg);
+                sc += cr;
+                sc2 += cr * cr;
+                pzl = pI;
+                pI = pzu;
+            }
             bool active = true;
             if (!UNIF) {
                 T D = T(0);
@@ -601,6 +627,19 @@ __global__ __launch_bounds__(kBlock) void k_divergence(TileDev TL, VelField<T> V
             }
             if (active) sum += double(sg);
         }
+    }
+    if (CHK) {
+        double t0, t1, t2, t3;
+        block_sum2(sum, sb2, lds, t0, t1);
+        block_sum2(sc, sc2, lds + 8, t2, t3);
+        if (threadIdx.x == 0) {
+            double* q = partial + 4 * size_t(block_linear());
+            q[0] = t0;
+            q[1] = t1;
+            q[2] = t2;
+            q[3] = t3;
+        }
+        return;
     }
     const double bs = block_sum(sum, lds);
     if (threadIdx.x == 0) partial[block_linear()] = bs;
@@ -961,11 +1000,22 @@ wl_status ns_tile_class(const Grid& g, const BdimFields<T>& B, unsigned char* cl
 template <typename T>
 wl_status ns_divergence(const VelField<T>& V, const ProjCoeffs<T>& C, bool unif, double c,
                         const double* dt_dev, T* sigma, double* partial, bool allper,
-                        hipStream_t s) {
+                        hipStream_t s, const T* p_check, T Lp) {
     const Launch ln = launch_for(V.g.n0, V.g.n1, V.g.n2);
     ProfScope ps(WL_PROF_DIVERGENCE, s, cells(V.g));
-#define WL_DIV(AP, UN) \
-    k_divergence<T, AP, UN><<<ln.grid, ln.block, 0, s>>>(ln.td, V, C, c, dt_dev, sigma, partial)
+    if (p_check) {
+        if (!allper || !unif || V.g.ndim != 3) {
+            set_error("internal: the fused first residual check needs a periodic uniform 3D grid");
+            return WL_ERR_INVALID_ARG;
+        }
+        k_divergence<T, true, true, true><<<ln.grid, ln.block, 0, s>>>(ln.td, V, C, c, dt_dev,
+                                                                       sigma, partial, p_check, Lp);
+        WL_CHECK_LAUNCH();
+        return WL_OK;
+    }
+#define WL_DIV(AP, UN)                                                                          \
+    k_divergence<T, AP, UN, false><<<ln.grid, ln.block, 0, s>>>(ln.td, V, C, c, dt_dev, sigma, \
+                                                                partial, nullptr, T(0))
     if (allper) {
         if (unif) WL_DIV(true, true); else WL_DIV(true, false);
     } else {
@@ -1039,7 +1089,8 @@ wl_status ns_set_scalar(double* p, double v, hipStream_t s) {
     template wl_status ns_bdim<T>(const VelField<T>&, const BdimFields<T>&, T* const*,            \
                                   hipStream_t);                                                   \
     template wl_status ns_divergence<T>(const VelField<T>&, const ProjCoeffs<T>&, bool, double,  \
-                                        const double*, T*, double*, bool, hipStream_t);           \
+                                        const double*, T*, double*, bool, hipStream_t, const T*,  \
+                                        T);                                                       \
     template wl_status ns_project<T>(const VelField<T>&, const T*, const ProjCoeffs<T>&, bool,    \
                                      double, const double*, T* const*, bool, double*, bool,        \
                                      hipStream_t);                                                \

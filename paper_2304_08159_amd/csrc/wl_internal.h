@@ -217,7 +217,7 @@ struct HostMailbox {
 constexpr int kResultDoubles = 16;
 constexpr int kResultCounter = 15;  // device count of mailbox posts
 struct Reduce {
-    double* partial = nullptr;   // capacity slots * 2
+    double* partial = nullptr;   // capacity slots * 2 (a simulation's: slots * 4)
     size_t slots = 0;
     double* result = nullptr;    // kResultDoubles doubles
     HostMailbox mb;
@@ -272,14 +272,24 @@ struct SolveResult {
 // run on the final solution and every mailbox post it made has arrived.
 using SolveTail = std::function<wl_status(hipStream_t)>;
 
+// What the producer of the right-hand side left in red.partial (per block of
+// the fine level's launch_for tiling): nothing, the sums of b over the active
+// cells, or (mg_producer_check) the four sums of the first residual check:
+// [b, b^2, c, c^2] with c = b - A x for the solve's initial x.
+enum class BPartials { None, Sums, Check };
+
+// Whether the producer of b may take the first residual check
+// (BPartials::Check): uniform periodic 3D fine level whose V-cycles start from
+// the iterate (fused sweep pairs), so that the check needs no output.
+template <typename T>
+bool mg_producer_check(const Hierarchy<T>& h);
+
 // Plain GMG solve on h (level 0 x = caller x).  b is the raw right-hand side.
 // Converged before a V-cycle when ||r||^2 <= tol^2 ||b||^2 or ||r||^2 <= abs_r2.
-// b_partials: red.partial already holds the per-block sums of b over the
-// active cells for the fine-level tiling (written by the producer of b).
 template <typename T>
 wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, double abs_r2,
-                   int max_vcycles, hipStream_t s, SolveResult* res, bool b_partials = false,
-                   const SolveTail* tail = nullptr);
+                   int max_vcycles, hipStream_t s, SolveResult* res,
+                   BPartials bp = BPartials::None, const SolveTail* tail = nullptr);
 
 // Mixed precision: FP64 outer residual with FP64 fine coefficients L64,
 // FP32 inner V-cycles on h32.

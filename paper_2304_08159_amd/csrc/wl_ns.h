@@ -79,10 +79,13 @@ wl_status ns_bdim(const VelField<T>& F, const BdimFields<T>& B, T* const out[3],
 // Tile classes (see BdimFields::cls) from the measured mu0 / mu1 n.
 template <typename T>
 wl_status ns_tile_class(const Grid& g, const BdimFields<T>& B, unsigned char* cls, hipStream_t s);
+// p_check (periodic, uniform, 3D): also the first residual check of the
+// pressure solve that starts from p, with Poisson coefficient Lp (partials of
+// [sigma, sigma^2, c, c^2], c = sigma - A p; see k_divergence).
 template <typename T>
 wl_status ns_divergence(const VelField<T>& V, const ProjCoeffs<T>& C, bool unif, double c,
                         const double* dt_dev, T* sigma, double* partial, bool allper,
-                        hipStream_t s);
+                        hipStream_t s, const T* p_check = nullptr, T Lp = T(0));
 template <typename T>
 wl_status ns_project(const VelField<T>& V, const T* p, const ProjCoeffs<T>& C, bool unif, double c,
                      const double* dt_dev, T* const out[3], bool cfl, double* partial, bool allper,

@@ -1,7 +1,10 @@
 """Fused pre/post-smoothing sweep pairs on uniform periodic 3D levels give the
 iterates of separate sweeps bit for bit: whole Navier-Stokes steps with every
 eligible level fused against none fused, in FP32, FP64 and mixed precision,
-on grids whose fused levels have full and ragged z chunks."""
+on grids whose fused levels have full and ragged z chunks.  With fused pairs
+the divergence kernel also takes each solve's first residual check (FP32 and
+FP64): the V-cycle counts and every field must still agree exactly, the
+reported residuals to rounding."""
 
 import numpy as np
 import pytest
@@ -45,5 +48,8 @@ def test_fused_sweep_pairs_are_bitwise_identical(precname, n, tol):
     sb, (ub, pb) = _run(wl, 0, precname, n, tol)
     print(precname, n, [s["vcycles"] for s in sa])
     assert sum(s["vcycles"][0] + s["vcycles"][1] for s in sa) >= 4
-    assert sa == sb
+    for x, y in zip(sa, sb):
+        assert (x["dt"], x["t"], x["vcycles"]) == (y["dt"], y["t"], y["vcycles"])
+        for q in range(2):
+            assert abs(x["resid"][q] - y["resid"][q]) <= 1e-6 * y["resid"][q] + 1e-300
     assert torch.equal(ua, ub) and torch.equal(pa, pb)
