@@ -281,14 +281,16 @@ wl_status wl_body_coeffs(const wl_body* body, int ndim, const int n[3], const in
 wl_status wl_set_graphs(int enable);
 
 /* Each pre- and post-smoothing pair of damped-Jacobi sweeps (Sec. 2's GMG
- * smoother) on a uniform, fully periodic 3D level whose x / y extents are
- * multiples of 64 / 8 runs as one kernel that keeps the intermediate iterate
- * on chip; the V-cycle then also checks the residual with a measuring pass
- * that writes nothing.  Iterates, norms and results are bitwise the same as
- * with separate sweeps.  mode 0: separate sweeps everywhere; 1 (default):
- * fused on such levels of at least 2^21 cells; 2: fused on every such level.
- * Process-wide; a solver or simulation takes the mode in force when it is
- * created.  WL_ERR_INVALID_ARG for another mode. */
+ * smoother) on a uniform, fully periodic 3D level whose x and y extents are
+ * multiples of 8 runs as one kernel that keeps the intermediate iterate on
+ * chip; the V-cycle then also checks the residual with a measuring pass that
+ * writes nothing, and a simulation's divergence kernel takes each solve's
+ * first check.  Iterates are bitwise the same as with separate sweeps (the
+ * reported residual norms agree to rounding).  mode 0: separate sweeps
+ * everywhere; 1 (default) and 2: fused on every such level (1 honours a
+ * minimum level size set for tuning).  Process-wide; a solver or simulation
+ * takes the mode in force when it is created.  WL_ERR_INVALID_ARG for
+ * another mode. */
 wl_status wl_set_fused_sweeps(int mode);
 
 /* ---- Kernel timing (measurement support) -------------------------------- */

@@ -242,9 +242,9 @@ def set_graphs(enable=True):
 
 def set_fused_sweeps(mode=1):
     """Fused pre/post-smoothing sweep pairs on uniform periodic 3D levels:
-    0 off, 1 on levels of at least 2^21 cells (default), 2 on every eligible
-    level.  Taken by solvers and simulations created afterwards; results are
-    bitwise the same in every mode."""
+    0 off, 1 (default) or 2 on every eligible level.  Taken by solvers and
+    simulations created afterwards; iterates are bitwise the same in every
+    mode."""
     check(load().wl_set_fused_sweeps(int(mode)))
 
 

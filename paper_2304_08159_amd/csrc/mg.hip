@@ -92,13 +92,13 @@ int auto_levels(int ndim, const int n[3], int requested) {
 // taken by each hierarchy when it is laid out.
 static std::atomic<int> g_pairs{1};
 
-// Levels smaller than this use separate sweeps in mode 1 (WL_PAIR_MIN_CELLS
-// overrides it for tuning).
+// Levels smaller than this use separate sweeps in mode 1 (default 0: every
+// eligible level is fused; WL_PAIR_MIN_CELLS overrides it for tuning).
 static size_t pair_min_cells() {
     static const size_t v = [] {
         const char* e = std::getenv("WL_PAIR_MIN_CELLS");
         const long t = e ? std::atol(e) : -1;
-        return t >= 0 ? size_t(t) : size_t(1) << 21;
+        return t >= 0 ? size_t(t) : size_t(0);
     }();
     return v;
 }
@@ -259,11 +259,18 @@ __global__ __launch_bounds__(kBlock) void k_smooth(TileDev TL, Grid g, XAccess<T
 // neighbouring workgroups with the same operations, so the result is bitwise
 // that of two separate sweeps while the intermediate iterate never reaches
 // memory (FP32: 12 instead of 24 bytes per cell for the pair).
-constexpr int kPairTX = 64, kPairTY = 8, kPairThreads = kPairTX * kPairTY;
-constexpr int kPairHX = kPairTX + 2, kPairHY = kPairTY + 2;       // first-sweep region
-constexpr int kPairGX = kPairTX + 4, kPairGY = kPairTY + 4;       // input region
-constexpr int kPairRing1 = kPairHX * kPairHY - kPairThreads;      // 148 cells
-constexpr int kPairRing2 = kPairGX * kPairGY - kPairHX * kPairHY; // 156 cells
+// Tiles are TX x 8 cells (TX = 64, 32, 16 or 8, the widest dividing the
+// level's x extent), one thread per cell.
+constexpr int kPairTY = 8;
+template <int TX>
+struct PairShape {
+    static constexpr int T = TX * kPairTY;                  // threads
+    static constexpr int HX = TX + 2, HY = kPairTY + 2;     // first-sweep region
+    static constexpr int GX = TX + 4, GY = kPairTY + 4;     // input region
+    static constexpr int R1 = HX * HY - T;                  // first-sweep ring cells
+    static constexpr int R2 = GX * GY - HX * HY;            // input ring cells
+    static_assert(R1 <= T && R2 <= T, "one ring cell per thread at most");
+};
 constexpr int kPairDepth = 1;  // planes of loads in flight per thread
 
 struct PairTile {
@@ -292,13 +299,16 @@ __device__ __forceinline__ void ring_cell(int r, int w, int h, int& x, int& y) {
     }
 }
 
-template <typename T, int XM>
-__global__ __launch_bounds__(kPairThreads) void k_smooth_pair(PairTile P, Grid g, XAccess<T, XM> X,
+template <typename T, int XM, int TX>
+__global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Grid g, XAccess<T, XM> X,
                                                               T Lc, const T* __restrict__ b,
                                                               T wD, T* __restrict__ xout,
                                                               const double* __restrict__ bshift) {
-    __shared__ T s0[2][kPairGY * kPairGX];  // input plane, tile widened by two
-    __shared__ T s1[2][kPairHY * kPairHX];  // first-sweep plane, tile widened by one
+    using Sh = PairShape<TX>;
+    constexpr int kPairTX = TX, kPairThreads = Sh::T, kPairHX = Sh::HX, kPairHY = Sh::HY;
+    constexpr int kPairGX = Sh::GX, kPairRing1 = Sh::R1, kPairRing2 = Sh::R2;
+    __shared__ T s0[2][Sh::GY * Sh::GX];  // input plane, tile widened by two
+    __shared__ T s1[2][Sh::HY * Sh::HX];  // first-sweep plane, tile widened by one
     unsigned blk = blockIdx.x;
     if (P.remap) blk = (blk & 7u) * (P.nb >> 3) + (blk >> 3);
     const int tix = int(blk % unsigned(P.tx));
@@ -941,24 +951,32 @@ static wl_status smooth(const Level<T>& L, const T* xin, const T* xc, const Grid
     return WL_OK;
 }
 
-// Fused pairs run on uniform, fully periodic 3D levels whose x / y extents
-// are multiples of the 64 x 8 tile (mode 1: only levels of at least
-// pair_min_cells() cells).
+// Fused pairs run on uniform, fully periodic 3D levels whose x extent is a
+// multiple of 8 and y extent a multiple of 8 (mode 1: only levels of at
+// least pair_min_cells() cells).
+static int pair_tx(int n0) {
+    for (int w = 64; w >= 8; w >>= 1)
+        if (n0 % w == 0) return w;
+    return 0;
+}
+
 template <typename T>
 static bool pair_ok(const Hierarchy<T>& h, const Level<T>& L) {
     if (!h.pairs || !L.uniform || L.g.ndim != 3) return false;
-    if (L.g.n0 % kPairTX != 0 || L.g.n1 % kPairTY != 0) return false;
+    if (pair_tx(L.g.n0) == 0 || L.g.n1 % kPairTY != 0) return false;
     return h.pairs == 2 || cells(L.g) >= pair_min_cells();
 }
 
 static PairTile pair_tile(const Grid& g) {
     PairTile p;
-    p.tx = g.n0 / kPairTX;
+    p.tx = g.n0 / pair_tx(g.n0);
     p.ty = g.n1 / kPairTY;
     const size_t cols = size_t(p.tx) * size_t(p.ty);
     size_t zc = (cols * size_t(g.n2) + pair_blocks() - 1) / pair_blocks();
-    // the chunk re-reads two input planes on either side: keep it >= 8
-    zc = std::min(std::max(zc, size_t(8)), size_t(g.n2));
+    // a chunk re-reads two input planes on either side: keep it >= 8 on
+    // large levels; small ones favour more, shorter workgroups
+    const size_t zmin = cells(g) >= (size_t(1) << 20) ? 8 : 2;
+    zc = std::min(std::max(zc, zmin), size_t(g.n2));
     const unsigned chunks = unsigned((size_t(g.n2) + zc - 1) / zc);
     p.zc = int(zc);
     p.nb = unsigned(cols) * chunks;
@@ -978,8 +996,19 @@ static wl_status pair(const Level<T>& L, const T* xin, const T* xc, const Grid* 
     const PairTile P = pair_tile(L.g);
     ProfScope ps(prof, s, cells(L.g));
     XAccess<T, XM> X{xin, xc, gc ? gc->n0 : 0, gc ? gc->n1 : 0};
-    k_smooth_pair<T, XM><<<P.nb, kPairThreads, 0, s>>>(P, L.g, X, L.Lc, b, uniform_wd(L, omega),
-                                                       xout, bshift);
+    const T wd = uniform_wd(L, omega);
+#define WL_PAIR(TX)                                                                              \
+    k_smooth_pair<T, XM, TX><<<P.nb, PairShape<TX>::T, 0, s>>>(P, L.g, X, L.Lc, b, wd, xout, bshift)
+    switch (pair_tx(L.g.n0)) {
+        case 64: WL_PAIR(64); break;
+        case 32: WL_PAIR(32); break;
+        case 16: WL_PAIR(16); break;
+        case 8: WL_PAIR(8); break;
+        default:
+            set_error("internal: no fused-pair tile for this level");
+            return WL_ERR_INVALID_ARG;
+    }
+#undef WL_PAIR
     WL_CHECK_LAUNCH();
     return WL_OK;
 }
