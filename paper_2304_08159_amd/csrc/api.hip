@@ -155,7 +155,6 @@ struct SimImpl {
     double* p64 = nullptr;
     double* sigma64 = nullptr;
     double t = 0.0;
-    double dt_next_host = 0.0;
     bool cfl_valid = false;
     AdjointWS<T>* adj = nullptr;  // host bookkeeping of the adjoint workspace
     ~SimImpl() {
@@ -352,10 +351,7 @@ static wl_status pressure_solve(SimImpl<T>& s, double cfac, double dt, hipStream
                                           c.d.max_vcycles, st, r);
             if (rc != WL_OK && rc != WL_ERR_NOT_CONVERGED) return rc;
             WL_TRY((convert<double, float>(s.p64, s.p, c.N, st)));
-            if (tail) {
-                WL_TRY((*tail)(st));
-                WL_TRY(host_wait(s.red, st));
-            }
+            if (tail) WL_TRY((*tail)(st));
             return rc;
         }
         return invalid("mixed precision needs FP32 fields");
@@ -370,26 +366,41 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
     const bool ap = c.allper;
     double* dt_dev = s.scal + s.dt_cur;
     double dt = 0.0;
+    bool dt_pending = false;
     if (dt_in > 0.0) {
         WL_TRY(ns_set_scalar(dt_dev, dt_in, st));
         dt = dt_in;
     } else if (s.cfl_valid) {
-        dt = s.dt_next_host;  // computed on the device by the last projection
+        // the last projection formed dt on the device (dt_dev) and posted it
+        // to mailbox slot 8; the host needs it only for the first
+        // convergence test, so the step's first kernels are enqueued before
+        // it is read
+        dt_pending = true;
     } else {
         WL_TRY(ns_cfl<T>(field_of(s, s.S, s.plane[s.PS]), ap, s.red.partial, st));
         WL_TRY(ns_dt_from_max(s.red.partial, s.red.slots, c.d.cfl, 2.0 * c.d.ndim * c.d.nu, dt_dev,
                               s.scal + 2, st));
         WL_TRY(host_read(s.red, dt_dev, 1, &dt, st));
     }
-    if (!(dt > 0.0) || !std::isfinite(dt)) {
-        set_error("time step is not positive (zero velocity and zero viscosity?)");
-        return WL_ERR_INVALID_ARG;
-    }
+    auto resolve_dt = [&]() -> wl_status {
+        if (dt_pending) {
+            // the latest post: no solve has posted since that projection
+            WL_TRY(host_wait(s.red, st));
+            dt = host_slot(s.red, 8);
+            dt_pending = false;
+        }
+        if (!(dt > 0.0) || !std::isfinite(dt)) {
+            set_error("time step is not positive (zero velocity and zero viscosity?)");
+            return WL_ERR_INVALID_ARG;
+        }
+        return WL_OK;
+    };
     const int S = s.S;
     const int A = (S + 1) % 3, B = (S + 2) % 3;
     const int PS = s.PS, P1 = (PS + 1) % 3, P2 = (PS + 2) % 3;
     TapeSlot<T>* tp = nullptr;
     if (s.adj && s.adj->recording && s.adj->count < s.adj->cap) {
+        WL_TRY(resolve_dt());
         tp = &s.adj->tape[s.adj->count];
         tp->dt = dt;
     }
@@ -430,6 +441,7 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
         const VelField<T> V = field_of(s, us, s.plane[P1]);
         WL_TRY(ns_divergence<T>(V, pc, c.unif, 1.0, dt_dev, s.sigma, s.red.partial, ap, st,
                                 producer_check(s) ? s.p : nullptr, s.h.lev[0].Lc));
+        WL_TRY(resolve_dt());
         wl_status rc = pressure_solve(s, 1.0, dt, st, &r1);
         if (rc == WL_ERR_NOT_CONVERGED) worst = rc;
         else if (rc != WL_OK) return rc;
@@ -496,7 +508,6 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
         s.S = dest;
         s.PS = P2;
     }
-    s.dt_next_host = host_slot(s.red, 8);
     s.dt_cur = 1 - s.dt_cur;
     s.cfl_valid = true;
     s.t += dt;

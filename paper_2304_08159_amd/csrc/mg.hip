@@ -692,19 +692,22 @@ wl_status host_post(Reduce& red, const double* src, int n, int slot, hipStream_t
     return WL_OK;
 }
 
-wl_status host_wait(Reduce& red, hipStream_t s) {
+wl_status host_wait(Reduce& red, hipStream_t s) { return host_wait_seq(red, red.mb.seq, s); }
+
+wl_status host_wait_seq(Reduce& red, unsigned q, hipStream_t s) {
     HostMailbox& mb = red.mb;
     if (!mb.vals) return WL_OK;
-    const unsigned q = mb.seq;
+    // arrived: the published count has reached q (wrap-safe)
+    auto arrived = [&] { return int(__atomic_load_n(mb.seqw, __ATOMIC_ACQUIRE) - q) >= 0; };
     // Poll for up to 20 ms (a step's solves publish every few hundred
     // microseconds), then let HIP wait and report any kernel failure.
     const auto t0 = std::chrono::steady_clock::now();
     unsigned spins = 0;
-    while (__atomic_load_n(mb.seqw, __ATOMIC_ACQUIRE) != q) {
+    while (!arrived()) {
         if ((++spins & 1023u) == 0u &&
             std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(20)) {
             WL_CHECK_HIP(hipStreamSynchronize(s));
-            if (__atomic_load_n(mb.seqw, __ATOMIC_ACQUIRE) != q) {
+            if (!arrived()) {
                 set_error("device result did not arrive in the host mailbox");
                 return WL_ERR_HIP;
             }
@@ -1289,10 +1292,12 @@ wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, d
         WL_TRY(reduce<T>(red, ln.nblocks(), 2, 1.0, red.result, s, post));
     }
     host_posted(red);
+    const unsigned q_check = red.mb.seq;
     // speculate that the initial iterate already converges: the tail runs on
-    // it while the host waits for the norms
+    // it while the host waits for the norms (not for the tail's own posts,
+    // which the caller reads later)
     if (tail) WL_TRY((*tail)(s));
-    WL_TRY(host_wait(red, s));
+    WL_TRY(host_wait_seq(red, q_check, s));
     double nr[2] = {host_slot(red, 0), host_slot(red, 1)};
     if (!std::isfinite(nr[0]) || !std::isfinite(nr[1])) {
         set_error("non-finite residual norm in the pressure solve");
@@ -1306,10 +1311,7 @@ wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, d
         WL_CHECK_LAUNCH();
         res->vcycles = 0;
         res->rel = 0.0;
-        if (tail) {
-            WL_TRY((*tail)(s));
-            WL_TRY(host_wait(red, s));
-        }
+        if (tail) WL_TRY((*tail)(s));
         return WL_OK;
     }
     double r2 = nr[0];
@@ -1339,11 +1341,8 @@ wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, d
     res->vcycles = k;
     res->rel = std::sqrt(r2 / b2);
     res->r2 = r2;
-    if (tail && k > 0) {
-        // the speculative tail saw the initial iterate: run it again
-        WL_TRY((*tail)(s));
-        WL_TRY(host_wait(red, s));
-    }
+    // the speculative tail saw the initial iterate: run it again
+    if (tail && k > 0) WL_TRY((*tail)(s));
     if (!done(r2)) {
         set_error("pressure solve reached max_vcycles before the tolerance");
         return WL_ERR_NOT_CONVERGED;

@@ -244,6 +244,9 @@ void host_posted(Reduce& red);
 // stream order): polls the mailbox for a bounded time, then falls back to
 // hipStreamSynchronize (which also reports a failed kernel).
 wl_status host_wait(Reduce& red, hipStream_t s);
+// The same for the post that made the host's count q (later posts may be
+// outstanding still).
+wl_status host_wait_seq(Reduce& red, unsigned q, hipStream_t s);
 inline double host_slot(const Reduce& red, int slot) { return red.mb.vals[slot]; }
 // host_post into slot 0, host_wait, and copy the values out.
 wl_status host_read(Reduce& red, const double* src, int n, double* out, hipStream_t s);
@@ -269,7 +272,8 @@ struct SolveResult {
 // projection).  mg_solve may enqueue it speculatively right after the first
 // norm check is enqueued and enqueue it again if V-cycles follow; it must
 // therefore be idempotent given the final solution.  On return the tail has
-// run on the final solution and every mailbox post it made has arrived.
+// been enqueued on the final solution; mailbox posts it makes may still be
+// in flight (host_wait before reading them).
 using SolveTail = std::function<wl_status(hipStream_t)>;
 
 // What the producer of the right-hand side left in red.partial (per block of
