@@ -181,7 +181,7 @@ static void carve_sim(Carver& c, SimImpl<T>& s, const SimConfig& cfg) {
     const int per[3] = {cfg.g.per0, cfg.g.per1, cfg.g.per2};
     carve_hierarchy<T>(c, s.h, cfg.d.ndim, cfg.d.n, per, cfg.nlev, cfg.d.prec == WL_MIXED);
     s.red.slots = reduce_slots_for(cfg.g);
-    s.red.partial = c.take<double>(4 * s.red.slots);
+    s.red.partial = c.take<double>(4 * std::max(s.red.slots, size_t(div_check_map(cfg.g).nblocks)));
     s.red.result = c.take<double>(kResultDoubles);
     s.scal = c.take<double>(4);
     if (cfg.d.prec == WL_MIXED) {
@@ -440,7 +440,8 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
         }
         const VelField<T> V = field_of(s, us, s.plane[P1]);
         WL_TRY(ns_divergence<T>(V, pc, c.unif, 1.0, dt_dev, s.sigma, s.red.partial, ap, st,
-                                producer_check(s) ? s.p : nullptr, s.h.lev[0].Lc));
+                                producer_check(s) ? s.p : nullptr, s.h.lev[0].Lc,
+                                &s.red.pslots));
         WL_TRY(resolve_dt());
         wl_status rc = pressure_solve(s, 1.0, dt, st, &r1);
         if (rc == WL_ERR_NOT_CONVERGED) worst = rc;
@@ -488,7 +489,8 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
         }
         const VelField<T> V2 = field_of(s, us2, s.plane[P2]);
         WL_TRY(ns_divergence<T>(V2, pc, c.unif, 0.5, dt_dev, s.sigma, s.red.partial, ap, st,
-                                producer_check(s) ? s.p : nullptr, s.h.lev[0].Lc));
+                                producer_check(s) ? s.p : nullptr, s.h.lev[0].Lc,
+                                &s.red.pslots));
         // projection, CFL maximum and next dt read only the final pressure
         // and write buffers nothing else reads: the solve may run them
         // speculatively before its first convergence check returns

@@ -280,25 +280,6 @@ struct PairTile {
     int remap;    // XCD-contiguous tile order (nb % 8 == 0)
 };
 
-// Cell r of the one-cell ring around a w x h rectangle, in coordinates of the
-// ring's (w + 2) x (h + 2) box: bottom row, top row, left and right columns.
-__device__ __forceinline__ void ring_cell(int r, int w, int h, int& x, int& y) {
-    const int W = w + 2;
-    if (r < W) {
-        x = r;
-        y = 0;
-    } else if (r < 2 * W) {
-        x = r - W;
-        y = h + 1;
-    } else if (r < 2 * W + h) {
-        x = 0;
-        y = r - 2 * W + 1;
-    } else {
-        x = W - 1;
-        y = r - 2 * W - h + 1;
-    }
-}
-
 template <typename T, int XM, int TX>
 __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Grid g, XAccess<T, XM> X,
                                                               T Lc, const T* __restrict__ b,
@@ -1279,8 +1260,8 @@ wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, d
     const double* bshift = red.result + 5;
     if (bp == BPartials::Check) {
         // the producer of b evaluated the first check
-        k_check_reduce<<<1, 1024, 0, s>>>(red.partial, ln.nblocks(), red.result + 6, red.result,
-                                          post);
+        k_check_reduce<<<1, 1024, 0, s>>>(red.partial, red.pslots ? red.pslots : ln.nblocks(),
+                                          red.result + 6, red.result, post);
         WL_CHECK_LAUNCH();
     } else {
         WL_TRY(active_mean(h, red, b, bp == BPartials::Sums, s));

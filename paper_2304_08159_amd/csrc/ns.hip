@@ -13,6 +13,7 @@
 // c = 1/2, CFL from the per-cell outflow velocity plus 2 d nu.
 #include <cmath>
 #include <cstdlib>
+#include <type_traits>
 
 #include "wl_device.h"
 #include "wl_jacobi.h"
@@ -645,6 +646,154 @@ __global__ __launch_bounds__(kBlock) void k_divergence(TileDev TL, VelField<T> V
     if (threadIdx.x == 0) partial[block_linear()] = bs;
 }
 
+// The same divergence with the pressure solve's first residual check on a
+// periodic grid with a uniform Poisson coefficient Lp (3D, x / y extents
+// multiples of 64 / 8): a 64 x 8 column tile walks a z chunk; per plane the
+// iterate p is staged in LDS with a one-cell ring (the first 148 threads hold
+// a ring cell each) for the x / y neighbours, the z neighbours come from the
+// thread's own column.  sigma is computed with the same operations as
+// k_divergence; partials as its CHK variant, one slot per workgroup.
+constexpr int DC_TX = 64, DC_TY = 8, DC_T = DC_TX * DC_TY;
+constexpr int DC_HX = DC_TX + 2, DC_HY = DC_TY + 2, DC_RING = DC_HX * DC_HY - DC_T;
+
+template <typename T>
+__global__ __launch_bounds__(DC_T) void k_div_check(TileMap tm, VelField<T> V, double c,
+                                                    const double* __restrict__ dt_dev,
+                                                    T* __restrict__ sigma,
+                                                    double* __restrict__ partial,
+                                                    const T* __restrict__ p, T Lp) {
+    __shared__ T sp[2][DC_HY * DC_HX];
+    __shared__ double red[4][DC_T / 64];
+    const Grid& g = V.g;
+    unsigned blk = blockIdx.x;
+    if (tm.remap) blk = (blk & 7u) * (tm.nblocks >> 3) + (blk >> 3);
+    const int tix = int(blk % unsigned(tm.tiles_x));
+    blk /= unsigned(tm.tiles_x);
+    const int tiy = int(blk % unsigned(tm.tiles_y));
+    const int z0 = int(blk / unsigned(tm.tiles_y)) * tm.zc;
+    const int z1 = min(z0 + tm.zc, g.n2);
+    const int i0 = tix * DC_TX, j0 = tiy * DC_TY;
+    const int t = int(threadIdx.x), ax = t % DC_TX, ay = t / DC_TX;
+    const unsigned n0 = unsigned(g.n0), plane = n0 * unsigned(g.n1);
+    // periodic grid column of ring-box position (hx, hy)
+    auto col = [&](int hx, int hy) -> unsigned {
+        int i = i0 + hx - 1, j = j0 + hy - 1;
+        i = i < 0 ? i + g.n0 : (i >= g.n0 ? i - g.n0 : i);
+        j = j < 0 ? j + g.n1 : (j >= g.n1 ? j - g.n1 : j);
+        return unsigned(i) + n0 * unsigned(j);
+    };
+    const unsigned cA = col(ax + 1, ay + 1);
+    const int hA = (ay + 1) * DC_HX + ax + 1;
+    const bool hasB = t < DC_RING;
+    unsigned cB = cA;  // threads without a ring cell load their own again
+    int hB = hA;
+    if (hasB) {
+        int hx, hy;
+        ring_cell(t, DC_TX, DC_TY, hx, hy);
+        cB = col(hx, hy);
+        hB = hy * DC_HX + hx;
+    }
+    const int i = i0 + ax, j = j0 + ay;
+    const int dxp = i + 1 < g.n0 ? 1 : -(g.n0 - 1);
+    const int dyp = j + 1 < g.n1 ? int(n0) : -int(n0) * (g.n1 - 1);
+    const T* __restrict__ ux = V.u[0];
+    const T* __restrict__ uy = V.u[1];
+    const T* __restrict__ uz = V.u[2];
+    const T scale = T(1.0 / (c * *dt_dev));
+    auto wrap = [&](int q) {
+        q %= g.n2;
+        return q < 0 ? q + g.n2 : q;
+    };
+    auto next = [&](int w) { return w + 1 == g.n2 ? 0 : w + 1; };
+    // p rings indexed by plane (mod 4): own column planes k - 1 .. k + 2, the
+    // ring cell planes k .. k + 1; the loop is unrolled 4 times
+    T pA[4] = {}, pB[4] = {};
+    int w = wrap(z0 - 1);
+    pA[3] = p[cA + unsigned(w) * plane];
+    w = next(w);
+    const int wz0 = w;
+    pA[0] = p[cA + unsigned(w) * plane];
+    pB[0] = p[cB + unsigned(w) * plane];
+    w = next(w);
+    pA[1] = p[cA + unsigned(w) * plane];
+    int wp1 = w, wp2 = next(w);  // wrapped planes k + 1, k + 2
+    unsigned id = cA + unsigned(wz0) * plane;
+    T wlo = uz[id];
+    double sum = 0.0, sb2 = 0.0, sc = 0.0, sc2 = 0.0;
+    int k = z0;
+    auto step = [&](auto rc) {
+        constexpr int r = decltype(rc)::value;
+        constexpr int im1 = (r + 3) % 4, ip1 = (r + 1) % 4, ip2 = (r + 2) % 4;
+        T* S = sp[k & 1];
+        S[hA] = pA[r];
+        if (hasB) S[hB] = pB[r];
+        __syncthreads();
+        if (k + 1 < z1) {
+            pA[ip2] = p[cA + unsigned(wp2) * plane];
+            pB[ip1] = p[cB + unsigned(wp1) * plane];
+        }
+        const T xu = ux[id + dxp], yu = uy[id + dyp];
+        const T wup = uz[cA + unsigned(wp1) * plane];
+        T div = (xu - ux[id]) + (yu - uy[id]);
+        div += wup - wlo;
+        wlo = wup;
+        const T sg = div * scale;
+        sigma[id] = sg;
+        T Ax, D;
+        jacobi_terms(pA[r], S[hA - 1], S[hA + 1], S[hA - DC_HX], S[hA + DC_HX], pA[im1], pA[ip1],
+                     Lp, Lp, Lp, Lp, Lp, Lp, true, Ax, D);
+        const double cr = double(sg - Ax);
+        sum += double(sg);
+        sb2 += double(sg) * double(sg);
+        sc += cr;
+        sc2 += cr * cr;
+        id = cA + unsigned(wp1) * plane;
+        wp1 = wp2;
+        wp2 = next(wp2);
+        ++k;
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    while (k < z1) {
+        step(I0{});
+        if (k >= z1) break;
+        step(I1{});
+        if (k >= z1) break;
+        step(I2{});
+        if (k >= z1) break;
+        step(I3{});
+    }
+    // fixed-order workgroup sums: wave butterflies, then waves in order
+    double v[4] = {sum, sb2, sc, sc2};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off, 64);
+        if ((t & 63) == 0) red[q][t >> 6] = v[q];
+    }
+    __syncthreads();
+    if (t == 0) {
+        double* out = partial + 4 * size_t(blockIdx.x);
+        for (int q = 0; q < 4; ++q) {
+            double s = 0.0;
+            for (int wv = 0; wv < DC_T / 64; ++wv) s += red[q][wv];
+            out[q] = s;
+        }
+    }
+}
+
+// Workgroups of k_div_check on g (0 when it does not apply).
+TileMap div_check_map(const Grid& g) {
+    TileMap tm{};
+    if (g.ndim != 3 || g.n0 % DC_TX != 0 || g.n1 % DC_TY != 0) return tm;
+    const size_t cols = size_t(g.n0 / DC_TX) * size_t(g.n1 / DC_TY);
+    int zc = int((cols * size_t(g.n2) + 2047) / 2048);
+    zc = zc < 8 ? 8 : zc;
+    return tile_map(g, DC_TX, DC_TY, zc);
+}
+
 // u = u* - c dt L grad(p) for every direction in one pass (the gradient loop
 // of Sec. 2 with coeff = c dt L, fused over directions).  Each thread walks
 // its column up the z chunk and evaluates every face once: the lower x and y
@@ -1000,16 +1149,23 @@ wl_status ns_tile_class(const Grid& g, const BdimFields<T>& B, unsigned char* cl
 template <typename T>
 wl_status ns_divergence(const VelField<T>& V, const ProjCoeffs<T>& C, bool unif, double c,
                         const double* dt_dev, T* sigma, double* partial, bool allper,
-                        hipStream_t s, const T* p_check, T Lp) {
+                        hipStream_t s, const T* p_check, T Lp, size_t* nslots) {
     const Launch ln = launch_for(V.g.n0, V.g.n1, V.g.n2);
     ProfScope ps(WL_PROF_DIVERGENCE, s, cells(V.g));
+    if (nslots) *nslots = ln.nblocks();
     if (p_check) {
         if (!allper || !unif || V.g.ndim != 3) {
             set_error("internal: the fused first residual check needs a periodic uniform 3D grid");
             return WL_ERR_INVALID_ARG;
         }
-        k_divergence<T, true, true, true><<<ln.grid, ln.block, 0, s>>>(ln.td, V, C, c, dt_dev,
-                                                                       sigma, partial, p_check, Lp);
+        const TileMap tm = div_check_map(V.g);
+        if (tm.nblocks > 0) {
+            k_div_check<T><<<tm.nblocks, DC_T, 0, s>>>(tm, V, c, dt_dev, sigma, partial, p_check, Lp);
+            if (nslots) *nslots = tm.nblocks;
+        } else {
+            k_divergence<T, true, true, true><<<ln.grid, ln.block, 0, s>>>(
+                ln.td, V, C, c, dt_dev, sigma, partial, p_check, Lp);
+        }
         WL_CHECK_LAUNCH();
         return WL_OK;
     }
@@ -1090,7 +1246,7 @@ wl_status ns_set_scalar(double* p, double v, hipStream_t s) {
                                   hipStream_t);                                                   \
     template wl_status ns_divergence<T>(const VelField<T>&, const ProjCoeffs<T>&, bool, double,  \
                                         const double*, T*, double*, bool, hipStream_t, const T*,  \
-                                        T);                                                       \
+                                        T, size_t*);                                              \
     template wl_status ns_project<T>(const VelField<T>&, const T*, const ProjCoeffs<T>&, bool,    \
                                      double, const double*, T* const*, bool, double*, bool,        \
                                      hipStream_t);                                                \

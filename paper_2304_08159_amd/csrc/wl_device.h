@@ -183,4 +183,23 @@ __device__ __forceinline__ double block_max(double v, double* lds) {
 
 __device__ __forceinline__ unsigned block_linear() { return blockIdx.x; }
 
+// Cell r of the one-cell ring around a w x h rectangle, in coordinates of the
+// ring's (w + 2) x (h + 2) box: bottom row, top row, left and right columns.
+__device__ __forceinline__ void ring_cell(int r, int w, int h, int& x, int& y) {
+    const int W = w + 2;
+    if (r < W) {
+        x = r;
+        y = 0;
+    } else if (r < 2 * W) {
+        x = r - W;
+        y = h + 1;
+    } else if (r < 2 * W + h) {
+        x = 0;
+        y = r - 2 * W + 1;
+    } else {
+        x = W - 1;
+        y = r - 2 * W - h + 1;
+    }
+}
+
 }  // namespace wl

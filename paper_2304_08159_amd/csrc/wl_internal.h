@@ -220,6 +220,7 @@ struct Reduce {
     double* partial = nullptr;   // capacity slots * 2 (a simulation's: slots * 4)
     size_t slots = 0;
     double* result = nullptr;    // kResultDoubles doubles
+    size_t pslots = 0;           // slots a producer's partials cover (BPartials::Check)
     HostMailbox mb;
 };
 

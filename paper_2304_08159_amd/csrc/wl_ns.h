@@ -82,10 +82,15 @@ wl_status ns_tile_class(const Grid& g, const BdimFields<T>& B, unsigned char* cl
 // p_check (periodic, uniform, 3D): also the first residual check of the
 // pressure solve that starts from p, with Poisson coefficient Lp (partials of
 // [sigma, sigma^2, c, c^2], c = sigma - A p; see k_divergence).
+// *nslots (if given): the partial slots written (workgroups of the launch).
 template <typename T>
 wl_status ns_divergence(const VelField<T>& V, const ProjCoeffs<T>& C, bool unif, double c,
                         const double* dt_dev, T* sigma, double* partial, bool allper,
-                        hipStream_t s, const T* p_check = nullptr, T Lp = T(0));
+                        hipStream_t s, const T* p_check = nullptr, T Lp = T(0),
+                        size_t* nslots = nullptr);
+// Workgroups of the tiled divergence-with-check kernel on g (nblocks 0 when
+// it does not apply); partial slot capacity must cover them.
+TileMap div_check_map(const Grid& g);
 template <typename T>
 wl_status ns_project(const VelField<T>& V, const T* p, const ProjCoeffs<T>& C, bool unif, double c,
                      const double* dt_dev, T* const out[3], bool cfl, double* partial, bool allper,

@@ -3,8 +3,10 @@ iterates of separate sweeps bit for bit: whole Navier-Stokes steps with every
 eligible level fused against none fused, in FP32, FP64 and mixed precision,
 on grids whose fused levels have full and ragged z chunks.  With fused pairs
 the divergence kernel also takes each solve's first residual check (FP32 and
-FP64): the V-cycle counts and every field must still agree exactly, the
-reported residuals to rounding."""
+FP64) and, on 64 x 8-divisible grids, sums the right-hand side's mean in
+another (fixed) order: there the V-cycle counts must agree exactly and the
+fields and reported residuals to rounding; the mixed-precision case, which
+keeps the separate mean, must agree bit for bit."""
 
 import numpy as np
 import pytest
@@ -48,8 +50,14 @@ def test_fused_sweep_pairs_are_bitwise_identical(precname, n, tol):
     sb, (ub, pb) = _run(wl, 0, precname, n, tol)
     print(precname, n, [s["vcycles"] for s in sa])
     assert sum(s["vcycles"][0] + s["vcycles"][1] for s in sa) >= 4
+    rel = {"fp32": 1e-5, "fp64": 1e-11, "mixed": 0.0}[precname]
     for x, y in zip(sa, sb):
-        assert (x["dt"], x["t"], x["vcycles"]) == (y["dt"], y["t"], y["vcycles"])
+        assert x["vcycles"] == y["vcycles"]
+        for key in ("dt", "t"):
+            assert abs(x[key] - y[key]) <= rel * abs(y[key])
         for q in range(2):
-            assert abs(x["resid"][q] - y["resid"][q]) <= 1e-6 * y["resid"][q] + 1e-300
-    assert torch.equal(ua, ub) and torch.equal(pa, pb)
+            assert abs(x["resid"][q] - y["resid"][q]) <= max(rel, 1e-6) * y["resid"][q] + 1e-300
+    for a, b in ((ua, ub), (pa, pb)):
+        err = (a - b).abs().max().item()
+        print(precname, "max field difference", err)
+        assert err <= rel * b.abs().max().item()
