@@ -186,7 +186,12 @@ __global__ __launch_bounds__(kBlock) void k_smooth(TileDev TL, Grid g, XAccess<T
             return v;
         };
         const bool shift = bshift != nullptr;
-        const double mean = shift ? *bshift : 0.0;
+        const T mean = shift ? T(*bshift) : T(0);
+        // uniform level: one D, the same for every cell
+        T Du = T(0);
+        Du += C.Lc + C.Lc;
+        Du += C.Lc + C.Lc;
+        if (d3) Du += C.Lc + C.Lc;
         const int k0 = sp.z0;
         unsigned id = unsigned(i) + n0 * unsigned(j) + plane * unsigned(k0);
         // z neighbours of the first cell
@@ -223,7 +228,13 @@ __global__ __launch_bounds__(kBlock) void k_smooth(TileDev TL, Grid g, XAccess<T
                 if (d3) Lzu = hzu ? C.L2[idu] : T(0);
             }
             T Ax, D;
-            jacobi_terms(xI, xxl, xxu, xyl, xyu, xzl, xzu, Lxl, Lxu, Lyl, Lyu, Lzl, Lzu, d3, Ax, D);
+            if (UNIF) {
+                Ax = jacobi_ax_uniform(xI, xxl, xxu, xyl, xyu, xzl, xzu, C.Lc, d3);
+                D = Du;
+            } else {
+                jacobi_terms(xI, xxl, xxu, xyl, xyu, xzl, xzu, Lxl, Lxu, Lyl, Lyu, Lzl, Lzu, d3, Ax,
+                             D);
+            }
             bv = jacobi_rhs(bv, D > T(0), shift, mean);
             if (FIRST && bproj) bproj[id] = bv;
             const T r = bv - Ax;
@@ -302,7 +313,7 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
     const unsigned n0 = unsigned(g.n0), plane = n0 * unsigned(g.n1);
     const unsigned ncp = unsigned(X.nc0) * unsigned(X.nc1);
     const bool shift = bshift != nullptr;
-    const double mean = shift ? *bshift : 0.0;
+    const T mean = shift ? T(*bshift) : T(0);
     // A cell this thread handles: periodic grid column, parent column (for
     // the prolongation) and position in the input-region LDS plane.
     struct Slot {
@@ -339,14 +350,34 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
     }
     // w: a plane index already wrapped into [0, n2)
     // input = fine part (+ coarse part for the prolongation), loaded apart
-    // and added when first used so that the add does not wait on the loads
+    // and added when first used so that the add does not wait on the loads;
+    // plane bases are workgroup-uniform, the per-thread offsets fixed
+    // FP32: buffer loads with the plane offset in a scalar register and the
+    // thread's fixed column offset in a vector register (no per-load address
+    // arithmetic; the descriptors bound each array)
+    const unsigned bytes = unsigned(cells(g) * sizeof(T));
+    const unsigned cbytes = unsigned(size_t(ncp) * unsigned(g.n2 > 1 ? (g.n2 + 1) / 2 : 1) * sizeof(T));
+    auto rsrc = [](const T* p, unsigned nbytes) {
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p), 0, int(nbytes), 0x00020000);
+    };
+    const auto dX = rsrc(XM == XM_ZERO ? b : X.x, bytes);
+    const auto dC = rsrc(XM == XM_PROLONG ? X.xc : b, XM == XM_PROLONG ? cbytes : bytes);
+    const auto dB = rsrc(b, bytes);
+    auto at = [&](const T* base, const __amdgpu_buffer_rsrc_t& r, unsigned elem,
+                  unsigned off) -> T {
+        if constexpr (sizeof(T) == 4)
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(
+                                             r, int(off * 4u), int(elem * 4u), 0));
+        else
+            return base[size_t(elem) + off];
+    };
     auto ld = [&](const Slot& S, int w) -> T {
-        return XM == XM_ZERO ? T(0) : X.x[S.col + unsigned(w) * plane];
+        return XM == XM_ZERO ? T(0) : at(X.x, dX, unsigned(w) * plane, S.col);
     };
     auto ldc = [&](const Slot& S, int w) -> T {
-        return XM == XM_PROLONG ? X.xc[S.pcol + ncp * unsigned(w >> 1)] : T(0);
+        return XM == XM_PROLONG ? at(X.xc, dC, ncp * unsigned(w >> 1), S.pcol) : T(0);
     };
-    auto ldb = [&](const Slot& S, int w) -> T { return b[S.col + unsigned(w) * plane]; };
+    auto ldb = [&](const Slot& S, int w) -> T { return at(b, dB, unsigned(w) * plane, S.col); };
     auto wrap = [&](int p) {
         p %= g.n2;
         return p < 0 ? p + g.n2 : p;
@@ -354,7 +385,11 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
     auto next = [&](int w) { return w + 1 == g.n2 ? 0 : w + 1; };
     // one D for the whole level; right-hand sides are shifted once, when
     // they become current, and serve both sweeps
-    const bool act = T(Lc + Lc) + T(Lc + Lc) + T(Lc + Lc) > T(0);
+    T Du = T(0);
+    Du += Lc + Lc;
+    Du += Lc + Lc;
+    Du += Lc + Lc;
+    const bool act = Du > T(0);
     auto rhs = [&](T v) { return jacobi_rhs(v, act, shift, mean); };
     // first sweep at input-region position q of plane S0 (bv shifted)
     auto sweep1 = [&](const T* S0, int q, T xI, T xzl, T xzu, T bv) -> T {
@@ -365,16 +400,14 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
             xyl = S0[q - kPairGX];
             xyu = S0[q + kPairGX];
         }
-        T Ax, D;
-        jacobi_terms(xI, xxl, xxu, xyl, xyu, xzl, xzu, Lc, Lc, Lc, Lc, Lc, Lc, true, Ax, D);
-        return jacobi_new_scaled(xI, bv - Ax, D > T(0), wD);
+        const T Ax = jacobi_ax_uniform(xI, xxl, xxu, xyl, xyu, xzl, xzu, Lc, true);
+        return jacobi_new_scaled(xI, bv - Ax, act, wD);
     };
     // second sweep at first-sweep position h of plane S1 (bv shifted)
     auto sweep2 = [&](const T* S1, int h, T xI, T xzl, T xzu, T bv) -> T {
-        T Ax, D;
-        jacobi_terms(xI, S1[h - 1], S1[h + 1], S1[h - kPairHX], S1[h + kPairHX], xzl, xzu, Lc, Lc,
-                     Lc, Lc, Lc, Lc, true, Ax, D);
-        return jacobi_new_scaled(xI, bv - Ax, D > T(0), wD);
+        const T Ax = jacobi_ax_uniform(xI, S1[h - 1], S1[h + 1], S1[h - kPairHX], S1[h + kPairHX],
+                                       xzl, xzu, Lc, true);
+        return jacobi_new_scaled(xI, bv - Ax, act, wD);
     };
     // Step s computes the first sweep on plane s and the second on plane
     // s - 1, for s = z0 - 1 .. z1, and issues the loads of plane s + 1 + Dp.
@@ -390,6 +423,7 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
     //           xB when a plane becomes s + 1 and into xC at plane s
     constexpr int Dp = kPairDepth;
     constexpr int R = Dp + 3;
+    static_assert(R % 2 == 0, "the LDS buffers alternate with the ring index");
     T xA[R] = {}, xB[R] = {}, rA[R] = {}, rB[R] = {}, xC[R] = {}, yA[R] = {};
     T pA[R] = {}, pB[R] = {}, pC[R] = {};
     const int s0p = z0 - 1;  // first step; ring slot of plane p is (p - s0p) mod R
@@ -428,9 +462,10 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
     auto step = [&](auto rc) {
         constexpr int r = decltype(rc)::value;
         constexpr int im1 = (r + R - 1) % R, i0 = r, ip1 = (r + 1) % R, im2 = (r + R - 2) % R;
-        T* S0 = s0[s & 1];
-        T* S1 = s1[s & 1];
-        const T* S1m = s1[(s & 1) ^ 1];
+        // consecutive steps alternate buffers (R is even)
+        T* S0 = s0[r & 1];
+        T* S1 = s1[r & 1];
+        const T* S1m = s1[(r & 1) ^ 1];
         if (XM == XM_PROLONG) xC[i0] += pC[i0];
         if (XM != XM_ZERO) {
             S0[A.q] = xA[i0];

@@ -600,9 +600,8 @@ __global__ __launch_bounds__(kBlock) void k_divergence(TileDev TL, VelField<T> V
             sigma[id] = sg;
             if (CHK) {
                 const T pzu = p[k + 1 < g.n2 ? id + plane : id - plane * unsigned(g.n2 - 1)];
-                T Ax, D;
-                jacobi_terms(pI, p[id + dxm], p[id + dxp], p[id + dym], p[id + dyp], pzl, pzu, Lp, Lp,
-                             Lp, Lp, Lp, Lp, true, Ax, D);
+                const T Ax = jacobi_ax_uniform(pI, p[id + dxm], p[id + dxp], p[id + dym],
+                                               p[id + dyp], pzl, pzu, Lp, true);
                 const double cr = double(sg - Ax);
                 sb2 += double(sg) * double(sg);
                 sc += cr;
@@ -739,9 +738,8 @@ __global__ __launch_bounds__(DC_T) void k_div_check(TileMap tm, VelField<T> V, d
         wlo = wup;
         const T sg = div * scale;
         sigma[id] = sg;
-        T Ax, D;
-        jacobi_terms(pA[r], S[hA - 1], S[hA + 1], S[hA - DC_HX], S[hA + DC_HX], pA[im1], pA[ip1],
-                     Lp, Lp, Lp, Lp, Lp, Lp, true, Ax, D);
+        const T Ax = jacobi_ax_uniform(pA[r], S[hA - 1], S[hA + 1], S[hA - DC_HX], S[hA + DC_HX],
+                                       pA[im1], pA[ip1], Lp, true);
         const double cr = double(sg - Ax);
         sum += double(sg);
         sb2 += double(sg) * double(sg);

@@ -27,11 +27,22 @@ __device__ __forceinline__ void jacobi_terms(T xI, T xxl, T xxu, T xyl, T xyu, T
     }
 }
 
-// Right-hand side seen by the sweep: with a mean to remove, b - mean on
-// active cells (computed in FP64) and 0 on inactive ones.
+// A x of a row on a level with one coefficient Lc: the second differences
+// of the directions summed, then one multiply.
 template <typename T>
-__device__ __forceinline__ T jacobi_rhs(T bv, bool act, bool shift, double mean) {
-    if (shift) bv = act ? T(double(bv) - mean) : T(0);
+__device__ __forceinline__ T jacobi_ax_uniform(T xI, T xxl, T xxu, T xyl, T xyu, T xzl, T xzu,
+                                               T Lc, bool d3) {
+    T s = (xxu - xI) - (xI - xxl);
+    s += (xyu - xI) - (xI - xyl);
+    if (d3) s += (xzu - xI) - (xI - xzl);
+    return Lc * s;
+}
+
+// Right-hand side seen by the sweep: with a mean to remove, b - mean on
+// active cells and 0 on inactive ones.
+template <typename T>
+__device__ __forceinline__ T jacobi_rhs(T bv, bool act, bool shift, T mean) {
+    if (shift) bv = act ? bv - mean : T(0);
     return bv;
 }
 
