@@ -175,7 +175,7 @@ def batch_compare(torch, wl, count=256, n=(128, 128), tol=1e-8):
     def reqs():
         return [dict(n=n, periodic=(False,) * d, coeffs=L, x=torch.zeros_like(b), b=b, tol=tol,
                      max_vcycles=400) for b in bs]
-    wl.poisson_batch_solve(reqs()[:8])          # warm-up
+    wl.poisson_batch_solve(reqs())              # warm-up at full size (workspace allocation)
     rq = reqs()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
