@@ -497,11 +497,14 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
         const int dest = (us2 == S) ? u1 : S;
         T* o3[3] = {s.vel[dest][0], s.vel[dest][1], s.vel[dest][2]};
         double* dt_next = s.scal + (1 - s.dt_cur);
+        MailboxPost dt_post;
+        WL_TRY(mailbox_post_args(s.red, 8, 1, st, &dt_post));
         const SolveTail tail = [&](hipStream_t q) -> wl_status {
             WL_TRY(ns_project<T>(V2, s.p, pc, c.unif, 0.5, dt_dev, o3, true, s.red.partial, ap, q));
             WL_TRY(ns_dt_from_max(s.red.partial, s.red.slots, c.d.cfl, 2.0 * c.d.ndim * c.d.nu,
-                                  dt_next, s.scal + 2, q));
-            return host_post(s.red, dt_next, 1, 8, q);
+                                  dt_next, s.scal + 2, q, &dt_post));
+            host_posted(s.red);
+            return WL_OK;
         };
         rc = pressure_solve(s, 0.5, dt, st, &r2, &tail);
         if (rc == WL_ERR_NOT_CONVERGED) worst = rc;

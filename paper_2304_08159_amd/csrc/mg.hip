@@ -654,16 +654,6 @@ __global__ __launch_bounds__(kBlock) void k_sum_active(TileDev TL, Grid g, Coeff
 template <typename T>
 __global__ void k_fill(T* __restrict__ p, size_t n, T v);
 
-// One thread: the values, then (after a system-scope fence) the next
-// sequence number, counted in device memory.
-__device__ void mailbox_write(const MailboxPost& P, const double* src) {
-    for (int k = 0; k < P.n; ++k) P.vals[P.slot + k] = src[k];
-    const double q = *P.counter + 1.0;
-    *P.counter = q;
-    __threadfence_system();
-    __hip_atomic_store(P.seqw, unsigned(q), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-
 __global__ void k_publish(const double* __restrict__ src, MailboxPost P) { mailbox_write(P, src); }
 
 HostMailbox::~HostMailbox() {
@@ -749,23 +739,22 @@ __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ part
                                                  int ncomp, double scale, double* __restrict__ out,
                                                  const double* __restrict__ count,
                                                  MailboxPost post) {
-    __shared__ double lds[1024];
-    for (int c = 0; c < ncomp; ++c) {
-        double s = 0.0;
-        for (size_t q = threadIdx.x; q < nslots; q += blockDim.x) s += partial[q * ncomp + c];
-        lds[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-            if (threadIdx.x < w) lds[threadIdx.x] += lds[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            out[c] = lds[0];
-            out[ncomp + c] = count ? (*count > 0.0 ? lds[0] / *count : 0.0) : lds[0] * scale;
-        }
-        __syncthreads();
+    __shared__ double lds[32];
+    double S[2] = {0.0, 0.0};
+    if (ncomp == 2) {
+        wg_slot_reduce<2, false>(partial, nslots, S, lds);
+    } else {
+        double S1[1];
+        wg_slot_reduce<1, false>(partial, nslots, S1, lds);
+        S[0] = S1[0];
     }
-    if (threadIdx.x == 0 && post.vals) mailbox_write(post, out);
+    if (threadIdx.x == 0) {
+        for (int c = 0; c < ncomp; ++c) {
+            out[c] = S[c];
+            out[ncomp + c] = count ? (*count > 0.0 ? S[c] / *count : 0.0) : S[c] * scale;
+        }
+        if (post.vals) mailbox_write(post, out);
+    }
 }
 
 // Coarsest level (see coarse_cg_block).
@@ -1217,20 +1206,9 @@ __global__ __launch_bounds__(1024) void k_check_reduce(const double* __restrict_
                                                        const double* __restrict__ count,
                                                        double* __restrict__ out,
                                                        MailboxPost post) {
-    __shared__ double lds[1024];
+    __shared__ double lds[64];
     double S[4];
-    for (int c = 0; c < 4; ++c) {
-        double v = 0.0;
-        for (size_t q = threadIdx.x; q < nslots; q += blockDim.x) v += partial[4 * q + c];
-        lds[threadIdx.x] = v;
-        __syncthreads();
-        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-            if (threadIdx.x < w) lds[threadIdx.x] += lds[threadIdx.x + w];
-            __syncthreads();
-        }
-        S[c] = lds[0];
-        __syncthreads();
-    }
+    wg_slot_reduce<4, false>(partial, nslots, S, lds);
     if (threadIdx.x == 0) {
         const double n = *count;
         const double m = n > 0.0 ? S[0] / n : 0.0;

@@ -921,24 +921,21 @@ __global__ __launch_bounds__(kBlock) void k_cfl(TileDev TL, VelField<T> V, doubl
     if (threadIdx.x == 0 && threadIdx.y == 0) partial[block_linear()] = m;
 }
 
-// dt = cfl / (max over slots + visc); visc = 2 d nu.  One block.
+// dt = cfl / (max over slots + visc); visc = 2 d nu.  One block; with
+// post.vals it also posts dt to the host mailbox.
 __global__ __launch_bounds__(1024) void k_dt_from_max(const double* __restrict__ partial,
                                                       size_t nslots, double cfl, double visc,
                                                       double* __restrict__ dt_out,
-                                                      double* __restrict__ max_out) {
-    __shared__ double lds[1024];
-    double m = 0.0;
-    for (size_t q = threadIdx.x; q < nslots; q += blockDim.x) m = fmax(m, partial[q]);
-    lds[threadIdx.x] = m;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) lds[threadIdx.x] = fmax(lds[threadIdx.x], lds[threadIdx.x + w]);
-        __syncthreads();
-    }
+                                                      double* __restrict__ max_out,
+                                                      MailboxPost post) {
+    __shared__ double lds[16];
+    double m[1];
+    wg_slot_reduce<1, true>(partial, nslots, m, lds);
     if (threadIdx.x == 0) {
-        const double den = lds[0] + visc;
-        *max_out = lds[0];
+        const double den = m[0] + visc;
+        *max_out = m[0];
         *dt_out = den > 0.0 ? cfl / den : 0.0;
+        if (post.vals) mailbox_write(post, dt_out);
     }
 }
 
@@ -1219,8 +1216,9 @@ wl_status ns_cfl(const VelField<T>& V, bool allper, double* partial, hipStream_t
 }
 
 wl_status ns_dt_from_max(const double* partial, size_t nslots, double cfl, double visc,
-                         double* dt_dev, double* max_dev, hipStream_t s) {
-    k_dt_from_max<<<1, 1024, 0, s>>>(partial, nslots, cfl, visc, dt_dev, max_dev);
+                         double* dt_dev, double* max_dev, hipStream_t s, const MailboxPost* post) {
+    k_dt_from_max<<<1, 1024, 0, s>>>(partial, nslots, cfl, visc, dt_dev, max_dev,
+                                     post ? *post : MailboxPost{});
     WL_CHECK_LAUNCH();
     return WL_OK;
 }

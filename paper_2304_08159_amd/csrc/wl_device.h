@@ -183,6 +183,54 @@ __device__ __forceinline__ double block_max(double v, double* lds) {
 
 __device__ __forceinline__ unsigned block_linear() { return blockIdx.x; }
 
+// One workgroup: fixed-order sums (MAX: maxima, of values >= 0) of K values
+// per slot over nslots slots (partial[K * q + k]): thread t takes slots t,
+// t + blockDim.x, ..., then wave butterflies, then the waves in index order.
+// Results in out[] of thread 0.  lds: >= 16 * K doubles.
+template <int K, bool MAX>
+__device__ inline void wg_slot_reduce(const double* __restrict__ partial, size_t nslots,
+                                      double (&out)[K], double* lds) {
+    double v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = 0.0;
+    for (size_t q = threadIdx.x; q < nslots; q += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double p = partial[K * q + k];
+            v[k] = MAX ? fmax(v[k], p) : v[k] + p;
+        }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_xor(v[k], off, 64);
+            v[k] = MAX ? fmax(v[k], o) : v[k] + o;
+        }
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) lds[(threadIdx.x >> 6) * K + k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = int(blockDim.x + 63) >> 6;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < nw; ++w) s = MAX ? fmax(s, lds[w * K + k]) : s + lds[w * K + k];
+            out[k] = s;
+        }
+    }
+}
+
+// One thread: a mailbox post, the values, then (after a system-scope fence)
+// the next sequence number, counted in device memory.
+__device__ inline void mailbox_write(const MailboxPost& P, const double* src) {
+    for (int k = 0; k < P.n; ++k) P.vals[P.slot + k] = src[k];
+    const double q = *P.counter + 1.0;
+    *P.counter = q;
+    __threadfence_system();
+    __hip_atomic_store(P.seqw, unsigned(q), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Cell r of the one-cell ring around a w x h rectangle, in coordinates of the
 // ring's (w + 2) x (h + 2) box: bottom row, top row, left and right columns.
 __device__ __forceinline__ void ring_cell(int r, int w, int h, int& x, int& y) {

@@ -97,8 +97,11 @@ wl_status ns_project(const VelField<T>& V, const T* p, const ProjCoeffs<T>& C, b
                      hipStream_t s);
 template <typename T>
 wl_status ns_cfl(const VelField<T>& V, bool allper, double* partial, hipStream_t s);
+// post (may be null): also post dt to the host mailbox (the caller then
+// calls host_posted).
 wl_status ns_dt_from_max(const double* partial, size_t nslots, double cfl, double visc,
-                         double* dt_dev, double* max_dev, hipStream_t s);
+                         double* dt_dev, double* max_dev, hipStream_t s,
+                         const MailboxPost* post = nullptr);
 wl_status ns_set_scalar(double* p, double v, hipStream_t s);
 template <typename T>
 wl_status ns_init_velocity(const Grid& g, const int bclo[3], const double U[3], T* const u[3],
