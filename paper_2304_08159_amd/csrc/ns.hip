@@ -262,7 +262,9 @@ __global__ __launch_bounds__(MT_T) void k_momentum_tiled(VelField<float> E,
             }
         }
     };
-    auto slot = [](int z) { return (z + MT_NP) % MT_NP; };  // z >= -1
+    // LDS ring slot of plane z: (z - z0 + 1) mod 3 (plane z0 - 1 in slot 0);
+    // register set of a fetched plane q: (q - z0) mod 3.  The plane loop is
+    // unrolled three times, so both are constants inside it.
     // u* -> u1 on a fetched plane; pb: the pressure of the plane below at
     // the same slots
     auto project = [&](MtPlane& P, const float (&pb)[MT_LOADS]) {
@@ -274,9 +276,8 @@ __global__ __launch_bounds__(MT_T) void k_momentum_tiled(VelField<float> E,
                 P.u[2][k] = proj_face(P.u[2][k], cl, P.p[k], pb[k]);
             }
     };
-    auto store = [&](int zz, const MtPlane& P) {
+    auto store = [&](int sl, const MtPlane& P) {
         const float (&r)[3][MT_LOADS] = P.u;
-        const int sl = slot(zz);
 #pragma unroll
         for (int k = 0; k < MT_LOADS; ++k)
             if (lpos[k] >= 0)
@@ -285,7 +286,9 @@ __global__ __launch_bounds__(MT_T) void k_momentum_tiled(VelField<float> E,
     };
     auto U = [&](int c, int sl, int p) -> float { return sU[c][sl][p]; };
 
-    MtPlane PA, PB;
+    MtPlane PR[3];
+    MtPlane& PA = PR[2];  // plane z0 - 1
+    MtPlane& PB = PR[0];  // plane z0
     float wm2[3];
     fetch(z0 - 1, PA);
     fetch(z0, PB);
@@ -310,42 +313,50 @@ __global__ __launch_bounds__(MT_T) void k_momentum_tiled(VelField<float> E,
         project(PA, pm2);
         project(PB, PA.p);
     }
-    store(z0 - 1, PA);
-    store(z0, PB);
-    fetch(z0 + 1, PA);
-    if (PROJ) project(PA, PB.p);
-    fetch(z0 + 2, PB);  // projected when its plane is first used
-    store(z0 + 1, PA);
+    store(0, PA);
+    store(1, PB);
+    fetch(z0 + 1, PR[1]);
+    if (PROJ) project(PR[1], PB.p);
+    fetch(z0 + 2, PR[2]);  // projected when its plane is first used
+    store(2, PR[1]);
     __syncthreads();
-    // own-column window: planes z-1, z, z+1 (plane z+2 is slot 0 of the
-    // register set that holds it)
-    float wm1[3], w0[3], wp1[3];
-    float Fzlo[3];
+    // own-column window W[q][c]: planes z-1, z, z+1 in the LDS ring's slots
+    // (plane z+2 is slot 0 of the register set that holds it); lower z-face
+    // fluxes Fz[q][c] of planes z and z+1 in slots (z - z0) mod 3
+    float W[3][3];
+    float Fz[3][3];
     {
-        const int sm1 = slot(z0 - 1), s0 = slot(z0), sp1 = slot(z0 + 1);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            wm1[c] = U(c, sm1, own);
-            w0[c] = U(c, s0, own);
-            wp1[c] = U(c, sp1, own);
+            W[0][c] = U(c, 0, own);
+            W[1][c] = U(c, 1, own);
+            W[2][c] = U(c, 2, own);
         }
-        const float wb[3] = {U(2, s0, own - 1), U(2, s0, own - MT_LX), wm1[2]};
+        const float wb[3] = {U(2, 1, own - 1), U(2, 1, own - MT_LX), W[0][2]};
 #pragma unroll
-        for (int c = 0; c < 3; ++c) Fzlo[c] = flux2(wm2[c], wm1[c], w0[c], wp1[c], w0[2] + wb[c], nu2);
+        for (int c = 0; c < 3; ++c)
+            Fz[0][c] = flux2(wm2[c], W[0][c], W[1][c], W[2][c], W[1][2] + wb[c], nu2);
     }
 
-    // One plane.  cur holds plane z + 2 (fetched one plane earlier), nxt
-    // receives plane z + 3.
-    auto do_plane = [&](int z, MtPlane& curP, MtPlane& nxt) {
-        const int s0 = slot(z), sm1 = slot(z - 1), sp1 = slot(z + 1);
+    // One plane, rc = (z - z0) mod 3.  Register set (r + 2) mod 3 holds
+    // plane z + 2 (fetched one plane earlier), set r (plane z, already in
+    // LDS) receives plane z + 3, set r + 1 holds plane z + 1 (whose pressure
+    // projects plane z + 2).
+    auto do_plane = [&](auto rc, int z) {
+        constexpr int r = decltype(rc)::value;
+        constexpr int sm1 = r, s0 = (r + 1) % 3, sp1 = (r + 2) % 3;
+        constexpr int flo = r, fhi = (r + 1) % 3;
+        MtPlane& curP = PR[(r + 2) % 3];
+        MtPlane& nxt = PR[r];
+        const MtPlane& below = PR[(r + 1) % 3];
+        float (&wm1)[3] = W[sm1];
+        float (&w0)[3] = W[s0];
+        float (&wp1)[3] = W[sp1];
+        float (&Fzlo)[3] = Fz[flo];
+        float (&Fzhi)[3] = Fz[fhi];
         const bool more = z + 1 < z1;
-        float pbelow[MT_LOADS];  // pressure of plane z + 1 (held by nxt until refetched)
-        if (PROJ) {
-#pragma unroll
-            for (int k = 0; k < MT_LOADS; ++k) pbelow[k] = nxt.p[k];
-        }
         if (more) fetch(z + 3, nxt);
-        if (PROJ) project(curP, pbelow);
+        if (PROJ) project(curP, below.p);
         const float (&cur)[3][MT_LOADS] = curP.u;
         const unsigned id = unsigned(gx) + unsigned(g.n0) * unsigned(gy) + plane * unsigned(z);
         float ubase[3] = {0.f, 0.f, 0.f};
@@ -395,7 +406,6 @@ __global__ __launch_bounds__(MT_T) void k_momentum_tiled(VelField<float> E,
                                               U(c, s0, p), U(c, s0, p + MT_LX), a0 + ab[c], nu2);
         }
         // upper z face of the own cell
-        float Fzhi[3];
         {
             const float wb[3] = {U(2, sp1, own - 1), U(2, sp1, own - MT_LX), w0[2]};
 #pragma unroll
@@ -420,19 +430,22 @@ __global__ __launch_bounds__(MT_T) void k_momentum_tiled(VelField<float> E,
                 fo[c][id] = v;
             }
         }
+        // plane z - 1 leaves the window, plane z + 2 enters its slot
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            Fzlo[c] = Fzhi[c];
-            wm1[c] = w0[c];
-            w0[c] = wp1[c];
-            wp1[c] = cur[c][0];
-        }
-        if (more) store(z + 2, curP);
+        for (int c = 0; c < 3; ++c) wm1[c] = cur[c][0];
+        if (more) store(sm1, curP);
         __syncthreads();
     };
-    for (int z = z0; z < z1; z += 2) {
-        do_plane(z, PB, PA);
-        if (z + 1 < z1) do_plane(z + 1, PA, PB);
+    using R0 = std::integral_constant<int, 0>;
+    using R1 = std::integral_constant<int, 1>;
+    using R2 = std::integral_constant<int, 2>;
+    for (int z = z0; z < z1;) {
+        do_plane(R0{}, z);
+        if (++z >= z1) break;
+        do_plane(R1{}, z);
+        if (++z >= z1) break;
+        do_plane(R2{}, z);
+        ++z;
     }
 }
 
