@@ -37,7 +37,8 @@ BYTES_PER_CELL = {
     "restrict_fine": 8.5,    # read x, b; write b_coarse (1/8)
     "momentum": 32.0,        # predictor 24 (read u, write f); corrector 40 (read u*, p, u^n,
                              # write f: it applies the predictor's projection as it loads)
-    "divergence": 16.0,      # read u* (3 comps); write sigma
+    "divergence": 20.0,      # read u* (3 comps) and p (the solve's first residual check,
+                             # fused in on this grid); write sigma
     "project": 28.0,         # read u* (3), p; write u (3)
     "norm_fine": 8.0,        # residual norm only: read x, b
     "pair_fine": 12.0,       # two sweeps in one pass: read x, b; write x''
@@ -54,13 +55,14 @@ def step_bytes_per_cell(vcycles_total, fused):
     - separate sweeps: first check-and-sweep 12; per V-cycle the fine
       sweep, restriction, prolongation sweep and sweep (12 + 8.5 + 12.5 + 12),
       the norm sweep (12) and 53 B per coarse cell;
-    - fused sweep pairs (fine and first coarse level): first check 8; per
-      V-cycle pair 12, restriction 8.5, prolongation pair 12.5, norm check 8,
-      29 B per level-1 cell (zero-start pair 8, restriction 8.5, prolongation
-      pair 12.5) and 53 B per cell of the coarser levels.
+    - fused sweep pairs (fine and first coarse level): the first check is
+      taken inside the divergence, which then also reads p (4); per V-cycle
+      pair 12, restriction 8.5, prolongation pair 12.5, norm check 8, 29 B per
+      level-1 cell (zero-start pair 8, restriction 8.5, prolongation pair
+      12.5) and 53 B per cell of the coarser levels.
     """
     if fused:
-        first = 8.0
+        first = 4.0
         per_vcycle = 12 + 8.5 + 12.5 + 8 + 29.0 / 8 + 53.0 * (1.0 / 7 - 1.0 / 8)
     else:
         first = 12.0
