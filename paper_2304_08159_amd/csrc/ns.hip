@@ -171,16 +171,12 @@ struct MtPlane {
 // u1 = u* - dt Lc grad(pp) as it fills its tile (the predictor's projection is
 // then never stored), with the same rounding as k_project.
 template <bool ALLPER, bool CORR, bool PROJ>
-__global__ __launch_bounds__(MT_T) void k_momentum_tiled(VelField<float> E,
-                                                           const float* __restrict__ un0,
-                                                           const float* __restrict__ un1,
-                                                           const float* __restrict__ un2,
-                                                           float* __restrict__ f0,
-                                                           float* __restrict__ f1,
-                                                           float* __restrict__ f2, float nu,
-                                                           const double* __restrict__ dt_dev,
-                                                           TileMap tm,
-                                                           const float* __restrict__ pp, float Lc) {
+__device__ __forceinline__ void momentum_tile(const VelField<float>& E, const float* __restrict__ un0,
+                                              const float* __restrict__ un1,
+                                              const float* __restrict__ un2, float* __restrict__ f0,
+                                              float* __restrict__ f1, float* __restrict__ f2,
+                                              float nu, const double* __restrict__ dt_dev, TileMap tm,
+                                              const float* __restrict__ pp, float Lc) {
     static_assert(!PROJ || ALLPER, "the fused projection assumes periodic wrap");
     __shared__ float sU[3][MT_NP][MT_PL];
     __shared__ float sFx[3][MT_Y][MT_X + 1];
@@ -235,17 +231,21 @@ __global__ __launch_bounds__(MT_T) void k_momentum_tiled(VelField<float> E,
         if (ALLPER) {
             const int gz = zz < 0 ? zz + g.n2 : (zz >= g.n2 ? zz - g.n2 : zz);
             const unsigned base = unsigned(gz) * plane;
+            // without PROJ the loads are unconditional: an unused slot
+            // (lpos < 0) reads the tile's corner, a valid address; no branch
+            // around the loads keeps the wait counts exact, so waiting for
+            // one plane never waits for the planes fetched after it
 #pragma unroll
-            for (int k = 0; k < MT_LOADS; ++k)
-                if (lpos[k] >= 0) {
+            for (int k = 0; k < MT_LOADS; ++k) {
+                if (PROJ && lpos[k] < 0) continue;
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) r[c][k] = E.u[c][base + offxy[k]];
-                    if (PROJ) {
-                        P.p[k] = pp[base + offxy[k]];
-                        P.pxm[k] = pp[base + offxm[k]];
-                        P.pym[k] = pp[base + offym[k]];
-                    }
+                for (int c = 0; c < 3; ++c) r[c][k] = E.u[c][base + offxy[k]];
+                if (PROJ) {
+                    P.p[k] = pp[base + offxy[k]];
+                    P.pxm[k] = pp[base + offxm[k]];
+                    P.pym[k] = pp[base + offym[k]];
                 }
+            }
         } else {
             const bool zin = zz >= 0 && zz < g.n2;
             const unsigned base = zin ? unsigned(zz) * plane : 0u;
@@ -317,7 +317,21 @@ __global__ __launch_bounds__(MT_T) void k_momentum_tiled(VelField<float> E,
     store(1, PB);
     fetch(z0 + 1, PR[1]);
     if (PROJ) project(PR[1], PB.p);
+    // Without PROJ, loads run two planes ahead and the corrector's u^n of the
+    // own cell one plane ahead, issued before that plane's prefetch so that
+    // waiting for it never waits for the prefetch.  Loads are unconditional
+    // (a thread outside a ragged tile reads the nearest cell, a chunk's last
+    // planes repeat its last fetch), so that the compiler's wait counts stay
+    // exact.  With PROJ (whose planes carry three times the loads, under
+    // per-slot conditions) one plane of lookahead measured faster.
+    const unsigned idl = unsigned(min(gx, g.n0 - 1)) + unsigned(g.n0) * unsigned(min(gy, g.n1 - 1));
+    float ubn[3] = {0.f, 0.f, 0.f};
+    if (CORR && !PROJ) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ubn[c] = un[c][idl + plane * unsigned(z0)];
+    }
     fetch(z0 + 2, PR[2]);  // projected when its plane is first used
+    if (!PROJ) fetch(min(z0 + 3, z1 + 1), PR[0]);
     store(2, PR[1]);
     __syncthreads();
     // own-column window W[q][c]: planes z-1, z, z+1 in the LDS ring's slots
@@ -339,31 +353,45 @@ __global__ __launch_bounds__(MT_T) void k_momentum_tiled(VelField<float> E,
     }
 
     // One plane, rc = (z - z0) mod 3.  Register set (r + 2) mod 3 holds
-    // plane z + 2 (fetched one plane earlier), set r (plane z, already in
-    // LDS) receives plane z + 3, set r + 1 holds plane z + 1 (whose pressure
-    // projects plane z + 2).
+    // plane z + 2.  Without PROJ: set r holds plane z + 3 (in flight since
+    // the previous plane) and set (r + 1) mod 3 (plane z + 1, already in LDS)
+    // receives plane z + 4.  With PROJ: set r (plane z, already in LDS)
+    // receives plane z + 3, and set (r + 1) mod 3 holds plane z + 1, whose
+    // pressure projects plane z + 2.
     auto do_plane = [&](auto rc, int z) {
         constexpr int r = decltype(rc)::value;
         constexpr int sm1 = r, s0 = (r + 1) % 3, sp1 = (r + 2) % 3;
         constexpr int flo = r, fhi = (r + 1) % 3;
         MtPlane& curP = PR[(r + 2) % 3];
-        MtPlane& nxt = PR[r];
-        const MtPlane& below = PR[(r + 1) % 3];
+        MtPlane& below = PR[(r + 1) % 3];
         float (&wm1)[3] = W[sm1];
         float (&w0)[3] = W[s0];
         float (&wp1)[3] = W[sp1];
         float (&Fzlo)[3] = Fz[flo];
         float (&Fzhi)[3] = Fz[fhi];
         const bool more = z + 1 < z1;
-        if (more) fetch(z + 3, nxt);
-        if (PROJ) project(curP, below.p);
-        const float (&cur)[3][MT_LOADS] = curP.u;
         const unsigned id = unsigned(gx) + unsigned(g.n0) * unsigned(gy) + plane * unsigned(z);
         float ubase[3] = {0.f, 0.f, 0.f};
-        if (CORR && inside) {
+        if constexpr (PROJ) {
+            if (more) fetch(z + 3, PR[r]);
+            project(curP, below.p);
+            if (CORR && inside) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) ubase[c] = un[c][id];
+                for (int c = 0; c < 3; ++c) ubase[c] = un[c][id];
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ubase[c] = ubn[c];
+            if (CORR) {
+                const unsigned zn = unsigned(min(z + 1, z1 - 1));
+#pragma unroll
+                for (int c = 0; c < 3; ++c) ubn[c] = un[c][idl + plane * zn];
+                // keep these loads ahead of the prefetch in issue order
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            fetch(min(z + 4, z1 + 1), below);
         }
+        const float (&cur)[3][MT_LOADS] = curP.u;
         // lower x face of the own cell (and the tile's upper x column)
         float Fxlo[3], Fylo[3];
         {
@@ -447,6 +475,26 @@ __global__ __launch_bounds__(MT_T) void k_momentum_tiled(VelField<float> E,
         do_plane(R2{}, z);
         ++z;
     }
+}
+
+// The two entry points differ only in their register budget: without the
+// projection, at most 128 VGPRs (4 waves per SIMD, two blocks per CU), which
+// keeps the two-plane lookahead from stretching the schedule; the projecting
+// corrector measured faster with the compiler's own choice.
+template <bool ALLPER, bool CORR>
+__global__ __launch_bounds__(MT_T) __attribute__((amdgpu_waves_per_eu(4))) void k_momentum_tiled(
+    VelField<float> E, const float* __restrict__ un0, const float* __restrict__ un1,
+    const float* __restrict__ un2, float* __restrict__ f0, float* __restrict__ f1,
+    float* __restrict__ f2, float nu, const double* __restrict__ dt_dev, TileMap tm) {
+    momentum_tile<ALLPER, CORR, false>(E, un0, un1, un2, f0, f1, f2, nu, dt_dev, tm, nullptr, 0.f);
+}
+
+__global__ __launch_bounds__(MT_T) void k_momentum_tiled_proj(
+    VelField<float> E, const float* __restrict__ un0, const float* __restrict__ un1,
+    const float* __restrict__ un2, float* __restrict__ f0, float* __restrict__ f1,
+    float* __restrict__ f2, float nu, const double* __restrict__ dt_dev, TileMap tm,
+    const float* __restrict__ pp, float Lc) {
+    momentum_tile<true, true, true>(E, un0, un1, un2, f0, f1, f2, nu, dt_dev, tm, pp, Lc);
 }
 
 // Outflow plane (upper x face): convective update d(uout)/dt = -U_x (uout -
@@ -1084,9 +1132,8 @@ wl_status ns_momentum(const VelField<T>& E, const T* const un[3], T* const f[3],
         if (g.ndim == 3) {
             const TileMap tm = tile_map(g, MT_X, MT_Y, momentum_zchunk());
 #define WL_MT(AP, CR)                                                                          \
-    k_momentum_tiled<AP, CR, false><<<tm.nblocks, MT_T, 0, s>>>(E, un[0], un[1], un[2], f[0],    \
-                                                                  f[1], f[2], nu, dt_dev, tm,  \
-                                                                  nullptr, 0.f)
+    k_momentum_tiled<AP, CR><<<tm.nblocks, MT_T, 0, s>>>(E, un[0], un[1], un[2], f[0], f[1],     \
+                                                         f[2], nu, dt_dev, tm)
             if (allper) {
                 if (corr) WL_MT(true, true); else WL_MT(true, false);
             } else {
@@ -1120,9 +1167,8 @@ wl_status ns_momentum_proj(const VelField<float>& E, const float* const un[3], f
     }
     ProfScope ps(WL_PROF_MOMENTUM, s, cells(g));
     const TileMap tm = tile_map(g, MT_X, MT_Y, momentum_zchunk());
-    k_momentum_tiled<true, true, true><<<tm.nblocks, MT_T, 0, s>>>(E, un[0], un[1], un[2], f[0],
-                                                                     f[1], f[2], nu, dt_dev, tm, p,
-                                                                     Lc);
+    k_momentum_tiled_proj<<<tm.nblocks, MT_T, 0, s>>>(E, un[0], un[1], un[2], f[0], f[1], f[2], nu,
+                                                      dt_dev, tm, p, Lc);
     WL_CHECK_LAUNCH();
     return WL_OK;
 }
