@@ -92,6 +92,27 @@ def test_tgv3d_fp32_replay_parity():
     _replay(sim, osim, 4, 1e-5, 1e-5, "tgv32")
 
 
+def test_tgv256_fp32_full_size_replay_parity():
+    """The benchmark's workload at its full size and in the launch
+    configuration it times (256^3 FP32 TGV, Re = 1600, tol 1e-5: momentum
+    z chunks of 64 planes over several chunks, fused sweep pairs on every
+    level, the first residual check inside the divergence, the predictor's
+    projection inside the corrector's convection-diffusion): after one warm-up
+    step (so that p^n is a real warm start), one step replayed by the oracle
+    over the whole field."""
+    import paper_2304_08159_amd as wl
+    N = 256
+    u, v, w, nu = W.tgv3d(N, Re=1600.0)
+    cfg = dict(n=(N, N, N), bc_lo=[0] * 3, bc_hi=[0] * 3, U=(0.0, 0.0, 0.0), nu=nu)
+    sim, osim = _make(cfg, wl.WL_FP32, 1e-5)
+    for i, a in enumerate((u, v, w)):
+        sim.set(wl.FIELD_U0 + i, to_device(a, 3, torch, torch.float32))
+    del u, v, w
+    print("tgv256 warm-up step:", sim.step(), flush=True)
+    _replay(sim, osim, 1, 1e-5, 1e-5, "tgv256")
+    sim.close()
+
+
 def test_tgv2d_fp64_free_running_matches_oracle():
     import paper_2304_08159_amd as wl
     N = 48
