@@ -78,6 +78,41 @@ def test_mixed_precision_reaches_fp64_tolerance():
     assert err <= 1e-6
 
 
+@pytest.mark.parametrize("n", [(256, 256, 256), (384, 256, 256)])
+def test_sphere_poisson_full_size_residual_and_coefficients(n):
+    """The mixed-precision Poisson workload at its full sizes (Neumann box,
+    sphere of radius 32 cells, N(0,1) right-hand side, tol 1e-8): the
+    library's BDIM coefficients equal the oracle's, and the mixed and the
+    plain FP64 solutions both leave an FP64 residual, recomputed by the oracle's
+    operator, within the tolerance."""
+    import paper_2304_08159_amd as wl
+    cfg = W.poisson_sphere_config(n, 32.0)
+    L = G.measure(n, [WALL] * 3, cfg["body"])[2]
+    sim = wl.Sim(n, cfg["bc_lo"], cfg["bc_hi"], (0.0, 0.0, 0.0), 0.0, body=cfg["body"],
+                 prec=wl.WL_FP64, levels=0, tol=1e-8)
+    Lg = [to_oracle(sim.get(wl.FIELD_L0 + i), 3) for i in range(3)]
+    sim.close()
+    for i in range(3):
+        assert np.max(np.abs(Lg[i] - L[i])) <= 1e-12
+    b = W.random_rhs(n, 2304)
+    h = P.Hierarchy(L, auto_levels(n), [False] * 3)
+    act = h.active[0]
+    bp = P.project_rhs(b, act)
+    C = _coeff_tensor(L, 3, torch.float64)
+    bd = to_device(b, 3, torch, torch.float64)
+    for prec in (wl.WL_MIXED, wl.WL_FP64):
+        ps = wl.Poisson(n, (False, False, False), prec=prec)
+        x = torch.zeros(ps.shape, dtype=torch.float64, device="cuda")
+        k, rel = ps.solve(C, x, bd, tol=1e-8, max_vcycles=400)
+        ps.close()
+        xg = to_oracle(x, 3)
+        res = np.linalg.norm(bp - P.apply_A(L, xg, [False] * 3)) / np.linalg.norm(bp)
+        print(f"{n} prec={prec}: vcycles={k} rel={rel:.3e} oracle-recomputed={res:.3e}",
+              flush=True)
+        assert rel <= 1e-8 and res <= 1.05e-8
+        assert np.all(xg[~act] == 0.0)
+
+
 def test_zero_rhs_and_not_converged_and_bad_args():
     import paper_2304_08159_amd as wl
     n, per = (16, 16, 16), (True, True, True)
