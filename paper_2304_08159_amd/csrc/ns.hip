@@ -11,6 +11,7 @@
 // kappa = 1/3 interpolant bounded by the Koren limiter (median form), cosine
 // BDIM kernel of half-width eps, Heun stages with projection factor c = 1 and
 // c = 1/2, CFL from the per-cell outflow velocity plus 2 d nu.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <type_traits>
@@ -478,11 +479,12 @@ __device__ __forceinline__ void momentum_tile(const VelField<float>& E, const fl
 }
 
 // The two entry points differ only in their register budget: without the
-// projection, at most 128 VGPRs (4 waves per SIMD, two blocks per CU), which
-// keeps the two-plane lookahead from stretching the schedule; the projecting
-// corrector measured faster with the compiler's own choice.
+// projection, at most 128 VGPRs (4 waves per SIMD, two blocks per CU), and
+// 80 for the periodic predictor (6 waves, three blocks per CU, no spills),
+// which keeps the two-plane lookahead from stretching the schedule; the
+// projecting corrector measured faster with the compiler's own choice.
 template <bool ALLPER, bool CORR>
-__global__ __launch_bounds__(MT_T) __attribute__((amdgpu_waves_per_eu(4))) void k_momentum_tiled(
+__global__ __launch_bounds__(MT_T) __attribute__((amdgpu_waves_per_eu(ALLPER && !CORR ? 6 : 4))) void k_momentum_tiled(
     VelField<float> E, const float* __restrict__ un0, const float* __restrict__ un1,
     const float* __restrict__ un2, float* __restrict__ f0, float* __restrict__ f1,
     float* __restrict__ f2, float nu, const double* __restrict__ dt_dev, TileMap tm) {
@@ -1101,14 +1103,26 @@ wl_status ns_measure(const Grid& g, const BodyDev& body, const int bclo[3], cons
     return WL_OK;
 }
 
-// z planes per block of the tiled momentum kernel (WL_MOM_ZC overrides).
-int momentum_zchunk() {
-    static const int zc = [] {
+// z planes per block of the tiled momentum kernel: enough z chunks that
+// every CU gets per_cu resident blocks, each chunk 8 to 64 planes (a chunk
+// reloads four planes around it); WL_MOM_ZC overrides.
+int momentum_zchunk(const Grid& g, int per_cu) {
+    static const int env = [] {
         const char* e = std::getenv("WL_MOM_ZC");
         const int v = e ? std::atoi(e) : 0;
-        return v > 0 ? v : 64;
+        return v > 0 ? v : 0;
     }();
-    return zc;
+    if (env) return env;
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        ncu <= 0)
+        ncu = 256;
+    const long tiles = long((g.n0 + MT_X - 1) / MT_X) * long((g.n1 + MT_Y - 1) / MT_Y);
+    const long want = long(per_cu) * ncu;
+    const long nch = std::max(1L, (want + tiles - 1) / tiles);
+    const int zc = int((g.n2 + nch - 1) / nch);
+    return std::min(64, std::max(8, zc));
 }
 
 TileMap tile_map(const Grid& g, int tile_x, int tile_y, int zc) {
@@ -1130,7 +1144,9 @@ wl_status ns_momentum(const VelField<T>& E, const T* const un[3], T* const f[3],
     ProfScope ps(WL_PROF_MOMENTUM, s, cells(g));
     if constexpr (sizeof(T) == 4) {
         if (g.ndim == 3) {
-            const TileMap tm = tile_map(g, MT_X, MT_Y, momentum_zchunk());
+            // blocks per CU the kernel's registers allow (LDS allows 3): the
+            // periodic predictor fits 80 VGPRs (6 waves per SIMD), the others 128
+            const TileMap tm = tile_map(g, MT_X, MT_Y, momentum_zchunk(g, allper && !corr ? 3 : 2));
 #define WL_MT(AP, CR)                                                                          \
     k_momentum_tiled<AP, CR><<<tm.nblocks, MT_T, 0, s>>>(E, un[0], un[1], un[2], f[0], f[1],     \
                                                          f[2], nu, dt_dev, tm)
@@ -1166,7 +1182,7 @@ wl_status ns_momentum_proj(const VelField<float>& E, const float* const un[3], f
         return WL_ERR_INVALID_ARG;
     }
     ProfScope ps(WL_PROF_MOMENTUM, s, cells(g));
-    const TileMap tm = tile_map(g, MT_X, MT_Y, momentum_zchunk());
+    const TileMap tm = tile_map(g, MT_X, MT_Y, momentum_zchunk(g, 2));
     k_momentum_tiled_proj<<<tm.nblocks, MT_T, 0, s>>>(E, un[0], un[1], un[2], f[0], f[1], f[2], nu,
                                                       dt_dev, tm, p, Lc);
     WL_CHECK_LAUNCH();

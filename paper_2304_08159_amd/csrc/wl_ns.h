@@ -49,7 +49,7 @@ struct TileMap {
     int remap;  // 1: XCD-contiguous block order (nblocks divisible by 8)
 };
 TileMap tile_map(const Grid& g, int tile_x, int tile_y, int zc);
-int momentum_zchunk();
+int momentum_zchunk(const Grid& g, int per_cu);
 
 struct BodyDev {
     int kind;

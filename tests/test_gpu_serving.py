@@ -15,9 +15,10 @@ pytestmark = pytest.mark.gpu
 
 def _mix():
     from paper_2304_08159_amd.serving import Request
-    sizes = [(64, 64), (128, 128), (32, 32, 32), (48, 48, 48), (64, 64, 64), (96, 64)]
+    sizes = [(64, 64), (128, 128), (32, 32, 32), (48, 48, 48), (64, 64, 64), (96, 64),
+             (256, 256), (128, 128, 128)]
     reqs = []
-    for k in range(12):
+    for k in range(16):
         n = sizes[k % len(sizes)]
         kind = "poisson" if k % 2 == 0 else "ns"
         reqs.append(Request(id=k, kind=kind, n=n, arrival=0.0,
@@ -37,7 +38,7 @@ def test_results_identical_alone_and_in_the_mix():
     mixed = Server(ex, 64 << 30, slots=8).run(_mix())
     s = summarize(mixed)
     print(s)
-    assert s["done"] == 12
+    assert s["done"] == 16
     for r in mixed:
         assert r.result[0] == alone[r.id], f"request {r.id} differs in the mix"
 
@@ -45,7 +46,8 @@ def test_results_identical_alone_and_in_the_mix():
 def test_served_poisson_meets_tolerance_on_oracle_operator():
     from paper_2304_08159_amd.serving import GpuExecutor, Request, Server
     ex = GpuExecutor(keep_fields=True)
-    for n in [(64, 48), (24, 32, 16)]:
+    # ragged small grids and the largest request sizes of the serving mix
+    for n in [(64, 48), (24, 32, 16), (256, 256), (128, 128, 128)]:
         r = Request(id=0, kind="poisson", n=n, radius=min(n) / 5.0, seed=7, tol=1e-8)
         out = Server(ex, 8 << 30, slots=1).run([r])[0]
         assert out.status == "done", out.error
