@@ -972,6 +972,9 @@ template <typename T>
 static bool pair_ok(const Hierarchy<T>& h, const Level<T>& L) {
     if (!h.pairs || !L.uniform || L.g.ndim != 3) return false;
     if (pair_tx(L.g.n0) == 0 || L.g.n1 % kPairTY != 0) return false;
+    // FP32 pairs address their arrays through buffer descriptors, whose
+    // 32-bit byte offsets cover arrays below 4 GiB (2^30 cells)
+    if (sizeof(T) == 4 && cells(L.g) >= (size_t(1) << 30)) return false;
     return h.pairs == 2 || cells(L.g) >= pair_min_cells();
 }
 
