@@ -171,7 +171,7 @@ struct MtPlane {
 // u* and pp its pressure; the kernel evaluates the projected field
 // u1 = u* - dt Lc grad(pp) as it fills its tile (the predictor's projection is
 // then never stored), with the same rounding as k_project.
-template <bool ALLPER, bool CORR, bool PROJ>
+template <bool ALLPER, bool CORR, bool PROJ, bool BUF>
 __device__ __forceinline__ void momentum_tile(const VelField<float>& E, const float* __restrict__ un0,
                                               const float* __restrict__ un1,
                                               const float* __restrict__ un2, float* __restrict__ f0,
@@ -179,6 +179,7 @@ __device__ __forceinline__ void momentum_tile(const VelField<float>& E, const fl
                                               float nu, const double* __restrict__ dt_dev, TileMap tm,
                                               const float* __restrict__ pp, float Lc) {
     static_assert(!PROJ || ALLPER, "the fused projection assumes periodic wrap");
+    static_assert(!BUF || ALLPER, "buffer addressing assumes periodic wrap");
     __shared__ float sU[3][MT_NP][MT_PL];
     __shared__ float sFx[3][MT_Y][MT_X + 1];
     __shared__ float sFy[3][MT_Y + 1][MT_X];
@@ -227,6 +228,51 @@ __device__ __forceinline__ void momentum_tile(const VelField<float>& E, const fl
                         : 0u;
     }
     const unsigned plane = unsigned(g.n0) * unsigned(g.n1);
+    // BUF (periodic, arrays below 4 GiB): loads and stores go through buffer
+    // descriptors with the plane's byte offset in a scalar register and the
+    // thread's fixed column offset in a vector register, so that no per-plane
+    // address arithmetic is repeated on the vector ALU
+    const int nbytes = BUF ? int(unsigned(size_t(plane) * unsigned(g.n2) * 4u)) : 0;
+    auto rsrc = [&](const float* q) {
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(q), 0, nbytes, 0x00020000);
+    };
+    const auto dU0 = rsrc(E.u[0]), dU1 = rsrc(E.u[1]), dU2 = rsrc(E.u[2]);
+    const auto dN0 = rsrc(un0), dN1 = rsrc(un1), dN2 = rsrc(un2);
+    const auto dF0 = rsrc(f0), dF1 = rsrc(f1), dF2 = rsrc(f2);
+    const auto dP = rsrc(pp);
+    // the plane offsets are uniform over the block; readfirstlane says so to
+    // the compiler, which otherwise may loop over "distinct" lanes' values
+    auto uni = [](unsigned v) { return int(__builtin_amdgcn_readfirstlane(int(v))); };
+    auto bld = [&](const __amdgpu_buffer_rsrc_t& rs, unsigned voff, unsigned soff) -> float {
+        return __builtin_bit_cast(float,
+                                  __builtin_amdgcn_raw_buffer_load_b32(rs, int(voff), uni(soff), 0));
+    };
+    auto ldu = [&](int c, unsigned col, unsigned pl) -> float {
+        if constexpr (BUF)
+            return bld(c == 0 ? dU0 : (c == 1 ? dU1 : dU2), col * 4u, pl * 4u);
+        else
+            return E.u[c][pl + col];
+    };
+    auto ldn = [&](int c, unsigned col, unsigned pl) -> float {
+        if constexpr (BUF)
+            return bld(c == 0 ? dN0 : (c == 1 ? dN1 : dN2), col * 4u, pl * 4u);
+        else
+            return un[c][pl + col];
+    };
+    auto ldp = [&](unsigned col, unsigned pl) -> float {
+        if constexpr (BUF)
+            return bld(dP, col * 4u, pl * 4u);
+        else
+            return pp[pl + col];
+    };
+    auto stf = [&](int c, unsigned col, unsigned pl, float v) {
+        if constexpr (BUF)
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v),
+                                                  c == 0 ? dF0 : (c == 1 ? dF1 : dF2),
+                                                  int(col * 4u), uni(pl * 4u), 0);
+        else
+            fo[c][pl + col] = v;
+    };
     auto fetch = [&](int zz, MtPlane& P) {
         float (&r)[3][MT_LOADS] = P.u;
         if (ALLPER) {
@@ -240,11 +286,11 @@ __device__ __forceinline__ void momentum_tile(const VelField<float>& E, const fl
             for (int k = 0; k < MT_LOADS; ++k) {
                 if (PROJ && lpos[k] < 0) continue;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) r[c][k] = E.u[c][base + offxy[k]];
+                for (int c = 0; c < 3; ++c) r[c][k] = ldu(c, offxy[k], base);
                 if (PROJ) {
-                    P.p[k] = pp[base + offxy[k]];
-                    P.pxm[k] = pp[base + offxm[k]];
-                    P.pym[k] = pp[base + offym[k]];
+                    P.p[k] = ldp(offxy[k], base);
+                    P.pxm[k] = ldp(offxm[k], base);
+                    P.pym[k] = ldp(offym[k], base);
                 }
             }
         } else {
@@ -329,7 +375,7 @@ __device__ __forceinline__ void momentum_tile(const VelField<float>& E, const fl
     float ubn[3] = {0.f, 0.f, 0.f};
     if (CORR && !PROJ) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) ubn[c] = un[c][idl + plane * unsigned(z0)];
+        for (int c = 0; c < 3; ++c) ubn[c] = ldn(c, idl, plane * unsigned(z0));
     }
     fetch(z0 + 2, PR[2]);  // projected when its plane is first used
     if (!PROJ) fetch(min(z0 + 3, z1 + 1), PR[0]);
@@ -371,14 +417,15 @@ __device__ __forceinline__ void momentum_tile(const VelField<float>& E, const fl
         float (&Fzlo)[3] = Fz[flo];
         float (&Fzhi)[3] = Fz[fhi];
         const bool more = z + 1 < z1;
-        const unsigned id = unsigned(gx) + unsigned(g.n0) * unsigned(gy) + plane * unsigned(z);
+        const unsigned col = unsigned(gx) + unsigned(g.n0) * unsigned(gy);
+        const unsigned zpl = plane * unsigned(z);
         float ubase[3] = {0.f, 0.f, 0.f};
         if constexpr (PROJ) {
             if (more) fetch(z + 3, PR[r]);
             project(curP, below.p);
             if (CORR && inside) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) ubase[c] = un[c][id];
+                for (int c = 0; c < 3; ++c) ubase[c] = ldn(c, col, zpl);
             }
         } else {
 #pragma unroll
@@ -386,7 +433,7 @@ __device__ __forceinline__ void momentum_tile(const VelField<float>& E, const fl
             if (CORR) {
                 const unsigned zn = unsigned(min(z + 1, z1 - 1));
 #pragma unroll
-                for (int c = 0; c < 3; ++c) ubn[c] = un[c][idl + plane * zn];
+                for (int c = 0; c < 3; ++c) ubn[c] = ldn(c, idl, plane * zn);
                 // keep these loads ahead of the prefetch in issue order
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -456,7 +503,7 @@ __device__ __forceinline__ void momentum_tile(const VelField<float>& E, const fl
                     R -= Fzhi[c] - Fzlo[c];
                     v = CORR ? 0.5f * (ubase[c] + w0[c] + hdt * R) : w0[c] + hdt * R;
                 }
-                fo[c][id] = v;
+                stf(c, col, zpl, v);
             }
         }
         // plane z - 1 leaves the window, plane z + 2 enters its slot
@@ -483,21 +530,26 @@ __device__ __forceinline__ void momentum_tile(const VelField<float>& E, const fl
 // 80 for the periodic predictor (6 waves, three blocks per CU, no spills),
 // which keeps the two-plane lookahead from stretching the schedule; the
 // projecting corrector measured faster with the compiler's own choice.
-template <bool ALLPER, bool CORR>
+template <bool ALLPER, bool CORR, bool BUF>
 __global__ __launch_bounds__(MT_T) __attribute__((amdgpu_waves_per_eu(ALLPER && !CORR ? 6 : 4))) void k_momentum_tiled(
     VelField<float> E, const float* __restrict__ un0, const float* __restrict__ un1,
     const float* __restrict__ un2, float* __restrict__ f0, float* __restrict__ f1,
     float* __restrict__ f2, float nu, const double* __restrict__ dt_dev, TileMap tm) {
-    momentum_tile<ALLPER, CORR, false>(E, un0, un1, un2, f0, f1, f2, nu, dt_dev, tm, nullptr, 0.f);
+    momentum_tile<ALLPER, CORR, false, BUF>(E, un0, un1, un2, f0, f1, f2, nu, dt_dev, tm, nullptr,
+                                            0.f);
 }
 
+template <bool BUF>
 __global__ __launch_bounds__(MT_T) void k_momentum_tiled_proj(
     VelField<float> E, const float* __restrict__ un0, const float* __restrict__ un1,
     const float* __restrict__ un2, float* __restrict__ f0, float* __restrict__ f1,
     float* __restrict__ f2, float nu, const double* __restrict__ dt_dev, TileMap tm,
     const float* __restrict__ pp, float Lc) {
-    momentum_tile<true, true, true>(E, un0, un1, un2, f0, f1, f2, nu, dt_dev, tm, pp, Lc);
+    momentum_tile<true, true, true, BUF>(E, un0, un1, un2, f0, f1, f2, nu, dt_dev, tm, pp, Lc);
 }
+
+// Buffer descriptors address 32-bit byte offsets: arrays below 4 GiB.
+static bool momentum_buf(const Grid& g) { return cells(g) < (size_t(1) << 30); }
 
 // Outflow plane (upper x face): convective update d(uout)/dt = -U_x (uout -
 // u_x(n0-1)) in the same stage form, then a uniform shift making its total
@@ -1147,13 +1199,18 @@ wl_status ns_momentum(const VelField<T>& E, const T* const un[3], T* const f[3],
             // blocks per CU the kernel's registers allow (LDS allows 3): the
             // periodic predictor fits 80 VGPRs (6 waves per SIMD), the others 128
             const TileMap tm = tile_map(g, MT_X, MT_Y, momentum_zchunk(g, allper && !corr ? 3 : 2));
-#define WL_MT(AP, CR)                                                                          \
-    k_momentum_tiled<AP, CR><<<tm.nblocks, MT_T, 0, s>>>(E, un[0], un[1], un[2], f[0], f[1],     \
-                                                         f[2], nu, dt_dev, tm)
+#define WL_MT(AP, CR, BF)                                                                      \
+    k_momentum_tiled<AP, CR, BF><<<tm.nblocks, MT_T, 0, s>>>(E, un[0], un[1], un[2], f[0], f[1], \
+                                                             f[2], nu, dt_dev, tm)
+            const bool bf = momentum_buf(g);
             if (allper) {
-                if (corr) WL_MT(true, true); else WL_MT(true, false);
+                if (corr) {
+                    if (bf) WL_MT(true, true, true); else WL_MT(true, true, false);
+                } else {
+                    if (bf) WL_MT(true, false, true); else WL_MT(true, false, false);
+                }
             } else {
-                if (corr) WL_MT(false, true); else WL_MT(false, false);
+                if (corr) WL_MT(false, true, false); else WL_MT(false, false, false);
             }
 #undef WL_MT
             WL_CHECK_LAUNCH();
@@ -1183,8 +1240,12 @@ wl_status ns_momentum_proj(const VelField<float>& E, const float* const un[3], f
     }
     ProfScope ps(WL_PROF_MOMENTUM, s, cells(g));
     const TileMap tm = tile_map(g, MT_X, MT_Y, momentum_zchunk(g, 2));
-    k_momentum_tiled_proj<<<tm.nblocks, MT_T, 0, s>>>(E, un[0], un[1], un[2], f[0], f[1], f[2], nu,
-                                                      dt_dev, tm, p, Lc);
+    if (momentum_buf(g))
+        k_momentum_tiled_proj<true><<<tm.nblocks, MT_T, 0, s>>>(E, un[0], un[1], un[2], f[0], f[1],
+                                                                f[2], nu, dt_dev, tm, p, Lc);
+    else
+        k_momentum_tiled_proj<false><<<tm.nblocks, MT_T, 0, s>>>(E, un[0], un[1], un[2], f[0], f[1],
+                                                                 f[2], nu, dt_dev, tm, p, Lc);
     WL_CHECK_LAUNCH();
     return WL_OK;
 }
