@@ -770,7 +770,7 @@ __global__ __launch_bounds__(kBlock) void k_divergence(TileDev TL, VelField<T> V
 constexpr int DC_TX = 64, DC_TY = 8, DC_T = DC_TX * DC_TY;
 constexpr int DC_HX = DC_TX + 2, DC_HY = DC_TY + 2, DC_RING = DC_HX * DC_HY - DC_T;
 
-template <typename T>
+template <typename T, bool BUF>
 __global__ __launch_bounds__(DC_T) void k_div_check(TileMap tm, VelField<T> V, double c,
                                                     const double* __restrict__ dt_dev,
                                                     T* __restrict__ sigma,
@@ -814,25 +814,57 @@ __global__ __launch_bounds__(DC_T) void k_div_check(TileMap tm, VelField<T> V, d
     const T* __restrict__ uy = V.u[1];
     const T* __restrict__ uz = V.u[2];
     const T scale = T(1.0 / (c * *dt_dev));
+    // BUF (FP32, arrays below 4 GiB): loads and stores through buffer
+    // descriptors, the plane's byte offset uniform (scalar), the column's in a
+    // vector register; the plane offsets are uniform over the block, which
+    // readfirstlane tells the compiler
+    static_assert(!BUF || sizeof(T) == 4, "buffer addressing is for FP32 arrays");
+    const int nbytes = BUF ? int(unsigned(size_t(plane) * unsigned(g.n2) * 4u)) : 0;
+    auto rsrc = [&](const T* q) {
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(q), 0, nbytes, 0x00020000);
+    };
+    const auto dX = rsrc(ux), dY = rsrc(uy), dZ = rsrc(uz), dP = rsrc(p), dS = rsrc(sigma);
+    auto uni = [](unsigned v) { return int(__builtin_amdgcn_readfirstlane(int(v))); };
+    // value of array a (descriptor d) at column offset cl (may be negative:
+    // a wrapped neighbour) of plane w
+    auto ld = [&](const T* a, const __amdgpu_buffer_rsrc_t& d, int cl, int w) -> T {
+        if constexpr (BUF)
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(
+                                             d, cl * 4, uni(unsigned(w) * plane * 4u), 0));
+        else
+            return a[unsigned(int(unsigned(w) * plane) + cl)];
+    };
     auto wrap = [&](int q) {
         q %= g.n2;
         return q < 0 ? q + g.n2 : q;
     };
     auto next = [&](int w) { return w + 1 == g.n2 ? 0 : w + 1; };
-    // p rings indexed by plane (mod 4): own column planes k - 1 .. k + 2, the
-    // ring cell planes k .. k + 1; the loop is unrolled 4 times
+    // p rings indexed by plane (mod 4): own column and ring cell planes up
+    // to k + 2 (loaded two planes ahead); velocity rings: the faces of planes
+    // k and k + 1 (loaded one plane ahead); the loop is unrolled 4 times
     T pA[4] = {}, pB[4] = {};
+    T xl[4] = {}, xh[4] = {}, yl[4] = {}, yh[4] = {}, zh[4] = {};
+    const int iA = int(cA), iB = int(cB);
     int w = wrap(z0 - 1);
-    pA[3] = p[cA + unsigned(w) * plane];
+    pA[3] = ld(p, dP, iA, w);
     w = next(w);
-    const int wz0 = w;
-    pA[0] = p[cA + unsigned(w) * plane];
-    pB[0] = p[cB + unsigned(w) * plane];
+    int wk = w;  // wrapped plane k
+    pA[0] = ld(p, dP, iA, w);
+    pB[0] = ld(p, dP, iB, w);
     w = next(w);
-    pA[1] = p[cA + unsigned(w) * plane];
+    pA[1] = ld(p, dP, iA, w);
+    pB[1] = ld(p, dP, iB, w);
     int wp1 = w, wp2 = next(w);  // wrapped planes k + 1, k + 2
-    unsigned id = cA + unsigned(wz0) * plane;
-    T wlo = uz[id];
+    T wlo = ld(uz, dZ, iA, wk);
+    // x, y faces of plane k and the upper z face (plane k + 1) of the own cell
+    auto ldu = [&](int q, int wq, int wq1) {
+        xl[q] = ld(ux, dX, iA, wq);
+        xh[q] = ld(ux, dX, iA + dxp, wq);
+        yl[q] = ld(uy, dY, iA, wq);
+        yh[q] = ld(uy, dY, iA + dyp, wq);
+        zh[q] = ld(uz, dZ, iA, wq1);
+    };
+    ldu(0, wk, wp1);
     double sum = 0.0, sb2 = 0.0, sc = 0.0, sc2 = 0.0;
     int k = z0;
     auto step = [&](auto rc) {
@@ -840,19 +872,28 @@ __global__ __launch_bounds__(DC_T) void k_div_check(TileMap tm, VelField<T> V, d
         constexpr int im1 = (r + 3) % 4, ip1 = (r + 1) % 4, ip2 = (r + 2) % 4;
         T* S = sp[k & 1];
         S[hA] = pA[r];
-        if (hasB) S[hB] = pB[r];
+        // unconditional: a thread without a ring cell stores its own value
+        // again (hB = hA, cB = cA); a conditional store would pull the load
+        // of pB into its branch and wait for it there
+        S[hB] = pB[r];
         __syncthreads();
-        if (k + 1 < z1) {
-            pA[ip2] = p[cA + unsigned(wp2) * plane];
-            pB[ip1] = p[cB + unsigned(wp1) * plane];
-        }
-        const T xu = ux[id + dxp], yu = uy[id + dyp];
-        const T wup = uz[cA + unsigned(wp1) * plane];
-        T div = (xu - ux[id]) + (yu - uy[id]);
+        // unconditional (the chunk's last plane loads a valid plane it does
+        // not use): no branch around loads keeps the wait counts exact
+        ldu(ip1, wp1, wp2);
+        pA[ip2] = ld(p, dP, iA, wp2);
+        pB[ip2] = ld(p, dP, iB, wp2);
+        // issue the next planes' loads here, not after this plane's work
+        __builtin_amdgcn_sched_barrier(0);
+        const T wup = zh[r];
+        T div = (xh[r] - xl[r]) + (yh[r] - yl[r]);
         div += wup - wlo;
         wlo = wup;
         const T sg = div * scale;
-        sigma[id] = sg;
+        if constexpr (BUF)
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, sg), dS, iA * 4,
+                                                  uni(unsigned(wk) * plane * 4u), 0);
+        else
+            sigma[cA + unsigned(wk) * plane] = sg;
         const T Ax = jacobi_ax_uniform(pA[r], S[hA - 1], S[hA + 1], S[hA - DC_HX], S[hA + DC_HX],
                                        pA[im1], pA[ip1], Lp, true);
         const double cr = double(sg - Ax);
@@ -860,7 +901,7 @@ __global__ __launch_bounds__(DC_T) void k_div_check(TileMap tm, VelField<T> V, d
         sb2 += double(sg) * double(sg);
         sc += cr;
         sc2 += cr * cr;
-        id = cA + unsigned(wp1) * plane;
+        wk = wp1;
         wp1 = wp2;
         wp2 = next(wp2);
         ++k;
@@ -869,14 +910,21 @@ __global__ __launch_bounds__(DC_T) void k_div_check(TileMap tm, VelField<T> V, d
     using I1 = std::integral_constant<int, 1>;
     using I2 = std::integral_constant<int, 2>;
     using I3 = std::integral_constant<int, 3>;
-    while (k < z1) {
+    // whole groups of four planes without exits between them (an exit
+    // between two planes would let the compiler sink the next plane's loads
+    // behind it, up to their use), then the remainder
+    while (k + 4 <= z1) {
         step(I0{});
-        if (k >= z1) break;
         step(I1{});
-        if (k >= z1) break;
         step(I2{});
-        if (k >= z1) break;
         step(I3{});
+    }
+    if (k < z1) {
+        step(I0{});
+        if (k < z1) {
+            step(I1{});
+            if (k < z1) step(I2{});
+        }
     }
     // fixed-order workgroup sums: wave butterflies, then waves in order
     double v[4] = {sum, sb2, sc, sc2};
@@ -1291,7 +1339,12 @@ wl_status ns_divergence(const VelField<T>& V, const ProjCoeffs<T>& C, bool unif,
         }
         const TileMap tm = div_check_map(V.g);
         if (tm.nblocks > 0) {
-            k_div_check<T><<<tm.nblocks, DC_T, 0, s>>>(tm, V, c, dt_dev, sigma, partial, p_check, Lp);
+            if (sizeof(T) == 4 && cells(V.g) < (size_t(1) << 30))
+                k_div_check<T, sizeof(T) == 4><<<tm.nblocks, DC_T, 0, s>>>(tm, V, c, dt_dev, sigma,
+                                                                           partial, p_check, Lp);
+            else
+                k_div_check<T, false><<<tm.nblocks, DC_T, 0, s>>>(tm, V, c, dt_dev, sigma, partial,
+                                                                  p_check, Lp);
             if (nslots) *nslots = tm.nblocks;
         } else {
             k_divergence<T, true, true, true><<<ln.grid, ln.block, 0, s>>>(
