@@ -458,22 +458,29 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
         }
     }
     int s = s0p;
-    // one step; r = (s - s0p) mod R
-    auto step = [&](auto rc) {
+    // one step; r = (s - s0p) mod R; st: whether plane s - 1 gets its second
+    // sweep (not in the first two steps, whose s - 1 lies below the chunk)
+    auto step = [&](auto rc, auto st) {
         constexpr int r = decltype(rc)::value;
+        constexpr bool store = decltype(st)::value;
         constexpr int im1 = (r + R - 1) % R, i0 = r, ip1 = (r + 1) % R, im2 = (r + R - 2) % R;
         // consecutive steps alternate buffers (R is even)
         T* S0 = s0[r & 1];
         T* S1 = s1[r & 1];
         const T* S1m = s1[(r & 1) ^ 1];
         if (XM == XM_PROLONG) xC[i0] += pC[i0];
+        // Stores and loads are unconditional: a thread without a ring cell
+        // stores its own value again (B and C default to A), and the chunk's
+        // last steps load wrapped planes they do not use.  A branch around a
+        // load, or around the only use of a loaded value, makes the compiler
+        // wait for it there (or for everything in flight).
         if (XM != XM_ZERO) {
             S0[A.q] = xA[i0];
-            if (hasB) S0[B.q] = xB[i0];
-            if (hasC) S0[C.q] = xC[i0];
+            S0[B.q] = xB[i0];
+            S0[C.q] = xC[i0];
         }
         __syncthreads();
-        if (s + Dp <= z1) {
+        {
             constexpr int j = (r + 1 + Dp) % R;
             xA[j] = ld(A, wx);
             xB[j] = ld(B, wx);
@@ -493,33 +500,35 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
         yA[i0] = y;
         S1[hA] = y;
         if (hasB) S1[hB] = sweep1(S0, B.q, xB[i0], xB[im1], xB[ip1], rhs(rB[i0]));
-        if (s > z0)
+        if (store)
             xout[A.col + unsigned(s - 1) * plane] = sweep2(S1m, hA, yA[im1], yA[im2], y, rA[im1]);
         wx = next(wx);
         ++s;
     };
     using I0 = std::integral_constant<int, 0>;
-    using I1 = std::integral_constant<int, 1 % R>;
-    using I2 = std::integral_constant<int, 2 % R>;
-    using I3 = std::integral_constant<int, 3 % R>;
-    using I4 = std::integral_constant<int, 4 % R>;
-    using I5 = std::integral_constant<int, 5 % R>;
-    static_assert(R <= 6, "unrolled steps cover rings of up to 6 planes");
-    while (s <= z1) {
-        step(I0{});
-        if (s > z1) break;
-        step(I1{});
-        if (s > z1) break;
-        step(I2{});
-        if (s > z1) break;
-        step(I3{});
-        if (R > 4) {
-            if (s > z1) break;
-            step(I4{});
-        }
-        if (R > 5) {
-            if (s > z1) break;
-            step(I5{});
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    using Skip = std::false_type;
+    using Store = std::true_type;
+    static_assert(R == 4, "the unrolled steps below cover a ring of 4 planes");
+    // steps s = z0 - 1 .. z1 (at least two): the first two store nothing,
+    // then whole groups of four without exits between them (an exit between
+    // two steps would let the compiler sink the next step's loads behind it),
+    // then the remainder
+    step(I0{}, Skip{});
+    step(I1{}, Skip{});
+    while (s + 3 <= z1) {
+        step(I2{}, Store{});
+        step(I3{}, Store{});
+        step(I0{}, Store{});
+        step(I1{}, Store{});
+    }
+    if (s <= z1) {
+        step(I2{}, Store{});
+        if (s <= z1) {
+            step(I3{}, Store{});
+            if (s <= z1) step(I0{}, Store{});
         }
     }
 }
