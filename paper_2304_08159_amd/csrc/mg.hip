@@ -428,6 +428,7 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
     T pA[R] = {}, pB[R] = {}, pC[R] = {};
     const int s0p = z0 - 1;  // first step; ring slot of plane p is (p - s0p) mod R
     int wx;                  // wrapped plane of the next loads, s + 1 + Dp
+    int wxm;                 // the one before it (already loaded)
     {
         // every thread issues the same loads (B and C default to A), so that
         // waits on earlier loads can count them; planes past z1 + 1 that a
@@ -449,6 +450,7 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
             pB[k] = ldc(B, w);
             pC[k] = ldc(C, w);
         }
+        wxm = w;       // s0p + Dp
         wx = next(w);  // s0p + 1 + Dp
         if (XM == XM_PROLONG) {
             xA[R - 1] += pA[R - 1];
@@ -481,15 +483,18 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
         }
         __syncthreads();
         {
+            // plane s + 1 + Dp; the last step, which never uses it, repeats
+            // the previous step's plane (cache hits)
             constexpr int j = (r + 1 + Dp) % R;
-            xA[j] = ld(A, wx);
-            xB[j] = ld(B, wx);
-            rA[j] = ldb(A, wx);
-            rB[j] = ldb(B, wx);
-            xC[j] = ld(C, wx);
-            pA[j] = ldc(A, wx);
-            pB[j] = ldc(B, wx);
-            pC[j] = ldc(C, wx);
+            const int wl = s < z1 ? wx : wxm;
+            xA[j] = ld(A, wl);
+            xB[j] = ld(B, wl);
+            rA[j] = ldb(A, wl);
+            rB[j] = ldb(B, wl);
+            xC[j] = ld(C, wl);
+            pA[j] = ldc(A, wl);
+            pB[j] = ldc(B, wl);
+            pC[j] = ldc(C, wl);
         }
         if (XM == XM_PROLONG) {
             xA[ip1] += pA[ip1];
@@ -502,6 +507,7 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
         if (hasB) S1[hB] = sweep1(S0, B.q, xB[i0], xB[im1], xB[ip1], rhs(rB[i0]));
         if (store)
             xout[A.col + unsigned(s - 1) * plane] = sweep2(S1m, hA, yA[im1], yA[im2], y, rA[im1]);
+        wxm = wx;
         wx = next(wx);
         ++s;
     };

@@ -877,11 +877,13 @@ __global__ __launch_bounds__(DC_T) void k_div_check(TileMap tm, VelField<T> V, d
         // of pB into its branch and wait for it there
         S[hB] = pB[r];
         __syncthreads();
-        // unconditional (the chunk's last plane loads a valid plane it does
-        // not use): no branch around loads keeps the wait counts exact
-        ldu(ip1, wp1, wp2);
-        pA[ip2] = ld(p, dP, iA, wp2);
-        pB[ip2] = ld(p, dP, iB, wp2);
+        // unconditional: no branch around loads keeps the wait counts exact;
+        // the chunk's last plane repeats planes it already holds (cache hits)
+        // instead of fetching ones it never uses
+        const int wl1 = k + 1 < z1 ? wp1 : wk, wl2 = k + 1 < z1 ? wp2 : wp1;
+        ldu(ip1, wl1, wl2);
+        pA[ip2] = ld(p, dP, iA, wl2);
+        pB[ip2] = ld(p, dP, iB, wl2);
         // issue the next planes' loads here, not after this plane's work
         __builtin_amdgcn_sched_barrier(0);
         const T wup = zh[r];
