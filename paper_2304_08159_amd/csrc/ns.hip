@@ -12,6 +12,7 @@
 // BDIM kernel of half-width eps, Heun stages with projection factor c = 1 and
 // c = 1/2, CFL from the per-cell outflow velocity plus 2 d nu.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <type_traits>
@@ -1215,11 +1216,16 @@ int momentum_zchunk(const Grid& g, int per_cu) {
         return v > 0 ? v : 0;
     }();
     if (env) return env;
+    // CU count of the current device, queried once per device
+    static std::atomic<int> cus[64];
     int dev = 0, ncu = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        ncu <= 0)
-        ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) ncu = cus[dev].load();
+    if (ncu <= 0) {
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            ncu <= 0)
+            ncu = 256;
+        if (dev >= 0 && dev < 64) cus[dev].store(ncu);
+    }
     const long tiles = long((g.n0 + MT_X - 1) / MT_X) * long((g.n1 + MT_Y - 1) / MT_Y);
     const long want = long(per_cu) * ncu;
     const long nch = std::max(1L, (want + tiles - 1) / tiles);
