@@ -113,6 +113,24 @@ def test_tgv256_fp32_full_size_replay_parity():
     sim.close()
 
 
+@pytest.mark.parametrize("n", [(72, 20, 44), (72, 32, 48)])
+def test_periodic_ragged_tiles_and_chunks_fp32_replay_parity(n):
+    """Periodic FP32 3D grids whose x / y extents leave ragged momentum tiles
+    (72 = 64 + 8, 20 = 2 x 8 + 4) and, for n2 = 44, a short last z chunk
+    (5 x 8 + 4 planes): the tile and chunk edge paths of the
+    convection-diffusion kernels (the predictor's clamped two-plane
+    prefetch, the corrector's fused projection); (72, 32, 48) also runs
+    fused sweep pairs with 8-wide tiles on its fine level."""
+    import paper_2304_08159_amd as wl
+    u, v, w = W.periodic_modes3d(n, seed=7)
+    cfg = dict(n=n, bc_lo=[0] * 3, bc_hi=[0] * 3, U=(0.0, 0.0, 0.0), nu=0.02)
+    sim, osim = _make(cfg, wl.WL_FP32, 1e-5)
+    for i, a in enumerate((u, v, w)):
+        sim.set(wl.FIELD_U0 + i, to_device(a, 3, torch, torch.float32))
+    _replay(sim, osim, 3, 1e-5, 1e-5, f"ragged{n}")
+    sim.close()
+
+
 def test_tgv2d_fp64_free_running_matches_oracle():
     import paper_2304_08159_amd as wl
     N = 48

@@ -44,6 +44,28 @@ def tgv3d(N, Re=1600.0):
     return u, v, w, (N / (2.0 * math.pi)) / Re
 
 
+def periodic_modes3d(n, seed=2304, modes=4):
+    """Smooth triply periodic 3D velocity field on an n[0] x n[1] x n[2] grid of
+    any shape: per component a sum of `modes` Fourier modes (wave numbers 1..2
+    per direction, amplitudes N(0, 1), random phases; seeded), sampled at the
+    staggered face positions.  Not divergence-free (a step projects it)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for comp in range(3):
+        X = staggered_coords(n, comp)
+        f = np.zeros(tuple(n))
+        for _ in range(modes):
+            k = rng.integers(1, 3, size=3)
+            ph = rng.uniform(0.0, 2.0 * math.pi, size=3)
+            a = rng.standard_normal()
+            term = np.full(tuple(n), a)
+            for d in range(3):
+                term = term * np.cos(2.0 * math.pi * k[d] * X[d] / n[d] + ph[d])
+            f += term
+        out.append(f)
+    return out
+
+
 def tgv2d(N, nu_phys, t_phys=0.0):
     """2D Taylor-Green vortex on [0, 2 pi)^2 (closed-form solution at t_phys).
 
