@@ -246,8 +246,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the served request mix")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(multi-GPU sharding is a design note, not implemented)"}))
+        print(json.dumps({"error": "the library and this benchmark run on one GPU only; --gpus "
+                                   "must be 1 (multi-GPU sharding is designed, not implemented)"}))
         sys.exit(2)
 
     import numpy as np
