@@ -428,7 +428,7 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
     T pA[R] = {}, pB[R] = {}, pC[R] = {};
     const int s0p = z0 - 1;  // first step; ring slot of plane p is (p - s0p) mod R
     int wx;                  // wrapped plane of the next loads, s + 1 + Dp
-    int wxm;                 // the one before it (already loaded)
+    int wxm;                 // the last plane loaded
     {
         // every thread issues the same loads (B and C default to A), so that
         // waits on earlier loads can count them; planes past z1 + 1 that a
@@ -483,10 +483,10 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
         }
         __syncthreads();
         {
-            // plane s + 1 + Dp; the last step, which never uses it, repeats
-            // the previous step's plane (cache hits)
+            // plane s + 1 + Dp; the chunk's last steps, which never use it
+            // (past z1 + 1), repeat the last plane loaded (cache hits)
             constexpr int j = (r + 1 + Dp) % R;
-            const int wl = s < z1 ? wx : wxm;
+            const int wl = s + Dp <= z1 ? wx : wxm;
             xA[j] = ld(A, wl);
             xB[j] = ld(B, wl);
             rA[j] = ldb(A, wl);
@@ -507,7 +507,7 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
         if (hasB) S1[hB] = sweep1(S0, B.q, xB[i0], xB[im1], xB[ip1], rhs(rB[i0]));
         if (store)
             xout[A.col + unsigned(s - 1) * plane] = sweep2(S1m, hA, yA[im1], yA[im2], y, rA[im1]);
-        wxm = wx;
+        if (s + Dp <= z1) wxm = wx;
         wx = next(wx);
         ++s;
     };
@@ -517,25 +517,43 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
     using I3 = std::integral_constant<int, 3>;
     using Skip = std::false_type;
     using Store = std::true_type;
-    static_assert(R == 4, "the unrolled steps below cover a ring of 4 planes");
+    using I4 = std::integral_constant<int, 4 % R>;
+    using I5 = std::integral_constant<int, 5 % R>;
+    static_assert(R == 4 || R == 6, "the unrolled steps below cover rings of 4 or 6 planes");
     // steps s = z0 - 1 .. z1 (at least two): the first two store nothing,
-    // then whole groups of four without exits between them (an exit between
-    // two steps would let the compiler sink the next step's loads behind it),
+    // then whole groups of R without exits between them (an exit between two
+    // steps would let the compiler sink the next step's loads behind it),
     // then the remainder
     step(I0{}, Skip{});
     step(I1{}, Skip{});
-    while (s + 3 <= z1) {
-        step(I2{}, Store{});
-        step(I3{}, Store{});
-        step(I0{}, Store{});
-        step(I1{}, Store{});
-    }
-    if (s <= z1) {
-        step(I2{}, Store{});
-        if (s <= z1) {
+    if constexpr (R == 4) {
+        while (s + 3 <= z1) {
+            step(I2{}, Store{});
             step(I3{}, Store{});
-            if (s <= z1) step(I0{}, Store{});
+            step(I0{}, Store{});
+            step(I1{}, Store{});
         }
+        if (s <= z1) {
+            step(I2{}, Store{});
+            if (s <= z1) {
+                step(I3{}, Store{});
+                if (s <= z1) step(I0{}, Store{});
+            }
+        }
+    } else {
+        while (s + 5 <= z1) {
+            step(I2{}, Store{});
+            step(I3{}, Store{});
+            step(I4{}, Store{});
+            step(I5{}, Store{});
+            step(I0{}, Store{});
+            step(I1{}, Store{});
+        }
+        if (s <= z1) step(I2{}, Store{});
+        if (s <= z1) step(I3{}, Store{});
+        if (s <= z1) step(I4{}, Store{});
+        if (s <= z1) step(I5{}, Store{});
+        if (s <= z1) step(I0{}, Store{});
     }
 }
 
