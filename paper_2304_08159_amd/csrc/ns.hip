@@ -91,8 +91,10 @@ __global__ __launch_bounds__(kBlock) void k_momentum(TileDev TL, VelField<T> E, 
 // owns a 64 x 8 column of cells and marches through a chunk of z planes.  Planes z-1, z,
 // z+1 of all three components (with a two-cell x/y halo) sit in a 3-plane LDS
 // ring; the thread's own column of planes z-2 .. z+2 is kept in registers for
-// the z stencil.  Planes are fetched two ahead into alternating register sets
-// (the loop is unrolled by two so no copy waits on a load).  Every face flux
+// the z stencil.  Fetched planes sit in three register sets indexed by plane
+// modulo 3, the loop unrolled three times so that no copy waits on a load;
+// the non-projecting kernels fetch two planes ahead, the projecting corrector
+// one.  Every face flux
 // is evaluated once: a thread computes the lower x, y and z faces of its cell;
 // the tile's extra x column goes to wave 1 and its extra y row to wave 2, and
 // the upper x / y fluxes a cell needs are read from LDS, the upper z flux is
