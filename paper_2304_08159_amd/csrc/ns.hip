@@ -551,8 +551,15 @@ __global__ __launch_bounds__(MT_T) void k_momentum_tiled_proj(
     momentum_tile<true, true, true, BUF>(E, un0, un1, un2, f0, f1, f2, nu, dt_dev, tm, pp, Lc);
 }
 
-// Buffer descriptors address 32-bit byte offsets: arrays below 4 GiB.
-static bool momentum_buf(const Grid& g) { return cells(g) < (size_t(1) << 30); }
+// Buffer descriptors address 32-bit byte offsets: arrays below 4 GiB.  The
+// environment variable WL_GLOBAL_ADDRESSING=1 (read at every launch) selects
+// the global-address kernels on any grid, so that the path arrays of 4 GiB
+// and more take can be checked on small ones.
+static bool buffer_addressing(const Grid& g) {
+    const char* e = std::getenv("WL_GLOBAL_ADDRESSING");
+    return cells(g) < (size_t(1) << 30) && !(e && e[0] == '1');
+}
+static bool momentum_buf(const Grid& g) { return buffer_addressing(g); }
 
 // Outflow plane (upper x face): convective update d(uout)/dt = -U_x (uout -
 // u_x(n0-1)) in the same stage form, then a uniform shift making its total
@@ -1349,7 +1356,7 @@ wl_status ns_divergence(const VelField<T>& V, const ProjCoeffs<T>& C, bool unif,
         }
         const TileMap tm = div_check_map(V.g);
         if (tm.nblocks > 0) {
-            if (sizeof(T) == 4 && cells(V.g) < (size_t(1) << 30))
+            if (sizeof(T) == 4 && buffer_addressing(V.g))
                 k_div_check<T, sizeof(T) == 4><<<tm.nblocks, DC_T, 0, s>>>(tm, V, c, dt_dev, sigma,
                                                                            partial, p_check, Lp);
             else

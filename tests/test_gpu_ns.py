@@ -234,6 +234,28 @@ def test_fused_predictor_projection_is_bitwise_identical():
     assert torch.equal(xa, xb) and torch.equal(pa, pb)
 
 
+def test_global_address_kernels_match_buffer_addressed_ones(monkeypatch):
+    """Periodic FP32 convection-diffusion and divergence kernels address
+    arrays below 4 GiB through buffer descriptors and larger ones through
+    global addresses; both ways give the same bits (WL_GLOBAL_ADDRESSING=1
+    forces the global path on a small grid)."""
+    import paper_2304_08159_amd as wl
+    N = 64
+    u, v, w, nu = W.tgv3d(N, Re=1600.0)
+    runs = []
+    for mode in ("0", "1"):
+        monkeypatch.setenv("WL_GLOBAL_ADDRESSING", mode)
+        sim = wl.Sim((N, N, N), [0] * 3, [0] * 3, (0.0, 0.0, 0.0), nu, prec=wl.WL_FP32, tol=1e-5)
+        for i, a in enumerate((u, v, w)):
+            sim.set(wl.FIELD_U0 + i, to_device(a, 3, torch, torch.float32))
+        stats = [sim.step() for _ in range(3)]
+        runs.append((stats, sim.get_state().clone(), sim.pressure().clone()))
+        sim.close()
+    (sa, xa, pa), (sb, xb, pb) = runs
+    assert sa == sb
+    assert torch.equal(xa, xb) and torch.equal(pa, pb)
+
+
 def test_run_equals_repeated_steps_and_stops_at_t_end():
     """wl_run (many steps in one call) gives bitwise the state of the same
     number of wl_step calls, and stops once the time reaches t_end."""
