@@ -108,7 +108,7 @@ static unsigned pair_blocks() {
     static const unsigned v = [] {
         const char* e = std::getenv("WL_PAIR_BLOCKS");
         const long t = e ? std::atol(e) : 0;
-        return t > 0 ? unsigned(t) : 2048u;
+        return t > 0 ? unsigned(t) : 1024u;
     }();
     return v;
 }
