@@ -13,6 +13,7 @@ as a CPU baseline.
 """
 
 import argparse
+import ast
 import ctypes
 import json
 import math
@@ -124,6 +125,47 @@ def cpu_baseline(N, vcycles):
     return dict(value=N ** 3 / secs, unit="cell-steps/s", cores=1, kind="oracle",
                 sample=f"one Heun step of the 3D TGV at {N}^3 (FP64 NumPy oracle, "
                        f"V-cycles per solve {tuple(vcycles)} = the GPU's mean), {secs:.1f} s")
+
+
+def cpu_routines(N, vcycles):
+    """The oracle's Heun step at N^3 split into the routines the paper's Table 2
+    times (convdiff!, BDIM!, BC!, project!, CFL!): its functions are wrapped in
+    timers inside a child process and the step itself runs unchanged."""
+    code = (
+        "import sys, time; sys.path.insert(0, %r)\n"
+        "import workloads as W\n"
+        "from oracle import step as S\n"
+        "T = dict(convdiff=0.0, BDIM=0.0, BC=0.0, project=0.0, CFL=0.0)\n"
+        "def timer(key, f):\n"
+        "    def g(*a, **k):\n"
+        "        t = time.perf_counter(); r = f(*a, **k); T[key] += time.perf_counter() - t\n"
+        "        return r\n"
+        "    return g\n"
+        "M = S.momentum\n"
+        "M.rhs = timer('convdiff', M.rhs); M.bdim = timer('BDIM', M.bdim)\n"
+        "M.exit_flux_correct = timer('BC', M.exit_flux_correct)\n"
+        "S.Sim._set_boundary = timer('BC', S.Sim._set_boundary)\n"
+        "M.cfl_dt = timer('CFL', M.cfl_dt)\n"
+        "S.divergence = timer('project', S.divergence)\n"
+        "S.poisson.solve = timer('project', S.poisson.solve)\n"
+        "S.grad_update = timer('project', S.grad_update)\n"
+        "N = %d\n"
+        "u, v, w, nu = W.tgv3d(N)\n"
+        "sim = S.Sim((N, N, N), [0]*3, [0]*3, (0, 0, 0), nu, tol=1e-5)\n"
+        "sim.u = [u, v, w]\n"
+        "for k in T: T[k] = 0.0\n"
+        "t = time.perf_counter()\n"
+        "sim.step(force_vcycles=%r)\n"
+        "T['step'] = time.perf_counter() - t\n"
+        "print(repr(T))\n"
+    ) % (ROOT, N, tuple(vcycles))
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                       timeout=600)
+    if r.returncode != 0:
+        raise RuntimeError(r.stderr)
+    T = ast.literal_eval(r.stdout.strip().splitlines()[-1])
+    return {k: 1e3 * v for k, v in T.items()}
 
 
 def poisson_compare(torch, wl, W, n, radius=32.0, tol=1e-8, reps=3):
@@ -244,6 +286,8 @@ def main():
     ap.add_argument("--no-poisson", action="store_true",
                     help="skip the mixed-vs-FP64 Poisson comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the served request mix")
+    ap.add_argument("--routines", action="store_true",
+                    help="also split the oracle's step into convdiff/BDIM/BC/project/CFL (ms)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the library and this benchmark run on one GPU only; --gpus "
@@ -326,7 +370,7 @@ def main():
     step_b = step_bytes_per_cell(sum(vc_mean), "pair_fine" in kern) * cells
     step_gbs = step_b / (ms_step * 1e-3) / 1e9
     out = {
-        "metric": "cell-steps/s (3D TGV 256^3 FP32)",
+        "metric": f"cell-steps/s (3D TGV {N}^3 FP32)",
         "value": value,
         "unit": "cell-steps/s",
         "n_gpus": 1,
@@ -390,6 +434,8 @@ def main():
         vcr = [max(1, int(round(x))) for x in vc_mean]
         try:
             out["cpu_baseline"] = cpu_baseline(args.cpu_N, vcr)
+            if args.routines:
+                out["cpu_baseline"]["routines_ms"] = cpu_routines(args.cpu_N, vcr)
         except Exception as e:  # report, do not hide
             out["cpu_baseline"] = {"error": str(e)[:200]}
     print(json.dumps(out))
