@@ -16,13 +16,20 @@ are the contract:
                                  - (1 + cos(pi r))/(2 pi^2) ],  |r| < 1; else 0;
   * sphere / circle SDF d(x) = |x - c| - R (positive in the fluid), outward
     normal n = (x - c)/|x - c| (zero at the centre);
+  * torus (the donut of Sec. 3, 3D), axis along x through c, major radius R,
+    tube radius a: with rho the distance of x - c from the axis,
+    d(x) = sqrt((x-c)_x^2 + (rho - R)^2) - a, n = grad d (the tube's own
+    radial direction; zero on the tube's centre circle or the axis);
   * per face (component i, cell I), evaluated at the face centre:
       mu0_i = mu0(d),  (mu1 n)_ij = mu1(d) n_j,  L_i = mu0_i,
     and L_i = 0 on non-periodic domain-boundary faces (Neumann pressure).
 
 Pins: closed-form values of mu0/mu1 at 0 and +-eps, derivative identities
 mu0' = K, mu1' = -d K (finite differences), the excluded volume
-sum(1 - mu0) -> body volume, and the deep-inside / far-outside limits.
+sum(1 - mu0) -> body volume (sphere 4/3 pi R^3, torus 2 pi^2 R a^2), the
+deep-inside / far-outside limits, and for the torus SDF: exact distances at
+points whose nearest surface point is known, |n| = 1, n = finite-difference
+gradient of d.
 """
 
 import math
@@ -81,10 +88,33 @@ def sphere_sdf(X, centre, radius):
     return dist - radius, normal
 
 
+def torus_sdf(X, centre, radius, radius2):
+    """Signed distance and outward unit normal of a torus about the x axis."""
+    rel = [X[j] - centre[j] for j in range(3)]
+    rho = np.sqrt(rel[1] ** 2 + rel[2] ** 2)
+    qr = rho - radius
+    q = np.sqrt(rel[0] ** 2 + qr ** 2)
+    qs = np.where(q > 0.0, q, 1.0)
+    rs = np.where(rho > 0.0, rho, 1.0)
+    radial = np.where(q > 0.0, qr / qs, 0.0)
+    normal = [np.where(q > 0.0, rel[0] / qs, 0.0),
+              np.where(rho > 0.0, radial * rel[1] / rs, 0.0),
+              np.where(rho > 0.0, radial * rel[2] / rs, 0.0)]
+    return q - radius2, normal
+
+
+def body_sdf(X, body):
+    """SDF and normal of a body dict: a sphere/circle, or kind="torus" (radius2 = tube)."""
+    if body.get("kind", "sphere") == "torus":
+        return torus_sdf(X, body["centre"], body["radius"], body["radius2"])
+    return sphere_sdf(X, body["centre"], body["radius"])
+
+
 def measure(n, bc_lo, body=None, eps=1.0):
     """BDIM moments and fine-level Poisson coefficients.
 
-    body: None, or dict(centre=(..), radius=R).  Returns (mu0[i], mu1n[i][j], L[i])
+    body: None, dict(centre=(..), radius=R), or dict(kind="torus", centre, radius,
+    radius2).  Returns (mu0[i], mu1n[i][j], L[i])
     with every array shaped like the grid.  Without a body mu0 = 1, mu1n = 0.
     """
     d = len(n)
@@ -95,7 +125,7 @@ def measure(n, bc_lo, body=None, eps=1.0):
             a1 = [np.zeros(n) for _ in range(d)]
         else:
             X = face_centres(n, i)
-            dist, normal = sphere_sdf(X, body["centre"], body["radius"])
+            dist, normal = body_sdf(X, body)
             a0 = mu0(dist, eps)
             m = mu1(dist, eps)
             a1 = [m * normal[j] for j in range(d)]
@@ -113,9 +143,14 @@ def measure(n, bc_lo, body=None, eps=1.0):
 def body_volume_estimate(n, body, eps=1.0):
     """sum over cells of (1 - mu0(d_cell)): the excluded volume seen by BDIM."""
     X = cell_centres(n)
-    dist, _ = sphere_sdf(X, body["centre"], body["radius"])
+    dist, _ = body_sdf(X, body)
     return float(np.sum(1.0 - mu0(dist, eps)))
 
 
 def exact_body_volume(d, radius):
     return math.pi * radius ** 2 if d == 2 else 4.0 / 3.0 * math.pi * radius ** 3
+
+
+def exact_torus_volume(radius, radius2):
+    """Pappus: the tube's cross-section pi a^2 swept round a circle of length 2 pi R."""
+    return 2.0 * math.pi ** 2 * radius * radius2 ** 2

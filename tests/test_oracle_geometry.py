@@ -90,3 +90,54 @@ def test_measure_limits_and_boundary_faces():
     m = G.mu1(G.sphere_sdf(G.face_centres(n, 0), body["centre"], body["radius"])[0])
     nrm = np.sqrt(sum(mu1n[0][j] ** 2 for j in range(3)))
     np.testing.assert_allclose(nrm, np.abs(m), atol=1e-15)
+
+
+@pytest.mark.parametrize("a,R,n", [(3.0, 9.0, (16, 32, 32)), (6.0, 12.0, (24, 48, 48))])
+def test_torus_excluded_volume_matches_pappus(a, R, n):
+    # sum(1 - mu0) against 2 pi^2 R a^2; the BDIM smoothing of the curved tube
+    # leaves a relative excess of about 0.13 / a^2 (cell units)
+    body = dict(kind="torus", centre=(n[0] / 2 + 0.2, n[1] / 2 - 0.1, n[2] / 2 + 0.3),
+                radius=R, radius2=a)
+    est = G.body_volume_estimate(n, body)
+    exact = G.exact_torus_volume(R, a)
+    assert abs(est - exact) / exact < 0.2 / a ** 2 + 1e-3
+
+
+def test_torus_sdf_exact_points_and_normals():
+    c, R, a = (10.0, 20.0, 21.0), 8.0, 3.0
+    pts = {  # point relative to c: (distance, outward normal)
+        (0.0, 0.0, 0.0): (R - a, (0.0, 0.0, 0.0)),          # on the axis
+        (3.5, R, 0.0): (3.5 - a, (1.0, 0.0, 0.0)),          # beside the tube, along x
+        (0.0, 0.0, R + 5.0): (5.0 - a, (0.0, 0.0, 1.0)),    # outside the ring
+        (0.0, R - 2.0, 0.0): (2.0 - a, (0.0, -1.0, 0.0)),   # inside the tube, towards the hole
+        (0.0, -(R + 1.0), 0.0): (1.0 - a, (0.0, -1.0, 0.0)),
+    }
+    X = [np.array([c[j] + p[j] for p in pts]) for j in range(3)]
+    d, nrm = G.torus_sdf(X, c, R, a)
+    for m, (p, (dx, nx)) in enumerate(pts.items()):
+        assert abs(d[m] - dx) < 1e-12, p
+        assert np.allclose([nrm[j][m] for j in range(3)], nx, atol=1e-12), p
+
+
+def test_torus_normal_is_unit_gradient_of_distance():
+    rng = np.random.default_rng(7)
+    c, R, a = (0.0, 0.0, 0.0), 6.0, 2.0
+    X = [rng.uniform(-10.0, 10.0, 400) for _ in range(3)]
+    d, nrm = G.torus_sdf(X, c, R, a)
+    h = 1e-5
+    for j in range(3):
+        Xp = [x + (h if k == j else 0.0) for k, x in enumerate(X)]
+        Xm = [x - (h if k == j else 0.0) for k, x in enumerate(X)]
+        fd = (G.torus_sdf(Xp, c, R, a)[0] - G.torus_sdf(Xm, c, R, a)[0]) / (2 * h)
+        assert np.max(np.abs(fd - nrm[j])) < 1e-6
+    assert np.allclose(sum(x * x for x in nrm), 1.0)
+
+
+def test_measure_accepts_a_torus_and_limits_hold():
+    n = (16, 24, 24)
+    body = dict(kind="torus", centre=(8.0, 12.0, 12.0), radius=6.0, radius2=2.5)
+    mu0, mu1n, L = G.measure(n, [WALL] * 3, body)
+    # the tube's centre circle is deep inside, the axis far outside
+    assert mu0[0][8, 12 + 6, 12] == 0.0 and mu0[0][8, 12, 12] == 1.0
+    assert all(np.all((m >= 0.0) & (m <= 1.0)) for m in mu0)
+    assert np.all(L[0][0] == 0.0) and np.all(L[1][:, 0] == 0.0)
