@@ -244,6 +244,30 @@ def batch_compare(torch, wl, count=256, n=(128, 128), tol=1e-8):
                 speedup=t_seq / t_batch, vcycles_mean=sum(o[1] for o in out) / count)
 
 
+def donut_bench(wl, W, p=7, steps=50, warmup=5):
+    """Flow past a torus at N = (2^(p+1), 2^p, 2^p), Re = 1000 (FP32 fields and
+    V-cycles, pressure solves to an RMS divergence of 1e-5): the paper's
+    pressure-dominated workload.  Wall time per step after warm-up."""
+    import torch
+    cfg = W.donut_config(p)
+    sim = wl.Sim(cfg["n"], cfg["bc_lo"], cfg["bc_hi"], cfg["U"], cfg["nu"], body=cfg["body"],
+                 prec=wl.WL_FP32, tol=cfg["tol"], max_vcycles=100, cfl=cfg["cfl"])
+    sim.run(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = sim.run(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    sim.close()
+    cells = cfg["n"][0] * cfg["n"][1] * cfg["n"][2]
+    return dict(workload=f"torus in a {cfg['n'][0]}x{cfg['n'][1]}x{cfg['n'][2]} channel, "
+                         f"R={cfg['body']['radius']:g}, tube {cfg['body']['radius2']:g}, Re=1000, "
+                         f"FP32, solves to 1e-5", steps=len(st),
+                ms_per_step=1e3 * el / len(st), cell_steps_per_s=cells * len(st) / el,
+                vcycles_per_solve_mean=[sum(x["vcycles"][i] for x in st) / len(st)
+                                        for i in range(2)])
+
+
 def serving_bench(count=512, seed=2304, budget=16e9, slots=8):
     """Served mix: sizes uniform over 2D {64^2,128^2,256^2} and 3D {64^3,96^3,128^3},
     half Poisson solves, half 20-step NS runs with a body; HBM budget 16 GB.
@@ -286,6 +310,8 @@ def main():
     ap.add_argument("--no-poisson", action="store_true",
                     help="skip the mixed-vs-FP64 Poisson comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the served request mix")
+    ap.add_argument("--donut", action="store_true",
+                    help="also time flow past a torus at 256x128x128 (Re 1000)")
     ap.add_argument("--routines", action="store_true",
                     help="also split the oracle's step into convdiff/BDIM/BC/project/CFL (ms)")
     args = ap.parse_args()
@@ -427,6 +453,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_poisson:
         out["poisson_mixed_vs_fp64"] = poisson_compare(torch, wl, W, (N, N, N))
+    if args.donut:
+        out["donut"] = donut_bench(wl, W)
     if not args.no_serving:
         out["poisson_batch"] = batch_compare(torch, wl)
         out["serving"] = serving_bench()

@@ -79,12 +79,18 @@ typedef enum {
 
 /* Body given by its signed-distance function (Sec. 2): kind 0 = none,
  * kind 1 = sphere (circle when ndim = 2) of the given centre and radius in
- * cell units.  eps is the BDIM kernel half-width (<= 0 selects 1 cell). */
+ * cell units, kind 2 = torus (the donut of Sec. 3; ndim = 3 only) whose axis
+ * is the x direction through centre, with major radius `radius` (centre to
+ * the tube's centre line) and minor radius `radius2` (the tube's), so that
+ * d = sqrt(x^2 + (sqrt(y^2 + z^2) - radius)^2) - radius2 relative to centre.
+ * eps is the BDIM kernel half-width (<= 0 selects 1 cell).  radius2 is read
+ * for kind 2 only.  Drag and the adjoint step support kinds 0 and 1. */
 typedef struct {
     int kind;
     double centre[3];
     double radius;
     double eps;
+    double radius2;
 } wl_body;
 
 typedef struct {

@@ -62,7 +62,8 @@ class Sim:
             d.n[i], d.bc_lo[i], d.bc_hi[i], d.U[i] = nn[i], bl[i], bh[i], float(Uv[i])
         d.nu = float(nu)
         if body is not None:
-            d.body.kind = 1
+            d.body.kind = _lib.body_kind(body)
+            d.body.radius2 = float(body.get("radius2", 0.0))
             c = list(body["centre"]) + [0.0] * (3 - ndim)
             for i in range(3):
                 d.body.centre[i] = float(c[i])
@@ -249,7 +250,7 @@ def set_fused_sweeps(mode=1):
 
 
 def body_coeffs(n, periodic, body=None, prec=WL_FP32, device="cuda"):
-    """BDIM Poisson coefficients of a sphere/circle body: tensor (ndim, n2, n1, n0)."""
+    """BDIM Poisson coefficients of a sphere/circle or torus body: tensor (ndim, n2, n1, n0)."""
     torch = _torch()
     lib = load()
     n = tuple(int(m) for m in n)
@@ -258,7 +259,8 @@ def body_coeffs(n, periodic, body=None, prec=WL_FP32, device="cuda"):
     per = (ctypes.c_int * 3)(*([int(bool(p)) for p in periodic] + [0] * (3 - ndim)))
     b = _lib.Body()
     if body is not None:
-        b.kind = 1
+        b.kind = _lib.body_kind(body)
+        b.radius2 = float(body.get("radius2", 0.0))
         c = list(body["centre"]) + [0.0] * (3 - ndim)
         for i in range(3):
             b.centre[i] = float(c[i])

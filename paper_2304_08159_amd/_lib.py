@@ -47,7 +47,13 @@ class WlError(RuntimeError):
 
 class Body(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("centre", ctypes.c_double * 3),
-                ("radius", ctypes.c_double), ("eps", ctypes.c_double)]
+                ("radius", ctypes.c_double), ("eps", ctypes.c_double),
+                ("radius2", ctypes.c_double)]
+
+
+def body_kind(body):
+    """wl_body.kind of a body dict: {"kind": "torus"} selects 2, else a sphere (1)."""
+    return 2 if body.get("kind", "sphere") == "torus" else 1
 
 
 class SimDesc(ctypes.Structure):

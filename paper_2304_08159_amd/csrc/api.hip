@@ -57,8 +57,12 @@ static wl_status check_desc(const wl_sim_desc* desc, SimConfig* cfg) {
     if (d.max_vcycles <= 0) d.max_vcycles = 100;
     if (d.inner_vcycles <= 0) d.inner_vcycles = 3;
     if (!(d.tol >= 0.0)) return invalid("tol must be >= 0");
-    if (d.body.kind != 0 && d.body.kind != 1) return invalid("body.kind must be 0 or 1");
-    if (d.body.kind == 1 && !(d.body.radius > 0.0)) return invalid("body radius must be > 0");
+    if (d.body.kind < 0 || d.body.kind > 2) return invalid("body.kind must be 0, 1 or 2");
+    if (d.body.kind != 0 && !(d.body.radius > 0.0)) return invalid("body radius must be > 0");
+    if (d.body.kind == 2 && (d.ndim != 3 || !(d.body.radius2 > 0.0)))
+        return invalid("a torus needs ndim = 3 and radius2 > 0");
+    if (d.body.kind == 2 && d.tape_steps > 0)
+        return invalid("the adjoint step supports sphere bodies only");
     if (!(d.body.eps > 0.0)) d.body.eps = 1.0;
     if (d.mg_levels < 0 || d.mg_levels > kMaxLevels) return invalid("mg_levels out of range");
     if (d.tape_steps < 0 || d.tape_steps > 100000) return invalid("tape_steps out of range");
@@ -77,7 +81,7 @@ static wl_status check_desc(const wl_sim_desc* desc, SimConfig* cfg) {
             return invalid("coarsest multigrid level exceeds 1024 cells (request more levels)");
     }
     c.allper = c.g.per0 && c.g.per1 && (d.ndim == 2 || c.g.per2);
-    c.body = d.body.kind == 1;
+    c.body = d.body.kind != 0;
     c.unif = c.allper && !c.body;
     c.outflow = d.bc_hi[0] == WL_BC_OUTFLOW;
     c.N = cells(c.g);
@@ -291,7 +295,8 @@ static wl_status sim_init(SimImpl<T>& s, hipStream_t st) {
     BodyDev body{c.d.body.kind,
                  {c.d.body.centre[0], c.d.body.centre[1], c.d.body.centre[2]},
                  c.d.body.radius,
-                 c.d.body.eps};
+                 c.d.body.eps,
+                 c.d.body.radius2};
     MeasureOut<T> M;
     for (int i = 0; i < 3; ++i) {
         M.mu0[i] = s.mu0[i];
@@ -622,10 +627,12 @@ static wl_status sim_drag(SimImpl<T>& s, double* F, hipStream_t st) {
         *F = 0.0;
         return WL_OK;
     }
+    if (c.d.body.kind != 1) return invalid("drag supports sphere bodies only");
     const BodyDev body{c.d.body.kind,
                        {c.d.body.centre[0], c.d.body.centre[1], c.d.body.centre[2]},
                        c.d.body.radius,
-                       c.d.body.eps};
+                       c.d.body.eps,
+                       c.d.body.radius2};
     T* L[3] = {s.h.lev[0].L[0], s.h.lev[0].L[1], s.h.lev[0].L[2]};
     WL_TRY(drag_sums<T>(c.g, body, s.p, L, s.red.partial, st));
     WL_TRY(reduce_cols(s.red.partial, s.red.slots, 4, s.red.result + 8, st));
@@ -652,7 +659,8 @@ static wl_status sim_step_adjoint(SimImpl<T>& s, const void* ubar_in, double dra
     const BodyDev body{c.d.body.kind,
                        {c.d.body.centre[0], c.d.body.centre[1], c.d.body.centre[2]},
                        c.d.body.radius,
-                       c.d.body.eps};
+                       c.d.body.eps,
+                       c.d.body.radius2};
     T* L[3] = {s.h.lev[0].L[0], s.h.lev[0].L[1], s.h.lev[0].L[2]};
     const T* in = static_cast<const T*>(ubar_in);
     for (int i = 0; i < c.d.ndim; ++i)
@@ -1154,8 +1162,10 @@ wl_status wl_body_coeffs(const wl_body* body, int ndim, const int n[3], const in
     for (int i = 0; i < ndim; ++i)
         if (n[i] < 1) return invalid("grid dimensions must be positive");
     if (prec < 0 || prec > 2) return invalid("prec must be WL_FP32, WL_FP64 or WL_MIXED");
-    if (body->kind != 0 && body->kind != 1) return invalid("body.kind must be 0 or 1");
-    if (body->kind == 1 && !(body->radius > 0.0)) return invalid("body radius must be > 0");
+    if (body->kind < 0 || body->kind > 2) return invalid("body.kind must be 0, 1 or 2");
+    if (body->kind != 0 && !(body->radius > 0.0)) return invalid("body radius must be > 0");
+    if (body->kind == 2 && (ndim != 3 || !(body->radius2 > 0.0)))
+        return invalid("a torus needs ndim = 3 and radius2 > 0");
     const Grid g{n[0], n[1], n[2], periodic[0] != 0, periodic[1] != 0,
                  ndim == 3 && periodic[2] != 0, ndim};
     const int bclo[3] = {g.per0 ? WL_BC_PERIODIC : WL_BC_WALL, g.per1 ? WL_BC_PERIODIC : WL_BC_WALL,
@@ -1163,7 +1173,8 @@ wl_status wl_body_coeffs(const wl_body* body, int ndim, const int n[3], const in
     BodyDev bd{body->kind,
                {body->centre[0], body->centre[1], body->centre[2]},
                body->radius,
-               body->eps > 0.0 ? body->eps : 1.0};
+               body->eps > 0.0 ? body->eps : 1.0,
+               body->radius2};
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     const size_t N = cells(g);
     if (prec == WL_FP32) {

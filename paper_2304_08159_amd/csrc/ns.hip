@@ -1137,18 +1137,33 @@ __global__ __launch_bounds__(kBlock) void k_measure(TileDev TL, Grid g, BodyDev 
     const int bclo[3] = {bclo0, bclo1, bclo2};
     for (int c = 0; c < 3; ++c) {
         double m0 = 1.0, m1 = 0.0, nrm[3] = {0.0, 0.0, 0.0};
-        if (body.kind == 1 && c < g.ndim) {
+        if (body.kind != 0 && c < g.ndim) {
             double x[3] = {i + 0.5, j + 0.5, k + 0.5};
             x[c] -= 0.5;
-            double rel[3], r2 = 0.0;
-            for (int d = 0; d < g.ndim; ++d) {
-                rel[d] = x[d] - body.centre[d];
-                r2 += rel[d] * rel[d];
+            double rel[3] = {0.0, 0.0, 0.0}, sd;
+            for (int d = 0; d < g.ndim; ++d) rel[d] = x[d] - body.centre[d];
+            if (body.kind == 1) {
+                double r2 = 0.0;
+                for (int d = 0; d < g.ndim; ++d) r2 += rel[d] * rel[d];
+                const double dist = sqrt(r2);
+                sd = dist - body.radius;
+                if (dist > 0.0)
+                    for (int d = 0; d < g.ndim; ++d) nrm[d] = rel[d] / dist;
+            } else {
+                // torus about the x axis: distance to the tube's centre circle
+                // (in the plane through x and the axis) minus the tube radius
+                const double rho = sqrt(rel[1] * rel[1] + rel[2] * rel[2]);
+                const double qr = rho - body.radius;
+                const double q = sqrt(rel[0] * rel[0] + qr * qr);
+                sd = q - body.radius2;
+                if (q > 0.0) {
+                    nrm[0] = rel[0] / q;
+                    if (rho > 0.0) {
+                        nrm[1] = qr / q * rel[1] / rho;
+                        nrm[2] = qr / q * rel[2] / rho;
+                    }
+                }
             }
-            const double dist = sqrt(r2);
-            const double sd = dist - body.radius;
-            if (dist > 0.0)
-                for (int d = 0; d < g.ndim; ++d) nrm[d] = rel[d] / dist;
             const double r = sd / body.eps;
             if (r >= 1.0) {
                 m0 = 1.0;

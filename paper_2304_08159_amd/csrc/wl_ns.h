@@ -56,6 +56,7 @@ struct BodyDev {
     double centre[3];
     double radius;
     double eps;
+    double radius2;   // torus tube radius (kind 2)
 };
 
 template <typename T>

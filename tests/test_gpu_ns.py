@@ -281,3 +281,61 @@ def test_run_equals_repeated_steps_and_stops_at_t_end():
     (sa, xa, pa), (sb, xb, pb) = outs
     assert sa == sb
     assert torch.equal(xa, xb) and torch.equal(pa, pb)
+
+
+def test_torus_measure_and_coefficients_match_oracle():
+    import paper_2304_08159_amd as wl
+    cfg = W.donut_config(4)
+    n, body = cfg["n"], cfg["body"]
+    for prec, tol in ((wl.WL_FP32, 2e-7), (wl.WL_FP64, 1e-14)):
+        sim = wl.Sim(n, cfg["bc_lo"], cfg["bc_hi"], cfg["U"], cfg["nu"], body=body, prec=prec)
+        mu0, mu1n, L = G.measure(n, cfg["bc_lo"], body)
+        for i in range(3):
+            np.testing.assert_allclose(to_oracle(sim.get(wl.FIELD_L0 + i), 3), L[i], atol=tol)
+            np.testing.assert_allclose(to_oracle(sim.get(wl.FIELD_MU0_0 + i), 3), mu0[i], atol=tol)
+            for j in range(3):
+                np.testing.assert_allclose(to_oracle(sim.get(wl.FIELD_MU1N + 3 * i + j), 3),
+                                           mu1n[i][j], atol=tol)
+        sim.close()
+    Lc = wl.body_coeffs(n, (False,) * 3, body, prec=wl.WL_FP64)
+    Lo = G.measure(n, [3] * 3, body)[2]
+    for i in range(3):
+        np.testing.assert_allclose(to_oracle(Lc[i], 3), Lo[i], atol=1e-15)
+
+
+def test_donut_fp32_replay_parity():
+    """Velocity to 1e-5 relative L2; the pressure in the energy norm of the
+    Poisson operator, sqrt(-e.A e / -p.A p): cells the thin tube nearly closes
+    (mu0 of a few 1e-3) are coupled by tiny L, so their pressure is weakly
+    determined and FP32 rounding moves it without changing the velocity."""
+    import paper_2304_08159_amd as wl
+    from oracle import poisson as P
+    cfg = W.donut_config(5)          # 64 x 32 x 32, R = 8, tube radius 2
+    sim, osim = _make(cfg, wl.WL_FP32, cfg["tol"])
+    per = [False] * 3
+    for step in range(3):
+        un = [to_oracle(t, 3) for t in sim.velocity()]
+        pn = to_oracle(sim.pressure(), 3)
+        uo = plane_to_oracle(sim.get(4), 3)
+        st = sim.step()
+        osim.u, osim.p, osim.uout = un, pn, uo
+        osim.step(dt=st["dt"], force_vcycles=st["vcycles"])
+        ug = [to_oracle(t, 3) for t in sim.velocity()]
+        eu = math.sqrt(sum(np.sum((a - b) ** 2) for a, b in zip(ug, osim.u)) /
+                       sum(np.sum(b ** 2) for b in osim.u))
+        e = to_oracle(sim.pressure(), 3) - osim.p
+        ea = math.sqrt(np.sum(e * P.apply_A(osim.L, e, per)) /
+                       np.sum(osim.p * P.apply_A(osim.L, osim.p, per)))
+        print(f"donut step {step}: dt={st['dt']:.6f} vc={st['vcycles']} err_u={eu:.2e} "
+              f"err_p(A-norm)={ea:.2e}")
+        assert eu <= 1e-5 and ea <= 1e-5
+
+
+def test_torus_rejected_where_unsupported():
+    import paper_2304_08159_amd as wl
+    cfg = W.donut_config(4)
+    with pytest.raises(wl.WlError):
+        wl.Sim((32, 16), [1, 3], [2, 3], (1.0, 0.0), 0.01, body=cfg["body"])
+    sim = wl.Sim(cfg["n"], cfg["bc_lo"], cfg["bc_hi"], cfg["U"], cfg["nu"], body=cfg["body"])
+    with pytest.raises(wl.WlError):
+        sim.drag()

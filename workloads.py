@@ -109,6 +109,20 @@ def sphere_flow_config(offset=(0.0, 0.0, 0.0)):
                 body=dict(centre=c, radius=r), levels=0, tol=1e-8, cfl=0.5, steps=50)
 
 
+def donut_config(p=4, Re=1000.0):
+    """Flow past a torus (the donut of Sec. 3): N = (2^(p+1), 2^p, 2^p), inflow U = 1
+    in x, convective outflow, free-slip side walls.  The paper gives no radii: the
+    torus axis is the x direction through (N_x/4, N_y/2, N_z/2), major radius
+    R = N_y/4, tube radius R/4, Re on the major diameter 2R."""
+    m = 2 ** p
+    R = m / 4.0
+    return dict(n=(2 * m, m, m), bc_lo=[INFLOW, WALL, WALL], bc_hi=[OUTFLOW, WALL, WALL],
+                U=(1.0, 0.0, 0.0), nu=2.0 * R / Re,
+                body=dict(kind="torus", centre=(m / 2.0, m / 2.0, m / 2.0), radius=R,
+                          radius2=R / 4.0),
+                levels=0, tol=1e-5, cfl=0.5)
+
+
 def poisson_sphere_config(n=(256, 256, 256), radius=32.0):
     """Neumann box with a centred sphere (BDIM coefficients), N(0,1) RHS."""
     return dict(n=tuple(n), bc_lo=[WALL] * 3, bc_hi=[WALL] * 3,
