@@ -20,7 +20,18 @@ for smoothing, kernel-friendly non-ordered relaxation):
   * smoother: damped Jacobi x <- x + w (b - A x)/diag(A), w = 2d/(2d+1),
     inactive cells held at zero; nu1 = nu2 = 2 sweeps (symmetric V-cycle);
   * restriction: coarse RHS = sum of the 2^d child residuals;
-  * prolongation: piecewise-constant injection x(I) += x_c(parent(I));
+  * prolongation: cell-centred (bi/tri)linear interpolation, direction by
+    direction: a fine cell takes 3/4 of its parent and 1/4 of the parent's
+    neighbour on the fine cell's side (wrapped on periodic directions; at a
+    non-periodic domain face the missing neighbour is the parent itself, the
+    even reflection of the homogeneous Neumann condition).  With the sum
+    restriction (transfer orders 2 + 1 > 2, the order rule for a second-order
+    operator) the V-cycle contraction does not degrade with the grid size,
+    which Sec. 2's linear-time claim needs; piecewise-constant prolongation
+    (orders 1 + 1) measurably does (asymptotic rate 0.42 / 0.50 / 0.58 at
+    32^3 / 64^3 / 128^3 against 0.25 for all three with linear
+    interpolation).  The V-cycle is then not a symmetric operator; nothing
+    relies on that (the adjoint treats each pressure solve as exact);
   * coarse coefficient: half the sum of the 2^(d-1) fine faces a coarse face
     covers (the unit-spacing rediscretisation of the integrated operator);
   * coarsest level: minimum-norm least squares (a library routine);
@@ -94,10 +105,37 @@ def restrict(r):
     return r.reshape(shp).sum(axis=tuple(range(1, 2 * d, 2)))
 
 
-def prolong(xc):
+def prolong(xc, per):
+    """Cell-centred linear interpolation onto the grid twice as fine.
+
+    Along each direction, fine cells 2I and 2I+1 sit a quarter of a coarse
+    cell below and above the centre of coarse cell I, so linear interpolation
+    gives them 3/4 x_c(I) + 1/4 x_c(I-1) and 3/4 x_c(I) + 1/4 x_c(I+1).
+    Periodic directions wrap; on a non-periodic direction the outside
+    neighbour is x_c(I) itself (zero normal gradient).
+    """
     x = xc
     for ax in range(xc.ndim):
-        x = np.repeat(x, 2, axis=ax)
+        n = x.shape[ax]
+        lower = shift(x, ax, -1, per[ax])
+        upper = shift(x, ax, 1, per[ax])
+        if not per[ax]:
+            first = [slice(None)] * x.ndim
+            first[ax] = 0
+            last = [slice(None)] * x.ndim
+            last[ax] = n - 1
+            lower[tuple(first)] = x[tuple(first)]
+            upper[tuple(last)] = x[tuple(last)]
+        shp = list(x.shape)
+        shp[ax] = 2 * n
+        fine = np.empty(shp)
+        even = [slice(None)] * x.ndim
+        even[ax] = slice(0, None, 2)
+        odd = [slice(None)] * x.ndim
+        odd[ax] = slice(1, None, 2)
+        fine[tuple(even)] = 0.75 * x + 0.25 * lower
+        fine[tuple(odd)] = 0.75 * x + 0.25 * upper
+        x = fine
     return x
 
 
@@ -180,7 +218,7 @@ def vcycle(h, lev, x, b):
         x = jacobi(L, x, b, per, diag)
     r = b - apply_A(L, x, per)
     xc = vcycle(h, lev + 1, np.zeros(tuple(m // 2 for m in x.shape)), restrict(r))
-    x = x + prolong(xc)
+    x = x + prolong(xc, per)
     for _ in range(NU2):
         x = jacobi(L, x, b, per, diag)
     return x
