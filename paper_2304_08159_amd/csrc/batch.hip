@@ -3,7 +3,7 @@
 // over the request table) until it is empty; a request is solved entirely by
 // the workgroup that took it, with the same method as wl_poisson_solve
 // (Sec. 2's project!: matrix-free GMG, damped Jacobi, sum restriction,
-// piecewise-constant prolongation, coarse coefficients = 1/2 the covered fine
+// cell-centred linear prolongation, coarse coefficients = 1/2 the covered fine
 // faces, minimum-norm coarsest solve) in FP64.  Every reduction is a
 // fixed-order workgroup sum, so a request's result does not depend on which
 // workgroup solved it or on the rest of the batch.
@@ -47,7 +47,7 @@ __device__ void solve_one(const BatchReq& q, BatchRes& res, CoarseLds& S) {
     const int N = int(cells(F.g));
     for (int l = 1; l < nlev; ++l) wg_coarsen<double>(q.lev[l - 1], q.lev[l]);
     // right-hand side projected onto the active cells, mean-free there
-    const XAccess<double, XM_ZERO> Z{nullptr, nullptr, 0, 0};
+    const XAccess<double, XM_ZERO> Z{nullptr};
     const Coeffs<double> C = wg_coeffs(F);
     double sb = 0.0, cnt = 0.0;
     for (int c = threadIdx.x; c < N; c += blockDim.x) {
@@ -84,7 +84,7 @@ __device__ void solve_one(const BatchReq& q, BatchRes& res, CoarseLds& S) {
     }
     const double tol2 = q.tol * q.tol * b2;
     // first sweep of the first V-cycle, with the norm of the initial residual
-    double r2 = wg_sweep<double, XM_PLAIN>(F, XAccess<double, XM_PLAIN>{x, nullptr, 0, 0}, F.b, w,
+    double r2 = wg_sweep<double, XM_PLAIN>(F, XAccess<double, XM_PLAIN>{x}, F.b, w,
                                            x1, true, red);
     int k = 0;
     int status = WL_OK;
@@ -96,19 +96,16 @@ __device__ void solve_one(const BatchReq& q, BatchRes& res, CoarseLds& S) {
         if (nlev == 1) {
             coarse_cg_block<double>(F.g, C, 0, F.b, x, 1e-10, N + 64, S);
         } else {
-            wg_sweep<double, XM_PLAIN>(F, XAccess<double, XM_PLAIN>{x1, nullptr, 0, 0}, F.b, w, x,
-                                       false, red);
+            wg_sweep<double, XM_PLAIN>(F, XAccess<double, XM_PLAIN>{x1}, F.b, w, x, false, red);
             wg_restrict<double>(F, x, F.b, q.lev[1]);
             wg_vcycle_tail<double>(&q.lev[1], nlev - 1, w, 1e-10, S);
             const BatchLevel& C1 = q.lev[1];
-            wg_sweep<double, XM_PROLONG>(F, XAccess<double, XM_PROLONG>{x, C1.x[1], C1.g.n0,
-                                                                        C1.g.n1},
-                                         F.b, w, x1, false, red);
-            wg_sweep<double, XM_PLAIN>(F, XAccess<double, XM_PLAIN>{x1, nullptr, 0, 0}, F.b, w, x,
-                                       false, red);
+            wg_prolong<double>(F, C1, C1.x[1], x);
+            wg_sweep<double, XM_PLAIN>(F, XAccess<double, XM_PLAIN>{x}, F.b, w, x1, false, red);
+            wg_sweep<double, XM_PLAIN>(F, XAccess<double, XM_PLAIN>{x1}, F.b, w, x, false, red);
         }
         ++k;
-        r2 = wg_sweep<double, XM_PLAIN>(F, XAccess<double, XM_PLAIN>{x, nullptr, 0, 0}, F.b, w, x1,
+        r2 = wg_sweep<double, XM_PLAIN>(F, XAccess<double, XM_PLAIN>{x}, F.b, w, x1,
                                         true, red);
     }
     if (status == WL_OK && !isfinite(r2)) status = WL_ERR_NONFINITE;

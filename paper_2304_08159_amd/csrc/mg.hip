@@ -4,8 +4,8 @@
 //
 // One thread per cell; every kernel is an HBM sweep with neighbour reads
 // served by L1/L2.  Damped Jacobi (w = 2d/(2d+1), two pre- and two
-// post-sweeps), residual fused with sum-restriction, piecewise-constant
-// prolongation fused with the first post-sweep, a one-workgroup FP64 CG on
+// post-sweeps), residual fused with sum-restriction, cell-centred linear
+// prolongation added in place before the post-sweeps, a one-workgroup FP64 CG on
 // the coarsest level, and FP64 fixed-order reductions for the norms and the
 // active-set mean.  On uniform periodic 3D levels each pair of sweeps runs as
 // one LDS-tiled kernel that keeps the intermediate iterate on chip.
@@ -172,19 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth(TileDev TL, Grid g, XAccess<T
         const bool hxu = i < g.n0 - 1 || g.per0, hyu = j < g.n1 - 1 || g.per1;
         const int oxm = ixm - i, oxp = ixp - i;
         const int oym = (jym - j) * int(n0), oyp = (jyp - j) * int(n0);
-        // prolongation: parent columns of the cell and its x / y neighbours
-        const unsigned ncp = unsigned(X.nc0) * unsigned(X.nc1);
-        const unsigned pc = unsigned(i >> 1) + unsigned(X.nc0) * unsigned(j >> 1);
-        const unsigned pxm = unsigned(ixm >> 1) + unsigned(X.nc0) * unsigned(j >> 1);
-        const unsigned pxp = unsigned(ixp >> 1) + unsigned(X.nc0) * unsigned(j >> 1);
-        const unsigned pym = unsigned(i >> 1) + unsigned(X.nc0) * unsigned(jym >> 1);
-        const unsigned pyp = unsigned(i >> 1) + unsigned(X.nc0) * unsigned(jyp >> 1);
-        auto xv = [&](unsigned idx, unsigned pcol, int k) -> T {
-            if (XM == XM_ZERO) return T(0);
-            T v = X.x[idx];
-            if (XM == XM_PROLONG) v += X.xc[pcol + ncp * unsigned(k >> 1)];
-            return v;
-        };
+        auto xv = [&](unsigned idx) -> T { return XM == XM_ZERO ? T(0) : X.x[idx]; };
         const bool shift = bshift != nullptr;
         const T mean = shift ? T(*bshift) : T(0);
         // uniform level: one D, the same for every cell
@@ -195,10 +183,10 @@ __global__ __launch_bounds__(kBlock) void k_smooth(TileDev TL, Grid g, XAccess<T
         const int k0 = sp.z0;
         unsigned id = unsigned(i) + n0 * unsigned(j) + plane * unsigned(k0);
         // z neighbours of the first cell
-        T xzl = T(0), xI = xv(id, pc, k0), Lzl = T(0);
+        T xzl = T(0), xI = xv(id), Lzl = T(0);
         if (d3) {
             const int km = k0 > 0 ? k0 - 1 : (g.per2 ? g.n2 - 1 : k0);
-            xzl = xv(id + unsigned(km - k0) * plane, pc, km);
+            xzl = xv(id + unsigned(km - k0) * plane);
             if (!UNIF) Lzl = C.L2[id];
         }
         for (int k = k0; k < sp.z1; ++k, id += plane) {
@@ -211,10 +199,10 @@ __global__ __launch_bounds__(kBlock) void k_smooth(TileDev TL, Grid g, XAccess<T
                 hzu = k < g.n2 - 1 || g.per2;
                 ku = k < g.n2 - 1 ? k + 1 : (g.per2 ? 0 : k);
                 idu = id + unsigned(ku - k) * plane;
-                xzu = xv(idu, pc, ku);
+                xzu = xv(idu);
             }
-            const T xxl = xv(id + oxm, pxm, k), xxu = xv(id + oxp, pxp, k);
-            const T xyl = xv(id + oym, pym, k), xyu = xv(id + oyp, pyp, k);
+            const T xxl = xv(id + oxm), xxu = xv(id + oxp);
+            const T xyl = xv(id + oym), xyu = xv(id + oyp);
             T bv = b[id];
             T Lxl, Lxu, Lyl, Lyu;
             if (UNIF) {
@@ -311,21 +299,19 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
     const int i0 = tix * kPairTX, j0 = tiy * kPairTY;
     const int t = int(threadIdx.x);
     const unsigned n0 = unsigned(g.n0), plane = n0 * unsigned(g.n1);
-    const unsigned ncp = unsigned(X.nc0) * unsigned(X.nc1);
     const bool shift = bshift != nullptr;
     const T mean = shift ? T(*bshift) : T(0);
-    // A cell this thread handles: periodic grid column, parent column (for
-    // the prolongation) and position in the input-region LDS plane.
+    // A cell this thread handles: periodic grid column and position in the
+    // input-region LDS plane.
     struct Slot {
-        unsigned col, pcol;
+        unsigned col;
         int q;
     };
     auto slot = [&](int gx, int gy) -> Slot {
         int i = i0 + gx - 2, j = j0 + gy - 2;
         i = i < 0 ? i + g.n0 : (i >= g.n0 ? i - g.n0 : i);
         j = j < 0 ? j + g.n1 : (j >= g.n1 ? j - g.n1 : j);
-        return Slot{unsigned(i) + n0 * unsigned(j),
-                    unsigned(i >> 1) + unsigned(X.nc0) * unsigned(j >> 1), gy * kPairGX + gx};
+        return Slot{unsigned(i) + n0 * unsigned(j), gy * kPairGX + gx};
     };
     // A: the thread's own tile cell; B: a cell of the first-sweep ring (the
     // first kPairRing1 threads); C: a cell of the input ring (the last
@@ -349,19 +335,15 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
         C = slot(gx, gy);
     }
     // w: a plane index already wrapped into [0, n2)
-    // input = fine part (+ coarse part for the prolongation), loaded apart
-    // and added when first used so that the add does not wait on the loads;
     // plane bases are workgroup-uniform, the per-thread offsets fixed
     // FP32: buffer loads with the plane offset in a scalar register and the
     // thread's fixed column offset in a vector register (no per-load address
     // arithmetic; the descriptors bound each array)
     const unsigned bytes = unsigned(cells(g) * sizeof(T));
-    const unsigned cbytes = unsigned(size_t(ncp) * unsigned(g.n2 > 1 ? (g.n2 + 1) / 2 : 1) * sizeof(T));
     auto rsrc = [](const T* p, unsigned nbytes) {
         return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p), 0, int(nbytes), 0x00020000);
     };
     const auto dX = rsrc(XM == XM_ZERO ? b : X.x, bytes);
-    const auto dC = rsrc(XM == XM_PROLONG ? X.xc : b, XM == XM_PROLONG ? cbytes : bytes);
     const auto dB = rsrc(b, bytes);
     auto at = [&](const T* base, const __amdgpu_buffer_rsrc_t& r, unsigned elem,
                   unsigned off) -> T {
@@ -373,9 +355,6 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
     };
     auto ld = [&](const Slot& S, int w) -> T {
         return XM == XM_ZERO ? T(0) : at(X.x, dX, unsigned(w) * plane, S.col);
-    };
-    auto ldc = [&](const Slot& S, int w) -> T {
-        return XM == XM_PROLONG ? at(X.xc, dC, ncp * unsigned(w >> 1), S.pcol) : T(0);
     };
     auto ldb = [&](const Slot& S, int w) -> T { return at(b, dB, unsigned(w) * plane, S.col); };
     auto wrap = [&](int p) {
@@ -419,13 +398,10 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
     //           plane s - 1 for the second sweep)
     //   xC:     input of slot C at plane s
     //   yA:     A's first-sweep values (planes s - 2 .. s)
-    //   pA, pB, pC: coarse parts of the prolongated inputs, added into xA,
-    //           xB when a plane becomes s + 1 and into xC at plane s
     constexpr int Dp = kPairDepth;
     constexpr int R = Dp + 3;
     static_assert(R % 2 == 0, "the LDS buffers alternate with the ring index");
     T xA[R] = {}, xB[R] = {}, rA[R] = {}, rB[R] = {}, xC[R] = {}, yA[R] = {};
-    T pA[R] = {}, pB[R] = {}, pC[R] = {};
     const int s0p = z0 - 1;  // first step; ring slot of plane p is (p - s0p) mod R
     int wx;                  // wrapped plane of the next loads, s + 1 + Dp
     int wxm;                 // the last plane loaded
@@ -436,8 +412,6 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
         int w = wrap(s0p - 1);
         xA[R - 1] = ld(A, w);
         xB[R - 1] = ld(B, w);
-        pA[R - 1] = ldc(A, w);
-        pB[R - 1] = ldc(B, w);
 #pragma unroll
         for (int k = 0; k <= Dp; ++k) {
             w = next(w);  // s0p + k
@@ -446,18 +420,9 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
             rA[k] = ldb(A, w);
             rB[k] = ldb(B, w);
             xC[k] = ld(C, w);
-            pA[k] = ldc(A, w);
-            pB[k] = ldc(B, w);
-            pC[k] = ldc(C, w);
         }
         wxm = w;       // s0p + Dp
         wx = next(w);  // s0p + 1 + Dp
-        if (XM == XM_PROLONG) {
-            xA[R - 1] += pA[R - 1];
-            xB[R - 1] += pB[R - 1];
-            xA[0] += pA[0];
-            xB[0] += pB[0];
-        }
     }
     int s = s0p;
     // one step; r = (s - s0p) mod R; st: whether plane s - 1 gets its second
@@ -470,7 +435,6 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
         T* S0 = s0[r & 1];
         T* S1 = s1[r & 1];
         const T* S1m = s1[(r & 1) ^ 1];
-        if (XM == XM_PROLONG) xC[i0] += pC[i0];
         // Stores and loads are unconditional: a thread without a ring cell
         // stores its own value again (B and C default to A), and the chunk's
         // last steps load wrapped planes they do not use.  A branch around a
@@ -492,13 +456,6 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
             rA[j] = ldb(A, wl);
             rB[j] = ldb(B, wl);
             xC[j] = ld(C, wl);
-            pA[j] = ldc(A, wl);
-            pB[j] = ldc(B, wl);
-            pC[j] = ldc(C, wl);
-        }
-        if (XM == XM_PROLONG) {
-            xA[ip1] += pA[ip1];
-            xB[ip1] += pB[ip1];
         }
         rA[i0] = rhs(rA[i0]);
         const T y = sweep1(S0, A.q, xA[i0], xA[im1], xA[ip1], rA[i0]);
@@ -555,6 +512,23 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
         if (s <= z1) step(I5{}, Store{});
         if (s <= z1) step(I0{}, Store{});
     }
+}
+
+// x += P xc: the coarse correction interpolated linearly onto the fine
+// level (prolong_at: 3/4 parent + 1/4 neighbour per direction, wrapped on
+// periodic directions, reflected at domain faces).  In place: a cell reads
+// only its own x and coarse values.  The thread walks its (i, j) column up
+// the z chunk; the 2^d coarse values a cell reads are shared with its
+// neighbours and come from L1 / L2 (the coarse level is 1/2^d the size).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong(TileDev TL, Grid g, Grid gc,
+                                                    const T* __restrict__ xc, T* __restrict__ x) {
+    const Span sp = tile_span(TL, g.n0, g.n1, g.n2);
+    if (sp.i >= g.n0 || sp.j >= g.n1) return;
+    const size_t plane = size_t(g.n0) * size_t(g.n1);
+    size_t id = size_t(sp.i) + size_t(g.n0) * size_t(sp.j) + plane * size_t(sp.z0);
+    for (int k = sp.z0; k < sp.z1; ++k, id += plane)
+        x[id] += prolong_at<T>(g, gc, xc, sp.i, sp.j, k);
 }
 
 // Coarse right-hand side = sum of the 2^d child residuals r = b - A x.  The
@@ -672,7 +646,7 @@ __global__ __launch_bounds__(kBlock) void k_sum_active(TileDev TL, Grid g, Coeff
     double s = 0.0;
     if (i < g.n0 && j < g.n1) {
         for (int k = sp.z0; k < sp.z1; ++k) {
-        XAccess<T, XM_ZERO> X{nullptr, nullptr, 0, 0};
+        XAccess<T, XM_ZERO> X{nullptr};
         T xI, Ax, D;
         apply_row<T, XM_ZERO, UNIF>(g, X, C, i, j, k, xI, Ax, D);
         if (D > T(0)) s += v ? double(v[cid(g, i, j, k)]) : 1.0;
@@ -976,12 +950,12 @@ static T uniform_wd(const Level<T>& L, T omega) {
 }
 
 template <typename T, int XM, bool NORM, bool FIRST>
-static wl_status smooth(const Level<T>& L, const T* xin, const T* xc, const Grid* gc,
-                        const T* b, T omega, T* xout, double* partial, const double* bshift,
-                        hipStream_t s, int prof = -1, T* bproj = nullptr) {
+static wl_status smooth(const Level<T>& L, const T* xin, const T* b, T omega, T* xout,
+                        double* partial, const double* bshift, hipStream_t s, int prof = -1,
+                        T* bproj = nullptr) {
     const Launch ln = launch_for(L.g.n0, L.g.n1, L.g.n2);
     ProfScope ps(prof, s, cells(L.g));
-    XAccess<T, XM> X{xin, xc, gc ? gc->n0 : 0, gc ? gc->n1 : 0};
+    XAccess<T, XM> X{xin};
     if (L.uniform)
         k_smooth<T, XM, true, NORM, FIRST><<<ln.grid, ln.block, 0, s>>>(ln.td, 
             L.g, X, coeffs_of(L), b, uniform_wd(L, omega), xout, partial, bshift, bproj);
@@ -1028,18 +1002,17 @@ static PairTile pair_tile(const Grid& g) {
     return p;
 }
 
-// xout = S(S(xin)) (XM_ZERO: from zero; XM_PROLONG: from xin plus the
-// piecewise-constant prolongation of xc).  xout must not alias the inputs.
+// xout = S(S(xin)) (XM_ZERO: from zero).  xout must not alias the inputs.
 template <typename T, int XM>
-static wl_status pair(const Level<T>& L, const T* xin, const T* xc, const Grid* gc, const T* b,
-                      T omega, T* xout, const double* bshift, hipStream_t s, int prof = -1) {
-    if (xout == xin || xout == xc || xout == b) {
+static wl_status pair(const Level<T>& L, const T* xin, const T* b, T omega, T* xout,
+                      const double* bshift, hipStream_t s, int prof = -1) {
+    if (xout == xin || xout == b) {
         set_error("internal: fused sweep pair output aliases an input");
         return WL_ERR_INVALID_ARG;
     }
     const PairTile P = pair_tile(L.g);
     ProfScope ps(prof, s, cells(L.g));
-    XAccess<T, XM> X{xin, xc, gc ? gc->n0 : 0, gc ? gc->n1 : 0};
+    XAccess<T, XM> X{xin};
     const T wd = uniform_wd(L, omega);
 #define WL_PAIR(TX)                                                                              \
     k_smooth_pair<T, XM, TX><<<P.nb, PairShape<TX>::T, 0, s>>>(P, L.g, X, L.Lc, b, wd, xout, bshift)
@@ -1053,6 +1026,16 @@ static wl_status pair(const Level<T>& L, const T* xin, const T* xc, const Grid* 
             return WL_ERR_INVALID_ARG;
     }
 #undef WL_PAIR
+    WL_CHECK_LAUNCH();
+    return WL_OK;
+}
+
+template <typename T>
+static wl_status prolong(const Level<T>& L, const Level<T>& C, T* x, hipStream_t s,
+                         int prof = -1) {
+    const Launch ln = launch_for(L.g.n0, L.g.n1, L.g.n2);
+    ProfScope ps(prof, s, cells(L.g));
+    k_prolong<T><<<ln.grid, ln.block, 0, s>>>(ln.td, L.g, C.g, C.x[1], x);
     WL_CHECK_LAUNCH();
     return WL_OK;
 }
@@ -1077,7 +1060,7 @@ static wl_status resid_restrict(const Level<T>& L, const T* x, const T* b, const
                                 Level<T>& C, hipStream_t s, int prof = -1) {
     const Launch ln = launch_pairs(L.g);
     ProfScope ps(prof, s, cells(L.g));
-    XAccess<T, XM_PLAIN> X{x, nullptr, 0, 0};
+    XAccess<T, XM_PLAIN> X{x};
     if (L.uniform)
         k_resid_restrict<T, true><<<ln.grid, ln.block, 0, s>>>(ln.td, L.g, C.g, X, coeffs_of(L), b, bshift,
                                                                C.b);
@@ -1161,29 +1144,29 @@ static wl_status pre_smooth(const Hierarchy<T>& h, const Level<T>& L, Pre mode, 
     const T w = T(h.omega);
     if (mode != Pre::Half && pair_ok(h, L)) {
         if (mode == Pre::Zero)
-            WL_TRY((pair<T, XM_ZERO>(L, nullptr, nullptr, nullptr, b, w, other, bs, s,
+            WL_TRY((pair<T, XM_ZERO>(L, nullptr, b, w, other, bs, s,
                                      fine ? WL_PROF_PAIR_FINE : -1)));
         else
-            WL_TRY((pair<T, XM_PLAIN>(L, home, nullptr, nullptr, b, w, other, bs, s,
+            WL_TRY((pair<T, XM_PLAIN>(L, home, b, w, other, bs, s,
                                       fine ? WL_PROF_PAIR_FINE : -1)));
         *out = other;
         return WL_OK;
     }
     if (mode == Pre::Zero)
-        WL_TRY((smooth<T, XM_ZERO, false, false>(L, nullptr, nullptr, nullptr, b, w, other, nullptr,
+        WL_TRY((smooth<T, XM_ZERO, false, false>(L, nullptr, b, w, other, nullptr,
                                                  bs, s)));
     else if (mode == Pre::Full)
-        WL_TRY((smooth<T, XM_PLAIN, false, false>(L, home, nullptr, nullptr, b, w, other, nullptr,
+        WL_TRY((smooth<T, XM_PLAIN, false, false>(L, home, b, w, other, nullptr,
                                                   bs, s)));
-    WL_TRY((smooth<T, XM_PLAIN, false, false>(L, other, nullptr, nullptr, b, w, home, nullptr, bs, s,
+    WL_TRY((smooth<T, XM_PLAIN, false, false>(L, other, b, w, home, nullptr, bs, s,
                                               fine ? WL_PROF_SMOOTH_FINE : -1)));
     *out = home;
     return WL_OK;
 }
 
-// Post-smoothing of one level: the coarse correction C.x[1] prolongated onto
-// the pre-smoothed iterate `pre`, fused with the first of two sweeps; the
-// result lands in home.
+// Post-smoothing of one level: the coarse correction C.x[1] interpolated onto
+// the pre-smoothed iterate `pre` (in place), then two sweeps; the result
+// lands in home.
 template <typename T>
 static wl_status post_smooth(const Hierarchy<T>& h, const Level<T>& L, const T* pre, T* home,
                              T* other, const Level<T>& C, const T* b, const double* bs,
@@ -1195,12 +1178,14 @@ static wl_status post_smooth(const Hierarchy<T>& h, const Level<T>& L, const T* 
             set_error("internal: unfused post-smoothing after a fused pre-smoothing");
             return WL_ERR_INVALID_ARG;
         }
-        return pair<T, XM_PROLONG>(L, other, C.x[1], &C.g, b, w, home, bs, s,
-                                   fine ? WL_PROF_PAIR_PROLONG_FINE : -1);
+        WL_TRY(prolong(L, C, other, s, fine ? WL_PROF_PROLONG_FINE : -1));
+        return pair<T, XM_PLAIN>(L, other, b, w, home, bs, s,
+                                 fine ? WL_PROF_PAIR_PROLONG_FINE : -1);
     }
-    WL_TRY((smooth<T, XM_PROLONG, false, false>(L, home, C.x[1], &C.g, b, w, other, nullptr, bs, s,
-                                                fine ? WL_PROF_PROLONG_FINE : -1)));
-    return smooth<T, XM_PLAIN, false, false>(L, other, nullptr, nullptr, b, w, home, nullptr, bs, s,
+    WL_TRY(prolong(L, C, home, s, fine ? WL_PROF_PROLONG_FINE : -1));
+    WL_TRY((smooth<T, XM_PLAIN, false, false>(L, home, b, w, other, nullptr, bs, s,
+                                              fine ? WL_PROF_SMOOTH_FINE : -1)));
+    return smooth<T, XM_PLAIN, false, false>(L, other, b, w, home, nullptr, bs, s,
                                              fine ? WL_PROF_SMOOTH_FINE : -1);
 }
 
@@ -1317,7 +1302,7 @@ wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, d
         // first check: ||r0|| and ||b - mean||.  Every fine-level sweep
         // removes the mean of b on the fly; only a one-level hierarchy (whose
         // coarse solve reads F.b) stores the projected copy.
-        WL_TRY((smooth<T, XM_PLAIN, true, true>(F, x, nullptr, nullptr, b, w, xnext, red.partial,
+        WL_TRY((smooth<T, XM_PLAIN, true, true>(F, x, b, w, xnext, red.partial,
                                                 bshift, s, -1, h.nlev == 1 ? F.b : nullptr)));
         WL_TRY(reduce<T>(red, ln.nblocks(), 2, 1.0, red.result, s, post));
     }
@@ -1350,7 +1335,7 @@ wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, d
     // one V-cycle and the residual norms it leaves (replayed as a graph)
     auto body = [&](hipStream_t q) -> wl_status {
         WL_TRY(vcycle_rest(h, fused ? Pre::Full : Pre::Half, b, bshift, q));
-        WL_TRY((smooth<T, XM_PLAIN, true, false>(F, x, nullptr, nullptr, b, w, xnext, red.partial,
+        WL_TRY((smooth<T, XM_PLAIN, true, false>(F, x, b, w, xnext, red.partial,
                                                  bshift, q,
                                                  fused ? WL_PROF_NORM_FINE : WL_PROF_SMOOTH_NORM)));
         return reduce<T>(red, ln.nblocks(), 2, 1.0, red.result, q, post);
@@ -1409,7 +1394,7 @@ wl_status mg_solve_mixed(Hierarchy<float>& h32, const Mixed64& m, Reduce& red, d
     MailboxPost post;
     WL_TRY(mailbox_post_args(red, 0, 2, s, &post));
     auto resid = [&](hipStream_t q) -> wl_status {
-        XAccess<double, XM_PLAIN> X{x, nullptr, 0, 0};
+        XAccess<double, XM_PLAIN> X{x};
         k_resid64<<<ln.grid, ln.block, 0, q>>>(ln.td, g, X, C64, b, red.result + 5, F.b, red.partial);
         WL_CHECK_LAUNCH();
         return reduce<double>(red, ln.nblocks(), 2, 1.0, red.result, q, post);

@@ -40,24 +40,58 @@ __device__ __forceinline__ int nb_up(int c, int n, int per) {
     return c < n - 1 ? c + 1 : (per ? 0 : c);
 }
 
-// How a smoother reads the iterate: the stored x, zero (first sweep on a
-// coarse level), or x plus the piecewise-constant prolongation of the
-// coarse correction xc.
-enum { XM_PLAIN = 0, XM_ZERO = 1, XM_PROLONG = 2 };
+// How a smoother reads the iterate: the stored x, or zero (first sweep on a
+// coarse level).
+enum { XM_PLAIN = 0, XM_ZERO = 1 };
 
 template <typename T, int XM>
 struct XAccess {
     const T* __restrict__ x;
-    const T* __restrict__ xc;
-    int nc0, nc1;
     __device__ __forceinline__ T operator()(const Grid& g, int i, int j, int k) const {
         if (XM == XM_ZERO) return T(0);
-        T v = x[cid(g, i, j, k)];
-        if (XM == XM_PROLONG)
-            v += xc[size_t(i >> 1) + size_t(nc0) * (size_t(j >> 1) + size_t(nc1) * size_t(k >> 1))];
-        return v;
+        return x[cid(g, i, j, k)];
     }
 };
+
+// Cell-centred linear interpolation weights along one direction: fine cell
+// c sits a quarter of a coarse cell from the centre of its parent c >> 1,
+// towards the parent's lower neighbour when c is even and its upper one when
+// c is odd; it takes 3/4 of the parent and 1/4 of that neighbour.  Across a
+// periodic direction the neighbour wraps; across a non-periodic domain face
+// it is the parent itself (the even reflection of a zero normal gradient).
+__device__ __forceinline__ void prolong_pair(int c, int nc, int per, int& p, int& q) {
+    p = c >> 1;
+    q = (c & 1) ? p + 1 : p - 1;
+    if (q < 0) q = per ? nc - 1 : p;
+    if (q >= nc) q = per ? 0 : p;
+}
+
+template <typename T>
+__device__ __forceinline__ T lerp34(T nearv, T farv) {
+    return fma(T(0.75), nearv, T(0.25) * farv);
+}
+
+// (P xc)(i, j, k): the coarse correction interpolated onto fine cell
+// (i, j, k), direction by direction (x, then y, then z; z only when it was
+// coarsened, i.e. in 3D).
+template <typename T>
+__device__ __forceinline__ T prolong_at(const Grid& g, const Grid& gc, const T* __restrict__ xc,
+                                        int i, int j, int k) {
+    int ip, iq, jp, jq;
+    prolong_pair(i, gc.n0, g.per0, ip, iq);
+    prolong_pair(j, gc.n1, g.per1, jp, jq);
+    const size_t n0 = size_t(gc.n0), pl = n0 * size_t(gc.n1);
+    auto plane = [&](size_t base) -> T {
+        const T* r = xc + base;
+        const T lo = lerp34(r[ip + n0 * jp], r[iq + n0 * jp]);
+        const T hi = lerp34(r[ip + n0 * jq], r[iq + n0 * jq]);
+        return lerp34(lo, hi);
+    };
+    if (gc.n2 == g.n2) return plane(pl * size_t(k));
+    int kp, kq;
+    prolong_pair(k, gc.n2, g.per2, kp, kq);
+    return lerp34(plane(pl * size_t(kp)), plane(pl * size_t(kq)));
+}
 
 template <typename T>
 struct Coeffs {

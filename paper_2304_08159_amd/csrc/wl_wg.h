@@ -76,7 +76,7 @@ __device__ double wg_sweep(const WgLevel<T>& L, const XAccess<T, XM>& X, const T
 template <typename T, bool UNIF>
 __device__ void wg_restrict_u(const WgLevel<T>& F, const T* x, const T* b, const WgLevel<T>& Cl) {
     const Coeffs<T> C = wg_coeffs(F);
-    const XAccess<T, XM_PLAIN> X{x, nullptr, 0, 0};
+    const XAccess<T, XM_PLAIN> X{x};
     const int Nc = int(cells(Cl.g));
     const int fz = F.g.n2 > Cl.g.n2 ? 2 : 1;
     for (int c = threadIdx.x; c < Nc; c += blockDim.x) {
@@ -102,6 +102,19 @@ __device__ void wg_restrict(const WgLevel<T>& F, const T* x, const T* b, const W
         wg_restrict_u<T, true>(F, x, b, Cl);
     else
         wg_restrict_u<T, false>(F, x, b, Cl);
+}
+
+// x += P xc on every cell of L: the coarse correction xc of level C,
+// interpolated linearly (prolong_at).
+template <typename T>
+__device__ void wg_prolong(const WgLevel<T>& L, const WgLevel<T>& C, const T* xc, T* x) {
+    const int N = int(cells(L.g));
+    for (int c = threadIdx.x; c < N; c += blockDim.x) {
+        int i, j, k;
+        wg_coords(L.g, c, i, j, k);
+        x[c] += prolong_at<T>(L.g, C.g, xc, i, j, k);
+    }
+    __syncthreads();
 }
 
 // Coarse coefficient = 1/2 the sum of the fine faces it covers.
@@ -132,15 +145,15 @@ __device__ void wg_coarsen(const WgLevel<T>& F, const WgLevel<T>& Cl) {
 // The rest of a V-cycle from level lev[0] (its right-hand side in place)
 // down to the coarsest lev[n - 1] and back up, leaving the corrected iterate
 // in lev[0].x[1]: per level a zero-start and a plain sweep, restriction,
-// the minimum-norm coarsest solve, then prolongation-fused and plain sweeps.
+// the minimum-norm coarsest solve, then the prolongation and two plain
+// sweeps.
 template <typename T>
 __device__ void wg_vcycle_tail(const WgLevel<T>* lev, int n, T w, double coarse_tol, CoarseLds& S) {
     for (int l = 0; l < n - 1; ++l) {
         const WgLevel<T>& L = lev[l];
-        wg_sweep<T, XM_ZERO>(L, XAccess<T, XM_ZERO>{nullptr, nullptr, 0, 0}, L.b, w, L.x[0], false,
+        wg_sweep<T, XM_ZERO>(L, XAccess<T, XM_ZERO>{nullptr}, L.b, w, L.x[0], false,
                              S.red);
-        wg_sweep<T, XM_PLAIN>(L, XAccess<T, XM_PLAIN>{L.x[0], nullptr, 0, 0}, L.b, w, L.x[1], false,
-                              S.red);
+        wg_sweep<T, XM_PLAIN>(L, XAccess<T, XM_PLAIN>{L.x[0]}, L.b, w, L.x[1], false, S.red);
         wg_restrict<T>(L, L.x[1], L.b, lev[l + 1]);
     }
     const WgLevel<T>& Cst = lev[n - 1];
@@ -149,10 +162,9 @@ __device__ void wg_vcycle_tail(const WgLevel<T>* lev, int n, T w, double coarse_
     for (int l = n - 2; l >= 0; --l) {
         const WgLevel<T>& L = lev[l];
         const WgLevel<T>& C = lev[l + 1];
-        wg_sweep<T, XM_PROLONG>(L, XAccess<T, XM_PROLONG>{L.x[1], C.x[1], C.g.n0, C.g.n1}, L.b, w,
-                                L.x[0], false, S.red);
-        wg_sweep<T, XM_PLAIN>(L, XAccess<T, XM_PLAIN>{L.x[0], nullptr, 0, 0}, L.b, w, L.x[1], false,
-                              S.red);
+        wg_prolong<T>(L, C, C.x[1], L.x[1]);
+        wg_sweep<T, XM_PLAIN>(L, XAccess<T, XM_PLAIN>{L.x[1]}, L.b, w, L.x[0], false, S.red);
+        wg_sweep<T, XM_PLAIN>(L, XAccess<T, XM_PLAIN>{L.x[0]}, L.b, w, L.x[1], false, S.red);
     }
 }
 
