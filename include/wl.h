@@ -103,13 +103,25 @@ typedef struct {
     wl_body body;
     int prec;             /* wl_precision                                     */
     int mg_levels;        /* 0 = automatic coarsening                         */
-    double tol;           /* pressure solves stop once the RMS divergence they
-                             leave in the projected velocity is <= tol        */
+    double tol;           /* pressure-solve tolerance, read per stop_rule     */
     int max_vcycles;      /* per pressure solve (<= 0 selects 100)            */
     int inner_vcycles;    /* MIXED: FP32 V-cycles per outer iteration (0: 3)  */
     double cfl;           /* CFL number of the adaptive time step (0: 0.5)    */
     int tape_steps;       /* steps the adjoint tape can hold (0: no adjoint)  */
+    int stop_rule;        /* wl_stop_rule of the in-step pressure solves      */
 } wl_sim_desc;
+
+/* When an in-step pressure solve stops (tested before each V-cycle, on the
+ * projection right-hand side sigma = div(u*)/(c dt) and the current pressure
+ * iterate p of the stage, Sec. 2 project!):
+ *  WL_STOP_DIVERGENCE: once the divergence the solve leaves in the projected
+ *    velocity, c dt (sigma - A p), has RMS over the active cells <= tol.  For
+ *    FP32 fields this is the usable rule: the rounding of an FP32 pressure
+ *    alone floors ||sigma - A p|| / ||sigma|| near 1e-5 on large grids, while
+ *    the divergence it leaves stays at the velocity's own rounding.
+ *  WL_STOP_RELATIVE: once ||sigma - A p||_2 <= tol ||sigma||_2 (FP64 or MIXED
+ *    fields, where the relative residual has no such floor). */
+typedef enum { WL_STOP_DIVERGENCE = 0, WL_STOP_RELATIVE = 1 } wl_stop_rule;
 
 typedef struct {
     double dt;            /* time step taken                                  */
@@ -117,6 +129,10 @@ typedef struct {
     int vcycles[2];       /* V-cycles of the predictor and corrector solves   */
     double resid[2];      /* RMS divergence each solve leaves in the projected
                              velocity, c dt ||sigma - A p||_2 / sqrt(n_active) */
+    double rel_resid[2];  /* relative residual each solve reached,
+                             ||sigma - A p||_2 / ||sigma||_2 (sigma with
+                             inactive cells dropped and the active mean removed;
+                             0 when sigma is 0)                               */
 } wl_step_stats;
 
 /* Fields addressable by wl_set_field / wl_get_field. */
@@ -154,6 +170,27 @@ wl_status wl_set_field(wl_sim* sim, int field, const void* src);
 wl_status wl_get_field(const wl_sim* sim, int field, void* dst);
 wl_status wl_set_time(wl_sim* sim, double t);
 
+/* Checkpoint / restart of a simulation (the state simstep! carries from one
+ * step to the next, Sec. 2-3): everything a later step reads, so that
+ * restoring a snapshot and stepping on gives bitwise the results of never
+ * having stopped.  The snapshot is one caller-owned DEVICE buffer of
+ * wl_state_size bytes (256-byte aligned), laid out as
+ *   bytes [0, 64)   : 8 doubles: format tag 1, time t, dt of the next
+ *                     CFL-adaptive step (0 when it is not yet known), ndim,
+ *                     n[0], n[1], n[2], precision;
+ *   then, each section at the next 256-byte boundary (first at 256): the
+ *   ndim velocity components (n cells each, sim dtype, wl_get_field layout),
+ *   the outflow plane (OUTFLOW simulations only, n[1]*n[2] values), the
+ *   pressure (n cells) and, for WL_MIXED, the FP64 pressure iterate the
+ *   mixed-precision solve warm-starts from (n doubles).
+ * Geometry, coefficients and the adjoint tape are not part of it (they are
+ * fixed by the description or recorded anew).  Both calls synchronise the
+ * stream.  wl_set_state returns WL_ERR_INVALID_ARG when the header does not
+ * match this simulation (tag, grid or precision) and then changes nothing. */
+wl_status wl_state_size(const wl_sim* sim, size_t* bytes);
+wl_status wl_get_state(const wl_sim* sim, void* dst);
+wl_status wl_set_state(wl_sim* sim, const void* src);
+
 /* Advance one Heun step (predictor and corrector, each: convection-diffusion,
  * BDIM blend, boundary rules, divergence, GMG pressure solve, projection).
  * dt <= 0 selects the CFL-adaptive step from the current velocity.  stats
@@ -189,14 +226,20 @@ wl_status wl_tape_record(wl_sim* sim, int on);
  * and the limiter / upwind branches frozen at their forward values and every
  * pressure solve treated as exact (its adjoint is the same GMG solve).
  * ubar_in: adjoint of the state after the step (ndim face arrays followed by
- * the outflow plane when there is one; sim dtype); ubar_out: adjoint of the
- * state before it (same layout; may alias ubar_in).  drag_weight: dJ/dF_x of
- * the step's drag.  g_params[4] (host, may be NULL) accumulates
- * dJ/d(radius, centre x, y, z) through the geometry (BDIM moments, Poisson
- * coefficients, drag weights).  Synchronous on the simulation's stream.
- * WL_ERR_STATE when the tape is empty. */
-wl_status wl_step_adjoint(wl_sim* sim, const void* ubar_in, double drag_weight, void* ubar_out,
-                          double* g_params);
+ * the outflow plane when there is one; sim dtype).  pbar_in (may be NULL =
+ * zero): adjoint of the pressure after the step (the corrector's pressure,
+ * n cells, sim dtype); the pressure is determined up to a constant, so the
+ * part of pbar_in that is constant over the active cells (and its values on
+ * inactive cells) does not contribute.  ubar_out: adjoint of the state
+ * before it (same layout as ubar_in; may alias it).  The pressure before the
+ * step is only the solves' starting guess, so it has no adjoint.
+ * drag_weight: dJ/dF_x of the step's drag (added to pbar_in's effect).
+ * g_params[4] (host, may be NULL) accumulates dJ/d(radius, centre x, y, z)
+ * through the geometry (BDIM moments, Poisson coefficients, drag weights).
+ * Synchronous on the simulation's stream.  WL_ERR_STATE when the tape is
+ * empty. */
+wl_status wl_step_adjoint(wl_sim* sim, const void* ubar_in, const void* pbar_in,
+                          double drag_weight, void* ubar_out, double* g_params);
 
 /* ---- Standalone pressure-Poisson GMG solve (project!, Sec. 2) ---------- */
 

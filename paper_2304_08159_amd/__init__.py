@@ -14,11 +14,11 @@ import ctypes
 
 from . import _lib
 from ._lib import (FIELD_L0, FIELD_MU0_0, FIELD_MU1N, FIELD_P, FIELD_SIGMA, FIELD_U0,  # noqa: F401
-                   FIELD_UOUT, INFLOW, OUTFLOW, PERIODIC, WALL, WL_FP32, WL_FP64, WL_MIXED,
-                   WlError, check, load)
+                   FIELD_UOUT, INFLOW, OUTFLOW, PERIODIC, STOP_DIVERGENCE, STOP_RELATIVE, WALL,
+                   WL_FP32, WL_FP64, WL_MIXED, WlError, check, load)
 
 __all__ = ["Sim", "Poisson", "body_coeffs", "set_graphs", "set_fused_sweeps", "poisson_batch_solve", "load", "WlError", "WL_FP32", "WL_FP64", "WL_MIXED",
-           "PERIODIC", "INFLOW", "OUTFLOW", "WALL"]
+           "PERIODIC", "INFLOW", "OUTFLOW", "WALL", "STOP_DIVERGENCE", "STOP_RELATIVE"]
 
 
 def _torch():
@@ -47,7 +47,8 @@ class Sim:
     """One Navier-Stokes configuration resident on the GPU (wl_sim)."""
 
     def __init__(self, n, bc_lo, bc_hi, U, nu, body=None, prec=WL_FP32, levels=0, tol=1e-5,
-                 max_vcycles=100, inner_vcycles=3, cfl=0.5, eps=1.0, tape_steps=0, device="cuda"):
+                 max_vcycles=100, inner_vcycles=3, cfl=0.5, eps=1.0, tape_steps=0,
+                 stop_rule=STOP_DIVERGENCE, device="cuda"):
         torch = _torch()
         lib = load()
         n = tuple(int(m) for m in n)
@@ -72,6 +73,7 @@ class Sim:
         d.prec, d.mg_levels, d.tol = int(prec), int(levels), float(tol)
         d.max_vcycles, d.inner_vcycles, d.cfl = int(max_vcycles), int(inner_vcycles), float(cfl)
         d.tape_steps = int(tape_steps)
+        d.stop_rule = int(stop_rule)
         nbytes = ctypes.c_size_t()
         check(lib.wl_sim_footprint(ctypes.byref(d), ctypes.byref(nbytes)))
         self.footprint = nbytes.value
@@ -134,15 +136,16 @@ class Sim:
         cells = self.shape[0] * self.shape[1] * self.shape[2]
         return self.ndim * cells + (self.shape[0] * self.shape[1] if self.has_outflow else 0)
 
-    def get_state(self):
-        """Velocity components and outflow plane as one flat tensor."""
+    def get_flow(self):
+        """Velocity components and outflow plane as one flat tensor (the
+        layout of the adjoint state that step_adjoint takes and returns)."""
         torch = _torch()
         parts = [t.reshape(-1) for t in self.velocity()]
         if self.has_outflow:
             parts.append(self.get(FIELD_UOUT).reshape(-1))
         return torch.cat(parts)
 
-    def set_state(self, vec, p=None):
+    def set_flow(self, vec, p=None):
         cells = self.shape[0] * self.shape[1] * self.shape[2]
         for i in range(self.ndim):
             self.set(FIELD_U0 + i, vec[i * cells:(i + 1) * cells].reshape(self.shape))
@@ -150,6 +153,32 @@ class Sim:
             self.set(FIELD_UOUT, vec[self.ndim * cells:].reshape(self.shape[0], self.shape[1]))
         if p is not None:
             self.set(FIELD_P, p)
+
+    def get_state(self):
+        """Snapshot of everything later steps read (wl_get_state): velocity,
+        outflow plane, pressure (and its FP64 iterate), time and the next dt,
+        in a device byte tensor (a view into a 256-byte aligned buffer)."""
+        torch = _torch()
+        nb = ctypes.c_size_t()
+        check(self._lib.wl_state_size(self._h, ctypes.byref(nb)))
+        buf, ptr, _ = _workspace(torch, nb.value, self.device)
+        check(self._lib.wl_get_state(self._h, ptr))
+        off = ptr.value - buf.data_ptr()
+        return buf[off:off + nb.value]
+
+    def set_state(self, snap):
+        """Restore a snapshot taken by get_state (wl_set_state)."""
+        torch = _torch()
+        nb = ctypes.c_size_t()
+        check(self._lib.wl_state_size(self._h, ctypes.byref(nb)))
+        if snap.dtype != torch.uint8 or snap.numel() != nb.value or not snap.is_cuda:
+            raise ValueError("not a snapshot of this simulation")
+        if snap.data_ptr() % 256:
+            buf, ptr, _ = _workspace(torch, nb.value, self.device)
+            off = ptr.value - buf.data_ptr()
+            buf[off:off + nb.value].copy_(snap)
+            snap = buf[off:off + nb.value]
+        check(self._lib.wl_set_state(self._h, _ptr(snap)))
 
     def drag(self):
         F = ctypes.c_double()
@@ -159,22 +188,32 @@ class Sim:
     def tape(self, on=True):
         check(self._lib.wl_tape_record(self._h, int(bool(on))))
 
-    def step_adjoint(self, ubar, drag_weight=0.0):
+    def step_adjoint(self, ubar, drag_weight=0.0, pbar=None):
         """Reverse the last recorded step: returns (adjoint of the state before
-        it, dJ/d(radius, cx, cy, cz) contributed by this step)."""
+        it, dJ/d(radius, cx, cy, cz) contributed by this step).  ubar: adjoint
+        of the state after it (get_flow layout); pbar: adjoint of the pressure
+        after it (None = zero)."""
         torch = _torch()
         ubar = ubar.to(device=self.device, dtype=self.dtype).contiguous()
         if ubar.numel() != self.state_size():
             raise ValueError("adjoint state has the wrong size")
+        pptr = ctypes.c_void_p()
+        if pbar is not None:
+            pbar = pbar.to(device=self.device, dtype=self.dtype).contiguous()
+            if tuple(pbar.shape) != self.shape:
+                raise ValueError("pressure adjoint has the wrong shape")
+            pptr = _ptr(pbar)
         out = torch.empty_like(ubar)
         g = (ctypes.c_double * 4)(0.0, 0.0, 0.0, 0.0)
-        check(self._lib.wl_step_adjoint(self._h, _ptr(ubar), float(drag_weight), _ptr(out), g))
+        check(self._lib.wl_step_adjoint(self._h, _ptr(ubar), pptr, float(drag_weight), _ptr(out),
+                                        g))
         return out, [g[0], g[1], g[2], g[3]]
 
     @staticmethod
     def _stats(st):
         return dict(dt=st.dt, t=st.t, vcycles=(st.vcycles[0], st.vcycles[1]),
-                    resid=(st.resid[0], st.resid[1]))
+                    resid=(st.resid[0], st.resid[1]),
+                    rel_resid=(st.rel_resid[0], st.rel_resid[1]))
 
     def step(self, dt=0.0, allow_not_converged=False):
         st = _lib.StepStats()

@@ -19,6 +19,7 @@ STATUS = {
     -3: "WL_ERR_NOT_CONVERGED", -4: "WL_ERR_NONFINITE", -5: "WL_ERR_HIP", -6: "WL_ERR_STATE",
 }
 WL_FP32, WL_FP64, WL_MIXED = 0, 1, 2
+STOP_DIVERGENCE, STOP_RELATIVE = 0, 1
 PERIODIC, INFLOW, OUTFLOW, WALL = 0, 1, 2, 3
 
 FIELD_U0, FIELD_U1, FIELD_U2, FIELD_P, FIELD_UOUT = 0, 1, 2, 3, 4
@@ -27,10 +28,12 @@ FIELD_L0, FIELD_MU0_0, FIELD_MU1N, FIELD_SIGMA = 5, 8, 11, 20
 # Every symbol include/wl.h declares.
 EXPORTS = (
     "wl_sim_footprint", "wl_sim_create", "wl_sim_destroy", "wl_set_field", "wl_get_field",
-    "wl_set_time", "wl_step", "wl_run", "wl_drag", "wl_tape_record", "wl_step_adjoint",
+    "wl_set_time", "wl_state_size", "wl_get_state", "wl_set_state", "wl_step", "wl_run",
+    "wl_drag", "wl_tape_record", "wl_step_adjoint",
     "wl_poisson_footprint", "wl_poisson_create",
     "wl_poisson_solve", "wl_poisson_destroy", "wl_poisson_batch_footprint",
-    "wl_poisson_batch_solve", "wl_body_coeffs", "wl_set_graphs", "wl_set_fused_sweeps",
+    "wl_poisson_batch_solve", "wl_body_coeffs",
+    "wl_set_graphs", "wl_set_fused_sweeps",
     "wl_profile_enable",
     "wl_profile_reset",
     "wl_profile_read", "wl_last_error", "wl_version",
@@ -62,7 +65,8 @@ class SimDesc(ctypes.Structure):
                 ("U", ctypes.c_double * 3), ("nu", ctypes.c_double), ("body", Body),
                 ("prec", ctypes.c_int), ("mg_levels", ctypes.c_int), ("tol", ctypes.c_double),
                 ("max_vcycles", ctypes.c_int), ("inner_vcycles", ctypes.c_int),
-                ("cfl", ctypes.c_double), ("tape_steps", ctypes.c_int)]
+                ("cfl", ctypes.c_double), ("tape_steps", ctypes.c_int),
+                ("stop_rule", ctypes.c_int)]
 
 
 class BatchRequest(ctypes.Structure):
@@ -77,7 +81,8 @@ class BatchResult(ctypes.Structure):
 
 class StepStats(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("t", ctypes.c_double),
-                ("vcycles", ctypes.c_int * 2), ("resid", ctypes.c_double * 2)]
+                ("vcycles", ctypes.c_int * 2), ("resid", ctypes.c_double * 2),
+                ("rel_resid", ctypes.c_double * 2)]
 
 
 _lib = None
@@ -100,11 +105,14 @@ def load():
         "wl_set_field": [vp, i32, vp],
         "wl_get_field": [vp, i32, vp],
         "wl_set_time": [vp, f64],
+        "wl_state_size": [vp, ctypes.POINTER(sz)],
+        "wl_get_state": [vp, vp],
+        "wl_set_state": [vp, vp],
         "wl_step": [vp, f64, ctypes.POINTER(StepStats)],
         "wl_run": [vp, i32, f64, ctypes.POINTER(StepStats), ctypes.POINTER(i32)],
         "wl_drag": [vp, ctypes.POINTER(f64)],
         "wl_tape_record": [vp, i32],
-        "wl_step_adjoint": [vp, vp, f64, vp, ctypes.POINTER(f64)],
+        "wl_step_adjoint": [vp, vp, vp, f64, vp, ctypes.POINTER(f64)],
         "wl_poisson_footprint": [i32, ip3, ip3, i32, i32, ctypes.POINTER(sz)],
         "wl_poisson_create": [i32, ip3, ip3, i32, i32, vp, sz, vp, ctypes.POINTER(vp)],
         "wl_poisson_solve": [vp, vp, vp, vp, f64, i32, ctypes.POINTER(i32), ctypes.POINTER(f64)],

@@ -2,7 +2,8 @@
 the body (radius and centre) through the hand-written adjoint of the step.
 
 J = sum_n dt_n F_x^n / sum_n dt_n with F_x^n the drag after step n.  The
-forward run keeps checkpoints (velocity, outflow plane, pressure) every
+forward run keeps checkpoints (wl_get_state snapshots: velocity, outflow
+plane, pressure, time) every
 `checkpoint` steps and the dt sequence; the reverse pass restores each
 segment's checkpoint, re-runs it with the tape recording (same dt sequence),
 and reverses its steps with wl_step_adjoint.  dt is frozen (the gradient of
@@ -19,20 +20,25 @@ class Rollout:
     """A body-in-a-stream configuration whose drag can be differentiated."""
 
     def __init__(self, n, bc_lo, bc_hi, U, nu, centre, radius, prec=wl.WL_MIXED, tol=1e-8,
-                 checkpoint=10, levels=0, max_vcycles=200):
+                 checkpoint=10, levels=0, max_vcycles=200, init=None):
         self.kw = dict(n=n, bc_lo=bc_lo, bc_hi=bc_hi, U=U, nu=nu, prec=prec, tol=tol,
                        levels=levels, max_vcycles=max_vcycles)
         self.base_centre = tuple(float(c) for c in centre)
         self.base_radius = float(radius)
         self.checkpoint = int(checkpoint)
+        # initial flow (Sim.get_flow layout; None: the uniform stream U)
+        self.init = init
 
     def make(self, params, tape_steps=0):
         r, cx, cy, cz = [float(v) for v in params]
         centre = (cx, cy, cz)[:len(self.kw["n"])]
-        return wl.Sim(self.kw["n"], self.kw["bc_lo"], self.kw["bc_hi"], self.kw["U"], self.kw["nu"],
-                      body=dict(centre=centre, radius=r), prec=self.kw["prec"],
-                      tol=self.kw["tol"], levels=self.kw["levels"],
-                      max_vcycles=self.kw["max_vcycles"], tape_steps=tape_steps)
+        sim = wl.Sim(self.kw["n"], self.kw["bc_lo"], self.kw["bc_hi"], self.kw["U"], self.kw["nu"],
+                     body=dict(centre=centre, radius=r), prec=self.kw["prec"],
+                     tol=self.kw["tol"], levels=self.kw["levels"],
+                     max_vcycles=self.kw["max_vcycles"], tape_steps=tape_steps)
+        if self.init is not None:
+            sim.set_flow(self.init)
+        return sim
 
     def forward(self, params, nsteps, dts=None, keep=True):
         """Returns (J, dts, checkpoints, sim)."""
@@ -42,7 +48,7 @@ class Rollout:
         num = 0.0
         for k in range(nsteps):
             if keep and k % self.checkpoint == 0:
-                cps[k] = (sim.get_state().clone(), sim.pressure().clone())
+                cps[k] = sim.get_state()
             st = sim.step(dts[k] if dts is not None else 0.0, allow_not_converged=True)
             used.append(st["dt"])
             num += st["dt"] * sim.drag()
@@ -67,8 +73,7 @@ class Rollout:
         starts = sorted(cps)
         for s0 in reversed(starts):
             s1 = min(s0 + self.checkpoint, nsteps)
-            state, p = cps[s0]
-            sim.set_state(state, p)
+            sim.set_state(cps[s0])
             sim.tape(True)
             for k in range(s0, s1):
                 sim.step(dts[k], allow_not_converged=True)

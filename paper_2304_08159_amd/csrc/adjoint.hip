@@ -457,6 +457,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_axpy(TileDev TL, Grid g, AdjPtrs
     }
 }
 
+// y += x over n cells (grid-stride).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cells_add(size_t n, const T* __restrict__ x,
+                                                      T* __restrict__ y) {
+    for (size_t q = size_t(blockIdx.x) * kBlock + threadIdx.x; q < n; q += size_t(gridDim.x) * kBlock)
+        y[q] += x[q];
+}
+
 // Face geometry for the parameter chain rule: signed distance d, unit normal
 // n and distance rho to the centre, at the centre of the lower c-face of cell
 // (i, j, k) (c < 0: the cell centre).
@@ -774,6 +782,16 @@ wl_status adj_faces_axpy(const Grid& g, T* const x[3], double alpha, T* const y[
 }
 
 template <typename T>
+wl_status adj_cells_add(size_t n, const T* x, T* y, hipStream_t s) {
+    if (n == 0) return WL_OK;
+    const size_t want = (n + kBlock - 1) / kBlock;
+    const unsigned blocks = unsigned(want < 4096 ? want : 4096);
+    k_cells_add<T><<<blocks, kBlock, 0, s>>>(n, x, y);
+    WL_CHECK_LAUNCH();
+    return WL_OK;
+}
+
+template <typename T>
 wl_status adj_params(const Grid& g, const BodyDev& body, T* const Lb[3], T* const mu0b[3],
                      T* const mu1nb[9], double* partial, hipStream_t s) {
     const Launch ln = launch_for(g.n0, g.n1, g.n2);
@@ -829,6 +847,7 @@ wl_status reduce_cols(const double* partial, size_t nslots, int ncomp, double* o
                                           hipStream_t);                                             \
     template wl_status adj_faces_axpy<T>(const Grid&, T* const*, double, T* const*, bool,            \
                                          hipStream_t);                                              \
+    template wl_status adj_cells_add<T>(size_t, const T*, T*, hipStream_t);                          \
     template wl_status adj_params<T>(const Grid&, const BodyDev&, T* const*, T* const*, T* const*,   \
                                      double*, hipStream_t);                                         \
     template wl_status drag_sums<T>(const Grid&, const BodyDev&, const T*, T* const*, double*,       \

@@ -57,6 +57,8 @@ static wl_status check_desc(const wl_sim_desc* desc, SimConfig* cfg) {
     if (d.max_vcycles <= 0) d.max_vcycles = 100;
     if (d.inner_vcycles <= 0) d.inner_vcycles = 3;
     if (!(d.tol >= 0.0)) return invalid("tol must be >= 0");
+    if (d.stop_rule != WL_STOP_DIVERGENCE && d.stop_rule != WL_STOP_RELATIVE)
+        return invalid("stop_rule must be WL_STOP_DIVERGENCE or WL_STOP_RELATIVE");
     if (d.body.kind < 0 || d.body.kind > 2) return invalid("body.kind must be 0, 1 or 2");
     if (d.body.kind != 0 && !(d.body.radius > 0.0)) return invalid("body radius must be > 0");
     if (d.body.kind == 2 && (d.ndim != 3 || !(d.body.radius2 > 0.0)))
@@ -160,6 +162,8 @@ struct SimImpl {
     double* sigma64 = nullptr;
     double t = 0.0;
     bool cfl_valid = false;
+    double dt_host = 0.0;    // the next step's dt when the host already knows it
+                             // (a restored state), else 0: read from the post
     AdjointWS<T>* adj = nullptr;  // host bookkeeping of the adjoint workspace
     ~SimImpl() {
         if (adj) {
@@ -332,9 +336,10 @@ static wl_status sim_init(SimImpl<T>& s, hipStream_t st) {
     return WL_OK;
 }
 
-// Pressure solve of one stage.  It stops once the divergence it leaves in the
-// projected velocity, c dt (sigma - A p), has RMS over the active cells <= tol,
-// i.e. ||r||^2 <= (tol sqrt(n_active) / (c dt))^2.  `tail` (may be null) is
+// Pressure solve of one stage.  WL_STOP_DIVERGENCE: it stops once the
+// divergence it leaves in the projected velocity, c dt (sigma - A p), has RMS
+// over the active cells <= tol, i.e. ||r||^2 <= (tol sqrt(n_active) / (c dt))^2;
+// WL_STOP_RELATIVE: once ||r|| <= tol ||sigma||.  `tail` (may be null) is
 // work that reads the final pressure, done before returning (see SolveTail).
 // The divergence kernel also takes the pressure solve's first residual
 // check (plain periodic FP32/FP64 solves on hierarchies that allow it).
@@ -347,12 +352,14 @@ template <typename T>
 static wl_status pressure_solve(SimImpl<T>& s, double cfac, double dt, hipStream_t st,
                                 SolveResult* r, const SolveTail* tail = nullptr) {
     const SimConfig& c = s.cfg;
+    const bool rel = c.d.stop_rule == WL_STOP_RELATIVE;
     const double a = c.d.tol * std::sqrt(double(s.h.n_active)) / (cfac * dt);
-    const double abs_r2 = a * a;
+    const double abs_r2 = rel ? 0.0 : a * a;
+    const double rtol = rel ? c.d.tol : 0.0;
     if (c.d.prec == WL_MIXED) {
         if constexpr (sizeof(T) == 4) {
             WL_TRY((convert<float, double>(s.sigma, s.sigma64, c.N, st)));
-            wl_status rc = mg_solve_mixed(s.h, s.mix, s.red, s.p64, s.sigma64, 0.0, abs_r2,
+            wl_status rc = mg_solve_mixed(s.h, s.mix, s.red, s.p64, s.sigma64, rtol, abs_r2,
                                           c.d.max_vcycles, st, r);
             if (rc != WL_OK && rc != WL_ERR_NOT_CONVERGED) return rc;
             WL_TRY((convert<double, float>(s.p64, s.p, c.N, st)));
@@ -361,7 +368,7 @@ static wl_status pressure_solve(SimImpl<T>& s, double cfac, double dt, hipStream
         }
         return invalid("mixed precision needs FP32 fields");
     }
-    return mg_solve<T>(s.h, s.red, s.p, s.sigma, 0.0, abs_r2, c.d.max_vcycles, st, r,
+    return mg_solve<T>(s.h, s.red, s.p, s.sigma, rtol, abs_r2, c.d.max_vcycles, st, r,
                        producer_check(s) ? BPartials::Check : BPartials::Sums, tail);
 }
 
@@ -375,6 +382,9 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
     if (dt_in > 0.0) {
         WL_TRY(ns_set_scalar(dt_dev, dt_in, st));
         dt = dt_in;
+    } else if (s.cfl_valid && s.dt_host > 0.0) {
+        // restored state: dt_dev already holds the saved dt
+        dt = s.dt_host;
     } else if (s.cfl_valid) {
         // the last projection formed dt on the device (dt_dev) and posted it
         // to mailbox slot 8; the host needs it only for the first
@@ -520,6 +530,7 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
     }
     s.dt_cur = 1 - s.dt_cur;
     s.cfl_valid = true;
+    s.dt_host = 0.0;
     s.t += dt;
     if (tp) s.adj->count += 1;
     if (stats) {
@@ -530,6 +541,8 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
         const double na = double(s.h.n_active > 0 ? s.h.n_active : 1);
         stats->resid[0] = 1.0 * dt * std::sqrt(r1.r2 / na);
         stats->resid[1] = 0.5 * dt * std::sqrt(r2.r2 / na);
+        stats->rel_resid[0] = r1.rel;
+        stats->rel_resid[1] = r2.rel;
     }
     return worst;
 }
@@ -644,8 +657,8 @@ static wl_status sim_drag(SimImpl<T>& s, double* F, hipStream_t st) {
 }
 
 template <typename T>
-static wl_status sim_step_adjoint(SimImpl<T>& s, const void* ubar_in, double drag_weight,
-                                  void* ubar_out, double* gp, hipStream_t st) {
+static wl_status sim_step_adjoint(SimImpl<T>& s, const void* ubar_in, const void* pbar_in,
+                                  double drag_weight, void* ubar_out, double* gp, hipStream_t st) {
     if (!s.adj || s.adj->count <= 0) {
         set_error("the adjoint tape is empty (record steps with wl_tape_record first)");
         return WL_ERR_STATE;
@@ -685,6 +698,14 @@ static wl_status sim_step_adjoint(SimImpl<T>& s, const void* ubar_in, double dra
         double dg[4];
         WL_TRY(read_doubles<T>(A.res, dg, 4, st));
         for (int q = 0; q < 4; ++q) gsum[q] += dg[q];
+        pbar = A.pbar;
+    }
+    // ---- the caller's adjoint of the step's pressure adds to the drag's
+    if (pbar_in) {
+        if (pbar)
+            WL_TRY(adj_cells_add<T>(N, static_cast<const T*>(pbar_in), A.pbar, st));
+        else
+            WL_CHECK_HIP(hipMemcpyAsync(A.pbar, pbar_in, N * sizeof(T), hipMemcpyDeviceToDevice, st));
         pbar = A.pbar;
     }
     // ---- corrector projection (c = 1/2) and BDIM: fb, fob
@@ -839,7 +860,10 @@ static wl_status copy_field(wl_sim* sim, int field, const void* src, void* dst) 
     WL_TRY(sim_field_ptr<T>(s, field, &ptr, &count, src != nullptr));
     if (src) {
         WL_CHECK_HIP(hipMemcpyAsync(ptr, src, count * sizeof(T), hipMemcpyDeviceToDevice, sim->stream));
-        if (field != WL_FIELD_P) s.cfl_valid = false;
+        if (field != WL_FIELD_P) {
+            s.cfl_valid = false;
+            s.dt_host = 0.0;
+        }
         if (field == WL_FIELD_P && s.p64)
             WL_TRY((convert<float, double>(reinterpret_cast<float*>(s.p), s.p64, count, sim->stream)));
     } else {
@@ -916,6 +940,113 @@ static wl_status tape_record(SimImpl<T>& s, int on, hipStream_t st) {
         s.adj->count = 0;
         WL_TRY(adj_clear(s, st));
     }
+    return WL_OK;
+}
+
+// ------------------------------------------------------- checkpoint state
+// Snapshot layout (see wl_state_size in wl.h): a 64-byte header of doubles
+// (tag, t, next dt, ndim, n0, n1, n2, precision), then velocity components,
+// outflow plane, pressure and (MIXED) the FP64 pressure, each at the next
+// 256-byte boundary.
+constexpr double kStateTag = 1.0;
+
+struct StateLayout {
+    size_t vel[3] = {0, 0, 0};
+    size_t plane = 0, p = 0, p64 = 0, bytes = 0;
+};
+
+template <typename T>
+static StateLayout state_layout(const SimImpl<T>& s) {
+    const SimConfig& c = s.cfg;
+    StateLayout Lo;
+    size_t off = 256;
+    auto take = [&](size_t nbytes) {
+        const size_t at = off;
+        off = (off + nbytes + 255) & ~size_t(255);
+        return at;
+    };
+    for (int i = 0; i < c.d.ndim; ++i) Lo.vel[i] = take(c.N * sizeof(T));
+    if (c.outflow) Lo.plane = take(c.P * sizeof(T));
+    Lo.p = take(c.N * sizeof(T));
+    if (s.p64) Lo.p64 = take(c.N * sizeof(double));
+    Lo.bytes = off;
+    return Lo;
+}
+
+template <typename T>
+static void state_header(const SimImpl<T>& s, double h[8]) {
+    const SimConfig& c = s.cfg;
+    h[0] = kStateTag;
+    h[1] = s.t;
+    h[2] = 0.0;
+    h[3] = c.d.ndim;
+    h[4] = c.d.n[0];
+    h[5] = c.d.n[1];
+    h[6] = c.d.n[2];
+    h[7] = c.d.prec;
+}
+
+template <typename T>
+static wl_status sim_get_state(SimImpl<T>& s, void* dst, hipStream_t st) {
+    const SimConfig& c = s.cfg;
+    const StateLayout Lo = state_layout(s);
+    char* d = static_cast<char*>(dst);
+    double h[8];
+    state_header(s, h);
+    WL_CHECK_HIP(hipMemcpyAsync(d, h, sizeof(h), hipMemcpyHostToDevice, st));
+    // the next dt lives on the device (the last projection formed it)
+    if (s.cfl_valid)
+        WL_CHECK_HIP(hipMemcpyAsync(d + 2 * sizeof(double), s.scal + s.dt_cur, sizeof(double),
+                                    hipMemcpyDeviceToDevice, st));
+    for (int i = 0; i < c.d.ndim; ++i)
+        WL_CHECK_HIP(hipMemcpyAsync(d + Lo.vel[i], s.vel[s.S][i], c.N * sizeof(T),
+                                    hipMemcpyDeviceToDevice, st));
+    if (c.outflow)
+        WL_CHECK_HIP(hipMemcpyAsync(d + Lo.plane, s.plane[s.PS], c.P * sizeof(T),
+                                    hipMemcpyDeviceToDevice, st));
+    WL_CHECK_HIP(hipMemcpyAsync(d + Lo.p, s.p, c.N * sizeof(T), hipMemcpyDeviceToDevice, st));
+    if (s.p64)
+        WL_CHECK_HIP(hipMemcpyAsync(d + Lo.p64, s.p64, c.N * sizeof(double),
+                                    hipMemcpyDeviceToDevice, st));
+    WL_CHECK_HIP(hipStreamSynchronize(st));  // h must outlive its copy
+    return WL_OK;
+}
+
+template <typename T>
+static wl_status sim_set_state(SimImpl<T>& s, const void* src, hipStream_t st) {
+    const SimConfig& c = s.cfg;
+    const StateLayout Lo = state_layout(s);
+    const char* d = static_cast<const char*>(src);
+    double h[8], want[8];
+    WL_CHECK_HIP(hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, st));
+    WL_CHECK_HIP(hipStreamSynchronize(st));
+    state_header(s, want);
+    if (h[0] != want[0]) return invalid("state buffer has no snapshot header");
+    for (int q = 3; q < 8; ++q)
+        if (h[q] != want[q]) return invalid("snapshot belongs to another grid or precision");
+    if (!std::isfinite(h[1]) || !(h[2] >= 0.0) || !std::isfinite(h[2]))
+        return invalid("snapshot time / dt is not finite");
+    for (int i = 0; i < c.d.ndim; ++i)
+        WL_CHECK_HIP(hipMemcpyAsync(s.vel[s.S][i], d + Lo.vel[i], c.N * sizeof(T),
+                                    hipMemcpyDeviceToDevice, st));
+    if (c.outflow)
+        WL_CHECK_HIP(hipMemcpyAsync(s.plane[s.PS], d + Lo.plane, c.P * sizeof(T),
+                                    hipMemcpyDeviceToDevice, st));
+    WL_CHECK_HIP(hipMemcpyAsync(s.p, d + Lo.p, c.N * sizeof(T), hipMemcpyDeviceToDevice, st));
+    if (s.p64)
+        WL_CHECK_HIP(hipMemcpyAsync(s.p64, d + Lo.p64, c.N * sizeof(double),
+                                    hipMemcpyDeviceToDevice, st));
+    s.t = h[1];
+    if (h[2] > 0.0) {
+        WL_CHECK_HIP(hipMemcpyAsync(s.scal + s.dt_cur, d + 2 * sizeof(double), sizeof(double),
+                                    hipMemcpyDeviceToDevice, st));
+        s.cfl_valid = true;
+        s.dt_host = h[2];
+    } else {
+        s.cfl_valid = false;
+        s.dt_host = 0.0;
+    }
+    WL_CHECK_HIP(hipStreamSynchronize(st));
     return WL_OK;
 }
 
@@ -1014,6 +1145,34 @@ wl_status wl_set_time(wl_sim* sim, double t) {
     return WL_OK;
 }
 
+wl_status wl_state_size(const wl_sim* sim, size_t* bytes) {
+    clear_error();
+    if (!sim || !bytes) return invalid("sim / bytes is NULL");
+    if (sim->prec == WL_FP64)
+        *bytes = state_layout(*static_cast<const SimImpl<double>*>(sim->impl)).bytes;
+    else
+        *bytes = state_layout(*static_cast<const SimImpl<float>*>(sim->impl)).bytes;
+    return WL_OK;
+}
+
+wl_status wl_get_state(const wl_sim* sim, void* dst) {
+    clear_error();
+    if (!sim || !dst) return invalid("sim / dst is NULL");
+    if (reinterpret_cast<uintptr_t>(dst) % 256) return invalid("dst must be 256-byte aligned");
+    if (sim->prec == WL_FP64)
+        return sim_get_state<double>(*static_cast<SimImpl<double>*>(sim->impl), dst, sim->stream);
+    return sim_get_state<float>(*static_cast<SimImpl<float>*>(sim->impl), dst, sim->stream);
+}
+
+wl_status wl_set_state(wl_sim* sim, const void* src) {
+    clear_error();
+    if (!sim || !src) return invalid("sim / src is NULL");
+    if (reinterpret_cast<uintptr_t>(src) % 256) return invalid("src must be 256-byte aligned");
+    if (sim->prec == WL_FP64)
+        return sim_set_state<double>(*static_cast<SimImpl<double>*>(sim->impl), src, sim->stream);
+    return sim_set_state<float>(*static_cast<SimImpl<float>*>(sim->impl), src, sim->stream);
+}
+
 wl_status wl_step(wl_sim* sim, double dt, wl_step_stats* stats) {
     clear_error();
     if (!sim) return invalid("sim is NULL");
@@ -1055,15 +1214,15 @@ wl_status wl_tape_record(wl_sim* sim, int on) {
     return tape_record<float>(*static_cast<SimImpl<float>*>(sim->impl), on, sim->stream);
 }
 
-wl_status wl_step_adjoint(wl_sim* sim, const void* ubar_in, double drag_weight, void* ubar_out,
-                          double* g_params) {
+wl_status wl_step_adjoint(wl_sim* sim, const void* ubar_in, const void* pbar_in,
+                          double drag_weight, void* ubar_out, double* g_params) {
     clear_error();
     if (!sim || !ubar_in || !ubar_out) return invalid("sim / ubar_in / ubar_out is NULL");
     if (sim->prec == WL_FP64)
         return sim_step_adjoint<double>(*static_cast<SimImpl<double>*>(sim->impl), ubar_in,
-                                        drag_weight, ubar_out, g_params, sim->stream);
-    return sim_step_adjoint<float>(*static_cast<SimImpl<float>*>(sim->impl), ubar_in, drag_weight,
-                                   ubar_out, g_params, sim->stream);
+                                        pbar_in, drag_weight, ubar_out, g_params, sim->stream);
+    return sim_step_adjoint<float>(*static_cast<SimImpl<float>*>(sim->impl), ubar_in, pbar_in,
+                                   drag_weight, ubar_out, g_params, sim->stream);
 }
 
 wl_status wl_poisson_footprint(int ndim, const int n[3], const int periodic[3], int prec, int levels,

@@ -70,6 +70,9 @@ wl_status adj_plane_stage(const Grid& g, const T* foutb, double wb, double adt, 
 template <typename T>
 wl_status adj_faces_axpy(const Grid& g, T* const x[3], double alpha, T* const y[3], bool accumulate,
                          hipStream_t s);
+// y += x over n cells.
+template <typename T>
+wl_status adj_cells_add(size_t n, const T* x, T* y, hipStream_t s);
 // Geometry adjoints -> parameter gradient (r, cx, cy, cz): partial sums per
 // block into partial[4*blk + k]; the accumulators are cleared.
 template <typename T>

@@ -123,3 +123,25 @@ def test_run_validates_arguments_without_a_gpu():
     taken = C.c_int(7)
     assert lib.wl_run(None, 3, 0.0, None, C.byref(taken)) == -1
     assert taken.value == 0 and b"sim" in lib.wl_last_error()
+
+
+def test_stop_rule_and_state_calls_validate_without_a_gpu():
+    from paper_2304_08159_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libwl.so not built")
+    lib = _lib.load()
+    d = _lib.SimDesc()
+    d.ndim = 3
+    for i in range(3):
+        d.n[i] = 16
+    d.nu, d.tol = 0.01, 1e-8
+    sz = ctypes.c_size_t()
+    for rule in (_lib.STOP_DIVERGENCE, _lib.STOP_RELATIVE):
+        d.stop_rule = rule
+        assert lib.wl_sim_footprint(ctypes.byref(d), ctypes.byref(sz)) == 0
+    d.stop_rule = 2
+    assert lib.wl_sim_footprint(ctypes.byref(d), ctypes.byref(sz)) == -1
+    assert b"stop_rule" in lib.wl_last_error()
+    assert lib.wl_state_size(None, ctypes.byref(sz)) == -1
+    assert lib.wl_get_state(None, None) == -1
+    assert lib.wl_set_state(None, None) == -1

@@ -36,7 +36,7 @@ def _run(wl, mode, precname, n, tol, steps=4):
             sim.set(wl.FIELD_U0 + i,
                     torch.from_numpy(np.ascontiguousarray(a.transpose(2, 1, 0))).to(dtype).cuda())
         stats = [sim.step() for _ in range(steps)]
-        out = (sim.get_state().clone(), sim.pressure().clone())
+        out = (sim.get_flow().clone(), sim.pressure().clone())
         sim.close()
         return stats, out
     finally:

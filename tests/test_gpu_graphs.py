@@ -70,7 +70,7 @@ def _ns_run(wl, graphs, case):
         stats = []
         for _ in range(6):
             stats.append(sim.step())
-        out = [sim.get_state().clone(), sim.pressure().clone()]
+        out = [sim.get_flow().clone(), sim.pressure().clone()]
         sim.close()
         return stats, out
     finally:

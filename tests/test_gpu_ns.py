@@ -30,25 +30,55 @@ def _make(cfg, prec, tol):
     return sim, osim
 
 
-def _replay(sim, osim, nsteps, tol_u, tol_p, label):
+def _max_rel(a, b):
+    """max |a - b| over max |b| (element-wise bound, any field list)."""
+    num = max(float(np.abs(x - y).max()) for x, y in zip(a, b))
+    den = max(float(np.abs(y).max()) for y in b)
+    return num / (den if den > 0 else 1.0)
+
+
+def _replay(sim, osim, nsteps, tol_u, tol_p, label, tol_dt=1e-6, tol_pmax=None):
+    """Replay nsteps GPU steps through the oracle and compare, per step:
+    velocity and outflow plane in relative L2 and element-wise (max |difference|
+    <= tol_u x max |field|), the mean-free pressure in relative L2 (tol_p) and
+    element-wise (tol_pmax, default 10 tol_p: cells the body nearly closes hold a
+    weakly determined pressure), and the GPU's CFL time step against the
+    oracle's cfl_dt of the same state (tol_dt relative: the GPU sums each
+    cell's outflow in the field precision)."""
+    if tol_pmax is None:
+        tol_pmax = 10 * tol_p
     d = sim.ndim
     worst_u = worst_p = 0.0
+    outflow = osim.bc_hi[0] == 2
     for step in range(nsteps):
         un = [to_oracle(t, d) for t in sim.velocity()]
         pn = to_oracle(sim.pressure(), d)
-        outflow = osim.bc_hi[0] == 2
         uo = plane_to_oracle(sim.get(4), d) if outflow else None
         st = sim.step()
+        dt_o = M.cfl_dt(un, uo, osim.bc_lo, osim.bc_hi, osim.U, osim.nu, osim.cfl)
+        edt = abs(st["dt"] - dt_o) / dt_o
         osim.u, osim.p, osim.uout = un, pn, uo
-        ost = osim.step(dt=st["dt"], force_vcycles=st["vcycles"])
+        osim.step(dt=st["dt"], force_vcycles=st["vcycles"])
         act = osim.h.active[0]
         ug = [to_oracle(t, d) for t in sim.velocity()]
         eu = math.sqrt(sum(np.sum((a - b) ** 2) for a, b in zip(ug, osim.u)) /
                        sum(np.sum(b ** 2) for b in osim.u))
-        ep = rel_l2(mean_free(to_oracle(sim.pressure(), d), act), mean_free(osim.p, act), act)
-        worst_u, worst_p = max(worst_u, eu), max(worst_p, ep)
-        print(f"{label} step {step}: dt={st['dt']:.6f} vc={st['vcycles']} "
-              f"div={st['resid'][0]:.2e},{st['resid'][1]:.2e} err_u={eu:.2e} err_p={ep:.2e}")
+        mu = _max_rel(ug, osim.u)
+        pg, po = mean_free(to_oracle(sim.pressure(), d), act), mean_free(osim.p, act)
+        ep = rel_l2(pg, po, act)
+        mp = _max_rel([pg], [po])
+        eo = mo = 0.0
+        if outflow:
+            og = plane_to_oracle(sim.get(4), d)
+            eo = rel_l2(og, osim.uout)
+            mo = _max_rel([og], [osim.uout])
+        worst_u = max(worst_u, eu, mu, eo, mo)
+        worst_p = max(worst_p, ep, mp * tol_p / tol_pmax)
+        print(f"{label} step {step}: dt={st['dt']:.6f} (oracle cfl_dt rel diff {edt:.1e}) "
+              f"vc={st['vcycles']} div={st['resid'][0]:.2e},{st['resid'][1]:.2e} "
+              f"err_u={eu:.2e} (max {mu:.2e}) err_p={ep:.2e} (max {mp:.2e})"
+              + (f" err_uout={eo:.2e} (max {mo:.2e})" if outflow else ""), flush=True)
+        assert edt <= tol_dt
     assert worst_u <= tol_u and worst_p <= tol_p
     return worst_u, worst_p
 
@@ -164,6 +194,41 @@ def test_cylinder_fp64_replay_parity():
     assert uo.sum() == pytest.approx(64.0, rel=1e-12)
 
 
+@pytest.mark.parametrize("case", ["circle-2d-fp64", "sphere-3d-fp32"])
+def test_outflow_perturbed_replay_parity(case):
+    """Inflow / convective outflow channels started from a disturbed state
+    (smooth seeded modes on the velocity and on the outlet plane), so that the
+    outflow rule moves a non-uniform plane and the exit-flux balance shifts
+    it: velocity, pressure and the outflow plane against the oracle."""
+    import paper_2304_08159_amd as wl
+    if case == "circle-2d-fp64":
+        cfg = dict(n=(96, 48), bc_lo=[1, 3], bc_hi=[2, 3], U=(1.0, 0.0), nu=0.05,
+                   body=dict(centre=(24.0, 24.3), radius=5.0), tol=1e-10)
+        prec, tdev, tol = wl.WL_FP64, torch.float64, 1e-9
+    else:
+        cfg = dict(n=(64, 32, 32), bc_lo=[1, 3, 3], bc_hi=[2, 3, 3], U=(1.0, 0.0, 0.0),
+                   nu=0.08, body=dict(centre=(16.0, 16.2, 15.8), radius=4.0), tol=1e-5)
+        prec, tdev, tol = wl.WL_FP32, torch.float32, 1e-5
+    n = cfg["n"]
+    d = len(n)
+    sim, osim = _make(cfg, prec, cfg["tol"])
+    n3 = tuple(n) + (1,) * (3 - d)
+    modes = W.periodic_modes3d(n3, seed=11)
+    for i in range(d):
+        a = cfg["U"][i] + 0.3 * (modes[i][:, :, 0] if d == 2 else modes[i])
+        # boundary faces keep their boundary values (inflow U, wall 0)
+        if i == 0:
+            a[0] = cfg["U"][0]
+        else:
+            a[(slice(None),) * i + (0,)] = 0.0
+        sim.set(wl.FIELD_U0 + i, to_device(a, d, torch, tdev))
+    yz = modes[0][-1]                                     # a smooth (n1, n2) pattern
+    plane = cfg["U"][0] + 0.3 * (yz[:, 0] if d == 2 else yz)
+    sim.set(wl.FIELD_UOUT, torch.from_numpy(np.ascontiguousarray(
+        plane[None, :] if d == 2 else plane.T)).to(device="cuda", dtype=tdev))
+    _replay(sim, osim, 3, tol, tol * (100 if d == 2 else 1), case)
+
+
 def test_sphere_fp32_replay_parity():
     import paper_2304_08159_amd as wl
     cfg = dict(n=(64, 32, 32), bc_lo=[1, 3, 3], bc_hi=[2, 3, 3], U=(1.0, 0.0, 0.0),
@@ -227,7 +292,7 @@ def test_fused_predictor_projection_is_bitwise_identical():
                     torch.from_numpy(np.ascontiguousarray(a.transpose(2, 1, 0))).float().cuda())
         sim.tape(record)
         stats = [sim.step() for _ in range(5)]
-        runs.append((stats, sim.get_state().clone(), sim.pressure().clone()))
+        runs.append((stats, sim.get_flow().clone(), sim.pressure().clone()))
         sim.close()
     (sa, xa, pa), (sb, xb, pb) = runs
     assert sa == sb
@@ -249,7 +314,7 @@ def test_global_address_kernels_match_buffer_addressed_ones(monkeypatch):
         for i, a in enumerate((u, v, w)):
             sim.set(wl.FIELD_U0 + i, to_device(a, 3, torch, torch.float32))
         stats = [sim.step() for _ in range(3)]
-        runs.append((stats, sim.get_state().clone(), sim.pressure().clone()))
+        runs.append((stats, sim.get_flow().clone(), sim.pressure().clone()))
         sim.close()
     (sa, xa, pa), (sb, xb, pb) = runs
     assert sa == sb
@@ -270,7 +335,7 @@ def test_run_equals_repeated_steps_and_stops_at_t_end():
             sim.set(wl.FIELD_U0 + i,
                     torch.from_numpy(np.ascontiguousarray(a.transpose(2, 1, 0))).float().cuda())
         stats = [sim.step() for _ in range(5)] if mode == "step" else sim.run(5)
-        outs.append((stats, sim.get_state().clone(), sim.pressure().clone()))
+        outs.append((stats, sim.get_flow().clone(), sim.pressure().clone()))
         if mode == "run":
             t_end = stats[-1]["t"] + 1.5 * stats[-1]["dt"]
             more = sim.run(50, t_end=t_end)
@@ -339,3 +404,40 @@ def test_torus_rejected_where_unsupported():
     sim = wl.Sim(cfg["n"], cfg["bc_lo"], cfg["bc_hi"], cfg["U"], cfg["nu"], body=cfg["body"])
     with pytest.raises(wl.WlError):
         sim.drag()
+
+
+def test_cylinder_fp64_free_running_100_steps_matches_oracle():
+    """The 2D configuration as stated (128 x 64, circle D = 16, Re = 250, FP64,
+    4 levels, 100 CFL-adaptive steps, every solve to relative residual 1e-8):
+    the GPU and the oracle each run all 100 steps on their own (own dt, own
+    V-cycle counts) from the same start; the error of the final state against
+    the oracle is stated and bounded."""
+    import paper_2304_08159_amd as wl
+    cfg = W.cylinder_config()
+    sim = wl.Sim(cfg["n"], cfg["bc_lo"], cfg["bc_hi"], cfg["U"], cfg["nu"], body=cfg["body"],
+                 prec=wl.WL_FP64, levels=cfg["levels"], tol=cfg["tol"], cfl=cfg["cfl"],
+                 stop_rule=wl.STOP_RELATIVE)
+    osim = S.Sim(cfg["n"], cfg["bc_lo"], cfg["bc_hi"], cfg["U"], cfg["nu"], body=cfg["body"],
+                 levels=cfg["levels"], tol=cfg["tol"], cfl=cfg["cfl"], stop_rule="relative")
+    worst_dt = 0.0
+    for k in range(cfg["steps"]):
+        st = sim.step()
+        ost = osim.step()
+        worst_dt = max(worst_dt, abs(st["dt"] - ost["dt"]) / ost["dt"])
+        assert max(st["rel_resid"]) <= cfg["tol"]
+        if k % 20 == 19:
+            print(f"cylinder free-running step {k + 1}: t={st['t']:.4f} vc={st['vcycles']}",
+                  flush=True)
+    act = osim.h.active[0]
+    ug = [to_oracle(t, 2) for t in sim.velocity()]
+    eu = math.sqrt(sum(np.sum((a - b) ** 2) for a, b in zip(ug, osim.u)) /
+                   sum(np.sum(b ** 2) for b in osim.u))
+    mu = _max_rel(ug, osim.u)
+    pg, po = mean_free(to_oracle(sim.pressure(), 2), act), mean_free(osim.p, act)
+    ep, mp = rel_l2(pg, po, act), _max_rel([pg], [po])
+    eo = rel_l2(plane_to_oracle(sim.get(4), 2), osim.uout)
+    print(f"C1 free-running 100 steps (t = {osim.t:.4f}): dt rel diff max {worst_dt:.1e}, "
+          f"velocity {eu:.2e} (max {mu:.2e}), pressure {ep:.2e} (max {mp:.2e}), "
+          f"outflow plane {eo:.2e}")
+    assert worst_dt <= 1e-6
+    assert eu <= 1e-6 and mu <= 1e-6 and eo <= 1e-6 and ep <= 1e-5

@@ -136,3 +136,37 @@ def test_zero_rhs_and_not_converged_and_bad_args():
     with pytest.raises(wl.WlError) as e:
         ps.solve(None, x.zero_(), nan_b, tol=1e-6)
     assert e.value.status == -4
+
+
+@pytest.mark.parametrize("kind", ["box", "sphere"])
+def test_vcycle_contraction_gate_64_to_256(kind):
+    """Sec. 2: GMG solution time linear in the cell count, i.e. a contraction
+    per V-cycle that does not degrade with the grid.  The library's FP64 solve
+    on a Neumann box (L = 1, or BDIM coefficients of a centred sphere of radius
+    N/8) from x = 0 and a seeded N(0,1) right-hand side: the asymptotic rate
+    (mean of the last 3 of 10 cycles) at 64^3, 128^3 and 256^3, gated at 0.30
+    and at a growth of at most 0.05 from 64^3 to 256^3."""
+    import paper_2304_08159_amd as wl
+    rates = {}
+    for N in (64, 128, 256):
+        n = (N, N, N)
+        body = None if kind == "box" else dict(centre=(N / 2.0,) * 3, radius=N / 8.0)
+        L = wl.body_coeffs(n, (False,) * 3, body, prec=wl.WL_FP64)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(2304)
+        b = torch.randn((N, N, N), generator=g, dtype=torch.float64, device="cuda")
+        ps = wl.Poisson(n, (False,) * 3, prec=wl.WL_FP64)
+        x = torch.zeros_like(b)
+        hist = [1.0]
+        for k in range(10):
+            _, rel = ps.solve(L if k == 0 else None, x, b, tol=0.0, max_vcycles=1,
+                              allow_not_converged=True)
+            hist.append(rel)
+        ps.close()
+        rho = [hist[i + 1] / hist[i] for i in range(10)]
+        rates[N] = float(np.mean(rho[-3:]))
+        print(f"{kind} {N}^3: residual history {['%.2e' % r for r in hist]} "
+              f"asymptotic rate {rates[N]:.3f}", flush=True)
+        del L, b, x
+    assert max(rates.values()) <= 0.30
+    assert rates[256] - rates[64] <= 0.05

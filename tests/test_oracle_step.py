@@ -147,3 +147,18 @@ def test_drag_of_a_linear_pressure_is_minus_gradient_times_volume(n, centre, rad
         sim.p = p
         bound = np.sum(np.abs(p) * np.abs(normal[0]) * G.kernel(dist))
         assert abs(S.drag(sim)) <= 0.01 * bound
+
+
+def test_relative_stopping_rule_stops_at_the_first_cycle_below_tol():
+    """stop_rule "relative": each stage's solve ends at the first V-cycle whose
+    relative residual is <= tol, and not before."""
+    cfg = W.cylinder_config()
+    sim = S.Sim((32, 16), cfg["bc_lo"], cfg["bc_hi"], cfg["U"], 0.02,
+                body=dict(centre=(8.0, 8.0), radius=3.0), tol=1e-9, stop_rule="relative")
+    for _ in range(2):
+        st = sim.step()
+    for hist in st["resid"]:
+        assert hist[-1] <= 1e-9
+        assert all(r > 1e-9 for r in hist[:-1])
+    with pytest.raises(ValueError):
+        S.Sim((32, 16), cfg["bc_lo"], cfg["bc_hi"], cfg["U"], 0.02, stop_rule="rms")
