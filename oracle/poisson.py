@@ -36,6 +36,15 @@ for smoothing, kernel-friendly non-ordered relaxation):
     covers (the unit-spacing rediscretisation of the integrated operator);
   * coarsest level: minimum-norm least squares (a library routine);
   * V-cycles until ||b - A x||_2 / ||b||_2 <= tol, tested before each cycle.
+
+Smoother "cg" (the paper's own choice, Sec. 2: conjugate-gradient smoothing
+within the GMG levels, because relaxations that visit points in order cannot
+be written as kernels).  READINGS: each smoothing step is a fresh run of
+Jacobi-preconditioned CG on the level's system from the current iterate
+(nu1 = nu2 = 2 iterations, the counts of the Jacobi smoother), on the
+positive semi-definite M = -A with the preconditioner D = -diag(A)
+(inactive cells, D = 0, stay at zero); the coarsest level is solved exactly
+as with Jacobi.
 """
 
 import numpy as np
@@ -95,6 +104,57 @@ def jacobi(L, x, b, per, diag=None):
     r = b - apply_A(L, x, per)
     safe = np.where(diag != 0.0, diag, 1.0)
     return np.where(diag != 0.0, x + omega(d) * r / safe, 0.0)
+
+
+def pcg_smooth(L, x, b, per, iters, diag=None, history=None):
+    """`iters` Jacobi-preconditioned conjugate-gradient iterations on A x = b
+    from x, written for M = -A, c = -b (M positive semi-definite) with the
+    preconditioner D = -diag(A):
+
+        r = P(c - M x),  z = r / D,  p = z
+        repeat: q = M p, alpha = (r.z) / (p.q), x += alpha p, r = P(r - alpha q),
+                z' = r / D, beta = (r.z') / (r.z)_old, p = z' + beta p,
+
+    P removing the mean over the active cells.  P keeps the residual in the
+    range of M (orthogonal to its null vector, the constant on the active
+    cells); in exact arithmetic it changes nothing (b is mean-free, and
+    1.M v = 0 for every v), in rounding it keeps iterations past the
+    solution's rounding floor from diverging (READING: CG on the singular
+    system restricted to the range of M).  Stops early when r.z or p.q
+    vanishes (the iterate is then exact).  With `history` (a list) each
+    iteration's (r, z, p) before the update is appended, for the conjugacy
+    pins."""
+    if diag is None:
+        diag = diag_A(L, per)
+    D = -diag
+    act = D > 0.0
+    safe = np.where(act, D, 1.0)
+
+    def M(v):
+        return -apply_A(L, v, per)
+
+    x = np.where(act, x, 0.0)
+    r = remove_mean(np.where(act, -b - M(x), 0.0), act)
+    z = np.where(act, r / safe, 0.0)
+    p = z.copy()
+    rz = float(np.sum(r * z))
+    for _ in range(iters):
+        if rz == 0.0:
+            break
+        q = M(p)
+        pq = float(np.sum(p * q))
+        if pq == 0.0:
+            break
+        if history is not None:
+            history.append((r.copy(), z.copy(), p.copy()))
+        alpha = rz / pq
+        x = x + alpha * p
+        r = remove_mean(r - alpha * q, act)
+        z = np.where(act, r / safe, 0.0)
+        rz_new = float(np.sum(r * z))
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return x
 
 
 def restrict(r):
@@ -188,9 +248,14 @@ def dense_matrix(L, per):
 
 
 class Hierarchy:
-    """Coefficients of every level plus the coarsest pseudo-inverse (cached)."""
+    """Coefficients of every level plus the coarsest pseudo-inverse (cached).
+    smoother: "jacobi" (damped Jacobi sweeps) or "cg" (Jacobi-preconditioned
+    CG iterations), NU1 before and NU2 after the coarse correction."""
 
-    def __init__(self, L, nlev, per):
+    def __init__(self, L, nlev, per, smoother="jacobi"):
+        if smoother not in ("jacobi", "cg"):
+            raise ValueError("smoother must be 'jacobi' or 'cg'")
+        self.smoother = smoother
         self.per = list(per)
         self.L = [list(L)]
         for _ in range(nlev - 1):
@@ -214,13 +279,19 @@ def vcycle(h, lev, x, b):
     L, per, diag = h.L[lev], h.per, h.diag[lev]
     if lev == h.nlev - 1:
         return h.coarse_solve(b)
-    for _ in range(NU1):
-        x = jacobi(L, x, b, per, diag)
+    if h.smoother == "cg":
+        x = pcg_smooth(L, x, b, per, NU1, diag)
+    else:
+        for _ in range(NU1):
+            x = jacobi(L, x, b, per, diag)
     r = b - apply_A(L, x, per)
     xc = vcycle(h, lev + 1, np.zeros(tuple(m // 2 for m in x.shape)), restrict(r))
     x = x + prolong(xc, per)
-    for _ in range(NU2):
-        x = jacobi(L, x, b, per, diag)
+    if h.smoother == "cg":
+        x = pcg_smooth(L, x, b, per, NU2, diag)
+    else:
+        for _ in range(NU2):
+            x = jacobi(L, x, b, per, diag)
     return x
 
 

@@ -256,3 +256,121 @@ def test_zero_rhs_returns_zero_and_replay_count_is_exact():
     b = np.random.default_rng(7).standard_normal(n)
     x, k, hist, ok = P.solve(h, b, force_vcycles=3)
     assert k == 3 and len(hist) == 4
+
+
+# ---------------------------------------------------------------- CG smoother
+
+def _small_problem(n, per, seed, solid=True):
+    rng = np.random.default_rng(seed)
+    d = len(n)
+    L = [rng.uniform(0.3, 1.0, n) for _ in range(d)]
+    for i in range(d):
+        if not per[i]:
+            idx = [slice(None)] * d
+            idx[i] = 0
+            L[i][tuple(idx)] = 0.0          # Neumann domain faces
+    if solid:
+        # one fully solid cell: all of its faces closed
+        c = tuple(m // 2 for m in n)
+        for i in range(d):
+            L[i][c] = 0.0
+            up = list(c)
+            up[i] += 1
+            if up[i] < n[i]:
+                L[i][tuple(up)] = 0.0
+    b = rng.standard_normal(n)
+    return L, b
+
+
+@pytest.mark.parametrize("n,per", [((8, 8), (False, False)), ((4, 4, 4), (True, False, True))])
+def test_pcg_terminates_at_the_min_norm_solution(n, per):
+    """Conjugate gradients end at the exact solution within (number of active
+    cells) iterations: against the dense least-squares minimum-norm solution."""
+    L, b = _small_problem(n, per, 3)
+    act = P.active_mask(L, list(per))
+    bp = P.project_rhs(b, act)
+    xs = P.min_norm_solution(L, list(per), b)
+    x = P.pcg_smooth(L, np.zeros(n), bp, list(per), int(act.sum()) + 5)
+    assert np.abs(P.remove_mean(x, act) - xs).max() <= 1e-9 * np.abs(xs).max()
+    assert np.all(x[~act] == 0.0)
+
+
+def test_pcg_iterate_minimises_the_energy_error_over_the_krylov_space():
+    """The defining property of preconditioned CG: after k iterations from x0,
+    x_k minimises the M-norm error (M = -A) over x0 + span{z0, (D^-1 M) z0, ...,
+    (D^-1 M)^(k-1) z0}, z0 = D^-1 r0.  Brute force: the Krylov basis is built
+    explicitly and the minimisation solved by dense least squares; a wrong
+    step length, direction update, sign or preconditioner breaks it."""
+    n, per = (6, 5, 4), [False, True, False]
+    L, b = _small_problem(n, per, 4)
+    act = P.active_mask(L, per)
+    bp = P.project_rhs(b, act)
+    A = P.dense_matrix(L, per)
+    M = -A
+    D = np.diag(M).copy()
+    Dinv = np.where(D > 0, 1.0 / np.where(D > 0, D, 1.0), 0.0)
+    xs = P.min_norm_solution(L, per, b).reshape(-1)
+    x0 = np.random.default_rng(8).standard_normal(n) * act
+    r0 = -bp.reshape(-1) - M @ x0.reshape(-1)
+    for k in (1, 2, 3, 5):
+        K = [Dinv * r0]
+        for _ in range(k - 1):
+            K.append(Dinv * (M @ K[-1]))
+        K = np.stack(K, axis=1)
+        # min over y of (x0 + K y - xs)^T M (x0 + K y - xs)
+        y = np.linalg.lstsq(K.T @ M @ K, K.T @ M @ (xs - x0.reshape(-1)), rcond=None)[0]
+        want = x0.reshape(-1) + K @ y
+        got = P.pcg_smooth(L, x0, bp, per, k).reshape(-1)
+        e = got - want
+        assert np.sqrt(abs(e @ M @ e)) <= 1e-9 * np.sqrt(abs(want @ M @ want)), k
+
+
+def test_pcg_residuals_and_directions_are_conjugate():
+    """Preconditioned residuals are mutually orthogonal (r_i . z_j = 0) and
+    search directions M-conjugate (p_i . M p_j = 0) for i != j."""
+    n, per = (7, 6, 5), [True, False, False]
+    L, b = _small_problem(n, per, 5)
+    act = P.active_mask(L, per)
+    bp = P.project_rhs(b, act)
+    hist = []
+    P.pcg_smooth(L, np.zeros(n), bp, per, 6, history=hist)
+    assert len(hist) == 6
+    Mp = [-P.apply_A(L, h[2], per) for h in hist]
+    for i in range(6):
+        for j in range(6):
+            if i == j:
+                continue
+            ri, zj = hist[i][0], hist[j][1]
+            assert abs(np.sum(ri * zj)) <= 1e-10 * np.sqrt(np.sum(ri * hist[i][1]) *
+                                                          np.sum(hist[j][0] * zj))
+            pi, pj = hist[i][2], hist[j][2]
+            assert abs(np.sum(pi * Mp[j])) <= 1e-10 * np.sqrt(np.sum(pi * Mp[i]) *
+                                                             np.sum(pj * Mp[j]))
+
+
+def test_gmg_with_cg_smoothing_matches_dense_solve_and_contracts():
+    """The V-cycle with CG smoothing (Sec. 2's smoother) converges to the
+    minimum-norm solution, and contracts at least as fast per cycle as the
+    Jacobi V-cycle, without degrading from 32^3 to 64^3."""
+    for n, per in [((8, 8), [False, False]), ((8, 8, 8), [True, False, True])]:
+        L, b = _small_problem(n, per, 6)
+        h = P.Hierarchy(L, auto_levels(n), per, smoother="cg")
+        x, k, hist, ok = P.solve(h, b, tol=1e-12, max_vcycles=100)
+        assert ok
+        act = h.active[0]
+        xs = P.min_norm_solution(L, per, b)
+        assert np.abs(P.remove_mean(x, act) - xs).max() <= 1e-9 * np.abs(xs).max()
+    rates = {}
+    for N in (32, 64):
+        n = (N, N, N)
+        body = dict(centre=(N / 2.0,) * 3, radius=N / 8.0)
+        L = G.measure(n, [WALL] * 3, body)[2]
+        bb = np.random.default_rng(6).standard_normal(n)
+        for sm in ("jacobi", "cg"):
+            h = P.Hierarchy(L, auto_levels(n), [False] * 3, smoother=sm)
+            _, _, hist, _ = P.solve(h, bb, tol=0.0, max_vcycles=10)
+            rates[(N, sm)] = float(np.mean([hist[i + 1] / hist[i] for i in range(7, 10)]))
+    assert rates[(32, "cg")] < rates[(32, "jacobi")] and rates[(64, "cg")] < rates[(64, "jacobi")]
+    assert rates[(64, "cg")] <= 0.2 and rates[(64, "cg")] - rates[(32, "cg")] <= 0.05
+    with pytest.raises(ValueError):
+        P.Hierarchy(L, 2, [False] * 3, smoother="sor")
