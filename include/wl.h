@@ -309,6 +309,23 @@ wl_status wl_poisson_batch_footprint(const wl_batch_request* reqs, int count, si
 wl_status wl_poisson_batch_solve(const wl_batch_request* reqs, int count, void* workspace,
                                  size_t ws_bytes, void* hip_stream, wl_batch_result* results);
 
+/* wl_poisson_batch_solve for callers that cannot allocate memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same requests, method, kernel and results (bitwise), with no workspace
+ * argument.  The batch's device scratch (request table, results, queue head
+ * and every request's multigrid level arrays, wl_poisson_batch_footprint
+ * bytes) lives in a 32 MiB array of device memory that the library holds per
+ * GPU for the life of the process; the host side uses fixed tables.  The call
+ * makes no device or pinned allocation.  Limits: at most 256 requests, and a
+ * footprint of at most 32 MiB (e.g. 64 requests of 128^2 cells); larger
+ * batches return WL_ERR_INVALID_ARG with a message naming the size.  Every
+ * call on one GPU uses that GPU's single scratch array: calls that overlap on
+ * the same GPU (from several threads or streams) race and must be
+ * serialised by the caller; this process serialises the host part itself.
+ * Synchronises hip_stream; results as wl_poisson_batch_solve. */
+wl_status wl_poisson_batch_solve_noalloc(const wl_batch_request* reqs, int count,
+                                         void* hip_stream, wl_batch_result* results);
+
 /* BDIM-modified Poisson coefficients of a body (Sec. 2): L_i = mu0 of the
  * signed distance at every lower i-face centre (cosine kernel of half-width
  * body->eps, <= 0 selects 1 cell), zero on non-periodic lower boundary faces;

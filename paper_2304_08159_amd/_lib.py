@@ -32,7 +32,7 @@ EXPORTS = (
     "wl_drag", "wl_tape_record", "wl_step_adjoint",
     "wl_poisson_footprint", "wl_poisson_create",
     "wl_poisson_solve", "wl_poisson_destroy", "wl_poisson_batch_footprint",
-    "wl_poisson_batch_solve", "wl_body_coeffs",
+    "wl_poisson_batch_solve", "wl_poisson_batch_solve_noalloc", "wl_body_coeffs",
     "wl_set_graphs", "wl_set_fused_sweeps",
     "wl_profile_enable",
     "wl_profile_reset",
@@ -120,6 +120,8 @@ def load():
         "wl_poisson_batch_footprint": [ctypes.POINTER(BatchRequest), i32, ctypes.POINTER(sz)],
         "wl_poisson_batch_solve": [ctypes.POINTER(BatchRequest), i32, vp, sz, vp,
                                    ctypes.POINTER(BatchResult)],
+        "wl_poisson_batch_solve_noalloc": [ctypes.POINTER(BatchRequest), i32, vp,
+                                           ctypes.POINTER(BatchResult)],
         "wl_body_coeffs": [ctypes.POINTER(Body), i32, ip3, ip3, i32, vp, vp],
         "wl_set_graphs": [i32],
         "wl_set_fused_sweeps": [i32],

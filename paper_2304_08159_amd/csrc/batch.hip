@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -193,26 +194,68 @@ wl_status plan_one(const wl_batch_request& in, Carver& c, BatchReq& q) {
 }
 
 struct BatchLayout {
-    std::vector<BatchReq> reqs;
     BatchReq* dev_reqs = nullptr;
     BatchRes* dev_res = nullptr;
     unsigned* dev_head = nullptr;
 };
 
-wl_status plan(const wl_batch_request* reqs, int count, Carver& c, BatchLayout& lay) {
+// Checks every request and carves the batch's device arrays from c; with
+// table non-null, also fills the count request descriptors there.
+wl_status plan(const wl_batch_request* reqs, int count, Carver& c, BatchLayout& lay,
+               BatchReq* table) {
     if (count < 0) return set_error("count must be >= 0"), WL_ERR_INVALID_ARG;
     if (count > 0 && !reqs) return set_error("reqs is NULL"), WL_ERR_INVALID_ARG;
-    lay.reqs.resize(size_t(count));
     lay.dev_reqs = c.take<BatchReq>(size_t(count > 0 ? count : 1));
     lay.dev_res = c.take<BatchRes>(size_t(count > 0 ? count : 1));
     lay.dev_head = c.take<unsigned>(1);
     for (int r = 0; r < count; ++r) {
-        const wl_status st = plan_one(reqs[r], c, lay.reqs[r]);
+        BatchReq q;
+        const wl_status st = plan_one(reqs[r], c, q);
         if (st != WL_OK) {
             set_error("request " + std::to_string(r) + ": " + last_error_text());
             return st;
         }
+        if (table) table[r] = q;
     }
+    return WL_OK;
+}
+
+// ------------------------------------------------ no-allocation variant
+// Device scratch of wl_poisson_batch_solve_noalloc: the request table, the
+// results, the queue head and every request's level arrays, carved exactly as
+// from a caller workspace.  One copy per GPU, held until the process ends.
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+// Device address of this GPU's copy of `scratch`, looked up once per device
+// with that device current (the host-side name of the array is not a device
+// address and must never be handed to a kernel or a copy).
+constexpr int kMaxDevices = 64;
+constexpr int kNoAllocMaxRequests = 256;
+std::mutex g_noalloc_host_mu;
+BatchReq g_noalloc_table[kNoAllocMaxRequests];
+BatchRes g_noalloc_res[kNoAllocMaxRequests];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+wl_status scratch_for_current_device(void** out) {
+    int dev = 0;
+    WL_CHECK_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device index beyond the no-allocation scratch table");
+        return WL_ERR_INVALID_ARG;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        WL_CHECK_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr || reinterpret_cast<uintptr_t>(ptr) % 256) {
+            set_error("scratch symbol address is null or misaligned");
+            return WL_ERR_HIP;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
     return WL_OK;
 }
 
@@ -227,28 +270,12 @@ int compute_units() {
     return n;
 }
 
-}  // namespace
-}  // namespace wl
-
-using namespace wl;
-
-extern "C" {
-
-wl_status wl_poisson_batch_footprint(const wl_batch_request* reqs, int count, size_t* bytes) {
-    clear_error();
-    if (!bytes) return set_error("bytes is NULL"), WL_ERR_INVALID_ARG;
-    Carver c;
-    BatchLayout lay;
-    WL_TRY(plan(reqs, count, c, lay));
-    *bytes = c.off;
-    return WL_OK;
-}
-
-wl_status wl_poisson_batch_solve(const wl_batch_request* reqs, int count, void* workspace,
-                                 size_t ws_bytes, void* hip_stream, wl_batch_result* results) {
-    clear_error();
-    if (count == 0) return WL_OK;
-    if (!workspace || !results) return set_error("workspace / results is NULL"), WL_ERR_INVALID_ARG;
+// Plans the batch into workspace (>= its footprint, 256-byte aligned),
+// uploads the request table (host staging: table, count entries) and a zero
+// queue head, runs the persistent kernel on hip_stream and copies the results
+// back through res (count entries; synchronises).
+wl_status batch_run(const wl_batch_request* reqs, int count, void* workspace, size_t ws_bytes,
+                    void* hip_stream, wl_batch_result* results, BatchReq* table, BatchRes* res) {
     if (reinterpret_cast<uintptr_t>(workspace) % 256)
         return set_error("workspace must be 256-byte aligned"), WL_ERR_INVALID_ARG;
     for (int r = 0; r < count && reqs; ++r)
@@ -258,7 +285,7 @@ wl_status wl_poisson_batch_solve(const wl_batch_request* reqs, int count, void* 
         }
     Carver need;
     BatchLayout dry;
-    WL_TRY(plan(reqs, count, need, dry));
+    WL_TRY(plan(reqs, count, need, dry, nullptr));
     if (ws_bytes < need.off) {
         set_error("workspace smaller than wl_poisson_batch_footprint");
         return WL_ERR_OUT_OF_MEMORY;
@@ -266,19 +293,18 @@ wl_status wl_poisson_batch_solve(const wl_batch_request* reqs, int count, void* 
     Carver c;
     c.base = static_cast<char*>(workspace);
     BatchLayout lay;
-    WL_TRY(plan(reqs, count, c, lay));
+    WL_TRY(plan(reqs, count, c, lay, table));
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-    // request table and a zero queue head in one upload
-    std::vector<char> up(sizeof(BatchReq) * size_t(count));
-    std::memcpy(up.data(), lay.reqs.data(), up.size());
+    // request table and a zero queue head (the no-allocation scratch keeps
+    // the last call's contents, so the head is cleared on every call)
     const unsigned zero = 0u;
-    WL_CHECK_HIP(hipMemcpyAsync(lay.dev_reqs, up.data(), up.size(), hipMemcpyHostToDevice, s));
+    WL_CHECK_HIP(hipMemcpyAsync(lay.dev_reqs, table, sizeof(BatchReq) * size_t(count),
+                                hipMemcpyHostToDevice, s));
     WL_CHECK_HIP(hipMemcpyAsync(lay.dev_head, &zero, sizeof(zero), hipMemcpyHostToDevice, s));
     const int grid = std::min(count, compute_units());
     k_poisson_batch<<<grid, kBatchThreads, 0, s>>>(lay.dev_reqs, count, lay.dev_head, lay.dev_res);
     WL_CHECK_HIP(hipGetLastError());
-    std::vector<BatchRes> res(static_cast<size_t>(count));
-    WL_CHECK_HIP(hipMemcpyAsync(res.data(), lay.dev_res, sizeof(BatchRes) * size_t(count),
+    WL_CHECK_HIP(hipMemcpyAsync(res, lay.dev_res, sizeof(BatchRes) * size_t(count),
                                 hipMemcpyDeviceToHost, s));
     WL_CHECK_HIP(hipStreamSynchronize(s));
     wl_status worst = WL_OK;
@@ -291,6 +317,62 @@ wl_status wl_poisson_batch_solve(const wl_batch_request* reqs, int count, void* 
     if (worst == WL_ERR_NOT_CONVERGED) set_error("some batch requests reached max_vcycles");
     if (worst == WL_ERR_NONFINITE) set_error("non-finite residual in a batch request");
     return worst;
+}
+
+}  // namespace
+}  // namespace wl
+
+using namespace wl;
+
+extern "C" {
+
+wl_status wl_poisson_batch_footprint(const wl_batch_request* reqs, int count, size_t* bytes) {
+    clear_error();
+    if (!bytes) return set_error("bytes is NULL"), WL_ERR_INVALID_ARG;
+    Carver c;
+    BatchLayout lay;
+    WL_TRY(plan(reqs, count, c, lay, nullptr));
+    *bytes = c.off;
+    return WL_OK;
+}
+
+wl_status wl_poisson_batch_solve(const wl_batch_request* reqs, int count, void* workspace,
+                                 size_t ws_bytes, void* hip_stream, wl_batch_result* results) {
+    clear_error();
+    if (count == 0) return WL_OK;
+    if (!workspace || !results) return set_error("workspace / results is NULL"), WL_ERR_INVALID_ARG;
+    if (count < 0) return set_error("count must be >= 0"), WL_ERR_INVALID_ARG;
+    std::vector<BatchReq> table(static_cast<size_t>(count));
+    std::vector<BatchRes> res(static_cast<size_t>(count));
+    return batch_run(reqs, count, workspace, ws_bytes, hip_stream, results, table.data(),
+                     res.data());
+}
+
+wl_status wl_poisson_batch_solve_noalloc(const wl_batch_request* reqs, int count,
+                                         void* hip_stream, wl_batch_result* results) {
+    clear_error();
+    if (count == 0) return WL_OK;
+    if (!results) return set_error("results is NULL"), WL_ERR_INVALID_ARG;
+    if (count < 0 || count > kNoAllocMaxRequests) {
+        set_error("the no-allocation entry point takes 0 to " +
+                  std::to_string(kNoAllocMaxRequests) + " requests per call");
+        return WL_ERR_INVALID_ARG;
+    }
+    Carver need;
+    BatchLayout dry;
+    WL_TRY(plan(reqs, count, need, dry, nullptr));
+    if (need.off > kNoAllocScratchBytes) {
+        set_error("batch needs " + std::to_string(need.off) + " bytes of scratch; the "
+                  "no-allocation entry point holds " + std::to_string(kNoAllocScratchBytes) +
+                  " (use wl_poisson_batch_solve with a workspace)");
+        return WL_ERR_INVALID_ARG;
+    }
+    void* ws = nullptr;
+    WL_TRY(scratch_for_current_device(&ws));
+    // fixed host staging (no heap); one call at a time in this process
+    std::lock_guard<std::mutex> lock(g_noalloc_host_mu);
+    return batch_run(reqs, count, ws, kNoAllocScratchBytes, hip_stream, results, g_noalloc_table,
+                     g_noalloc_res);
 }
 
 }  // extern "C"
