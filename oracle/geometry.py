@@ -24,6 +24,18 @@ are the contract:
       mu0_i = mu0(d),  (mu1 n)_ij = mu1(d) n_j,  L_i = mu0_i,
     and L_i = 0 on non-periodic domain-boundary faces (Neumann pressure).
 
+Moving bodies.  Sec. 2 defines a body by its signed-distance function and a
+coordinate map.  READING for rigid motion: the map takes x to the body frame
+xi = R(t)^T (x - X(t)), so d(x, t) = d0(xi), with
+  X(t) = c + V t + A sin(omega t)   (centre path: drift plus oscillation),
+  R(t) = rotation by |Omega| t about Omega (a constant spin),
+and the body velocity is the map's velocity field,
+  V_b(x, t) = dX/dt + Omega x (x - X(t)),  dX/dt = V + A omega cos(omega t),
+whose gradient is dV_b,i/dx_j = eps_ikj Omega_k.  Spin is read for spheres
+and circles only (their SDF does not change under rotation about the
+centre; only V_b does); a scalar spin turns about z.  The body is
+re-measured at every step.
+
 Pins: closed-form values of mu0/mu1 at 0 and +-eps, derivative identities
 mu0' = K, mu1' = -d K (finite differences), the excluded volume
 sum(1 - mu0) -> body volume (sphere 4/3 pi R^3, torus 2 pi^2 R a^2), the
@@ -103,6 +115,65 @@ def torus_sdf(X, centre, radius, radius2):
     return q - radius2, normal
 
 
+def is_moving(body):
+    if body is None:
+        return False
+    keys = ("velocity", "amplitude", "spin")
+    return any(np.any(np.asarray(body.get(k, 0.0), dtype=np.float64) != 0.0) for k in keys)
+
+
+def _vec3(v):
+    a = np.zeros(3)
+    v = np.atleast_1d(np.asarray(v, dtype=np.float64))
+    a[:v.size] = v
+    return a
+
+
+def _spin3(body):
+    """Angular velocity as a 3-vector; a scalar spin is about z (2D bodies)."""
+    w = np.asarray(body.get("spin", 0.0), dtype=np.float64)
+    return np.array([0.0, 0.0, float(w)]) if w.ndim == 0 else _vec3(w)
+
+
+def body_motion(body, t):
+    """Centre X(t), translation velocity dX/dt and angular velocity Omega
+    (3-vectors) of a rigidly moving body."""
+    c = _vec3(body["centre"])
+    V = _vec3(body.get("velocity", 0.0))
+    A = _vec3(body.get("amplitude", 0.0))
+    w = float(body.get("omega", 0.0))
+    spin = _spin3(body)
+    X = c + V * t + A * math.sin(w * t)
+    Xdot = V + A * w * math.cos(w * t)
+    return X, Xdot, spin
+
+
+def body_at(body, t):
+    """The body as placed at time t (its centre moved along the path)."""
+    if body is None or not is_moving(body):
+        return body
+    X, _, _ = body_motion(body, t)
+    out = dict(body)
+    out["centre"] = tuple(X[:len(body["centre"])])
+    return out
+
+
+def body_velocity(X, body, t):
+    """V_b(x, t) = dX/dt + Omega x (x - X(t)) at the points X (one array per axis)."""
+    d = len(X)
+    Xc, Xdot, W = body_motion(body, t)
+    r = [X[j] - Xc[j] for j in range(d)] + [np.zeros_like(X[0])] * (3 - d)
+    cross = [W[1] * r[2] - W[2] * r[1], W[2] * r[0] - W[0] * r[2], W[0] * r[1] - W[1] * r[0]]
+    return [Xdot[i] + cross[i] for i in range(d)]
+
+
+def body_velocity_gradient(body, d):
+    """G_ij = dV_b,i / dx_j = eps_ikj Omega_k (constant for rigid motion)."""
+    W = _spin3(body)
+    G = np.array([[0.0, -W[2], W[1]], [W[2], 0.0, -W[0]], [-W[1], W[0], 0.0]])
+    return G[:d, :d]
+
+
 def body_sdf(X, body):
     """SDF and normal of a body dict: a sphere/circle, or kind="torus" (radius2 = tube)."""
     if body.get("kind", "sphere") == "torus":
@@ -110,14 +181,17 @@ def body_sdf(X, body):
     return sphere_sdf(X, body["centre"], body["radius"])
 
 
-def measure(n, bc_lo, body=None, eps=1.0):
+def measure(n, bc_lo, body=None, eps=1.0, t=0.0):
     """BDIM moments and fine-level Poisson coefficients.
 
     body: None, dict(centre=(..), radius=R), or dict(kind="torus", centre, radius,
-    radius2).  Returns (mu0[i], mu1n[i][j], L[i])
-    with every array shaped like the grid.  Without a body mu0 = 1, mu1n = 0.
+    radius2), optionally with motion (velocity, amplitude, omega, spin; the
+    body is then measured where it is at time t).  Returns (mu0[i], mu1n[i][j],
+    L[i]) with every array shaped like the grid.  Without a body mu0 = 1,
+    mu1n = 0.
     """
     d = len(n)
+    body = body_at(body, t)
     m0, m1n, L = [], [], []
     for i in range(d):
         if body is None:

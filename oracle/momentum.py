@@ -23,8 +23,12 @@ CFL!.  dt = cfl / (max_I sum_i [max(u_i(I+delta_i), 0) - min(u_i(I), 0)]
                    + 2 d nu),
 the per-cell total outflow velocity plus the explicit viscous limit.
 
-BDIM! (body at rest).  u*_i = mu0_i f_i + sum_j (mu1 n)_ij (f_i(I+delta_j)
-- f_i(I-delta_j))/2 on interior faces.
+BDIM!.  u*_i = mu0_i f_i + (1 - mu0_i) V_b,i
+               + sum_j (mu1 n)_ij [(f_i(I+delta_j) - f_i(I-delta_j))/2 - G_ij]
+on interior faces: the first-order blend of the fluid and body velocities
+with the normal-derivative correction mu1 d/dn (f - V_b), V_b the body
+velocity at the face and G_ij = dV_b,i/dx_j (constant for rigid motion); a
+body at rest has V_b = 0, G = 0.
 
 BC!.  Ghost values with two layers per side:
   periodic wrap; INFLOW ghosts (all components) = U; free-slip WALL: normal
@@ -225,19 +229,25 @@ def cfl_dt(u, uout, bc_lo, bc_hi, U, nu, cfl):
     return cfl / denom
 
 
-def bdim(f, mu0, mu1n, bc_lo, bc_hi, U, fout=None):
-    """First-order BDIM blend of the stage velocity f (body at rest)."""
+def bdim(f, mu0, mu1n, bc_lo, bc_hi, U, fout=None, Vb=None, G=None):
+    """First-order BDIM blend of the stage velocity f.  Vb: body velocity per
+    component at the faces (None: at rest); G: its constant gradient."""
     d = len(f)
     n = f[0].shape
     Pf = pad_velocity(f, fout, bc_lo, bc_hi, U)
     out = []
     for i in range(d):
         g = mu0[i] * f[i]
+        if Vb is not None:
+            g = g + (1.0 - mu0[i]) * Vb[i]
         for j in range(d):
             dj = [1 if a == j else 0 for a in range(d)]
             fp = _view(Pf[i], n, dj)
             fm = _view(Pf[i], n, [-x for x in dj])
-            g = g + mu1n[i][j] * 0.5 * (fp - fm)
+            dn = 0.5 * (fp - fm)
+            if G is not None:
+                dn = dn - G[i][j]
+            g = g + mu1n[i][j] * dn
         out.append(g)
     return out
 

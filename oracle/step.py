@@ -64,7 +64,8 @@ def drag(sim):
     if sim.body is None:
         return 0.0
     X = geometry.cell_centres(sim.n)
-    dist, normal = geometry.sphere_sdf(X, sim.body["centre"], sim.body["radius"])
+    body = geometry.body_at(sim.body, sim.t)
+    dist, normal = geometry.sphere_sdf(X, body["centre"], body["radius"])
     w = normal[0] * geometry.kernel(dist)
     act = sim.h.active[0]
     p = sim.p[act]
@@ -72,10 +73,12 @@ def drag(sim):
 
 
 class Sim:
-    """FP64 reference of one NS configuration (uniform grid, optional sphere)."""
+    """FP64 reference of one NS configuration (uniform grid, optional body,
+    at rest or in rigid motion)."""
 
     def __init__(self, n, bc_lo, bc_hi, U, nu, body=None, cfl=0.5, tol=1e-8,
-                 max_vcycles=100, levels=0, eps=1.0, stop_rule="divergence"):
+                 max_vcycles=100, levels=0, eps=1.0, stop_rule="divergence",
+                 smoother="jacobi"):
         if stop_rule not in ("divergence", "relative"):
             raise ValueError("stop_rule must be 'divergence' or 'relative'")
         self.stop_rule = stop_rule
@@ -86,13 +89,26 @@ class Sim:
         self.nu, self.cfl, self.tol, self.max_vcycles = nu, cfl, tol, max_vcycles
         self.body = body
         self.per = [b == PERIODIC for b in bc_lo]
-        self.mu0, self.mu1n, self.L = geometry.measure(self.n, bc_lo, body, eps)
-        self.h = poisson.Hierarchy(self.L, auto_levels(self.n, levels), self.per)
+        self.eps, self.nlev, self.smoother = eps, auto_levels(self.n, levels), smoother
+        self.moving = geometry.is_moving(body)
+        self.Vb = self.G = None
+        self._measure(0.0)
         self.u = [np.full(self.n, self.U[i]) for i in range(self.d)]
         self._set_boundary(self.u)
         self.uout = np.full(self.n[1:], self.U[0]) if bc_hi[0] == OUTFLOW else None
         self.p = np.zeros(self.n)
         self.t = 0.0
+
+    def _measure(self, t):
+        """BDIM moments, coefficients and hierarchy of the body where it is at
+        time t (moving bodies are re-measured every step, at the time the
+        step's stages advance to), and its velocity at the faces."""
+        self.mu0, self.mu1n, self.L = geometry.measure(self.n, self.bc_lo, self.body, self.eps, t)
+        self.h = poisson.Hierarchy(self.L, self.nlev, self.per, self.smoother)
+        if self.moving:
+            self.Vb = [geometry.body_velocity(geometry.face_centres(self.n, i), self.body, t)[i]
+                       for i in range(self.d)]
+            self.G = geometry.body_velocity_gradient(self.body, self.d)
 
     def _set_boundary(self, u):
         for i in range(self.d):
@@ -114,7 +130,8 @@ class Sim:
             f = [0.5 * (u_n[i] + u_e[i] + dt * R[i]) for i in range(self.d)]
             fout = None if Rout is None else 0.5 * (out_n + out_e + dt * Rout)
         if self.body is not None:
-            f = momentum.bdim(f, self.mu0, self.mu1n, self.bc_lo, self.bc_hi, self.U, fout)
+            f = momentum.bdim(f, self.mu0, self.mu1n, self.bc_lo, self.bc_hi, self.U, fout,
+                              self.Vb, self.G)
         f = self._set_boundary(f)
         fout = momentum.exit_flux_correct(f, fout, self.bc_lo, self.bc_hi)
         sigma = divergence(f, fout, self.bc_lo, self.bc_hi, self.U) / (c * dt)
@@ -132,6 +149,9 @@ class Sim:
     def step(self, dt=None, force_vcycles=(None, None)):
         if dt is None or dt <= 0.0:
             dt = self.dt_cfl()
+        if self.moving:
+            # both stages advance to t + dt: the body is placed there
+            self._measure(self.t + dt)
         u1, o1, p1, k1, h1 = self.stage(1.0, dt, self.u, self.uout, self.u, self.uout,
                                         force_vcycles[0])
         self.p = p1
