@@ -1,15 +1,21 @@
 """Benchmark: 3D Taylor-Green vortex time steps on one MI355X.
 
 Workload (the metric configuration): triply periodic TGV, N^3 = 256^3 cells,
-FP32 fields and FP32 GMG pressure solves to relative residual 1e-5, Re = 1600,
-no body, CFL-adaptive Heun steps.  A step is one full pass of the hot path:
-CFL time step, two stages of convection-diffusion + divergence + GMG solve +
-projection.  Inputs are resident in HBM before the timed region.
+FP32 fields and FP32 GMG pressure solves, Re = 1600, no body, CFL-adaptive
+Heun steps.  The in-step solves stop once the divergence they leave in the
+projected velocity has an RMS of at most 1e-5 (the configuration's FP32 GMG
+tolerance read as a divergence bound: an FP32 pressure's rounding alone
+floors the relative residual near 6e-5 at 256^3); the relative residuals the
+solves actually reach are reported beside it.  A step is one full pass of the
+hot path: CFL time step, two stages of convection-diffusion + divergence +
+GMG solve + projection.  Inputs are resident in HBM before the timed region.
 
 Prints one JSON line: cell-steps/s, the roofline of the dominant kernel
 (algorithmic bytes / HIP-event-timed launch duration vs 8 TB/s), the
-whole-step algorithmic-byte fraction, and the FP64 oracle timed on the host
-as a CPU baseline.
+whole-step algorithmic-byte fraction, a leg with a fixed number of V-cycles
+per solve (the GMG loaded: per-V-cycle time and bytes), the standalone
+Poisson solve (mixed vs FP64, with its roofline by the byte model below) and
+the FP64 oracle timed on the host as a CPU baseline.
 """
 
 import argparse
@@ -34,7 +40,7 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL = {
     "smooth_fine": 12.0,     # read x, b; write x'
     "smooth_norm": 12.0,     # same sweep + per-block partial sums
-    "prolong_fine": 12.5,    # read x, b, x_coarse (1/8); write x'
+    "prolong_fine": 8.5,     # x += P x_coarse in place: read x, x_coarse (1/8); write x
     "restrict_fine": 8.5,    # read x, b; write b_coarse (1/8)
     "momentum": 32.0,        # predictor 24 (read u, write f); corrector 40 (read u*, p, u^n,
                              # write f: it applies the predictor's projection as it loads)
@@ -43,32 +49,48 @@ BYTES_PER_CELL = {
     "project": 28.0,         # read u* (3), p; write u (3)
     "norm_fine": 8.0,        # residual norm only: read x, b
     "pair_fine": 12.0,       # two sweeps in one pass: read x, b; write x''
-    "pair_prolong_fine": 12.5,  # prolongation + two sweeps: read x, b, x_coarse (1/8); write x''
+    "pair_prolong_fine": 12.0,  # post-smoothing pair after the prolongation: read x, b; write x''
 }
+
+
+# Per V-cycle with fused sweep pairs on every level (FP32, uniform, 3D), per
+# fine cell: pre pair 12, restriction 8.5, prolongation 8.5, post pair 12,
+# the measuring residual check 8; each coarser level costs 37 B per own cell
+# (zero-start pair 8, restriction 8.5, prolongation 8.5, post pair 12), i.e.
+# 37 (1/8 + 1/64 + ...) = 37/7 per fine cell.
+VCYCLE_FUSED = 12 + 8.5 + 8.5 + 12 + 8 + 37.0 / 7
+# Separate sweeps: the check doubles as the first pre-sweep (12), second
+# pre-sweep 12, restriction 8.5, prolongation 8.5, two post sweeps 24, and
+# 61 B per cell of each coarser level (four sweeps, restriction, prolongation).
+VCYCLE_SEPARATE = 12 + 12 + 8.5 + 8.5 + 24 + 61.0 / 7
 
 
 def step_bytes_per_cell(vcycles_total, fused):
     """Algorithmic bytes of one step per fine cell (FP32, uniform L, 3D).
 
     momentum 24 + 40 (the corrector applies the predictor's projection as it
-    loads u*), divergence 2 x 16, the corrector's projection 28, then per
-    solve and per V-cycle (coarse levels 1/8, 1/64, ... of the fine count):
-    - separate sweeps: first check-and-sweep 12; per V-cycle the fine
-      sweep, restriction, prolongation sweep and sweep (12 + 8.5 + 12.5 + 12),
-      the norm sweep (12) and 53 B per coarse cell;
-    - fused sweep pairs (fine and first coarse level): the first check is
-      taken inside the divergence, which then also reads p (4); per V-cycle
-      pair 12, restriction 8.5, prolongation pair 12.5, norm check 8, 29 B per
-      level-1 cell (zero-start pair 8, restriction 8.5, prolongation pair
-      12.5) and 53 B per cell of the coarser levels.
+    loads u*), divergence 2 x 16, the corrector's projection 28, per solve the
+    first residual check (fused pairs: taken inside the divergence, which then
+    also reads p, 4; separate sweeps: a check-and-sweep pass, 12), and per
+    V-cycle VCYCLE_FUSED or VCYCLE_SEPARATE.
     """
-    if fused:
-        first = 4.0
-        per_vcycle = 12 + 8.5 + 12.5 + 8 + 29.0 / 8 + 53.0 * (1.0 / 7 - 1.0 / 8)
-    else:
-        first = 12.0
-        per_vcycle = 12 + 8.5 + 12.5 + 12 + 12 + 53.0 / 7
+    first = 4.0 if fused else 12.0
+    per_vcycle = VCYCLE_FUSED if fused else VCYCLE_SEPARATE
     return 64.0 + 32.0 + 28.0 + 2 * first + per_vcycle * vcycles_total
+
+
+# Standalone Poisson solve with BDIM coefficients (the C3 workload), per fine
+# cell, by the byte model that prices x and b only (the coefficients counted
+# as read on the body's tiles alone): plain FP64, the active mean of b (8) and
+# the first check (x, b: 16), then 146 B per V-cycle; mixed precision, the
+# FP64 mean (8) and first residual (read x, b, write the FP32 defect: 20),
+# then per outer iteration the FP64 update (read e, x, write x: 20) and
+# residual (20), plus 65 B per inner FP32 V-cycle.
+def poisson_bytes_per_cell(prec, vcycles, inner=3):
+    if prec == "fp64":
+        return 24.0 + 146.0 * vcycles
+    outer = -(-vcycles // inner)
+    return 28.0 + 40.0 * outer + 65.0 * vcycles
 
 
 # HBM traffic of the dominant kernel per launch from rocprofv3 counters
@@ -123,8 +145,21 @@ def cpu_baseline(N, vcycles):
         raise RuntimeError(r.stderr)
     secs = float(r.stdout.strip().splitlines()[-1])
     return dict(value=N ** 3 / secs, unit="cell-steps/s", cores=1, kind="oracle",
-                sample=f"one Heun step of the 3D TGV at {N}^3 (FP64 NumPy oracle, "
-                       f"V-cycles per solve {tuple(vcycles)} = the GPU's mean), {secs:.1f} s")
+                cpu_model=host_cpu_model(),
+                sample=f"one Heun step of the 3D TGV at {N}^3 (FP64 NumPy oracle, one thread, "
+                       f"V-cycles per solve {tuple(vcycles)} = the GPU's mean rounded), "
+                       f"{secs:.1f} s")
+
+
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_routines(N, vcycles):
@@ -195,10 +230,19 @@ def poisson_compare(torch, wl, W, n, radius=32.0, tol=1e-8, reps=3):
             k, rel = ps.solve(None, x, b, tol=tol, max_vcycles=400)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
-        out[name] = {"ms": 1e3 * min(times), "vcycles": k, "rel_resid": rel,
-                     "footprint_MB": ps.footprint / 1e6}
+        ms = 1e3 * min(times)
+        nbytes = poisson_bytes_per_cell(name, k) * n[0] * n[1] * n[2]
+        out[name] = {"ms": ms, "vcycles": k, "rel_resid": rel,
+                     "footprint_MB": ps.footprint / 1e6,
+                     "roofline": {"bound": "hbm", "alg_bytes": nbytes,
+                                  "achieved": nbytes / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                                  "unit": "GB/s",
+                                  "frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
         ps.close()
     out["speedup_mixed_over_fp64"] = out["fp64"]["ms"] / out["mixed"]["ms"]
+    out["byte_model"] = ("x and b only (coefficients on the body's tiles alone): FP64 "
+                         "24 + 146 B/cell per V-cycle; mixed 28 + 40 B/cell per outer iteration "
+                         "+ 65 B/cell per inner FP32 V-cycle")
     out["workload"] = (f"Poisson {n[0]}x{n[1]}x{n[2]} Neumann box, sphere r={radius} BDIM "
                        f"coefficients, N(0,1) RHS seed 2304, to relative residual {tol}")
     return out
@@ -244,6 +288,71 @@ def batch_compare(torch, wl, count=256, n=(128, 128), tol=1e-8):
                 speedup=t_seq / t_batch, vcycles_mean=sum(o[1] for o in out) / count)
 
 
+def vcycle_leg(torch, wl, _lib, lib, W, N, steps=20):
+    """The 256^3 TGV step with the GMG loaded: every solve runs a fixed number
+    of V-cycles (tolerance 0, max_vcycles = K) for K = 1 and K = 3; the
+    per-V-cycle time is the difference over the 4 extra V-cycles per step, and
+    the fine-level multigrid kernels of the K = 3 leg are event-timed."""
+    import numpy as np
+    u, v, w, nu = W.tgv3d(N)
+    fields = [torch.from_numpy(np.ascontiguousarray(a.transpose(2, 1, 0))).float().cuda()
+              for a in (u, v, w)]
+    del u, v, w
+    res = {}
+    kern = {}
+    for K in (1, 3):
+        sim = wl.Sim((N, N, N), [0] * 3, [0] * 3, (0.0, 0.0, 0.0), nu, prec=wl.WL_FP32, tol=0.0,
+                     max_vcycles=K)
+        for i, f in enumerate(fields):
+            sim.set(wl.FIELD_U0 + i, f)
+        for _ in range(3):
+            sim.step(allow_not_converged=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = [sim.step(allow_not_converged=True) for _ in range(steps)]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res[K] = dict(ms_per_step=1e3 * el / steps,
+                      vcycles_per_solve=[st[-1]["vcycles"][0], st[-1]["vcycles"][1]],
+                      rel_resid_mean=[float(np.mean([x["rel_resid"][i] for x in st]))
+                                      for i in range(2)])
+        if K == 3:
+            names = ("pair_fine", "restrict_fine", "prolong_fine", "pair_prolong_fine",
+                     "norm_fine")
+            mask = sum(1 << _lib.PROF[nm] for nm in names)
+            lib.wl_profile_enable(mask)
+            lib.wl_profile_reset()
+            for _ in range(5):
+                sim.step(allow_not_converged=True)
+            torch.cuda.synchronize()
+            lib.wl_profile_enable(0)
+            for nm in names:
+                ms, cnt, cellsn = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_longlong()
+                lib.wl_profile_read(_lib.PROF[nm], ctypes.byref(ms), ctypes.byref(cnt),
+                                    ctypes.byref(cellsn))
+                if cnt.value:
+                    avg = 1e3 * ms.value / cnt.value
+                    b = BYTES_PER_CELL[nm] * cellsn.value
+                    kern[nm] = dict(launches=cnt.value, avg_us=avg, gbs=b / (avg * 1e-6) / 1e9)
+        sim.close()
+        del sim
+    per_v_ms = (res[3]["ms_per_step"] - res[1]["ms_per_step"]) / 4.0
+    vbytes = VCYCLE_FUSED * N ** 3
+    fine_us = sum(kern[k]["avg_us"] for k in ("pair_fine", "restrict_fine", "prolong_fine",
+                                              "pair_prolong_fine", "norm_fine") if k in kern)
+    fine_bytes = (12 + 8.5 + 8.5 + 12 + 8) * N ** 3
+    return dict(workload=f"256^3 TGV steps with every solve fixed at K V-cycles (K = 1, 3)",
+                legs={str(k): v for k, v in res.items()}, ms_per_vcycle=per_v_ms,
+                vcycle_bytes_per_cell=VCYCLE_FUSED,
+                vcycle_roofline={"bound": "hbm", "achieved": vbytes / (per_v_ms * 1e-3) / 1e9,
+                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": vbytes / (per_v_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                fine_level_kernels=kern,
+                fine_level_roofline={"bytes_per_cell": 49.0, "kernel_us": fine_us,
+                                     "achieved": fine_bytes / (fine_us * 1e-6) / 1e9 if fine_us
+                                     else None})
+
+
 def donut_bench(wl, W, p=7, steps=50, warmup=5):
     """Flow past a torus at N = (2^(p+1), 2^p, 2^p), Re = 1000 (FP32 fields and
     V-cycles, pressure solves to an RMS divergence of 1e-5): the paper's
@@ -270,32 +379,39 @@ def donut_bench(wl, W, p=7, steps=50, warmup=5):
 
 def serving_bench(count=512, seed=2304, budget=16e9, slots=8):
     """Served mix: sizes uniform over 2D {64^2,128^2,256^2} and 3D {64^3,96^3,128^3},
-    half Poisson solves, half 20-step NS runs with a body; HBM budget 16 GB.
-    Poisson requests of at most 65536 cells are batched into one persistent
-    work-queue kernel (FP64, to 1e-8), larger ones run alone (FP32 V-cycles +
-    FP64 refinement to 1e-8).  Saturated throughput first (all requests at
-    t = 0), then Poisson arrivals at 0.5 and 0.8 of it."""
+    half Poisson solves, half 20-step NS runs with a body, all to a relative
+    residual of 1e-8 with FP32 V-cycles and FP64 refinement; HBM budget 16 GB.
+    Poisson requests of at most 262144 cells and NS requests of at most 65536
+    cells are batched by kind into persistent work-queue kernels, larger ones
+    run alone.  Saturated throughput first (all requests at t = 0), then
+    Poisson arrivals at 0.5 and 0.8 of it."""
     from paper_2304_08159_amd.serving import GpuExecutor, Server, make_requests, summarize
     ex = GpuExecutor()
     Server(ex, budget, slots=slots).run(make_requests(count=16, seed=seed + 1))   # warm-up
 
-    def batch_stats(srv):
+    def batch_stats(srv, reqs):
+        done = [r for r in reqs if r.status == "done"]
+        nb = sum(1 for r in done if r.result[1].get("batched"))
         return dict(units=len(srv.batches),
-                    mean_size=(sum(srv.batches) / len(srv.batches)) if srv.batches else 0.0)
+                    mean_size=(sum(srv.batches) / len(srv.batches)) if srv.batches else 0.0,
+                    batched_fraction=nb / max(len(done), 1))
     srv = Server(ex, budget, slots=slots)
-    sat = summarize(srv.run(make_requests(count=count, seed=seed)))
-    sat["batched"] = batch_stats(srv)
+    done = srv.run(make_requests(count=count, seed=seed))
+    sat = summarize(done)
+    sat["batched"] = batch_stats(srv, done)
     mu = sat["throughput_rps"]
     res = {"saturated": sat}
     for frac in (0.5, 0.8):
         srv = Server(ex, budget, slots=slots)
-        r = summarize(srv.run(make_requests(count=count, seed=seed, rate=frac * mu)))
+        done = srv.run(make_requests(count=count, seed=seed, rate=frac * mu))
+        r = summarize(done)
         r["arrival_rate_rps"] = frac * mu
         r["peak_bytes"] = srv.peak_bytes
-        r["batched"] = batch_stats(srv)
+        r["batched"] = batch_stats(srv, done)
         res[f"rate_{frac}"] = r
     res["config"] = dict(requests=count, budget_bytes=budget, slots=slots, seed=seed,
-                         batch_cells=ex.batch_cells)
+                         batch_cells=ex.batch_cells, ns_batch_cells=ex.ns_batch_cells,
+                         tol=1e-8)
     return res
 
 
@@ -312,6 +428,12 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the served request mix")
     ap.add_argument("--donut", action="store_true",
                     help="also time flow past a torus at 256x128x128 (Re 1000)")
+    ap.add_argument("--only-poisson", action="store_true",
+                    help="run only the standalone mixed-vs-FP64 Poisson comparison (profiling)")
+    ap.add_argument("--only-serving", action="store_true",
+                    help="run only the batched-Poisson and served-mix legs")
+    ap.add_argument("--no-vcycle-leg", action="store_true",
+                    help="skip the leg with a fixed number of V-cycles per solve")
     ap.add_argument("--routines", action="store_true",
                     help="also split the oracle's step into convdiff/BDIM/BC/project/CFL (ms)")
     args = ap.parse_args()
@@ -329,6 +451,13 @@ def main():
 
     torch.cuda.set_device(0)
     N = args.N
+    if args.only_poisson:
+        print(json.dumps({"poisson_mixed_vs_fp64": poisson_compare(torch, wl, W, (N, N, N))}))
+        return
+    if args.only_serving:
+        print(json.dumps({"poisson_batch": batch_compare(torch, wl),
+                          "serving": serving_bench()}))
+        return
     u, v, w, nu = W.tgv3d(N)
     sim = wl.Sim((N, N, N), [0] * 3, [0] * 3, (0.0, 0.0, 0.0), nu, prec=wl.WL_FP32, tol=1e-5,
                  max_vcycles=100)
@@ -388,6 +517,7 @@ def main():
     if len(stats) != args.steps:
         raise RuntimeError(f"the run stopped after {len(stats)} of {args.steps} steps")
     vcs = [st["vcycles"] for st in stats]
+    rel_reached = [float(np.mean([st["rel_resid"][i] for st in stats])) for i in range(2)]
     dom_live = read_prof()[dom]
     ms_step = 1e3 * elapsed / args.steps
     cells = N ** 3
@@ -409,9 +539,11 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"3D Taylor-Green vortex, triply periodic {N}^3, FP32, Re=1600, "
-                               f"no body, CFL 0.5 Heun steps, FP32 GMG to 1e-5",
-                   "N": N, "Re": 1600, "tol": 1e-5,
-                   "vcycles_per_solve_mean": vc_mean},
+                               f"no body, CFL 0.5 Heun steps, FP32 GMG solves stopped at an RMS "
+                               f"divergence of 1e-5",
+                   "N": N, "Re": 1600, "tol": 1e-5, "stop_rule": "rms_divergence",
+                   "vcycles_per_solve_mean": vc_mean,
+                   "rel_resid_reached_mean": rel_reached},
         "roofline": {
             "bound": "hbm",
             "kernel": dom,
@@ -451,6 +583,9 @@ def main():
     sim.close()
     del sim
     torch.cuda.empty_cache()
+    if not args.no_vcycle_leg:
+        out["vcycle_leg"] = vcycle_leg(torch, wl, _lib, lib, W, N)
+        torch.cuda.empty_cache()
     if not args.no_poisson:
         out["poisson_mixed_vs_fp64"] = poisson_compare(torch, wl, W, (N, N, N))
     if args.donut:
@@ -459,7 +594,7 @@ def main():
         out["poisson_batch"] = batch_compare(torch, wl)
         out["serving"] = serving_bench()
     if not args.no_cpu_baseline:
-        vcr = [max(1, int(round(x))) for x in vc_mean]
+        vcr = [int(round(x)) for x in vc_mean]
         try:
             out["cpu_baseline"] = cpu_baseline(args.cpu_N, vcr)
             if args.routines:

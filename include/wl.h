@@ -84,13 +84,31 @@ typedef enum {
  * the tube's centre line) and minor radius `radius2` (the tube's), so that
  * d = sqrt(x^2 + (sqrt(y^2 + z^2) - radius)^2) - radius2 relative to centre.
  * eps is the BDIM kernel half-width (<= 0 selects 1 cell).  radius2 is read
- * for kind 2 only.  Drag and the adjoint step support kinds 0 and 1. */
+ * for kind 2 only.  Drag and the adjoint step support kinds 0 and 1.
+ *
+ * Motion (Sec. 2: the body is its SDF composed with a coordinate map; here
+ * the map of a rigid motion).  The centre follows
+ *     X(t) = centre + velocity t + amplitude sin(omega t)
+ * and the body spins at the constant angular velocity `spin` (kind 1 only:
+ * the sphere's shape is unchanged by it; in 2D only spin[2], about z).  The
+ * body velocity V_b(x, t) = dX/dt + spin x (x - X(t)) enters the BDIM blend,
+ *     u* = mu0 f + (1 - mu0) V_b + (mu1 n) . (grad f - grad V_b),
+ * and a moving body is measured again before every step at the time t + dt
+ * the step advances to (moments, Poisson coefficients on every level, tile
+ * classes).  All zero (the default of a zero-initialised struct): a body at
+ * rest.  In 2D the z components of velocity and amplitude must be 0.  The
+ * body must stay clear of periodic boundaries (its SDF is not wrapped).
+ * Moving bodies are not supported by the adjoint step. */
 typedef struct {
     int kind;
     double centre[3];
     double radius;
     double eps;
     double radius2;
+    double velocity[3];   /* drift of the centre (cells per time unit)       */
+    double amplitude[3];  /* oscillation amplitude of the centre (cells)     */
+    double omega;         /* oscillation angular frequency (1 / time unit)    */
+    double spin[3];       /* angular velocity of the body (1 / time unit)     */
 } wl_body;
 
 typedef struct {
@@ -269,13 +287,16 @@ wl_status wl_poisson_destroy(wl_poisson* ps);
 /* ---- Batched small Poisson solves (serving) ------------------------------ */
 
 /* One Poisson problem of a batch: the same operator, method and stopping rule
- * as wl_poisson_solve (Sec. 2, project!) in FP64.  coeffs: ndim face arrays of
+ * as wl_poisson_solve (Sec. 2, project!).  coeffs: ndim face arrays of
  * double (layout above; zero faces are walls / solid); x: initial guess in,
  * solution out (double); b: right-hand side (double, projected onto the
  * active cells and made mean-free there by the solver, not modified).  All
- * device pointers owned by the caller.  At most 262144 cells; the coarsest
- * multigrid level (every direction halved while all are even and >= 8) must
- * have at most 1024 cells. */
+ * device pointers owned by the caller.  mixed = 0: FP64 V-cycles; mixed = 1:
+ * FP32 V-cycles (three per outer iteration, from zero, on FP32 copies of the
+ * coefficients) with the FP64 defect correction x += e around them, as
+ * WL_MIXED (the residual test and x stay FP64).  At most 262144 cells; the
+ * coarsest multigrid level (every direction halved while all are even and
+ * >= 8) must have at most 1024 cells. */
 typedef struct {
     int ndim;
     int n[3];
@@ -284,7 +305,8 @@ typedef struct {
     void* x;
     const void* b;
     double tol;           /* stop once ||b - A x|| <= tol ||b||              */
-    int max_vcycles;
+    int max_vcycles;      /* mixed: inner FP32 V-cycles in total             */
+    int mixed;
 } wl_batch_request;
 
 typedef struct {
@@ -326,6 +348,64 @@ wl_status wl_poisson_batch_solve(const wl_batch_request* reqs, int count, void* 
 wl_status wl_poisson_batch_solve_noalloc(const wl_batch_request* reqs, int count,
                                          void* hip_stream, wl_batch_result* results);
 
+/* ---- Batched small Navier-Stokes runs (serving) ------------------------- */
+
+/* One small simulation of a batch: `steps` CFL-adaptive Heun steps (Sec. 3
+ * simstep!: convection-diffusion, BDIM, boundary rules, GMG projection, CFL)
+ * of the flow described as in wl_sim_desc, with FP32 fields and each pressure
+ * solve in FP32 V-cycles with an FP64 defect correction to the relative
+ * residual tol (the method and readings of WL_MIXED with WL_STOP_RELATIVE).
+ * The body (kinds 0-2) must be at rest.  u: ndim face arrays of float
+ * (layout above), the state in and out; uout: the outflow plane (float,
+ * n[1]*n[2]; OUTFLOW requests only, else NULL); p: the pressure (double,
+ * n cells), the solves' warm start in and the last solve's result out.  All
+ * device pointers owned by the caller.  At most 262144 cells; the coarsest
+ * multigrid level (every direction halved while all are even and >= 8) must
+ * have at most 1024 cells. */
+typedef struct {
+    int ndim;
+    int n[3];
+    int bc_lo[3];
+    int bc_hi[3];
+    double U[3];
+    double nu;
+    wl_body body;
+    double tol;           /* relative residual of every pressure solve       */
+    int max_vcycles;      /* inner FP32 V-cycles per solve (<= 0: 100)        */
+    int steps;
+    double cfl;           /* <= 0: 0.5                                        */
+    void* u;
+    void* uout;
+    void* p;
+} wl_ns_request;
+
+typedef struct {
+    int status;           /* WL_OK, WL_ERR_NOT_CONVERGED (some solve hit
+                             max_vcycles; the run still completes),
+                             WL_ERR_NONFINITE or WL_ERR_INVALID_ARG (a time
+                             step that is not positive)                      */
+    int vcycles;          /* inner V-cycles of all its solves                 */
+    double t;             /* simulated time                                   */
+    double dt;            /* last time step                                   */
+} wl_ns_result;
+
+/* Exact device workspace for wl_ns_batch_run on these requests (host only;
+ * the requests' device pointers may be NULL here).  WL_ERR_INVALID_ARG names
+ * the first request that is malformed or too large. */
+wl_status wl_ns_batch_footprint(const wl_ns_request* reqs, int count, size_t* bytes);
+
+/* Runs count requests with one persistent kernel on hip_stream: its
+ * workgroups (at most one per compute unit) take requests from a device work
+ * queue until it is empty; a request's whole run is taken by one workgroup,
+ * every phase of a step a loop over its cells followed by a barrier, every
+ * reduction a fixed-order workgroup sum, so each result is bitwise
+ * independent of the batch it is in.  workspace: >= the footprint, 256-byte
+ * aligned.  results: count entries (host), filled on return (synchronises
+ * the stream).  Returns WL_OK when every request completed cleanly, else the
+ * first failing request's status. */
+wl_status wl_ns_batch_run(const wl_ns_request* reqs, int count, void* workspace, size_t ws_bytes,
+                          void* hip_stream, wl_ns_result* results);
+
 /* BDIM-modified Poisson coefficients of a body (Sec. 2): L_i = mu0 of the
  * signed distance at every lower i-face centre (cosine kernel of half-width
  * body->eps, <= 0 selects 1 cell), zero on non-periodic lower boundary faces;
@@ -359,6 +439,24 @@ wl_status wl_set_graphs(int enable);
  * another mode. */
 wl_status wl_set_fused_sweeps(int mode);
 
+/* Smoother of the multigrid levels (every level but the coarsest, which is
+ * solved exactly).  WL_SMOOTH_JACOBI (default): damped Jacobi,
+ * w = 2d/(2d+1), two sweeps before and two after the coarse correction.
+ * WL_SMOOTH_CG: the conjugate-gradient smoothing Sec. 2 names for the GMG
+ * levels: each smoothing step is a fresh run of two Jacobi-preconditioned CG
+ * iterations on the level's system from the current iterate, with the
+ * residual kept mean-free over the active cells; every dot product is a
+ * fixed-order FP64 device reduction and no scalar returns to the host, so
+ * results are deterministic and the V-cycle can be replayed as a graph.
+ * CG smoothing needs four more arrays per level (residual, direction, M p,
+ * inverse diagonal) and turns off the fused Jacobi sweep pairs.
+ * Process-wide; a solver or simulation takes the smoother in force when its
+ * footprint is computed and when it is created (keep it unchanged between
+ * the two).  The batched solver (wl_poisson_batch_solve) always uses Jacobi.
+ * WL_ERR_INVALID_ARG for another kind. */
+enum { WL_SMOOTH_JACOBI = 0, WL_SMOOTH_CG = 1 };
+wl_status wl_set_smoother(int kind);
+
 /* ---- Kernel timing (measurement support) -------------------------------- */
 
 /* Kernels whose launches can be bracketed by HIP events, to turn algorithmic
@@ -367,14 +465,15 @@ wl_status wl_set_fused_sweeps(int mode);
 enum {
     WL_PROF_SMOOTH_FINE = 0,     /* plain damped-Jacobi sweep, fine level     */
     WL_PROF_SMOOTH_NORM = 1,     /* sweep fused with the residual norm        */
-    WL_PROF_PROLONG_FINE = 2,    /* prolongation fused with a sweep, fine     */
+    WL_PROF_PROLONG_FINE = 2,    /* prolongation added in place, fine level   */
     WL_PROF_RESTRICT_FINE = 3,   /* residual + restriction, fine level        */
     WL_PROF_MOMENTUM = 4,        /* convection-diffusion stage update         */
     WL_PROF_DIVERGENCE = 5,      /* projection right-hand side                */
     WL_PROF_PROJECT = 6,         /* pressure-gradient update (+ CFL)          */
     WL_PROF_NORM_FINE = 7,       /* residual norm only, fine level            */
     WL_PROF_PAIR_FINE = 8,       /* two sweeps fused, fine level              */
-    WL_PROF_PAIR_PROLONG_FINE = 9, /* prolongation and two sweeps fused, fine */
+    WL_PROF_PAIR_PROLONG_FINE = 9, /* post-smoothing pair (after the
+                                      prolongation), fine level            */
     WL_PROF_COUNT = 10
 };
 

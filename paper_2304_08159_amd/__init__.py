@@ -17,7 +17,8 @@ from ._lib import (FIELD_L0, FIELD_MU0_0, FIELD_MU1N, FIELD_P, FIELD_SIGMA, FIEL
                    FIELD_UOUT, INFLOW, OUTFLOW, PERIODIC, STOP_DIVERGENCE, STOP_RELATIVE, WALL,
                    WL_FP32, WL_FP64, WL_MIXED, WlError, check, load)
 
-__all__ = ["Sim", "Poisson", "body_coeffs", "set_graphs", "set_fused_sweeps", "poisson_batch_solve", "load", "WlError", "WL_FP32", "WL_FP64", "WL_MIXED",
+__all__ = ["Sim", "Poisson", "body_coeffs", "set_graphs", "set_fused_sweeps", "set_smoother",
+           "poisson_batch_solve", "ns_batch_run", "ns_batch_footprint", "load", "WlError", "WL_FP32", "WL_FP64", "WL_MIXED",
            "PERIODIC", "INFLOW", "OUTFLOW", "WALL", "STOP_DIVERGENCE", "STOP_RELATIVE"]
 
 
@@ -63,13 +64,7 @@ class Sim:
             d.n[i], d.bc_lo[i], d.bc_hi[i], d.U[i] = nn[i], bl[i], bh[i], float(Uv[i])
         d.nu = float(nu)
         if body is not None:
-            d.body.kind = _lib.body_kind(body)
-            d.body.radius2 = float(body.get("radius2", 0.0))
-            c = list(body["centre"]) + [0.0] * (3 - ndim)
-            for i in range(3):
-                d.body.centre[i] = float(c[i])
-            d.body.radius = float(body["radius"])
-            d.body.eps = float(body.get("eps", eps))
+            _lib.fill_body(d.body, body, ndim, eps)
         d.prec, d.mg_levels, d.tol = int(prec), int(levels), float(tol)
         d.max_vcycles, d.inner_vcycles, d.cfl = int(max_vcycles), int(inner_vcycles), float(cfl)
         d.tape_steps = int(tape_steps)
@@ -232,11 +227,12 @@ class Sim:
 
 
 def poisson_batch_solve(requests, allow_not_converged=False):
-    """Solve many small Poisson problems with one persistent kernel (FP64).
+    """Solve many small Poisson problems with one persistent kernel.
 
     requests: list of dicts with n (2 or 3 ints), periodic, coeffs (float64
     tensor (ndim, n2, n1, n0)), x (float64, guess in / solution out), b
-    (float64), tol (relative, default 1e-8), max_vcycles (default 200).
+    (float64), tol (relative, default 1e-8), max_vcycles (default 200),
+    mixed (FP32 V-cycles with FP64 defect correction; default FP64).
     Returns a list of (status, vcycles, rel_resid)."""
     torch = _torch()
     lib = load()
@@ -264,6 +260,7 @@ def poisson_batch_solve(requests, allow_not_converged=False):
         a.b = r["b"].data_ptr()
         a.tol = float(r.get("tol", 1e-8))
         a.max_vcycles = int(r.get("max_vcycles", 200))
+        a.mixed = int(bool(r.get("mixed", False)))
     nbytes = ctypes.c_size_t()
     check(lib.wl_poisson_batch_footprint(arr, count, ctypes.byref(nbytes)))
     ws, ptr, nb = _workspace(torch, nbytes.value, dev)
@@ -272,6 +269,71 @@ def poisson_batch_solve(requests, allow_not_converged=False):
     check(lib.wl_poisson_batch_solve(arr, count, ptr, nb, _stream(torch), res), allow=allow)
     del ws
     return [(res[q].status, res[q].vcycles, res[q].rel_resid) for q in range(count)]
+
+
+def _ns_request(r, q):
+    """Fill an NsRequest from a dict (see ns_batch_run)."""
+    torch = _torch()
+    n = [int(m) for m in r["n"]]
+    ndim = len(n)
+    q.ndim = ndim
+    bl = list(r["bc_lo"]) + [WALL] * (3 - ndim)
+    bh = list(r["bc_hi"]) + [WALL] * (3 - ndim)
+    Uv = list(r.get("U", (0.0,) * ndim)) + [0.0] * (3 - ndim)
+    for i in range(3):
+        q.n[i] = (n + [1] * (3 - ndim))[i]
+        q.bc_lo[i], q.bc_hi[i], q.U[i] = int(bl[i]), int(bh[i]), float(Uv[i])
+    q.nu = float(r["nu"])
+    if r.get("body") is not None:
+        _lib.fill_body(q.body, r["body"], ndim)
+    q.tol = float(r.get("tol", 1e-8))
+    q.max_vcycles = int(r.get("max_vcycles", 100))
+    q.steps = int(r["steps"])
+    q.cfl = float(r.get("cfl", 0.5))
+    for t, dt in (("u", torch.float32), ("p", torch.float64)):
+        ten = r[t]
+        if ten.dtype != dt or not ten.is_cuda or not ten.is_contiguous():
+            raise ValueError(f"{t} must be a contiguous {dt} CUDA tensor")
+    q.u = r["u"].data_ptr()
+    q.p = r["p"].data_ptr()
+    q.uout = r["uout"].data_ptr() if r.get("uout") is not None else None
+
+
+def ns_batch_footprint(requests):
+    lib = load()
+    arr = (_lib.NsRequest * max(len(requests), 1))()
+    for q, r in enumerate(requests):
+        _ns_request(r, arr[q])
+    nb = ctypes.c_size_t()
+    check(lib.wl_ns_batch_footprint(arr, len(requests), ctypes.byref(nb)))
+    return nb.value
+
+
+def ns_batch_run(requests, allow_not_converged=False):
+    """Run many small simulations with one persistent kernel (FP32 fields,
+    mixed-precision solves to a relative residual).
+
+    requests: list of dicts with n, bc_lo, bc_hi, U, nu, body (at rest; may be
+    None), tol (default 1e-8), max_vcycles, steps, cfl, and the state tensors
+    u (float32, (ndim, n2, n1, n0), in/out), uout (float32 (n2, n1) for an
+    OUTFLOW run, in/out) and p (float64 (n2, n1, n0), in/out).  Returns a list
+    of (status, vcycles, t, last dt)."""
+    torch = _torch()
+    lib = load()
+    count = len(requests)
+    if count == 0:
+        return []
+    arr = (_lib.NsRequest * count)()
+    for q, r in enumerate(requests):
+        _ns_request(r, arr[q])
+    nb = ctypes.c_size_t()
+    check(lib.wl_ns_batch_footprint(arr, count, ctypes.byref(nb)))
+    ws, ptr, n = _workspace(torch, nb.value, requests[0]["u"].device)
+    res = (_lib.NsResult * count)()
+    allow = (-3,) if allow_not_converged else ()
+    check(lib.wl_ns_batch_run(arr, count, ptr, n, _stream(torch), res), allow=allow)
+    del ws
+    return [(res[q].status, res[q].vcycles, res[q].t, res[q].dt) for q in range(count)]
 
 
 def set_graphs(enable=True):
@@ -288,6 +350,16 @@ def set_fused_sweeps(mode=1):
     check(load().wl_set_fused_sweeps(int(mode)))
 
 
+def set_smoother(kind="jacobi"):
+    """Smoother of the multigrid levels for solvers and simulations created
+    afterwards: "jacobi" (damped Jacobi, default) or "cg" (the paper's
+    conjugate-gradient smoothing)."""
+    kinds = {"jacobi": _lib.SMOOTH_JACOBI, "cg": _lib.SMOOTH_CG}
+    if kind not in kinds:
+        raise ValueError("smoother must be 'jacobi' or 'cg'")
+    check(load().wl_set_smoother(kinds[kind]))
+
+
 def body_coeffs(n, periodic, body=None, prec=WL_FP32, device="cuda"):
     """BDIM Poisson coefficients of a sphere/circle or torus body: tensor (ndim, n2, n1, n0)."""
     torch = _torch()
@@ -298,13 +370,7 @@ def body_coeffs(n, periodic, body=None, prec=WL_FP32, device="cuda"):
     per = (ctypes.c_int * 3)(*([int(bool(p)) for p in periodic] + [0] * (3 - ndim)))
     b = _lib.Body()
     if body is not None:
-        b.kind = _lib.body_kind(body)
-        b.radius2 = float(body.get("radius2", 0.0))
-        c = list(body["centre"]) + [0.0] * (3 - ndim)
-        for i in range(3):
-            b.centre[i] = float(c[i])
-        b.radius = float(body["radius"])
-        b.eps = float(body.get("eps", 1.0))
+        _lib.fill_body(b, body, ndim)
     dtype = torch.float32 if prec == WL_FP32 else torch.float64
     L = torch.empty((ndim, nn[2], nn[1], nn[0]), dtype=dtype, device=device)
     check(lib.wl_body_coeffs(ctypes.byref(b), ndim, nn, per, int(prec), _ptr(L), _stream(torch)))

@@ -20,6 +20,7 @@ STATUS = {
 }
 WL_FP32, WL_FP64, WL_MIXED = 0, 1, 2
 STOP_DIVERGENCE, STOP_RELATIVE = 0, 1
+SMOOTH_JACOBI, SMOOTH_CG = 0, 1
 PERIODIC, INFLOW, OUTFLOW, WALL = 0, 1, 2, 3
 
 FIELD_U0, FIELD_U1, FIELD_U2, FIELD_P, FIELD_UOUT = 0, 1, 2, 3, 4
@@ -32,8 +33,9 @@ EXPORTS = (
     "wl_drag", "wl_tape_record", "wl_step_adjoint",
     "wl_poisson_footprint", "wl_poisson_create",
     "wl_poisson_solve", "wl_poisson_destroy", "wl_poisson_batch_footprint",
-    "wl_poisson_batch_solve", "wl_poisson_batch_solve_noalloc", "wl_body_coeffs",
-    "wl_set_graphs", "wl_set_fused_sweeps",
+    "wl_poisson_batch_solve", "wl_poisson_batch_solve_noalloc", "wl_ns_batch_footprint",
+    "wl_ns_batch_run", "wl_body_coeffs",
+    "wl_set_graphs", "wl_set_fused_sweeps", "wl_set_smoother",
     "wl_profile_enable",
     "wl_profile_reset",
     "wl_profile_read", "wl_last_error", "wl_version",
@@ -51,12 +53,35 @@ class WlError(RuntimeError):
 class Body(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("centre", ctypes.c_double * 3),
                 ("radius", ctypes.c_double), ("eps", ctypes.c_double),
-                ("radius2", ctypes.c_double)]
+                ("radius2", ctypes.c_double), ("velocity", ctypes.c_double * 3),
+                ("amplitude", ctypes.c_double * 3), ("omega", ctypes.c_double),
+                ("spin", ctypes.c_double * 3)]
 
 
 def body_kind(body):
     """wl_body.kind of a body dict: {"kind": "torus"} selects 2, else a sphere (1)."""
     return 2 if body.get("kind", "sphere") == "torus" else 1
+
+
+def fill_body(b, body, ndim, eps=1.0):
+    """Fill a Body from a dict: centre, radius, optional kind / radius2 / eps
+    and motion (velocity, amplitude, omega; spin as a 3-vector, or a scalar
+    about z)."""
+    b.kind = body_kind(body)
+    b.radius2 = float(body.get("radius2", 0.0))
+    c = list(body["centre"]) + [0.0] * (3 - ndim)
+    v = list(body.get("velocity", (0.0,) * ndim)) + [0.0] * (3 - ndim)
+    a = list(body.get("amplitude", (0.0,) * ndim)) + [0.0] * (3 - ndim)
+    sp = body.get("spin", 0.0)
+    sp = [0.0, 0.0, float(sp)] if not hasattr(sp, "__len__") else list(sp) + [0.0] * (3 - len(sp))
+    for i in range(3):
+        b.centre[i] = float(c[i])
+        b.velocity[i] = float(v[i])
+        b.amplitude[i] = float(a[i])
+        b.spin[i] = float(sp[i])
+    b.omega = float(body.get("omega", 0.0))
+    b.radius = float(body["radius"])
+    b.eps = float(body.get("eps", eps))
 
 
 class SimDesc(ctypes.Structure):
@@ -72,11 +97,24 @@ class SimDesc(ctypes.Structure):
 class BatchRequest(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int * 3), ("periodic", ctypes.c_int * 3),
                 ("coeffs", ctypes.c_void_p), ("x", ctypes.c_void_p), ("b", ctypes.c_void_p),
-                ("tol", ctypes.c_double), ("max_vcycles", ctypes.c_int)]
+                ("tol", ctypes.c_double), ("max_vcycles", ctypes.c_int), ("mixed", ctypes.c_int)]
 
 
 class BatchResult(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("vcycles", ctypes.c_int), ("rel_resid", ctypes.c_double)]
+
+
+class NsRequest(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int * 3), ("bc_lo", ctypes.c_int * 3),
+                ("bc_hi", ctypes.c_int * 3), ("U", ctypes.c_double * 3), ("nu", ctypes.c_double),
+                ("body", Body), ("tol", ctypes.c_double), ("max_vcycles", ctypes.c_int),
+                ("steps", ctypes.c_int), ("cfl", ctypes.c_double), ("u", ctypes.c_void_p),
+                ("uout", ctypes.c_void_p), ("p", ctypes.c_void_p)]
+
+
+class NsResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("vcycles", ctypes.c_int), ("t", ctypes.c_double),
+                ("dt", ctypes.c_double)]
 
 
 class StepStats(ctypes.Structure):
@@ -122,9 +160,12 @@ def load():
                                    ctypes.POINTER(BatchResult)],
         "wl_poisson_batch_solve_noalloc": [ctypes.POINTER(BatchRequest), i32, vp,
                                            ctypes.POINTER(BatchResult)],
+        "wl_ns_batch_footprint": [ctypes.POINTER(NsRequest), i32, ctypes.POINTER(sz)],
+        "wl_ns_batch_run": [ctypes.POINTER(NsRequest), i32, vp, sz, vp, ctypes.POINTER(NsResult)],
         "wl_body_coeffs": [ctypes.POINTER(Body), i32, ip3, ip3, i32, vp, vp],
         "wl_set_graphs": [i32],
         "wl_set_fused_sweeps": [i32],
+        "wl_set_smoother": [i32],
         "wl_profile_enable": [ctypes.c_uint],
         "wl_profile_reset": [],
         "wl_profile_read": [i32, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_longlong),

@@ -29,8 +29,38 @@ struct SimConfig {
     Grid g;
     int nlev;
     bool allper, unif, outflow, body;
+    bool moving;  // the body follows a rigid motion (re-measured every step)
     size_t N, P;  // cells, outflow-plane points
 };
+
+static bool body_moves(const wl_body& b) {
+    if (b.kind == 0) return false;
+    for (int i = 0; i < 3; ++i)
+        if (b.velocity[i] != 0.0 || b.amplitude[i] != 0.0 || b.spin[i] != 0.0) return true;
+    return false;
+}
+
+// The body placed where its motion has taken it at time t (the measure
+// kernels see a body at rest there), and its rigid motion at t.
+static BodyDev body_at(const wl_body& b, double t) {
+    BodyDev d{b.kind, {b.centre[0], b.centre[1], b.centre[2]}, b.radius, b.eps, b.radius2};
+    for (int i = 0; i < 3; ++i)
+        d.centre[i] += b.velocity[i] * t + b.amplitude[i] * std::sin(b.omega * t);
+    return d;
+}
+
+static BodyMotionDev motion_at(const wl_body& b, double t) {
+    BodyMotionDev m{};
+    if (!body_moves(b)) return m;
+    m.on = 1;
+    const BodyDev at = body_at(b, t);
+    for (int i = 0; i < 3; ++i) {
+        m.X[i] = at.centre[i];
+        m.xdot[i] = b.velocity[i] + b.amplitude[i] * b.omega * std::cos(b.omega * t);
+        m.w[i] = b.spin[i];
+    }
+    return m;
+}
 
 static wl_status check_desc(const wl_sim_desc* desc, SimConfig* cfg) {
     if (!desc) return invalid("desc is NULL");
@@ -66,6 +96,19 @@ static wl_status check_desc(const wl_sim_desc* desc, SimConfig* cfg) {
     if (d.body.kind == 2 && d.tape_steps > 0)
         return invalid("the adjoint step supports sphere bodies only");
     if (!(d.body.eps > 0.0)) d.body.eps = 1.0;
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(d.body.velocity[i]) || !std::isfinite(d.body.amplitude[i]) ||
+            !std::isfinite(d.body.spin[i]) || !std::isfinite(d.body.omega))
+            return invalid("body motion parameters must be finite");
+    if (body_moves(d.body)) {
+        if (d.body.kind != 1 && (d.body.spin[0] != 0.0 || d.body.spin[1] != 0.0 ||
+                                 d.body.spin[2] != 0.0))
+            return invalid("a spinning body must be a sphere or circle (kind 1)");
+        if (d.ndim == 2 && (d.body.velocity[2] != 0.0 || d.body.amplitude[2] != 0.0 ||
+                            d.body.spin[0] != 0.0 || d.body.spin[1] != 0.0))
+            return invalid("a 2D body moves in the x-y plane and spins about z only");
+        if (d.tape_steps > 0) return invalid("the adjoint step supports bodies at rest only");
+    }
     if (d.mg_levels < 0 || d.mg_levels > kMaxLevels) return invalid("mg_levels out of range");
     if (d.tape_steps < 0 || d.tape_steps > 100000) return invalid("tape_steps out of range");
     SimConfig c;
@@ -84,6 +127,7 @@ static wl_status check_desc(const wl_sim_desc* desc, SimConfig* cfg) {
     }
     c.allper = c.g.per0 && c.g.per1 && (d.ndim == 2 || c.g.per2);
     c.body = d.body.kind != 0;
+    c.moving = body_moves(d.body);
     c.unif = c.allper && !c.body;
     c.outflow = d.bc_hi[0] == WL_BC_OUTFLOW;
     c.N = cells(c.g);
@@ -291,16 +335,13 @@ static BdimFields<T> bdim_fields(const SimImpl<T>& s) {
     return b;
 }
 
+// Geometry of the body where it is at time t: BDIM moments, fine Poisson
+// coefficients (and their FP64 copy), tile classes, coarse coefficients and
+// the active-cell count (synchronises).
 template <typename T>
-static wl_status sim_init(SimImpl<T>& s, hipStream_t st) {
+static wl_status sim_measure(SimImpl<T>& s, double t, hipStream_t st) {
     const SimConfig& c = s.cfg;
-    const size_t N = c.N;
-    // geometry: BDIM moments and fine Poisson coefficients
-    BodyDev body{c.d.body.kind,
-                 {c.d.body.centre[0], c.d.body.centre[1], c.d.body.centre[2]},
-                 c.d.body.radius,
-                 c.d.body.eps,
-                 c.d.body.radius2};
+    const BodyDev body = body_at(c.d.body, t);
     MeasureOut<T> M;
     for (int i = 0; i < 3; ++i) {
         M.mu0[i] = s.mu0[i];
@@ -313,12 +354,19 @@ static wl_status sim_init(SimImpl<T>& s, hipStream_t st) {
     s.h.lev[0].uniform = c.unif ? 1 : 0;
     s.h.lev[0].Lc = T(1);
     WL_TRY(mg_coarsen_all<T>(s.h, st));
+    return mg_count_active<T>(s.h, s.red, st);
+}
+
+template <typename T>
+static wl_status sim_init(SimImpl<T>& s, hipStream_t st) {
+    const SimConfig& c = s.cfg;
+    const size_t N = c.N;
+    WL_TRY(sim_measure(s, 0.0, st));
     if (c.d.prec == WL_MIXED) {
         s.h.coarse_tol = 1e-6;
     } else {
         s.h.coarse_tol = sizeof(T) == 8 ? 1e-10 : 1e-6;
     }
-    WL_TRY(mg_count_active<T>(s.h, s.red, st));
     // initial state: u = U on every face, boundary faces at their values, p = 0
     {
         T* u0[3] = {s.vel[0][0], s.vel[0][1], s.vel[0][2]};
@@ -413,6 +461,13 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
     const int S = s.S;
     const int A = (S + 1) % 3, B = (S + 2) % 3;
     const int PS = s.PS, P1 = (PS + 1) % 3, P2 = (PS + 2) % 3;
+    BodyMotionDev motion{};
+    if (c.moving) {
+        // both stages advance to t + dt: the body is measured there
+        WL_TRY(resolve_dt());
+        WL_TRY(sim_measure(s, s.t + dt, st));
+        motion = motion_at(c.d.body, s.t + dt);
+    }
     TapeSlot<T>* tp = nullptr;
     if (s.adj && s.adj->recording && s.adj->count < s.adj->cap) {
         WL_TRY(resolve_dt());
@@ -450,7 +505,7 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
         int us = A;
         if (c.body) {
             T* o[3] = {s.vel[B][0], s.vel[B][1], s.vel[B][2]};
-            WL_TRY(ns_bdim<T>(field_of(s, A, s.plane[P1]), bdim_fields(s), o, st));
+            WL_TRY(ns_bdim<T>(field_of(s, A, s.plane[P1]), bdim_fields(s), o, st, motion));
             us = B;
         }
         const VelField<T> V = field_of(s, us, s.plane[P1]);
@@ -499,7 +554,7 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
         int us2 = fr;
         if (c.body) {
             T* o2[3] = {s.vel[S][0], s.vel[S][1], s.vel[S][2]};
-            WL_TRY(ns_bdim<T>(field_of(s, fr, s.plane[P2]), bdim_fields(s), o2, st));
+            WL_TRY(ns_bdim<T>(field_of(s, fr, s.plane[P2]), bdim_fields(s), o2, st, motion));
             us2 = S;
         }
         const VelField<T> V2 = field_of(s, us2, s.plane[P2]);
@@ -641,11 +696,7 @@ static wl_status sim_drag(SimImpl<T>& s, double* F, hipStream_t st) {
         return WL_OK;
     }
     if (c.d.body.kind != 1) return invalid("drag supports sphere bodies only");
-    const BodyDev body{c.d.body.kind,
-                       {c.d.body.centre[0], c.d.body.centre[1], c.d.body.centre[2]},
-                       c.d.body.radius,
-                       c.d.body.eps,
-                       c.d.body.radius2};
+    const BodyDev body = body_at(c.d.body, s.t);
     T* L[3] = {s.h.lev[0].L[0], s.h.lev[0].L[1], s.h.lev[0].L[2]};
     WL_TRY(drag_sums<T>(c.g, body, s.p, L, s.red.partial, st));
     WL_TRY(reduce_cols(s.red.partial, s.red.slots, 4, s.red.result + 8, st));

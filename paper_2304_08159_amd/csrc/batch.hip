@@ -4,7 +4,8 @@
 // the workgroup that took it, with the same method as wl_poisson_solve
 // (Sec. 2's project!: matrix-free GMG, damped Jacobi, sum restriction,
 // cell-centred linear prolongation, coarse coefficients = 1/2 the covered fine
-// faces, minimum-norm coarsest solve) in FP64.  Every reduction is a
+// faces, minimum-norm coarsest solve) in FP64, or in FP32 V-cycles with an
+// FP64 defect correction around them (per request).  Every reduction is a
 // fixed-order workgroup sum, so a request's result does not depend on which
 // workgroup solved it or on the rest of the batch.
 #include <algorithm>
@@ -16,6 +17,7 @@
 
 #include "wl_internal.h"
 #include "wl_wg.h"
+#include "wl_wgsolve.h"
 
 namespace wl {
 namespace {
@@ -29,9 +31,12 @@ struct BatchReq {
     int nlev;
     double tol, omega;
     int max_vcycles;
+    int mixed;                            // FP32 inner V-cycles, FP64 outer
     const double* b_in;
-    BatchLevel lev[kMaxLevels];
+    BatchLevel lev[kMaxLevels];           // mixed: only the fine level (FP64 x, b, L)
+    WgLevel<float> lev32[kMaxLevels];     // mixed: the FP32 hierarchy
 };
+
 
 struct BatchRes {
     int status, vcycles;
@@ -115,6 +120,29 @@ __device__ void solve_one(const BatchReq& q, BatchRes& res, CoarseLds& S) {
     __syncthreads();
 }
 
+// Mixed precision (see wg_solve_mixed): the FP32 coefficients of every level
+// from the request's FP64 ones, the projected right-hand side, then the
+// defect-correction loop.
+__device__ void solve_one_mixed(const BatchReq& q, BatchRes& res, CoarseLds& S) {
+    const BatchLevel& F = q.lev[0];
+    wg_coeffs32(F, q.lev32, q.nlev);
+    const double b2 = wg_project_rhs(F, q.b_in, S.red);
+    if (b2 == 0.0) {
+        const int N = int(cells(F.g));
+        for (int c = threadIdx.x; c < N; c += blockDim.x) F.x[0][c] = 0.0;
+        __syncthreads();
+        if (threadIdx.x == 0) res = BatchRes{WL_OK, 0, 0.0};
+        __syncthreads();
+        return;
+    }
+    double r2 = 0.0;
+    int k = 0;
+    const int st = wg_solve_mixed(F, q.lev32, q.nlev, float(q.omega), q.tol * q.tol * b2, 0.0,
+                                  q.max_vcycles, S, &k, &r2);
+    if (threadIdx.x == 0) res = BatchRes{st, k, sqrt(r2 / b2)};
+    __syncthreads();
+}
+
 // Persistent kernel: each workgroup takes the next request from the queue
 // until none is left (every workgroup reaches the exit).
 __global__ __launch_bounds__(kBatchThreads) void k_poisson_batch(const BatchReq* __restrict__ reqs,
@@ -128,7 +156,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_poisson_batch(const BatchReq*
         const int r = take;
         __syncthreads();
         if (r >= count) return;
-        solve_one(reqs[r], res[r], S);
+        if (reqs[r].mixed)
+            solve_one_mixed(reqs[r], res[r], S);
+        else
+            solve_one(reqs[r], res[r], S);
     }
 }
 
@@ -162,13 +193,46 @@ wl_status plan_one(const wl_batch_request& in, Carver& c, BatchReq& q) {
         set_error("batch request: coarsest multigrid level exceeds 1024 cells");
         return WL_ERR_INVALID_ARG;
     }
+    if (in.mixed != 0 && in.mixed != 1) {
+        set_error("batch request: mixed must be 0 or 1");
+        return WL_ERR_INVALID_ARG;
+    }
     q = BatchReq{};
     q.nlev = nlev;
     q.tol = in.tol;
     q.omega = 2.0 * ndim / (2.0 * ndim + 1.0);
     q.max_vcycles = in.max_vcycles;
+    q.mixed = in.mixed;
     q.b_in = static_cast<const double*>(in.b);
     int n[3] = {in.n[0], in.n[1], in.n[2]};
+    if (in.mixed) {
+        // FP64 fine level (x, projected b, the request's coefficients) and an
+        // FP32 hierarchy (e, sweep buffer, right-hand side, coefficients)
+        BatchLevel& F = q.lev[0];
+        F.g = Grid{n[0], n[1], n[2], in.periodic[0] != 0, in.periodic[1] != 0,
+                   ndim == 3 && in.periodic[2] != 0, ndim};
+        F.Lc = 1.0;
+        F.uniform = 0;
+        const size_t N0 = size_t(n[0]) * n[1] * n[2];
+        F.x[0] = static_cast<double*>(in.x);
+        F.x[1] = nullptr;
+        F.b = c.take<double>(N0);
+        const double* co = static_cast<const double*>(in.coeffs);
+        for (int d = 0; d < 3; ++d) F.L[d] = d < ndim ? const_cast<double*>(co + d * N0) : nullptr;
+        for (int l = 0; l < nlev; ++l) {
+            WgLevel<float>& L = q.lev32[l];
+            L.g = Grid{n[0], n[1], n[2], F.g.per0, F.g.per1, F.g.per2, ndim};
+            L.Lc = 1.0f;
+            L.uniform = 0;
+            const size_t Nl = size_t(n[0]) * n[1] * n[2];
+            L.x[0] = c.take<float>(Nl);
+            L.x[1] = c.take<float>(Nl);
+            L.b = c.take<float>(Nl);
+            for (int d = 0; d < 3; ++d) L.L[d] = d < ndim ? c.take<float>(Nl) : nullptr;
+            for (int d = 0; d < ndim; ++d) n[d] /= 2;
+        }
+        return WL_OK;
+    }
     for (int l = 0; l < nlev; ++l) {
         BatchLevel& L = q.lev[l];
         L.g = Grid{n[0], n[1], n[2], in.periodic[0] != 0, in.periodic[1] != 0,

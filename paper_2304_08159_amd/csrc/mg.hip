@@ -113,11 +113,19 @@ static unsigned pair_blocks() {
     return v;
 }
 
+static Launch launch_pairs(const Grid& g);
+
+// Process-wide smoother of the multigrid levels (wl_set_smoother), taken by
+// each hierarchy when it is laid out: 0 damped Jacobi, 1 conjugate gradients.
+static std::atomic<int> g_smoother{0};
+
 template <typename T>
 void carve_hierarchy(Carver& c, Hierarchy<T>& h, int ndim, const int n[3], const int per[3],
                      int nlev, bool alloc_fine_x) {
     h.nlev = nlev;
-    h.pairs = g_pairs.load(std::memory_order_relaxed);
+    h.smoother = g_smoother.load(std::memory_order_relaxed);
+    // the fused two-sweep kernels are Jacobi sweeps
+    h.pairs = h.smoother == 0 ? g_pairs.load(std::memory_order_relaxed) : 0;
     h.omega = 2.0 * ndim / (2.0 * ndim + 1.0);
     int m[3] = {n[0], n[1], n[2]};
     for (int l = 0; l < nlev; ++l) {
@@ -128,7 +136,20 @@ void carve_hierarchy(Carver& c, Hierarchy<T>& h, int ndim, const int n[3], const
         L.x[0] = (l > 0 || alloc_fine_x) ? c.take<T>(N) : nullptr;
         L.x[1] = c.take<T>(N);
         L.b = c.take<T>(N);
+        L.cls = c.take<unsigned char>(reduce_slots_for(L.g));
+        L.cls_pairs = c.take<unsigned char>(launch_pairs(L.g).nblocks());
+        if (h.smoother == 1 && l < nlev - 1) {
+            L.cr = c.take<T>(N);
+            L.cp = c.take<T>(N);
+            L.cq = c.take<T>(N);
+            L.cd = c.take<T>(N);
+            L.cgs = c.take<double>(8);
+        }
         for (int d = 0; d < ndim; ++d) m[d] /= 2;
+    }
+    if (h.smoother == 1) {
+        const Grid& g0 = h.lev[0].g;
+        h.cgpart = c.take<double>(5 * reduce_slots_for(g0));
     }
 }
 
@@ -180,6 +201,8 @@ __global__ __launch_bounds__(kBlock) void k_smooth(TileDev TL, Grid g, XAccess<T
         Du += C.Lc + C.Lc;
         Du += C.Lc + C.Lc;
         if (d3) Du += C.Lc + C.Lc;
+        // a block of class 0 takes its coefficients from the position
+        const bool walled = !UNIF && C.cls && C.cls[block_linear()] == 0;
         const int k0 = sp.z0;
         unsigned id = unsigned(i) + n0 * unsigned(j) + plane * unsigned(k0);
         // z neighbours of the first cell
@@ -187,7 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth(TileDev TL, Grid g, XAccess<T
         if (d3) {
             const int km = k0 > 0 ? k0 - 1 : (g.per2 ? g.n2 - 1 : k0);
             xzl = xv(id + unsigned(km - k0) * plane);
-            if (!UNIF) Lzl = C.L2[id];
+            if (!UNIF) Lzl = walled ? ((k0 == 0 && !g.per2) ? T(0) : C.Lc) : C.L2[id];
         }
         for (int k = k0; k < sp.z1; ++k, id += plane) {
             // upper z neighbour (carried up as the next centre)
@@ -208,6 +231,9 @@ __global__ __launch_bounds__(kBlock) void k_smooth(TileDev TL, Grid g, XAccess<T
             if (UNIF) {
                 Lxl = Lxu = Lyl = Lyu = Lzu = C.Lc;
                 Lzl = C.Lc;
+            } else if (walled) {
+                T zl;
+                walled_faces<T>(g, i, j, k, C.Lc, Lxl, Lxu, Lyl, Lyu, zl, Lzu);
             } else {
                 Lxl = C.L0[id];
                 Lxu = hxu ? C.L0[id + oxp] : T(0);
@@ -561,12 +587,28 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(TileDev TL, Grid g, G
     // residual of one cell given its z neighbours and z coefficients
     const bool shift = bshift != nullptr;
     const double mean = shift ? *bshift : 0.0;
+    // a block of class 0 takes its coefficients from the position
+    const bool walled = !UNIF && C.cls && C.cls[block_linear()] == 0;
+    const T Lxl_w = (i == 0 && !g.per0) ? T(0) : C.Lc;
+    const T Lxu_w = (i == g.n0 - 1 && !g.per0) ? T(0) : C.Lc;
+    const T Lyl_w = (j == 0 && !g.per1) ? T(0) : C.Lc;
+    const T Lyu_w = (j == g.n1 - 1 && !g.per1) ? T(0) : C.Lc;
+    auto Lz_at = [&](int kk, unsigned c) -> T {     // lower z face of cell kk
+        if (UNIF) return C.Lc;
+        if (walled) return (kk == 0 && !g.per2) ? T(0) : C.Lc;
+        return C.L2[c];
+    };
     auto resid = [&](unsigned c, T xI, T xzl, T xzu, T Lzl, T Lzu) -> T {
         const T xxl = X.x[c + oxm], xxu = X.x[c + oxp], xyl = X.x[c + oym], xyu = X.x[c + oyp];
         T bv = b[c];
         T Lxl, Lxu, Lyl, Lyu;
         if (UNIF) {
             Lxl = Lxu = Lyl = Lyu = C.Lc;
+        } else if (walled) {
+            Lxl = Lxl_w;
+            Lxu = Lxu_w;
+            Lyl = Lyl_w;
+            Lyu = Lyu_w;
         } else {
             Lxl = C.L0[c];
             Lxu = hxu ? C.L0[c + oxp] : T(0);
@@ -595,7 +637,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(TileDev TL, Grid g, G
         if (d3) {
             const int k0 = sp.z0, km = k0 > 0 ? k0 - 1 : (g.per2 ? g.n2 - 1 : k0);
             xzl = X.x[id + unsigned(km - k0) * plane];
-            Lzl = UNIF ? C.Lc : C.L2[id];
+            Lzl = Lz_at(k0, id);
         }
     }
     for (int k = sp.z0; k < sp.z1; k += fz, id += unsigned(fz) * plane) {
@@ -607,11 +649,11 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(TileDev TL, Grid g, G
                 bool l1, l2;
                 const unsigned u1 = zup(k, id, l1);
                 const T x1 = X.x[u1];
-                const T Lz1 = l1 ? (UNIF ? C.Lc : C.L2[u1]) : T(0);
+                const T Lz1 = l1 ? Lz_at(k + 1 < g.n2 ? k + 1 : 0, u1) : T(0);
                 if (fz == 2) {
                     const unsigned u2 = zup(k + 1, u1, l2);
                     const T x2 = X.x[u2];
-                    const T Lz2 = l2 ? (UNIF ? C.Lc : C.L2[u2]) : T(0);
+                    const T Lz2 = l2 ? Lz_at(k + 2 < g.n2 ? k + 2 : 0, u2) : T(0);
                     r = resid(id, xI, xzl, x1, Lzl, Lz1);
                     r += resid(u1, x1, xI, x2, Lz1, Lz2);
                     xzl = x1;
@@ -771,6 +813,38 @@ __global__ __launch_bounds__(256) void k_coarse_cg(Grid g, Coeffs<T> C, int unif
                                                    double tol, int maxit) {
     __shared__ CoarseLds S;
     coarse_cg_block<T>(g, C, uniform, b, xout, tol, maxit, S);
+}
+
+// Per-block class of a level for a tiling (see Coeffs::cls): 0 when every
+// face any cell of the block reads equals Lc, or 0 on a non-periodic
+// domain-boundary face (exact comparisons: class-0 blocks then compute
+// bitwise what reading the arrays gives).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_level_class(TileDev TL, Grid g, Coeffs<T> C,
+                                                        unsigned char* __restrict__ cls) {
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    const Span sp = tile_span(TL, g.n0, g.n1, g.n2);
+    const int i = sp.i, j = sp.j;
+    bool odd = false;
+    if (i < g.n0 && j < g.n1)
+        for (int k = sp.z0; k < sp.z1 && !odd; ++k) {
+            const size_t id = cid(g, i, j, k);
+            T Lxl, Lxu, Lyl, Lyu, Lzl, Lzu;
+            walled_faces<T>(g, i, j, k, C.Lc, Lxl, Lxu, Lyl, Lyu, Lzl, Lzu);
+            odd = odd || C.L0[id] != Lxl || C.L1[id] != Lyl;
+            if (i < g.n0 - 1 || g.per0) odd = odd || C.L0[cid(g, nb_up(i, g.n0, g.per0), j, k)] != Lxu;
+            if (j < g.n1 - 1 || g.per1) odd = odd || C.L1[cid(g, i, nb_up(j, g.n1, g.per1), k)] != Lyu;
+            if (g.ndim == 3) {
+                odd = odd || C.L2[id] != Lzl;
+                if (k < g.n2 - 1 || g.per2)
+                    odd = odd || C.L2[cid(g, i, j, nb_up(k, g.n2, g.per2))] != Lzu;
+            }
+        }
+    if (odd) any = 1;  // benign race: every writer stores 1
+    __syncthreads();
+    if (threadIdx.x == 0) cls[block_linear()] = any ? 1 : 0;
 }
 
 // Coarse coefficient = 1/2 * sum of the fine faces the coarse face covers.
@@ -935,8 +1009,10 @@ wl_status mg_count_active64(const Grid& g, double* const L64[3], Reduce& red, si
 // ----------------------------------------------------------- host driving
 
 template <typename T>
-static Coeffs<T> coeffs_of(const Level<T>& L) {
-    return Coeffs<T>{L.L[0], L.L[1], L.L[2], L.Lc};
+static Coeffs<T> coeffs_of(const Level<T>& L, const unsigned char* cls = nullptr) {
+    Coeffs<T> C{L.L[0], L.L[1], L.L[2], L.Lc};
+    C.cls = L.uniform ? nullptr : cls;
+    return C;
 }
 
 // w / D of a uniform level, D summed in the kernels' order.
@@ -961,7 +1037,7 @@ static wl_status smooth(const Level<T>& L, const T* xin, const T* b, T omega, T*
             L.g, X, coeffs_of(L), b, uniform_wd(L, omega), xout, partial, bshift, bproj);
     else
         k_smooth<T, XM, false, NORM, FIRST><<<ln.grid, ln.block, 0, s>>>(ln.td, 
-            L.g, X, coeffs_of(L), b, omega, xout, partial, bshift, bproj);
+            L.g, X, coeffs_of(L, L.cls), b, omega, xout, partial, bshift, bproj);
     WL_CHECK_LAUNCH();
     return WL_OK;
 }
@@ -1065,7 +1141,8 @@ static wl_status resid_restrict(const Level<T>& L, const T* x, const T* b, const
         k_resid_restrict<T, true><<<ln.grid, ln.block, 0, s>>>(ln.td, L.g, C.g, X, coeffs_of(L), b, bshift,
                                                                C.b);
     else
-        k_resid_restrict<T, false><<<ln.grid, ln.block, 0, s>>>(ln.td, L.g, C.g, X, coeffs_of(L), b,
+        k_resid_restrict<T, false><<<ln.grid, ln.block, 0, s>>>(ln.td, L.g, C.g, X,
+                                                                coeffs_of(L, L.cls_pairs), b,
                                                                 bshift, C.b);
     WL_CHECK_LAUNCH();
     return WL_OK;
@@ -1099,6 +1176,18 @@ wl_status mg_coarsen_all(Hierarchy<T>& h, hipStream_t s) {
         WL_CHECK_LAUNCH();
         C.uniform = F.uniform;
         C.Lc = F.Lc * (F.g.ndim == 3 ? T(2) : T(1));
+    }
+    // block classes of the non-uniform levels for both tilings
+    for (int l = 0; l < h.nlev; ++l) {
+        Level<T>& L = h.lev[l];
+        if (L.uniform || !L.cls) continue;
+        const Coeffs<T> C{L.L[0], L.L[1], L.L[2], L.Lc};
+        const Launch a = launch_for(L.g.n0, L.g.n1, L.g.n2);
+        k_level_class<T><<<a.grid, a.block, 0, s>>>(a.td, L.g, C, L.cls);
+        WL_CHECK_LAUNCH();
+        const Launch b = launch_pairs(L.g);
+        k_level_class<T><<<b.grid, b.block, 0, s>>>(b.td, L.g, C, L.cls_pairs);
+        WL_CHECK_LAUNCH();
     }
     return WL_OK;
 }
@@ -1142,6 +1231,16 @@ static wl_status pre_smooth(const Hierarchy<T>& h, const Level<T>& L, Pre mode, 
                             const T* b, const double* bs, hipStream_t s, const T** out,
                             bool fine) {
     const T w = T(h.omega);
+    if (h.smoother == 1) {
+        // conjugate gradients: two iterations from the iterate (or zero), in place
+        if (mode == Pre::Half) {
+            set_error("internal: half-done pre-smoothing with the CG smoother");
+            return WL_ERR_INVALID_ARG;
+        }
+        WL_TRY(cg_smooth<T>(h, L, home, mode == Pre::Zero, b, bs, 2, s));
+        *out = home;
+        return WL_OK;
+    }
     if (mode != Pre::Half && pair_ok(h, L)) {
         if (mode == Pre::Zero)
             WL_TRY((pair<T, XM_ZERO>(L, nullptr, b, w, other, bs, s,
@@ -1172,6 +1271,10 @@ static wl_status post_smooth(const Hierarchy<T>& h, const Level<T>& L, const T* 
                              T* other, const Level<T>& C, const T* b, const double* bs,
                              hipStream_t s, bool fine) {
     const T w = T(h.omega);
+    if (h.smoother == 1) {
+        WL_TRY(prolong(L, C, home, s, fine ? WL_PROF_PROLONG_FINE : -1));
+        return cg_smooth<T>(h, L, home, false, b, bs, 2, s);
+    }
     if (pre == other) {
         // only a fused pre-smoothing leaves its result in other
         if (!pair_ok(h, L)) {
@@ -1283,7 +1386,10 @@ wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, d
     // and the residual checks only measure; otherwise every check is also
     // the first pre-sweep of the next V-cycle (into F.x[1]).
     const bool fused = h.nlev > 1 && pair_ok(h, F);
-    T* const xnext = fused ? nullptr : F.x[1];
+    // with CG smoothing, too, the checks only measure and each V-cycle
+    // smooths from the iterate
+    const bool measure = fused || h.smoother == 1;
+    T* const xnext = measure ? nullptr : F.x[1];
     if (bp == BPartials::Check && !mg_producer_check(h)) {
         set_error("internal: first residual check given for a hierarchy that cannot take it");
         return WL_ERR_INVALID_ARG;
@@ -1334,10 +1440,10 @@ wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, d
     int k = 0;
     // one V-cycle and the residual norms it leaves (replayed as a graph)
     auto body = [&](hipStream_t q) -> wl_status {
-        WL_TRY(vcycle_rest(h, fused ? Pre::Full : Pre::Half, b, bshift, q));
+        WL_TRY(vcycle_rest(h, measure ? Pre::Full : Pre::Half, b, bshift, q));
         WL_TRY((smooth<T, XM_PLAIN, true, false>(F, x, b, w, xnext, red.partial,
                                                  bshift, q,
-                                                 fused ? WL_PROF_NORM_FINE : WL_PROF_SMOOTH_NORM)));
+                                                 measure ? WL_PROF_NORM_FINE : WL_PROF_SMOOTH_NORM)));
         return reduce<T>(red, ln.nblocks(), 2, 1.0, red.result, q, post);
     };
     while (!done(r2) && k < max_vcycles) {
@@ -1450,6 +1556,16 @@ wl_status mg_solve_mixed(Hierarchy<float>& h32, const Mixed64& m, Reduce& red, d
 }
 
 }  // namespace wl
+
+extern "C" wl_status wl_set_smoother(int kind) {
+    wl::clear_error();
+    if (kind != WL_SMOOTH_JACOBI && kind != WL_SMOOTH_CG) {
+        wl::set_error("wl_set_smoother: kind must be WL_SMOOTH_JACOBI or WL_SMOOTH_CG");
+        return WL_ERR_INVALID_ARG;
+    }
+    wl::g_smoother.store(kind, std::memory_order_relaxed);
+    return WL_OK;
+}
 
 extern "C" wl_status wl_set_fused_sweeps(int mode) {
     wl::clear_error();

@@ -21,31 +21,9 @@
 #include "wl_jacobi.h"
 #include "wl_ns.h"
 #include "wl_vel.h"
+#include "wl_nsdev.h"
 
 namespace wl {
-
-// Flux of u_c through the lower d-face of the c-momentum control volume at J:
-// ubar * phi - nu (u_c(J) - u_c(J - delta_d)), phi the limited third-order
-// upwind-biased face value.
-template <typename T, bool ALLPER>
-__device__ __forceinline__ T face_flux(const VelField<T>& V, int c, int d, int i, int j, int k,
-                                       T nu) {
-    const int di = d == 0, dj = d == 1, dk = d == 2;
-    const int ci = c == 0, cj = c == 1, ck = c == 2;
-    const T um2 = vget<T, ALLPER>(V, c, i - 2 * di, j - 2 * dj, k - 2 * dk);
-    const T um1 = vget<T, ALLPER>(V, c, i - di, j - dj, k - dk);
-    const T u0 = vget<T, ALLPER>(V, c, i, j, k);
-    const T up1 = vget<T, ALLPER>(V, c, i + di, j + dj, k + dk);
-    const T ubar = T(0.5) * (vget<T, ALLPER>(V, d, i, j, k) +
-                             vget<T, ALLPER>(V, d, i - ci, j - cj, k - ck));
-    const bool pos = ubar >= T(0);
-    const T cu = pos ? um1 : u0;
-    const T bd = pos ? u0 : um1;
-    const T au = pos ? um2 : up1;
-    const T phik = (T(5) * cu + T(2) * bd - au) / T(6);
-    const T phi = med3(phik, cu, med3(T(2) * cu - au, cu, bd));
-    return ubar * phi - nu * (u0 - um1);
-}
 
 // Stage update of every interior face of cell (i,j,k):
 //   PRED: f = u_e + dt R(u_e)          CORR: f = (u_n + u_e + dt R(u_e)) / 2
@@ -600,12 +578,14 @@ __global__ __launch_bounds__(1024) void k_outflow(Grid g, const T* __restrict__ 
     for (int q = threadIdx.x; q < P; q += blockDim.x) fout[q] += shift;
 }
 
-// First-order BDIM blend (body at rest) on interior faces:
-//   u*_c = mu0_c f_c + sum_d (mu1 n)_cd (f_c(I+delta_d) - f_c(I-delta_d)) / 2.
+// First-order BDIM blend on interior faces:
+//   u*_c = mu0_c f_c + (1 - mu0_c) V_b,c
+//          + sum_d (mu1 n)_cd [(f_c(I+delta_d) - f_c(I-delta_d)) / 2 - dV_b,c/dx_d],
+// V_b the body velocity at the face (zero for a body at rest).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_bdim(TileDev TL, VelField<T> F, BdimFields<T> B,
                                                  T* __restrict__ o0, T* __restrict__ o1,
-                                                 T* __restrict__ o2) {
+                                                 T* __restrict__ o2, BodyMotionDev mo) {
     const Grid& g = F.g;
     const Span sp = tile_span(TL, g.n0, g.n1, g.n2);
     const int i = sp.i, j = sp.j;
@@ -619,28 +599,10 @@ __global__ __launch_bounds__(kBlock) void k_bdim(TileDev TL, VelField<T> F, Bdim
         }
         return;
     }
-    for (int k = sp.z0; k < sp.z1; ++k) {
-    const size_t id = cid(g, i, j, k);
-    const int coord[3] = {i, j, k};
-    const int per[3] = {g.per0, g.per1, g.per2};
     T* out[3] = {o0, o1, o2};
-    for (int c = 0; c < g.ndim; ++c) {
-        const T f = F.u[c][id];
-        if (!per[c] && coord[c] == 0) {
-            out[c][id] = f;
-            continue;
-        }
-        T v = B.mu0[c][id] * f;
-        for (int d = 0; d < g.ndim; ++d) {
-            const T m = B.mu1n[3 * c + d][id];
-            if (m != T(0)) {
-                const T fp = vget<T, false>(F, c, i + (d == 0), j + (d == 1), k + (d == 2));
-                const T fm = vget<T, false>(F, c, i - (d == 0), j - (d == 1), k - (d == 2));
-                v += m * (T(0.5) * (fp - fm));
-            }
-        }
-        out[c][id] = v;
-    }
+    for (int k = sp.z0; k < sp.z1; ++k) {
+        const size_t id = cid(g, i, j, k);
+        for (int c = 0; c < g.ndim; ++c) out[c][id] = bdim_face<T>(F, B, mo, c, i, j, k);
     }
 }
 
@@ -1131,60 +1093,19 @@ __global__ __launch_bounds__(kBlock) void k_measure(TileDev TL, Grid g, BodyDev 
     const Span sp = tile_span(TL, g.n0, g.n1, g.n2);
     const int i = sp.i, j = sp.j;
     if (i >= g.n0 || j >= g.n1) return;
-    for (int k = sp.z0; k < sp.z1; ++k) {
-    const size_t id = cid(g, i, j, k);
-    const int coord[3] = {i, j, k};
     const int bclo[3] = {bclo0, bclo1, bclo2};
-    for (int c = 0; c < 3; ++c) {
-        double m0 = 1.0, m1 = 0.0, nrm[3] = {0.0, 0.0, 0.0};
-        if (body.kind != 0 && c < g.ndim) {
-            double x[3] = {i + 0.5, j + 0.5, k + 0.5};
-            x[c] -= 0.5;
-            double rel[3] = {0.0, 0.0, 0.0}, sd;
-            for (int d = 0; d < g.ndim; ++d) rel[d] = x[d] - body.centre[d];
-            if (body.kind == 1) {
-                double r2 = 0.0;
-                for (int d = 0; d < g.ndim; ++d) r2 += rel[d] * rel[d];
-                const double dist = sqrt(r2);
-                sd = dist - body.radius;
-                if (dist > 0.0)
-                    for (int d = 0; d < g.ndim; ++d) nrm[d] = rel[d] / dist;
-            } else {
-                // torus about the x axis: distance to the tube's centre circle
-                // (in the plane through x and the axis) minus the tube radius
-                const double rho = sqrt(rel[1] * rel[1] + rel[2] * rel[2]);
-                const double qr = rho - body.radius;
-                const double q = sqrt(rel[0] * rel[0] + qr * qr);
-                sd = q - body.radius2;
-                if (q > 0.0) {
-                    nrm[0] = rel[0] / q;
-                    if (rho > 0.0) {
-                        nrm[1] = qr / q * rel[1] / rho;
-                        nrm[2] = qr / q * rel[2] / rho;
-                    }
-                }
-            }
-            const double r = sd / body.eps;
-            if (r >= 1.0) {
-                m0 = 1.0;
-            } else if (r <= -1.0) {
-                m0 = 0.0;
-            } else {
-                const double pi = 3.14159265358979323846;
-                const double sn = sin(pi * r), cs = cos(pi * r);
-                m0 = 0.5 * (1.0 + r + sn / pi);
-                m1 = body.eps * ((1.0 - r * r) / 4.0 - r * sn / (2.0 * pi) -
-                                 (1.0 + cs) / (2.0 * pi * pi));
-            }
+    for (int k = sp.z0; k < sp.z1; ++k) {
+        const size_t id = cid(g, i, j, k);
+        for (int c = 0; c < 3; ++c) {
+            double m0, m1, nrm[3];
+            measure_face(g, body, c, i, j, k, m0, m1, nrm);
+            if (M.mu0[c]) M.mu0[c][id] = T(m0);
+            if (M.mu1n[3 * c])
+                for (int d = 0; d < 3; ++d) M.mu1n[3 * c + d][id] = T(m1 * nrm[d]);
+            const double L = face_coeff(g, bclo, c, i, j, k, m0);
+            if (M.L[c]) M.L[c][id] = T(L);
+            if (M.L64[c]) M.L64[c][id] = L;
         }
-        if (M.mu0[c]) M.mu0[c][id] = T(m0);
-        if (M.mu1n[3 * c])
-            for (int d = 0; d < 3; ++d) M.mu1n[3 * c + d][id] = T(m1 * nrm[d]);
-        double L = (c < g.ndim) ? m0 : 0.0;
-        if (bclo[c] != WL_BC_PERIODIC && coord[c] == 0) L = 0.0;
-        if (M.L[c]) M.L[c][id] = T(L);
-        if (M.L64[c]) M.L64[c][id] = L;
-    }
     }
 }
 
@@ -1344,9 +1265,10 @@ wl_status ns_outflow(const Grid& g, const T* ue_x, const T* out_e, const T* out_
 }
 
 template <typename T>
-wl_status ns_bdim(const VelField<T>& F, const BdimFields<T>& B, T* const out[3], hipStream_t s) {
+wl_status ns_bdim(const VelField<T>& F, const BdimFields<T>& B, T* const out[3], hipStream_t s,
+                  const BodyMotionDev& motion) {
     const Launch ln = launch_for(F.g.n0, F.g.n1, F.g.n2);
-    k_bdim<T><<<ln.grid, ln.block, 0, s>>>(ln.td, F, B, out[0], out[1], out[2]);
+    k_bdim<T><<<ln.grid, ln.block, 0, s>>>(ln.td, F, B, out[0], out[1], out[2], motion);
     WL_CHECK_LAUNCH();
     return WL_OK;
 }
@@ -1462,7 +1384,7 @@ wl_status ns_set_scalar(double* p, double v, hipStream_t s) {
     template wl_status ns_outflow<T>(const Grid&, const T*, const T*, const T*, const T*, T, bool, \
                                      const double*, T*, hipStream_t);                             \
     template wl_status ns_bdim<T>(const VelField<T>&, const BdimFields<T>&, T* const*,            \
-                                  hipStream_t);                                                   \
+                                  hipStream_t, const BodyMotionDev&);                             \
     template wl_status ns_divergence<T>(const VelField<T>&, const ProjCoeffs<T>&, bool, double,  \
                                         const double*, T*, double*, bool, hipStream_t, const T*,  \
                                         T, size_t*);                                              \

@@ -99,7 +99,25 @@ struct Coeffs {
     const T* __restrict__ L1;
     const T* __restrict__ L2;
     T Lc;  // the constant coefficient when the level is uniform
+    // Optional per-block classes of the launching kernel's tiling: 0 where
+    // every face of every cell of the block equals Lc except non-periodic
+    // domain-boundary faces (0), so the coefficients follow from the position
+    // and need not be read; null: always read them.
+    const unsigned char* __restrict__ cls = nullptr;
 };
+
+// Face coefficients of cell (i, j, k) on a block of class 0 (see Coeffs::cls):
+// Lc, or 0 on a non-periodic domain-boundary face.  Exactly the stored values.
+template <typename T>
+__device__ __forceinline__ void walled_faces(const Grid& g, int i, int j, int k, T Lc, T& Lxl,
+                                             T& Lxu, T& Lyl, T& Lyu, T& Lzl, T& Lzu) {
+    Lxl = (i == 0 && !g.per0) ? T(0) : Lc;
+    Lxu = (i == g.n0 - 1 && !g.per0) ? T(0) : Lc;
+    Lyl = (j == 0 && !g.per1) ? T(0) : Lc;
+    Lyu = (j == g.n1 - 1 && !g.per1) ? T(0) : Lc;
+    Lzl = (g.ndim == 3 && !(k == 0 && !g.per2)) ? Lc : T(0);
+    Lzu = (g.ndim == 3 && !(k == g.n2 - 1 && !g.per2)) ? Lc : T(0);
+}
 
 // (A x)(I) and the diagonal magnitude D(I) = sum of the 2d face coefficients,
 // for A x = sum_d L_d(I+delta_d)(x(I+delta_d)-x(I)) - L_d(I)(x(I)-x(I-delta_d)).

@@ -109,6 +109,18 @@ struct Level {
     T* b = nullptr;                         // right-hand side (level 0: projected copy)
     int uniform = 0;                        // all active faces equal Lc, fully periodic
     T Lc = T(1);
+    // conjugate-gradient smoothing (carved only when the hierarchy uses it):
+    // residual, search direction, M p, inverse diagonal (non-uniform levels)
+    // and the level's CG scalars (double[8] on the device)
+    // per-block classes (see Coeffs::cls) for the launch_for and the
+    // launch_pairs tilings of this level (non-uniform levels)
+    unsigned char* cls = nullptr;
+    unsigned char* cls_pairs = nullptr;
+    T* cr = nullptr;
+    T* cp = nullptr;
+    T* cq = nullptr;
+    T* cd = nullptr;
+    double* cgs = nullptr;
 };
 
 // Executable HIP graphs of a repeated solve body (one V-cycle with its norm,
@@ -190,8 +202,18 @@ struct Hierarchy {
     double coarse_tol = 1e-10;
     size_t n_active = 0;         // active fine cells (host copy)
     int pairs = 0;               // fused two-sweep kernels: 0 off, 1 on large levels, 2 on all
+    int smoother = 0;            // 0 damped Jacobi, 1 conjugate gradients (WL_SMOOTH_*)
+    double* cgpart = nullptr;    // CG per-block partial sums (5 per block of level 0)
     GraphCache graphs;
 };
+
+// Conjugate-gradient smoothing of one level (cgsmooth.hip): `iters`
+// Jacobi-preconditioned CG iterations on A x = b from x (zero: from x = 0,
+// which is then written), with b shifted by -*bshift on active cells when
+// bshift is given.  Enqueued on s; the level's scalars stay on the device.
+template <typename T>
+wl_status cg_smooth(const Hierarchy<T>& h, const Level<T>& L, T* x, bool zero, const T* b,
+                    const double* bshift, int iters, hipStream_t s);
 
 // A few doubles handed from the device to the host without a copy engine or
 // a stream synchronisation: a kernel writes them into coherent pinned host

@@ -59,6 +59,14 @@ struct BodyDev {
     double radius2;   // torus tube radius (kind 2)
 };
 
+// Rigid motion of a body at one time, for the BDIM blend: the body velocity
+// V_b(x) = xdot + w x (x - X) and its gradient dV_b,i/dx_j = eps_ikj w_k.
+// on = 0: body at rest (V_b = 0).
+struct BodyMotionDev {
+    int on;
+    double X[3], xdot[3], w[3];
+};
+
 template <typename T>
 wl_status ns_measure(const Grid& g, const BodyDev& body, const int bclo[3], const MeasureOut<T>& M,
                      hipStream_t s);
@@ -76,7 +84,8 @@ template <typename T>
 wl_status ns_outflow(const Grid& g, const T* ue_x, const T* out_e, const T* out_n, const T* f_x,
                      T Ux, bool corr, const double* dt_dev, T* fout, hipStream_t s);
 template <typename T>
-wl_status ns_bdim(const VelField<T>& F, const BdimFields<T>& B, T* const out[3], hipStream_t s);
+wl_status ns_bdim(const VelField<T>& F, const BdimFields<T>& B, T* const out[3], hipStream_t s,
+                  const BodyMotionDev& motion = BodyMotionDev{});
 // Tile classes (see BdimFields::cls) from the measured mu0 / mu1 n.
 template <typename T>
 wl_status ns_tile_class(const Grid& g, const BdimFields<T>& B, unsigned char* cls, hipStream_t s);

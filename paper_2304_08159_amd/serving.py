@@ -9,12 +9,14 @@ being admitted as earlier ones finish.  Every reduction in the library is a
 fixed-order FP64 sum, so a request's result does not depend on what runs
 beside it (checked bitwise by the tests through result fingerprints).
 
-Small Poisson requests are batched: when one of them is admitted, the
-dispatcher gathers further waiting small Poisson requests (FIFO, up to
+Small requests are batched: when one of them is admitted, the dispatcher
+gathers further waiting small requests of the same kind (FIFO, up to
 `batch_max`, within the free budget) into the same unit, which the executor
-solves with one persistent work-queue kernel (`wl_poisson_batch_solve`: its
-workgroups take requests from a device queue, one request per workgroup at a
-time).  A unit occupies one slot.
+runs with one persistent work-queue kernel whose workgroups take requests
+from a device queue, one request per workgroup at a time: Poisson solves
+(`wl_poisson_batch_solve`, FP32 V-cycles with FP64 defect correction) or
+whole Navier-Stokes runs (`wl_ns_batch_run`, FP32 fields, mixed-precision
+solves).  A unit occupies one slot.
 
 The scheduler is host logic only and talks to an `Executor`; `GpuExecutor`
 drives libwl, tests can drive a fake one on the CPU.
@@ -61,6 +63,9 @@ class Executor:
 
     def batchable(self, req):      # may the request share a batched launch?
         return False
+
+    def batch_key(self, req):      # requests with the same key may share a unit
+        return "batch" if self.batchable(req) else None
 
     def run_batch(self, reqs):     # results (or Exception instances), one per request
         raise NotImplementedError
@@ -163,11 +168,12 @@ class Server:
                         state["free"] -= r.footprint
                         state["active"] += 1
                         unit = [r]
-                        if self.ex.batchable(r):
+                        key = self.ex.batch_key(r)
+                        if key is not None:
                             for q in list(waiting):
                                 if len(unit) >= self.batch_max:
                                     break
-                                if self.ex.batchable(q) and q.footprint <= state["free"]:
+                                if self.ex.batch_key(q) == key and q.footprint <= state["free"]:
                                     waiting.remove(q)
                                     state["free"] -= q.footprint
                                     unit.append(q)
@@ -247,10 +253,11 @@ class GpuExecutor(Executor):
     sphere / circle coefficients, N(0,1) right-hand side drawn on the device,
     FP32 V-cycles with FP64 defect correction) or `steps` Navier-Stokes steps
     of a body in a uniform inflow (Re 250 in 2D, 100 in 3D, mixed-precision
-    pressure solves).  Results are (fingerprint, stats) pairs; the fingerprint
+    pressure solves to the request's relative residual, 1e-8 by default).  Results are (fingerprint, stats) pairs; the fingerprint
     is an exact integer hash of the output bits."""
 
-    def __init__(self, device="cuda", keep_fields=False, batch_cells=65536):
+    def __init__(self, device="cuda", keep_fields=False, batch_cells=65536,
+                 ns_batch_cells=16384):
         import torch
 
         import paper_2304_08159_amd as wl
@@ -258,6 +265,7 @@ class GpuExecutor(Executor):
         self.device = device
         self.keep = keep_fields
         self.batch_cells = int(batch_cells)   # Poisson requests up to this size are batched
+        self.ns_batch_cells = int(ns_batch_cells)   # NS requests up to this size are batched
         self._tls = threading.local()
 
     def _stream(self):
@@ -280,7 +288,11 @@ class GpuExecutor(Executor):
                     body=dict(centre=centre, radius=r.radius))
 
     def batchable(self, r):
-        return r.kind == "poisson" and math.prod(r.n) <= self.batch_cells
+        limit = self.batch_cells if r.kind == "poisson" else self.ns_batch_cells
+        return math.prod(r.n) <= limit
+
+    def batch_key(self, r):
+        return r.kind if self.batchable(r) else None
 
     def footprint(self, r):
         import ctypes
@@ -292,12 +304,24 @@ class GpuExecutor(Executor):
             cells *= m
         nn = (ctypes.c_int * 3)(*(list(r.n) + [1] * (3 - ndim)))
         sz = ctypes.c_size_t()
+        if self.batchable(r) and r.kind == "ns":
+            a = self._ns_args(r)
+            q = _lib.NsRequest()
+            q.ndim = ndim
+            for i in range(3):
+                q.n[i] = nn[i]
+                q.bc_lo[i] = (a["bc_lo"] + [3] * 3)[i]
+                q.bc_hi[i] = (a["bc_hi"] + [3] * 3)[i]
+            q.nu, q.tol, q.steps = a["nu"], r.tol, r.steps
+            _lib.fill_body(q.body, a["body"], ndim)
+            _lib.check(lib.wl_ns_batch_footprint(ctypes.byref(q), 1, ctypes.byref(sz)))
+            return sz.value + cells * (4 * ndim + 8) + 4 * nn[1] * nn[2] + 512
         if self.batchable(r):
             q = _lib.BatchRequest()
             q.ndim = ndim
             for i in range(3):
                 q.n[i] = nn[i]
-            q.tol, q.max_vcycles = r.tol, 400
+            q.tol, q.max_vcycles, q.mixed = r.tol, 400, 1
             _lib.check(lib.wl_poisson_batch_footprint(ctypes.byref(q), 1, ctypes.byref(sz)))
             return sz.value + 8 * cells * (2 + ndim) + 256
         if r.kind == "poisson":
@@ -311,7 +335,8 @@ class GpuExecutor(Executor):
             d.n[i] = nn[i]
             d.bc_lo[i] = (a["bc_lo"] + [3] * 3)[i]
             d.bc_hi[i] = (a["bc_hi"] + [3] * 3)[i]
-        d.nu, d.prec, d.tol = a["nu"], _lib.WL_MIXED, 1e-7
+        d.nu, d.prec, d.tol = a["nu"], _lib.WL_MIXED, r.tol
+        d.stop_rule = _lib.STOP_RELATIVE
         d.body.kind = 1
         d.body.radius = r.radius
         _lib.check(lib.wl_sim_footprint(ctypes.byref(d), ctypes.byref(sz)))
@@ -324,9 +349,65 @@ class GpuExecutor(Executor):
         w = (torch.arange(bits.numel(), device=bits.device, dtype=torch.int64) % 1000003) + 1
         return int((bits.to(torch.int64) * w).sum().item())
 
+    def _ns_state(self, r):
+        """Initial state of an NS request: U on every face (boundary faces at
+        their value), the outflow plane at U, p = 0."""
+        torch = self.torch
+        ndim = len(r.n)
+        shape = tuple(reversed(list(r.n) + [1] * (3 - ndim)))
+        u = torch.zeros((ndim,) + shape, dtype=torch.float32, device=self.device)
+        u[0].fill_(1.0)
+        u[0][..., 0] = 1.0          # inflow face
+        for i in range(1, ndim):    # walls: zero normal velocity (already zero)
+            pass
+        uout = torch.ones(shape[:2], dtype=torch.float32, device=self.device)
+        p = torch.zeros(shape, dtype=torch.float64, device=self.device)
+        return u, uout, p
+
+    def run_ns_batch(self, rs):
+        """Small NS requests through one persistent kernel (a whole run per
+        workgroup).  With keep_fields the last step runs as a launch of its
+        own, so that the state before it is kept for replays (same bits)."""
+        torch, wl = self.torch, self.wl
+        stream = self._stream()
+        with torch.cuda.stream(stream):
+            reqs, states = [], []
+            for r in rs:
+                a = self._ns_args(r)
+                u, uout, p = self._ns_state(r)
+                reqs.append(dict(n=a["n"], bc_lo=a["bc_lo"], bc_hi=a["bc_hi"], U=a["U"],
+                                 nu=a["nu"], body=a["body"], tol=r.tol, max_vcycles=400,
+                                 steps=r.steps, u=u, uout=uout, p=p))
+                states.append((u, uout, p))
+            before = None
+            if self.keep:
+                first = [dict(q, steps=max(q["steps"] - 1, 0)) for q in reqs]
+                res0 = wl.ns_batch_run(first, allow_not_converged=True)
+                before = [(u.clone(), o.clone(), p.clone(), t) for (u, o, p), (_, _, t, _)
+                          in zip(states, res0)]
+                res = wl.ns_batch_run([dict(q, steps=1) for q in reqs], allow_not_converged=True)
+                res = [(s1, v0 + v1, t0 + t1, d1) for (s1, v1, t1, d1), (_, v0, t0, _)
+                       in zip(res, res0)]
+            else:
+                res = wl.ns_batch_run(reqs, allow_not_converged=True)
+            outs = []
+            for k, ((st, vc, t, dt), (u, uout, p)) in enumerate(zip(res, states)):
+                if st != 0:
+                    outs.append(RuntimeError(f"batched NS run status {st}"))
+                    continue
+                fp = self._fingerprint(u) * 1000003 + self._fingerprint(p)
+                outs.append((fp, dict(vcycles=vc, t=t, dt=dt, batched=True),
+                             (u, uout, p, before[k] if before else None) if self.keep else None))
+            stream.synchronize()
+        return outs
+
     def run_batch(self, rs):
-        """Small Poisson requests (FP64, Neumann box, centred sphere / circle,
-        N(0,1) right-hand side) through one persistent work-queue kernel."""
+        """Small Poisson requests (Neumann box, centred sphere / circle, N(0,1)
+        right-hand side; FP32 V-cycles with FP64 defect correction) through one
+        persistent work-queue kernel; small NS requests through the batched
+        NS kernel."""
+        if rs and rs[0].kind == "ns":
+            return self.run_ns_batch(rs)
         torch, wl = self.torch, self.wl
         stream = self._stream()
         with torch.cuda.stream(stream):
@@ -341,7 +422,7 @@ class GpuExecutor(Executor):
                 b = torch.randn(shape, generator=g, dtype=torch.float64, device=self.device)
                 x = torch.zeros_like(b)
                 reqs.append(dict(n=r.n, periodic=(False,) * ndim, coeffs=L, x=x, b=b, tol=r.tol,
-                                 max_vcycles=400))
+                                 max_vcycles=400, mixed=True))
                 keep.append((x, b, L))
             res = wl.poisson_batch_solve(reqs, allow_not_converged=True)
             outs = []
@@ -381,7 +462,8 @@ class GpuExecutor(Executor):
             else:
                 a = self._ns_args(r)
                 sim = wl.Sim(a["n"], a["bc_lo"], a["bc_hi"], a["U"], a["nu"], body=a["body"],
-                             prec=wl.WL_MIXED, tol=1e-7)
+                             prec=wl.WL_MIXED, tol=r.tol, stop_rule=wl.STOP_RELATIVE,
+                             max_vcycles=400)
                 vc = 0
                 for _ in range(r.steps):
                     st = sim.step()

@@ -145,3 +145,25 @@ def test_stop_rule_and_state_calls_validate_without_a_gpu():
     assert lib.wl_state_size(None, ctypes.byref(sz)) == -1
     assert lib.wl_get_state(None, None) == -1
     assert lib.wl_set_state(None, None) == -1
+
+
+def test_smoother_switch_is_validated_without_a_gpu():
+    from paper_2304_08159_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libwl.so not built")
+    lib = _lib.load()
+    assert lib.wl_set_smoother(2) == -1 and b"kind" in lib.wl_last_error()
+    d = _lib.SimDesc()
+    d.ndim = 3
+    for i in range(3):
+        d.n[i] = 32
+    d.nu, d.tol = 0.01, 1e-5
+    sizes = {}
+    for kind in (_lib.SMOOTH_CG, _lib.SMOOTH_JACOBI):
+        assert lib.wl_set_smoother(kind) == 0
+        sz = ctypes.c_size_t()
+        assert lib.wl_sim_footprint(ctypes.byref(d), ctypes.byref(sz)) == 0
+        sizes[kind] = sz.value
+    # CG smoothing carves four more arrays per level (residual, direction,
+    # M p, inverse diagonal): at least 4 fine-level FP32 fields
+    assert sizes[_lib.SMOOTH_CG] - sizes[_lib.SMOOTH_JACOBI] >= 4 * 4 * 32 ** 3

@@ -119,3 +119,35 @@ def test_zero_rhs_and_not_converged():
     out = wl.poisson_batch_solve([r0, r1], allow_not_converged=True)
     assert out[0][0] == 0 and out[0][1] == 0 and torch.all(r0["x"] == 0)
     assert out[1][0] == -3 and out[1][1] == 1
+
+
+def test_mixed_precision_batch_meets_fp64_tolerance():
+    """FP32 V-cycles with the FP64 defect correction inside the persistent
+    kernel: each request (including a 64^3 one, the largest a workgroup
+    takes) reaches the FP64 tolerance on the oracle's operator, in at most a
+    few more V-cycles than the FP64 solve, and its bits do not depend on the
+    batch."""
+    import paper_2304_08159_amd as wl
+    cases = CASES + [((64, 64, 64), (False, False, False), dict(centre=(32.0, 31.5, 32.4),
+                                                                 radius=9.0), 17)]
+    reqs, host = zip(*[_request(*c, tol=1e-9) for c in cases])
+    reqs = list(reqs)
+    for r in reqs:
+        r["mixed"] = True
+    out = wl.poisson_batch_solve(reqs)
+    ref = [_request(*c, tol=1e-9)[0] for c in cases]
+    out64 = wl.poisson_batch_solve(ref)
+    for (n, per, body, seed), r, (L, b), (st, k, rel), (st6, k6, rel6) in zip(
+            cases, reqs, host, out, out64):
+        act = P.active_mask(L, list(per))
+        b0 = P.project_rhs(b, act)
+        x = to_oracle(r["x"], len(n))
+        res = np.linalg.norm(b0 - P.apply_A(L, x, list(per))) / np.linalg.norm(b0)
+        print(n, per, "mixed vcycles", k, "rel", rel, "oracle rel", res, "| fp64 vcycles", k6)
+        assert st == 0 and res <= 1.05e-9
+        assert abs(rel - res) <= 1e-3 * rel + 1e-15
+        assert k <= k6 + 6
+    alone = _request(*cases[0], tol=1e-9)[0]
+    alone["mixed"] = True
+    wl.poisson_batch_solve([alone])
+    assert torch.equal(alone["x"], reqs[0]["x"])

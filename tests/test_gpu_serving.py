@@ -62,3 +62,40 @@ def test_served_poisson_meets_tolerance_on_oracle_operator():
         res = np.linalg.norm(bp - P.apply_A(Lo, xg, [False] * d)) / np.linalg.norm(bp)
         print(n, "served residual (oracle operator)", res, out.result[1])
         assert res <= 1.05e-8
+
+
+def test_served_ns_request_last_step_replays_against_the_oracle():
+    """A served (batched) NS request: its last step, from the state the server
+    kept before it, replayed by the FP64 oracle with the served dt: velocity
+    and outflow plane to 1e-5, pressure to 1e-5 in the energy norm."""
+    import math
+    from oracle import step as S
+    from tests.gpu_util import mean_free, plane_to_oracle
+    from paper_2304_08159_amd.serving import GpuExecutor, Request, Server
+    ex = GpuExecutor(keep_fields=True)
+    r = Request(id=0, kind="ns", n=(128, 64), radius=6.0, steps=6, tol=1e-8)
+    out = Server(ex, 8 << 30, slots=1).run([r])[0]
+    assert out.status == "done", out.error
+    fp, stats, (u, uout, p, before) = out.result
+    assert stats["batched"]
+    u0, o0, p0, t0 = before
+    a = ex._ns_args(r)
+    d = 2
+    osim = S.Sim(a["n"], a["bc_lo"], a["bc_hi"], a["U"], a["nu"], body=a["body"], tol=1e-12,
+                 stop_rule="relative", max_vcycles=300)
+    osim.u = [to_oracle(u0[i], d) for i in range(d)]
+    osim.uout = plane_to_oracle(o0, d)
+    osim.p = to_oracle(p0, d)
+    osim.step(dt=stats["dt"])
+    ug = [to_oracle(u[i], d) for i in range(d)]
+    eu = math.sqrt(sum(np.sum((x - y) ** 2) for x, y in zip(ug, osim.u)) /
+                   sum(np.sum(y ** 2) for y in osim.u))
+    eo = np.linalg.norm(plane_to_oracle(uout, d) - osim.uout) / np.linalg.norm(osim.uout)
+    act = osim.h.active[0]
+    pg, po = mean_free(to_oracle(p, d), act), mean_free(osim.p, act)
+    e = pg - po
+    ea = math.sqrt(abs(np.sum(e * P.apply_A(osim.L, e, [False, False]))) /
+                   abs(np.sum(po * P.apply_A(osim.L, po, [False, False]))))
+    print(f"served NS last step (t {t0:.3f} -> {stats['t']:.3f}): err_u={eu:.2e} "
+          f"err_uout={eo:.2e} err_p(energy)={ea:.2e}")
+    assert eu <= 1e-5 and eo <= 1e-5 and ea <= 1e-5
