@@ -381,9 +381,10 @@ def serving_bench(count=512, seed=2304, budget=16e9, slots=8):
     """Served mix: sizes uniform over 2D {64^2,128^2,256^2} and 3D {64^3,96^3,128^3},
     half Poisson solves, half 20-step NS runs with a body, all to a relative
     residual of 1e-8 with FP32 V-cycles and FP64 refinement; HBM budget 16 GB.
-    Poisson requests of at most 262144 cells and NS requests of at most 65536
+    Poisson requests of at most 16384 cells and NS requests of at most 4096
     cells are batched by kind into persistent work-queue kernels, larger ones
-    run alone.  Saturated throughput first (all requests at t = 0), then
+    run alone (the limits follow the latency of one request in one workgroup
+    against the whole GPU).  Saturated throughput first (all requests at t = 0), then
     Poisson arrivals at 0.5 and 0.8 of it."""
     from paper_2304_08159_amd.serving import GpuExecutor, Server, make_requests, summarize
     ex = GpuExecutor()

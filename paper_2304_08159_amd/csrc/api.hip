@@ -195,6 +195,7 @@ struct SimImpl {
     T* mu0[3];
     T* mu1n[9];
     unsigned char* tile_cls = nullptr;  // BDIM tile classes (one per block of the cell tiling)
+    unsigned char* cell_flag = nullptr;  // BDIM per-cell flags (bodies only)
     Hierarchy<T> h;
     Reduce red;
     double* scal = nullptr;  // [0] dt, [1] dt_next, [2] cfl max
@@ -230,6 +231,7 @@ static void carve_sim(Carver& c, SimImpl<T>& s, const SimConfig& cfg) {
     for (int i = 0; i < 3; ++i) s.mu0[i] = c.take<T>(N);
     for (int i = 0; i < 9; ++i) s.mu1n[i] = c.take<T>(N);
     s.tile_cls = c.take<unsigned char>(reduce_slots_for(cfg.g));
+    s.cell_flag = cfg.body ? c.take<unsigned char>(N) : nullptr;
     const int per[3] = {cfg.g.per0, cfg.g.per1, cfg.g.per2};
     carve_hierarchy<T>(c, s.h, cfg.d.ndim, cfg.d.n, per, cfg.nlev, cfg.d.prec == WL_MIXED);
     s.red.slots = reduce_slots_for(cfg.g);
@@ -238,6 +240,7 @@ static void carve_sim(Carver& c, SimImpl<T>& s, const SimConfig& cfg) {
     s.scal = c.take<double>(4);
     if (cfg.d.prec == WL_MIXED) {
         for (int i = 0; i < 3; ++i) s.mix.L[i] = c.take<double>(N);
+        s.mix.cls = c.take<unsigned char>(reduce_slots_for(cfg.g));
         s.mix.inner = cfg.d.inner_vcycles;
         s.p64 = c.take<double>(N);
         s.sigma64 = c.take<double>(N);
@@ -332,6 +335,7 @@ static BdimFields<T> bdim_fields(const SimImpl<T>& s) {
     for (int i = 0; i < 3; ++i) b.mu0[i] = s.mu0[i];
     for (int i = 0; i < 9; ++i) b.mu1n[i] = s.mu1n[i];
     b.cls = s.tile_cls;
+    b.cflag = s.cell_flag;
     return b;
 }
 
@@ -350,10 +354,11 @@ static wl_status sim_measure(SimImpl<T>& s, double t, hipStream_t st) {
     }
     for (int i = 0; i < 9; ++i) M.mu1n[i] = s.mu1n[i];
     WL_TRY(ns_measure<T>(c.g, body, c.d.bc_lo, M, st));
-    if (c.body) WL_TRY(ns_tile_class<T>(c.g, bdim_fields(s), s.tile_cls, st));
+    if (c.body) WL_TRY(ns_tile_class<T>(c.g, bdim_fields(s), s.tile_cls, st, s.cell_flag));
     s.h.lev[0].uniform = c.unif ? 1 : 0;
     s.h.lev[0].Lc = T(1);
     WL_TRY(mg_coarsen_all<T>(s.h, st));
+    if (c.d.prec == WL_MIXED) WL_TRY(mg_mixed_classes(c.g, s.mix, st));
     return mg_count_active<T>(s.h, s.red, st);
 }
 
@@ -502,11 +507,12 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
             WL_TRY(rec3(tp->f1, s.vel[A]));
             if (c.outflow) WL_TRY(rec(tp->fo1, s.plane[P1], c.P));
         }
-        int us = A;
+        // BDIM in place: u* stays in A (set B is its scratch on the body's tiles)
+        const int us = A;
         if (c.body) {
-            T* o[3] = {s.vel[B][0], s.vel[B][1], s.vel[B][2]};
-            WL_TRY(ns_bdim<T>(field_of(s, A, s.plane[P1]), bdim_fields(s), o, st, motion));
-            us = B;
+            T* w[3] = {s.vel[B][0], s.vel[B][1], s.vel[B][2]};
+            WL_TRY(ns_bdim_in_place<T>(field_of(s, A, s.plane[P1]), f, bdim_fields(s), w, st,
+                                       motion));
         }
         const VelField<T> V = field_of(s, us, s.plane[P1]);
         WL_TRY(ns_divergence<T>(V, pc, c.unif, 1.0, dt_dev, s.sigma, s.red.partial, ap, st,
@@ -551,11 +557,12 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
             WL_TRY(rec3(tp->f2, s.vel[fr]));
             if (c.outflow) WL_TRY(rec(tp->fo2, s.plane[P2], c.P));
         }
-        int us2 = fr;
+        // u* stays in fr; u^n (set S) is no longer read and serves as scratch
+        const int us2 = fr;
         if (c.body) {
-            T* o2[3] = {s.vel[S][0], s.vel[S][1], s.vel[S][2]};
-            WL_TRY(ns_bdim<T>(field_of(s, fr, s.plane[P2]), bdim_fields(s), o2, st, motion));
-            us2 = S;
+            T* w2[3] = {s.vel[S][0], s.vel[S][1], s.vel[S][2]};
+            WL_TRY(ns_bdim_in_place<T>(field_of(s, fr, s.plane[P2]), f2, bdim_fields(s), w2, st,
+                                       motion));
         }
         const VelField<T> V2 = field_of(s, us2, s.plane[P2]);
         WL_TRY(ns_divergence<T>(V2, pc, c.unif, 0.5, dt_dev, s.sigma, s.red.partial, ap, st,
@@ -954,6 +961,7 @@ static wl_status poisson_solve_mixed(wl_poisson* ps, const void* coeffs, void* x
                                               P.mix.L, st)));
         P.h.lev[0].uniform = 0;
         WL_TRY(mg_coarsen_all<float>(P.h, st));
+        WL_TRY(mg_mixed_classes(P.g, P.mix, st));
         WL_TRY(mg_count_active64(P.g, P.mix.L, P.red, &P.h.n_active, st));
         P.have = true;
     }
@@ -1294,6 +1302,7 @@ wl_status wl_poisson_footprint(int ndim, const int n[3], const int periodic[3], 
         PoissonMixedImpl P;
         carve_poisson_common(c, P, g, nlev, true);
         for (int i = 0; i < 3; ++i) P.mix.L[i] = c.take<double>(cells(g));
+        P.mix.cls = c.take<unsigned char>(reduce_slots_for(g));
     }
     *bytes = c.off;
     return WL_OK;
@@ -1341,6 +1350,7 @@ wl_status wl_poisson_create(int ndim, const int n[3], const int periodic[3], int
         P->nlev = nlev;
         carve_poisson_common(c, *P, g, nlev, true);
         for (int i = 0; i < 3; ++i) P->mix.L[i] = c.take<double>(cells(g));
+        P->mix.cls = c.take<unsigned char>(reduce_slots_for(g));
         P->h.coarse_tol = 1e-6;
         ps->impl = P;
     }

@@ -7,8 +7,9 @@
 // post-sweeps), residual fused with sum-restriction, cell-centred linear
 // prolongation added in place before the post-sweeps, a one-workgroup FP64 CG on
 // the coarsest level, and FP64 fixed-order reductions for the norms and the
-// active-set mean.  On uniform periodic 3D levels each pair of sweeps runs as
-// one LDS-tiled kernel that keeps the intermediate iterate on chip.
+// active-set mean.  On 3D levels whose x and y extents are multiples of 8
+// each pair of sweeps runs as one LDS-tiled kernel that keeps the
+// intermediate iterate on chip.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -114,6 +115,30 @@ static unsigned pair_blocks() {
 }
 
 static Launch launch_pairs(const Grid& g);
+// Workgroups of the fused-pair tiling of a 3D level (0 when it does not fit).
+static unsigned pair_class_slots(const Grid& g);
+
+// Fused pairs on non-uniform or non-periodic levels (WL_GEN_PAIRS=0 turns
+// them off, for measurement; the iterates are the same either way).
+static bool gen_pairs() {
+    static const bool v = [] {
+        const char* e = std::getenv("WL_GEN_PAIRS");
+        return !(e && std::atoi(e) == 0);
+    }();
+    return v;
+}
+
+// Smallest non-uniform level fused in mode 1 (WL_GEN_PAIR_MIN_CELLS
+// overrides it): below it the two launches of a pair cost more than the
+// separate sweeps they replace.
+static size_t gen_pair_min_cells() {
+    static const size_t v = [] {
+        const char* e = std::getenv("WL_GEN_PAIR_MIN_CELLS");
+        const long t = e ? std::atol(e) : -1;
+        return t >= 0 ? size_t(t) : (size_t(1) << 22);
+    }();
+    return v;
+}
 
 // Process-wide smoother of the multigrid levels (wl_set_smoother), taken by
 // each hierarchy when it is laid out: 0 damped Jacobi, 1 conjugate gradients.
@@ -138,6 +163,9 @@ void carve_hierarchy(Carver& c, Hierarchy<T>& h, int ndim, const int n[3], const
         L.b = c.take<T>(N);
         L.cls = c.take<unsigned char>(reduce_slots_for(L.g));
         L.cls_pairs = c.take<unsigned char>(launch_pairs(L.g).nblocks());
+        const unsigned fp = pair_class_slots(L.g);
+        L.cls_fp = fp ? c.take<unsigned char>(fp) : nullptr;
+        L.fp_list = fp ? c.take<unsigned>(size_t(fp) + 1) : nullptr;
         if (h.smoother == 1 && l < nlev - 1) {
             L.cr = c.take<T>(N);
             L.cp = c.take<T>(N);
@@ -303,25 +331,61 @@ struct PairTile {
     int zc;       // z planes per workgroup
     unsigned nb;  // workgroups
     int remap;    // XCD-contiguous tile order (nb % 8 == 0)
+    int split;    // MODE 2: workgroups per chunk (each walks zc / split planes)
 };
 
-template <typename T, int XM, int TX>
+// MODE 0: a uniform, fully periodic level (wD = w / D).  MODE 1 / 2: a
+// non-uniform level with any boundaries, in two launches over the same
+// workgroups: MODE 1 runs the workgroups whose widened region is of class 0
+// (see k_pair_class; face coefficients from the position), MODE 2 the others
+// (coefficients read), so each instance keeps its own register budget:
+// MODE 1 runs over all workgroups and leaves the class-1 ones at once, MODE 2
+// over the list fpl of the class-1 workgroups (fpl[P.nb] of them), each
+// chunk walked by P.split workgroups, a part of the planes each (the parts
+// recompute the first sweep of one plane on either side), so that the few
+// body chunks do not make a long tail on a handful of CUs.  Coordinates outside a non-periodic direction are
+// clamped (the cells there are only ever weighted by a zero face
+// coefficient, so any finite value serves), each cell has its own D, and wD
+// is the damping w.  The arithmetic per cell is that of k_smooth's
+// non-uniform path, so the result is again bitwise that of two separate
+// sweeps.
+template <typename T, int XM, int TX, int MODE>
 __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Grid g, XAccess<T, XM> X,
-                                                              T Lc, const T* __restrict__ b,
+                                                              Coeffs<T> Cf, const T* __restrict__ b,
                                                               T wD, T* __restrict__ xout,
-                                                              const double* __restrict__ bshift) {
+                                                              const double* __restrict__ bshift,
+                                                              const unsigned* __restrict__ fpl) {
     using Sh = PairShape<TX>;
+    const T Lc = Cf.Lc;
+    constexpr bool GEN = MODE != 0;
+    // MODE 2: part `part` of the chunk of listed workgroup blockIdx.x / split
+    unsigned wg = blockIdx.x;
+    int part = 0;
+    if constexpr (MODE == 1) {
+        if (Cf.cls[wg] != 0) return;  // the MODE 2 launch takes it
+    } else if constexpr (MODE == 2) {
+        const unsigned q = blockIdx.x / unsigned(P.split);
+        if (q >= fpl[P.nb]) return;  // the grid covers the largest count met
+        wg = fpl[q];
+        part = int(blockIdx.x % unsigned(P.split));
+    }
     constexpr int kPairTX = TX, kPairThreads = Sh::T, kPairHX = Sh::HX, kPairHY = Sh::HY;
     constexpr int kPairGX = Sh::GX, kPairRing1 = Sh::R1, kPairRing2 = Sh::R2;
     __shared__ T s0[2][Sh::GY * Sh::GX];  // input plane, tile widened by two
     __shared__ T s1[2][Sh::HY * Sh::HX];  // first-sweep plane, tile widened by one
-    unsigned blk = blockIdx.x;
+    unsigned blk = wg;
     if (P.remap) blk = (blk & 7u) * (P.nb >> 3) + (blk >> 3);
     const int tix = int(blk % unsigned(P.tx));
     blk /= unsigned(P.tx);
     const int tiy = int(blk % unsigned(P.ty));
-    const int z0 = int(blk / unsigned(P.ty)) * P.zc;
-    const int z1 = min(z0 + P.zc, g.n2);
+    int z0 = int(blk / unsigned(P.ty)) * P.zc;
+    int z1 = min(z0 + P.zc, g.n2);
+    if constexpr (MODE == 2) {
+        const int zs = (P.zc + P.split - 1) / P.split;
+        z0 += part * zs;
+        z1 = min(z0 + zs, z1);
+        if (z0 >= z1) return;
+    }
     const int i0 = tix * kPairTX, j0 = tiy * kPairTY;
     const int t = int(threadIdx.x);
     const unsigned n0 = unsigned(g.n0), plane = n0 * unsigned(g.n1);
@@ -332,12 +396,19 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
     struct Slot {
         unsigned col;
         int q;
+        int ci, cj;  // grid coordinates of the column
     };
     auto slot = [&](int gx, int gy) -> Slot {
         int i = i0 + gx - 2, j = j0 + gy - 2;
-        i = i < 0 ? i + g.n0 : (i >= g.n0 ? i - g.n0 : i);
-        j = j < 0 ? j + g.n1 : (j >= g.n1 ? j - g.n1 : j);
-        return Slot{unsigned(i) + n0 * unsigned(j), gy * kPairGX + gx};
+        if (!GEN || g.per0)
+            i = i < 0 ? i + g.n0 : (i >= g.n0 ? i - g.n0 : i);
+        else
+            i = min(max(i, 0), g.n0 - 1);
+        if (!GEN || g.per1)
+            j = j < 0 ? j + g.n1 : (j >= g.n1 ? j - g.n1 : j);
+        else
+            j = min(max(j, 0), g.n1 - 1);
+        return Slot{unsigned(i) + n0 * unsigned(j), gy * kPairGX + gx, i, j};
     };
     // A: the thread's own tile cell; B: a cell of the first-sweep ring (the
     // first kPairRing1 threads); C: a cell of the input ring (the last
@@ -388,6 +459,12 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
         return p < 0 ? p + g.n2 : p;
     };
     auto next = [&](int w) { return w + 1 == g.n2 ? 0 : w + 1; };
+    // GEN keeps plane numbers unwrapped and maps them at each load (wrapped
+    // on a periodic z, clamped otherwise)
+    auto zmap = [&](int p) { return g.per2 ? wrap(p) : min(max(p, 0), g.n2 - 1); };
+    auto zfirst = [&](int p) { return GEN ? p : wrap(p); };
+    auto znext = [&](int w) { return GEN ? w + 1 : next(w); };
+    auto zld = [&](int w) { return GEN ? zmap(w) : w; };
     // one D for the whole level; right-hand sides are shifted once, when
     // they become current, and serve both sweeps
     T Du = T(0);
@@ -414,6 +491,90 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
                                        xzl, xzu, Lc, true);
         return jacobi_new_scaled(xI, bv - Ax, act, wD);
     };
+    // GEN, by mode: 1 a workgroup of class 0 (coefficients from the
+    // position), 2 one that reads them.
+    // Face coefficients of the column S at plane k (k inside the grid).
+    auto faces = [&](auto mt, const Slot& S, int k, T& Lxl, T& Lxu, T& Lyl, T& Lyu, T& Lzl,
+                     T& Lzu) {
+        if constexpr (decltype(mt)::value == 1) {
+            walled_faces<T>(g, S.ci, S.cj, k, Lc, Lxl, Lxu, Lyl, Lyu, Lzl, Lzu);
+            return;
+        }
+        const size_t id = size_t(S.col) + size_t(k) * size_t(plane);
+        const bool hxu = S.ci < g.n0 - 1 || g.per0, hyu = S.cj < g.n1 - 1 || g.per1;
+        const bool hzu = k < g.n2 - 1 || g.per2;
+        const long long oxp = S.ci < g.n0 - 1 ? 1 : 1 - (long long)g.n0;
+        const long long oyp = S.cj < g.n1 - 1 ? (long long)n0 : -(long long)n0 * (g.n1 - 1);
+        const long long ozp =
+            k < g.n2 - 1 ? (long long)plane : -(long long)plane * (g.n2 - 1);
+        Lxl = Cf.L0[id];
+        Lxu = hxu ? Cf.L0[(long long)id + oxp] : T(0);
+        Lyl = Cf.L1[id];
+        Lyu = hyu ? Cf.L1[(long long)id + oyp] : T(0);
+        Lzl = Cf.L2[id];
+        Lzu = hzu ? Cf.L2[(long long)id + ozp] : T(0);
+    };
+    // Mode 1: every cell is active and D = (6 - nb) Lc exactly, nb the
+    // cell's non-periodic domain-boundary faces, so w / D is one of four
+    // values, formed once by the same division.
+    T tb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) tb[q] = wD / (T(6 - q) * Lc);
+    auto wd_walled = [&](const Slot& S, int k) -> T {
+        const int nb = int(S.ci == 0 && !g.per0) + int(S.ci == g.n0 - 1 && !g.per0) +
+                       int(S.cj == 0 && !g.per1) + int(S.cj == g.n1 - 1 && !g.per1) +
+                       int(k == 0 && !g.per2) + int(k == g.n2 - 1 && !g.per2);
+        return nb == 0 ? tb[0] : (nb == 1 ? tb[1] : (nb == 2 ? tb[2] : tb[3]));
+    };
+    // x - (w / D) r as jacobi_new forms it
+    auto update = [&](auto mt, const Slot& S, int k, T xI, T r, T D) -> T {
+        if constexpr (decltype(mt)::value == 1)
+            return xI - wd_walled(S, k) * r;
+        else
+            return jacobi_new(xI, r, D, wD);
+    };
+    // First sweep of column S at plane k (input-region position S.q of S0);
+    // bv comes in raw and leaves shifted.
+    // (Mode 2 passes the coefficients it loaded at the start of the step in
+    // F; mode 1 forms them here.)
+    auto coef = [&](auto mt, const Slot& S, int k, const T (&F)[6], T& Lxl, T& Lxu, T& Lyl,
+                    T& Lyu, T& Lzl, T& Lzu) {
+        if constexpr (decltype(mt)::value == 2) {
+            Lxl = F[0];
+            Lxu = F[1];
+            Lyl = F[2];
+            Lyu = F[3];
+            Lzl = F[4];
+            Lzu = F[5];
+        } else {
+            faces(mt, S, k, Lxl, Lxu, Lyl, Lyu, Lzl, Lzu);
+        }
+    };
+    auto sweep1g = [&](auto mt, const T* S0, const Slot& S, int k, T xI, T xzl, T xzu,
+                       T& bv, const T (&F)[6]) -> T {
+        T xxl = T(0), xxu = T(0), xyl = T(0), xyu = T(0);
+        if (XM != XM_ZERO) {
+            xxl = S0[S.q - 1];
+            xxu = S0[S.q + 1];
+            xyl = S0[S.q - kPairGX];
+            xyu = S0[S.q + kPairGX];
+        }
+        T Lxl, Lxu, Lyl, Lyu, Lzl, Lzu, Ax, D;
+        coef(mt, S, k, F, Lxl, Lxu, Lyl, Lyu, Lzl, Lzu);
+        jacobi_terms(xI, xxl, xxu, xyl, xyu, xzl, xzu, Lxl, Lxu, Lyl, Lyu, Lzl, Lzu, true, Ax, D);
+        bv = jacobi_rhs(bv, decltype(mt)::value == 1 || D > T(0), shift, mean);
+        return update(mt, S, k, xI, bv - Ax, D);
+    };
+    // Second sweep of column S at plane k (first-sweep position h of S1; bv
+    // already shifted).
+    auto sweep2g = [&](auto mt, const T* S1, int h, const Slot& S, int k, T xI, T xzl, T xzu,
+                       T bv, const T (&F)[6]) -> T {
+        T Lxl, Lxu, Lyl, Lyu, Lzl, Lzu, Ax, D;
+        coef(mt, S, k, F, Lxl, Lxu, Lyl, Lyu, Lzl, Lzu);
+        jacobi_terms(xI, S1[h - 1], S1[h + 1], S1[h - kPairHX], S1[h + kPairHX], xzl, xzu, Lxl,
+                     Lxu, Lyl, Lyu, Lzl, Lzu, true, Ax, D);
+        return update(mt, S, k, xI, bv - Ax, D);
+    };
     // Step s computes the first sweep on plane s and the second on plane
     // s - 1, for s = z0 - 1 .. z1, and issues the loads of plane s + 1 + Dp.
     // Per-plane values live in register rings indexed by plane (mod R); the
@@ -424,10 +585,16 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
     //           plane s - 1 for the second sweep)
     //   xC:     input of slot C at plane s
     //   yA:     A's first-sweep values (planes s - 2 .. s)
+    // The whole walk, for one mode (0: the uniform kernel); a workgroup runs
+    // the instance of its class, so no cell branches on it.
+    auto run = [&](auto mt) {
     constexpr int Dp = kPairDepth;
     constexpr int R = Dp + 3;
     static_assert(R % 2 == 0, "the LDS buffers alternate with the ring index");
     T xA[R] = {}, xB[R] = {}, rA[R] = {}, rB[R] = {}, xC[R] = {}, yA[R] = {};
+    // mode 2: face coefficients of A at planes s and s - 1 (by step parity)
+    // and of B at plane s
+    T fA[2][6] = {}, fB[6] = {};
     const int s0p = z0 - 1;  // first step; ring slot of plane p is (p - s0p) mod R
     int wx;                  // wrapped plane of the next loads, s + 1 + Dp
     int wxm;                 // the last plane loaded
@@ -435,20 +602,20 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
         // every thread issues the same loads (B and C default to A), so that
         // waits on earlier loads can count them; planes past z1 + 1 that a
         // short chunk loads here are not used
-        int w = wrap(s0p - 1);
-        xA[R - 1] = ld(A, w);
-        xB[R - 1] = ld(B, w);
+        int w = zfirst(s0p - 1);
+        xA[R - 1] = ld(A, zld(w));
+        xB[R - 1] = ld(B, zld(w));
 #pragma unroll
         for (int k = 0; k <= Dp; ++k) {
-            w = next(w);  // s0p + k
-            xA[k] = ld(A, w);
-            xB[k] = ld(B, w);
-            rA[k] = ldb(A, w);
-            rB[k] = ldb(B, w);
-            xC[k] = ld(C, w);
+            w = znext(w);  // s0p + k
+            xA[k] = ld(A, zld(w));
+            xB[k] = ld(B, zld(w));
+            rA[k] = ldb(A, zld(w));
+            rB[k] = ldb(B, zld(w));
+            xC[k] = ld(C, zld(w));
         }
-        wxm = w;       // s0p + Dp
-        wx = next(w);  // s0p + 1 + Dp
+        wxm = w;        // s0p + Dp
+        wx = znext(w);  // s0p + 1 + Dp
     }
     int s = s0p;
     // one step; r = (s - s0p) mod R; st: whether plane s - 1 gets its second
@@ -461,6 +628,14 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
         T* S0 = s0[r & 1];
         T* S1 = s1[r & 1];
         const T* S1m = s1[(r & 1) ^ 1];
+        if constexpr (decltype(mt)::value == 2) {
+            // all twelve coefficient loads of the step in flight together
+            // (B defaults to A: the loads are unconditional)
+            const int kc = zmap(s);
+            faces(mt, A, kc, fA[r & 1][0], fA[r & 1][1], fA[r & 1][2], fA[r & 1][3],
+                  fA[r & 1][4], fA[r & 1][5]);
+            faces(mt, B, kc, fB[0], fB[1], fB[2], fB[3], fB[4], fB[5]);
+        }
         // Stores and loads are unconditional: a thread without a ring cell
         // stores its own value again (B and C default to A), and the chunk's
         // last steps load wrapped planes they do not use.  A branch around a
@@ -476,22 +651,37 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
             // plane s + 1 + Dp; the chunk's last steps, which never use it
             // (past z1 + 1), repeat the last plane loaded (cache hits)
             constexpr int j = (r + 1 + Dp) % R;
-            const int wl = s + Dp <= z1 ? wx : wxm;
+            const int wl = zld(s + Dp <= z1 ? wx : wxm);
             xA[j] = ld(A, wl);
             xB[j] = ld(B, wl);
             rA[j] = ldb(A, wl);
             rB[j] = ldb(B, wl);
             xC[j] = ld(C, wl);
         }
-        rA[i0] = rhs(rA[i0]);
-        const T y = sweep1(S0, A.q, xA[i0], xA[im1], xA[ip1], rA[i0]);
-        yA[i0] = y;
-        S1[hA] = y;
-        if (hasB) S1[hB] = sweep1(S0, B.q, xB[i0], xB[im1], xB[ip1], rhs(rB[i0]));
-        if (store)
-            xout[A.col + unsigned(s - 1) * plane] = sweep2(S1m, hA, yA[im1], yA[im2], y, rA[im1]);
+        if constexpr (decltype(mt)::value != 0) {
+            const int kc = zmap(s);
+            const T y = sweep1g(mt, S0, A, kc, xA[i0], xA[im1], xA[ip1], rA[i0], fA[r & 1]);
+            yA[i0] = y;
+            S1[hA] = y;
+            if (hasB) {
+                T bvB = rB[i0];
+                S1[hB] = sweep1g(mt, S0, B, kc, xB[i0], xB[im1], xB[ip1], bvB, fB);
+            }
+            if (store)
+                xout[A.col + unsigned(s - 1) * plane] = sweep2g(
+                    mt, S1m, hA, A, s - 1, yA[im1], yA[im2], y, rA[im1], fA[(r & 1) ^ 1]);
+        } else {
+            rA[i0] = rhs(rA[i0]);
+            const T y = sweep1(S0, A.q, xA[i0], xA[im1], xA[ip1], rA[i0]);
+            yA[i0] = y;
+            S1[hA] = y;
+            if (hasB) S1[hB] = sweep1(S0, B.q, xB[i0], xB[im1], xB[ip1], rhs(rB[i0]));
+            if (store)
+                xout[A.col + unsigned(s - 1) * plane] =
+                    sweep2(S1m, hA, yA[im1], yA[im2], y, rA[im1]);
+        }
         if (s + Dp <= z1) wxm = wx;
-        wx = next(wx);
+        wx = znext(wx);
         ++s;
     };
     using I0 = std::integral_constant<int, 0>;
@@ -538,6 +728,8 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
         if (s <= z1) step(I5{}, Store{});
         if (s <= z1) step(I0{}, Store{});
     }
+    };
+    run(std::integral_constant<int, MODE>{});
 }
 
 // x += P xc: the coarse correction interpolated linearly onto the fine
@@ -546,6 +738,10 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
 // only its own x and coarse values.  The thread walks its (i, j) column up
 // the z chunk; the 2^d coarse values a cell reads are shared with its
 // neighbours and come from L1 / L2 (the coarse level is 1/2^d the size).
+// In 3D each coarse plane's x / y interpolation onto the thread's column
+// (prolong_at's per-plane value, the same operations) is formed once and
+// kept while the walk needs it: two fine planes share each coarse plane, so
+// a fine cell costs two coarse loads instead of eight.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prolong(TileDev TL, Grid g, Grid gc,
                                                     const T* __restrict__ xc, T* __restrict__ x) {
@@ -553,8 +749,45 @@ __global__ __launch_bounds__(kBlock) void k_prolong(TileDev TL, Grid g, Grid gc,
     if (sp.i >= g.n0 || sp.j >= g.n1) return;
     const size_t plane = size_t(g.n0) * size_t(g.n1);
     size_t id = size_t(sp.i) + size_t(g.n0) * size_t(sp.j) + plane * size_t(sp.z0);
-    for (int k = sp.z0; k < sp.z1; ++k, id += plane)
-        x[id] += prolong_at<T>(g, gc, xc, sp.i, sp.j, k);
+    if (gc.n2 == g.n2) {  // z not coarsened (2D)
+        for (int k = sp.z0; k < sp.z1; ++k, id += plane)
+            x[id] += prolong_at<T>(g, gc, xc, sp.i, sp.j, k);
+        return;
+    }
+    int ip, iq, jp, jq;
+    prolong_pair(sp.i, gc.n0, g.per0, ip, iq);
+    prolong_pair(sp.j, gc.n1, g.per1, jp, jq);
+    const size_t cn0 = size_t(gc.n0), cpl = cn0 * size_t(gc.n1);
+    auto cplane = [&](int K) -> T {
+        const T* r = xc + cpl * size_t(K);
+        const T lo = lerp34(r[ip + cn0 * jp], r[iq + cn0 * jp]);
+        const T hi = lerp34(r[ip + cn0 * jq], r[iq + cn0 * jq]);
+        return lerp34(lo, hi);
+    };
+    // the last three coarse planes formed (plane numbers are the same for
+    // the whole workgroup, so the lookups do not diverge)
+    int ka = -1, kb = -1, kc = -1;
+    T va = T(0), vb = T(0), vc = T(0);
+    auto get = [&](int K) -> T {
+        if (K == kc) return vc;
+        if (K == kb) return vb;
+        if (K == ka) return va;
+        const T v = cplane(K);
+        ka = kb;
+        va = vb;
+        kb = kc;
+        vb = vc;
+        kc = K;
+        vc = v;
+        return v;
+    };
+    for (int k = sp.z0; k < sp.z1; ++k, id += plane) {
+        int kp, kq;
+        prolong_pair(k, gc.n2, g.per2, kp, kq);
+        const T near = get(kp);
+        const T far = get(kq);
+        x[id] += lerp34(near, far);
+    }
 }
 
 // Coarse right-hand side = sum of the 2^d child residuals r = b - A x.  The
@@ -806,13 +1039,91 @@ __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ part
     }
 }
 
-// Coarsest level (see coarse_cg_block).
+// Coarsest level: the iteration of coarse_cg_block (CG on -A over the active
+// cells, mean-free right-hand side and result, FP64) with one cell per thread
+// (N <= blockDim <= 1024).  Each thread builds its cell's stencil once (the
+// diagonal, six face coefficients and six neighbour slots, a missing
+// neighbour being the cell itself with the coefficient the generic solver
+// uses), so an iteration is six LDS reads of the search direction, two
+// fixed-order sums (one barrier each, alternating buffers) and the barrier
+// after the direction update.
 template <typename T>
-__global__ __launch_bounds__(256) void k_coarse_cg(Grid g, Coeffs<T> C, int uniform,
-                                                   const T* __restrict__ b, T* __restrict__ xout,
-                                                   double tol, int maxit) {
-    __shared__ CoarseLds S;
-    coarse_cg_block<T>(g, C, uniform, b, xout, tol, maxit, S);
+__global__ __launch_bounds__(1024) void k_coarse_cg(Grid g, Coeffs<T> C, int uniform,
+                                                    const T* __restrict__ b, T* __restrict__ xout,
+                                                    double tol, int maxit) {
+    __shared__ double sp[kCoarseMax];
+    __shared__ double red[2][16];
+    const int N = int(cells(g));
+    const int t = int(threadIdx.x), nw = int(blockDim.x) >> 6;
+    const bool own = t < N;
+    auto wsum = [&](double v, int buf) -> double {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if ((t & 63) == 0) red[buf][t >> 6] = v;
+        __syncthreads();
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += red[buf][w];
+        return s;
+    };
+    double D = 0.0, cf[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int nb[6] = {t, t, t, t, t, t};
+    if (own) {
+        const int i = t % g.n0, j = (t / g.n0) % g.n1, k = t / (g.n0 * g.n1);
+        const int n[3] = {g.n0, g.n1, g.n2}, per[3] = {g.per0, g.per1, g.per2};
+        const int co[3] = {i, j, k}, st[3] = {1, g.n0, g.n0 * g.n1};
+        const T* Ld[3] = {C.L0, C.L1, C.L2};
+        for (int d = 0; d < g.ndim; ++d) {
+            const int lo = nb_lo(co[d], n[d], per[d]), up = nb_up(co[d], n[d], per[d]);
+            nb[2 * d] = t + (lo - co[d]) * st[d];
+            nb[2 * d + 1] = t + (up - co[d]) * st[d];
+            const double Ll = uniform ? double(C.Lc) : double(Ld[d][t]);
+            const double Lu = (co[d] < n[d] - 1 || per[d])
+                                  ? (uniform ? double(C.Lc) : double(Ld[d][nb[2 * d + 1]]))
+                                  : 0.0;
+            cf[2 * d] = Ll;
+            cf[2 * d + 1] = Lu;
+            D += Ll + Lu;
+        }
+    }
+    const bool act = D > 0.0;
+    // mean of b over the active cells
+    const double sumb = wsum(act ? double(b[t]) : 0.0, 0);
+    const double cnt = wsum(act ? 1.0 : 0.0, 1);
+    const double mean = cnt > 0.0 ? sumb / cnt : 0.0;
+    // solve M x = B with M = -A, B = -(b - mean) on active cells
+    const double B = act ? -(double(b[t]) - mean) : 0.0;
+    double x = 0.0, r = B, p = B;
+    if (own) sp[t] = p;
+    double rr = wsum(B * B, 0);  // its barrier also publishes sp
+    const double rr0 = rr;
+    if (rr0 > 0.0) {
+        for (int it = 0; it < maxit; ++it) {
+            double Mp = 0.0;
+            if (act) {
+                Mp = D * p;
+#pragma unroll
+                for (int m = 0; m < 6; ++m) Mp -= cf[m] * sp[nb[m]];
+            }
+            const double pq = wsum(p * Mp, 1);
+            if (!(pq > 0.0)) break;
+            const double alpha = rr / pq;
+            x += alpha * p;
+            r -= alpha * Mp;
+            const double rn = wsum(r * r, 0);
+            if (rn <= tol * tol * rr0) break;
+            const double beta = rn / rr;
+            rr = rn;
+            p = r + beta * p;
+            if (own) sp[t] = p;
+            __syncthreads();
+        }
+    }
+    // mean-free result on the active cells (the barrier keeps the last
+    // sum's buffer until every wave has read it)
+    __syncthreads();
+    const double xs = wsum(act ? x : 0.0, 1);
+    const double xm = cnt > 0.0 ? xs / cnt : 0.0;
+    if (own) xout[t] = act ? T(x - xm) : T(0);
 }
 
 // Per-block class of a level for a tiling (see Coeffs::cls): 0 when every
@@ -845,6 +1156,81 @@ __global__ __launch_bounds__(kBlock) void k_level_class(TileDev TL, Grid g, Coef
     if (odd) any = 1;  // benign race: every writer stores 1
     __syncthreads();
     if (threadIdx.x == 0) cls[block_linear()] = any ? 1 : 0;
+}
+
+// Class of each fused-pair workgroup (k_smooth_pair, MODE 1 / 2): 0 when every
+// face of every cell whose first sweep the workgroup computes (its tile
+// widened by one cell in x and y, its z chunk by one plane on either side;
+// cells outside a non-periodic direction excluded) equals what walled_faces
+// gives, else 1.  The workgroup-to-tile map is the pair kernel's.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pair_class(PairTile P, Grid g, int tx, Coeffs<T> C,
+                                                    unsigned char* __restrict__ cls) {
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    unsigned blk = blockIdx.x;
+    if (P.remap) blk = (blk & 7u) * (P.nb >> 3) + (blk >> 3);
+    const int tix = int(blk % unsigned(P.tx));
+    blk /= unsigned(P.tx);
+    const int tiy = int(blk % unsigned(P.ty));
+    const int z0 = int(blk / unsigned(P.ty)) * P.zc;
+    const int z1 = min(z0 + P.zc, g.n2);
+    const int i0 = tix * tx, j0 = tiy * kPairTY;
+    const int wx = tx + 2, wy = kPairTY + 2, wz = z1 - z0 + 2;
+    const int count = wx * wy * wz;
+    bool odd = false;
+    for (int q = int(threadIdx.x); q < count && !odd; q += int(blockDim.x)) {
+        int i = i0 - 1 + q % wx;
+        int j = j0 - 1 + (q / wx) % wy;
+        int k = z0 - 1 + q / (wx * wy);
+        if (i < 0 || i >= g.n0) {
+            if (!g.per0) continue;
+            i = i < 0 ? i + g.n0 : i - g.n0;
+        }
+        if (j < 0 || j >= g.n1) {
+            if (!g.per1) continue;
+            j = j < 0 ? j + g.n1 : j - g.n1;
+        }
+        if (k < 0 || k >= g.n2) {
+            if (!g.per2) continue;
+            k = k < 0 ? k + g.n2 : k - g.n2;
+        }
+        const size_t id = cid(g, i, j, k);
+        T Lxl, Lxu, Lyl, Lyu, Lzl, Lzu;
+        walled_faces<T>(g, i, j, k, C.Lc, Lxl, Lxu, Lyl, Lyu, Lzl, Lzu);
+        odd = odd || C.L0[id] != Lxl || C.L1[id] != Lyl || C.L2[id] != Lzl;
+        if (i < g.n0 - 1 || g.per0) odd = odd || C.L0[cid(g, nb_up(i, g.n0, g.per0), j, k)] != Lxu;
+        if (j < g.n1 - 1 || g.per1) odd = odd || C.L1[cid(g, i, nb_up(j, g.n1, g.per1), k)] != Lyu;
+        if (k < g.n2 - 1 || g.per2) odd = odd || C.L2[cid(g, i, j, nb_up(k, g.n2, g.per2))] != Lzu;
+    }
+    if (odd) any = 1;  // benign race: every writer stores 1
+    __syncthreads();
+    if (threadIdx.x == 0) cls[blockIdx.x] = any ? 1 : 0;
+}
+
+// Ordered list of the class-1 workgroups of a fused-pair tiling: list[k] the
+// k-th of them, list[nb] their count.  One workgroup of 1024 threads, each
+// scanning a contiguous run of the classes.
+__global__ __launch_bounds__(1024) void k_pair_list(const unsigned char* __restrict__ cls,
+                                                    unsigned nb, unsigned* __restrict__ list) {
+    __shared__ unsigned part[1024];
+    const unsigned t = threadIdx.x, per = (nb + 1023u) / 1024u;
+    const unsigned a = min(nb, t * per), e = min(nb, a + per);
+    unsigned c = 0;
+    for (unsigned q = a; q < e; ++q) c += cls[q] != 0 ? 1u : 0u;
+    part[t] = c;
+    __syncthreads();
+    for (unsigned off = 1; off < 1024u; off <<= 1) {  // inclusive scan
+        const unsigned v = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    unsigned pos = part[t] - c;
+    for (unsigned q = a; q < e; ++q)
+        if (cls[q] != 0) list[pos++] = q;
+    if (t == 1023u) list[nb] = part[1023];
 }
 
 // Coarse coefficient = 1/2 * sum of the fine faces the coarse face covers.
@@ -898,11 +1284,31 @@ __global__ __launch_bounds__(kBlock) void k_resid64(TileDev TL, Grid g, XAccess<
     const Span sp = tile_span(TL, g.n0, g.n1, g.n2);
     const int i = sp.i, j = sp.j;
     double r2 = 0.0, b2 = 0.0;
+    // a block of class 0 takes its coefficients from the position (the same
+    // values, so the same residual)
+    const bool walled = C.cls && C.cls[block_linear()] == 0;
     if (i < g.n0 && j < g.n1) {
         for (int k = sp.z0; k < sp.z1; ++k) {
         const size_t id = cid(g, i, j, k);
         double xI, Ax, D;
-        apply_row<double, XM_PLAIN, false>(g, X, C, i, j, k, xI, Ax, D);
+        if (walled) {
+            double Lxl, Lxu, Lyl, Lyu, Lzl, Lzu;
+            walled_faces<double>(g, i, j, k, C.Lc, Lxl, Lxu, Lyl, Lyu, Lzl, Lzu);
+            xI = X(g, i, j, k);
+            const double xxl = X(g, nb_lo(i, g.n0, g.per0), j, k);
+            const double xxu = X(g, nb_up(i, g.n0, g.per0), j, k);
+            const double xyl = X(g, i, nb_lo(j, g.n1, g.per1), k);
+            const double xyu = X(g, i, nb_up(j, g.n1, g.per1), k);
+            double xzl = 0.0, xzu = 0.0;
+            if (g.ndim == 3) {
+                xzl = X(g, i, j, nb_lo(k, g.n2, g.per2));
+                xzu = X(g, i, j, nb_up(k, g.n2, g.per2));
+            }
+            jacobi_terms(xI, xxl, xxu, xyl, xyu, xzl, xzu, Lxl, Lxu, Lyl, Lyu, Lzl, Lzu,
+                         g.ndim == 3, Ax, D);
+        } else {
+            apply_row<double, XM_PLAIN, false>(g, X, C, i, j, k, xI, Ax, D);
+        }
         const double bv = (D > 0.0) ? b[id] - *bmean : 0.0;
         const double r = bv - Ax;
         r32[id] = float(r);
@@ -1042,9 +1448,10 @@ static wl_status smooth(const Level<T>& L, const T* xin, const T* b, T omega, T*
     return WL_OK;
 }
 
-// Fused pairs run on uniform, fully periodic 3D levels whose x extent is a
-// multiple of 8 and y extent a multiple of 8 (mode 1: only levels of at
-// least pair_min_cells() cells).
+// Fused pairs run on 3D levels whose x and y extents are multiples of 8:
+// uniform, fully periodic levels (one coefficient, w / D per level) and
+// non-uniform levels with any boundaries (per-workgroup classes; see
+// k_pair_class).  Mode 1: only levels of at least pair_min_cells() cells.
 static int pair_tx(int n0) {
     for (int w = 64; w >= 8; w >>= 1)
         if (n0 % w == 0) return w;
@@ -1053,12 +1460,26 @@ static int pair_tx(int n0) {
 
 template <typename T>
 static bool pair_ok(const Hierarchy<T>& h, const Level<T>& L) {
-    if (!h.pairs || !L.uniform || L.g.ndim != 3) return false;
+    if (!h.pairs || L.g.ndim != 3) return false;
     if (pair_tx(L.g.n0) == 0 || L.g.n1 % kPairTY != 0) return false;
+    if (L.uniform) {
+        // the uniform kernel wraps every direction
+        if (!(L.g.per0 && L.g.per1 && L.g.per2)) return false;
+    } else {
+        if (!L.cls_fp || !gen_pairs()) return false;
+        // mode 1: non-uniform levels fuse from gen_pair_min_cells() on
+        if (h.pairs != 2 && cells(L.g) < gen_pair_min_cells()) return false;
+    }
     // FP32 pairs address their arrays through buffer descriptors, whose
     // 32-bit byte offsets cover arrays below 4 GiB (2^30 cells)
     if (sizeof(T) == 4 && cells(L.g) >= (size_t(1) << 30)) return false;
     return h.pairs == 2 || cells(L.g) >= pair_min_cells();
+}
+
+static PairTile pair_tile(const Grid& g);
+static unsigned pair_class_slots(const Grid& g) {
+    if (g.ndim != 3 || pair_tx(g.n0) == 0 || g.n1 % kPairTY != 0) return 0;
+    return pair_tile(g).nb;
 }
 
 static PairTile pair_tile(const Grid& g) {
@@ -1075,6 +1496,9 @@ static PairTile pair_tile(const Grid& g) {
     p.zc = int(zc);
     p.nb = unsigned(cols) * chunks;
     p.remap = (p.nb % 8u == 0u) ? 1 : 0;
+    // the body chunks of a non-uniform level are walked in parts of about
+    // four planes
+    p.split = std::max(1, p.zc / 4);
     return p;
 }
 
@@ -1089,9 +1513,24 @@ static wl_status pair(const Level<T>& L, const T* xin, const T* b, T omega, T* x
     const PairTile P = pair_tile(L.g);
     ProfScope ps(prof, s, cells(L.g));
     XAccess<T, XM> X{xin};
-    const T wd = uniform_wd(L, omega);
-#define WL_PAIR(TX)                                                                              \
-    k_smooth_pair<T, XM, TX><<<P.nb, PairShape<TX>::T, 0, s>>>(P, L.g, X, L.Lc, b, wd, xout, bshift)
+    // uniform levels pass w / D, the others w and their classes
+    const bool gen = !L.uniform;
+    const T wd = gen ? omega : uniform_wd(L, omega);
+    const Coeffs<T> C = coeffs_of(L, L.cls_fp);
+#define WL_PAIR(TX)                                                                             \
+    do {                                                                                        \
+        if (gen) {                                                                              \
+            k_smooth_pair<T, XM, TX, 1><<<P.nb, PairShape<TX>::T, 0, s>>>(                      \
+                P, L.g, X, C, b, wd, xout, bshift, nullptr);                                    \
+            if (L.fp_grid)                                                                      \
+                k_smooth_pair<T, XM, TX, 2>                                                     \
+                    <<<L.fp_grid * unsigned(P.split), PairShape<TX>::T, 0, s>>>(                \
+                        P, L.g, X, C, b, wd, xout, bshift, L.fp_list);                          \
+        } else {                                                                                \
+            k_smooth_pair<T, XM, TX, 0><<<P.nb, PairShape<TX>::T, 0, s>>>(                      \
+                P, L.g, X, C, b, wd, xout, bshift, nullptr);                                    \
+        }                                                                                       \
+    } while (0)
     switch (pair_tx(L.g.n0)) {
         case 64: WL_PAIR(64); break;
         case 32: WL_PAIR(32); break;
@@ -1152,7 +1591,12 @@ template <typename T>
 static wl_status coarse_solve(const Hierarchy<T>& h, const Level<T>& L, T* xout, hipStream_t s) {
     const int N = int(cells(L.g));
     const int maxit = N + 64;
-    k_coarse_cg<T><<<1, 256, 0, s>>>(L.g, coeffs_of(L), L.uniform, L.b, xout, h.coarse_tol, maxit);
+    if (N > kCoarseMax) {
+        set_error("internal: coarsest level larger than the one-workgroup solver");
+        return WL_ERR_INVALID_ARG;
+    }
+    const unsigned nt = unsigned(std::max(64, (N + 63) / 64 * 64));
+    k_coarse_cg<T><<<1, nt, 0, s>>>(L.g, coeffs_of(L), L.uniform, L.b, xout, h.coarse_tol, maxit);
     WL_CHECK_LAUNCH();
     return WL_OK;
 }
@@ -1188,6 +1632,35 @@ wl_status mg_coarsen_all(Hierarchy<T>& h, hipStream_t s) {
         const Launch b = launch_pairs(L.g);
         k_level_class<T><<<b.grid, b.block, 0, s>>>(b.td, L.g, C, L.cls_pairs);
         WL_CHECK_LAUNCH();
+        if (L.cls_fp) {
+            const PairTile P = pair_tile(L.g);
+            k_pair_class<T><<<P.nb, 256, 0, s>>>(P, L.g, pair_tx(L.g.n0), C, L.cls_fp);
+            WL_CHECK_LAUNCH();
+            k_pair_list<<<1, 1024, 0, s>>>(L.cls_fp, P.nb, L.fp_list);
+            WL_CHECK_LAUNCH();
+        }
+    }
+    // the class-1 launch's grid covers the largest count met so far; when it
+    // grows, captured bodies (whose grids are baked in) are dropped
+    unsigned cnt[kMaxLevels] = {};
+    bool any = false;
+    for (int l = 0; l < h.nlev; ++l) {
+        const Level<T>& L = h.lev[l];
+        if (L.uniform || !L.cls || !L.cls_fp) continue;
+        WL_CHECK_HIP(hipMemcpyAsync(&cnt[l], L.fp_list + pair_tile(L.g).nb, sizeof(unsigned),
+                                    hipMemcpyDeviceToHost, s));
+        any = true;
+    }
+    if (any) {
+        WL_CHECK_HIP(hipStreamSynchronize(s));
+        bool grew = false;
+        for (int l = 0; l < h.nlev; ++l) {
+            if (cnt[l] > h.lev[l].fp_grid) {
+                h.lev[l].fp_grid = cnt[l];
+                grew = true;
+            }
+        }
+        if (grew) h.graphs.clear();
     }
     return WL_OK;
 }
@@ -1350,7 +1823,7 @@ __global__ __launch_bounds__(1024) void k_check_reduce(const double* __restrict_
 
 template <typename T>
 bool mg_producer_check(const Hierarchy<T>& h) {
-    return h.nlev > 1 && pair_ok(h, h.lev[0]);
+    return h.nlev > 1 && h.lev[0].uniform && pair_ok(h, h.lev[0]);
 }
 template bool mg_producer_check<float>(const Hierarchy<float>&);
 template bool mg_producer_check<double>(const Hierarchy<double>&);
@@ -1478,6 +1951,15 @@ template wl_status mg_solve<double>(Hierarchy<double>&, Reduce&, double*, const 
                                     double, int, hipStream_t, SolveResult*, BPartials,
                                     const SolveTail*);
 
+wl_status mg_mixed_classes(const Grid& g, const Mixed64& m, hipStream_t s) {
+    if (!m.cls) return WL_OK;
+    const Launch ln = launch_for(g.n0, g.n1, g.n2);
+    const Coeffs<double> C{m.L[0], m.L[1], m.L[2], 1.0};
+    k_level_class<double><<<ln.grid, ln.block, 0, s>>>(ln.td, g, C, m.cls);
+    WL_CHECK_LAUNCH();
+    return WL_OK;
+}
+
 wl_status mg_solve_mixed(Hierarchy<float>& h32, const Mixed64& m, Reduce& red, double* x,
                          const double* b, double tol, double abs_r2, int max_vcycles,
                          hipStream_t s, SolveResult* res) {
@@ -1488,6 +1970,7 @@ wl_status mg_solve_mixed(Hierarchy<float>& h32, const Mixed64& m, Reduce& red, d
     Coeffs<double> C64{m.L[0], m.L[1], m.L[2], 1.0};
     // active mean of b in FP64 (result[5])
     k_sum_active<double, false><<<ln.grid, ln.block, 0, s>>>(ln.td, g, C64, b, red.partial);
+    C64.cls = m.cls;
     WL_CHECK_LAUNCH();
     k_reduce<<<1, 1024, 0, s>>>(red.partial, ln.nblocks(), 1, 1.0, red.result + 4,
                                 red.result + 6, MailboxPost{});

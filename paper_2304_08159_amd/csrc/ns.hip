@@ -606,11 +606,51 @@ __global__ __launch_bounds__(kBlock) void k_bdim(TileDev TL, VelField<T> F, Bdim
     }
 }
 
+// The same blend on the flagged cells only (B.cflag), one thread per cell,
+// into w: the few cells near the body each take one thread, so no thread
+// walks a chain of them.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bdim_cells(VelField<T> F, BdimFields<T> B,
+                                                       T* __restrict__ w0, T* __restrict__ w1,
+                                                       T* __restrict__ w2, BodyMotionDev mo) {
+    const Grid& g = F.g;
+    const size_t id = size_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (id >= cells(g) || !B.cflag[id]) return;
+    const size_t plane = size_t(g.n0) * size_t(g.n1);
+    const int k = int(id / plane);
+    const size_t r = id - size_t(k) * plane;
+    const int j = int(r / size_t(g.n0)), i = int(r - size_t(j) * size_t(g.n0));
+    // every component's loads before any store
+    T v[3] = {T(0), T(0), T(0)};
+    for (int c = 0; c < g.ndim; ++c) v[c] = bdim_face<T, true>(F, B, mo, c, i, j, k);
+    w0[id] = v[0];
+    w1[id] = v[1];
+    if (g.ndim == 3) w2[id] = v[2];
+}
+
+// The flagged cells' u* (k_bdim_cells, in w) copied into f, after every
+// thread has read f.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bdim_commit(Grid g,
+                                                        const unsigned char* __restrict__ cflag,
+                                                        const T* __restrict__ w0,
+                                                        const T* __restrict__ w1,
+                                                        const T* __restrict__ w2,
+                                                        T* __restrict__ f0, T* __restrict__ f1,
+                                                        T* __restrict__ f2) {
+    const size_t id = size_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (id >= cells(g) || !cflag[id]) return;
+    f0[id] = w0[id];
+    f1[id] = w1[id];
+    if (g.ndim == 3) f2[id] = w2[id];
+}
+
 // Tile class of each block: 1 if any face of its tile has mu0 != 1 or a
 // nonzero mu1 n component.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_tile_class(TileDev TL, Grid g, BdimFields<T> B,
-                                                       unsigned char* __restrict__ cls) {
+                                                       unsigned char* __restrict__ cls,
+                                                       unsigned char* __restrict__ cflag) {
     __shared__ int any;
     if (threadIdx.x == 0) any = 0;
     __syncthreads();
@@ -618,12 +658,15 @@ __global__ __launch_bounds__(kBlock) void k_tile_class(TileDev TL, Grid g, BdimF
     const int i = sp.i, j = sp.j;
     bool near = false;
     if (i < g.n0 && j < g.n1)
-        for (int k = sp.z0; k < sp.z1 && !near; ++k) {
+        for (int k = sp.z0; k < sp.z1 && (cflag || !near); ++k) {
             const size_t id = cid(g, i, j, k);
+            bool cell = false;
             for (int c = 0; c < g.ndim; ++c) {
-                near = near || B.mu0[c][id] != T(1);
-                for (int d = 0; d < g.ndim; ++d) near = near || B.mu1n[3 * c + d][id] != T(0);
+                cell = cell || B.mu0[c][id] != T(1);
+                for (int d = 0; d < g.ndim; ++d) cell = cell || B.mu1n[3 * c + d][id] != T(0);
             }
+            if (cflag) cflag[id] = cell ? 1 : 0;
+            near = near || cell;
         }
     if (near) any = 1;  // benign race: every writer stores 1
     __syncthreads();
@@ -1274,9 +1317,25 @@ wl_status ns_bdim(const VelField<T>& F, const BdimFields<T>& B, T* const out[3],
 }
 
 template <typename T>
-wl_status ns_tile_class(const Grid& g, const BdimFields<T>& B, unsigned char* cls, hipStream_t s) {
+wl_status ns_bdim_in_place(const VelField<T>& F, T* const f[3], const BdimFields<T>& B,
+                           T* const w[3], hipStream_t s, const BodyMotionDev& motion) {
+    if (!B.cflag) {
+        set_error("internal: in-place BDIM needs the per-cell flags");
+        return WL_ERR_INVALID_ARG;
+    }
+    const unsigned nb = unsigned((cells(F.g) + kBlock - 1) / kBlock);
+    k_bdim_cells<T><<<nb, kBlock, 0, s>>>(F, B, w[0], w[1], w[2], motion);
+    WL_CHECK_LAUNCH();
+    k_bdim_commit<T><<<nb, kBlock, 0, s>>>(F.g, B.cflag, w[0], w[1], w[2], f[0], f[1], f[2]);
+    WL_CHECK_LAUNCH();
+    return WL_OK;
+}
+
+template <typename T>
+wl_status ns_tile_class(const Grid& g, const BdimFields<T>& B, unsigned char* cls, hipStream_t s,
+                        unsigned char* cflag) {
     const Launch ln = launch_for(g.n0, g.n1, g.n2);
-    k_tile_class<T><<<ln.grid, ln.block, 0, s>>>(ln.td, g, B, cls);
+    k_tile_class<T><<<ln.grid, ln.block, 0, s>>>(ln.td, g, B, cls, cflag);
     WL_CHECK_LAUNCH();
     return WL_OK;
 }
@@ -1376,7 +1435,7 @@ wl_status ns_set_scalar(double* p, double v, hipStream_t s) {
 
 #define WL_INST(T)                                                                               \
     template wl_status ns_tile_class<T>(const Grid&, const BdimFields<T>&, unsigned char*,        \
-                                        hipStream_t);                                             \
+                                        hipStream_t, unsigned char*);                             \
     template wl_status ns_measure<T>(const Grid&, const BodyDev&, const int*,                     \
                                      const MeasureOut<T>&, hipStream_t);                          \
     template wl_status ns_momentum<T>(const VelField<T>&, const T* const*, T* const*, T, bool,   \
@@ -1385,6 +1444,8 @@ wl_status ns_set_scalar(double* p, double v, hipStream_t s) {
                                      const double*, T*, hipStream_t);                             \
     template wl_status ns_bdim<T>(const VelField<T>&, const BdimFields<T>&, T* const*,            \
                                   hipStream_t, const BodyMotionDev&);                             \
+    template wl_status ns_bdim_in_place<T>(const VelField<T>&, T* const*, const BdimFields<T>&,   \
+                                           T* const*, hipStream_t, const BodyMotionDev&);         \
     template wl_status ns_divergence<T>(const VelField<T>&, const ProjCoeffs<T>&, bool, double,  \
                                         const double*, T*, double*, bool, hipStream_t, const T*,  \
                                         T, size_t*);                                              \

@@ -67,6 +67,13 @@ GraphCache::~GraphCache() {
     if (cap) (void)hipStreamDestroy(cap);
 }
 
+void GraphCache::clear() {
+    for (auto& en : e) {
+        if (en.exec) (void)hipGraphExecDestroy(en.exec);
+        en = Entry{};
+    }
+}
+
 ProfScope::ProfScope(int kernel, hipStream_t stream, size_t ncells) : id(kernel), s(stream) {
     Profiler& P = prof();
     on = kernel >= 0 && kernel < WL_PROF_COUNT && (P.mask.load() >> kernel & 1u);

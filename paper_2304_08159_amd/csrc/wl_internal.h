@@ -116,6 +116,13 @@ struct Level {
     // launch_pairs tilings of this level (non-uniform levels)
     unsigned char* cls = nullptr;
     unsigned char* cls_pairs = nullptr;
+    // per-workgroup classes of the fused-pair tiling (3D levels it fits), the
+    // ordered list of its class-1 workgroups followed by their count, and on
+    // the host the largest count met so far (the grid of the class-1 launch,
+    // which captured graphs keep)
+    unsigned char* cls_fp = nullptr;
+    unsigned* fp_list = nullptr;
+    unsigned fp_grid = 0;
     T* cr = nullptr;
     T* cp = nullptr;
     T* cq = nullptr;
@@ -143,6 +150,7 @@ struct GraphCache {
     GraphCache(const GraphCache&) = delete;
     GraphCache& operator=(const GraphCache&) = delete;
     ~GraphCache();
+    void clear();  // drops every captured body (call with the stream idle)
 };
 
 // Process-wide switch for graph replay (wl_set_graphs) and whether a kernel
@@ -322,8 +330,12 @@ wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, d
 // FP32 inner V-cycles on h32.
 struct Mixed64 {
     double* L[3] = {nullptr, nullptr, nullptr};
+    // per-block classes of L for the fine level's launch_for tiling (see
+    // Coeffs::cls); mg_mixed_classes fills them when L changes
+    unsigned char* cls = nullptr;
     int inner = 3;
 };
+wl_status mg_mixed_classes(const Grid& g, const Mixed64& m, hipStream_t s);
 wl_status mg_solve_mixed(Hierarchy<float>& h32, const Mixed64& m, Reduce& red, double* x,
                          const double* b, double tol, double abs_r2, int max_vcycles,
                          hipStream_t s, SolveResult* res);

@@ -46,10 +46,12 @@ __device__ __forceinline__ T jacobi_rhs(T bv, bool act, bool shift, T mean) {
     return bv;
 }
 
-// x - w r / D on active cells (D > 0), 0 elsewhere.
+// x - (w / D) r on active cells (D > 0), 0 elsewhere.  The factor is one
+// correctly rounded division of w by D, so a kernel that knows D from the
+// cell's position may take it from a table formed by the same division.
 template <typename T>
 __device__ __forceinline__ T jacobi_new(T xI, T r, T D, T omega) {
-    return D > T(0) ? xI - omega * r / D : T(0);
+    return D > T(0) ? xI - (omega / D) * r : T(0);
 }
 
 // The same with the factor w / D given: levels with one coefficient

@@ -25,6 +25,9 @@ struct BdimFields {
     // face of the tile has mu0 = 1 and mu1 n = 0, so BDIM is the identity
     // there; null treats every tile as touching the body.
     const unsigned char* cls = nullptr;
+    // Per cell: 1 where the blend differs from f on any face of the cell
+    // (mu0 != 1 or a nonzero mu1 n component); null: every cell.
+    const unsigned char* cflag = nullptr;
 };
 
 template <typename T>
@@ -86,9 +89,18 @@ wl_status ns_outflow(const Grid& g, const T* ue_x, const T* out_e, const T* out_
 template <typename T>
 wl_status ns_bdim(const VelField<T>& F, const BdimFields<T>& B, T* const out[3], hipStream_t s,
                   const BodyMotionDev& motion = BodyMotionDev{});
-// Tile classes (see BdimFields::cls) from the measured mu0 / mu1 n.
+// The same blend left in f itself (f = the arrays of F): only the cells whose
+// blend differs from f (B.cflag) are touched, through the scratch arrays w;
+// f serves as u* unchanged elsewhere.  Needs B.cflag.
 template <typename T>
-wl_status ns_tile_class(const Grid& g, const BdimFields<T>& B, unsigned char* cls, hipStream_t s);
+wl_status ns_bdim_in_place(const VelField<T>& F, T* const f[3], const BdimFields<T>& B,
+                           T* const w[3], hipStream_t s,
+                           const BodyMotionDev& motion = BodyMotionDev{});
+// Tile classes (see BdimFields::cls) from the measured mu0 / mu1 n.
+// With cflag, also the per-cell flags (see BdimFields::cflag).
+template <typename T>
+wl_status ns_tile_class(const Grid& g, const BdimFields<T>& B, unsigned char* cls, hipStream_t s,
+                        unsigned char* cflag = nullptr);
 // p_check (periodic, uniform, 3D): also the first residual check of the
 // pressure solve that starts from p, with Poisson coefficient Lp (partials of
 // [sigma, sigma^2, c, c^2], c = sigma - A p; see k_divergence).

@@ -97,8 +97,9 @@ __device__ __forceinline__ double face_coeff(const Grid& g, const int bclo[3], i
 //   u*_c = mu0_c f_c + (1 - mu0_c) V_b,c
 //          + sum_d (mu1 n)_cd [(f_c(I+delta_d) - f_c(I-delta_d)) / 2 - dV_b,c/dx_d],
 // V_b the body velocity at the face (zero for a body at rest); boundary faces
-// keep f.
-template <typename T>
+// keep f.  EAGER loads the neighbours of every direction before testing
+// (mu1 n)_cd, so that the loads do not wait on it (same result).
+template <typename T, bool EAGER = false>
 __device__ __forceinline__ T bdim_face(const VelField<T>& F, const BdimFields<T>& B,
                                        const BodyMotionDev& mo, int c, int i, int j, int k) {
     const Grid& g = F.g;
@@ -123,6 +124,17 @@ __device__ __forceinline__ T bdim_face(const VelField<T>& F, const BdimFields<T>
                                 {mo.w[2], 0.0, -mo.w[0]},
                                 {-mo.w[1], mo.w[0], 0.0}};
         for (int d = 0; d < 3; ++d) gw[d] = G[c][d];
+    }
+    if constexpr (EAGER) {
+        T m[3], fp[3], fm[3];
+        for (int d = 0; d < g.ndim; ++d) {
+            m[d] = B.mu1n[3 * c + d][id];
+            fp[d] = vget<T, false>(F, c, i + (d == 0), j + (d == 1), k + (d == 2));
+            fm[d] = vget<T, false>(F, c, i - (d == 0), j - (d == 1), k - (d == 2));
+        }
+        for (int d = 0; d < g.ndim; ++d)
+            if (m[d] != T(0)) v += m[d] * (T(0.5) * (fp[d] - fm[d]) - T(gw[d]));
+        return v;
     }
     for (int d = 0; d < g.ndim; ++d) {
         const T m = B.mu1n[3 * c + d][id];

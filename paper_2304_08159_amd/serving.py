@@ -256,8 +256,15 @@ class GpuExecutor(Executor):
     pressure solves to the request's relative residual, 1e-8 by default).  Results are (fingerprint, stats) pairs; the fingerprint
     is an exact integer hash of the output bits."""
 
-    def __init__(self, device="cuda", keep_fields=False, batch_cells=65536,
-                 ns_batch_cells=16384):
+    # Batching limits from measured latencies of one request (MI355X): a
+    # Poisson solve takes 1.8-2.1 ms on the whole GPU at every size of the
+    # mix and 1.4 / 2.6 / 7.7 / 46 ms as one workgroup of the persistent
+    # kernel at 64^2 / 128^2 / 256^2 / 64^3; a 20-step NS run 35 / 41 / 48 ms
+    # alone and 49 / 140 / 538 ms in one workgroup at 64^2 / 128^2 / 256^2.
+    # Kinds are batched only where one workgroup stays within about 1.5x of
+    # the whole-GPU latency.
+    def __init__(self, device="cuda", keep_fields=False, batch_cells=16384,
+                 ns_batch_cells=4096):
         import torch
 
         import paper_2304_08159_amd as wl

@@ -72,7 +72,7 @@ def test_served_ns_request_last_step_replays_against_the_oracle():
     from oracle import step as S
     from tests.gpu_util import mean_free, plane_to_oracle
     from paper_2304_08159_amd.serving import GpuExecutor, Request, Server
-    ex = GpuExecutor(keep_fields=True)
+    ex = GpuExecutor(keep_fields=True, ns_batch_cells=16384)   # batch this size
     r = Request(id=0, kind="ns", n=(128, 64), radius=6.0, steps=6, tol=1e-8)
     out = Server(ex, 8 << 30, slots=1).run([r])[0]
     assert out.status == "done", out.error
