@@ -349,23 +349,42 @@ struct PairTile {
 // is the damping w.  The arithmetic per cell is that of k_smooth's
 // non-uniform path, so the result is again bitwise that of two separate
 // sweeps.
-template <typename T, int XM, int TX, int MODE>
+// NM (MODE 1 / 2): the pair also measures the residual of its input, as a
+// measuring check would: per-workgroup FP64 partial sums of r^2 (r = b - A x
+// on the tile's cells of its own planes, from the first sweep) and, NM = 2,
+// of the projected b^2, in slot blockIdx.x (MODE 1) or P.nb + blockIdx.x
+// (MODE 2); workgroups with nothing to do store zeros.
+template <typename T, int XM, int TX, int MODE, int NM = 0>
 __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Grid g, XAccess<T, XM> X,
                                                               Coeffs<T> Cf, const T* __restrict__ b,
                                                               T wD, T* __restrict__ xout,
                                                               const double* __restrict__ bshift,
-                                                              const unsigned* __restrict__ fpl) {
+                                                              const unsigned* __restrict__ fpl,
+                                                              double* __restrict__ partial) {
     using Sh = PairShape<TX>;
     const T Lc = Cf.Lc;
     constexpr bool GEN = MODE != 0;
     // MODE 2: part `part` of the chunk of listed workgroup blockIdx.x / split
     unsigned wg = blockIdx.x;
     int part = 0;
+    const unsigned pslot = MODE == 2 ? P.nb + blockIdx.x : blockIdx.x;
+    auto no_partials = [&]() {
+        if (NM != 0 && threadIdx.x == 0) {
+            partial[2 * pslot] = 0.0;
+            partial[2 * pslot + 1] = 0.0;
+        }
+    };
     if constexpr (MODE == 1) {
-        if (Cf.cls[wg] != 0) return;  // the MODE 2 launch takes it
+        if (Cf.cls[wg] != 0) {  // the MODE 2 launch takes it
+            no_partials();
+            return;
+        }
     } else if constexpr (MODE == 2) {
         const unsigned q = blockIdx.x / unsigned(P.split);
-        if (q >= fpl[P.nb]) return;  // the grid covers the largest count met
+        if (q >= fpl[P.nb]) {  // the grid covers the largest count met
+            no_partials();
+            return;
+        }
         wg = fpl[q];
         part = int(blockIdx.x % unsigned(P.split));
     }
@@ -384,8 +403,12 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
         const int zs = (P.zc + P.split - 1) / P.split;
         z0 += part * zs;
         z1 = min(z0 + zs, z1);
-        if (z0 >= z1) return;
+        if (z0 >= z1) {
+            no_partials();
+            return;
+        }
     }
+    double nr2 = 0.0, nb2 = 0.0;  // NM: this thread's residual / rhs sums
     const int i0 = tix * kPairTX, j0 = tiy * kPairTY;
     const int t = int(threadIdx.x);
     const unsigned n0 = unsigned(g.n0), plane = n0 * unsigned(g.n1);
@@ -551,7 +574,7 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
         }
     };
     auto sweep1g = [&](auto mt, const T* S0, const Slot& S, int k, T xI, T xzl, T xzu,
-                       T& bv, const T (&F)[6]) -> T {
+                       T& bv, const T (&F)[6], T& rr) -> T {
         T xxl = T(0), xxu = T(0), xyl = T(0), xyu = T(0);
         if (XM != XM_ZERO) {
             xxl = S0[S.q - 1];
@@ -563,7 +586,8 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
         coef(mt, S, k, F, Lxl, Lxu, Lyl, Lyu, Lzl, Lzu);
         jacobi_terms(xI, xxl, xxu, xyl, xyu, xzl, xzu, Lxl, Lxu, Lyl, Lyu, Lzl, Lzu, true, Ax, D);
         bv = jacobi_rhs(bv, decltype(mt)::value == 1 || D > T(0), shift, mean);
-        return update(mt, S, k, xI, bv - Ax, D);
+        rr = bv - Ax;
+        return update(mt, S, k, xI, rr, D);
     };
     // Second sweep of column S at plane k (first-sweep position h of S1; bv
     // already shifted).
@@ -660,12 +684,21 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
         }
         if constexpr (decltype(mt)::value != 0) {
             const int kc = zmap(s);
-            const T y = sweep1g(mt, S0, A, kc, xA[i0], xA[im1], xA[ip1], rA[i0], fA[r & 1]);
+            T rrA, rrB;
+            const T y =
+                sweep1g(mt, S0, A, kc, xA[i0], xA[im1], xA[ip1], rA[i0], fA[r & 1], rrA);
             yA[i0] = y;
             S1[hA] = y;
+            if constexpr (NM != 0) {
+                // the tile's cells of this workgroup's own planes
+                if (s >= z0 && s < z1) {
+                    nr2 += double(rrA) * double(rrA);
+                    if (NM == 2) nb2 += double(rA[i0]) * double(rA[i0]);
+                }
+            }
             if (hasB) {
                 T bvB = rB[i0];
-                S1[hB] = sweep1g(mt, S0, B, kc, xB[i0], xB[im1], xB[ip1], bvB, fB);
+                S1[hB] = sweep1g(mt, S0, B, kc, xB[i0], xB[im1], xB[ip1], bvB, fB, rrB);
             }
             if (store)
                 xout[A.col + unsigned(s - 1) * plane] = sweep2g(
@@ -730,6 +763,29 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
     }
     };
     run(std::integral_constant<int, MODE>{});
+    if constexpr (NM != 0) {
+        // fixed-order workgroup sums
+        __shared__ double red[2][Sh::T / 64];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            nr2 += __shfl_xor(nr2, off, 64);
+            nb2 += __shfl_xor(nb2, off, 64);
+        }
+        if ((t & 63) == 0) {
+            red[0][t >> 6] = nr2;
+            red[1][t >> 6] = nb2;
+        }
+        __syncthreads();
+        if (t == 0) {
+            double a = 0.0, c = 0.0;
+            for (int w = 0; w < Sh::T / 64; ++w) {
+                a += red[0][w];
+                c += red[1][w];
+            }
+            partial[2 * pslot] = a;
+            partial[2 * pslot + 1] = c;
+        }
+    }
 }
 
 // x += P xc: the coarse correction interpolated linearly onto the fine
@@ -1521,14 +1577,14 @@ static wl_status pair(const Level<T>& L, const T* xin, const T* b, T omega, T* x
     do {                                                                                        \
         if (gen) {                                                                              \
             k_smooth_pair<T, XM, TX, 1><<<P.nb, PairShape<TX>::T, 0, s>>>(                      \
-                P, L.g, X, C, b, wd, xout, bshift, nullptr);                                    \
+                P, L.g, X, C, b, wd, xout, bshift, nullptr, nullptr);                           \
             if (L.fp_grid)                                                                      \
                 k_smooth_pair<T, XM, TX, 2>                                                     \
                     <<<L.fp_grid * unsigned(P.split), PairShape<TX>::T, 0, s>>>(                \
-                        P, L.g, X, C, b, wd, xout, bshift, L.fp_list);                          \
+                        P, L.g, X, C, b, wd, xout, bshift, L.fp_list, nullptr);                 \
         } else {                                                                                \
             k_smooth_pair<T, XM, TX, 0><<<P.nb, PairShape<TX>::T, 0, s>>>(                      \
-                P, L.g, X, C, b, wd, xout, bshift, nullptr);                                    \
+                P, L.g, X, C, b, wd, xout, bshift, nullptr, nullptr);                           \
         }                                                                                       \
     } while (0)
     switch (pair_tx(L.g.n0)) {
@@ -1541,6 +1597,51 @@ static wl_status pair(const Level<T>& L, const T* xin, const T* b, T omega, T* x
             return WL_ERR_INVALID_ARG;
     }
 #undef WL_PAIR
+    WL_CHECK_LAUNCH();
+    return WL_OK;
+}
+
+// Partial-sum slots a measuring pair on a non-uniform level writes (see
+// k_smooth_pair's NM).
+template <typename T>
+static size_t pair_norm_slots(const Level<T>& L) {
+    const PairTile P = pair_tile(L.g);
+    return size_t(P.nb) + size_t(L.fp_grid) * size_t(P.split);
+}
+
+// xout = S(S(xin)) on a non-uniform level, with the residual norm of xin
+// (and, FIRST, of the projected b) in partial[0 .. 2 * pair_norm_slots).
+template <typename T, bool FIRST>
+static wl_status pair_norm(const Level<T>& L, const T* xin, const T* b, T omega, T* xout,
+                           const double* bshift, double* partial, hipStream_t s, int prof = -1) {
+    if (xout == xin || xout == b || L.uniform) {
+        set_error("internal: measuring pair on a uniform level or with aliased buffers");
+        return WL_ERR_INVALID_ARG;
+    }
+    const PairTile P = pair_tile(L.g);
+    ProfScope ps(prof, s, cells(L.g));
+    XAccess<T, XM_PLAIN> X{xin};
+    const Coeffs<T> C = coeffs_of(L, L.cls_fp);
+    constexpr int NM = FIRST ? 2 : 1;
+#define WL_PAIRN(TX)                                                                            \
+    do {                                                                                        \
+        k_smooth_pair<T, XM_PLAIN, TX, 1, NM><<<P.nb, PairShape<TX>::T, 0, s>>>(                \
+            P, L.g, X, C, b, omega, xout, bshift, nullptr, partial);                            \
+        if (L.fp_grid)                                                                          \
+            k_smooth_pair<T, XM_PLAIN, TX, 2, NM>                                               \
+                <<<L.fp_grid * unsigned(P.split), PairShape<TX>::T, 0, s>>>(                    \
+                    P, L.g, X, C, b, omega, xout, bshift, L.fp_list, partial);                  \
+    } while (0)
+    switch (pair_tx(L.g.n0)) {
+        case 64: WL_PAIRN(64); break;
+        case 32: WL_PAIRN(32); break;
+        case 16: WL_PAIRN(16); break;
+        case 8: WL_PAIRN(8); break;
+        default:
+            set_error("internal: no fused-pair tile for this level");
+            return WL_ERR_INVALID_ARG;
+    }
+#undef WL_PAIRN
     WL_CHECK_LAUNCH();
     return WL_OK;
 }
@@ -1693,7 +1794,7 @@ template wl_status mg_count_active<double>(Hierarchy<double>&, Reduce&, hipStrea
 // How a V-cycle finds the fine level's pre-smoothing: the first sweep
 // already done into x[1] (Half), both sweeps still to do from the fine
 // iterate (Full) or from zero (Zero).
-enum class Pre { Half, Full, Zero };
+enum class Pre { Half, Full, Zero, PairDone };
 
 // Pre-smoothing of one level: two sweeps from `home` (or zero), with `other`
 // as the second buffer.  Separate sweeps end in home, a fused pair in other;
@@ -1704,6 +1805,11 @@ static wl_status pre_smooth(const Hierarchy<T>& h, const Level<T>& L, Pre mode, 
                             const T* b, const double* bs, hipStream_t s, const T** out,
                             bool fine) {
     const T w = T(h.omega);
+    if (mode == Pre::PairDone) {
+        // a measuring pair already smoothed home into other
+        *out = other;
+        return WL_OK;
+    }
     if (h.smoother == 1) {
         // conjugate gradients: two iterations from the iterate (or zero), in place
         if (mode == Pre::Half) {
@@ -1863,6 +1969,12 @@ wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, d
     // smooths from the iterate
     const bool measure = fused || h.smoother == 1;
     T* const xnext = measure ? nullptr : F.x[1];
+    // On a fused non-uniform fine level each check is the next V-cycle's
+    // pre-smoothing pair, which measures its input as it goes (into F.x[1];
+    // the last one, after convergence, is not used): no separate pass reads
+    // x and b for the norm.
+    const bool pairnorm = fused && !F.uniform && pair_norm_slots(F) <= red.slots;
+    const size_t nslots = pairnorm ? pair_norm_slots(F) : ln.nblocks();
     if (bp == BPartials::Check && !mg_producer_check(h)) {
         set_error("internal: first residual check given for a hierarchy that cannot take it");
         return WL_ERR_INVALID_ARG;
@@ -1881,9 +1993,12 @@ wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, d
         // first check: ||r0|| and ||b - mean||.  Every fine-level sweep
         // removes the mean of b on the fly; only a one-level hierarchy (whose
         // coarse solve reads F.b) stores the projected copy.
-        WL_TRY((smooth<T, XM_PLAIN, true, true>(F, x, b, w, xnext, red.partial,
-                                                bshift, s, -1, h.nlev == 1 ? F.b : nullptr)));
-        WL_TRY(reduce<T>(red, ln.nblocks(), 2, 1.0, red.result, s, post));
+        if (pairnorm)
+            WL_TRY((pair_norm<T, true>(F, x, b, w, F.x[1], bshift, red.partial, s)));
+        else
+            WL_TRY((smooth<T, XM_PLAIN, true, true>(F, x, b, w, xnext, red.partial,
+                                                    bshift, s, -1, h.nlev == 1 ? F.b : nullptr)));
+        WL_TRY(reduce<T>(red, nslots, 2, 1.0, red.result, s, post));
     }
     host_posted(red);
     const unsigned q_check = red.mb.seq;
@@ -1913,6 +2028,12 @@ wl_status mg_solve(Hierarchy<T>& h, Reduce& red, T* x, const T* b, double tol, d
     int k = 0;
     // one V-cycle and the residual norms it leaves (replayed as a graph)
     auto body = [&](hipStream_t q) -> wl_status {
+        if (pairnorm) {
+            WL_TRY(vcycle_rest(h, Pre::PairDone, b, bshift, q));
+            WL_TRY((pair_norm<T, false>(F, x, b, w, F.x[1], bshift, red.partial, q,
+                                        WL_PROF_PAIR_FINE)));
+            return reduce<T>(red, nslots, 2, 1.0, red.result, q, post);
+        }
         WL_TRY(vcycle_rest(h, measure ? Pre::Full : Pre::Half, b, bshift, q));
         WL_TRY((smooth<T, XM_PLAIN, true, false>(F, x, b, w, xnext, red.partial,
                                                  bshift, q,

@@ -108,7 +108,9 @@ def test_fused_pairs_on_body_levels_are_bitwise_identical(precname, n, per, body
     kb, rb, xb = _solve_body(wl, 0, precname, n, per, body)
     print(precname, n, per, "vcycles", ka, kb, "rel", ra, rb, flush=True)
     assert ka >= 3 and ka == kb
-    assert ra == rb
+    # with fused fine pairs the residual norms are summed per pair workgroup
+    # (the pair measures its input), in another order than the separate checks
+    assert abs(ra - rb) <= 1e-12 * rb
     assert torch.equal(xa, xb)
 
 
@@ -134,4 +136,6 @@ def test_fused_pairs_in_body_steps_are_bitwise_identical():
     assert sum(s["vcycles"][0] + s["vcycles"][1] for s in sa) >= 4
     for x, y in zip(sa, sb):
         assert x["vcycles"] == y["vcycles"] and x["dt"] == y["dt"]
+        for q in range(2):
+            assert abs(x["resid"][q] - y["resid"][q]) <= 1e-6 * y["resid"][q] + 1e-300
     assert torch.equal(ua, ub) and torch.equal(pa, pb)
