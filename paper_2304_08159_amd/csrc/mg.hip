@@ -968,19 +968,25 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(TileDev TL, Grid g, G
 }
 
 // Per-block partial sums of v over active cells (v == nullptr counts them).
+// Every cell of a class-0 block (C.cls) is active: no coefficient is read.
 template <typename T, bool UNIF>
 __global__ __launch_bounds__(kBlock) void k_sum_active(TileDev TL, Grid g, Coeffs<T> C, const T* __restrict__ v,
                                                        double* __restrict__ partial) {
     __shared__ double lds[8];
     const Span sp = tile_span(TL, g.n0, g.n1, g.n2);
     const int i = sp.i, j = sp.j;
+    const bool walled = !UNIF && C.cls && C.cls[block_linear()] == 0;
     double s = 0.0;
     if (i < g.n0 && j < g.n1) {
         for (int k = sp.z0; k < sp.z1; ++k) {
-        XAccess<T, XM_ZERO> X{nullptr};
-        T xI, Ax, D;
-        apply_row<T, XM_ZERO, UNIF>(g, X, C, i, j, k, xI, Ax, D);
-        if (D > T(0)) s += v ? double(v[cid(g, i, j, k)]) : 1.0;
+        bool act = true;
+        if (!walled) {
+            XAccess<T, XM_ZERO> X{nullptr};
+            T xI, Ax, D;
+            apply_row<T, XM_ZERO, UNIF>(g, X, C, i, j, k, xI, Ax, D);
+            act = D > T(0);
+        }
+        if (act) s += v ? double(v[cid(g, i, j, k)]) : 1.0;
         }
     }
     s = block_sum(s, lds);
@@ -1343,33 +1349,64 @@ __global__ __launch_bounds__(kBlock) void k_resid64(TileDev TL, Grid g, XAccess<
     // a block of class 0 takes its coefficients from the position (the same
     // values, so the same residual)
     const bool walled = C.cls && C.cls[block_linear()] == 0;
-    if (i < g.n0 && j < g.n1) {
-        for (int k = sp.z0; k < sp.z1; ++k) {
-        const size_t id = cid(g, i, j, k);
-        double xI, Ax, D;
-        if (walled) {
-            double Lxl, Lxu, Lyl, Lyu, Lzl, Lzu;
-            walled_faces<double>(g, i, j, k, C.Lc, Lxl, Lxu, Lyl, Lyu, Lzl, Lzu);
-            xI = X(g, i, j, k);
-            const double xxl = X(g, nb_lo(i, g.n0, g.per0), j, k);
-            const double xxu = X(g, nb_up(i, g.n0, g.per0), j, k);
-            const double xyl = X(g, i, nb_lo(j, g.n1, g.per1), k);
-            const double xyu = X(g, i, nb_up(j, g.n1, g.per1), k);
-            double xzl = 0.0, xzu = 0.0;
-            if (g.ndim == 3) {
-                xzl = X(g, i, j, nb_lo(k, g.n2, g.per2));
-                xzu = X(g, i, j, nb_up(k, g.n2, g.per2));
-            }
-            jacobi_terms(xI, xxl, xxu, xyl, xyu, xzl, xzu, Lxl, Lxu, Lyl, Lyu, Lzl, Lzu,
-                         g.ndim == 3, Ax, D);
-        } else {
-            apply_row<double, XM_PLAIN, false>(g, X, C, i, j, k, xI, Ax, D);
+    if (i < g.n0 && j < g.n1 && sp.z0 < sp.z1) {
+        // the column walk of k_smooth: x / y neighbour offsets fixed, the
+        // lower z neighbour and coefficient carried, every load of a cell
+        // issued before any is used (the operations of apply_row, in order)
+        const unsigned n0 = unsigned(g.n0), plane = n0 * unsigned(g.n1);
+        const bool d3 = g.ndim == 3;
+        const int ixm = i > 0 ? i - 1 : (g.per0 ? g.n0 - 1 : i);
+        const int ixp = i < g.n0 - 1 ? i + 1 : (g.per0 ? 0 : i);
+        const int jym = j > 0 ? j - 1 : (g.per1 ? g.n1 - 1 : j);
+        const int jyp = j < g.n1 - 1 ? j + 1 : (g.per1 ? 0 : j);
+        const bool hxu = i < g.n0 - 1 || g.per0, hyu = j < g.n1 - 1 || g.per1;
+        const int oxm = ixm - i, oxp = ixp - i;
+        const int oym = (jym - j) * int(n0), oyp = (jyp - j) * int(n0);
+        const double mean = *bmean;
+        const double* x = X.x;
+        const int k0 = sp.z0;
+        unsigned id = unsigned(i) + n0 * unsigned(j) + plane * unsigned(k0);
+        double xzl = 0.0, xI = x[id], Lzl = 0.0;
+        if (d3) {
+            const int km = k0 > 0 ? k0 - 1 : (g.per2 ? g.n2 - 1 : k0);
+            xzl = x[id + unsigned(km - k0) * plane];
+            Lzl = walled ? ((k0 == 0 && !g.per2) ? 0.0 : C.Lc) : C.L2[id];
         }
-        const double bv = (D > 0.0) ? b[id] - *bmean : 0.0;
-        const double r = bv - Ax;
-        r32[id] = float(r);
-        r2 += r * r;
-        b2 += bv * bv;
+        for (int k = k0; k < sp.z1; ++k, id += plane) {
+            double xzu = 0.0, Lzu = 0.0;
+            bool hzu = false;
+            unsigned idu = id;
+            if (d3) {
+                hzu = k < g.n2 - 1 || g.per2;
+                const int ku = k < g.n2 - 1 ? k + 1 : (g.per2 ? 0 : k);
+                idu = id + unsigned(ku - k) * plane;
+                xzu = x[idu];
+            }
+            const double xxl = x[id + oxm], xxu = x[id + oxp];
+            const double xyl = x[id + oym], xyu = x[id + oyp];
+            const double bb = b[id];
+            double Lxl, Lxu, Lyl, Lyu;
+            if (walled) {
+                double zl;
+                walled_faces<double>(g, i, j, k, C.Lc, Lxl, Lxu, Lyl, Lyu, zl, Lzu);
+            } else {
+                Lxl = C.L0[id];
+                Lxu = hxu ? C.L0[id + oxp] : 0.0;
+                Lyl = C.L1[id];
+                Lyu = hyu ? C.L1[id + oyp] : 0.0;
+                if (d3) Lzu = hzu ? C.L2[idu] : 0.0;
+            }
+            double Ax, D;
+            jacobi_terms(xI, xxl, xxu, xyl, xyu, xzl, xzu, Lxl, Lxu, Lyl, Lyu, Lzl, Lzu, d3, Ax,
+                         D);
+            const double bv = (D > 0.0) ? bb - mean : 0.0;
+            const double r = bv - Ax;
+            r32[id] = float(r);
+            r2 += r * r;
+            b2 += bv * bv;
+            xzl = xI;
+            xI = xzu;
+            Lzl = Lzu;
         }
     }
     double s, sb;
@@ -1944,7 +1981,8 @@ static wl_status active_mean(Hierarchy<T>& h, Reduce& red, const T* b, bool have
     } else if (F.uniform)
         k_sum_active<T, true><<<ln.grid, ln.block, 0, s>>>(ln.td, F.g, coeffs_of(F), b, red.partial);
     else
-        k_sum_active<T, false><<<ln.grid, ln.block, 0, s>>>(ln.td, F.g, coeffs_of(F), b, red.partial);
+        k_sum_active<T, false><<<ln.grid, ln.block, 0, s>>>(ln.td, F.g, coeffs_of(F, F.cls), b,
+                                                            red.partial);
     WL_CHECK_LAUNCH();
     // result[4] = sum, result[5] = mean over the active count result[6]
     k_reduce<<<1, 1024, 0, s>>>(red.partial, ln.nblocks(), 1, 1.0, red.result + 4,
@@ -2089,9 +2127,9 @@ wl_status mg_solve_mixed(Hierarchy<float>& h32, const Mixed64& m, Reduce& red, d
     const Launch ln = launch_for(g.n0, g.n1, g.n2);
     const size_t N = cells(g);
     Coeffs<double> C64{m.L[0], m.L[1], m.L[2], 1.0};
+    C64.cls = m.cls;
     // active mean of b in FP64 (result[5])
     k_sum_active<double, false><<<ln.grid, ln.block, 0, s>>>(ln.td, g, C64, b, red.partial);
-    C64.cls = m.cls;
     WL_CHECK_LAUNCH();
     k_reduce<<<1, 1024, 0, s>>>(red.partial, ln.nblocks(), 1, 1.0, red.result + 4,
                                 red.result + 6, MailboxPost{});
