@@ -482,8 +482,8 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
         return p < 0 ? p + g.n2 : p;
     };
     auto next = [&](int w) { return w + 1 == g.n2 ? 0 : w + 1; };
-    // GEN keeps plane numbers unwrapped and maps them at each load (wrapped
-    // on a periodic z, clamped otherwise)
+    // modes 1 and 2 keep plane numbers unwrapped and map them at each load
+    // (wrapped on a periodic z, clamped otherwise); mode 0 wraps as it walks
     auto zmap = [&](int p) { return g.per2 ? wrap(p) : min(max(p, 0), g.n2 - 1); };
     auto zfirst = [&](int p) { return GEN ? p : wrap(p); };
     auto znext = [&](int w) { return GEN ? w + 1 : next(w); };
@@ -514,8 +514,8 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
                                        xzl, xzu, Lc, true);
         return jacobi_new_scaled(xI, bv - Ax, act, wD);
     };
-    // GEN, by mode: 1 a workgroup of class 0 (coefficients from the
-    // position), 2 one that reads them.
+    // mt is the mode of the walk: 1 a workgroup of class 0 (coefficients
+    // from the position), 2 one that reads them.
     // Face coefficients of the column S at plane k (k inside the grid).
     auto faces = [&](auto mt, const Slot& S, int k, T& Lxl, T& Lxu, T& Lyl, T& Lyu, T& Lzl,
                      T& Lzu) {
