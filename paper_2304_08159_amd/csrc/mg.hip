@@ -140,6 +140,18 @@ static size_t gen_pair_min_cells() {
     return v;
 }
 
+// Largest level that the one-workgroup V-cycle tail takes (WL_TAIL_CELLS
+// overrides it; 0 turns the tail off): from 16^3 down, the per-level
+// launches cost more than one workgroup's pass over the level.
+static size_t tail_cells() {
+    static const size_t v = [] {
+        const char* e = std::getenv("WL_TAIL_CELLS");
+        const long t = e ? std::atol(e) : -1;
+        return t >= 0 ? size_t(t) : size_t(4096);
+    }();
+    return v;
+}
+
 // Process-wide smoother of the multigrid levels (wl_set_smoother), taken by
 // each hierarchy when it is laid out: 0 damped Jacobi, 1 conjugate gradients.
 static std::atomic<int> g_smoother{0};
@@ -904,17 +916,14 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(TileDev TL, Grid g, G
             Lyl = C.L1[c];
             Lyu = hyu ? C.L1[c + oyp] : T(0);
         }
-        T Ax = T(0), D = T(0);
-        Ax += Lxu * (xxu - xI) - Lxl * (xI - xxl);
-        D += Lxl + Lxu;
-        Ax += Lyu * (xyu - xI) - Lyl * (xI - xyl);
-        D += Lyl + Lyu;
-        if (d3) {
-            Ax += Lzu * (xzu - xI) - Lzl * (xI - xzl);
-            D += Lzl + Lzu;
+        if (shift) {
+            T D = T(0);
+            D += Lxl + Lxu;
+            D += Lyl + Lyu;
+            if (d3) D += Lzl + Lzu;
+            bv = D > T(0) ? T(double(bv) - mean) : T(0);
         }
-        if (shift) bv = D > T(0) ? T(double(bv) - mean) : T(0);
-        return bv - Ax;
+        return resid_row(bv, xI, xxl, xxu, xyl, xyu, xzl, xzu, Lxl, Lxu, Lyl, Lyu, Lzl, Lzu, d3);
     };
     auto zup = [&](int k, unsigned c, bool& live) -> unsigned {  // index of the upper z neighbour
         live = k < g.n2 - 1 || g.per2;
@@ -1101,27 +1110,28 @@ __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ part
     }
 }
 
-// Coarsest level: the iteration of coarse_cg_block (CG on -A over the active
+// Coarsest level: the iteration of coarse_cg_regs (CG on -A over the active
 // cells, mean-free right-hand side and result, FP64) with one cell per thread
 // (N <= blockDim <= 1024).  Each thread builds its cell's stencil once (the
 // diagonal, six face coefficients and six neighbour slots, a missing
 // neighbour being the cell itself with the coefficient the generic solver
 // uses), so an iteration is six LDS reads of the search direction, two
 // fixed-order sums (one barrier each, alternating buffers) and the barrier
-// after the direction update.
+// after the direction update.  The sums run over the first nw waves (those
+// that can own a cell: every wave of the workgroup executes each barrier, so
+// a larger workgroup, as in the V-cycle tail, gets the same sums bitwise).
+// sp: kCoarseMax doubles of LDS, red: 2 x 16 of LDS.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_coarse_cg(Grid g, Coeffs<T> C, int uniform,
-                                                    const T* __restrict__ b, T* __restrict__ xout,
-                                                    double tol, int maxit) {
-    __shared__ double sp[kCoarseMax];
-    __shared__ double red[2][16];
+__device__ void coarse_cg_regs(const Grid& g, const T* L0, const T* L1, const T* L2, T Lc,
+                                int uniform, const T* b, T* xout, double tol, int maxit, int nw,
+                                double* sp, double (*red)[16]) {
     const int N = int(cells(g));
-    const int t = int(threadIdx.x), nw = int(blockDim.x) >> 6;
+    const int t = int(threadIdx.x);
     const bool own = t < N;
     auto wsum = [&](double v, int buf) -> double {
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        if ((t & 63) == 0) red[buf][t >> 6] = v;
+        if ((t & 63) == 0 && (t >> 6) < nw) red[buf][t >> 6] = v;
         __syncthreads();
         double s = 0.0;
         for (int w = 0; w < nw; ++w) s += red[buf][w];
@@ -1133,14 +1143,14 @@ __global__ __launch_bounds__(1024) void k_coarse_cg(Grid g, Coeffs<T> C, int uni
         const int i = t % g.n0, j = (t / g.n0) % g.n1, k = t / (g.n0 * g.n1);
         const int n[3] = {g.n0, g.n1, g.n2}, per[3] = {g.per0, g.per1, g.per2};
         const int co[3] = {i, j, k}, st[3] = {1, g.n0, g.n0 * g.n1};
-        const T* Ld[3] = {C.L0, C.L1, C.L2};
+        const T* Ld[3] = {L0, L1, L2};
         for (int d = 0; d < g.ndim; ++d) {
             const int lo = nb_lo(co[d], n[d], per[d]), up = nb_up(co[d], n[d], per[d]);
             nb[2 * d] = t + (lo - co[d]) * st[d];
             nb[2 * d + 1] = t + (up - co[d]) * st[d];
-            const double Ll = uniform ? double(C.Lc) : double(Ld[d][t]);
+            const double Ll = uniform ? double(Lc) : double(Ld[d][t]);
             const double Lu = (co[d] < n[d] - 1 || per[d])
-                                  ? (uniform ? double(C.Lc) : double(Ld[d][nb[2 * d + 1]]))
+                                  ? (uniform ? double(Lc) : double(Ld[d][nb[2 * d + 1]]))
                                   : 0.0;
             cf[2 * d] = Ll;
             cf[2 * d + 1] = Lu;
@@ -1148,12 +1158,13 @@ __global__ __launch_bounds__(1024) void k_coarse_cg(Grid g, Coeffs<T> C, int uni
         }
     }
     const bool act = D > 0.0;
+    const double bt = own ? double(b[t]) : 0.0;
     // mean of b over the active cells
-    const double sumb = wsum(act ? double(b[t]) : 0.0, 0);
+    const double sumb = wsum(act ? bt : 0.0, 0);
     const double cnt = wsum(act ? 1.0 : 0.0, 1);
     const double mean = cnt > 0.0 ? sumb / cnt : 0.0;
     // solve M x = B with M = -A, B = -(b - mean) on active cells
-    const double B = act ? -(double(b[t]) - mean) : 0.0;
+    const double B = act ? -(bt - mean) : 0.0;
     double x = 0.0, r = B, p = B;
     if (own) sp[t] = p;
     double rr = wsum(B * B, 0);  // its barrier also publishes sp
@@ -1186,6 +1197,461 @@ __global__ __launch_bounds__(1024) void k_coarse_cg(Grid g, Coeffs<T> C, int uni
     const double xs = wsum(act ? x : 0.0, 1);
     const double xm = cnt > 0.0 ? xs / cnt : 0.0;
     if (own) xout[t] = act ? T(x - xm) : T(0);
+}
+
+// Coarsest level of at most kCgWaveMax cells in one wave: the same CG as
+// coarse_cg_regs with lane l owning cells l, l + 64, ... (PER of them), the
+// stencils in registers and the search direction in LDS (sp, wave-
+// synchronous: one wave writes and reads it).  Every rounding is spelled out
+// (contraction off, fused multiply-adds written as such), so the standalone
+// kernel and the V-cycle tail, which both call it, agree bit for bit.  Sums:
+// per lane over its cells in order, then wave_sum_f64.
+constexpr int kCgWaveMax = 256;
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): this wave's LDS traffic done
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Data-parallel move of a double across the lanes of a row (CTRL: a DPP
+// control, every lane valid).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, int(u), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, int(u >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                                static_cast<long long>(static_cast<unsigned>(lo)));
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(int(u), lane);
+    const int hi = __builtin_amdgcn_readlane(int(u >> 32), lane);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                                static_cast<long long>(static_cast<unsigned>(lo)));
+}
+
+// Sum over the 64 lanes of a full wave, the same value in every lane: lane
+// pairs, quads, half rows and rows by data-parallel moves (each add takes
+// two equal partial sums in either order, so every lane of a row ends with
+// the same bits), then the four row sums in row order.
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma clang fp contract(off)
+    v = v + dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v = v + dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v = v + dpp_f64<0x141>(v);  // row_half_mirror
+    v = v + dpp_f64<0x140>(v);  // row_mirror
+    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
+template <typename T, int PER>
+__device__ void coarse_cg_wave(const Grid& g, const T* L0, const T* L1, const T* L2, T Lc,
+                               int uniform, const T* b, T* xout, double tol, int maxit,
+                               double* sp) {
+#pragma clang fp contract(off)
+    const int N = int(cells(g));
+    const int lane = int(threadIdx.x) & 63;
+    double D[PER], cf[PER][6], x[PER], r[PER], p[PER], Mp[PER], bt[PER];
+    int nb[PER][6];
+    bool act[PER], own[PER];
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+        const int c = lane + 64 * m;
+        own[m] = c < N;
+        D[m] = 0.0;
+        bt[m] = 0.0;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            cf[m][f] = 0.0;
+            nb[m][f] = own[m] ? c : 0;
+        }
+        if (own[m]) {
+            const int i = c % g.n0, j = (c / g.n0) % g.n1, k = c / (g.n0 * g.n1);
+            const int n[3] = {g.n0, g.n1, g.n2}, per[3] = {g.per0, g.per1, g.per2};
+            const int co[3] = {i, j, k}, st[3] = {1, g.n0, g.n0 * g.n1};
+            const T* Ld[3] = {L0, L1, L2};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                if (d >= g.ndim) break;
+                const int lo = nb_lo(co[d], n[d], per[d]), up = nb_up(co[d], n[d], per[d]);
+                nb[m][2 * d] = c + (lo - co[d]) * st[d];
+                nb[m][2 * d + 1] = c + (up - co[d]) * st[d];
+                const double Ll = uniform ? double(Lc) : double(Ld[d][c]);
+                const double Lu = (co[d] < n[d] - 1 || per[d])
+                                      ? (uniform ? double(Lc) : double(Ld[d][nb[m][2 * d + 1]]))
+                                      : 0.0;
+                cf[m][2 * d] = Ll;
+                cf[m][2 * d + 1] = Lu;
+                D[m] = D[m] + (Ll + Lu);
+            }
+            bt[m] = double(b[c]);
+        }
+        act[m] = D[m] > 0.0;
+    }
+    auto wsum = [&](const double (&v)[PER]) -> double {
+        double s = v[0];
+#pragma unroll
+        for (int m = 1; m < PER; ++m) s = s + v[m];
+        return wave_sum_f64(s);
+    };
+    double t0[PER], t1[PER];
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+        t0[m] = act[m] ? bt[m] : 0.0;
+        t1[m] = act[m] ? 1.0 : 0.0;
+    }
+    const double sumb = wsum(t0), cnt = wsum(t1);
+    const double mean = cnt > 0.0 ? sumb / cnt : 0.0;
+    // solve M x = B with M = -A, B = -(b - mean) on active cells
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+        const double B = act[m] ? -(bt[m] - mean) : 0.0;
+        x[m] = 0.0;
+        r[m] = B;
+        p[m] = B;
+        if (own[m]) sp[lane + 64 * m] = B;
+        t0[m] = B * B;
+    }
+    double rr = wsum(t0);
+    const double rr0 = rr;
+    wave_lds_sync();
+    if (rr0 > 0.0) {
+        for (int it = 0; it < maxit; ++it) {
+#pragma unroll
+            for (int m = 0; m < PER; ++m) {
+                double v = 0.0;
+                if (act[m]) {
+                    v = D[m] * p[m];
+#pragma unroll
+                    for (int f = 0; f < 6; ++f) v = fma(-cf[m][f], sp[nb[m][f]], v);
+                }
+                Mp[m] = v;
+                t0[m] = p[m] * v;
+            }
+            const double pq = wsum(t0);
+            if (!(pq > 0.0)) break;
+            const double alpha = rr / pq;
+#pragma unroll
+            for (int m = 0; m < PER; ++m) {
+                x[m] = fma(alpha, p[m], x[m]);
+                r[m] = fma(-alpha, Mp[m], r[m]);
+                t0[m] = r[m] * r[m];
+            }
+            const double rn = wsum(t0);
+            if (rn <= tol * tol * rr0) break;
+            const double beta = rn / rr;
+            rr = rn;
+            wave_lds_sync();  // every lane has read sp
+#pragma unroll
+            for (int m = 0; m < PER; ++m) {
+                p[m] = fma(beta, p[m], r[m]);
+                if (own[m]) sp[lane + 64 * m] = p[m];
+            }
+            wave_lds_sync();
+        }
+    }
+    // mean-free result on the active cells
+#pragma unroll
+    for (int m = 0; m < PER; ++m) t0[m] = act[m] ? x[m] : 0.0;
+    const double xm = cnt > 0.0 ? wsum(t0) / cnt : 0.0;
+#pragma unroll
+    for (int m = 0; m < PER; ++m)
+        if (own[m]) xout[lane + 64 * m] = act[m] ? T(x[m] - xm) : T(0);
+}
+
+// The one-wave solve for the level's size (PER = cells per lane, at most
+// MAXPER).
+template <typename T, int MAXPER>
+__device__ __forceinline__ void coarse_cg_wave_any(const Grid& g, const T* L0, const T* L1,
+                                                   const T* L2, T Lc, int uniform, const T* b,
+                                                   T* xout, double tol, int maxit, double* sp) {
+    const int N = int(cells(g));
+    if (N <= 64)
+        coarse_cg_wave<T, 1>(g, L0, L1, L2, Lc, uniform, b, xout, tol, maxit, sp);
+    else if (MAXPER < 4 || N <= 128)
+        coarse_cg_wave<T, 2>(g, L0, L1, L2, Lc, uniform, b, xout, tol, maxit, sp);
+    else
+        coarse_cg_wave<T, 4>(g, L0, L1, L2, Lc, uniform, b, xout, tol, maxit, sp);
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_coarse_cg_wave(Grid g, Coeffs<T> C, int uniform,
+                                                       const T* __restrict__ b,
+                                                       T* __restrict__ xout, double tol,
+                                                       int maxit) {
+    __shared__ double sp[kCgWaveMax];
+    coarse_cg_wave_any<T, 4>(g, C.L0, C.L1, C.L2, C.Lc, uniform, b, xout, tol, maxit, sp);
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_coarse_cg(Grid g, Coeffs<T> C, int uniform,
+                                                    const T* __restrict__ b, T* __restrict__ xout,
+                                                    double tol, int maxit) {
+    __shared__ double sp[kCoarseMax];
+    __shared__ double red[2][16];
+    coarse_cg_regs<T>(g, C.L0, C.L1, C.L2, C.Lc, uniform, b, xout, tol, maxit,
+                      int(blockDim.x) >> 6, sp, red);
+}
+
+// ------------------------------------------------- V-cycle tail, one workgroup
+// The coarse end of a V-cycle (Sec. 2's GMG on its smallest levels) in one
+// launch: below a few thousand cells every per-level kernel is a handful of
+// waves whose launch costs more than its work.  One workgroup of
+// kTailThreads runs the levels from the first small one down to the
+// coarsest and back up with every iterate and right-hand side in LDS: the
+// top level's right-hand side is read once, its corrected iterate written
+// once, and the steps in between are separated by barriers.  Per level, as
+// the per-level kernels do it: a sweep from zero into x0, a sweep from x0
+// into x1, the residual of x1 (kept in x0, free until the post-smoothing)
+// summed into the coarse right-hand side, and on the way up the in-place
+// prolongation into x1 and two sweeps back into x1; the coarsest level is
+// coarse_cg_wave, run by the first wave.  Each cell's arithmetic is that of
+// k_smooth, k_resid_restrict (resid_row and the same sum order over the 2^d
+// children), k_prolong and k_coarse_cg, so the result is bitwise that of
+// the per-level launches.  Face coefficients are read from global memory
+// (L1 / L2).
+constexpr int kTailLevels = 8;
+constexpr int kTailThreads = 1024;
+constexpr int kTailPer = 4;                               // cells per thread and level
+constexpr int kTailLdsCells = kTailThreads * kTailPer * 4 / 3 + 64;  // all levels, 2D included
+constexpr int kTailCgMax = 128;  // coarsest level: two cells per lane
+
+template <typename T>
+struct TailLevel {
+    Grid g;
+    const T* L0;
+    const T* L1;
+    const T* L2;
+    T Lc;
+    T wD;                      // w / D of a uniform level
+    unsigned long long m0, m1, mN;  // ceil(2^32 / d) for n0, n1 and the cell count: exact quotients
+    int ox0, ox1, ob;          // LDS offsets of x0, x1 and b
+};
+
+template <typename T>
+struct TailArgs {
+    TailLevel<T> lev[kTailLevels];
+    const T* b;  // right-hand side of the top tail level
+    T* x;        // its corrected iterate
+    int n;       // levels: n - 1 smoothed, the last one solved
+    T omega;
+    double tol;
+};
+
+// Coordinates and neighbour offsets of cell c as the tiled kernels form
+// them: a non-periodic boundary points at the cell itself (its face
+// coefficient is zero), a periodic one wraps.
+struct TailCell {
+    int i, j, k;
+    int oxm, oxp, oym, oyp, ozm, ozp;
+    bool hxu, hyu, hzu;
+};
+
+template <typename T>
+__device__ __forceinline__ TailCell tail_cell(const TailLevel<T>& L, int c) {
+    const Grid& g = L.g;
+    TailCell q;
+    const unsigned r = unsigned((unsigned long long)unsigned(c) * L.m0 >> 32);  // c / n0
+    q.i = c - int(r) * g.n0;
+    q.k = int((unsigned long long)r * L.m1 >> 32);                             // r / n1
+    q.j = int(r) - q.k * g.n1;
+    const int n0 = g.n0, plane = g.n0 * g.n1;
+    const int ixm = q.i > 0 ? q.i - 1 : (g.per0 ? g.n0 - 1 : q.i);
+    const int ixp = q.i < g.n0 - 1 ? q.i + 1 : (g.per0 ? 0 : q.i);
+    const int jym = q.j > 0 ? q.j - 1 : (g.per1 ? g.n1 - 1 : q.j);
+    const int jyp = q.j < g.n1 - 1 ? q.j + 1 : (g.per1 ? 0 : q.j);
+    const int kzm = q.k > 0 ? q.k - 1 : (g.per2 ? g.n2 - 1 : q.k);
+    const int kzp = q.k < g.n2 - 1 ? q.k + 1 : (g.per2 ? 0 : q.k);
+    q.oxm = ixm - q.i;
+    q.oxp = ixp - q.i;
+    q.oym = (jym - q.j) * n0;
+    q.oyp = (jyp - q.j) * n0;
+    q.ozm = (kzm - q.k) * plane;
+    q.ozp = (kzp - q.k) * plane;
+    q.hxu = q.i < g.n0 - 1 || g.per0;
+    q.hyu = q.j < g.n1 - 1 || g.per1;
+    q.hzu = q.k < g.n2 - 1 || g.per2;
+    return q;
+}
+
+// Face coefficients of cell c (the z pair zero in 2D).  Every load is made
+// (a missing upper face reads the cell's own lower face) and the value
+// selected, so the loads carry no branch.
+template <typename T, bool UNIF, bool D3>
+__device__ __forceinline__ void tail_faces(const TailLevel<T>& L, int c, const TailCell& q, T& Lxl,
+                                           T& Lxu, T& Lyl, T& Lyu, T& Lzl, T& Lzu) {
+    if (UNIF) {
+        Lxl = Lxu = Lyl = Lyu = L.Lc;
+        Lzl = Lzu = D3 ? L.Lc : T(0);
+        return;
+    }
+    Lxl = L.L0[c];
+    Lxu = L.L0[c + q.oxp];
+    Lyl = L.L1[c];
+    Lyu = L.L1[c + q.oyp];
+    if (!q.hxu) Lxu = T(0);
+    if (!q.hyu) Lyu = T(0);
+    Lzl = Lzu = T(0);
+    if (D3) {
+        Lzl = L.L2[c];
+        Lzu = L.L2[c + q.ozp];
+        if (!q.hzu) Lzu = T(0);
+    }
+}
+
+// Runs v = body(c) for the thread's cells of a level of N cells, then
+// store(c, v) for each: the P cells' loads are all issued before any store
+// (the pointers the bodies read are restrict-qualified and no branch
+// separates the cells).  On the last, partial batch a thread past the end
+// takes the cell N apart (c mod N, distinct within a wave for N >= 64) and
+// stores the same value its owner stores; with P = 1 such a thread does
+// nothing.
+template <int P, typename Body, typename Store>
+__device__ __forceinline__ void tail_batch(int N, unsigned long long mN, Body&& body, Store&& store) {
+    using V = decltype(body(0));
+    V v[P];
+    int cc[P];
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+        const int c0 = int(threadIdx.x) + u * kTailThreads;
+        cc[u] = c0 < N ? c0 : c0 - N * int((unsigned long long)unsigned(c0) * mN >> 32);
+        v[u] = body(cc[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < P; ++u) store(cc[u], v[u]);
+}
+
+template <typename Body, typename Store>
+__device__ __forceinline__ void tail_cells(int N, unsigned long long mN, Body&& body, Store&& store) {
+    const int P = (N + kTailThreads - 1) / kTailThreads;
+    if (P <= 1) {
+        const int c = int(threadIdx.x);
+        if (c < N) store(c, body(c));
+    } else if (P == 2) {
+        tail_batch<2>(N, mN, body, store);
+    } else if (P == 3) {
+        tail_batch<3>(N, mN, body, store);
+    } else {
+        tail_batch<4>(N, mN, body, store);
+    }
+    __syncthreads();
+}
+
+// One damped-Jacobi sweep of the whole level, x -> xout (ZERO: from x = 0),
+// each cell as k_smooth updates it.
+template <typename T, bool UNIF, bool D3, bool ZERO>
+__device__ void tail_sweep(const TailLevel<T>& L, const T* __restrict__ x,
+                           const T* __restrict__ b, T omega, T* __restrict__ xout) {
+    auto body = [&](int c) -> T {
+        const TailCell q = tail_cell(L, c);
+        auto xv = [&](int idx) -> T { return ZERO ? T(0) : x[idx]; };
+        const T xI = xv(c);
+        const T xxl = xv(c + q.oxm), xxu = xv(c + q.oxp);
+        const T xyl = xv(c + q.oym), xyu = xv(c + q.oyp);
+        const T xzl = D3 ? xv(c + q.ozm) : T(0), xzu = D3 ? xv(c + q.ozp) : T(0);
+        T Lxl, Lxu, Lyl, Lyu, Lzl, Lzu;
+        tail_faces<T, UNIF, D3>(L, c, q, Lxl, Lxu, Lyl, Lyu, Lzl, Lzu);
+        T Ax, D;
+        if (UNIF) {
+            // the sweep of a uniform level: one D, second differences
+            Ax = jacobi_ax_uniform(xI, xxl, xxu, xyl, xyu, xzl, xzu, L.Lc, D3);
+            D = T(0);
+            D += L.Lc + L.Lc;
+            D += L.Lc + L.Lc;
+            if (D3) D += L.Lc + L.Lc;
+        } else {
+            jacobi_terms(xI, xxl, xxu, xyl, xyu, xzl, xzu, Lxl, Lxu, Lyl, Lyu, Lzl, Lzu, D3, Ax, D);
+        }
+        const T r = b[c] - Ax;
+        return UNIF ? jacobi_new_scaled(xI, r, D > T(0), L.wD) : jacobi_new(xI, r, D, omega);
+    };
+    tail_cells(int(cells(L.g)), L.mN, body, [&](int c, T v) { xout[c] = v; });
+}
+
+// Residual b - A x of level F into rs, then the coarse right-hand side bc:
+// the z pair of each child column summed first, then the x pair, then the y
+// pair (the order of k_resid_restrict).
+template <typename T, bool UNIF, bool D3>
+__device__ void tail_restrict(const TailLevel<T>& F, const T* __restrict__ x,
+                              const T* __restrict__ b, T* __restrict__ rs, const TailLevel<T>& C,
+                              T* __restrict__ bc) {
+    auto resid = [&](int c) -> T {
+        const TailCell q = tail_cell(F, c);
+        const T xI = x[c];
+        const T xxl = x[c + q.oxm], xxu = x[c + q.oxp], xyl = x[c + q.oym], xyu = x[c + q.oyp];
+        const T xzl = D3 ? x[c + q.ozm] : T(0), xzu = D3 ? x[c + q.ozp] : T(0);
+        T Lxl, Lxu, Lyl, Lyu, Lzl, Lzu;
+        tail_faces<T, UNIF, D3>(F, c, q, Lxl, Lxu, Lyl, Lyu, Lzl, Lzu);
+        return resid_row(b[c], xI, xxl, xxu, xyl, xyu, xzl, xzu, Lxl, Lxu, Lyl, Lyu, Lzl, Lzu, D3);
+    };
+    tail_cells(int(cells(F.g)), F.mN, resid, [&](int c, T v) { rs[c] = v; });
+    const int n0 = F.g.n0, plane = F.g.n0 * F.g.n1;
+    auto sum = [&](int c) -> T {
+        const unsigned r = unsigned((unsigned long long)unsigned(c) * C.m0 >> 32);
+        const int ic = c - int(r) * C.g.n0;
+        const int kc = int((unsigned long long)r * C.m1 >> 32);
+        const int jc = int(r) - kc * C.g.n1;
+        const int f = 2 * ic + n0 * (2 * jc) + plane * (D3 ? 2 * kc : kc);
+        auto zs = [&](int o) -> T { return D3 ? rs[f + o] + rs[f + o + plane] : rs[f + o]; };
+        return (zs(0) + zs(1)) + (zs(n0) + zs(n0 + 1));
+    };
+    tail_cells(int(cells(C.g)), C.mN, sum, [&](int c, T v) { bc[c] = v; });
+}
+
+// xout = x + P xc: the coarse correction interpolated onto the level.
+template <typename T>
+__device__ void tail_prolong(const TailLevel<T>& L, const TailLevel<T>& C,
+                             const T* __restrict__ xc, const T* __restrict__ x,
+                             T* __restrict__ xout) {
+    auto body = [&](int c) -> T {
+        const unsigned r = unsigned((unsigned long long)unsigned(c) * L.m0 >> 32);
+        const int i = c - int(r) * L.g.n0;
+        const int k = int((unsigned long long)r * L.m1 >> 32);
+        const int j = int(r) - k * L.g.n1;
+        return x[c] + prolong_at<T>(L.g, C.g, xc, i, j, k);
+    };
+    tail_cells(int(cells(L.g)), L.mN, body, [&](int c, T v) { xout[c] = v; });
+}
+
+template <typename T, bool UNIF, bool D3>
+__global__ __launch_bounds__(kTailThreads) void k_vcycle_tail(TailArgs<T> A) {
+    // per level: x0, x1 and b, level after level
+    __shared__ T lds[3 * kTailLdsCells];
+    __shared__ double sp[kTailCgMax];
+    const int n = A.n;
+    auto X0 = [&](int l) -> T* { return lds + A.lev[l].ox0; };
+    auto X1 = [&](int l) -> T* { return lds + A.lev[l].ox1; };
+    auto Bv = [&](int l) -> T* { return lds + A.lev[l].ob; };
+    {
+        const T* __restrict__ bg = A.b;
+        T* b0 = Bv(0);
+        tail_cells(int(cells(A.lev[0].g)), A.lev[0].mN, [&](int c) -> T { return bg[c]; },
+                   [&](int c, T v) { b0[c] = v; });
+    }
+    // down: the pre-smoothed iterate stays in x1, x0 takes the residual
+    for (int l = 0; l < n - 1; ++l) {
+        const TailLevel<T>& L = A.lev[l];
+        tail_sweep<T, UNIF, D3, true>(L, nullptr, Bv(l), A.omega, X0(l));
+        tail_sweep<T, UNIF, D3, false>(L, X0(l), Bv(l), A.omega, X1(l));
+        tail_restrict<T, UNIF, D3>(L, X1(l), Bv(l), X0(l), A.lev[l + 1], Bv(l + 1));
+    }
+    // coarsest: the first wave; each level's corrected iterate then lands in
+    // its x0 (the top level's in global memory)
+    if (threadIdx.x < 64) {
+        const TailLevel<T>& C = A.lev[n - 1];
+        coarse_cg_wave_any<T, 2>(C.g, C.L0, C.L1, C.L2, C.Lc, UNIF ? 1 : 0, Bv(n - 1), X0(n - 1),
+                                 A.tol, int(cells(C.g)) + 64, sp);
+    }
+    __syncthreads();
+    for (int l = n - 2; l >= 0; --l) {
+        const TailLevel<T>& L = A.lev[l];
+        tail_prolong<T>(L, A.lev[l + 1], X0(l + 1), X1(l), X0(l));
+        tail_sweep<T, UNIF, D3, false>(L, X0(l), Bv(l), A.omega, X1(l));
+        tail_sweep<T, UNIF, D3, false>(L, X1(l), Bv(l), A.omega, l == 0 ? A.x : X0(l));
+    }
 }
 
 // Per-block class of a level for a tiling (see Coeffs::cls): 0 when every
@@ -1733,8 +2199,81 @@ static wl_status coarse_solve(const Hierarchy<T>& h, const Level<T>& L, T* xout,
         set_error("internal: coarsest level larger than the one-workgroup solver");
         return WL_ERR_INVALID_ARG;
     }
-    const unsigned nt = unsigned(std::max(64, (N + 63) / 64 * 64));
-    k_coarse_cg<T><<<1, nt, 0, s>>>(L.g, coeffs_of(L), L.uniform, L.b, xout, h.coarse_tol, maxit);
+    if (N <= kCgWaveMax) {
+        k_coarse_cg_wave<T><<<1, 64, 0, s>>>(L.g, coeffs_of(L), L.uniform, L.b, xout, h.coarse_tol,
+                                             maxit);
+    } else {
+        const unsigned nt = unsigned((N + 63) / 64 * 64);
+        k_coarse_cg<T><<<1, nt, 0, s>>>(L.g, coeffs_of(L), L.uniform, L.b, xout, h.coarse_tol,
+                                        maxit);
+    }
+    WL_CHECK_LAUNCH();
+    return WL_OK;
+}
+
+// First level of the V-cycle tail (k_vcycle_tail), 0 for none: with fused
+// kernels on (wl_set_fused_sweeps) and the Jacobi smoother, the first level
+// below the fine one of at most tail_cells() cells, provided at least one
+// smoothed level lies above the coarsest, the coarsest fits the one-wave
+// solve and the levels fit the tail's LDS.
+template <typename T>
+static int tail_level(const Hierarchy<T>& h) {
+    const size_t lim = std::min(tail_cells(), size_t(kTailThreads) * kTailPer);
+    if (h.pairs == 0 || h.smoother != 0 || h.nlev < 3 || lim == 0) return 0;
+    if (cells(h.lev[h.nlev - 1].g) > size_t(kTailCgMax)) return 0;
+    for (int l = 1; l < h.nlev - 1; ++l) {
+        if (cells(h.lev[l].g) > lim) continue;
+        const int lt = std::max(l, h.nlev - kTailLevels);
+        size_t sum = 0;
+        for (int q = lt; q < h.nlev; ++q) sum += cells(h.lev[q].g);
+        return sum <= size_t(kTailLdsCells) ? lt : 0;
+    }
+    return 0;
+}
+
+template <typename T>
+static wl_status vcycle_tail(const Hierarchy<T>& h, int lt, hipStream_t s) {
+    TailArgs<T> A{};
+    A.n = h.nlev - lt;
+    A.omega = T(h.omega);
+    A.tol = h.coarse_tol;
+    A.b = h.lev[lt].b;
+    A.x = h.lev[lt].x[1];
+    if (A.n < 2 || A.n > kTailLevels) {
+        set_error("internal: V-cycle tail of an unsupported depth");
+        return WL_ERR_INVALID_ARG;
+    }
+    const unsigned long long two32 = 1ull << 32;
+    int off = 0;
+    for (int t = 0; t < A.n; ++t) {
+        const Level<T>& L = h.lev[lt + t];
+        TailLevel<T>& D = A.lev[t];
+        D.g = L.g;
+        D.L0 = L.L[0];
+        D.L1 = L.L[1];
+        D.L2 = L.L[2];
+        D.Lc = L.Lc;
+        D.wD = uniform_wd(L, T(h.omega));
+        D.m0 = (two32 + unsigned(L.g.n0) - 1) / unsigned(L.g.n0);
+        D.m1 = (two32 + unsigned(L.g.n1) - 1) / unsigned(L.g.n1);
+        const int N = int(cells(L.g));
+        D.mN = (two32 + unsigned(N) - 1) / unsigned(N);
+        D.ox0 = off;
+        D.ox1 = off + N;
+        D.ob = off + 2 * N;
+        off += 3 * N;
+    }
+    if (off > 3 * kTailLdsCells) {
+        set_error("internal: V-cycle tail levels exceed its LDS");
+        return WL_ERR_INVALID_ARG;
+    }
+    const bool d3 = h.lev[lt].g.ndim == 3;
+    if (h.lev[lt].uniform)
+        d3 ? k_vcycle_tail<T, true, true><<<1, kTailThreads, 0, s>>>(A)
+           : k_vcycle_tail<T, true, false><<<1, kTailThreads, 0, s>>>(A);
+    else
+        d3 ? k_vcycle_tail<T, false, true><<<1, kTailThreads, 0, s>>>(A)
+           : k_vcycle_tail<T, false, false><<<1, kTailThreads, 0, s>>>(A);
     WL_CHECK_LAUNCH();
     return WL_OK;
 }
@@ -1920,16 +2459,24 @@ static wl_status vcycle_rest(Hierarchy<T>& h, Pre mode, const T* fb, const doubl
     Level<T>& F = h.lev[0];
     if (h.nlev == 1) return coarse_solve(h, F, F.x[0], s);
     const T* pre[kMaxLevels];
+    // levels 1 .. top - 1 run per-level kernels; from top on, the tail
+    // kernel (or, without one, the coarsest solve alone)
+    const int lt = tail_level(h);
+    const int top = lt > 0 ? lt : h.nlev - 1;
     WL_TRY(pre_smooth(h, F, mode, F.x[0], F.x[1], fb, fshift, s, &pre[0], true));
     WL_TRY(resid_restrict(F, pre[0], fb, fshift, h.lev[1], s, WL_PROF_RESTRICT_FINE));
-    for (int l = 1; l < h.nlev - 1; ++l) {
+    for (int l = 1; l < top; ++l) {
         Level<T>& L = h.lev[l];
         WL_TRY(pre_smooth(h, L, Pre::Zero, L.x[1], L.x[0], L.b, nullptr, s, &pre[l], false));
         WL_TRY(resid_restrict(L, pre[l], L.b, nullptr, h.lev[l + 1], s));
     }
-    Level<T>& Cst = h.lev[h.nlev - 1];
-    WL_TRY(coarse_solve(h, Cst, Cst.x[1], s));
-    for (int l = h.nlev - 2; l >= 1; --l) {
+    if (lt > 0) {
+        WL_TRY(vcycle_tail(h, lt, s));
+    } else {
+        Level<T>& Cst = h.lev[h.nlev - 1];
+        WL_TRY(coarse_solve(h, Cst, Cst.x[1], s));
+    }
+    for (int l = top - 1; l >= 1; --l) {
         Level<T>& L = h.lev[l];
         WL_TRY(post_smooth(h, L, pre[l], L.x[1], L.x[0], h.lev[l + 1], L.b, nullptr, s, false));
     }

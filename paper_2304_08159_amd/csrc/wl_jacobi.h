@@ -27,6 +27,22 @@ __device__ __forceinline__ void jacobi_terms(T xI, T xxl, T xxu, T xyl, T xyu, T
     }
 }
 
+// Residual b - A x of one row as the restriction forms it, with every
+// rounding fixed: per direction one product and one fused multiply-add, the
+// directions summed x, y, z.  A kernel that walks column pairs shares the
+// product of the face between the two cells, which would otherwise let the
+// compiler fuse the other product of the lower cell's term; written out,
+// the pair kernel and one that forms single cells agree bit for bit.
+template <typename T>
+__device__ __forceinline__ T resid_row(T bv, T xI, T xxl, T xxu, T xyl, T xyu, T xzl, T xzu,
+                                       T Lxl, T Lxu, T Lyl, T Lyu, T Lzl, T Lzu, bool d3) {
+#pragma clang fp contract(off)
+    T Ax = fma(Lxu, xxu - xI, -(Lxl * (xI - xxl)));
+    Ax = Ax + fma(Lyu, xyu - xI, -(Lyl * (xI - xyl)));
+    if (d3) Ax = Ax + fma(Lzu, xzu - xI, -(Lzl * (xI - xzl)));
+    return bv - Ax;
+}
+
 // A x of a row on a level with one coefficient Lc: the second differences
 // of the directions summed, then one multiply.
 template <typename T>
