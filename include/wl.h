@@ -431,12 +431,15 @@ wl_status wl_set_graphs(int enable);
  * multiples of 8 runs as one kernel that keeps the intermediate iterate on
  * chip; the V-cycle then also checks the residual with a measuring pass that
  * writes nothing, and a simulation's divergence kernel takes each solve's
- * first check.  Iterates are bitwise the same as with separate sweeps (the
- * reported residual norms agree to rounding).  mode 0: separate sweeps
- * everywhere; 1 (default) and 2: fused on every such level (1 honours a
- * minimum level size set for tuning).  Process-wide; a solver or simulation
- * takes the mode in force when it is created.  WL_ERR_INVALID_ARG for
- * another mode. */
+ * first check.  Levels with face coefficients or walls are fused too from
+ * 2^22 cells up.  The coarse end of each V-cycle (the levels of at most 16^3
+ * cells, with a coarsest level of at most 128 cells) runs as one
+ * one-workgroup launch.  Iterates are bitwise the same as with separate
+ * sweeps and per-level launches (the reported residual norms agree to
+ * rounding).  mode 0: separate sweeps and per-level launches everywhere; 1
+ * (default) and 2: fused (1 honours the minimum level sizes; 2 fuses every
+ * eligible level).  Process-wide; a solver or simulation takes the mode in
+ * force when it is created.  WL_ERR_INVALID_ARG for another mode. */
 wl_status wl_set_fused_sweeps(int mode);
 
 /* Smoother of the multigrid levels (every level but the coarsest, which is

@@ -1427,8 +1427,9 @@ struct TailLevel {
     const T* L2;
     T Lc;
     T wD;                      // w / D of a uniform level
-    unsigned long long m0, m1, mN;  // ceil(2^32 / d) for n0, n1 and the cell count: exact quotients
-    int ox0, ox1, ob;          // LDS offsets of x0, x1 and b
+    unsigned long long m0, mc;  // ceil(2^32 / d) for n0 and the column count: exact quotients
+    int parts, seg;             // column walks: z segments per column, planes per segment
+    int ox0, ox1, ob;           // LDS offsets of x0, x1 and b
 };
 
 template <typename T>
@@ -1441,179 +1442,179 @@ struct TailArgs {
     double tol;
 };
 
-// Coordinates and neighbour offsets of cell c as the tiled kernels form
-// them: a non-periodic boundary points at the cell itself (its face
-// coefficient is zero), a periodic one wraps.
-struct TailCell {
-    int i, j, k;
-    int oxm, oxp, oym, oyp, ozm, ozp;
-    bool hxu, hyu, hzu;
-};
-
-template <typename T>
-__device__ __forceinline__ TailCell tail_cell(const TailLevel<T>& L, int c) {
-    const Grid& g = L.g;
-    TailCell q;
-    const unsigned r = unsigned((unsigned long long)unsigned(c) * L.m0 >> 32);  // c / n0
-    q.i = c - int(r) * g.n0;
-    q.k = int((unsigned long long)r * L.m1 >> 32);                             // r / n1
-    q.j = int(r) - q.k * g.n1;
-    const int n0 = g.n0, plane = g.n0 * g.n1;
-    const int ixm = q.i > 0 ? q.i - 1 : (g.per0 ? g.n0 - 1 : q.i);
-    const int ixp = q.i < g.n0 - 1 ? q.i + 1 : (g.per0 ? 0 : q.i);
-    const int jym = q.j > 0 ? q.j - 1 : (g.per1 ? g.n1 - 1 : q.j);
-    const int jyp = q.j < g.n1 - 1 ? q.j + 1 : (g.per1 ? 0 : q.j);
-    const int kzm = q.k > 0 ? q.k - 1 : (g.per2 ? g.n2 - 1 : q.k);
-    const int kzp = q.k < g.n2 - 1 ? q.k + 1 : (g.per2 ? 0 : q.k);
-    q.oxm = ixm - q.i;
-    q.oxp = ixp - q.i;
-    q.oym = (jym - q.j) * n0;
-    q.oyp = (jyp - q.j) * n0;
-    q.ozm = (kzm - q.k) * plane;
-    q.ozp = (kzp - q.k) * plane;
-    q.hxu = q.i < g.n0 - 1 || g.per0;
-    q.hyu = q.j < g.n1 - 1 || g.per1;
-    q.hzu = q.k < g.n2 - 1 || g.per2;
-    return q;
-}
-
-// Face coefficients of cell c (the z pair zero in 2D).  Every load is made
-// (a missing upper face reads the cell's own lower face) and the value
-// selected, so the loads carry no branch.
-template <typename T, bool UNIF, bool D3>
-__device__ __forceinline__ void tail_faces(const TailLevel<T>& L, int c, const TailCell& q, T& Lxl,
-                                           T& Lxu, T& Lyl, T& Lyu, T& Lzl, T& Lzu) {
-    if (UNIF) {
-        Lxl = Lxu = Lyl = Lyu = L.Lc;
-        Lzl = Lzu = D3 ? L.Lc : T(0);
-        return;
-    }
-    Lxl = L.L0[c];
-    Lxu = L.L0[c + q.oxp];
-    Lyl = L.L1[c];
-    Lyu = L.L1[c + q.oyp];
-    if (!q.hxu) Lxu = T(0);
-    if (!q.hyu) Lyu = T(0);
-    Lzl = Lzu = T(0);
-    if (D3) {
-        Lzl = L.L2[c];
-        Lzu = L.L2[c + q.ozp];
-        if (!q.hzu) Lzu = T(0);
-    }
-}
-
-// Runs v = body(c) for the thread's cells of a level of N cells, then
-// store(c, v) for each: the P cells' loads are all issued before any store
-// (the pointers the bodies read are restrict-qualified and no branch
-// separates the cells).  On the last, partial batch a thread past the end
-// takes the cell N apart (c mod N, distinct within a wave for N >= 64) and
-// stores the same value its owner stores; with P = 1 such a thread does
-// nothing.
-template <int P, typename Body, typename Store>
-__device__ __forceinline__ void tail_batch(int N, unsigned long long mN, Body&& body, Store&& store) {
-    using V = decltype(body(0));
-    V v[P];
-    int cc[P];
-#pragma unroll
-    for (int u = 0; u < P; ++u) {
-        const int c0 = int(threadIdx.x) + u * kTailThreads;
-        cc[u] = c0 < N ? c0 : c0 - N * int((unsigned long long)unsigned(c0) * mN >> 32);
-        v[u] = body(cc[u]);
-    }
-#pragma unroll
-    for (int u = 0; u < P; ++u) store(cc[u], v[u]);
-}
-
-template <typename Body, typename Store>
-__device__ __forceinline__ void tail_cells(int N, unsigned long long mN, Body&& body, Store&& store) {
-    const int P = (N + kTailThreads - 1) / kTailThreads;
-    if (P <= 1) {
-        const int c = int(threadIdx.x);
-        if (c < N) store(c, body(c));
-    } else if (P == 2) {
-        tail_batch<2>(N, mN, body, store);
-    } else if (P == 3) {
-        tail_batch<3>(N, mN, body, store);
-    } else {
-        tail_batch<4>(N, mN, body, store);
+// Column walks: a level of n0 x n1 columns; with fewer columns than
+// threads each column is split into `parts` z segments of `seg` planes and
+// thread t takes column t mod cols, segment t / cols; otherwise thread t
+// takes the whole columns t, t + kTailThreads, ...  fn(col, i, j, k0, k1)
+// walks its cells up z as the tiled kernels do (x / y neighbour offsets
+// fixed along the column, the lower z neighbour carried), so a cell costs
+// little besides its own arithmetic.  Ends with a barrier.
+template <typename T, typename Fn>
+__device__ __forceinline__ void tail_columns(const TailLevel<T>& L, Fn&& fn) {
+    const int t = int(threadIdx.x);
+    const int cols = L.g.n0 * L.g.n1;
+    auto run = [&](int col, int k0, int k1) {
+        const int j = int((unsigned long long)unsigned(col) * L.m0 >> 32);
+        fn(col, col - j * L.g.n0, j, k0, k1);
+    };
+    if (cols >= kTailThreads) {
+        for (int col = t; col < cols; col += kTailThreads) run(col, 0, L.g.n2);
+    } else if (t < L.parts * cols) {
+        const int part = int((unsigned long long)unsigned(t) * L.mc >> 32);
+        const int k0 = part * L.seg;
+        run(t - part * cols, k0, min(L.g.n2, k0 + L.seg));
     }
     __syncthreads();
 }
 
-// One damped-Jacobi sweep of the whole level, x -> xout (ZERO: from x = 0),
-// each cell as k_smooth updates it.
-template <typename T, bool UNIF, bool D3, bool ZERO>
+// x / y neighbour offsets of column (i, j) as the tiled kernels form them: a
+// non-periodic boundary points at the cell itself (its face coefficient is
+// zero), a periodic one wraps.
+struct TailCol {
+    int oxm, oxp, oym, oyp;
+    bool hxu, hyu;
+};
+
+__device__ __forceinline__ TailCol tail_col(const Grid& g, int i, int j) {
+    TailCol q;
+    const int ixm = i > 0 ? i - 1 : (g.per0 ? g.n0 - 1 : i);
+    const int ixp = i < g.n0 - 1 ? i + 1 : (g.per0 ? 0 : i);
+    const int jym = j > 0 ? j - 1 : (g.per1 ? g.n1 - 1 : j);
+    const int jyp = j < g.n1 - 1 ? j + 1 : (g.per1 ? 0 : j);
+    q.oxm = ixm - i;
+    q.oxp = ixp - i;
+    q.oym = (jym - j) * g.n0;
+    q.oyp = (jyp - j) * g.n0;
+    q.hxu = i < g.n0 - 1 || g.per0;
+    q.hyu = j < g.n1 - 1 || g.per1;
+    return q;
+}
+
+// Offset of the upper / lower z neighbour of plane k (self at a
+// non-periodic end) and whether the upper face exists.
+__device__ __forceinline__ int tail_zup(const Grid& g, int k, int plane, bool& hzu) {
+    hzu = k < g.n2 - 1 || g.per2;
+    return (k < g.n2 - 1 ? plane : (g.per2 ? -(g.n2 - 1) * plane : 0));
+}
+__device__ __forceinline__ int tail_zlo(const Grid& g, int k, int plane) {
+    return k > 0 ? -plane : (g.per2 ? (g.n2 - 1) * plane : 0);
+}
+
+// Damped-Jacobi sweep of the whole level, x -> xout (ZERO: from x = 0), or
+// (RESID) the residual b - A x into xout; each cell as k_smooth updates it
+// (resid_row as k_resid_restrict forms it).
+template <typename T, bool UNIF, bool D3, bool ZERO, bool RESID>
 __device__ void tail_sweep(const TailLevel<T>& L, const T* __restrict__ x,
                            const T* __restrict__ b, T omega, T* __restrict__ xout) {
-    auto body = [&](int c) -> T {
-        const TailCell q = tail_cell(L, c);
+    const Grid& g = L.g;
+    const int plane = g.n0 * g.n1;
+    tail_columns(L, [&](int col, int i, int j, int k0, int k1) {
+        const TailCol q = tail_col(g, i, j);
         auto xv = [&](int idx) -> T { return ZERO ? T(0) : x[idx]; };
-        const T xI = xv(c);
-        const T xxl = xv(c + q.oxm), xxu = xv(c + q.oxp);
-        const T xyl = xv(c + q.oym), xyu = xv(c + q.oyp);
-        const T xzl = D3 ? xv(c + q.ozm) : T(0), xzu = D3 ? xv(c + q.ozp) : T(0);
-        T Lxl, Lxu, Lyl, Lyu, Lzl, Lzu;
-        tail_faces<T, UNIF, D3>(L, c, q, Lxl, Lxu, Lyl, Lyu, Lzl, Lzu);
-        T Ax, D;
-        if (UNIF) {
-            // the sweep of a uniform level: one D, second differences
-            Ax = jacobi_ax_uniform(xI, xxl, xxu, xyl, xyu, xzl, xzu, L.Lc, D3);
-            D = T(0);
-            D += L.Lc + L.Lc;
-            D += L.Lc + L.Lc;
-            if (D3) D += L.Lc + L.Lc;
-        } else {
-            jacobi_terms(xI, xxl, xxu, xyl, xyu, xzl, xzu, Lxl, Lxu, Lyl, Lyu, Lzl, Lzu, D3, Ax, D);
+        int c = col + k0 * plane;
+        T xI = xv(c), xzl = T(0), Lzl = T(0);
+        if (D3) {
+            xzl = xv(c + tail_zlo(g, k0, plane));
+            if (!UNIF) Lzl = L.L2[c];
         }
-        const T r = b[c] - Ax;
-        return UNIF ? jacobi_new_scaled(xI, r, D > T(0), L.wD) : jacobi_new(xI, r, D, omega);
-    };
-    tail_cells(int(cells(L.g)), L.mN, body, [&](int c, T v) { xout[c] = v; });
+        for (int k = k0; k < k1; ++k, c += plane) {
+            T xzu = T(0), Lzu = T(0);
+            bool hzu = false;
+            if (D3) {
+                const int cu = c + tail_zup(g, k, plane, hzu);
+                xzu = xv(cu);
+                if (!UNIF) {
+                    Lzu = L.L2[cu];
+                    if (!hzu) Lzu = T(0);
+                }
+            }
+            const T xxl = xv(c + q.oxm), xxu = xv(c + q.oxp);
+            const T xyl = xv(c + q.oym), xyu = xv(c + q.oyp);
+            const T bv = b[c];
+            T Lxl, Lxu, Lyl, Lyu;
+            if (UNIF) {
+                Lxl = Lxu = Lyl = Lyu = L.Lc;
+            } else {
+                Lxl = L.L0[c];
+                Lxu = L.L0[c + q.oxp];
+                Lyl = L.L1[c];
+                Lyu = L.L1[c + q.oyp];
+                if (!q.hxu) Lxu = T(0);
+                if (!q.hyu) Lyu = T(0);
+            }
+            if (RESID) {
+                const T Lz0 = UNIF ? (D3 ? L.Lc : T(0)) : Lzl, Lz1 = UNIF ? (D3 ? L.Lc : T(0)) : Lzu;
+                xout[c] = resid_row(bv, xI, xxl, xxu, xyl, xyu, xzl, xzu, Lxl, Lxu, Lyl, Lyu, Lz0,
+                                    Lz1, D3);
+            } else if (UNIF) {
+                // the sweep of a uniform level: one D, second differences
+                const T Ax = jacobi_ax_uniform(xI, xxl, xxu, xyl, xyu, xzl, xzu, L.Lc, D3);
+                T D = T(0);
+                D += L.Lc + L.Lc;
+                D += L.Lc + L.Lc;
+                if (D3) D += L.Lc + L.Lc;
+                xout[c] = jacobi_new_scaled(xI, bv - Ax, D > T(0), L.wD);
+            } else {
+                T Ax, D;
+                jacobi_terms(xI, xxl, xxu, xyl, xyu, xzl, xzu, Lxl, Lxu, Lyl, Lyu, Lzl, Lzu, D3, Ax,
+                             D);
+                xout[c] = jacobi_new(xI, bv - Ax, D, omega);
+            }
+            xzl = xI;
+            xI = xzu;
+            Lzl = Lzu;
+        }
+    });
 }
 
-// Residual b - A x of level F into rs, then the coarse right-hand side bc:
-// the z pair of each child column summed first, then the x pair, then the y
-// pair (the order of k_resid_restrict).
-template <typename T, bool UNIF, bool D3>
-__device__ void tail_restrict(const TailLevel<T>& F, const T* __restrict__ x,
-                              const T* __restrict__ b, T* __restrict__ rs, const TailLevel<T>& C,
-                              T* __restrict__ bc) {
-    auto resid = [&](int c) -> T {
-        const TailCell q = tail_cell(F, c);
-        const T xI = x[c];
-        const T xxl = x[c + q.oxm], xxu = x[c + q.oxp], xyl = x[c + q.oym], xyu = x[c + q.oyp];
-        const T xzl = D3 ? x[c + q.ozm] : T(0), xzu = D3 ? x[c + q.ozp] : T(0);
-        T Lxl, Lxu, Lyl, Lyu, Lzl, Lzu;
-        tail_faces<T, UNIF, D3>(F, c, q, Lxl, Lxu, Lyl, Lyu, Lzl, Lzu);
-        return resid_row(b[c], xI, xxl, xxu, xyl, xyu, xzl, xzu, Lxl, Lxu, Lyl, Lyu, Lzl, Lzu, D3);
-    };
-    tail_cells(int(cells(F.g)), F.mN, resid, [&](int c, T v) { rs[c] = v; });
-    const int n0 = F.g.n0, plane = F.g.n0 * F.g.n1;
-    auto sum = [&](int c) -> T {
-        const unsigned r = unsigned((unsigned long long)unsigned(c) * C.m0 >> 32);
-        const int ic = c - int(r) * C.g.n0;
-        const int kc = int((unsigned long long)r * C.m1 >> 32);
-        const int jc = int(r) - kc * C.g.n1;
-        const int f = 2 * ic + n0 * (2 * jc) + plane * (D3 ? 2 * kc : kc);
-        auto zs = [&](int o) -> T { return D3 ? rs[f + o] + rs[f + o + plane] : rs[f + o]; };
-        return (zs(0) + zs(1)) + (zs(n0) + zs(n0 + 1));
-    };
-    tail_cells(int(cells(C.g)), C.mN, sum, [&](int c, T v) { bc[c] = v; });
+// Coarse right-hand side bc from the residual rs of level F: the z pair of
+// each child column summed first, then the x pair, then the y pair (the
+// order of k_resid_restrict).
+template <typename T, bool D3>
+__device__ void tail_restrict_sum(const TailLevel<T>& F, const T* __restrict__ rs,
+                                  const TailLevel<T>& C, T* __restrict__ bc) {
+    const int n0 = F.g.n0, plane = F.g.n0 * F.g.n1, cplane = C.g.n0 * C.g.n1;
+    tail_columns(C, [&](int col, int ic, int jc, int k0, int k1) {
+        const int f0 = 2 * ic + n0 * (2 * jc);
+        for (int kc = k0; kc < k1; ++kc) {
+            const int f = f0 + plane * (D3 ? 2 * kc : kc);
+            auto zs = [&](int o) -> T { return D3 ? rs[f + o] + rs[f + o + plane] : rs[f + o]; };
+            bc[col + kc * cplane] = (zs(0) + zs(1)) + (zs(n0) + zs(n0 + 1));
+        }
+    });
 }
 
-// xout = x + P xc: the coarse correction interpolated onto the level.
-template <typename T>
+// xout = x + P xc: the coarse correction interpolated onto the level, each
+// coarse plane's x / y interpolation formed once per column walk (the
+// operations of prolong_at).
+template <typename T, bool D3>
 __device__ void tail_prolong(const TailLevel<T>& L, const TailLevel<T>& C,
                              const T* __restrict__ xc, const T* __restrict__ x,
                              T* __restrict__ xout) {
-    auto body = [&](int c) -> T {
-        const unsigned r = unsigned((unsigned long long)unsigned(c) * L.m0 >> 32);
-        const int i = c - int(r) * L.g.n0;
-        const int k = int((unsigned long long)r * L.m1 >> 32);
-        const int j = int(r) - k * L.g.n1;
-        return x[c] + prolong_at<T>(L.g, C.g, xc, i, j, k);
-    };
-    tail_cells(int(cells(L.g)), L.mN, body, [&](int c, T v) { xout[c] = v; });
+    const Grid& g = L.g;
+    const int plane = g.n0 * g.n1;
+    tail_columns(L, [&](int col, int i, int j, int k0, int k1) {
+        int ip, iq, jp, jq;
+        prolong_pair(i, C.g.n0, g.per0, ip, iq);
+        prolong_pair(j, C.g.n1, g.per1, jp, jq);
+        const int cn0 = C.g.n0, cpl = C.g.n0 * C.g.n1;
+        auto cplane = [&](int K) -> T {
+            const T* r = xc + cpl * K;
+            const T lo = lerp34(r[ip + cn0 * jp], r[iq + cn0 * jp]);
+            const T hi = lerp34(r[ip + cn0 * jq], r[iq + cn0 * jq]);
+            return lerp34(lo, hi);
+        };
+        int c = col + k0 * plane;
+        if (!D3) {
+            xout[c] = x[c] + cplane(0);
+            return;
+        }
+        for (int k = k0; k < k1; ++k, c += plane) {
+            int kp, kq;
+            prolong_pair(k, C.g.n2, g.per2, kp, kq);
+            xout[c] = x[c] + lerp34(cplane(kp), cplane(kq));
+        }
+    });
 }
 
 template <typename T, bool UNIF, bool D3>
@@ -1627,16 +1628,18 @@ __global__ __launch_bounds__(kTailThreads) void k_vcycle_tail(TailArgs<T> A) {
     auto Bv = [&](int l) -> T* { return lds + A.lev[l].ob; };
     {
         const T* __restrict__ bg = A.b;
-        T* b0 = Bv(0);
-        tail_cells(int(cells(A.lev[0].g)), A.lev[0].mN, [&](int c) -> T { return bg[c]; },
-                   [&](int c, T v) { b0[c] = v; });
+        T* __restrict__ b0 = Bv(0);
+        const int N = int(cells(A.lev[0].g));
+        for (int c = int(threadIdx.x); c < N; c += kTailThreads) b0[c] = bg[c];
+        __syncthreads();
     }
     // down: the pre-smoothed iterate stays in x1, x0 takes the residual
     for (int l = 0; l < n - 1; ++l) {
         const TailLevel<T>& L = A.lev[l];
-        tail_sweep<T, UNIF, D3, true>(L, nullptr, Bv(l), A.omega, X0(l));
-        tail_sweep<T, UNIF, D3, false>(L, X0(l), Bv(l), A.omega, X1(l));
-        tail_restrict<T, UNIF, D3>(L, X1(l), Bv(l), X0(l), A.lev[l + 1], Bv(l + 1));
+        tail_sweep<T, UNIF, D3, true, false>(L, nullptr, Bv(l), A.omega, X0(l));
+        tail_sweep<T, UNIF, D3, false, false>(L, X0(l), Bv(l), A.omega, X1(l));
+        tail_sweep<T, UNIF, D3, false, true>(L, X1(l), Bv(l), A.omega, X0(l));
+        tail_restrict_sum<T, D3>(L, X0(l), A.lev[l + 1], Bv(l + 1));
     }
     // coarsest: the first wave; each level's corrected iterate then lands in
     // its x0 (the top level's in global memory)
@@ -1648,9 +1651,9 @@ __global__ __launch_bounds__(kTailThreads) void k_vcycle_tail(TailArgs<T> A) {
     __syncthreads();
     for (int l = n - 2; l >= 0; --l) {
         const TailLevel<T>& L = A.lev[l];
-        tail_prolong<T>(L, A.lev[l + 1], X0(l + 1), X1(l), X0(l));
-        tail_sweep<T, UNIF, D3, false>(L, X0(l), Bv(l), A.omega, X1(l));
-        tail_sweep<T, UNIF, D3, false>(L, X1(l), Bv(l), A.omega, l == 0 ? A.x : X0(l));
+        tail_prolong<T, D3>(L, A.lev[l + 1], X0(l + 1), X1(l), X0(l));
+        tail_sweep<T, UNIF, D3, false, false>(L, X0(l), Bv(l), A.omega, X1(l));
+        tail_sweep<T, UNIF, D3, false, false>(L, X1(l), Bv(l), A.omega, l == 0 ? A.x : X0(l));
     }
 }
 
@@ -2254,10 +2257,12 @@ static wl_status vcycle_tail(const Hierarchy<T>& h, int lt, hipStream_t s) {
         D.L2 = L.L[2];
         D.Lc = L.Lc;
         D.wD = uniform_wd(L, T(h.omega));
+        const int N = int(cells(L.g)), cols = L.g.n0 * L.g.n1;
         D.m0 = (two32 + unsigned(L.g.n0) - 1) / unsigned(L.g.n0);
-        D.m1 = (two32 + unsigned(L.g.n1) - 1) / unsigned(L.g.n1);
-        const int N = int(cells(L.g));
-        D.mN = (two32 + unsigned(N) - 1) / unsigned(N);
+        D.mc = (two32 + unsigned(cols) - 1) / unsigned(cols);
+        int parts = cols >= kTailThreads ? 1 : std::max(1, std::min(L.g.n2, kTailThreads / cols));
+        D.seg = (L.g.n2 + parts - 1) / parts;
+        D.parts = (L.g.n2 + D.seg - 1) / D.seg;
         D.ox0 = off;
         D.ox1 = off + N;
         D.ob = off + 2 * N;
