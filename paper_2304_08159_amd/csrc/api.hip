@@ -502,7 +502,7 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
         WL_TRY(ns_momentum<T>(field_of(s, S, s.plane[PS]), un, f, T(c.d.nu), false, ap, dt_dev, st));
         if (c.outflow)
             WL_TRY(ns_outflow<T>(c.g, s.vel[S][0], s.plane[PS], s.plane[PS], s.vel[A][0],
-                                 T(c.d.U[0]), false, dt_dev, s.plane[P1], st));
+                                 T(c.d.U[0]), false, dt_dev, s.plane[P1], s.red.partial, st));
         if (tp) {
             WL_TRY(rec3(tp->f1, s.vel[A]));
             if (c.outflow) WL_TRY(rec(tp->fo1, s.plane[P1], c.P));
@@ -552,7 +552,7 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
         }
         if (c.outflow)
             WL_TRY(ns_outflow<T>(c.g, s.vel[u1][0], s.plane[P1], s.plane[PS], s.vel[fr][0],
-                                 T(c.d.U[0]), true, dt_dev, s.plane[P2], st));
+                                 T(c.d.U[0]), true, dt_dev, s.plane[P2], s.red.partial, st));
         if (tp) {
             WL_TRY(rec3(tp->f2, s.vel[fr]));
             if (c.outflow) WL_TRY(rec(tp->fo2, s.plane[P2], c.P));

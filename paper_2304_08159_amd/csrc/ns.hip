@@ -541,41 +541,90 @@ static bool momentum_buf(const Grid& g) { return buffer_addressing(g); }
 
 // Outflow plane (upper x face): convective update d(uout)/dt = -U_x (uout -
 // u_x(n0-1)) in the same stage form, then a uniform shift making its total
-// flux equal to the inflow plane's (FP64 sums, one workgroup, fixed order).
+// flux equal to the inflow plane's.  Two launches over the plane's cells
+// (the plane's and the inflow plane's cells are a column stride apart in
+// memory, so each thread takes one and all loads are in flight at once):
+// the first writes the unshifted plane and per-workgroup FP64 sums of both
+// fluxes, the second forms the totals from those sums in a fixed order (every
+// workgroup the same) and adds the shift.
+constexpr int kOutflowThreads = 256;
+
 template <typename T, bool CORR>
-__global__ __launch_bounds__(1024) void k_outflow(Grid g, const T* __restrict__ ue_x,
-                                                  const T* __restrict__ out_e,
-                                                  const T* __restrict__ out_n,
-                                                  const T* __restrict__ f_x, T Ux,
-                                                  const double* __restrict__ dt_dev,
-                                                  T* __restrict__ fout) {
-    __shared__ double lds[32];
+__global__ __launch_bounds__(kOutflowThreads) void k_outflow_flux(Grid g, const T* __restrict__ ue_x,
+                                                                  const T* __restrict__ out_e,
+                                                                  const T* __restrict__ out_n,
+                                                                  const T* __restrict__ f_x, T Ux,
+                                                                  const double* __restrict__ dt_dev,
+                                                                  T* __restrict__ fout,
+                                                                  double* __restrict__ part) {
+    __shared__ double lds[2][kOutflowThreads / 64];
     const int P = g.n1 * g.n2;
-    const T dt = T(*dt_dev);
+    const int q = int(blockIdx.x) * kOutflowThreads + int(threadIdx.x);
     double sin_ = 0.0, sout = 0.0;
-    for (int q = threadIdx.x; q < P; q += blockDim.x) {
+    if (q < P) {
+        const T dt = T(*dt_dev);
         const int j = q % g.n1, k = q / g.n1;
         const T last = ue_x[cid(g, g.n0 - 1, j, k)];
         const T R = -Ux * (out_e[q] - last);
         const T f = CORR ? T(0.5) * (out_n[q] + out_e[q] + dt * R) : out_e[q] + dt * R;
         fout[q] = f;
-        sout += double(f);
-        sin_ += double(f_x[cid(g, 0, j, k)]);
+        sout = double(f);
+        sin_ = double(f_x[cid(g, 0, j, k)]);
     }
-    auto bsum = [&](double v) -> double {
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
-        __syncthreads();
-        double s = 0.0;
-        for (int w = 0; w < int(blockDim.x + 63) / 64; ++w) s += lds[w];
-        __syncthreads();
-        return s;
-    };
-    const double tin = bsum(sin_);
-    const double tout = bsum(sout);
-    const T shift = T((tin - tout) / double(P));
-    for (int q = threadIdx.x; q < P; q += blockDim.x) fout[q] += shift;
+    for (int off = 32; off > 0; off >>= 1) {
+        sin_ += __shfl_xor(sin_, off, 64);
+        sout += __shfl_xor(sout, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        lds[0][threadIdx.x >> 6] = sin_;
+        lds[1][threadIdx.x >> 6] = sout;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, c = 0.0;
+        for (int w = 0; w < kOutflowThreads / 64; ++w) {
+            a += lds[0][w];
+            c += lds[1][w];
+        }
+        part[2 * blockIdx.x] = a;
+        part[2 * blockIdx.x + 1] = c;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kOutflowThreads) void k_outflow_shift(Grid g,
+                                                                   const double* __restrict__ part,
+                                                                   int nblk, T* __restrict__ fout) {
+    __shared__ double lds[2][kOutflowThreads / 64];
+    __shared__ double shift_s;
+    double a = 0.0, c = 0.0;
+    for (int w = int(threadIdx.x); w < nblk; w += kOutflowThreads) {
+        a += part[2 * w];
+        c += part[2 * w + 1];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off, 64);
+        c += __shfl_xor(c, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        lds[0][threadIdx.x >> 6] = a;
+        lds[1][threadIdx.x >> 6] = c;
+    }
+    __syncthreads();
+    const int P = g.n1 * g.n2;
+    if (threadIdx.x == 0) {
+        double tin = 0.0, tout = 0.0;
+        for (int w = 0; w < kOutflowThreads / 64; ++w) {
+            tin += lds[0][w];
+            tout += lds[1][w];
+        }
+        shift_s = (tin - tout) / double(P);
+    }
+    __syncthreads();
+    const int q = int(blockIdx.x) * kOutflowThreads + int(threadIdx.x);
+    if (q < P) fout[q] += T(shift_s);
 }
 
 // First-order BDIM blend on interior faces:
@@ -1298,11 +1347,18 @@ wl_status ns_momentum_proj(const VelField<float>& E, const float* const un[3], f
 
 template <typename T>
 wl_status ns_outflow(const Grid& g, const T* ue_x, const T* out_e, const T* out_n, const T* f_x,
-                     T Ux, bool corr, const double* dt_dev, T* fout, hipStream_t s) {
+                     T Ux, bool corr, const double* dt_dev, T* fout, double* part,
+                     hipStream_t s) {
+    const int P = g.n1 * g.n2;
+    const int nblk = (P + kOutflowThreads - 1) / kOutflowThreads;
     if (corr)
-        k_outflow<T, true><<<1, 1024, 0, s>>>(g, ue_x, out_e, out_n, f_x, Ux, dt_dev, fout);
+        k_outflow_flux<T, true><<<nblk, kOutflowThreads, 0, s>>>(g, ue_x, out_e, out_n, f_x, Ux,
+                                                                 dt_dev, fout, part);
     else
-        k_outflow<T, false><<<1, 1024, 0, s>>>(g, ue_x, out_e, out_n, f_x, Ux, dt_dev, fout);
+        k_outflow_flux<T, false><<<nblk, kOutflowThreads, 0, s>>>(g, ue_x, out_e, out_n, f_x, Ux,
+                                                                  dt_dev, fout, part);
+    WL_CHECK_LAUNCH();
+    k_outflow_shift<T><<<nblk, kOutflowThreads, 0, s>>>(g, part, nblk, fout);
     WL_CHECK_LAUNCH();
     return WL_OK;
 }
@@ -1441,7 +1497,7 @@ wl_status ns_set_scalar(double* p, double v, hipStream_t s) {
     template wl_status ns_momentum<T>(const VelField<T>&, const T* const*, T* const*, T, bool,   \
                                       bool, const double*, hipStream_t);                          \
     template wl_status ns_outflow<T>(const Grid&, const T*, const T*, const T*, const T*, T, bool, \
-                                     const double*, T*, hipStream_t);                             \
+                                     const double*, T*, double*, hipStream_t);                    \
     template wl_status ns_bdim<T>(const VelField<T>&, const BdimFields<T>&, T* const*,            \
                                   hipStream_t, const BodyMotionDev&);                             \
     template wl_status ns_bdim_in_place<T>(const VelField<T>&, T* const*, const BdimFields<T>&,   \

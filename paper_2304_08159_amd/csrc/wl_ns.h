@@ -83,9 +83,13 @@ wl_status ns_momentum(const VelField<T>& E, const T* const un[3], T* const f[3],
 wl_status ns_momentum_proj(const VelField<float>& E, const float* const un[3], float* const f[3],
                            float nu, const double* dt_dev, const float* p, float Lc,
                            hipStream_t s);
+// Convective outflow plane and its exit-flux balance; part: scratch for two
+// FP64 sums per 256 plane cells (a simulation's reduction partials, free
+// between the momentum kernel and the divergence).
 template <typename T>
 wl_status ns_outflow(const Grid& g, const T* ue_x, const T* out_e, const T* out_n, const T* f_x,
-                     T Ux, bool corr, const double* dt_dev, T* fout, hipStream_t s);
+                     T Ux, bool corr, const double* dt_dev, T* fout, double* part,
+                     hipStream_t s);
 template <typename T>
 wl_status ns_bdim(const VelField<T>& F, const BdimFields<T>& B, T* const out[3], hipStream_t s,
                   const BodyMotionDev& motion = BodyMotionDev{});
