@@ -111,20 +111,62 @@ __device__ __forceinline__ int mt_pos(int t, int k) {
     return (r + 2) * MT_LX + (c < 2 ? c : MT_X + c);
 }
 
-// Ghost-rule read, kept out of line: the tiled kernel takes it only for halo
-// positions outside the grid, and inlining it at every load site would tie
-// up registers for the whole z march.
-__device__ __noinline__ float ghost_fetch(const VelField<float>* V, int c, int gx, int gy, int gz) {
-    return vget<float, false>(*V, c, gx, gy, gz);
+// The velocity ghost rule (vget) evaluated inline for the halo of a tile at a
+// domain face:
+// the first coordinate outside the grid (x, then y, then z, after the
+// periodic wraps) picks the branch of the rule, the others are clamped, and
+// only that branch runs, so a tile at a face pays a few instructions per
+// ghost slot instead of a call.
+__device__ __forceinline__ float ghost_inl(const VelField<float>& V, int c, int px, int py, int pz) {
+    // the grid and boundary fields pass through readfirstlane (they are
+    // uniform): a per-lane choice between fields loaded from the kernel
+    // argument would otherwise become a per-lane load from a private copy
+    auto u_ = [](int v) { return __builtin_amdgcn_readfirstlane(v); };
+    const int n0 = u_(V.g.n0), n1 = u_(V.g.n1), n2 = u_(V.g.n2);
+    if (V.g.per0) px = px < 0 ? px + n0 : (px >= n0 ? px - n0 : px);
+    if (V.g.per1) py = py < 0 ? py + n1 : (py >= n1 ? py - n1 : py);
+    if (V.g.per2) pz = pz < 0 ? pz + n2 : (pz >= n2 ? pz - n2 : pz);
+    const bool ox_ = px < 0 || px >= n0, oy_ = py < 0 || py >= n1;
+    const int d = ox_ ? 0 : (oy_ ? 1 : 2);
+    const int kk = d == 0 ? px : (d == 1 ? py : pz);
+    const int m = d == 0 ? n0 : (d == 1 ? n1 : n2);
+    const int cx = min(max(px, 0), n0 - 1), cy = min(max(py, 0), n1 - 1);
+    const int cz = min(max(pz, 0), n2 - 1);
+    auto at = [&](int idx) -> float {
+        idx = min(max(idx, 0), m - 1);
+        const int x = d == 0 ? idx : cx, y = d == 1 ? idx : cy, z = d == 2 ? idx : cz;
+        return V.u[c][size_t(x) + size_t(n0) * (size_t(y) + size_t(n1) * size_t(z))];
+    };
+    const int l0 = u_(V.bclo[0]), l1 = u_(V.bclo[1]), l2 = u_(V.bclo[2]);
+    const int h0 = u_(V.bchi[0]), h1 = u_(V.bchi[1]), h2 = u_(V.bchi[2]);
+    const int blo = d == 0 ? l0 : (d == 1 ? l1 : l2);
+    const int bhi = d == 0 ? h0 : (d == 1 ? h1 : h2);
+    if (kk < 0) {
+        if (blo == WL_BC_INFLOW) return V.U[c];
+        if (c == d) {
+            const int mir = -kk;
+            return -at(mir < m ? mir : 0);
+        }
+        const int mir = -1 - kk;
+        return at(mir < m - 1 ? mir : m - 1);
+    }
+    if (c == d) {
+        if (bhi == WL_BC_OUTFLOW) return V.uout[cy + size_t(n1) * cz];
+        if (kk == m) return 0.f;
+        return -at(m - 1 > 0 ? m - 1 : 0);
+    }
+    if (bhi == WL_BC_OUTFLOW) return at(m - 1);
+    if (kk == m) return at(m - 1);
+    return at(m - 2 > 0 ? m - 2 : 0);
 }
 
 template <bool ALLPER>
 __device__ __forceinline__ float tile_fetch(const VelField<float>& V, int c, int gx, int gy, int gz) {
-    if (ALLPER) {
-        const Grid& g = V.g;
-        return V.u[c][cid(g, wrapi(gx, g.n0), wrapi(gy, g.n1), wrapi(gz, g.n2))];
-    }
-    return vget<float, false>(V, c, gx, gy, gz);
+    const Grid& g = V.g;
+    if (ALLPER) return V.u[c][cid(g, wrapi(gx, g.n0), wrapi(gy, g.n1), wrapi(gz, g.n2))];
+    if (gx >= 0 && gx < g.n0 && gy >= 0 && gy < g.n1 && gz >= 0 && gz < g.n2)
+        return V.u[c][cid(g, gx, gy, gz)];
+    return ghost_inl(V, c, gx, gy, gz);
 }
 
 // Twice the flux through a face of a momentum control volume: s is the sum of
@@ -275,17 +317,22 @@ __device__ __forceinline__ void momentum_tile(const VelField<float>& E, const fl
                 }
             }
         } else {
+            // every slot first loads an address inside the grid (the plane
+            // clamped in z, offset 0 for a position outside it), with no branch
+            // around the loads; the slots outside the grid then take the ghost
+            // rule, a branch no lane of an interior tile enters
             const bool zin = zz >= 0 && zz < g.n2;
-            const unsigned base = zin ? unsigned(zz) * plane : 0u;
+            const unsigned base = unsigned(min(max(zz, 0), g.n2 - 1)) * plane;
 #pragma unroll
             for (int k = 0; k < MT_LOADS; ++k) {
-                if (lpos[k] < 0) continue;
-                if (zin && inxy[k]) {
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) r[c][k] = E.u[c][base + offxy[k]];
-                } else {
+                for (int c = 0; c < 3; ++c) r[c][k] = E.u[c][base + offxy[k]];
+            }
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) r[c][k] = ghost_fetch(&E, c, pxs[k], pys[k], zz);
+            for (int k = 0; k < MT_LOADS; ++k) {
+                if (lpos[k] >= 0 && !(zin && inxy[k])) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) r[c][k] = ghost_inl(E, c, pxs[k], pys[k], zz);
                 }
             }
         }
