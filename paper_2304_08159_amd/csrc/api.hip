@@ -495,7 +495,8 @@ static wl_status sim_step(SimImpl<T>& s, double dt_in, wl_step_stats* stats, hip
     const T* un[3] = {s.vel[S][0], s.vel[S][1], s.vel[S][2]};
     wl_status worst = WL_OK;
     SolveResult r1, r2;
-    const ProjCoeffs<T> pc{{s.h.lev[0].L[0], s.h.lev[0].L[1], s.h.lev[0].L[2]}, T(1)};
+    const ProjCoeffs<T> pc{{s.h.lev[0].L[0], s.h.lev[0].L[1], s.h.lev[0].L[2]}, T(1),
+                           s.h.lev[0].uniform ? nullptr : s.h.lev[0].cls};
     // ---- predictor (c = 1)
     {
         T* f[3] = {s.vel[A][0], s.vel[A][1], s.vel[A][2]};

@@ -776,6 +776,19 @@ __global__ __launch_bounds__(kBlock) void k_tile_class(TileDev TL, Grid g, BdimF
 // solve's initial iterate p and c = sigma - A p, the per-block sums
 // [sigma, sigma^2, c, c^2] (partial[4 * block + q]), from which the mean m and
 // ||r||^2 = sum (c - m)^2, ||b - m||^2 follow without another pass.
+// Component d on the cell above (i, j, k) in direction d when that cell lies
+// past a non-periodic upper face (the other coordinates inside): the ghost
+// rule's value there, the outflow plane or zero (vget's branch for it,
+// without the rest of the rule).
+template <typename T>
+__device__ __forceinline__ T ghost_up(const VelField<T>& V, int d, int j, int k) {
+    const Grid& g = V.g;
+    const int bh = d == 0 ? V.bchi[0] : (d == 1 ? V.bchi[1] : V.bchi[2]);
+    if (bh != WL_BC_OUTFLOW) return T(0);
+    const int a = min(j + (d == 1), g.n1 - 1), b = min(k + (d == 2), g.n2 - 1);
+    return V.uout[a + size_t(g.n1) * b];
+}
+
 template <typename T, bool ALLPER, bool UNIF, bool CHK>
 __global__ __launch_bounds__(kBlock) void k_divergence(TileDev TL, VelField<T> V, ProjCoeffs<T> C,
                                                        double c, const double* __restrict__ dt_dev,
@@ -802,6 +815,8 @@ __global__ __launch_bounds__(kBlock) void k_divergence(TileDev TL, VelField<T> V
         const T* __restrict__ uz = V.u[2];
         unsigned id = unsigned(i) + n0 * unsigned(j) + plane * unsigned(sp.z0);
         T wlo = d3 ? uz[id] : T(0);  // lower z face, carried up the column
+        // a class-0 block: every cell active, no coefficient read
+        const bool walled = !UNIF && C.cls && C.cls[block_linear()] == 0;
         // CHK: periodic x / y neighbour offsets of p; p at k - 1 and k carried
         const int dxm = i > 0 ? -1 : g.n0 - 1;
         const int dym = j > 0 ? -int(n0) : int(n0) * (g.n1 - 1);
@@ -811,14 +826,14 @@ __global__ __launch_bounds__(kBlock) void k_divergence(TileDev TL, VelField<T> V
             pzl = p[sp.z0 > 0 ? id - plane : id + plane * unsigned(g.n2 - 1)];
         }
         for (int k = sp.z0; k < sp.z1; ++k, id += plane) {
-            const T xu = xin ? ux[id + dxp] : vget<T, ALLPER>(V, 0, i + 1, j, k);
-            const T yu = yin ? uy[id + dyp] : vget<T, ALLPER>(V, 1, i, j + 1, k);
+            const T xu = xin ? ux[id + dxp] : ghost_up<T>(V, 0, j, k);
+            const T yu = yin ? uy[id + dyp] : ghost_up<T>(V, 1, j, k);
             T div = (xu - ux[id]) + (yu - uy[id]);
             if (d3) {
                 T wup;
                 if (k + 1 < g.n2) wup = uz[id + plane];
                 else if (ALLPER || g.per2) wup = uz[id - plane * unsigned(g.n2 - 1)];
-                else wup = vget<T, ALLPER>(V, 2, i, j, k + 1);
+                else wup = ghost_up<T>(V, 2, j, k);
                 div += wup - wlo;
                 wlo = wup;
             }
@@ -836,12 +851,14 @@ __global__ __launch_bounds__(kBlock) void k_divergence(TileDev TL, VelField<T> V
                 pI = pzu;
             }
             bool active = true;
-            if (!UNIF) {
+            if (!UNIF && !walled) {
                 T D = T(0);
                 const int n[3] = {g.n0, g.n1, g.n2};
                 const int per[3] = {g.per0, g.per1, g.per2};
                 const int q[3] = {i, j, k};
-                for (int d = 0; d < g.ndim; ++d) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    if (d >= g.ndim) break;
                     D += C.L[d][id];
                     if (q[d] + 1 < n[d] || per[d]) {
                         int r[3] = {i, j, k};
@@ -1103,7 +1120,10 @@ __global__ __launch_bounds__(kBlock) void k_project(TileDev TL, VelField<T> V, c
     const T* sx = V.u[0];  // no restrict: the output may alias u*
     const T* sy = V.u[1];
     const T* sz = V.u[2];
-    auto Lat = [&](int d, unsigned id) -> T { return UNIF ? C.Lc : C.L[d][id]; };
+    // a class-0 block reads no coefficient: every face it projects is Lc
+    // (the wall faces are handled apart)
+    const bool walled = !UNIF && C.cls && C.cls[block_linear()] == 0;
+    auto Lat = [&](int d, unsigned id) -> T { return (UNIF || walled) ? C.Lc : C.L[d][id]; };
     // projected face d with lower cell offset dm (its cell holds pI)
     auto face = [&](int d, const T* u, unsigned id, int dm, T pI) -> T {
         return proj_face(u[id], coef * Lat(d, id), pI, p[id + dm]);
@@ -1119,7 +1139,7 @@ __global__ __launch_bounds__(kBlock) void k_project(TileDev TL, VelField<T> V, c
             const unsigned idu = id + du;
             return proj_face(V.u[d][idu], coef * Lat(d, idu), p[idu], pI);
         }
-        return vget<T, ALLPER>(V, d, i + (d == 0), j + (d == 1), k + (d == 2));
+        return ghost_up<T>(V, d, j, k);
     };
     double cfl = 0.0;
     unsigned id = unsigned(i) + n0 * unsigned(j) + plane * unsigned(sp.z0);
@@ -1145,7 +1165,7 @@ __global__ __launch_bounds__(kBlock) void k_project(TileDev TL, VelField<T> V, c
                     const unsigned i0 = id - plane * unsigned(g.n2 - 1);
                     wup = proj_face(sz[i0], coef * Lat(2, i0), p[i0], pI);
                 } else {
-                    wup = vget<T, ALLPER>(V, 2, i, j, k + 1);
+                    wup = ghost_up<T>(V, 2, j, k);
                 }
             }
             o0[id] = ux;

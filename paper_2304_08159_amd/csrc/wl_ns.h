@@ -34,6 +34,10 @@ template <typename T>
 struct ProjCoeffs {
     const T* L[3];
     T Lc;
+    // optional block classes of the fine level's launch_for tiling (see
+    // Coeffs::cls): a class-0 block has every face Lc or 0 on a domain wall,
+    // so all its cells are active
+    const unsigned char* cls = nullptr;
 };
 
 template <typename T>
