@@ -128,12 +128,25 @@ static bool gen_pairs() {
     return v;
 }
 
-// Smallest non-uniform level fused in mode 1 (WL_GEN_PAIR_MIN_CELLS
-// overrides it): below it the two launches of a pair cost more than the
-// separate sweeps they replace.
+// Smallest non-uniform level whose pairs run as two launches, one per kind
+// of workgroup (WL_GEN_PAIR_MIN_CELLS overrides it); smaller levels run both
+// kinds in one launch (k_smooth_pair mode 3), where a second launch would
+// cost more than the shared register budget.
 static size_t gen_pair_min_cells() {
     static const size_t v = [] {
         const char* e = std::getenv("WL_GEN_PAIR_MIN_CELLS");
+        const long t = e ? std::atol(e) : -1;
+        return t >= 0 ? size_t(t) : (size_t(1) << 22);
+    }();
+    return v;
+}
+
+// Largest non-uniform level below gen_pair_min_cells() that runs its pairs in
+// one launch (WL_PAIR3_MAX_CELLS overrides it); the levels between keep
+// separate sweeps.
+static size_t pair3_max_cells() {
+    static const size_t v = [] {
+        const char* e = std::getenv("WL_PAIR3_MAX_CELLS");
         const long t = e ? std::atol(e) : -1;
         return t >= 0 ? size_t(t) : (size_t(1) << 22);
     }();
@@ -361,6 +374,9 @@ struct PairTile {
 // is the damping w.  The arithmetic per cell is that of k_smooth's
 // non-uniform path, so the result is again bitwise that of two separate
 // sweeps.
+// MODE 3: both kinds of workgroup in one launch over all of them, each
+// taking its class's walk over its whole chunk: small levels, where a second
+// launch costs more than the shared register budget.
 // NM (MODE 1 / 2): the pair also measures the residual of its input, as a
 // measuring check would: per-workgroup FP64 partial sums of r^2 (r = b - A x
 // on the tile's cells of its own planes, from the first sweep) and, NM = 2,
@@ -774,7 +790,14 @@ __global__ __launch_bounds__(PairShape<TX>::T) void k_smooth_pair(PairTile P, Gr
         if (s <= z1) step(I0{}, Store{});
     }
     };
-    run(std::integral_constant<int, MODE>{});
+    if constexpr (MODE == 3) {
+        if (Cf.cls[wg] == 0)
+            run(std::integral_constant<int, 1>{});
+        else
+            run(std::integral_constant<int, 2>{});
+    } else {
+        run(std::integral_constant<int, MODE>{});
+    }
     if constexpr (NM != 0) {
         // fixed-order workgroup sums
         __shared__ double red[2][Sh::T / 64];
@@ -2029,8 +2052,10 @@ static bool pair_ok(const Hierarchy<T>& h, const Level<T>& L) {
         if (!(L.g.per0 && L.g.per1 && L.g.per2)) return false;
     } else {
         if (!L.cls_fp || !gen_pairs()) return false;
-        // mode 1: non-uniform levels fuse from gen_pair_min_cells() on
-        if (h.pairs != 2 && cells(L.g) < gen_pair_min_cells()) return false;
+        // mode 1: single-launch pairs up to pair3_max_cells(), two launches
+        // from gen_pair_min_cells() on, separate sweeps between
+        if (h.pairs != 2 && cells(L.g) > pair3_max_cells() && cells(L.g) < gen_pair_min_cells())
+            return false;
     }
     // FP32 pairs address their arrays through buffer descriptors, whose
     // 32-bit byte offsets cover arrays below 4 GiB (2^30 cells)
@@ -2081,7 +2106,10 @@ static wl_status pair(const Level<T>& L, const T* xin, const T* b, T omega, T* x
     const Coeffs<T> C = coeffs_of(L, L.cls_fp);
 #define WL_PAIR(TX)                                                                             \
     do {                                                                                        \
-        if (gen) {                                                                              \
+        if (gen && cells(L.g) < gen_pair_min_cells()) {                                         \
+            k_smooth_pair<T, XM, TX, 3><<<P.nb, PairShape<TX>::T, 0, s>>>(                      \
+                P, L.g, X, C, b, wd, xout, bshift, nullptr, nullptr);                           \
+        } else if (gen) {                                                                       \
             k_smooth_pair<T, XM, TX, 1><<<P.nb, PairShape<TX>::T, 0, s>>>(                      \
                 P, L.g, X, C, b, wd, xout, bshift, nullptr, nullptr);                           \
             if (L.fp_grid)                                                                      \
