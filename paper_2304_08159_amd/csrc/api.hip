@@ -234,6 +234,9 @@ static void carve_sim(Carver& c, SimImpl<T>& s, const SimConfig& cfg) {
     s.cell_flag = cfg.body ? c.take<unsigned char>(N) : nullptr;
     const int per[3] = {cfg.g.per0, cfg.g.per1, cfg.g.per2};
     carve_hierarchy<T>(c, s.h, cfg.d.ndim, cfg.d.n, per, cfg.nlev, cfg.d.prec == WL_MIXED);
+    // a body that moves re-measures every step: the coarsest inverse would be
+    // formed again each time, so its solve stays the CG
+    s.h.direct_coarse = !cfg.moving;
     s.red.slots = reduce_slots_for(cfg.g);
     s.red.partial = c.take<double>(4 * std::max(s.red.slots, size_t(div_check_map(cfg.g).nblocks)));
     s.red.result = c.take<double>(kResultDoubles);

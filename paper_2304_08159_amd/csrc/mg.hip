@@ -204,6 +204,11 @@ void carve_hierarchy(Carver& c, Hierarchy<T>& h, int ndim, const int n[3], const
         const Grid& g0 = h.lev[0].g;
         h.cgpart = c.take<double>(5 * reduce_slots_for(g0));
     }
+    const size_t Nc = cells(h.lev[nlev - 1].g);
+    if (Nc <= size_t(kDirectMax)) {
+        h.cinv = c.take<double>(Nc * Nc);
+        h.cinv_ok = c.take<int>(1);
+    }
 }
 
 template void carve_hierarchy<float>(Carver&, Hierarchy<float>&, int, const int*, const int*, int,
@@ -1400,13 +1405,213 @@ __device__ __forceinline__ void coarse_cg_wave_any(const Grid& g, const T* L0, c
         coarse_cg_wave<T, 4>(g, L0, L1, L2, Lc, uniform, b, xout, tol, maxit, sp);
 }
 
+// Coarsest level by its inverse (levels of at most kDirectMax cells).  On
+// the active cells (D > 0) M = -A is singular with the constant as null
+// vector (per connected set of active cells); M + a 1 1^T, a = (mean D) /
+// n_act, is positive definite when the active cells are connected, and its
+// inverse G maps every mean-free right-hand side B to the mean-free solution
+// of M x = B: the minimum-norm solution a pseudo-inverse gives.  Formed once
+// per coefficient change by Gauss-Jordan elimination without pivoting (one
+// workgroup, the matrix in LDS); a pivot that is not positive (disconnected
+// active cells, or a singular level) clears *ok and the CG solves instead.
+// Inactive rows and columns of G are zero.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_coarse_inverse(Grid g, Coeffs<T> C, int uniform,
+                                                         double* __restrict__ G,
+                                                         int* __restrict__ ok) {
+    // N x N matrix (row stride N), then the pivot column and the sums
+    __shared__ double A[kDirectMax * kDirectMax + kDirectMax + 32];
+    const int N = int(cells(g));
+    double* colp = A + N * N;
+    double* red = colp + N;
+    const int t = int(threadIdx.x), nt = int(blockDim.x);
+    double D = 0.0;
+    if (t < N) {
+        for (int j = 0; j < N; ++j) A[t * N + j] = 0.0;
+        const int i = t % g.n0, j = (t / g.n0) % g.n1, k = t / (g.n0 * g.n1);
+        const int n[3] = {g.n0, g.n1, g.n2}, per[3] = {g.per0, g.per1, g.per2};
+        const int co[3] = {i, j, k}, st[3] = {1, g.n0, g.n0 * g.n1};
+        const T* Ld[3] = {C.L0, C.L1, C.L2};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (d >= g.ndim) break;
+            const int lo = nb_lo(co[d], n[d], per[d]), up = nb_up(co[d], n[d], per[d]);
+            const int nlo = t + (lo - co[d]) * st[d], nup = t + (up - co[d]) * st[d];
+            const double Ll = uniform ? double(C.Lc) : double(Ld[d][t]);
+            const double Lu =
+                (co[d] < n[d] - 1 || per[d]) ? (uniform ? double(C.Lc) : double(Ld[d][nup])) : 0.0;
+            D += Ll + Lu;
+            A[t * N + nlo] -= Ll;
+            A[t * N + nup] -= Lu;
+        }
+        A[t * N + t] += D;
+    }
+    const bool act = t < N && D > 0.0;
+    // active count and diagonal sum (fixed order over the waves)
+    double c0 = act ? 1.0 : 0.0, c1 = act ? D : 0.0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        c0 += __shfl_xor(c0, off, 64);
+        c1 += __shfl_xor(c1, off, 64);
+    }
+    if ((t & 63) == 0) {
+        red[2 * (t >> 6)] = c0;
+        red[2 * (t >> 6) + 1] = c1;
+    }
+    // an inactive cell's row and column are zero (its faces are): its
+    // diagonal becomes 1, its flag 0
+    if (t < N && !act) A[t * N + t] = 1.0;
+    if (t < N) colp[t] = act ? 1.0 : 0.0;
+    __syncthreads();
+    double nact = 0.0, dsum = 0.0;
+    for (int w = 0; w < nt / 64; ++w) {
+        nact += red[2 * w];
+        dsum += red[2 * w + 1];
+    }
+    const double scale = nact > 0.0 ? dsum / nact : 1.0;
+    const double a = nact > 0.0 ? scale / nact : 0.0;
+    if (act)
+        for (int j = 0; j < N; ++j)
+            if (colp[j] != 0.0) A[t * N + j] += a;
+    __syncthreads();
+    bool good = true;
+    for (int p = 0; p < N; ++p) {
+        const double piv = A[p * N + p];
+        good = piv > 1e-12 * scale;  // the same value in every thread
+        if (!good) break;
+        if (t < N) colp[t] = A[t * N + p];
+        __syncthreads();
+        const double inv = 1.0 / piv;
+        for (int j = t; j < N; j += nt) A[p * N + j] = (j == p) ? inv : A[p * N + j] * inv;
+        __syncthreads();
+        for (int e = t; e < N * N; e += nt) {
+            const int i = e / N, j = e - i * N;
+            if (i == p) continue;
+            A[e] = (j == p) ? -colp[i] * inv : A[e] - colp[i] * A[p * N + j];
+        }
+        __syncthreads();
+    }
+    if (t < N) colp[t] = act ? 1.0 : 0.0;
+    __syncthreads();
+    for (int e = t; e < N * N; e += nt) {
+        const int i = e / N, j = e - i * N;
+        G[e] = (good && colp[i] != 0.0 && colp[j] != 0.0) ? A[e] : 0.0;
+    }
+    if (t == 0) *ok = good ? 1 : 0;
+}
+
+// x = G B on the coarsest level in one wave, B the mean-free right-hand side
+// (as coarse_cg_wave forms it), then the mean of x over the active cells
+// removed.  Sums as in coarse_cg_wave; sp: LDS for N doubles.
+template <typename T, int PER>
+__device__ void coarse_direct_wave(const Grid& g, const T* L0, const T* L1, const T* L2, T Lc,
+                                   int uniform, const T* b, T* xout, const double* G,
+                                   double* sp) {
+#pragma clang fp contract(off)
+    const int N = int(cells(g));
+    const int lane = int(threadIdx.x) & 63;
+    double bt[PER], x[PER], t0[PER], t1[PER];
+    bool act[PER], own[PER];
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+        const int c = lane + 64 * m;
+        own[m] = c < N;
+        double D = 0.0;
+        bt[m] = 0.0;
+        if (own[m]) {
+            const int i = c % g.n0, j = (c / g.n0) % g.n1, k = c / (g.n0 * g.n1);
+            const int n[3] = {g.n0, g.n1, g.n2}, per[3] = {g.per0, g.per1, g.per2};
+            const int co[3] = {i, j, k}, st[3] = {1, g.n0, g.n0 * g.n1};
+            const T* Ld[3] = {L0, L1, L2};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                if (d >= g.ndim) break;
+                const int up = nb_up(co[d], n[d], per[d]);
+                const double Ll = uniform ? double(Lc) : double(Ld[d][c]);
+                const double Lu = (co[d] < n[d] - 1 || per[d])
+                                      ? (uniform ? double(Lc) : double(Ld[d][c + (up - co[d]) * st[d]]))
+                                      : 0.0;
+                D = D + (Ll + Lu);
+            }
+            bt[m] = double(b[c]);
+        }
+        act[m] = D > 0.0;
+        t0[m] = act[m] ? bt[m] : 0.0;
+        t1[m] = act[m] ? 1.0 : 0.0;
+    }
+    auto wsum = [&](const double (&v)[PER]) -> double {
+        double s = v[0];
+#pragma unroll
+        for (int m = 1; m < PER; ++m) s = s + v[m];
+        return wave_sum_f64(s);
+    };
+    const double sumb = wsum(t0), cnt = wsum(t1);
+    const double mean = cnt > 0.0 ? sumb / cnt : 0.0;
+#pragma unroll
+    for (int m = 0; m < PER; ++m)
+        if (own[m]) sp[lane + 64 * m] = act[m] ? -(bt[m] - mean) : 0.0;
+    wave_lds_sync();
+#pragma unroll
+    for (int m = 0; m < PER; ++m) x[m] = 0.0;
+    // G is symmetric: column c read along the rows keeps the lanes' loads
+    // consecutive; 16 / PER rows' loads are issued before they are used
+    constexpr int U = 16 / PER;
+    int cc[PER];
+#pragma unroll
+    for (int m = 0; m < PER; ++m) cc[m] = own[m] ? lane + 64 * m : 0;
+    int j = 0;
+    for (; j + U <= N; j += U) {
+        double gv[PER][U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int m = 0; m < PER; ++m) gv[m][u] = G[size_t(j + u) * N + cc[m]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double Bj = sp[j + u];
+#pragma unroll
+            for (int m = 0; m < PER; ++m) x[m] = fma(gv[m][u], Bj, x[m]);
+        }
+    }
+    for (; j < N; ++j) {
+        const double Bj = sp[j];
+#pragma unroll
+        for (int m = 0; m < PER; ++m) x[m] = fma(G[size_t(j) * N + cc[m]], Bj, x[m]);
+    }
+#pragma unroll
+    for (int m = 0; m < PER; ++m) t0[m] = act[m] ? x[m] : 0.0;
+    const double xm = cnt > 0.0 ? wsum(t0) / cnt : 0.0;
+#pragma unroll
+    for (int m = 0; m < PER; ++m)
+        if (own[m]) xout[lane + 64 * m] = act[m] ? T(x[m] - xm) : T(0);
+}
+
+// The coarsest solve of a one-wave level: the inverse when it is valid, else
+// the CG.
+template <typename T, int MAXPER>
+__device__ __forceinline__ void coarse_wave_solve(const Grid& g, const T* L0, const T* L1,
+                                                  const T* L2, T Lc, int uniform, const T* b,
+                                                  T* xout, double tol, int maxit, double* sp,
+                                                  const double* G, const int* ok) {
+    const int N = int(cells(g));
+    if (G && *ok) {
+        if (N <= 64)
+            coarse_direct_wave<T, 1>(g, L0, L1, L2, Lc, uniform, b, xout, G, sp);
+        else
+            coarse_direct_wave<T, 2>(g, L0, L1, L2, Lc, uniform, b, xout, G, sp);
+        return;
+    }
+    coarse_cg_wave_any<T, MAXPER>(g, L0, L1, L2, Lc, uniform, b, xout, tol, maxit, sp);
+}
+
 template <typename T>
 __global__ __launch_bounds__(64) void k_coarse_cg_wave(Grid g, Coeffs<T> C, int uniform,
                                                        const T* __restrict__ b,
                                                        T* __restrict__ xout, double tol,
-                                                       int maxit) {
+                                                       int maxit, const double* G,
+                                                       const int* ok) {
     __shared__ double sp[kCgWaveMax];
-    coarse_cg_wave_any<T, 4>(g, C.L0, C.L1, C.L2, C.Lc, uniform, b, xout, tol, maxit, sp);
+    coarse_wave_solve<T, 4>(g, C.L0, C.L1, C.L2, C.Lc, uniform, b, xout, tol, maxit, sp, G, ok);
 }
 
 template <typename T>
@@ -1460,6 +1665,8 @@ struct TailArgs {
     TailLevel<T> lev[kTailLevels];
     const T* b;  // right-hand side of the top tail level
     T* x;        // its corrected iterate
+    const double* G;  // the coarsest level's inverse and its flag (null: CG)
+    const int* ok;
     int n;       // levels: n - 1 smoothed, the last one solved
     T omega;
     double tol;
@@ -1668,8 +1875,8 @@ __global__ __launch_bounds__(kTailThreads) void k_vcycle_tail(TailArgs<T> A) {
     // its x0 (the top level's in global memory)
     if (threadIdx.x < 64) {
         const TailLevel<T>& C = A.lev[n - 1];
-        coarse_cg_wave_any<T, 2>(C.g, C.L0, C.L1, C.L2, C.Lc, UNIF ? 1 : 0, Bv(n - 1), X0(n - 1),
-                                 A.tol, int(cells(C.g)) + 64, sp);
+        coarse_wave_solve<T, 2>(C.g, C.L0, C.L1, C.L2, C.Lc, UNIF ? 1 : 0, Bv(n - 1), X0(n - 1),
+                                A.tol, int(cells(C.g)) + 64, sp, A.G, A.ok);
     }
     __syncthreads();
     for (int l = n - 2; l >= 0; --l) {
@@ -2231,8 +2438,10 @@ static wl_status coarse_solve(const Hierarchy<T>& h, const Level<T>& L, T* xout,
         return WL_ERR_INVALID_ARG;
     }
     if (N <= kCgWaveMax) {
+        const bool dir = h.cinv_set && &L == &h.lev[h.nlev - 1];
         k_coarse_cg_wave<T><<<1, 64, 0, s>>>(L.g, coeffs_of(L), L.uniform, L.b, xout, h.coarse_tol,
-                                             maxit);
+                                             maxit, dir ? h.cinv : nullptr,
+                                             dir ? h.cinv_ok : nullptr);
     } else {
         const unsigned nt = unsigned((N + 63) / 64 * 64);
         k_coarse_cg<T><<<1, nt, 0, s>>>(L.g, coeffs_of(L), L.uniform, L.b, xout, h.coarse_tol,
@@ -2270,6 +2479,8 @@ static wl_status vcycle_tail(const Hierarchy<T>& h, int lt, hipStream_t s) {
     A.tol = h.coarse_tol;
     A.b = h.lev[lt].b;
     A.x = h.lev[lt].x[1];
+    A.G = h.cinv_set ? h.cinv : nullptr;
+    A.ok = h.cinv_set ? h.cinv_ok : nullptr;
     if (A.n < 2 || A.n > kTailLevels) {
         set_error("internal: V-cycle tail of an unsupported depth");
         return WL_ERR_INVALID_ARG;
@@ -2349,6 +2560,19 @@ wl_status mg_coarsen_all(Hierarchy<T>& h, hipStream_t s) {
             k_pair_list<<<1, 1024, 0, s>>>(L.cls_fp, P.nb, L.fp_list);
             WL_CHECK_LAUNCH();
         }
+    }
+    // the coarsest level's inverse (about a tenth of a V-cycle's time to
+    // form, recovered within a solve), or a cleared flag: the CG solves
+    if (h.cinv) {
+        const Level<T>& Cst = h.lev[h.nlev - 1];
+        if (h.direct_coarse) {
+            k_coarse_inverse<T><<<1, 1024, 0, s>>>(Cst.g, coeffs_of(Cst), Cst.uniform, h.cinv,
+                                                   h.cinv_ok);
+            WL_CHECK_LAUNCH();
+        } else {
+            WL_CHECK_HIP(hipMemsetAsync(h.cinv_ok, 0, sizeof(int), s));
+        }
+        h.cinv_set = true;
     }
     // the class-1 launch's grid covers the largest count met so far; when it
     // grows, captured bodies (whose grids are baked in) are dropped

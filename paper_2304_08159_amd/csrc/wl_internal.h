@@ -16,6 +16,7 @@ namespace wl {
 constexpr int kMaxLevels = 16;
 constexpr int kBlock = 256;           // threads per block of the stencil kernels
 constexpr int kCoarseMax = 1024;      // cells a one-workgroup coarsest solve accepts
+constexpr int kDirectMax = 128;       // cells a coarsest level solved by its inverse may have
 
 // ---------------------------------------------------------------- errors
 void set_error(const std::string& msg);
@@ -211,6 +212,14 @@ struct Hierarchy {
     size_t n_active = 0;         // active fine cells (host copy)
     int pairs = 0;               // fused two-sweep kernels: 0 off, 1 on large levels, 2 on all
     int smoother = 0;            // 0 damped Jacobi, 1 conjugate gradients (WL_SMOOTH_*)
+    // coarsest levels of at most kDirectMax cells: the inverse of the
+    // operator with the mean constraint (N x N, FP64; see k_coarse_inverse)
+    // and its validity flag, formed when the coefficients change unless
+    // direct_coarse is off (then the CG solves)
+    double* cinv = nullptr;
+    int* cinv_ok = nullptr;
+    bool direct_coarse = true;
+    bool cinv_set = false;  // host: the flag has been set since the carve
     double* cgpart = nullptr;    // CG per-block partial sums (5 per block of level 0)
     GraphCache graphs;
 };
