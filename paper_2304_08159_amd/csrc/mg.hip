@@ -1405,9 +1405,9 @@ __device__ __forceinline__ void coarse_cg_wave_any(const Grid& g, const T* L0, c
         coarse_cg_wave<T, 4>(g, L0, L1, L2, Lc, uniform, b, xout, tol, maxit, sp);
 }
 
-// Coarsest level by its inverse (levels of at most kDirectMax cells).  On
-// the active cells (D > 0) M = -A is singular with the constant as null
-// vector (per connected set of active cells); M + a 1 1^T, a = (mean D) /
+// Coarsest level by its inverse (non-uniform levels of at most kDirectMax
+// cells).  On the active cells (D > 0) M = -A is singular with the constant
+// as null vector (per connected set of active cells); M + a 1 1^T, a = (mean D) /
 // n_act, is positive definite when the active cells are connected, and its
 // inverse G maps every mean-free right-hand side B to the mean-free solution
 // of M x = B: the minimum-norm solution a pseudo-inverse gives.  Formed once
@@ -1594,11 +1594,8 @@ __device__ __forceinline__ void coarse_wave_solve(const Grid& g, const T* L0, co
                                                   T* xout, double tol, int maxit, double* sp,
                                                   const double* G, const int* ok) {
     const int N = int(cells(g));
-    if (G && *ok) {
-        if (N <= 64)
-            coarse_direct_wave<T, 1>(g, L0, L1, L2, Lc, uniform, b, xout, G, sp);
-        else
-            coarse_direct_wave<T, 2>(g, L0, L1, L2, Lc, uniform, b, xout, G, sp);
+    if (G && N <= 64 && *ok) {
+        coarse_direct_wave<T, 1>(g, L0, L1, L2, Lc, uniform, b, xout, G, sp);
         return;
     }
     coarse_cg_wave_any<T, MAXPER>(g, L0, L1, L2, Lc, uniform, b, xout, tol, maxit, sp);
@@ -2561,11 +2558,13 @@ wl_status mg_coarsen_all(Hierarchy<T>& h, hipStream_t s) {
             WL_CHECK_LAUNCH();
         }
     }
-    // the coarsest level's inverse (about a tenth of a V-cycle's time to
-    // form, recovered within a solve), or a cleared flag: the CG solves
+    // the coarsest level's inverse on non-uniform levels, where the CG takes
+    // many iterations (formed in about a fifth of a V-cycle's time,
+    // recovered within a solve); on uniform ones the CG converges in a few
+    // and keeps the solve (a cleared flag)
     if (h.cinv) {
         const Level<T>& Cst = h.lev[h.nlev - 1];
-        if (h.direct_coarse) {
+        if (h.direct_coarse && !Cst.uniform) {
             k_coarse_inverse<T><<<1, 1024, 0, s>>>(Cst.g, coeffs_of(Cst), Cst.uniform, h.cinv,
                                                    h.cinv_ok);
             WL_CHECK_LAUNCH();

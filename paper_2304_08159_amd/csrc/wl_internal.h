@@ -16,7 +16,7 @@ namespace wl {
 constexpr int kMaxLevels = 16;
 constexpr int kBlock = 256;           // threads per block of the stencil kernels
 constexpr int kCoarseMax = 1024;      // cells a one-workgroup coarsest solve accepts
-constexpr int kDirectMax = 128;       // cells a coarsest level solved by its inverse may have
+constexpr int kDirectMax = 64;        // cells a coarsest level solved by its inverse may have
 
 // ---------------------------------------------------------------- errors
 void set_error(const std::string& msg);
