@@ -1419,15 +1419,21 @@ template <typename T>
 __global__ __launch_bounds__(1024) void k_coarse_inverse(Grid g, Coeffs<T> C, int uniform,
                                                          double* __restrict__ G,
                                                          int* __restrict__ ok) {
-    // N x N matrix (row stride N), then the pivot column and the sums
-    __shared__ double A[kDirectMax * kDirectMax + kDirectMax + 32];
+    // the matrix in LDS with row stride kS; thread t owns row t / 16 and
+    // columns t % 16 + 16 q (q < 4) of the elimination
+    constexpr int kS = kDirectMax, kQ = kDirectMax / 16;
+    static_assert(kDirectMax % 16 == 0 && kDirectMax * 16 <= 1024, "one element group per thread");
+    __shared__ double A[kS * kS];
+    __shared__ double actf[kS];
+    __shared__ double red[2 * 16];
     const int N = int(cells(g));
-    double* colp = A + N * N;
-    double* red = colp + N;
     const int t = int(threadIdx.x), nt = int(blockDim.x);
+    const int ri = t >> 4, cj = t & 15;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) A[ri * kS + cj + 16 * q] = 0.0;
+    __syncthreads();
     double D = 0.0;
     if (t < N) {
-        for (int j = 0; j < N; ++j) A[t * N + j] = 0.0;
         const int i = t % g.n0, j = (t / g.n0) % g.n1, k = t / (g.n0 * g.n1);
         const int n[3] = {g.n0, g.n1, g.n2}, per[3] = {g.per0, g.per1, g.per2};
         const int co[3] = {i, j, k}, st[3] = {1, g.n0, g.n0 * g.n1};
@@ -1441,10 +1447,10 @@ __global__ __launch_bounds__(1024) void k_coarse_inverse(Grid g, Coeffs<T> C, in
             const double Lu =
                 (co[d] < n[d] - 1 || per[d]) ? (uniform ? double(C.Lc) : double(Ld[d][nup])) : 0.0;
             D += Ll + Lu;
-            A[t * N + nlo] -= Ll;
-            A[t * N + nup] -= Lu;
+            A[t * kS + nlo] -= Ll;
+            A[t * kS + nup] -= Lu;
         }
-        A[t * N + t] += D;
+        A[t * kS + t] += D;
     }
     const bool act = t < N && D > 0.0;
     // active count and diagonal sum (fixed order over the waves)
@@ -1460,8 +1466,8 @@ __global__ __launch_bounds__(1024) void k_coarse_inverse(Grid g, Coeffs<T> C, in
     }
     // an inactive cell's row and column are zero (its faces are): its
     // diagonal becomes 1, its flag 0
-    if (t < N && !act) A[t * N + t] = 1.0;
-    if (t < N) colp[t] = act ? 1.0 : 0.0;
+    if (t < N && !act) A[t * kS + t] = 1.0;
+    if (t < kS) actf[t] = act ? 1.0 : 0.0;
     __syncthreads();
     double nact = 0.0, dsum = 0.0;
     for (int w = 0; w < nt / 64; ++w) {
@@ -1470,32 +1476,41 @@ __global__ __launch_bounds__(1024) void k_coarse_inverse(Grid g, Coeffs<T> C, in
     }
     const double scale = nact > 0.0 ? dsum / nact : 1.0;
     const double a = nact > 0.0 ? scale / nact : 0.0;
-    if (act)
-        for (int j = 0; j < N; ++j)
-            if (colp[j] != 0.0) A[t * N + j] += a;
+    const bool rowact = ri < N && actf[ri] != 0.0;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        const int j = cj + 16 * q;
+        if (rowact && j < N && actf[j] != 0.0) A[ri * kS + j] += a;
+    }
     __syncthreads();
     bool good = true;
     for (int p = 0; p < N; ++p) {
-        const double piv = A[p * N + p];
+        const double piv = A[p * kS + p];
         good = piv > 1e-12 * scale;  // the same value in every thread
         if (!good) break;
-        if (t < N) colp[t] = A[t * N + p];
+        const double cv = A[ri * kS + p];
+        double rv[kQ];
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) rv[q] = A[p * kS + cj + 16 * q];
         __syncthreads();
         const double inv = 1.0 / piv;
-        for (int j = t; j < N; j += nt) A[p * N + j] = (j == p) ? inv : A[p * N + j] * inv;
-        __syncthreads();
-        for (int e = t; e < N * N; e += nt) {
-            const int i = e / N, j = e - i * N;
-            if (i == p) continue;
-            A[e] = (j == p) ? -colp[i] * inv : A[e] - colp[i] * A[p * N + j];
+        if (ri < N) {
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                const int j = cj + 16 * q;
+                if (j >= N) continue;
+                const double prow = (j == p) ? inv : rv[q] * inv;  // the scaled pivot row
+                double& e = A[ri * kS + j];
+                e = (ri == p) ? prow : (j == p) ? -cv * inv : e - cv * prow;
+            }
         }
         __syncthreads();
     }
-    if (t < N) colp[t] = act ? 1.0 : 0.0;
-    __syncthreads();
-    for (int e = t; e < N * N; e += nt) {
-        const int i = e / N, j = e - i * N;
-        G[e] = (good && colp[i] != 0.0 && colp[j] != 0.0) ? A[e] : 0.0;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        const int j = cj + 16 * q;
+        if (ri < N && j < N)
+            G[ri * N + j] = (good && actf[ri] != 0.0 && actf[j] != 0.0) ? A[ri * kS + j] : 0.0;
     }
     if (t == 0) *ok = good ? 1 : 0;
 }
