@@ -104,6 +104,14 @@ static size_t pair_min_cells() {
     return v;
 }
 
+// WL_DIRECT_COARSE=0 keeps the coarsest level's CG where its inverse would
+// solve it (read whenever the coefficients change, so that the two can be
+// compared within one process).
+static bool direct_coarse_enabled() {
+    const char* e = std::getenv("WL_DIRECT_COARSE");
+    return !(e && std::atoi(e) == 0);
+}
+
 // Target workgroup count of a fused launch (WL_PAIR_BLOCKS overrides it).
 static unsigned pair_blocks() {
     static const unsigned v = [] {
@@ -2579,13 +2587,13 @@ wl_status mg_coarsen_all(Hierarchy<T>& h, hipStream_t s) {
     // and keeps the solve (a cleared flag)
     if (h.cinv) {
         const Level<T>& Cst = h.lev[h.nlev - 1];
-        if (h.direct_coarse && !Cst.uniform) {
+        if (h.direct_coarse && !Cst.uniform && direct_coarse_enabled()) {
             k_coarse_inverse<T><<<1, 1024, 0, s>>>(Cst.g, coeffs_of(Cst), Cst.uniform, h.cinv,
                                                    h.cinv_ok);
-            WL_CHECK_LAUNCH();
         } else {
-            WL_CHECK_HIP(hipMemsetAsync(h.cinv_ok, 0, sizeof(int), s));
+            k_fill<int><<<1, 64, 0, s>>>(h.cinv_ok, 1, 0);
         }
+        WL_CHECK_LAUNCH();
         h.cinv_set = true;
     }
     // the class-1 launch's grid covers the largest count met so far; when it

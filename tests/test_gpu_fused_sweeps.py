@@ -170,3 +170,37 @@ def test_vcycle_tail_is_bitwise_identical(precname, n, per, body):
     assert ka >= 3 and ka == kb
     assert abs(ra - rb) <= 1e-12 * rb
     assert torch.equal(xa, xb)
+
+
+# Non-uniform coarsest levels of at most 64 cells, solved by the level's
+# inverse by default: 96x80 -> 6x5 (30 cells), 64^3 and 32^3 -> 4^3.
+DIRECT_CASES = [
+    ("fp64", (96, 80), (False, False), dict(centre=(40.3, 37.6), radius=11.0)),
+    ("fp32", (64, 64, 64), (False, False, False), dict(centre=(30.3, 33.6, 31.2), radius=9.0)),
+    ("mixed", (32, 32, 32), (False, False, False), dict(centre=(15.3, 16.6, 16.2), radius=5.0)),
+]
+
+
+@pytest.mark.parametrize("precname,n,per,body", DIRECT_CASES,
+                         ids=[f"{c[0]}-{'x'.join(map(str, c[1]))}" for c in DIRECT_CASES])
+def test_direct_coarsest_solve_matches_cg(precname, n, per, body, monkeypatch):
+    """The coarsest level solved by its inverse against the one-wave CG
+    (WL_DIRECT_COARSE=0): both give the level's minimum-norm solution, the CG
+    to its tolerance, so the solves take the same V-cycles to the same
+    residual and agree to the solve's tolerance; they differ in rounding,
+    which shows that the switch changes the path."""
+    import paper_2304_08159_amd as wl
+    ka, ra, xa = _solve_body(wl, 1, precname, n, per, body)
+    monkeypatch.setenv("WL_DIRECT_COARSE", "0")
+    kb, rb, xb = _solve_body(wl, 1, precname, n, per, body)
+    print(precname, n, "vcycles", ka, kb, "rel", ra, rb, flush=True)
+    assert ka >= 3 and abs(ka - kb) <= 1
+    fp32 = precname == "fp32"
+    if ka == kb:
+        assert abs(ra - rb) <= (0.05 if fp32 else 1e-3) * rb
+    assert not torch.equal(xa, xb)
+    da, db = xa.double(), xb.double()
+    da, db = da - da.mean(), db - db.mean()
+    rel = float((da - db).norm() / db.norm())
+    print("relative difference of the solutions", rel, flush=True)
+    assert rel <= (1e-2 if fp32 else 1e-6)
